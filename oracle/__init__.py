@@ -1,0 +1,223 @@
+"""FP64 CPU oracle for the hierarchical ZNCC block-matching hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the benchmark's
+CPU-baseline leg may import this package.  The product library shares no code
+with it and never calls it.
+
+The arithmetic lives in `msibm_oracle.c` (plain C, double precision, direct loops);
+this module compiles it with gcc, loads it with ctypes, and composes the per-step
+functions into the method's steps in the paper's order (Section III):
+
+  1. a K-level Gaussian pyramid of both views;
+  2. a full winner-take-all ZNCC search at the coarsest level (Eqs. 3-4);
+  3. for each finer level, a search restricted to +-r around the doubled,
+     nearest-neighbour-upsampled coarser map (Eqs. 8-9, first branch).
+
+Plus the differentiable finest level (soft-argmax) and its gradient, which the
+paper does not have.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import List, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "msibm_oracle.c")
+_LIB = os.path.join(_HERE, "libmsibm_oracle.so")
+_lib = None
+
+_D = ctypes.POINTER(ctypes.c_double)
+_I16 = ctypes.POINTER(ctypes.c_int16)
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP).  Returns the library path."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
+        lib = ctypes.CDLL(_LIB)
+        c_int, c_double = ctypes.c_int, ctypes.c_double
+        lib.orc_reduce.argtypes = [_D, c_int, c_int, _D]
+        lib.orc_reduce.restype = None
+        lib.orc_zncc.argtypes = [_D, _D, c_int, c_int, c_int, c_int, c_int, c_int, c_double]
+        lib.orc_zncc.restype = c_double
+        lib.orc_match_level.argtypes = [_D, _D, c_int, c_int, c_int, c_int, _I16, c_int, c_int,
+                                        c_int, c_double, _I16, _D, _D]
+        lib.orc_match_level.restype = None
+        lib.orc_soft_level0.argtypes = [_D, _D, c_int, c_int, c_int, c_int, _I16, c_int, c_int,
+                                        c_int, c_double, c_double, _D, _I16, _D, _D]
+        lib.orc_soft_level0.restype = None
+        lib.orc_backward.argtypes = [_D, _D, c_int, c_int, c_int, c_int, _I16, c_int, c_int,
+                                     c_int, c_double, c_double, _D, c_int, c_int, _D, _D]
+        lib.orc_backward.restype = None
+        _lib = lib
+    return _lib
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _p(a, t):
+    return a.ctypes.data_as(t)
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle will use (OMP_NUM_THREADS, else the CPU count)."""
+    v = os.environ.get("OMP_NUM_THREADS")
+    return int(v) if v else (os.cpu_count() or 1)
+
+
+# --------------------------------------------------------------------------- steps
+
+def reduce(img: np.ndarray) -> np.ndarray:
+    """One pyramid step: 5x5 binomial blur, clamp-to-edge, keep even samples."""
+    x = _f64(img)
+    H, W = x.shape
+    out = np.empty(((H + 1) // 2, (W + 1) // 2), dtype=np.float64)
+    _load().orc_reduce(_p(x, _D), H, W, _p(out, _D))
+    return out
+
+
+def pyramid(img: np.ndarray, K: int) -> List[np.ndarray]:
+    """Levels 0..K-1; level 0 is the input converted to float64."""
+    levels = [_f64(img)]
+    for _ in range(K - 1):
+        levels.append(reduce(levels[-1]))
+    return levels
+
+
+def level_range(D: int, k: int) -> int:
+    """D_k = ceil(D / 2^k) candidates at level k (reading of d_max^k = D_max/2^k)."""
+    return -(-D // (1 << k))
+
+
+def zncc(L: np.ndarray, R: np.ndarray, n: int, i: int, j: int, z: int, eps: float) -> float:
+    """Score of left pixel (i, j) against right pixel (i, j - z) (Eqs. 1-2)."""
+    L = _f64(L)
+    R = _f64(R)
+    H, W = L.shape
+    return _load().orc_zncc(_p(L, _D), _p(R, _D), H, W, n, i, j, z, eps)
+
+
+def match_level(L: np.ndarray, R: np.ndarray, n: int, Dk: int,
+                coarse: Optional[np.ndarray], r: int, eps: float):
+    """Winner-take-all of one level.  `coarse` = level k+1 map (int16) for the
+    restricted search, or None for a full search.  Returns (d, C, C2)."""
+    L = _f64(L)
+    R = _f64(R)
+    H, W = L.shape
+    d = np.empty((H, W), dtype=np.int16)
+    C = np.empty((H, W), dtype=np.float64)
+    C2 = np.empty((H, W), dtype=np.float64)
+    if coarse is not None:
+        cz = np.ascontiguousarray(coarse, dtype=np.int16)
+        Hc, Wc = cz.shape
+        assert Hc == (H + 1) // 2 and Wc == (W + 1) // 2, "prior shape"
+        cptr = _p(cz, _I16)
+    else:
+        cz, Hc, Wc, cptr = None, 0, 0, None
+    _load().orc_match_level(_p(L, _D), _p(R, _D), H, W, n, Dk, cptr, Hc, Wc, r, eps,
+                            _p(d, _I16), _p(C, _D), _p(C2, _D))
+    return d, C, C2
+
+
+def disparity(left: np.ndarray, right: np.ndarray, D: int, K: int, n: int, r: int,
+              eps: float, priors: Optional[List[Optional[np.ndarray]]] = None):
+    """The hierarchical forward pass (Section III, hot path).
+
+    Returns a list, index k = level, of (d_k, C_k, C2_k).  `priors[k]`, if given,
+    replaces the map that feeds level k (teacher forcing: the level-(k+1) map
+    used as the prior of level k)."""
+    PL = pyramid(left, K)
+    PR = pyramid(right, K)
+    out: List = [None] * K
+    kc = K - 1
+    out[kc] = match_level(PL[kc], PR[kc], n, level_range(D, kc), None, r, eps)
+    for k in range(K - 2, -1, -1):
+        prior = out[k + 1][0]
+        if priors is not None and priors[k] is not None:
+            prior = priors[k]
+        out[k] = match_level(PL[k], PR[k], n, level_range(D, k), prior, r, eps)
+    return out
+
+
+def flat_bm(left: np.ndarray, right: np.ndarray, D: int, n: int, eps: float):
+    """Standard block matching: a full search at full resolution."""
+    return match_level(_f64(left), _f64(right), n, D, None, 0, eps)
+
+
+def soft_level0(L0: np.ndarray, R0: np.ndarray, n: int, D: int, coarse1: np.ndarray,
+                rs: int, tau: float, eps: float):
+    """Soft-argmax at level 0 over the radius-rs interval around the doubled
+    level-1 map.  Returns (d_soft, d_hard, C, C2)."""
+    assert 0 <= rs < 500
+    L0 = _f64(L0)
+    R0 = _f64(R0)
+    H, W = L0.shape
+    cz = np.ascontiguousarray(coarse1, dtype=np.int16)
+    Hc, Wc = cz.shape
+    assert Hc == (H + 1) // 2 and Wc == (W + 1) // 2, "prior shape"
+    ds = np.empty((H, W), dtype=np.float64)
+    dh = np.empty((H, W), dtype=np.int16)
+    C = np.empty((H, W), dtype=np.float64)
+    C2 = np.empty((H, W), dtype=np.float64)
+    _load().orc_soft_level0(_p(L0, _D), _p(R0, _D), H, W, n, D, _p(cz, _I16), Hc, Wc, rs, tau,
+                            eps, _p(ds, _D), _p(dh, _I16), _p(C, _D), _p(C2, _D))
+    return ds, dh, C, C2
+
+
+def backward(L0: np.ndarray, R0: np.ndarray, n: int, D: int, coarse1: np.ndarray, rs: int,
+             tau: float, eps: float, gd: np.ndarray, rows: Optional[tuple] = None):
+    """(dL/dL0, dL/dR0) for L = sum gd * d_soft with the level-1 prior frozen.
+    `rows` = (i0, i1) restricts the contributing source pixels to those rows."""
+    assert 0 <= rs < 500
+    L0 = _f64(L0)
+    R0 = _f64(R0)
+    g = _f64(gd)
+    H, W = L0.shape
+    cz = np.ascontiguousarray(coarse1, dtype=np.int16)
+    Hc, Wc = cz.shape
+    assert Hc == (H + 1) // 2 and Wc == (W + 1) // 2, "prior shape"
+    i0, i1 = rows if rows is not None else (0, H)
+    gL = np.empty((H, W), dtype=np.float64)
+    gR = np.empty((H, W), dtype=np.float64)
+    _load().orc_backward(_p(L0, _D), _p(R0, _D), H, W, n, D, _p(cz, _I16), Hc, Wc, rs, tau, eps,
+                         _p(g, _D), int(i0), int(i1), _p(gL, _D), _p(gR, _D))
+    return gL, gR
+
+
+def loss_mask(nonocc: np.ndarray, n: int) -> np.ndarray:
+    """Pixels that enter the loss: visible in the right view and at least n pixels
+    from every border (a reading; the paper has no loss)."""
+    H, W = nonocc.shape
+    m = nonocc.copy()
+    m[:n, :] = False
+    m[H - n:, :] = False
+    m[:, :n] = False
+    m[:, W - n:] = False
+    return m
+
+
+def l1_loss(dsoft: np.ndarray, dgt: np.ndarray, mask: np.ndarray):
+    """Masked mean absolute error and its gradient with respect to d_soft
+    (sign(0) = 0)."""
+    cnt = int(mask.sum())
+    diff = dsoft - dgt
+    loss = float(np.abs(diff[mask]).sum() / max(cnt, 1))
+    g = np.where(mask, np.sign(diff), 0.0) / max(cnt, 1)
+    return loss, g

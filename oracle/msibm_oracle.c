@@ -1,0 +1,265 @@
+/*
+ * FP64 reference ("oracle") for the multi-scale hierarchical block matching hot
+ * path.  TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark call it; the product library never links, loads or calls
+ * it, and the two share no code.
+ *
+ * Every function below is the plain definition written out with direct loops in
+ * double precision: no running sums, no blocking, no reuse across candidates.
+ * Where the paper is silent or garbled, the adopted reading is stated at the
+ * function and listed with the others in the design notes.
+ *
+ * Conventions shared by all functions
+ *   - images are row-major double arrays, H rows by W columns, no padding;
+ *   - window reads clamp to the nearest edge pixel (replicate border);
+ *   - the right-image column of candidate z for left column j is j - z
+ *     (left-reference convention for rectified pairs);
+ *   - candidate z is valid iff 0 <= z <= min(D_k - 1, j).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+/* One Gaussian-pyramid step (Section III, K-level Gaussian pyramid).  The paper
+ * does not name the blur; the reading is the 5-tap binomial [1 4 6 4 1]/16 in
+ * each direction, sampled at even positions, output size ceil(H/2) x ceil(W/2),
+ * written here as the full 25-tap 2-D sum. */
+void orc_reduce(const double* in, int H, int W, double* out)
+{
+    static const double w[5] = {1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16};
+    const int Ho = (H + 1) / 2, Wo = (W + 1) / 2;
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < Ho; ++y) {
+        for (int x = 0; x < Wo; ++x) {
+            double s = 0.0;
+            for (int a = -2; a <= 2; ++a)
+                for (int b = -2; b <= 2; ++b)
+                    s += w[a + 2] * w[b + 2] *
+                         in[(size_t)clampi(2 * y + a, 0, H - 1) * W + clampi(2 * x + b, 0, W - 1)];
+            out[(size_t)y * Wo + x] = s;
+        }
+    }
+}
+
+/* Zero-mean normalised cross-correlation of the (2n+1)^2 window of L centred at
+ * (i, j) and the window of R centred at (i, j - z) (Eq. 2, with the matching
+ * cost of Eq. 1).  Readings: each view is centred by its own window mean and the
+ * normaliser is the product of the two window standard deviations, so the value
+ * is C / sqrt(A B) with A, B, C the centred sums of squares and cross products.
+ * A window is flat when its variance A / N is at most `eps`; a flat window scores
+ * 0.  The result is clamped to [-1, 1] against rounding. */
+double orc_zncc(const double* L, const double* R, int H, int W, int n,
+                int i, int j, int z, double eps)
+{
+    const int N = (2 * n + 1) * (2 * n + 1);
+    double sl = 0.0, sr = 0.0;
+    for (int a = -n; a <= n; ++a)
+        for (int b = -n; b <= n; ++b) {
+            const int y = clampi(i + a, 0, H - 1);
+            sl += L[(size_t)y * W + clampi(j + b, 0, W - 1)];
+            sr += R[(size_t)y * W + clampi(j - z + b, 0, W - 1)];
+        }
+    const double ml = sl / N, mr = sr / N;
+    double A = 0.0, B = 0.0, C = 0.0;
+    for (int a = -n; a <= n; ++a)
+        for (int b = -n; b <= n; ++b) {
+            const int y = clampi(i + a, 0, H - 1);
+            const double l = L[(size_t)y * W + clampi(j + b, 0, W - 1)] - ml;
+            const double r = R[(size_t)y * W + clampi(j - z + b, 0, W - 1)] - mr;
+            A += l * l;
+            B += r * r;
+            C += l * r;
+        }
+    if (A <= N * eps || B <= N * eps) return 0.0;
+    double rho = C / sqrt(A * B);
+    if (rho > 1.0) rho = 1.0;
+    if (rho < -1.0) rho = -1.0;
+    return rho;
+}
+
+/* Candidate interval of pixel (i, j) at one level.
+ * Full search (coarse == NULL, Eqs. 3-4): [0, min(D_k - 1, j)].
+ * Restricted search (Eqs. 8-9, first branch): the prior is the coarser map
+ * upsampled by nearest neighbour with its values doubled,
+ * dhat = 2 d^{k+1}(i/2, j/2); with c = min(dhat, j) the interval is
+ * [max(0, c - r), min(D_k - 1, j, c + r)].  Readings: the paper's open interval
+ * around dhat with "3 comparisons" is taken as the closed radius-r interval,
+ * and the prior is doubled because d_max halves per level. */
+static void cand_range(int i, int j, int Dk, const int16_t* coarse, int Wc,
+                       int r, int* lo, int* hi)
+{
+    int top = Dk - 1 < j ? Dk - 1 : j;
+    if (!coarse) {
+        *lo = 0;
+        *hi = top;
+        return;
+    }
+    int dh = 2 * (int)coarse[(size_t)(i / 2) * Wc + (j / 2)];
+    int c = dh < j ? dh : j;
+    *lo = c - r > 0 ? c - r : 0;
+    *hi = c + r < top ? c + r : top;
+}
+
+/* Winner-take-all matching of one level (Eqs. 3-4 for a full search, Eqs. 8-9
+ * first branch for a restricted one).  Outputs per pixel: d = the lowest valid z
+ * whose score is maximal (ties break to the lowest z), C = that score, and C2 =
+ * the second-largest score among the valid candidates (-inf when there is only
+ * one), so tests can tell genuine near-ties apart. */
+void orc_match_level(const double* L, const double* R, int H, int W, int n, int Dk,
+                     const int16_t* coarse, int Hc, int Wc, int r, double eps,
+                     int16_t* d, double* C, double* C2)
+{
+    (void)Hc;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int i = 0; i < H; ++i) {
+        for (int j = 0; j < W; ++j) {
+            int lo, hi;
+            cand_range(i, j, Dk, coarse, Wc, r, &lo, &hi);
+            double best = -INFINITY, second = -INFINITY;
+            int bz = lo;
+            for (int z = lo; z <= hi; ++z) {
+                const double rho = orc_zncc(L, R, H, W, n, i, j, z, eps);
+                if (rho > best) {
+                    second = best;
+                    best = rho;
+                    bz = z;
+                } else if (rho > second) {
+                    second = rho;
+                }
+            }
+            d[(size_t)i * W + j] = (int16_t)bz;
+            C[(size_t)i * W + j] = best;
+            C2[(size_t)i * W + j] = second;
+        }
+    }
+}
+
+/* Soft-argmax at the finest level (an addition to the paper: the differentiable
+ * form).  Candidates are the restricted interval of radius rs around the doubled
+ * level-1 prior; p_z = exp((rho_z - max rho) / tau) / sum, d_soft = sum p_z z.
+ * The hard winner-take-all over the same interval is returned too. */
+void orc_soft_level0(const double* L, const double* R, int H, int W, int n, int D,
+                     const int16_t* coarse, int Hc, int Wc, int rs, double tau, double eps,
+                     double* dsoft, int16_t* dhard, double* C, double* C2)
+{
+    (void)Hc;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int i = 0; i < H; ++i) {
+        double rho[1024];
+        for (int j = 0; j < W; ++j) {
+            int lo, hi;
+            cand_range(i, j, D, coarse, Wc, rs, &lo, &hi);
+            double best = -INFINITY, second = -INFINITY;
+            int bz = lo;
+            for (int z = lo; z <= hi; ++z) {
+                rho[z - lo] = orc_zncc(L, R, H, W, n, i, j, z, eps);
+                if (rho[z - lo] > best) {
+                    second = best;
+                    best = rho[z - lo];
+                    bz = z;
+                } else if (rho[z - lo] > second) {
+                    second = rho[z - lo];
+                }
+            }
+            double sp = 0.0, spz = 0.0;
+            for (int z = lo; z <= hi; ++z) {
+                const double p = exp((rho[z - lo] - best) / tau);
+                sp += p;
+                spz += p * z;
+            }
+            dsoft[(size_t)i * W + j] = spz / sp;
+            dhard[(size_t)i * W + j] = (int16_t)bz;
+            C[(size_t)i * W + j] = best;
+            C2[(size_t)i * W + j] = second;
+        }
+    }
+}
+
+/* Gradient of sum_{ij} gd(i,j) d_soft(i,j) with respect to every pixel of L and
+ * R, with the level-1 prior held fixed (it is piecewise constant in the inputs).
+ *   dd/drho_z = p_z (z - d_soft) / tau;
+ *   drho/dl_ab = (r_ab - mu_r)/sqrt(AB) - rho (l_ab - mu_l)/A;
+ *   drho/dr_ab = (l_ab - mu_l)/sqrt(AB) - rho (r_ab - mu_r)/B;
+ * flat candidates (score fixed at 0) contribute nothing; a clamped read passes
+ * its gradient to the edge pixel it read.  Only source pixels with rows in
+ * [i0, i1) contribute (i0 = 0, i1 = H for the whole image).  Serial on purpose:
+ * the scatter is written as the plain sum. */
+void orc_backward(const double* L, const double* R, int H, int W, int n, int D,
+                  const int16_t* coarse, int Hc, int Wc, int rs, double tau, double eps,
+                  const double* gd, int i0, int i1, double* gL, double* gR)
+{
+    (void)Hc;
+    const int N = (2 * n + 1) * (2 * n + 1);
+    memset(gL, 0, sizeof(double) * (size_t)H * W);
+    memset(gR, 0, sizeof(double) * (size_t)H * W);
+    double rho[1024], ml[1024], mr[1024], A[1024], B[1024], Cc[1024];
+    int flat[1024];
+    for (int i = i0; i < i1; ++i) {
+        for (int j = 0; j < W; ++j) {
+            const double g = gd[(size_t)i * W + j];
+            if (g == 0.0) continue;
+            int lo, hi;
+            cand_range(i, j, D, coarse, Wc, rs, &lo, &hi);
+            double best = -INFINITY;
+            for (int z = lo; z <= hi; ++z) {
+                const int q = z - lo;
+                double sl = 0.0, sr = 0.0;
+                for (int a = -n; a <= n; ++a)
+                    for (int b = -n; b <= n; ++b) {
+                        const int y = clampi(i + a, 0, H - 1);
+                        sl += L[(size_t)y * W + clampi(j + b, 0, W - 1)];
+                        sr += R[(size_t)y * W + clampi(j - z + b, 0, W - 1)];
+                    }
+                ml[q] = sl / N;
+                mr[q] = sr / N;
+                A[q] = B[q] = Cc[q] = 0.0;
+                for (int a = -n; a <= n; ++a)
+                    for (int b = -n; b <= n; ++b) {
+                        const int y = clampi(i + a, 0, H - 1);
+                        const double l = L[(size_t)y * W + clampi(j + b, 0, W - 1)] - ml[q];
+                        const double r = R[(size_t)y * W + clampi(j - z + b, 0, W - 1)] - mr[q];
+                        A[q] += l * l;
+                        B[q] += r * r;
+                        Cc[q] += l * r;
+                    }
+                flat[q] = (A[q] <= N * eps || B[q] <= N * eps);
+                if (flat[q]) {
+                    rho[q] = 0.0;
+                } else {
+                    rho[q] = Cc[q] / sqrt(A[q] * B[q]);
+                    if (rho[q] > 1.0) rho[q] = 1.0;
+                    if (rho[q] < -1.0) rho[q] = -1.0;
+                }
+                if (rho[q] > best) best = rho[q];
+            }
+            double sp = 0.0, spz = 0.0;
+            double p[1024];
+            for (int z = lo; z <= hi; ++z) {
+                p[z - lo] = exp((rho[z - lo] - best) / tau);
+                sp += p[z - lo];
+                spz += p[z - lo] * z;
+            }
+            const double ds = spz / sp;
+            for (int z = lo; z <= hi; ++z) {
+                const int q = z - lo;
+                if (flat[q]) continue;
+                const double gz = g * (p[q] / sp) * (z - ds) / tau;
+                const double s = sqrt(A[q] * B[q]);
+                const double rr = Cc[q] / s;
+                for (int a = -n; a <= n; ++a)
+                    for (int b = -n; b <= n; ++b) {
+                        const int y = clampi(i + a, 0, H - 1);
+                        const size_t il = (size_t)y * W + clampi(j + b, 0, W - 1);
+                        const size_t ir = (size_t)y * W + clampi(j - z + b, 0, W - 1);
+                        const double l = L[il] - ml[q];
+                        const double r = R[ir] - mr[q];
+                        gL[il] += gz * (r / s - rr * l / A[q]);
+                        gR[ir] += gz * (l / s - rr * r / B[q]);
+                    }
+            }
+        }
+    }
+}

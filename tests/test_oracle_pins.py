@@ -1,0 +1,336 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types the oracle's formulas: each check uses a library routine
+(numpy's Pearson correlation, scipy's correlation filter), a closed form, an
+invariant or brute force on tiny inputs, so a dropped term, a wrong sign or index,
+or a transposed operand in the oracle fails at least one of them.
+"""
+import numpy as np
+import pytest
+from scipy import ndimage
+
+import oracle
+from paper_1901_09593_amd import synth
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _window(img, i, j, n):
+    """Clamp-to-edge (2n+1)^2 window via numpy's edge padding."""
+    p = np.pad(img, n, mode="edge")
+    return p[i:i + 2 * n + 1, j:j + 2 * n + 1]
+
+
+def _pearson(a, b):
+    return float(np.corrcoef(a.ravel(), b.ravel())[0, 1])
+
+
+# ---------------------------------------------------------------- ZNCC (Eq. 2)
+
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_zncc_equals_pearson_interior_and_border(n):
+    rng = _rng(1)
+    L = rng.random((15, 19))
+    R = rng.random((15, 19))
+    for (i, j, z) in [(7, 9, 0), (7, 9, 3), (0, 0, 0), (14, 18, 5), (3, 4, 4), (10, 2, 2),
+                      (1, 18, 18)]:
+        ref = _pearson(_window(L, i, j, n), _window(R, i, j - z, n))
+        got = oracle.zncc(L, R, n, i, j, z, 1e-12)
+        assert abs(got - ref) < 1e-12, (i, j, z, got, ref)
+
+
+@pytest.mark.parametrize("a,b", [(2.5, 0.3), (-0.7, 4.0), (1e-3, -9.0)])
+def test_zncc_linear_relation_closed_form(a, b):
+    # R(y, x) = a L(y, x + z0) + b: the right window at (i, j - z0) is an affine
+    # image of the left window at (i, j), so the score is exactly sign(a).
+    rng = _rng(2)
+    z0, n = 4, 2
+    T = rng.random((12, 30))
+    L = T[:, :26]
+    R = a * T[:, z0:z0 + 26] + b
+    for (i, j) in [(5, 10), (6, 20), (2, 13)]:
+        got = oracle.zncc(L, R, n, i, j, z0, 0.0)
+        assert abs(got - np.sign(a)) < 1e-12
+        other = oracle.zncc(L, R, n, i, j, z0 + 1, 0.0)
+        assert abs(other) < 0.999  # the wrong shift does not reach the bound
+
+
+def test_zncc_gain_offset_invariance_and_bounds():
+    rng = _rng(3)
+    L = rng.random((13, 17))
+    R = rng.random((13, 17))
+    for (i, j, z) in [(6, 8, 2), (0, 16, 7), (12, 5, 0)]:
+        base = oracle.zncc(L, R, 2, i, j, z, 1e-12)
+        assert -1.0 <= base <= 1.0
+        assert abs(oracle.zncc(L, 3.0 * R + 7.0, 2, i, j, z, 1e-12) - base) < 1e-12
+        assert abs(oracle.zncc(0.25 * L - 1.0, R, 2, i, j, z, 1e-12) - base) < 1e-12
+        assert abs(oracle.zncc(L, -2.0 * R, 2, i, j, z, 1e-12) + base) < 1e-12
+
+
+def test_zncc_identical_windows_and_flat_windows():
+    rng = _rng(4)
+    L = rng.random((9, 9))
+    assert abs(oracle.zncc(L, L, 2, 4, 4, 0, 1e-12) - 1.0) < 1e-12
+    flat = np.full((9, 9), 0.5)
+    assert oracle.zncc(L, flat, 2, 4, 4, 0, 1e-12) == 0.0
+    assert oracle.zncc(flat, L, 2, 4, 4, 0, 1e-12) == 0.0
+    # variance floor: a window with variance below eps scores 0, above it does not
+    tiny = 0.5 + 1e-4 * rng.standard_normal((9, 9))
+    var = np.var(_window(tiny, 4, 4, 2))
+    assert oracle.zncc(L, tiny, 2, 4, 4, 0, var * 1.01) == 0.0
+    assert oracle.zncc(L, tiny, 2, 4, 4, 0, var * 0.99) != 0.0
+
+
+# ----------------------------------------------------------- pyramid (Sec. III)
+
+@pytest.mark.parametrize("shape", [(16, 16), (17, 23), (5, 3), (1, 7)])
+def test_reduce_equals_scipy_binomial_filter(shape):
+    rng = _rng(5)
+    img = rng.random(shape) * 255
+    w = np.array([1, 4, 6, 4, 1], dtype=np.float64) / 16
+    ref = ndimage.correlate(img, np.outer(w, w), mode="nearest")[::2, ::2]
+    got = oracle.reduce(img)
+    assert got.shape == ((shape[0] + 1) // 2, (shape[1] + 1) // 2)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-12)
+
+
+def test_reduce_constant_and_linear():
+    assert np.all(oracle.reduce(np.full((11, 14), 37.0)) == 37.0)
+    # the binomial kernel is symmetric with unit sum, so a linear image keeps its
+    # value at the sampled positions away from the border
+    yy, xx = np.mgrid[0:20, 0:24].astype(np.float64)
+    img = 3.0 * xx - 2.0 * yy + 5.0
+    out = oracle.reduce(img)
+    inner = out[1:-1, 1:-1]
+    ys, xs = np.mgrid[1:out.shape[0] - 1, 1:out.shape[1] - 1]
+    np.testing.assert_allclose(inner, 3.0 * 2 * xs - 2.0 * 2 * ys + 5.0, atol=1e-12)
+
+
+def test_pyramid_levels_and_sizes():
+    img = _rng(6).integers(0, 256, size=(37, 50)).astype(np.uint8)
+    lv = oracle.pyramid(img, 4)
+    assert [l.shape for l in lv] == [(37, 50), (19, 25), (10, 13), (5, 7)]
+    # uint8 input: level k values are multiples of 2^-8k (dyadic weights)
+    for k in (1, 2):
+        scaled = lv[k] * (1 << (8 * k))
+        assert np.all(scaled == np.rint(scaled))
+
+
+# ------------------------------------------------ winner-take-all (Eqs. 3-4, 8-9)
+
+def _brute_level(L, R, n, Dk, coarse, r, eps):
+    """Exhaustive search with Pearson scores from numpy; lowest z on ties."""
+    H, W = L.shape
+    d = np.zeros((H, W), dtype=np.int16)
+    C = np.zeros((H, W))
+    for i in range(H):
+        for j in range(W):
+            top = min(Dk - 1, j)
+            if coarse is None:
+                lo, hi = 0, top
+            else:
+                c = min(2 * int(coarse[i // 2, j // 2]), j)
+                lo, hi = max(0, c - r), min(top, c + r)
+            best, bz = -np.inf, lo
+            for z in range(lo, hi + 1):
+                lw = _window(L, i, j, n)
+                rw = _window(R, i, j - z, n)
+                if lw.var() <= eps or rw.var() <= eps:
+                    s = 0.0
+                else:
+                    s = _pearson(lw, rw)
+                if s > best:
+                    best, bz = s, z
+            d[i, j] = bz
+            C[i, j] = best
+    return d, C
+
+
+@pytest.mark.parametrize("shape,n,D", [((12, 10), 1, 6), ((9, 17), 2, 5), ((7, 8), 1, 3)])
+def test_full_search_brute_force(shape, n, D):
+    rng = _rng(7)
+    L = rng.integers(0, 256, size=shape).astype(np.float64)
+    R = rng.integers(0, 256, size=shape).astype(np.float64)
+    L[:3, :3] = 9.0  # a flat patch exercises the floor
+    d, C, C2 = oracle.match_level(L, R, n, D, None, 0, 0.065)
+    bd, bC = _brute_level(L, R, n, D, None, 0, 0.065)
+    assert np.array_equal(d, bd)
+    np.testing.assert_allclose(C, bC, atol=1e-12)
+    assert np.all(C >= C2)
+
+
+@pytest.mark.parametrize("r", [0, 1, 2])
+def test_restricted_search_brute_force(r):
+    rng = _rng(8)
+    H, W, D, n = 11, 14, 8, 1
+    L = rng.random((H, W))
+    R = rng.random((H, W))
+    coarse = rng.integers(0, (D + 1) // 2, size=((H + 1) // 2, (W + 1) // 2)).astype(np.int16)
+    d, C, _ = oracle.match_level(L, R, n, D, coarse, r, 1e-9)
+    bd, bC = _brute_level(L, R, n, D, coarse, r, 1e-9)
+    assert np.array_equal(d, bd)
+    np.testing.assert_allclose(C, bC, atol=1e-12)
+
+
+def test_ties_break_to_lowest_disparity():
+    # a texture periodic in x with period p: the right view equals the left one,
+    # so z = 0 and z = p tie at score 1 in the interior; the lowest must win
+    p, n = 5, 2
+    base = _rng(9).random((16, p))
+    L = np.tile(base, (1, 8))
+    d, C, C2 = oracle.match_level(L, L, n, 12, None, 0, 1e-12)
+    inner = (slice(n, -n), slice(p + n, -n))
+    assert np.all(d[inner] == 0)
+    assert np.allclose(C[inner], 1.0) and np.allclose(C2[inner], 1.0)
+
+
+def _shifted_pair(H, W, s, seed=10):
+    T = synth.texture(_rng(seed), H, W + s) * 255
+    return T[:, :W].copy(), T[:, s:s + W].copy()
+
+
+@pytest.mark.parametrize("K,s", [(3, 8), (2, 6), (4, 16)])
+def test_constant_shift_recovered_at_every_level(K, s):
+    # R(y, x - s) = L(y, x); decimation commutes with shifts that are multiples of
+    # 2^(K-1), so every level recovers s / 2^k away from the borders
+    H, W, n, D = 64, 96, 2, 40
+    L, R = _shifted_pair(H, W, s)
+    out = oracle.disparity(L, R, D, K, n, 1, 0.065)
+    for k in range(K):
+        dk = out[k][0]
+        m = 3 * (1 << (K - 1 - k)) + n + 3
+        inner = dk[m:-m, s // (1 << k) + m:-m]
+        assert np.all(inner == s >> k), (k, np.unique(inner))
+
+
+def test_odd_shift_recovered_at_level_zero():
+    H, W, n, D = 48, 80, 2, 30
+    L, R = _shifted_pair(H, W, 7, seed=11)
+    out = oracle.disparity(L, R, D, 2, n, 2, 0.065)
+    inner = out[0][0][8:-8, 7 + 8:-8]
+    assert np.all(inner == 7)
+
+
+def test_single_level_equals_flat_and_wide_refine_equals_flat():
+    p = synth.make_pair(3, 40, 64, 3, 2, 14, True, 1.0, 0.0, 1.0, "u8")
+    eps, n, D = 0.065, 2, 16
+    flat = oracle.flat_bm(p.left, p.right, D, n, eps)
+    one = oracle.disparity(p.left, p.right, D, 1, n, 2, eps)[0]
+    assert np.array_equal(flat[0], one[0])
+    # a refine radius covering every candidate makes level 0 a full search,
+    # whatever the prior says
+    rnd = _rng(12).integers(0, 8, size=(20, 32)).astype(np.int16)
+    wide = oracle.disparity(p.left, p.right, D, 2, n, 2 * D, eps, priors=[rnd, None])[0]
+    assert np.array_equal(flat[0], wide[0])
+    np.testing.assert_allclose(flat[1], wide[1], atol=1e-12)
+
+
+def test_disparity_invariant_to_right_gain_and_offset():
+    p = synth.make_pair(4, 48, 72, 4, 2, 20, True, 1.0, 0.0, 2.0, "u8")
+    L = p.left.astype(np.float64)
+    R = p.right.astype(np.float64)
+    a = oracle.disparity(L, R, 24, 3, 2, 2, 0.065)
+    b = oracle.disparity(L, 0.8 * R + 11.0, 24, 3, 2, 2, 0.065 * 0.64)
+    for k in range(3):
+        gap = a[k][1] - a[k][2]
+        same = (a[k][0] == b[k][0]) | (gap < 1e-9)
+        assert same.all()
+
+
+def test_prior_range_never_exceeds_level_range():
+    # 2 d^{k+1} <= D_k - 1 whenever d^{k+1} <= D_{k+1} - 1
+    for D in range(1, 1200):
+        for k in range(0, 7):
+            Dk, Dk1 = oracle.level_range(D, k), oracle.level_range(D, k + 1)
+            assert 2 * (Dk1 - 1) <= Dk - 1
+
+
+# --------------------------------------------------- soft-argmax and gradient
+
+def _soft_case(seed=13, H=12, W=16, D=8):
+    rng = _rng(seed)
+    L = rng.random((H, W))
+    R = rng.random((H, W))
+    coarse = rng.integers(0, (D + 1) // 2, size=((H + 1) // 2, (W + 1) // 2)).astype(np.int16)
+    return L, R, coarse
+
+
+def test_soft_argmax_limits():
+    L, R, coarse = _soft_case()
+    n, D, rs = 1, 8, 2
+    ds, dh, C, C2 = oracle.soft_level0(L, R, n, D, coarse, rs, 1e-4, 1e-9)
+    sharp = (C - C2) > 0.01
+    np.testing.assert_allclose(ds[sharp], dh[sharp], atol=1e-12)
+    ds_hot, *_ = oracle.soft_level0(L, R, n, D, coarse, rs, 1e9, 1e-9)
+    H, W = L.shape
+    for i in range(H):
+        for j in range(W):
+            c = min(2 * int(coarse[i // 2, j // 2]), j)
+            lo, hi = max(0, c - rs), min(D - 1, j, c + rs)
+            assert abs(ds_hot[i, j] - 0.5 * (lo + hi)) < 1e-6
+    one, *_ = oracle.soft_level0(L, R, n, 1, np.zeros_like(coarse), rs, 0.05, 1e-9)
+    assert np.all(one == 0.0)
+
+
+@pytest.mark.parametrize("n,rs", [(1, 2), (2, 1)])
+def test_backward_matches_central_differences(n, rs):
+    L, R, coarse = _soft_case(seed=14, H=10, W=13)
+    D, tau, eps = 8, 0.3, 1e-12
+    g = _rng(15).standard_normal(L.shape)
+    gL, gR = oracle.backward(L, R, n, D, coarse, rs, tau, eps, g)
+
+    def f(Lx, Rx):
+        ds, *_ = oracle.soft_level0(Lx, Rx, n, D, coarse, rs, tau, eps)
+        return float((g * ds).sum())
+
+    h = 1e-6
+    fdL = np.zeros_like(L)
+    fdR = np.zeros_like(R)
+    for idx in np.ndindex(L.shape):
+        e = np.zeros_like(L)
+        e[idx] = h
+        fdL[idx] = (f(L + e, R) - f(L - e, R)) / (2 * h)
+        fdR[idx] = (f(L, R + e) - f(L, R - e)) / (2 * h)
+    for got, ref in ((gL, fdL), (gR, fdR)):
+        rel = np.linalg.norm(got - ref) / np.linalg.norm(ref)
+        assert rel < 1e-6, rel
+
+
+def test_backward_sum_rules():
+    # adding a constant to, or scaling, either view leaves every score unchanged,
+    # so sum dL/dI = 0 and sum I dL/dI = 0 for both views
+    L, R, coarse = _soft_case(seed=16, H=14, W=18, D=10)
+    g = _rng(17).standard_normal(L.shape)
+    gL, gR = oracle.backward(L, R, 2, 10, coarse, 2, 0.05, 1e-12, g)
+    scale = np.abs(gL).sum() + np.abs(gR).sum()
+    assert scale > 0
+    for grad, img in ((gL, L), (gR, R)):
+        assert abs(grad.sum()) < 1e-12 * scale * 10
+        assert abs((grad * img).sum()) < 1e-12 * scale * 10
+
+
+def test_backward_row_restriction_is_a_partition():
+    L, R, coarse = _soft_case(seed=18, H=12, W=12)
+    g = _rng(19).standard_normal(L.shape)
+    full = oracle.backward(L, R, 1, 8, coarse, 2, 0.1, 1e-12, g)
+    a = oracle.backward(L, R, 1, 8, coarse, 2, 0.1, 1e-12, g, rows=(0, 5))
+    b = oracle.backward(L, R, 1, 8, coarse, 2, 0.1, 1e-12, g, rows=(5, 12))
+    np.testing.assert_allclose(full[0], a[0] + b[0], atol=1e-12)
+    np.testing.assert_allclose(full[1], a[1] + b[1], atol=1e-12)
+
+
+def test_l1_loss_gradient():
+    rng = _rng(20)
+    ds = rng.random((6, 7)) * 10
+    gt = rng.random((6, 7)) * 10
+    m = rng.random((6, 7)) > 0.3
+    loss, g = oracle.l1_loss(ds, gt, m)
+    assert abs(loss - np.abs(ds - gt)[m].mean()) < 1e-12
+    h = 1e-7
+    for idx in [(0, 0), (2, 3), (5, 6)]:
+        e = np.zeros_like(ds)
+        e[idx] = h
+        fd = (oracle.l1_loss(ds + e, gt, m)[0] - oracle.l1_loss(ds - e, gt, m)[0]) / (2 * h)
+        assert abs(fd - g[idx]) < 1e-6
