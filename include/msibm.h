@@ -1,0 +1,215 @@
+/*
+ * msibm.h - C ABI of the MI355X (gfx950) multi-scale hierarchical block matching
+ * library (libmsibm.so).
+ *
+ * The method (Kaushik and Lall, "Fast Hierarchical depth map computation from
+ * stereo", Section III): build a K-level Gaussian pyramid of a rectified stereo
+ * pair, find every pixel's disparity at the coarsest level by a full
+ * winner-take-all search of the zero-mean normalised cross-correlation (ZNCC,
+ * Eq. 2) over the disparity search image of Eq. 1 (Eqs. 3-4), then at each finer
+ * level search only a small interval around the nearest-neighbour-upsampled
+ * coarser disparity (Eqs. 8-9, first branch).  The confidence gates and the
+ * median filter (Eqs. 5-7, 10) are not part of this library.
+ *
+ * Conventions used by every entry point
+ *   - All image, map and gradient pointers are DEVICE pointers allocated by the
+ *     caller (for instance by torch).  The library never allocates memory that
+ *     the caller sees; scratch comes from a caller-provided workspace whose size
+ *     the *_workspace_size functions give.  Pointers are not retained after a
+ *     call returns (except inside a captured graph, see MSIBM_FLAG_GRAPH).
+ *   - Images are row-major with a row pitch counted in ELEMENTS (pitch >= width).
+ *     Pixel (i, j) is row i, column j.
+ *   - Disparity convention: left pixel (i, j) is compared with right pixel
+ *     (i, j - z) (left-reference convention for rectified pairs).  Candidate z
+ *     is valid iff 0 <= z <= min(D_k - 1, j).
+ *   - Level k has height ceil(H_{k-1}/2) and width ceil(W_{k-1}/2) and searches
+ *     D_k = ceil(D / 2^k) candidates (the paper's d_max^k = D_max / 2^k with D
+ *     counting candidates).
+ *   - Window reads clamp to the nearest edge pixel.  A window whose variance is
+ *     at most var_eps is flat and scores 0.  Ties break to the lowest z.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  Every
+ *     call only enqueues work on that stream and returns; outputs are valid once
+ *     the stream has reached that point.
+ *   - Every entry point validates its arguments before enqueuing anything.  On
+ *     a validation error nothing is enqueued and a negative msibm_status is
+ *     returned; msibm_last_error() then describes it (thread-local string).
+ *     MSIBM_ERR_HIP reports a failure of the HIP runtime (launch or capture).
+ */
+#ifndef MSIBM_H
+#define MSIBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t msibm_status;
+
+#define MSIBM_OK 0
+#define MSIBM_ERR_INVALID_ARG (-1) /* null pointer, negative size, bad enum   */
+#define MSIBM_ERR_SHAPE (-2)       /* sizes inconsistent or too small/large   */
+#define MSIBM_ERR_WORKSPACE (-3)   /* workspace missing or too small          */
+#define MSIBM_ERR_UNSUPPORTED (-4) /* parameter outside the compiled range    */
+#define MSIBM_ERR_HIP (-5)         /* HIP runtime error                       */
+#define MSIBM_ERR_DEADLOCK (-6)    /* batched scheduler watchdog fired        */
+
+/* element types of input images */
+#define MSIBM_U8 0  /* uint8_t, intensity range 0..255 */
+#define MSIBM_F32 1 /* float                             */
+
+#define MSIBM_MAX_LEVELS 8        /* K <= 8                                  */
+#define MSIBM_MAX_HALF_WINDOW 6   /* n <= 6: windows up to 13 x 13           */
+#define MSIBM_MAX_RADIUS 4        /* refine and soft radius <= 4             */
+#define MSIBM_MAX_DISP 2048       /* D <= 2048                               */
+#define MSIBM_MAX_PAIRS 256       /* pairs per msibm_disparity call          */
+
+/* flags of msibm_config.flags */
+#define MSIBM_FLAG_BATCHED 1 /* all pairs and levels in one persistent launch */
+#define MSIBM_FLAG_GRAPH 2   /* with BATCHED: capture once, replay a hipGraph */
+
+/* One rectified stereo pair.  left/right are device pointers of `dtype`. */
+typedef struct msibm_pair {
+    const void* left;
+    const void* right;
+    int32_t dtype;      /* MSIBM_U8 or MSIBM_F32                               */
+    int32_t height;     /* H >= 1                                              */
+    int32_t width;      /* W >= 1                                              */
+    int32_t pitch;      /* row pitch of left and right, elements, >= W         */
+    int32_t max_disp;   /* D: candidates 0..D-1 at level 0, 1 <= D <= 2048     */
+    int32_t num_levels; /* K: pyramid images (level 0 = input); 0 = automatic:
+                           the smallest K with D_{K-1} <= 32                   */
+} msibm_pair;
+
+/* Matching parameters shared by all pairs of a call. */
+typedef struct msibm_config {
+    int32_t half_window;   /* n: windows are (2n+1) x (2n+1), 1 <= n <= 6       */
+    int32_t refine_radius; /* r: restricted search [c-r, c+r], 0 <= r <= 4       */
+    float var_eps;         /* flat-window variance floor, intensity^2 units     */
+    int32_t soft_radius;   /* r_s: 0 = hard WTA at level 0; 1..4 = level 0 also
+                              computes the soft-argmax over [c-r_s, c+r_s] and
+                              its hard WTA is taken over that interval          */
+    float tau;             /* soft-argmax temperature, > 0 when soft_radius > 0 */
+    int32_t flags;         /* MSIBM_FLAG_*                                      */
+} msibm_config;
+
+/* Thread-local description of the last error of this thread ("" if none). */
+const char* msibm_last_error(void);
+
+/* Library version string. */
+const char* msibm_version(void);
+
+/*
+ * msibm_pyramid - the K-level Gaussian pyramid of one image (Section III).
+ * The blur is the separable 5-tap binomial [1 4 6 4 1]/16 with clamp-to-edge
+ * reads, sampled at even rows and columns.
+ *   img         device image of `dtype`, H x W, row pitch `pitch` elements.
+ *   levels[k]   K device float pointers; levels[0] receives img converted to
+ *               float (exact for uint8), levels[k] the level-k image of size
+ *               H_k x W_k with row pitch level_pitch[k] >= W_k.
+ *   level_pitch host array of K pitches.
+ * Errors: INVALID_ARG (null pointer, bad dtype), SHAPE (H, W < 1, pitches),
+ *         UNSUPPORTED (K outside 1..MSIBM_MAX_LEVELS), HIP.
+ */
+msibm_status msibm_pyramid(const void* img, int32_t dtype, int32_t H, int32_t W, int32_t pitch,
+                           int32_t K, float* const* levels, const int32_t* level_pitch,
+                           void* stream);
+
+/* Bytes of workspace msibm_match_level needs for an H x W level. */
+size_t msibm_level_workspace_size(int32_t H, int32_t W);
+
+/*
+ * msibm_match_level - winner-take-all ZNCC matching of one pyramid level.
+ *   prior == NULL: full search of z in [0, min(D_k - 1, j)] (Eqs. 3-4; also
+ *                  standard block matching when applied at level 0 with D).
+ *   prior != NULL: restricted search (Eqs. 8-9, first branch).  `prior` is the
+ *                  level-(k+1) disparity map, Hc x Wc int16 with Hc =
+ *                  ceil(H/2), Wc = ceil(W/2), row pitch prior_pitch; pixel
+ *                  (i, j) takes c = min(2 prior(i/2, j/2), j) and searches
+ *                  [max(0, c - r), min(D_k - 1, j, c + r)].
+ *   L, R       device images of `dtype` (MSIBM_U8 or MSIBM_F32), H x W, pitch.
+ *   d_out      device int16 H x W (row pitch out_pitch): lowest z of the best score.
+ *   cost_out   device float H x W or NULL: the best score (Eq. 4 / Eq. 9).
+ *   workspace  device scratch of msibm_level_workspace_size(H, W) bytes.
+ * Errors: INVALID_ARG, SHAPE (sizes, pitches, prior shape), UNSUPPORTED (n, r,
+ *         D_k out of range), WORKSPACE, HIP.
+ */
+msibm_status msibm_match_level(const void* L, const void* R, int32_t dtype, int32_t H, int32_t W,
+                               int32_t pitch, int32_t n, int32_t Dk, const int16_t* prior,
+                               int32_t Hc, int32_t Wc, int32_t prior_pitch, int32_t r,
+                               float var_eps, int16_t* d_out, float* cost_out, int32_t out_pitch,
+                               void* workspace, size_t ws_bytes, void* stream);
+
+/* Bytes of workspace msibm_disparity / msibm_backward need for these pairs. */
+size_t msibm_workspace_size(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg);
+
+/*
+ * msibm_disparity - the hierarchical forward pass for n_pairs stereo pairs.
+ * For each pair: pyramid of both views, full search at level K-1, restricted
+ * search at levels K-2..0, each level's prior being the next coarser map.
+ *   pairs, cfg     host arrays/structs (copied; need not outlive the call unless
+ *                  MSIBM_FLAG_GRAPH, which caches by shape, see below).
+ *   disp[p]        device int16 H x W (row pitch = pairs[p].width): level-0 map.
+ *   cost[p]        NULL or NULL entries, or device float H x W: level-0 score.
+ *   soft_disp[p]   required iff cfg->soft_radius > 0: device float H x W,
+ *                  sum_z p_z z with p = softmax(score / tau) over level 0's
+ *                  candidates (an addition to the paper: the differentiable form).
+ *   prior1[p]      NULL, or device int16 H_1 x W_1 (pitch W_1) receiving the
+ *                  level-1 map (the prior of level 0) that msibm_backward needs;
+ *                  unused when K == 1.
+ *   workspace      device scratch of msibm_workspace_size(pairs, n_pairs, cfg).
+ * Without MSIBM_FLAG_BATCHED the pairs run one after another (plain path).  With
+ * it every pair and level runs in ONE persistent kernel launch with a device
+ * task queue; with MSIBM_FLAG_GRAPH too, that launch (and the queue reset) is
+ * captured in a hipGraph keyed by the pairs' shapes, pointers and cfg and
+ * replayed on later calls with the same key.
+ * Errors: INVALID_ARG, SHAPE, UNSUPPORTED, WORKSPACE, HIP, DEADLOCK.
+ */
+msibm_status msibm_disparity(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg,
+                             int16_t* const* disp, float* const* cost, float* const* soft_disp,
+                             int16_t* const* prior1, void* workspace, size_t ws_bytes,
+                             void* stream);
+
+/*
+ * msibm_backward - gradient of sum_{ij} g(i,j) d_soft(i,j) with respect to the
+ * level-0 left and right images, with the level-1 prior held fixed (it is
+ * piecewise constant in the images).  Recomputes every window statistic and
+ * score; no cost volume is stored.  The gradient flows through
+ *   d_soft = sum_z p_z z,  p = softmax(rho / tau)  ->  dd/drho_z = p_z (z - d_soft) / tau,
+ *   rho = C / sqrt(A B)  ->  drho/dl = (r - mu_r)/sqrt(AB) - rho (l - mu_l)/A  (and
+ *   symmetrically for r); flat candidates contribute nothing and a clamped read
+ *   passes its gradient to the edge pixel it read.
+ *   pairs[p]        must be MSIBM_F32 (UNSUPPORTED otherwise), K >= 2.
+ *   cfg             as in the forward call, soft_radius >= 1.
+ *   prior1[p]       device int16 level-1 map saved by msibm_disparity.
+ *   grad_soft[p]    device float H x W (pitch W): dL/dd_soft.
+ *   grad_left[p], grad_right[p]  device float H x W (pitch W), OVERWRITTEN.
+ *   workspace       as for msibm_disparity.
+ * Errors: INVALID_ARG, SHAPE, UNSUPPORTED, WORKSPACE, HIP.
+ */
+msibm_status msibm_backward(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg,
+                            const int16_t* const* prior1, const float* const* grad_soft,
+                            float* const* grad_left, float* const* grad_right, void* workspace,
+                            size_t ws_bytes, void* stream);
+
+/*
+ * Launch timing (instrumentation, off by default).  While enabled, every kernel
+ * launch that msibm_disparity and msibm_backward enqueue is bracketed by two HIP
+ * events on the launch stream, labelled by kernel and level (for example
+ * "match_refine_l0").  Enabling or disabling clears the accumulated totals.
+ */
+msibm_status msibm_timing_enable(int32_t on);
+
+/*
+ * Waits for every pending timed launch, folds it into per-label totals and
+ * writes up to `cap` entries: labels (64 chars each, NUL-terminated, may be
+ * NULL), total milliseconds and launch counts.  Returns the entry count.
+ */
+int32_t msibm_timing_read(int32_t cap, char* labels, double* total_ms, int32_t* counts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSIBM_H */

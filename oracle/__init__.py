@@ -64,6 +64,13 @@ def _load():
         lib.orc_backward.argtypes = [_D, _D, c_int, c_int, c_int, c_int, _I16, c_int, c_int,
                                      c_int, c_double, c_double, _D, c_int, c_int, _D, _D]
         lib.orc_backward.restype = None
+        _I32P = ctypes.POINTER(ctypes.c_int32)
+        lib.orc_zncc_many.argtypes = [_D, _D, c_int, c_int, c_int, c_double, _I32P, _I32P, _I32P,
+                                      c_int, _D]
+        lib.orc_zncc_many.restype = None
+        lib.orc_match_pixels.argtypes = [_D, _D, c_int, c_int, c_int, c_int, _I16, c_int, c_int,
+                                         c_int, c_double, _I32P, _I32P, c_int, _I16, _D, _D]
+        lib.orc_match_pixels.restype = None
         _lib = lib
     return _lib
 
@@ -112,6 +119,47 @@ def zncc(L: np.ndarray, R: np.ndarray, n: int, i: int, j: int, z: int, eps: floa
     R = _f64(R)
     H, W = L.shape
     return _load().orc_zncc(_p(L, _D), _p(R, _D), H, W, n, i, j, z, eps)
+
+
+def zncc_many(L: np.ndarray, R: np.ndarray, n: int, ii, jj, zz, eps: float) -> np.ndarray:
+    """Scores at arrays of (i, j, z) triples."""
+    L = _f64(L)
+    R = _f64(R)
+    H, W = L.shape
+    ii = np.ascontiguousarray(ii, dtype=np.int32)
+    jj = np.ascontiguousarray(jj, dtype=np.int32)
+    zz = np.ascontiguousarray(zz, dtype=np.int32)
+    assert ii.shape == jj.shape == zz.shape
+    out = np.empty(ii.shape, dtype=np.float64)
+    I32P = ctypes.POINTER(ctypes.c_int32)
+    _load().orc_zncc_many(_p(L, _D), _p(R, _D), H, W, n, eps, _p(ii, I32P), _p(jj, I32P),
+                          _p(zz, I32P), ii.size, _p(out, _D))
+    return out
+
+
+def match_pixels(L: np.ndarray, R: np.ndarray, n: int, Dk: int, coarse: Optional[np.ndarray],
+                 r: int, eps: float, ii, jj):
+    """match_level evaluated only at the pixels (ii[q], jj[q]); returns (d, C, C2)."""
+    L = _f64(L)
+    R = _f64(R)
+    H, W = L.shape
+    ii = np.ascontiguousarray(ii, dtype=np.int32)
+    jj = np.ascontiguousarray(jj, dtype=np.int32)
+    cnt = ii.size
+    d = np.empty(cnt, dtype=np.int16)
+    C = np.empty(cnt, dtype=np.float64)
+    C2 = np.empty(cnt, dtype=np.float64)
+    if coarse is not None:
+        cz = np.ascontiguousarray(coarse, dtype=np.int16)
+        Hc, Wc = cz.shape
+        assert Hc == (H + 1) // 2 and Wc == (W + 1) // 2, "prior shape"
+        cptr = _p(cz, _I16)
+    else:
+        cz, Hc, Wc, cptr = None, 0, 0, None
+    I32P = ctypes.POINTER(ctypes.c_int32)
+    _load().orc_match_pixels(_p(L, _D), _p(R, _D), H, W, n, Dk, cptr, Hc, Wc, r, eps,
+                             _p(ii, I32P), _p(jj, I32P), cnt, _p(d, _I16), _p(C, _D), _p(C2, _D))
+    return d, C, C2
 
 
 def match_level(L: np.ndarray, R: np.ndarray, n: int, Dk: int,

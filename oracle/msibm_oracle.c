@@ -263,3 +263,41 @@ void orc_backward(const double* L, const double* R, int H, int W, int n, int D,
         }
     }
 }
+
+/* Scores at a list of (i, j, z) triples (Eq. 2), for sampled comparisons. */
+void orc_zncc_many(const double* L, const double* R, int H, int W, int n, double eps,
+                   const int32_t* ii, const int32_t* jj, const int32_t* zz, int count, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int q = 0; q < count; ++q) out[q] = orc_zncc(L, R, H, W, n, ii[q], jj[q], zz[q], eps);
+}
+
+/* orc_match_level restricted to a list of pixels (same outputs, one per pixel). */
+void orc_match_pixels(const double* L, const double* R, int H, int W, int n, int Dk,
+                      const int16_t* coarse, int Hc, int Wc, int r, double eps,
+                      const int32_t* ii, const int32_t* jj, int count,
+                      int16_t* d, double* C, double* C2)
+{
+    (void)Hc;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int q = 0; q < count; ++q) {
+        const int i = ii[q], j = jj[q];
+        int lo, hi;
+        cand_range(i, j, Dk, coarse, Wc, r, &lo, &hi);
+        double best = -INFINITY, second = -INFINITY;
+        int bz = lo;
+        for (int z = lo; z <= hi; ++z) {
+            const double rho = orc_zncc(L, R, H, W, n, i, j, z, eps);
+            if (rho > best) {
+                second = best;
+                best = rho;
+                bz = z;
+            } else if (rho > second) {
+                second = rho;
+            }
+        }
+        d[q] = (int16_t)bz;
+        C[q] = best;
+        C2[q] = second;
+    }
+}

@@ -1,0 +1,343 @@
+// C ABI of libmsibm: argument validation, workspace layout and launch sequencing.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "msibm.h"
+#include "plan.hpp"
+
+using namespace msibm;
+
+namespace {
+
+thread_local std::string g_err;
+
+msibm_status fail(msibm_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+msibm_status ok()
+{
+    g_err.clear();
+    return MSIBM_OK;
+}
+
+msibm_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(MSIBM_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ helpers
+
+namespace msibm {
+
+int level_dim(int v, int k)
+{
+    for (int i = 0; i < k; ++i) v = (v + 1) / 2;
+    return v;
+}
+
+int level_range(int D, int k) { return (int)(((long long)D + (1LL << k) - 1) >> k); }
+
+int auto_levels(int D)
+{
+    int k = 1;
+    while (level_range(D, k - 1) > 32 && k < MSIBM_MAX_LEVELS) ++k;
+    return k;
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
+
+msibm_status validate_config(const msibm_config* cfg)
+{
+    if (!cfg) return fail(MSIBM_ERR_INVALID_ARG, "cfg is NULL");
+    if (cfg->half_window < 1 || cfg->half_window > MSIBM_MAX_HALF_WINDOW)
+        return fail(MSIBM_ERR_UNSUPPORTED, "half_window %d outside 1..%d", cfg->half_window,
+                    MSIBM_MAX_HALF_WINDOW);
+    if (cfg->refine_radius < 0 || cfg->refine_radius > MSIBM_MAX_RADIUS)
+        return fail(MSIBM_ERR_UNSUPPORTED, "refine_radius %d outside 0..%d", cfg->refine_radius,
+                    MSIBM_MAX_RADIUS);
+    if (!(cfg->var_eps >= 0.f) || !std::isfinite(cfg->var_eps))
+        return fail(MSIBM_ERR_INVALID_ARG, "var_eps must be finite and >= 0");
+    if (cfg->soft_radius < 0 || cfg->soft_radius > MSIBM_MAX_RADIUS)
+        return fail(MSIBM_ERR_UNSUPPORTED, "soft_radius %d outside 0..%d", cfg->soft_radius,
+                    MSIBM_MAX_RADIUS);
+    if (cfg->soft_radius > 0 && (!(cfg->tau > 0.f) || !std::isfinite(cfg->tau)))
+        return fail(MSIBM_ERR_INVALID_ARG, "tau must be finite and > 0");
+    if (cfg->flags & ~(MSIBM_FLAG_BATCHED | MSIBM_FLAG_GRAPH))
+        return fail(MSIBM_ERR_INVALID_ARG, "unknown flags 0x%x", cfg->flags);
+    return MSIBM_OK;
+}
+
+msibm_status validate_pair(const msibm_pair& p, int idx, const msibm_config* cfg, int* K_out)
+{
+    if (!p.left || !p.right) return fail(MSIBM_ERR_INVALID_ARG, "pair %d: NULL image", idx);
+    if (p.dtype != MSIBM_U8 && p.dtype != MSIBM_F32)
+        return fail(MSIBM_ERR_INVALID_ARG, "pair %d: dtype %d", idx, p.dtype);
+    if (p.height < 1 || p.width < 1) return fail(MSIBM_ERR_SHAPE, "pair %d: size %dx%d", idx, p.height, p.width);
+    if (p.pitch < p.width) return fail(MSIBM_ERR_SHAPE, "pair %d: pitch %d < width %d", idx, p.pitch, p.width);
+    if (p.max_disp < 1 || p.max_disp > MSIBM_MAX_DISP)
+        return fail(MSIBM_ERR_UNSUPPORTED, "pair %d: max_disp %d outside 1..%d", idx, p.max_disp, MSIBM_MAX_DISP);
+    if (p.num_levels < 0 || p.num_levels > MSIBM_MAX_LEVELS)
+        return fail(MSIBM_ERR_UNSUPPORTED, "pair %d: num_levels %d outside 0..%d", idx, p.num_levels,
+                    MSIBM_MAX_LEVELS);
+    const int K = p.num_levels ? p.num_levels : auto_levels(p.max_disp);
+    if (cfg->soft_radius > 0) {
+        if (p.dtype != MSIBM_F32)
+            return fail(MSIBM_ERR_UNSUPPORTED, "pair %d: the soft-argmax level takes float images", idx);
+        if (K < 2) return fail(MSIBM_ERR_UNSUPPORTED, "pair %d: the soft-argmax level needs K >= 2", idx);
+    }
+    *K_out = K;
+    return MSIBM_OK;
+}
+
+// Workspace layout of one pair (offsets from the pair's base).
+PairLayout pair_layout(const msibm_pair& p, int K)
+{
+    PairLayout L{};
+    L.K = K;
+    size_t off = 0;
+    for (int k = 0; k < K; ++k) {
+        L.h[k] = level_dim(p.height, k);
+        L.w[k] = level_dim(p.width, k);
+        const size_t px = (size_t)L.h[k] * L.w[k];
+        for (int v = 0; v < 2; ++v) {
+            if (k > 0) {
+                L.img[k][v] = off;
+                off = align_up(off + px * sizeof(float));
+            }
+            L.stat[k][v] = off;
+            off = align_up(off + px * sizeof(float4));
+        }
+        if (k > 0) {
+            L.map[k] = off;
+            off = align_up(off + px * sizeof(int16_t));
+        }
+    }
+    L.bytes = off;
+    return L;
+}
+
+}  // namespace msibm
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char* msibm_last_error(void) { return g_err.c_str(); }
+
+const char* msibm_version(void) { return "msibm 0.1 gfx950"; }
+
+msibm_status msibm_pyramid(const void* img, int32_t dtype, int32_t H, int32_t W, int32_t pitch,
+                           int32_t K, float* const* levels, const int32_t* level_pitch, void* stream)
+{
+    if (!img || !levels || !level_pitch) return fail(MSIBM_ERR_INVALID_ARG, "NULL pointer argument");
+    if (dtype != MSIBM_U8 && dtype != MSIBM_F32) return fail(MSIBM_ERR_INVALID_ARG, "dtype %d", dtype);
+    if (H < 1 || W < 1 || pitch < W) return fail(MSIBM_ERR_SHAPE, "size %dx%d pitch %d", H, W, pitch);
+    if (K < 1 || K > MSIBM_MAX_LEVELS) return fail(MSIBM_ERR_UNSUPPORTED, "K %d outside 1..%d", K, MSIBM_MAX_LEVELS);
+    for (int k = 0; k < K; ++k) {
+        if (!levels[k]) return fail(MSIBM_ERR_INVALID_ARG, "levels[%d] is NULL", k);
+        if (level_pitch[k] < level_dim(W, k))
+            return fail(MSIBM_ERR_SHAPE, "level_pitch[%d] = %d < %d", k, level_pitch[k], level_dim(W, k));
+    }
+    hipStream_t s = (hipStream_t)stream;
+    ConvertArgs c{img, levels[0], H, W, pitch, level_pitch[0]};
+    hipError_t e = launch_convert(dtype, c, s);
+    if (e != hipSuccess) return hip_fail(e, "pyramid convert launch");
+    for (int k = 1; k < K; ++k) {
+        ReduceArgs r{};
+        r.src[0] = levels[k - 1];
+        r.dst[0] = levels[k];
+        r.views = 1;
+        r.H = level_dim(H, k - 1);
+        r.W = level_dim(W, k - 1);
+        r.spitch = level_pitch[k - 1];
+        r.Ho = level_dim(H, k);
+        r.Wo = level_dim(W, k);
+        r.dpitch = level_pitch[k];
+        e = launch_reduce(MSIBM_F32, r, s);
+        if (e != hipSuccess) return hip_fail(e, "pyramid reduce launch");
+    }
+    return ok();
+}
+
+size_t msibm_level_workspace_size(int32_t H, int32_t W)
+{
+    if (H < 1 || W < 1) return 0;
+    return 2 * align_up((size_t)H * W * sizeof(float4));
+}
+
+msibm_status msibm_match_level(const void* L, const void* R, int32_t dtype, int32_t H, int32_t W,
+                               int32_t pitch, int32_t n, int32_t Dk, const int16_t* prior, int32_t Hc,
+                               int32_t Wc, int32_t prior_pitch, int32_t r, float var_eps, int16_t* d_out,
+                               float* cost_out, int32_t out_pitch, void* workspace, size_t ws_bytes,
+                               void* stream)
+{
+    if (!L || !R || !d_out) return fail(MSIBM_ERR_INVALID_ARG, "NULL image or output");
+    if (dtype != MSIBM_U8 && dtype != MSIBM_F32) return fail(MSIBM_ERR_INVALID_ARG, "dtype %d", dtype);
+    if (H < 1 || W < 1 || pitch < W || out_pitch < W)
+        return fail(MSIBM_ERR_SHAPE, "size %dx%d pitch %d out_pitch %d", H, W, pitch, out_pitch);
+    if (n < 1 || n > MSIBM_MAX_HALF_WINDOW) return fail(MSIBM_ERR_UNSUPPORTED, "n %d outside 1..%d", n, MSIBM_MAX_HALF_WINDOW);
+    if (Dk < 1 || Dk > MSIBM_MAX_DISP) return fail(MSIBM_ERR_UNSUPPORTED, "D_k %d outside 1..%d", Dk, MSIBM_MAX_DISP);
+    if (!(var_eps >= 0.f) || !std::isfinite(var_eps)) return fail(MSIBM_ERR_INVALID_ARG, "var_eps");
+    if (prior) {
+        if (r < 0 || r > MSIBM_MAX_RADIUS) return fail(MSIBM_ERR_UNSUPPORTED, "r %d outside 0..%d", r, MSIBM_MAX_RADIUS);
+        if (Hc != (H + 1) / 2 || Wc != (W + 1) / 2 || prior_pitch < Wc)
+            return fail(MSIBM_ERR_SHAPE, "prior %dx%d (pitch %d) does not match level %dx%d", Hc, Wc,
+                        prior_pitch, H, W);
+    }
+    const size_t need = msibm_level_workspace_size(H, W);
+    if (!workspace || ws_bytes < need)
+        return fail(MSIBM_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace ? ws_bytes : (size_t)0, need);
+    hipStream_t s = (hipStream_t)stream;
+    float4* st = (float4*)workspace;
+    float4* st_r = (float4*)((char*)workspace + align_up((size_t)H * W * sizeof(float4)));
+    StatsArgs sa{};
+    sa.src[0] = L;
+    sa.src[1] = R;
+    sa.dst[0] = st;
+    sa.dst[1] = st_r;
+    sa.views = 2;
+    sa.H = H;
+    sa.W = W;
+    sa.spitch = pitch;
+    sa.dpitch = W;
+    sa.n = n;
+    sa.var_eps = var_eps;
+    hipError_t e = launch_stats(dtype, sa, s);
+    if (e != hipSuccess) return hip_fail(e, "stats launch");
+    MatchArgs a{};
+    a.L = L;
+    a.R = R;
+    a.H = H;
+    a.W = W;
+    a.pitch = pitch;
+    a.statL = st;
+    a.statR = st_r;
+    a.spitch = W;
+    a.Dk = Dk;
+    a.prior = prior;
+    a.Hc = Hc;
+    a.Wc = Wc;
+    a.ppitch = prior_pitch;
+    a.r = r;
+    a.d_out = d_out;
+    a.c_out = cost_out;
+    a.soft_out = nullptr;
+    a.opitch = out_pitch;
+    a.inv_tau = 0.f;
+    const int mode = prior ? MODE_REFINE : MODE_FULL;
+    e = launch_match(n, dtype, mode, prior ? slots_for_radius(r) : FULL_NC, a, s);
+    if (e != hipSuccess) return hip_fail(e, "match launch");
+    return ok();
+}
+
+size_t msibm_workspace_size(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg)
+{
+    if (!pairs || n_pairs < 1 || n_pairs > MSIBM_MAX_PAIRS || !cfg) return 0;
+    if (validate_config(cfg) != MSIBM_OK) return 0;
+    size_t tot = 0;
+    for (int p = 0; p < n_pairs; ++p) {
+        int K;
+        if (validate_pair(pairs[p], p, cfg, &K) != MSIBM_OK) return 0;
+        tot += pair_layout(pairs[p], K).bytes;
+    }
+    tot += batch_extra_bytes(pairs, n_pairs, cfg);
+    return tot;
+}
+
+msibm_status msibm_disparity(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg,
+                             int16_t* const* disp, float* const* cost, float* const* soft_disp,
+                             int16_t* const* prior1, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!pairs || !disp) return fail(MSIBM_ERR_INVALID_ARG, "pairs or disp is NULL");
+    if (n_pairs < 1 || n_pairs > MSIBM_MAX_PAIRS)
+        return fail(MSIBM_ERR_INVALID_ARG, "n_pairs %d outside 1..%d", n_pairs, MSIBM_MAX_PAIRS);
+    msibm_status st = validate_config(cfg);
+    if (st != MSIBM_OK) return st;
+    std::vector<int> Ks(n_pairs);
+    for (int p = 0; p < n_pairs; ++p) {
+        st = validate_pair(pairs[p], p, cfg, &Ks[p]);
+        if (st != MSIBM_OK) return st;
+        if (!disp[p]) return fail(MSIBM_ERR_INVALID_ARG, "disp[%d] is NULL", p);
+        if (cfg->soft_radius > 0 && (!soft_disp || !soft_disp[p]))
+            return fail(MSIBM_ERR_INVALID_ARG, "soft_disp[%d] is NULL but soft_radius > 0", p);
+    }
+    const size_t need = msibm_workspace_size(pairs, n_pairs, cfg);
+    if (!workspace || ws_bytes < need)
+        return fail(MSIBM_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace ? ws_bytes : (size_t)0, need);
+
+    hipStream_t s = (hipStream_t)stream;
+    if (cfg->flags & MSIBM_FLAG_BATCHED) {
+        BatchOutputs out{disp, cost, soft_disp, prior1};
+        std::string err;
+        const int rc = run_batched(pairs, n_pairs, cfg, out, workspace, ws_bytes, s, &err);
+        if (rc != MSIBM_OK) return fail(rc, "%s", err.c_str());
+        return ok();
+    }
+    size_t base = 0;
+    for (int p = 0; p < n_pairs; ++p) {
+        const msibm_pair& P = pairs[p];
+        const PairLayout lay = pair_layout(P, Ks[p]);
+        char* ws = (char*)workspace + base;
+        base += lay.bytes;
+        std::string err;
+        const int rc = run_pair_plain(P, lay, cfg, ws, disp[p], cost ? cost[p] : nullptr,
+                                      soft_disp ? soft_disp[p] : nullptr, prior1 ? prior1[p] : nullptr, s,
+                                      &err);
+        if (rc != MSIBM_OK) return fail(rc, "pair %d: %s", p, err.c_str());
+    }
+    return ok();
+}
+
+msibm_status msibm_backward(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg,
+                            const int16_t* const* prior1, const float* const* grad_soft,
+                            float* const* grad_left, float* const* grad_right, void* workspace,
+                            size_t ws_bytes, void* stream)
+{
+    if (!pairs || !prior1 || !grad_soft || !grad_left || !grad_right)
+        return fail(MSIBM_ERR_INVALID_ARG, "NULL argument");
+    if (n_pairs < 1 || n_pairs > MSIBM_MAX_PAIRS)
+        return fail(MSIBM_ERR_INVALID_ARG, "n_pairs %d outside 1..%d", n_pairs, MSIBM_MAX_PAIRS);
+    msibm_status st = validate_config(cfg);
+    if (st != MSIBM_OK) return st;
+    if (cfg->soft_radius < 1) return fail(MSIBM_ERR_INVALID_ARG, "backward needs soft_radius >= 1");
+    std::vector<int> Ks(n_pairs);
+    for (int p = 0; p < n_pairs; ++p) {
+        st = validate_pair(pairs[p], p, cfg, &Ks[p]);
+        if (st != MSIBM_OK) return st;
+        if (!prior1[p] || !grad_soft[p] || !grad_left[p] || !grad_right[p])
+            return fail(MSIBM_ERR_INVALID_ARG, "pair %d: NULL prior or gradient buffer", p);
+    }
+    const size_t need = msibm_workspace_size(pairs, n_pairs, cfg);
+    if (!workspace || ws_bytes < need)
+        return fail(MSIBM_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace ? ws_bytes : (size_t)0, need);
+    hipStream_t s = (hipStream_t)stream;
+    size_t base = 0;
+    for (int p = 0; p < n_pairs; ++p) {
+        const PairLayout lay = pair_layout(pairs[p], Ks[p]);
+        char* ws = (char*)workspace + base;
+        base += lay.bytes;
+        std::string err;
+        const int rc = run_pair_backward(pairs[p], lay, cfg, ws, prior1[p], grad_soft[p], grad_left[p],
+                                         grad_right[p], s, &err);
+        if (rc != MSIBM_OK) return fail(rc, "pair %d: %s", p, err.c_str());
+    }
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,93 @@
+// Shared definitions of the gfx950 kernels and the host library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msibm {
+
+// ---------------------------------------------------------------- tiling
+// The matching kernels give each thread a 2x2 block of pixels.  Pixels of one
+// block share the propagated prior (nearest-neighbour upsampling maps the 2x2
+// block onto one coarser pixel), so they share one window of candidate slots,
+// and their four windows share most of their row products.
+constexpr int MATCH_TX = 64;               // threads across a workgroup (one wave)
+constexpr int MATCH_TY = 4;                // waves per workgroup
+constexpr int MATCH_THREADS = MATCH_TX * MATCH_TY;
+constexpr int TILE_W = 2 * MATCH_TX;       // 128 pixel columns per workgroup
+constexpr int TILE_H = 2 * MATCH_TY;       // 8 pixel rows per workgroup
+constexpr int CHUNK = 96;                  // candidates held in LDS per right-image chunk
+constexpr int FULL_NC = 8;                 // slots per step of a full search
+
+enum MatchMode { MODE_FULL = 0, MODE_REFINE = 1, MODE_SOFT = 2 };
+
+// Per-pixel window statistics of one view at one level (float4): x + y = the
+// window mean as an unevaluated sum of two floats (x = the mean rounded to
+// float, y = the rounding remainder), z = 1/sqrt(sum of squared deviations) or 0
+// for a flat window, w unused.
+struct MatchArgs {
+    const void* L;
+    const void* R;
+    int H, W, pitch;          // level image size and row pitch (elements)
+    const float4* statL;      // H x W, row pitch spitch
+    const float4* statR;
+    int spitch;
+    int Dk;                   // candidates at this level
+    const int16_t* prior;     // level k+1 map (refine / soft), else unused
+    int Hc, Wc, ppitch;
+    int r;                    // refine or soft radius
+    int16_t* d_out;           // H x W, row pitch opitch
+    float* c_out;             // nullable
+    float* soft_out;          // soft mode only
+    int opitch;
+    float inv_tau;
+};
+
+struct ReduceArgs {
+    const void* src[2];
+    float* dst[2];
+    int views;                // 1 or 2 (grid z)
+    int H, W, spitch;         // source level
+    int Ho, Wo, dpitch;       // destination level
+};
+
+struct StatsArgs {
+    const void* src[2];
+    float4* dst[2];
+    int views;
+    int H, W, spitch, dpitch;
+    int n;
+    double var_eps;
+};
+
+struct ConvertArgs {
+    const void* src;
+    float* dst;
+    int H, W, spitch, dpitch;
+};
+
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
+
+template <typename T>
+__device__ __forceinline__ float to_f(T v) { return static_cast<float>(v); }
+
+// Host-side launchers (one translation unit per half-window size for the
+// matching kernels, so the template instances compile in parallel).
+hipError_t launch_reduce(int dtype, const ReduceArgs& a, hipStream_t s);
+hipError_t launch_convert(int dtype, const ConvertArgs& a, hipStream_t s);
+hipError_t launch_stats(int dtype, const StatsArgs& a, hipStream_t s);
+hipError_t launch_match(int n, int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
+
+hipError_t launch_match_n1(int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
+hipError_t launch_match_n2(int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
+hipError_t launch_match_n3(int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
+hipError_t launch_match_n4(int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
+hipError_t launch_match_n5(int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
+hipError_t launch_match_n6(int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
+
+// Slots evaluated per block: 2r+1, but at least 2 so that a block whose prior
+// is clipped by the left image border (pixel columns j0 and j0+1 then centre
+// on j0 and j0+1) still fits one window.
+inline int slots_for_radius(int r) { return 2 * r + 1 < 2 ? 2 : 2 * r + 1; }
+
+}  // namespace msibm

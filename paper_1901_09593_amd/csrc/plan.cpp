@@ -1,0 +1,150 @@
+// Launch sequences of the plain (one pair at a time) forward pass.
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+#include "plan.hpp"
+#include "timing.hpp"
+
+#include <cstdio>
+
+namespace msibm {
+
+hipError_t launch_match(int n, int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s)
+{
+    switch (n) {
+        case 1: return launch_match_n1(dtype, mode, nc, a, s);
+        case 2: return launch_match_n2(dtype, mode, nc, a, s);
+        case 3: return launch_match_n3(dtype, mode, nc, a, s);
+        case 4: return launch_match_n4(dtype, mode, nc, a, s);
+        case 5: return launch_match_n5(dtype, mode, nc, a, s);
+        case 6: return launch_match_n6(dtype, mode, nc, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+static int hip_err(hipError_t e, const char* what, std::string* err)
+{
+    *err = std::string(what) + ": " + hipGetErrorString(e);
+    return MSIBM_ERR_HIP;
+}
+
+int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,
+                   int16_t* disp, float* cost, float* soft, int16_t* prior1, hipStream_t s,
+                   std::string* err)
+{
+    const int K = lay.K;
+    const int n = cfg->half_window;
+    hipError_t e;
+    // image pointers per level and view (level 0 is the caller's input)
+    const void* img[MSIBM_MAX_LEVELS][2];
+    int pitch[MSIBM_MAX_LEVELS];
+    img[0][0] = P.left;
+    img[0][1] = P.right;
+    pitch[0] = P.pitch;
+    for (int k = 1; k < K; ++k) {
+        ReduceArgs r{};
+        r.src[0] = img[k - 1][0];
+        r.src[1] = img[k - 1][1];
+        r.dst[0] = (float*)(ws + lay.img[k][0]);
+        r.dst[1] = (float*)(ws + lay.img[k][1]);
+        r.views = 2;
+        r.H = lay.h[k - 1];
+        r.W = lay.w[k - 1];
+        r.spitch = pitch[k - 1];
+        r.Ho = lay.h[k];
+        r.Wo = lay.w[k];
+        r.dpitch = lay.w[k];
+        char lab[32];
+        snprintf(lab, sizeof(lab), "reduce_l%d", k);
+        {
+            TimedLaunch t(lab, s);
+            e = launch_reduce(k == 1 ? P.dtype : MSIBM_F32, r, s);
+        }
+        if (e != hipSuccess) return hip_err(e, "reduce launch", err);
+        img[k][0] = r.dst[0];
+        img[k][1] = r.dst[1];
+        pitch[k] = lay.w[k];
+    }
+    for (int k = 0; k < K; ++k) {
+        StatsArgs sa{};
+        sa.src[0] = img[k][0];
+        sa.src[1] = img[k][1];
+        sa.dst[0] = (float4*)(ws + lay.stat[k][0]);
+        sa.dst[1] = (float4*)(ws + lay.stat[k][1]);
+        sa.views = 2;
+        sa.H = lay.h[k];
+        sa.W = lay.w[k];
+        sa.spitch = pitch[k];
+        sa.dpitch = lay.w[k];
+        sa.n = n;
+        sa.var_eps = cfg->var_eps;
+        char lab[32];
+        snprintf(lab, sizeof(lab), "stats_l%d", k);
+        {
+            TimedLaunch t(lab, s);
+            e = launch_stats(k == 0 ? P.dtype : MSIBM_F32, sa, s);
+        }
+        if (e != hipSuccess) return hip_err(e, "stats launch", err);
+    }
+    for (int k = K - 1; k >= 0; --k) {
+        MatchArgs a{};
+        a.L = img[k][0];
+        a.R = img[k][1];
+        a.H = lay.h[k];
+        a.W = lay.w[k];
+        a.pitch = pitch[k];
+        a.statL = (const float4*)(ws + lay.stat[k][0]);
+        a.statR = (const float4*)(ws + lay.stat[k][1]);
+        a.spitch = lay.w[k];
+        a.Dk = level_range(P.max_disp, k);
+        const bool coarsest = (k == K - 1);
+        if (!coarsest) {
+            a.prior = (k + 1 == 1 && prior1) ? prior1 : (const int16_t*)(ws + lay.map[k + 1]);
+            a.Hc = lay.h[k + 1];
+            a.Wc = lay.w[k + 1];
+            a.ppitch = lay.w[k + 1];
+        }
+        const bool soft_level = (k == 0 && cfg->soft_radius > 0);
+        a.r = soft_level ? cfg->soft_radius : cfg->refine_radius;
+        if (k == 0) {
+            a.d_out = disp;
+            a.c_out = cost;
+            a.soft_out = soft;
+        } else {
+            a.d_out = (k == 1 && prior1) ? prior1 : (int16_t*)(ws + lay.map[k]);
+            a.c_out = nullptr;
+            a.soft_out = nullptr;
+        }
+        a.opitch = lay.w[k];
+        a.inv_tau = soft_level ? 1.f / cfg->tau : 0.f;
+        const int mode = coarsest ? MODE_FULL : (soft_level ? MODE_SOFT : MODE_REFINE);
+        const int nc = coarsest ? FULL_NC : slots_for_radius(a.r);
+        char lab[32];
+        snprintf(lab, sizeof(lab), "match_%s_l%d",
+                 mode == MODE_FULL ? "full" : (mode == MODE_SOFT ? "soft" : "refine"), k);
+        {
+            TimedLaunch t(lab, s);
+            e = launch_match(n, k == 0 ? P.dtype : MSIBM_F32, mode, nc, a, s);
+        }
+        if (e != hipSuccess) return hip_err(e, "match launch", err);
+    }
+    return MSIBM_OK;
+}
+
+int run_pair_backward(const msibm_pair&, const PairLayout&, const msibm_config*, char*, const int16_t*,
+                      const float*, float*, float*, hipStream_t, std::string* err)
+{
+    *err = "backward not built yet";
+    return MSIBM_ERR_UNSUPPORTED;
+}
+
+size_t batch_extra_bytes(const msibm_pair*, int, const msibm_config*) { return 0; }
+
+int run_batched(const msibm_pair*, int, const msibm_config*, const BatchOutputs&, void*, size_t,
+                hipStream_t, std::string* err)
+{
+    *err = "batched path not built yet";
+    return MSIBM_ERR_UNSUPPORTED;
+}
+
+}  // namespace msibm

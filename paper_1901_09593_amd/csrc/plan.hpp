@@ -1,0 +1,52 @@
+// Host-side planning shared by the C ABI: workspace layout and launch sequences.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "msibm.h"
+
+namespace msibm {
+
+int level_dim(int v, int k);
+int level_range(int D, int k);
+int auto_levels(int D);
+size_t align_up(size_t v);
+
+// Workspace offsets of one pair.  Level k (k >= 1) holds both views' pyramid
+// images (float, W_k pitch); every level holds both views' window statistics
+// (float4 per pixel); levels k >= 1 hold the winner-take-all map (int16).
+struct PairLayout {
+    int K;
+    int h[MSIBM_MAX_LEVELS], w[MSIBM_MAX_LEVELS];
+    size_t img[MSIBM_MAX_LEVELS][2];
+    size_t stat[MSIBM_MAX_LEVELS][2];
+    size_t map[MSIBM_MAX_LEVELS];
+    size_t bytes;
+};
+
+PairLayout pair_layout(const msibm_pair& p, int K);
+
+struct BatchOutputs {
+    int16_t* const* disp;
+    float* const* cost;
+    float* const* soft;
+    int16_t* const* prior1;
+};
+
+// Plain per-pair forward: 2K launches on `s`.
+int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,
+                   int16_t* disp, float* cost, float* soft, int16_t* prior1, hipStream_t s,
+                   std::string* err);
+
+int run_pair_backward(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,
+                      const int16_t* prior1, const float* grad_soft, float* grad_left,
+                      float* grad_right, hipStream_t s, std::string* err);
+
+size_t batch_extra_bytes(const msibm_pair* pairs, int n_pairs, const msibm_config* cfg);
+
+int run_batched(const msibm_pair* pairs, int n_pairs, const msibm_config* cfg, const BatchOutputs& out,
+                void* workspace, size_t ws_bytes, hipStream_t s, std::string* err);
+
+}  // namespace msibm

@@ -1,0 +1,326 @@
+"""Python binding of libmsibm (ctypes).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  torch supplies device memory and the current HIP stream; outputs are
+allocated with torch.empty on the inputs' device, and calls are asynchronous on
+torch's current stream like any torch op.
+
+The library must be built (`python -m paper_1901_09593_amd.build`); importing
+this module without it raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmsibm.so")
+
+MSIBM_U8 = 0
+MSIBM_F32 = 1
+FLAG_BATCHED = 1
+FLAG_GRAPH = 2
+MAX_LEVELS = 8
+
+
+class MsibmError(RuntimeError):
+    """A libmsibm call returned a negative status."""
+
+    def __init__(self, status: int, message: str):
+        super().__init__(f"msibm status {status}: {message}")
+        self.status = status
+
+
+class Pair(ctypes.Structure):
+    _fields_ = [("left", ctypes.c_void_p), ("right", ctypes.c_void_p), ("dtype", ctypes.c_int32),
+                ("height", ctypes.c_int32), ("width", ctypes.c_int32), ("pitch", ctypes.c_int32),
+                ("max_disp", ctypes.c_int32), ("num_levels", ctypes.c_int32)]
+
+
+class Config(ctypes.Structure):
+    _fields_ = [("half_window", ctypes.c_int32), ("refine_radius", ctypes.c_int32),
+                ("var_eps", ctypes.c_float), ("soft_radius", ctypes.c_int32),
+                ("tau", ctypes.c_float), ("flags", ctypes.c_int32)]
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_PP = ctypes.POINTER(ctypes.c_void_p)
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1901_09593_amd.build` (there is no CPU fallback)")
+        L = ctypes.CDLL(LIB_PATH)
+        L.msibm_last_error.restype = ctypes.c_char_p
+        L.msibm_version.restype = ctypes.c_char_p
+        L.msibm_pyramid.argtypes = [_VP, _I32, _I32, _I32, _I32, _I32, _PP,
+                                    ctypes.POINTER(_I32), _VP]
+        L.msibm_pyramid.restype = _I32
+        L.msibm_level_workspace_size.argtypes = [_I32, _I32]
+        L.msibm_level_workspace_size.restype = ctypes.c_size_t
+        L.msibm_match_level.argtypes = [_VP, _VP, _I32, _I32, _I32, _I32, _I32, _I32, _VP, _I32,
+                                        _I32, _I32, _I32, ctypes.c_float, _VP, _VP, _I32, _VP,
+                                        ctypes.c_size_t, _VP]
+        L.msibm_match_level.restype = _I32
+        L.msibm_workspace_size.argtypes = [ctypes.POINTER(Pair), _I32, ctypes.POINTER(Config)]
+        L.msibm_workspace_size.restype = ctypes.c_size_t
+        L.msibm_disparity.argtypes = [ctypes.POINTER(Pair), _I32, ctypes.POINTER(Config), _PP, _PP,
+                                      _PP, _PP, _VP, ctypes.c_size_t, _VP]
+        L.msibm_disparity.restype = _I32
+        L.msibm_backward.argtypes = [ctypes.POINTER(Pair), _I32, ctypes.POINTER(Config), _PP, _PP,
+                                     _PP, _PP, _VP, ctypes.c_size_t, _VP]
+        L.msibm_backward.restype = _I32
+        L.msibm_timing_enable.argtypes = [_I32]
+        L.msibm_timing_enable.restype = _I32
+        L.msibm_timing_read.argtypes = [_I32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(_I32)]
+        L.msibm_timing_read.restype = _I32
+        _lib = L
+    return _lib
+
+
+def version() -> str:
+    return lib().msibm_version().decode()
+
+
+def _check(status: int):
+    if status != 0:
+        raise MsibmError(status, lib().msibm_last_error().decode())
+
+
+def _stream(dev: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _ptr_array(ts: Sequence[Optional[torch.Tensor]]):
+    arr = (ctypes.c_void_p * len(ts))()
+    for i, t in enumerate(ts):
+        arr[i] = None if t is None else t.data_ptr()
+    return arr
+
+
+def _dtype_code(t: torch.Tensor) -> int:
+    if t.dtype == torch.uint8:
+        return MSIBM_U8
+    if t.dtype == torch.float32:
+        return MSIBM_F32
+    raise TypeError(f"images must be uint8 or float32, got {t.dtype}")
+
+
+def _image(t: torch.Tensor) -> torch.Tensor:
+    if t.dim() != 2 or not t.is_cuda:
+        raise ValueError("images must be 2-D device tensors")
+    if t.stride(1) != 1:
+        t = t.contiguous()
+    return t
+
+
+def level_dim(v: int, k: int) -> int:
+    for _ in range(k):
+        v = (v + 1) // 2
+    return v
+
+
+def level_range(D: int, k: int) -> int:
+    return -(-D // (1 << k))
+
+
+def auto_levels(D: int) -> int:
+    k = 1
+    while level_range(D, k - 1) > 32 and k < MAX_LEVELS:
+        k += 1
+    return k
+
+
+def make_config(n: int, r: int, var_eps: float, soft_radius: int = 0, tau: float = 0.05,
+                flags: int = 0) -> Config:
+    return Config(n, r, float(var_eps), soft_radius, float(tau), flags)
+
+
+def timing_enable(on: bool = True):
+    """Bracket every library kernel launch with HIP events (clears totals)."""
+    _check(lib().msibm_timing_enable(1 if on else 0))
+
+
+def timing_read() -> Dict[str, Tuple[float, int]]:
+    """{label: (total ms, launches)} of the timed launches so far (waits for them)."""
+    cap = 256
+    labels = ctypes.create_string_buffer(64 * cap)
+    tot = (ctypes.c_double * cap)()
+    cnt = (ctypes.c_int32 * cap)()
+    m = lib().msibm_timing_read(cap, labels, tot, cnt)
+    out = {}
+    for i in range(m):
+        name = labels.raw[64 * i:64 * (i + 1)].split(b"\0", 1)[0].decode()
+        out[name] = (tot[i], cnt[i])
+    return out
+
+
+# ------------------------------------------------------------------ entry points
+
+def pyramid(img: torch.Tensor, K: int) -> List[torch.Tensor]:
+    """K-level binomial pyramid of one image; level 0 is the float copy."""
+    img = _image(img)
+    H, W = img.shape
+    levels = [torch.empty((level_dim(H, k), level_dim(W, k)), dtype=torch.float32, device=img.device)
+              for k in range(K)]
+    ptrs = _ptr_array(levels)
+    pitches = (ctypes.c_int32 * K)(*[l.shape[1] for l in levels])
+    _check(lib().msibm_pyramid(_ptr(img), _dtype_code(img), H, W, img.stride(0), K, ptrs, pitches,
+                               _stream(img.device)))
+    return levels
+
+
+def match_level(L: torch.Tensor, R: torch.Tensor, n: int, Dk: int,
+                prior: Optional[torch.Tensor] = None, r: int = 2, var_eps: float = 0.065,
+                with_cost: bool = True) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
+    """Winner-take-all of one level; prior = level k+1 map (int16) or None."""
+    L = _image(L)
+    R = _image(R)
+    if L.shape != R.shape or L.dtype != R.dtype or L.stride(0) != R.stride(0):
+        raise ValueError("left and right must share shape, dtype and pitch")
+    H, W = L.shape
+    dev = L.device
+    d = torch.empty((H, W), dtype=torch.int16, device=dev)
+    C = torch.empty((H, W), dtype=torch.float32, device=dev) if with_cost else None
+    ws_bytes = lib().msibm_level_workspace_size(H, W)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    if prior is not None:
+        prior = prior.contiguous()
+        Hc, Wc, pp = prior.shape[0], prior.shape[1], prior.stride(0)
+    else:
+        Hc = Wc = pp = 0
+    _check(lib().msibm_match_level(_ptr(L), _ptr(R), _dtype_code(L), H, W, L.stride(0), n, Dk,
+                                   _ptr(prior), Hc, Wc, pp, r, float(var_eps), _ptr(d), _ptr(C), W,
+                                   _ptr(ws), ws_bytes, _stream(dev)))
+    return d, C
+
+
+def _pairs(lefts, rights, Ds, Ks) -> Tuple[ctypes.Array, list]:
+    n = len(lefts)
+    arr = (Pair * n)()
+    keep = []
+    for i in range(n):
+        L = _image(lefts[i])
+        R = _image(rights[i])
+        if L.shape != R.shape or L.dtype != R.dtype or L.stride(0) != R.stride(0):
+            raise ValueError("left and right must share shape, dtype and pitch")
+        keep += [L, R]
+        arr[i] = Pair(L.data_ptr(), R.data_ptr(), _dtype_code(L), L.shape[0], L.shape[1],
+                      L.stride(0), int(Ds[i]), int(Ks[i]))
+    return arr, keep
+
+
+def workspace_bytes(pairs_arr, n: int, cfg: Config) -> int:
+    b = lib().msibm_workspace_size(pairs_arr, n, ctypes.byref(cfg))
+    if b == 0:
+        raise MsibmError(-1, "invalid pairs or config: " + lib().msibm_last_error().decode())
+    return b
+
+
+def disparity(L: torch.Tensor, R: torch.Tensor, D: int, K: int, n: int, r: int, var_eps: float,
+              soft_radius: int = 0, tau: float = 0.05, with_cost: bool = True,
+              with_prior1: bool = False) -> Dict[str, torch.Tensor]:
+    """Hierarchical forward pass of one pair.  Returns a dict with 'disp'
+    (int16), 'cost' (float, optional), 'soft' (float, if soft_radius > 0) and
+    'prior1' (int16 level-1 map, if requested or soft)."""
+    out = disparity_many([L], [R], [D], [K], n, r, var_eps, soft_radius, tau, with_cost,
+                         with_prior1)
+    return out[0]
+
+
+def disparity_many(lefts: Sequence[torch.Tensor], rights: Sequence[torch.Tensor], Ds: Sequence[int],
+                   Ks: Sequence[int], n: int, r: int, var_eps: float, soft_radius: int = 0,
+                   tau: float = 0.05, with_cost: bool = True, with_prior1: bool = False,
+                   flags: int = 0, workspace: Optional[torch.Tensor] = None,
+                   outputs: Optional[List[Dict[str, torch.Tensor]]] = None) -> List[Dict[str, torch.Tensor]]:
+    """Forward pass of several pairs in one call (flags: FLAG_BATCHED, FLAG_GRAPH).
+    `workspace` and `outputs` may be passed in to reuse buffers across calls."""
+    pairs, keep = _pairs(lefts, rights, Ds, Ks)
+    npair = len(lefts)
+    cfg = make_config(n, r, var_eps, soft_radius, tau, flags)
+    ws_bytes = workspace_bytes(pairs, npair, cfg)
+    dev = lefts[0].device
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    if outputs is None:
+        outputs = []
+        for i in range(npair):
+            H, W = lefts[i].shape
+            K = Ks[i] or auto_levels(Ds[i])
+            o = {"disp": torch.empty((H, W), dtype=torch.int16, device=dev)}
+            if with_cost:
+                o["cost"] = torch.empty((H, W), dtype=torch.float32, device=dev)
+            if soft_radius > 0:
+                o["soft"] = torch.empty((H, W), dtype=torch.float32, device=dev)
+            if (with_prior1 or soft_radius > 0) and K >= 2:
+                o["prior1"] = torch.empty((level_dim(H, 1), level_dim(W, 1)), dtype=torch.int16,
+                                          device=dev)
+            outputs.append(o)
+    disp = _ptr_array([o["disp"] for o in outputs])
+    cost = _ptr_array([o.get("cost") for o in outputs]) if with_cost else None
+    soft = _ptr_array([o.get("soft") for o in outputs]) if soft_radius > 0 else None
+    pri = _ptr_array([o.get("prior1") for o in outputs])
+    _check(lib().msibm_disparity(pairs, npair, ctypes.byref(cfg), disp, cost, soft, pri,
+                                 _ptr(workspace), workspace.numel(), _stream(dev)))
+    del keep
+    return outputs
+
+
+def backward(L: torch.Tensor, R: torch.Tensor, prior1: torch.Tensor, grad_soft: torch.Tensor,
+             D: int, K: int, n: int, r: int, var_eps: float, soft_radius: int,
+             tau: float) -> Tuple[torch.Tensor, torch.Tensor]:
+    """(dLoss/dL, dLoss/dR) given dLoss/d(d_soft), the level-1 prior held fixed."""
+    pairs, keep = _pairs([L], [R], [D], [K])
+    cfg = make_config(n, r, var_eps, soft_radius, tau, 0)
+    ws_bytes = workspace_bytes(pairs, 1, cfg)
+    dev = L.device
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    g = grad_soft.contiguous().to(torch.float32)
+    gL = torch.empty(L.shape, dtype=torch.float32, device=dev)
+    gR = torch.empty(L.shape, dtype=torch.float32, device=dev)
+    p1 = prior1.contiguous()
+    _check(lib().msibm_backward(pairs, 1, ctypes.byref(cfg), _ptr_array([p1]), _ptr_array([g]),
+                                _ptr_array([gL]), _ptr_array([gR]), _ptr(ws), ws_bytes,
+                                _stream(dev)))
+    del keep
+    return gL, gR
+
+
+class MsibmFunction(torch.autograd.Function):
+    """d_soft = MsibmFunction.apply(L, R, D, K, n, r, var_eps, soft_radius, tau).
+
+    Forward runs the whole hierarchy (soft-argmax at level 0); backward returns
+    dLoss/dL and dLoss/dR through the level-0 scores with the level-1 prior held
+    fixed.  L and R are float32 device images."""
+
+    @staticmethod
+    def forward(ctx, L, R, D, K, n, r, var_eps, soft_radius, tau):
+        out = disparity(L, R, D, K, n, r, var_eps, soft_radius, tau, with_cost=False,
+                        with_prior1=True)
+        ctx.save_for_backward(L, R, out["prior1"])
+        ctx.params = (D, K, n, r, var_eps, soft_radius, tau)
+        ctx.mark_non_differentiable(out["disp"])
+        return out["soft"], out["disp"]
+
+    @staticmethod
+    def backward(ctx, grad_soft, grad_disp):
+        L, R, p1 = ctx.saved_tensors
+        D, K, n, r, var_eps, soft_radius, tau = ctx.params
+        if grad_soft is None:
+            grad_soft = torch.zeros_like(L)
+        gL, gR = backward(L, R, p1, grad_soft, D, K, n, r, var_eps, soft_radius, tau)
+        return gL, gR, None, None, None, None, None, None, None

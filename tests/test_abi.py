@@ -1,0 +1,103 @@
+"""The C-ABI library loads on the CPU, exports every declared entry point, and its
+argument validation rejects bad calls before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "msibm.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(msibm_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1901_09593_amd import msibm
+    if not os.path.exists(msibm.LIB_PATH):
+        pytest.skip("libmsibm.so not built")
+    return msibm.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert {"msibm_pyramid", "msibm_match_level", "msibm_disparity", "msibm_backward"} <= set(names)
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_validation_errors_from_host(lib):
+    from paper_1901_09593_amd import msibm
+    e = msibm.lib()
+    # pyramid: null image, bad dtype, bad size, bad K
+    assert e.msibm_pyramid(None, 0, 4, 4, 4, 2, None, None, None) == -1
+    fake = ctypes.c_void_p(0x1000)
+    lv = (ctypes.c_void_p * 2)(0x1000, 0x2000)
+    pit = (ctypes.c_int32 * 2)(4, 2)
+    assert e.msibm_pyramid(fake, 7, 4, 4, 4, 2, lv, pit, None) == -1
+    assert e.msibm_pyramid(fake, 0, 0, 4, 4, 2, lv, pit, None) == -2
+    assert e.msibm_pyramid(fake, 0, 4, 4, 3, 2, lv, pit, None) == -2
+    assert e.msibm_pyramid(fake, 0, 4, 4, 4, 9, lv, pit, None) == -4
+    badpit = (ctypes.c_int32 * 2)(4, 1)
+    assert e.msibm_pyramid(fake, 0, 4, 4, 4, 2, lv, badpit, None) == -2
+    assert b"level_pitch" in e.msibm_last_error()
+    # match_level: window, range, prior shape, workspace
+    args = dict(L=fake, R=fake, dtype=0, H=8, W=8, pitch=8, n=2, Dk=4, prior=None, Hc=0, Wc=0,
+                pp=0, r=1, eps=0.1, d=fake, c=None, op=8, ws=fake, wsb=10 ** 6, s=None)
+
+    def call(**kw):
+        a = dict(args, **kw)
+        return e.msibm_match_level(a["L"], a["R"], a["dtype"], a["H"], a["W"], a["pitch"], a["n"],
+                                   a["Dk"], a["prior"], a["Hc"], a["Wc"], a["pp"], a["r"], a["eps"],
+                                   a["d"], a["c"], a["op"], a["ws"], a["wsb"], a["s"])
+    assert call(n=0) == -4 and call(n=7) == -4
+    assert call(Dk=0) == -4 and call(Dk=5000) == -4
+    assert call(d=None) == -1
+    assert call(eps=-1.0) == -1
+    assert call(prior=fake, Hc=3, Wc=4, pp=4) == -2
+    assert call(prior=fake, Hc=4, Wc=4, pp=4, r=9) == -4
+    assert call(wsb=10) == -3 and call(ws=None) == -3
+    assert call(pitch=7) == -2
+
+
+def test_config_and_pair_validation(lib):
+    from paper_1901_09593_amd import msibm
+    e = msibm.lib()
+    P = msibm.Pair(0x1000, 0x2000, 0, 64, 80, 80, 32, 0)
+    arr = (msibm.Pair * 1)(P)
+    good = msibm.make_config(3, 2, 0.065)
+    assert e.msibm_workspace_size(arr, 1, ctypes.byref(good)) > 0
+    for bad in (msibm.make_config(0, 2, 0.065), msibm.make_config(3, 5, 0.065),
+                msibm.make_config(3, 2, -1.0), msibm.make_config(3, 2, 0.1, 2, 0.0),
+                msibm.make_config(3, 2, 0.1, 0, 0.05, 64)):
+        assert e.msibm_workspace_size(arr, 1, ctypes.byref(bad)) == 0
+    # the soft level needs float images
+    soft = msibm.make_config(3, 2, 0.065, 3, 0.05)
+    assert e.msibm_workspace_size(arr, 1, ctypes.byref(soft)) == 0
+    disp = (ctypes.c_void_p * 1)(0x3000)
+    rc = e.msibm_disparity(arr, 1, ctypes.byref(soft), disp, None, None, None, None, 0, None)
+    assert rc == -4 and b"float" in e.msibm_last_error()
+    rc = e.msibm_disparity(arr, 0, ctypes.byref(good), disp, None, None, None, None, 0, None)
+    assert rc == -1
+    rc = e.msibm_disparity(arr, 1, ctypes.byref(good), disp, None, None, None, None, 0, None)
+    assert rc == -3
+    # automatic level count: smallest K with ceil(D / 2^(K-1)) <= 32
+    assert msibm.auto_levels(32) == 1 and msibm.auto_levels(33) == 2 and msibm.auto_levels(400) == 5
+
+
+def test_workspace_grows_with_levels(lib):
+    from paper_1901_09593_amd import msibm
+    e = msibm.lib()
+    cfg = msibm.make_config(4, 2, 0.065)
+    sizes = []
+    for K in (1, 2, 4):
+        arr = (msibm.Pair * 1)(msibm.Pair(0x1000, 0x2000, 0, 992, 1436, 1436, 256, K))
+        sizes.append(e.msibm_workspace_size(arr, 1, ctypes.byref(cfg)))
+    assert sizes[0] < sizes[1] < sizes[2]
+    # stats of both views at level 0 dominate: 16 bytes per pixel
+    assert sizes[0] >= 992 * 1436 * 16

@@ -1,0 +1,235 @@
+"""GPU forward parity: pyramid, full search, restricted search, the whole
+hierarchy and the soft-argmax level, against the FP64 oracle (through the C ABI)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_09593_amd import synth
+from parity import TOL_ZNCC, check_level, check_pixels
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1901_09593_amd import msibm
+    msibm.lib()
+    return msibm
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _tex_pair(seed, H, W, s, dtype="u8", noise=2.0):
+    """A textured pair with a smooth disparity field (slanted planes)."""
+    p = synth.make_pair(seed, H, W, 3, max(1, s // 2), s, True, 0.9, 5.0 if dtype == "u8" else 0.02,
+                        noise if dtype == "u8" else noise / 255, dtype)
+    return p
+
+
+# ------------------------------------------------------------------ pyramid
+
+@pytest.mark.parametrize("dtype,shape", [("u8", (240, 320)), ("u8", (37, 53)), ("f32", (61, 90))])
+def test_pyramid_matches_oracle(M, dtype, shape):
+    p = _tex_pair(1, shape[0], shape[1], 8, dtype)
+    K = 5
+    lv = M.pyramid(dev(p.left), K)
+    ref = oracle.pyramid(p.left, K)
+    for k in range(K):
+        got = host(lv[k]).astype(np.float64)
+        assert got.shape == ref[k].shape
+        if dtype == "u8" and k <= 2:
+            assert np.array_equal(got, ref[k]), f"level {k} not bit-exact"
+        else:
+            # float rounding from level 3 on (uint8) or level 1 on (float input):
+            # a few units in the last place of the intensity range
+            scale = 255.0 if dtype == "u8" else 1.0
+            assert np.abs(got - ref[k]).max() <= 4e-7 * scale
+
+
+# ------------------------------------------------------------------ full search
+
+FULL_CASES = [
+    # (H, W, n, D, dtype, seed)
+    (60, 80, 3, 16, "u8", 0),
+    (37, 150, 2, 40, "u8", 1),     # several candidate steps, ragged tile
+    (23, 301, 4, 200, "f32", 2),   # several right-image chunks
+    (9, 17, 1, 30, "u8", 3),       # D > W: clipped by the column index
+    (12, 12, 6, 5, "f32", 4),      # window larger than the image
+    (1, 40, 2, 8, "u8", 5),        # one row
+    (33, 1, 1, 4, "f32", 6),       # one column
+    (16, 130, 5, 1, "u8", 7),      # a single candidate
+]
+
+
+@pytest.mark.parametrize("H,W,n,D,dtype,seed", FULL_CASES)
+def test_full_search_parity(M, H, W, n, D, dtype, seed):
+    p = _tex_pair(seed, H, W, max(2, D // 2), dtype)
+    eps = 0.065 if dtype == "u8" else 1e-6
+    d, C = M.match_level(dev(p.left), dev(p.right), n, D, None, 0, eps)
+    st = check_level(host(d), host(C), p.left, p.right, n, D, None, 0, eps)
+    assert st["mismatch"] <= 0.01
+
+
+def test_flat_block_matching_small320(M):
+    p, cfg = synth.workload("small320")
+    d, C = M.match_level(dev(p.left), dev(p.right), cfg.half_window, cfg.max_disp, None, 0,
+                         cfg.var_eps)
+    st = check_level(host(d), host(C), p.left, p.right, cfg.half_window, cfg.max_disp, None, 0,
+                     cfg.var_eps)
+    print("flat BM small320", st)
+
+
+# ------------------------------------------------------------------ restricted search
+
+REFINE_CASES = [
+    # (H, W, n, Dk, r, dtype, seed)
+    (48, 70, 2, 24, 0, "u8", 10),
+    (48, 70, 2, 24, 1, "u8", 11),
+    (64, 200, 3, 60, 2, "u8", 12),
+    (31, 133, 4, 64, 3, "f32", 13),
+    (40, 100, 1, 40, 4, "f32", 14),
+    (17, 45, 6, 30, 2, "u8", 15),
+    (25, 257, 5, 128, 2, "f32", 16),
+]
+
+
+@pytest.mark.parametrize("H,W,n,Dk,r,dtype,seed", REFINE_CASES)
+def test_restricted_search_parity(M, H, W, n, Dk, r, dtype, seed):
+    p = _tex_pair(seed, H, W, Dk * 3 // 4, dtype)
+    eps = 0.065 if dtype == "u8" else 1e-6
+    rng = np.random.Generator(np.random.PCG64(seed))
+    Hc, Wc = (H + 1) // 2, (W + 1) // 2
+    Dc = -(-Dk // 2)
+    # half the priors from the ground truth (a plausible coarse map), half random
+    # (outliers spread over the whole range, several right-image chunks per tile)
+    gt = np.clip(np.rint(p.disp[::2, ::2] / 2), 0, Dc - 1).astype(np.int16)
+    rnd = rng.integers(0, Dc, size=(Hc, Wc)).astype(np.int16)
+    prior = np.where(rng.random((Hc, Wc)) < 0.5, gt, rnd).astype(np.int16)
+    d, C = M.match_level(dev(p.left), dev(p.right), n, Dk, dev(prior), r, eps)
+    st = check_level(host(d), host(C), p.left, p.right, n, Dk, prior, r, eps)
+    assert st["mismatch"] <= 0.01
+
+
+# ------------------------------------------------------------------ hierarchy
+
+def test_hierarchy_small320_per_level_and_end_to_end(M):
+    p, cfg = synth.workload("small320")
+    K, n, r, D, eps = cfg.levels, cfg.half_window, cfg.refine_radius, cfg.max_disp, cfg.var_eps
+    Lg, Rg = dev(p.left), dev(p.right)
+    out = M.disparity(Lg, Rg, D, K, n, r, eps, with_prior1=True)
+    # the same kernels level by level: GPU pyramid, then teacher-forced levels
+    PL = M.pyramid(Lg, K)
+    PR = M.pyramid(Rg, K)
+    maps = [None] * K
+    costs = [None] * K
+    for k in range(K - 1, -1, -1):
+        Lk = Lg if k == 0 else PL[k]
+        Rk = Rg if k == 0 else PR[k]
+        prior = None if k == K - 1 else maps[k + 1]
+        maps[k], costs[k] = M.match_level(Lk, Rk, n, -(-D // (1 << k)), prior, r, eps)
+    assert torch.equal(maps[0], out["disp"]) and torch.equal(costs[0], out["cost"])
+    assert torch.equal(maps[1], out["prior1"])
+    # each level against the oracle with the GPU's own prior (teacher forcing)
+    for k in range(K):
+        Lk = host(PL[k]).astype(np.float64)
+        Rk = host(PR[k]).astype(np.float64)
+        prior = None if k == K - 1 else host(maps[k + 1])
+        st = check_level(host(maps[k]), host(costs[k]), Lk, Rk, n, -(-D // (1 << k)), prior, r, eps)
+        print(f"level {k}", st)
+    # end to end without teacher forcing: report the cascaded mismatch rate
+    ref = oracle.disparity(p.left, p.right, D, K, n, r, eps)
+    mism = float((host(out["disp"]) != ref[0][0]).mean())
+    print("end-to-end level-0 mismatch rate", mism)
+    assert mism < 0.01
+
+
+def test_mid1436_full_size_sampled(M):
+    """The benchmark workload at full size, in the launch configuration the
+    benchmark times; level 0 checked on sampled pixels against the oracle fed
+    the GPU's level-1 map."""
+    p, cfg = synth.workload("mid1436")
+    K, n, r, D, eps = cfg.levels, cfg.half_window, cfg.refine_radius, cfg.max_disp, cfg.var_eps
+    out = M.disparity(dev(p.left), dev(p.right), D, K, n, r, eps, with_prior1=True)
+    d, C, p1 = host(out["disp"]), host(out["cost"]), host(out["prior1"])
+    rng = np.random.Generator(np.random.PCG64(99))
+    H, W = d.shape
+    ii = rng.integers(0, H, 6000)
+    jj = rng.integers(0, W, 6000)
+    # include the borders and the left strip where priors get clipped
+    ii = np.concatenate([ii, np.zeros(50, int), np.full(50, H - 1), rng.integers(0, H, 100)])
+    jj = np.concatenate([jj, rng.integers(0, W, 100), np.arange(100) % 7])
+    st = check_pixels(d, C, p.left, p.right, n, D, p1, r, eps, ii, jj)
+    print("mid1436 sampled", st)
+    # accuracy sanity against the generator's ground truth
+    vis = p.nonocc
+    err = np.abs(d.astype(np.float64) - p.disp)
+    print("mid1436 mean |d - gt| on visible pixels", err[vis].mean(), "bad>2px", (err[vis] > 2).mean())
+    assert (err[vis] <= 2).mean() > 0.8
+
+
+def test_repeatable(M):
+    p, cfg = synth.workload("small320")
+    a = M.disparity(dev(p.left), dev(p.right), cfg.max_disp, cfg.levels, cfg.half_window,
+                    cfg.refine_radius, cfg.var_eps)
+    b = M.disparity(dev(p.left), dev(p.right), cfg.max_disp, cfg.levels, cfg.half_window,
+                    cfg.refine_radius, cfg.var_eps)
+    assert torch.equal(a["disp"], b["disp"]) and torch.equal(a["cost"], b["cost"])
+
+
+@pytest.mark.parametrize("H,W,K", [(1, 1, 1), (1, 1, 3), (3, 2, 2), (5, 9, 8), (2, 300, 4)])
+def test_degenerate_shapes(M, H, W, K):
+    rng = np.random.Generator(np.random.PCG64(H * 100 + W))
+    L = rng.integers(0, 256, size=(H, W)).astype(np.uint8)
+    R = rng.integers(0, 256, size=(H, W)).astype(np.uint8)
+    D, n, r, eps = 12, 2, 1, 0.065
+    out = M.disparity(dev(L), dev(R), D, K, n, r, eps, with_prior1=K >= 2)
+    ref = oracle.disparity(L, R, D, K, n, r, eps)
+    d = host(out["disp"])
+    # teacher-forced level 0 check with the GPU's level-1 map
+    prior = host(out["prior1"]) if K >= 2 else None
+    check_level(d, host(out["cost"]), L, R, n, D, prior, r, eps)
+    if K == 1:
+        gap = ref[0][1] - ref[0][2]
+        assert np.all((d == ref[0][0]) | (gap <= TOL_ZNCC))
+
+
+def test_pitched_input(M):
+    p, cfg = synth.workload("small320")
+    big_l = torch.zeros((240, 384), dtype=torch.uint8, device="cuda")
+    big_r = torch.zeros((240, 384), dtype=torch.uint8, device="cuda")
+    big_l[:, :320] = dev(p.left)
+    big_r[:, :320] = dev(p.right)
+    a = M.disparity(big_l[:, :320], big_r[:, :320], cfg.max_disp, cfg.levels, cfg.half_window,
+                    cfg.refine_radius, cfg.var_eps)
+    b = M.disparity(dev(p.left), dev(p.right), cfg.max_disp, cfg.levels, cfg.half_window,
+                    cfg.refine_radius, cfg.var_eps)
+    assert torch.equal(a["disp"], b["disp"])
+
+
+# ------------------------------------------------------------------ soft level
+
+def test_soft_level_parity_diff960_crop(M):
+    p, cfg = synth.workload("diff960", 0)
+    L = np.ascontiguousarray(p.left[:180, :320])
+    R = np.ascontiguousarray(p.right[:180, :320])
+    K, n, r, D, eps, rs, tau = cfg.levels, cfg.half_window, cfg.refine_radius, cfg.max_disp, \
+        cfg.var_eps, cfg.soft_radius, cfg.tau
+    out = M.disparity(dev(L), dev(R), D, K, n, r, eps, soft_radius=rs, tau=tau)
+    p1 = host(out["prior1"])
+    ds_o, dh_o, C_o, C2_o = oracle.soft_level0(L, R, n, D, p1, rs, tau, eps)
+    ds = host(out["soft"]).astype(np.float64)
+    assert np.abs(ds - ds_o).max() <= 1e-2
+    print("soft max |dd|", np.abs(ds - ds_o).max())
+    check_level(host(out["disp"]), host(out["cost"]), L, R, n, D, p1, rs, eps,
+                ref=(dh_o, C_o, C2_o))
