@@ -101,6 +101,15 @@ const char* msibm_last_error(void);
 const char* msibm_version(void);
 
 /*
+ * msibm_force_variant - pin the matching kernel's shape for every later call in
+ * this process (for tests and tuning): 1 = right window statistics staged in
+ * LDS with the right tile, 0 = read by each thread from global memory; -1
+ * restores the automatic choice.  Results do not depend on the variant.
+ * Errors: INVALID_ARG (outside -1..1).
+ */
+msibm_status msibm_force_variant(int32_t variant);
+
+/*
  * msibm_pyramid - the K-level Gaussian pyramid of one image (Section III).
  * The blur is the separable 5-tap binomial [1 4 6 4 1]/16 with clamp-to-edge
  * reads, sampled at even rows and columns.

@@ -142,6 +142,13 @@ const char* msibm_last_error(void) { return g_err.c_str(); }
 
 const char* msibm_version(void) { return "msibm 0.1 gfx950"; }
 
+msibm_status msibm_force_variant(int32_t variant)
+{
+    if (variant < -1 || variant > 1) return fail(MSIBM_ERR_INVALID_ARG, "variant %d outside -1..1", variant);
+    force_variant(variant);
+    return ok();
+}
+
 msibm_status msibm_pyramid(const void* img, int32_t dtype, int32_t H, int32_t W, int32_t pitch,
                            int32_t K, float* const* levels, const int32_t* level_pitch, void* stream)
 {
@@ -207,18 +214,12 @@ msibm_status msibm_match_level(const void* L, const void* R, int32_t dtype, int3
     float4* st = (float4*)workspace;
     float4* st_r = (float4*)((char*)workspace + align_up((size_t)H * W * sizeof(float4)));
     StatsArgs sa{};
-    sa.src[0] = L;
-    sa.src[1] = R;
-    sa.dst[0] = st;
-    sa.dst[1] = st_r;
-    sa.views = 2;
-    sa.H = H;
-    sa.W = W;
-    sa.spitch = pitch;
-    sa.dpitch = W;
+    sa.seg[0] = StatsSeg{L, st, dtype, H, W, pitch, W, 0};
+    sa.seg[1] = StatsSeg{R, st_r, dtype, H, W, pitch, W, 0};
+    sa.nseg = 2;
     sa.n = n;
     sa.var_eps = var_eps;
-    hipError_t e = launch_stats(dtype, sa, s);
+    hipError_t e = launch_stats(sa, s);
     if (e != hipSuccess) return hip_fail(e, "stats launch");
     MatchArgs a{};
     a.L = L;
@@ -241,6 +242,7 @@ msibm_status msibm_match_level(const void* L, const void* R, int32_t dtype, int3
     a.opitch = out_pitch;
     a.inv_tau = 0.f;
     const int mode = prior ? MODE_REFINE : MODE_FULL;
+    a.variant = pick_variant(H, W, mode);
     e = launch_match(n, dtype, mode, prior ? slots_for_radius(r) : FULL_NC, a, s);
     if (e != hipSuccess) return hip_fail(e, "match launch");
     return ok();

@@ -15,8 +15,7 @@ constexpr int MATCH_TX = 64;               // threads across a workgroup (one wa
 constexpr int MATCH_TY = 4;                // waves per workgroup
 constexpr int MATCH_THREADS = MATCH_TX * MATCH_TY;
 constexpr int TILE_W = 2 * MATCH_TX;       // 128 pixel columns per workgroup
-constexpr int TILE_H = 2 * MATCH_TY;       // 8 pixel rows per workgroup
-constexpr int CHUNK = 96;                  // candidates held in LDS per right-image chunk
+constexpr int TILE_H1 = 2 * MATCH_TY;      // 8 pixel rows per block row of the workgroup
 constexpr int FULL_NC = 8;                 // slots per step of a full search
 
 enum MatchMode { MODE_FULL = 0, MODE_REFINE = 1, MODE_SOFT = 2 };
@@ -41,7 +40,11 @@ struct MatchArgs {
     float* soft_out;          // soft mode only
     int opitch;
     float inv_tau;
+    int variant;              // VARIANT_* bits (kernel shape chosen by the tuner)
 };
+
+// Kernel shape variants of the matching kernel.
+constexpr int VARIANT_STATS_LDS = 1;  // right statistics staged in LDS
 
 struct ReduceArgs {
     const void* src[2];
@@ -51,11 +54,19 @@ struct ReduceArgs {
     int Ho, Wo, dpitch;       // destination level
 };
 
-struct StatsArgs {
-    const void* src[2];
-    float4* dst[2];
-    int views;
+// One (level, view) image whose window statistics a stats launch computes.
+struct StatsSeg {
+    const void* src;
+    float4* dst;
+    int dtype;                // MSIBM_U8 / MSIBM_F32 element type of src
     int H, W, spitch, dpitch;
+    int tile0;                // first tile index (filled by the launcher)
+};
+constexpr int STATS_MAX_SEG = 16;
+
+struct StatsArgs {
+    StatsSeg seg[STATS_MAX_SEG];
+    int nseg;
     int n;
     double var_eps;
 };
@@ -75,7 +86,7 @@ __device__ __forceinline__ float to_f(T v) { return static_cast<float>(v); }
 // matching kernels, so the template instances compile in parallel).
 hipError_t launch_reduce(int dtype, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_convert(int dtype, const ConvertArgs& a, hipStream_t s);
-hipError_t launch_stats(int dtype, const StatsArgs& a, hipStream_t s);
+hipError_t launch_stats(StatsArgs a, hipStream_t s);
 hipError_t launch_match(int n, int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
 
 hipError_t launch_match_n1(int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);

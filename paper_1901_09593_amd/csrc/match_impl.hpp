@@ -1,17 +1,18 @@
 // ZNCC winner-take-all matching of one pyramid level (Eqs. 1-4 and 8-9), with
 // the soft-argmax of the differentiable finest level.
 //
-// Work split.  A workgroup of 4 waves covers a TILE_H x TILE_W (8 x 128) pixel
-// tile; each thread owns one 2x2 pixel block.  The left tile with its window
-// halo sits in LDS once; the right image is staged in LDS one CHUNK of candidate
-// disparities at a time.  For a block and a window of NC consecutive candidate
-// slots, the thread walks the 2n+2 window rows: it loads the 2n+2 left values
-// and 2n+1+NC right values of the row from LDS and accumulates, per slot, the
-// products shared by both pixel columns once plus one edge product per column.
-// That costs (2n+2)^2 fused multiply-adds per slot for the block's 4 window
-// sums instead of 4 (2n+1)^2 for four independent windows.  The cross sum is
-// then normalised with per-pixel statistics (window mean, 1/sqrt(A)) and the
-// running winner-take-all keeps the lowest z among equal scores.
+// Work split.  A workgroup of 4 waves covers a TILE_H x 128 pixel tile, TILE_H =
+// 8 BY; each thread owns BY 2x2 pixel blocks stacked 8 rows apart.  The left
+// tile with its window halo sits in LDS once; the right image and its window
+// statistics are staged in LDS one chunk of candidate disparities at a time.
+// For a block and a window of NC consecutive candidate slots, the thread walks
+// the 2n+2 window rows: it loads the 2n+2 left values and 2n+1+NC right values
+// of the row from LDS and accumulates, per slot, the products shared by both
+// pixel columns once plus one edge product per column.  That costs (2n+2)^2
+// fused multiply-adds per slot for the block's 4 window sums instead of
+// 4 (2n+1)^2 for four independent windows.  The cross sum is then normalised
+// with per-pixel statistics (window mean, 1/sqrt(A)) and a running
+// winner-take-all keeps the lowest z among equal scores.
 //
 // Modes
 //   MODE_FULL   every valid candidate 0..min(D_k-1, j) in steps of NC slots
@@ -24,6 +25,8 @@
 // columns.  A wave's 64 lanes read columns 2*lane + t, which this layout turns
 // into 64 consecutive words (no bank conflicts), and t's parity is a
 // compile-time constant, so every load is one ds_read with an immediate offset.
+// Staging writes one even and one odd column per lane and iteration, straight
+// to their two halves.
 //
 // Precision.  The score is invariant to a constant offset of either window, so
 // each thread centres its left windows on a = the window mean of its block's
@@ -40,61 +43,141 @@
 
 namespace msibm {
 
-template <int NW>
-struct Geo {
-    static constexpr int WN = 2 * NW + 2;          // rows/cols spanned by a block's windows
-    static constexpr int LROWS = TILE_H + 2 * NW;  // LDS rows (both views)
-    static constexpr int LCOLS = TILE_W + 2 * NW;  // left tile logical width
-    static constexpr int LHALF = (LCOLS + 1) / 2;
-    static constexpr int LSTRIDE = 2 * LHALF + 1;
-    static constexpr int RCOLS = TILE_W + 2 * NW + CHUNK - 1;
-    static constexpr int RHALF = (RCOLS + 1) / 2;
-    static constexpr int RSTRIDE = 2 * RHALF + 1;
+// Candidates per right-image chunk: a full search streams through every
+// candidate, a restricted search normally needs one short window per tile.
+template <int MODE>
+struct ChunkOf {
+    static constexpr int value = (MODE == MODE_FULL) ? 96 : 32;
 };
 
-__device__ __forceinline__ int split_pos(int c, int half) { return (c & 1) ? half + (c >> 1) : (c >> 1); }
+template <int NW, int CH, int BY>
+struct Geo {
+    static constexpr int TH = TILE_H1 * BY;       // tile height in pixels
+    static constexpr int WN = 2 * NW + 2;         // rows/cols spanned by a block's windows
+    static constexpr int LROWS = TH + 2 * NW;     // LDS rows (both views)
+    static constexpr int LCOLS = TILE_W + 2 * NW; // left tile logical width
+    static constexpr int LHALF = (LCOLS + 1) / 2;
+    static constexpr int LSTRIDE = 2 * LHALF + 1;
+    static constexpr int RCOLS = TILE_W + 2 * NW + CH - 1;
+    static constexpr int RHALF = (RCOLS + 1) / 2;
+    static constexpr int RSTRIDE = 2 * RHALF + 1;
+    static constexpr int SCOLS = TILE_W + CH - 1;  // right statistics columns
+    static constexpr int SHALF = (SCOLS + 1) / 2;
+    static constexpr int SSTRIDE = 2 * SHALF + 1;
+};
 
-// Stage rows [gy0, gy0+rows) x cols [gx0, gx0+cols) of `src` (clamped to the
-// image) into LDS in split layout, centred by c.  Each wave takes whole rows and
-// its lanes consecutive columns, so global reads coalesce.
-template <typename T>
+// LDS of one matching tile: the left tile, one chunk of the right tile, and the
+// right window statistics of the chunk's columns (window mean minus the right
+// centring constant, and 1/sd).
+template <int NW, int CH, int BY>
+struct MatchSmem {
+    using G = Geo<NW, CH, BY>;
+    float Ls[G::LROWS * G::LSTRIDE];
+    float Rs[G::LROWS * G::RSTRIDE];
+    float Sm[G::TH * G::SSTRIDE];
+    float Si[G::TH * G::SSTRIDE];
+    int lo, hi;
+    unsigned mask;
+};
+
+// Stage rows [gy0, gy0+ROWS) x cols [gx0, gx0+cols) (cols <= MAXCOLS) of `src`,
+// clamped to the image, into LDS in split layout (even columns at [0, half),
+// odd ones at [half, ...)), centred by c.  Each wave takes whole rows; lane l of
+// iteration k stages columns 2(l + 64k) and 2(l + 64k) + 1.  Clamped addresses
+// are always valid, so every load of the thread is issued unconditionally
+// before any LDS store and their latencies overlap.
+template <typename T, int ROWS, int MAXCOLS>
 __device__ __forceinline__ void stage_tile(float* dst, int stride, int half, const T* __restrict__ src,
-                                           int pitch, int H, int W, int gy0, int gx0, int rows, int cols,
-                                           float c)
+                                           int pitch, int H, int W, int gy0, int gx0, int cols, float c)
 {
+    constexpr int RI = (ROWS + MATCH_TY - 1) / MATCH_TY;
+    constexpr int CI = (MAXCOLS + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
-    for (int rr = wave; rr < rows; rr += MATCH_TY) {
+    T v0[RI][CI], v1[RI][CI];
+#pragma unroll
+    for (int ri = 0; ri < RI; ++ri) {
+        const int rr = wave + MATCH_TY * ri;
         const T* srow = src + (size_t)clampi(gy0 + rr, 0, H - 1) * pitch;
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci) {
+            const int cc = 2 * (lane + MATCH_TX * ci);
+            v0[ri][ci] = srow[clampi(gx0 + cc, 0, W - 1)];
+            v1[ri][ci] = srow[clampi(gx0 + cc + 1, 0, W - 1)];
+        }
+    }
+#pragma unroll
+    for (int ri = 0; ri < RI; ++ri) {
+        const int rr = wave + MATCH_TY * ri;
+        if (rr >= ROWS) continue;
         float* drow = dst + rr * stride;
-        for (int cc = lane; cc < cols; cc += MATCH_TX)
-            drow[split_pos(cc, half)] = to_f(srow[clampi(gx0 + cc, 0, W - 1)]) - c;
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci) {
+            const int ch = lane + MATCH_TX * ci;  // column pair index
+            if (2 * ch < cols) drow[ch] = to_f(v0[ri][ci]) - c;
+            if (2 * ch + 1 < cols) drow[half + ch] = to_f(v1[ri][ci]) - c;
+        }
     }
 }
 
-// Window sums for one block and NC candidate slots.
-//   lrow0   LDS row of the block's first window row (2*ty)
-//   ltx     thread column index (the block's first window column is 2*ltx)
-//   rcol0   logical LDS column of the right value that pairs with the first
-//           window column at the LAST slot (largest z)
-//   ca      the thread's left centring constant
-// S[p][s]: p = 0 (row 0, col 0), 1 (row 0, col 1), 2 (row 1, col 0), 3 (row 1, col 1).
-// One window row: load the block's 2n+2 left values and 2n+1+NC right values.
-template <int NW, int NC>
+// Stage the right statistics of rows [gy0, gy0+ROWS) x cols [gx0, gx0+cols)
+// into two split-layout LDS planes: the window mean minus c (its float value and
+// rounding remainder summed after the subtraction) and 1/sd.
+template <int ROWS, int MAXCOLS>
+__device__ __forceinline__ void stage_stats(float* mc, float* is, int stride, int half,
+                                            const float4* __restrict__ src, int spitch, int H, int W,
+                                            int gy0, int gx0, int cols, float c)
+{
+    constexpr int RI = (ROWS + MATCH_TY - 1) / MATCH_TY;
+    constexpr int CI = (MAXCOLS + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
+    const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
+    float4 v0[RI][CI], v1[RI][CI];
+#pragma unroll
+    for (int ri = 0; ri < RI; ++ri) {
+        const int rr = wave + MATCH_TY * ri;
+        const float4* srow = src + (size_t)clampi(gy0 + rr, 0, H - 1) * spitch;
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci) {
+            const int cc = 2 * (lane + MATCH_TX * ci);
+            v0[ri][ci] = srow[clampi(gx0 + cc, 0, W - 1)];
+            v1[ri][ci] = srow[clampi(gx0 + cc + 1, 0, W - 1)];
+        }
+    }
+#pragma unroll
+    for (int ri = 0; ri < RI; ++ri) {
+        const int rr = wave + MATCH_TY * ri;
+        if (rr >= ROWS) continue;
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci) {
+            const int ch = lane + MATCH_TX * ci;
+            if (2 * ch < cols) {
+                mc[rr * stride + ch] = (v0[ri][ci].x - c) + v0[ri][ci].y;
+                is[rr * stride + ch] = v0[ri][ci].z;
+            }
+            if (2 * ch + 1 < cols) {
+                mc[rr * stride + half + ch] = (v1[ri][ci].x - c) + v1[ri][ci].y;
+                is[rr * stride + half + ch] = v1[ri][ci].z;
+            }
+        }
+    }
+}
+
+// One window row: load the block's 2n+2 left values (centred by ca) and
+// 2n+1+NC right values.
+template <int NW, int NC, int LSTRIDE, int LHALF, int RSTRIDE>
 __device__ __forceinline__ void load_row(const float* __restrict__ Ls, const float* __restrict__ Rs,
                                          int row, int ltx, int pa, int pb, float ca,
                                          float (&l)[2 * NW + 2], float (&r)[2 * NW + 1 + NC])
 {
-    using G = Geo<NW>;
-    const float* lr_ = Ls + row * G::LSTRIDE + ltx;
-    const float* rr_ = Rs + row * G::RSTRIDE;
+    const float* lr_ = Ls + row * LSTRIDE + ltx;
+    const float* rr_ = Rs + row * RSTRIDE;
 #pragma unroll
-    for (int t = 0; t < 2 * NW + 2; ++t) l[t] = lr_[(t & 1) ? G::LHALF + (t >> 1) : (t >> 1)] - ca;
+    for (int t = 0; t < 2 * NW + 2; ++t) l[t] = lr_[(t & 1) ? LHALF + (t >> 1) : (t >> 1)] - ca;
 #pragma unroll
     for (int u = 0; u < 2 * NW + 1 + NC; ++u) r[u] = (u & 1) ? rr_[pb + (u >> 1)] : rr_[pa + (u >> 1)];
 }
 
 // Window sums for one block and NC candidate slots.
-//   lrow0   LDS row of the block's first window row (2*ty)
+//   lrow0   LDS row of the block's first window row
 //   ltx     thread column index (the block's first window column is 2*ltx)
 //   rcol0   logical LDS column of the right value that pairs with the first
 //           window column at the LAST slot (largest z)
@@ -102,12 +185,11 @@ __device__ __forceinline__ void load_row(const float* __restrict__ Ls, const flo
 // S[p][s]: p = 0 (row 0, col 0), 1 (row 0, col 1), 2 (row 1, col 0), 3 (row 1, col 1).
 // Rows 1..2n feed both pixel rows (accumulated once: MC for the columns both
 // pixel columns share, M0/M1 for each column's extra edge column); row 0 feeds
-// only the upper pixels (T0/T1) and row 2n+1 only the lower ones (B0/B1).
-template <int NW, int NC>
+// only the upper pixels and row 2n+1 only the lower ones.
+template <int NW, int NC, class G>
 __device__ __forceinline__ void window_sums(const float* __restrict__ Ls, const float* __restrict__ Rs,
                                             int lrow0, int ltx, int rcol0, float ca, float (&S)[4][NC])
 {
-    using G = Geo<NW>;
     constexpr int WN = G::WN;
     // right row: even logical offsets u come from base pa, odd ones from pb
     int pa, pb;
@@ -121,7 +203,7 @@ __device__ __forceinline__ void window_sums(const float* __restrict__ Ls, const 
     float l[WN], r[WN + NC - 1];
     float MC[NC], M0[NC], M1[NC];
     // first row: upper pixels only
-    load_row<NW, NC>(Ls, Rs, lrow0, ltx, pa, pb, ca, l, r);
+    load_row<NW, NC, G::LSTRIDE, G::LHALF, G::RSTRIDE>(Ls, Rs, lrow0, ltx, pa, pb, ca, l, r);
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
         const int o = NC - 1 - s;  // slot s pairs column t with right value t + o
@@ -135,7 +217,7 @@ __device__ __forceinline__ void window_sums(const float* __restrict__ Ls, const 
     // shared rows
 #pragma unroll 2
     for (int y = 1; y < WN - 1; ++y) {
-        load_row<NW, NC>(Ls, Rs, lrow0 + y, ltx, pa, pb, ca, l, r);
+        load_row<NW, NC, G::LSTRIDE, G::LHALF, G::RSTRIDE>(Ls, Rs, lrow0 + y, ltx, pa, pb, ca, l, r);
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
             const int o = NC - 1 - s;
@@ -148,7 +230,7 @@ __device__ __forceinline__ void window_sums(const float* __restrict__ Ls, const 
         }
     }
     // last row: lower pixels only
-    load_row<NW, NC>(Ls, Rs, lrow0 + WN - 1, ltx, pa, pb, ca, l, r);
+    load_row<NW, NC, G::LSTRIDE, G::LHALF, G::RSTRIDE>(Ls, Rs, lrow0 + WN - 1, ltx, pa, pb, ca, l, r);
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
         const int o = NC - 1 - s;
@@ -163,204 +245,283 @@ __device__ __forceinline__ void window_sums(const float* __restrict__ Ls, const 
     }
 }
 
-template <typename T, int NW, int NC, int MODE>
-__global__ __launch_bounds__(MATCH_THREADS) void match_kernel(MatchArgs a)
-{
-    using G = Geo<NW>;
-    constexpr float Nf = (float)((2 * NW + 1) * (2 * NW + 1));
-    constexpr int STEP = (MODE == MODE_FULL) ? CHUNK : (CHUNK - NC + 1);
-    static_assert(MODE != MODE_FULL || CHUNK % NC == 0, "full search steps must tile a chunk");
+// Per-block state: the block's pixel coordinates (clamped into the image), which
+// of its pixels exist, each pixel's candidate interval, the block's first slot.
+struct BlockState {
+    int ia, ib, ja, jb;
+    bool act[4];
+    int lo[4], hi[4];
+    int zs;
+};
 
-    __shared__ float Ls[G::LROWS * G::LSTRIDE];
-    __shared__ float Rs[G::LROWS * G::RSTRIDE];
-    __shared__ int s_lo, s_hi;
-    __shared__ unsigned s_mask;
+// One TILE_H x TILE_W tile (tile column bx, tile row by) of one level.  Called
+// by the per-level kernel below and by the persistent batched kernel; every
+// thread of the workgroup must call it (it synchronises the workgroup).
+// SL selects where the right statistics come from: staged in LDS with the right
+// tile (1), or read by each thread from global memory (0).
+template <typename T, int NW, int NC, int MODE, int BY, int SL>
+__device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
+                                           MatchSmem<NW, ChunkOf<MODE>::value, BY>& sm)
+{
+    constexpr int CH = ChunkOf<MODE>::value;
+    using G = Geo<NW, CH, BY>;
+    constexpr float Nf = (float)((2 * NW + 1) * (2 * NW + 1));
+    constexpr int STEP = (MODE == MODE_FULL) ? CH : (CH - NC + 1);
+    static_assert(MODE != MODE_FULL || CH % NC == 0, "full search steps must tile a chunk");
+    static_assert(CH >= NC, "a chunk must hold one slot window");
 
     const T* __restrict__ Lg = static_cast<const T*>(a.L);
     const T* __restrict__ Rg = static_cast<const T*>(a.R);
     const int tx = threadIdx.x & (MATCH_TX - 1), ty = threadIdx.x / MATCH_TX;
-    const int x0 = blockIdx.x * TILE_W, y0 = blockIdx.y * TILE_H;
-    const int i0 = y0 + 2 * ty, j0 = x0 + 2 * tx;
-    const bool act[4] = {i0 < a.H && j0 < a.W, i0 < a.H && j0 + 1 < a.W,
-                         i0 + 1 < a.H && j0 < a.W, i0 + 1 < a.H && j0 + 1 < a.W};
-    const bool any = act[0];
-    // clamped coordinates: every load below stays inside the image even for
-    // pixels of a block that hang over the image edge
-    const int ia = min(i0, a.H - 1), ib = min(i0 + 1, a.H - 1);
-    const int ja = min(j0, a.W - 1), jb = min(j0 + 1, a.W - 1);
-    const int ip[4] = {ia, ia, ib, ib};
-    const int jp[4] = {ja, jb, ja, jb};
+    const int x0 = bx * TILE_W, y0 = by * G::TH;
+    const int j0 = x0 + 2 * tx;
 
-    // candidate interval of each pixel and the block's first slot
-    int lo[4], hi[4], zs = 0;
-    if (MODE == MODE_FULL) {
+    // per block: coordinates, candidate intervals and first slot
+    BlockState bs[BY];
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            lo[p] = 0;
-            hi[p] = min(a.Dk - 1, jp[p]);
-        }
-    } else {
-        int dh = 0;
-        // out-of-range prior values (never produced by the coarser level) are
-        // clamped so that every index below stays inside its buffer
-        if (any) dh = clampi(2 * (int)a.prior[(size_t)(ia >> 1) * a.ppitch + (ja >> 1)], 0, a.Dk - 1);
-        zs = (dh <= j0) ? dh - a.r : j0 + 2 - NC;
+    for (int b = 0; b < BY; ++b) {
+        BlockState& q = bs[b];
+        const int i0 = y0 + 2 * ty + TILE_H1 * b;
+        q.act[0] = i0 < a.H && j0 < a.W;
+        q.act[1] = i0 < a.H && j0 + 1 < a.W;
+        q.act[2] = i0 + 1 < a.H && j0 < a.W;
+        q.act[3] = i0 + 1 < a.H && j0 + 1 < a.W;
+        // clamped coordinates keep every load inside the image even for pixels
+        // of a block that hang over the image edge
+        q.ia = min(i0, a.H - 1);
+        q.ib = min(i0 + 1, a.H - 1);
+        q.ja = min(j0, a.W - 1);
+        q.jb = min(j0 + 1, a.W - 1);
+        const int jp[4] = {q.ja, q.jb, q.ja, q.jb};
+        if (MODE == MODE_FULL) {
+            q.zs = 0;
 #pragma unroll
-        for (int p = 0; p < 4; ++p) {
-            const int c = min(dh, jp[p]);
-            lo[p] = max(0, c - a.r);
-            hi[p] = min(min(a.Dk - 1, jp[p]), c + a.r);
+            for (int p = 0; p < 4; ++p) {
+                q.lo[p] = 0;
+                q.hi[p] = min(a.Dk - 1, jp[p]);
+            }
+        } else {
+            // out-of-range prior values (never produced by the coarser level)
+            // are clamped so that every index below stays inside its buffer
+            const int dh = clampi(2 * (int)a.prior[(size_t)(q.ia >> 1) * a.ppitch + (q.ja >> 1)], 0, a.Dk - 1);
+            q.zs = (dh <= j0) ? dh - a.r : j0 + 2 - NC;
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int c = min(dh, jp[p]);
+                q.lo[p] = max(0, c - a.r);
+                q.hi[p] = min(min(a.Dk - 1, jp[p]), c + a.r);
+            }
         }
     }
+    const int cy = min(y0 + G::TH / 2, a.H - 1), cx = min(x0 + TILE_W / 2, a.W - 1);
+    const float cR = to_f(Rg[(size_t)cy * a.pitch + cx]);
+
+    // left tile (uncentred: each thread centres its own windows)
+    stage_tile<T, G::LROWS, G::LCOLS>(sm.Ls, G::LSTRIDE, G::LHALF, Lg, a.pitch, a.H, a.W, y0 - NW,
+                                      x0 - NW, G::LCOLS, 0.f);
 
     // workgroup-wide candidate range; for a restricted search also the set of
     // right-image chunks some block of the tile needs
     if (threadIdx.x == 0) {
-        s_lo = 0x7fffffff;
-        s_hi = -0x7fffffff;
-        s_mask = 0u;
+        sm.lo = 0x7fffffff;
+        sm.hi = -0x7fffffff;
+        sm.mask = 0u;
     }
     __syncthreads();
     if (MODE == MODE_FULL) {
         if (threadIdx.x == 0) {
-            s_lo = 0;
-            s_hi = min(a.Dk - 1, min(x0 + TILE_W, a.W) - 1);
+            sm.lo = 0;
+            sm.hi = min(a.Dk - 1, min(x0 + TILE_W, a.W) - 1);
         }
-    } else if (any) {
-        atomicMin(&s_lo, zs);
-        atomicMax(&s_hi, zs);
+    } else {
+#pragma unroll
+        for (int b = 0; b < BY; ++b)
+            if (bs[b].act[0]) {
+                atomicMin(&sm.lo, bs[b].zs);
+                atomicMax(&sm.hi, bs[b].zs);
+            }
     }
     __syncthreads();
-    const int zlo = s_lo, zhi = s_hi;
-    if (MODE != MODE_FULL && any) atomicOr(&s_mask, 1u << ((zs - zlo) / STEP));
-    __syncthreads();
-    const unsigned mask = (MODE == MODE_FULL) ? 0xffffffffu : s_mask;
-
-    // right-tile centring constant (offsets do not change the score)
-    const int cy = min(y0 + TILE_H / 2, a.H - 1), cx = min(x0 + TILE_W / 2, a.W - 1);
-    const float cR = to_f(Rg[(size_t)cy * a.pitch + cx]);
-    stage_tile<T>(Ls, G::LSTRIDE, G::LHALF, Lg, a.pitch, a.H, a.W, y0 - NW, x0 - NW, G::LROWS,
-                  G::LCOLS, 0.f);
-
-    // per-pixel left statistics; the block's left windows are centred on its
-    // first pixel's window mean
-    float ndl[4], invl[4], ca;
-    {
-        float4 st[4];
+    const int zlo = sm.lo, zhi = sm.hi;
+    if (MODE != MODE_FULL) {
 #pragma unroll
-        for (int p = 0; p < 4; ++p) st[p] = a.statL[(size_t)ip[p] * a.spitch + jp[p]];
-        ca = st[0].x;
+        for (int b = 0; b < BY; ++b)
+            if (bs[b].act[0]) atomicOr(&sm.mask, 1u << ((bs[b].zs - zlo) / STEP));
+    }
+    __syncthreads();
+    const unsigned mask = (MODE == MODE_FULL) ? 0xffffffffu : sm.mask;
+
+    constexpr int SB = (MODE == MODE_SOFT) ? BY : 1, SN = (MODE == MODE_SOFT) ? NC : 1;
+    float best[BY][4], rho_keep[SB][4][SN];
+    int bz[BY][4];
+#pragma unroll
+    for (int b = 0; b < BY; ++b)
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            ndl[p] = -Nf * ((st[p].x - ca) + st[p].y);
-            invl[p] = st[p].z;
+            best[b][p] = -3.f;
+            bz[b][p] = 0;
         }
-    }
-
-    float best[4] = {-3.f, -3.f, -3.f, -3.f};
-    int bz[4] = {0, 0, 0, 0};
-    float rho_keep[(MODE == MODE_SOFT) ? 4 : 1][(MODE == MODE_SOFT) ? NC : 1];
 
     for (int zc = zlo, ci = 0; zc <= zhi; zc += STEP, ++ci) {
         if (MODE != MODE_FULL && !((mask >> ci) & 1u)) continue;
         // largest candidate slot of this chunk: the right tile's column 0 pairs
-        // with the first window column of that slot
-        const int ztop = min(zc + CHUNK - 1, zhi + NC - 1);
-        __syncthreads();  // previous chunk fully consumed (and left tile staged)
-        stage_tile<T>(Rs, G::RSTRIDE, G::RHALF, Rg, a.pitch, a.H, a.W, y0 - NW, x0 - NW - ztop,
-                      G::LROWS, TILE_W + 2 * NW + (ztop - zc), cR);
+        // with the first window column of that slot, and statistics column 0 is
+        // the window centre of the tile's first pixel column at that slot
+        const int ztop = min(zc + CH - 1, zhi + NC - 1);
+        if (zc != zlo) __syncthreads();  // previous chunk fully consumed
+        stage_tile<T, G::LROWS, G::RCOLS>(sm.Rs, G::RSTRIDE, G::RHALF, Rg, a.pitch, a.H, a.W, y0 - NW,
+                                          x0 - NW - ztop, TILE_W + 2 * NW + (ztop - zc), cR);
+        if (SL)
+            stage_stats<G::TH, G::SCOLS>(sm.Sm, sm.Si, G::SSTRIDE, G::SHALF, a.statR, a.spitch, a.H, a.W,
+                                         y0, x0 - ztop, TILE_W + (ztop - zc), cR);
         __syncthreads();
-        if (!any) continue;
 
-        // slot windows this thread evaluates in this chunk
-        int w_first, w_last;
-        if (MODE == MODE_FULL) {
-            w_first = zc;
-            w_last = min(zc + CHUNK - 1, max(hi[0], hi[1]));
-        } else {
-            w_first = zs;
-            w_last = (zs >= zc && zs < zc + STEP) ? zs : zs - 1;
-        }
-        for (int wz = w_first; wz <= w_last; wz += NC) {
-            float S[4][NC];
-            const int rcol0 = 2 * tx + (ztop - wz) - (NC - 1);
-            window_sums<NW, NC>(Ls, Rs, 2 * ty, tx, rcol0, ca, S);
-            // right statistics for columns j0 + 1 - wz - q, q = 0..NC
 #pragma unroll
-            for (int rowp = 0; rowp < 2; ++rowp) {
-                const float4* srow = a.statR + (size_t)ip[2 * rowp] * a.spitch;
-                float4 sr[NC + 1];
+        for (int b = 0; b < BY; ++b) {
+            const BlockState& q = bs[b];
+            if (!q.act[0]) continue;
+            // slot windows of this block in this chunk
+            int w_first, w_last;
+            if (MODE == MODE_FULL) {
+                w_first = zc;
+                w_last = min(zc + CH - 1, max(q.hi[0], q.hi[1]));
+            } else {
+                w_first = q.zs;
+                w_last = (q.zs >= zc && q.zs < zc + STEP) ? q.zs : q.zs - 1;
+            }
+            if (w_first > w_last) continue;
+            // left statistics; the block's left windows are centred on its
+            // first pixel's window mean
+            float4 stl[4];
+            stl[0] = a.statL[(size_t)q.ia * a.spitch + q.ja];
+            stl[1] = a.statL[(size_t)q.ia * a.spitch + q.jb];
+            stl[2] = a.statL[(size_t)q.ib * a.spitch + q.ja];
+            stl[3] = a.statL[(size_t)q.ib * a.spitch + q.jb];
+            const float ca = stl[0].x;
+            float ndl[4], invl[4];
 #pragma unroll
-                for (int q = 0; q <= NC; ++q) sr[q] = srow[clampi(j0 + 1 - wz - q, 0, a.W - 1)];
+            for (int p = 0; p < 4; ++p) {
+                ndl[p] = -Nf * ((stl[p].x - ca) + stl[p].y);
+                invl[p] = stl[p].z;
+            }
+            const int lrow0 = 2 * ty + TILE_H1 * b;
+            for (int wz = w_first; wz <= w_last; wz += NC) {
+                float S[4][NC];
+                const int rcol0 = 2 * tx + (ztop - wz) - (NC - 1);
+                window_sums<NW, NC, G>(sm.Ls, sm.Rs, lrow0, tx, rcol0, ca, S);
+                // right statistics of columns c0 - q, q = 0..NC (c0 = the centre
+                // of pixel column j0 + 1 at slot 0): pixel column cp at slot s is
+                // q = s + 1 - cp
+                const int c0 = 2 * tx + (ztop - wz) + 1;
+                const int be = (c0 & 1) ? G::SHALF + (c0 >> 1) : (c0 >> 1);      // q even
+                const int bo = (c0 & 1) ? (c0 >> 1) : G::SHALF + (c0 >> 1) - 1;  // q odd
 #pragma unroll
-                for (int cp = 0; cp < 2; ++cp) {
-                    const int p = 2 * rowp + cp;
+                for (int rowp = 0; rowp < 2; ++rowp) {
+                    float smc[NC + 1], sis[NC + 1];
+                    if (SL) {
+                        const int so = (lrow0 + rowp) * G::SSTRIDE;
 #pragma unroll
-                    for (int s = 0; s < NC; ++s) {
-                        const int z = wz + s;
-                        const float4 st = sr[s + 1 - cp];
-                        const float C = fmaf(ndl[p], (st.x - cR) + st.y, S[p][s]);
-                        float rho = C * invl[p] * st.z;
-                        rho = fminf(fmaxf(rho, -1.f), 1.f);
-                        const bool ok = (z >= lo[p]) && (z <= hi[p]);
-                        if (MODE == MODE_SOFT) rho_keep[p][s] = ok ? rho : -1e30f;
-                        if (ok && rho > best[p]) {
-                            best[p] = rho;
-                            bz[p] = z;
+                        for (int qq = 0; qq <= NC; ++qq) {
+                            const int o = so + ((qq & 1) ? bo - (qq >> 1) : be - (qq >> 1));
+                            smc[qq] = sm.Sm[o];
+                            sis[qq] = sm.Si[o];
+                        }
+                    } else {
+                        // columns j0 + 1 - wz - q of pixel row ia or ib
+                        const float4* srow = a.statR + (size_t)(rowp ? q.ib : q.ia) * a.spitch;
+#pragma unroll
+                        for (int qq = 0; qq <= NC; ++qq) {
+                            const float4 st = srow[clampi(j0 + 1 - wz - qq, 0, a.W - 1)];
+                            smc[qq] = (st.x - cR) + st.y;
+                            sis[qq] = st.z;
+                        }
+                    }
+#pragma unroll
+                    for (int cp = 0; cp < 2; ++cp) {
+                        const int p = 2 * rowp + cp;
+#pragma unroll
+                        for (int s = 0; s < NC; ++s) {
+                            const int z = wz + s;
+                            const int qq = s + 1 - cp;
+                            const float C = fmaf(ndl[p], smc[qq], S[p][s]);
+                            float rho = C * invl[p] * sis[qq];
+                            rho = fminf(fmaxf(rho, -1.f), 1.f);
+                            const bool ok = (z >= q.lo[p]) && (z <= q.hi[p]);
+                            if (MODE == MODE_SOFT) rho_keep[MODE == MODE_SOFT ? b : 0][p][MODE == MODE_SOFT ? s : 0] = ok ? rho : -1e30f;
+                            if (ok && rho > best[b][p]) {
+                                best[b][p] = rho;
+                                bz[b][p] = z;
+                            }
                         }
                     }
                 }
             }
         }
     }
-    if (!any) return;
-
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        if (!act[p]) continue;
-        const size_t o = (size_t)ip[p] * a.opitch + jp[p];
-        a.d_out[o] = (int16_t)bz[p];
-        if (a.c_out) a.c_out[o] = best[p];
-        if (MODE == MODE_SOFT) {
-            float se = 0.f, sz = 0.f;
+    for (int b = 0; b < BY; ++b) {
+        const BlockState& q = bs[b];
+        const int ip[4] = {q.ia, q.ia, q.ib, q.ib};
+        const int jp[4] = {q.ja, q.jb, q.ja, q.jb};
 #pragma unroll
-            for (int s = 0; s < NC; ++s) {
-                const float e = __expf((rho_keep[p][s] - best[p]) * a.inv_tau);
-                se += e;
-                sz = fmaf(e, (float)(zs + s), sz);
+        for (int p = 0; p < 4; ++p) {
+            if (!q.act[p]) continue;
+            const size_t o = (size_t)ip[p] * a.opitch + jp[p];
+            a.d_out[o] = (int16_t)bz[b][p];
+            if (a.c_out) a.c_out[o] = best[b][p];
+            if (MODE == MODE_SOFT) {
+                float se = 0.f, sz = 0.f;
+#pragma unroll
+                for (int s = 0; s < SN; ++s) {
+                    const float e = __expf((rho_keep[MODE == MODE_SOFT ? b : 0][p][s] - best[b][p]) * a.inv_tau);
+                    se += e;
+                    sz = fmaf(e, (float)(q.zs + s), sz);
+                }
+                a.soft_out[o] = sz / se;
             }
-            a.soft_out[o] = sz / se;
         }
     }
+    __syncthreads();  // LDS may be reused by the caller's next tile
 }
 
-template <typename T, int NW, int NC, int MODE>
+template <typename T, int NW, int NC, int MODE, int BY, int SL>
+__global__ __launch_bounds__(MATCH_THREADS) void match_kernel(MatchArgs a)
+{
+    __shared__ MatchSmem<NW, ChunkOf<MODE>::value, BY> sm;
+    match_tile<T, NW, NC, MODE, BY, SL>(a, blockIdx.x, blockIdx.y, sm);
+}
+
+template <typename T, int NW, int NC, int MODE, int BY>
 static hipError_t launch_one(const MatchArgs& a, hipStream_t s)
 {
-    dim3 grid((a.W + TILE_W - 1) / TILE_W, (a.H + TILE_H - 1) / TILE_H, 1);
-    hipLaunchKernelGGL((match_kernel<T, NW, NC, MODE>), grid, dim3(MATCH_THREADS), 0, s, a);
+    constexpr int TH = TILE_H1 * BY;
+    dim3 grid((a.W + TILE_W - 1) / TILE_W, (a.H + TH - 1) / TH, 1);
+    if (a.variant & VARIANT_STATS_LDS)
+        hipLaunchKernelGGL((match_kernel<T, NW, NC, MODE, BY, 1>), grid, dim3(MATCH_THREADS), 0, s, a);
+    else
+        hipLaunchKernelGGL((match_kernel<T, NW, NC, MODE, BY, 0>), grid, dim3(MATCH_THREADS), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int NW>
+template <typename T, int NW, int BY>
 static hipError_t dispatch_nc(int mode, int nc, const MatchArgs& a, hipStream_t s)
 {
-    if (mode == MODE_FULL) return launch_one<T, NW, FULL_NC, MODE_FULL>(a, s);
+    if (mode == MODE_FULL) return launch_one<T, NW, FULL_NC, MODE_FULL, BY>(a, s);
     if (mode == MODE_REFINE) {
         switch (nc) {
-            case 2: return launch_one<T, NW, 2, MODE_REFINE>(a, s);
-            case 3: return launch_one<T, NW, 3, MODE_REFINE>(a, s);
-            case 5: return launch_one<T, NW, 5, MODE_REFINE>(a, s);
-            case 7: return launch_one<T, NW, 7, MODE_REFINE>(a, s);
-            case 9: return launch_one<T, NW, 9, MODE_REFINE>(a, s);
+            case 2: return launch_one<T, NW, 2, MODE_REFINE, BY>(a, s);
+            case 3: return launch_one<T, NW, 3, MODE_REFINE, BY>(a, s);
+            case 5: return launch_one<T, NW, 5, MODE_REFINE, BY>(a, s);
+            case 7: return launch_one<T, NW, 7, MODE_REFINE, BY>(a, s);
+            case 9: return launch_one<T, NW, 9, MODE_REFINE, BY>(a, s);
         }
         return hipErrorInvalidValue;
     }
     switch (nc) {
-        case 3: return launch_one<T, NW, 3, MODE_SOFT>(a, s);
-        case 5: return launch_one<T, NW, 5, MODE_SOFT>(a, s);
-        case 7: return launch_one<T, NW, 7, MODE_SOFT>(a, s);
-        case 9: return launch_one<T, NW, 9, MODE_SOFT>(a, s);
+        case 3: return launch_one<T, NW, 3, MODE_SOFT, BY>(a, s);
+        case 5: return launch_one<T, NW, 5, MODE_SOFT, BY>(a, s);
+        case 7: return launch_one<T, NW, 7, MODE_SOFT, BY>(a, s);
+        case 9: return launch_one<T, NW, 9, MODE_SOFT, BY>(a, s);
     }
     return hipErrorInvalidValue;
 }
@@ -368,11 +529,9 @@ static hipError_t dispatch_nc(int mode, int nc, const MatchArgs& a, hipStream_t 
 template <int NW>
 static hipError_t dispatch_match(int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s)
 {
-    if (dtype == 0) {
-        if (mode == MODE_SOFT) return hipErrorInvalidValue;  // soft mode takes float images
-        return dispatch_nc<uint8_t, NW>(mode, nc, a, s);
-    }
-    return dispatch_nc<float, NW>(mode, nc, a, s);
+    if (dtype == 0 && mode == MODE_SOFT) return hipErrorInvalidValue;  // soft mode takes float images
+    if (dtype == 0) return dispatch_nc<uint8_t, NW, 1>(mode, nc, a, s);
+    return dispatch_nc<float, NW, 1>(mode, nc, a, s);
 }
 
 }  // namespace msibm

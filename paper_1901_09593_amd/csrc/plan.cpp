@@ -6,6 +6,7 @@
 #include "timing.hpp"
 
 #include <cstdio>
+#include <cstdlib>
 
 namespace msibm {
 
@@ -20,6 +21,26 @@ hipError_t launch_match(int n, int dtype, int mode, int nc, const MatchArgs& a, 
         case 6: return launch_match_n6(dtype, mode, nc, a, s);
     }
     return hipErrorInvalidValue;
+}
+
+// Kernel shape of the matching kernel for one level (VARIANT_* bits).
+// MSIBM_FORCE_VARIANT overrides the choice (tests and tuning).
+static int g_forced_variant = [] {
+    const char* v = getenv("MSIBM_FORCE_VARIANT");
+    return v ? atoi(v) : -1;
+}();
+
+void force_variant(int v) { g_forced_variant = v; }
+
+int pick_variant(int H, int W, int mode)
+{
+    const int forced = g_forced_variant;
+    if (forced >= 0) return forced & VARIANT_STATS_LDS;
+    (void)H;
+    (void)W;
+    // measured on MI355X: a full search reuses each staged statistics column for
+    // every candidate, a restricted search reads only a few per pixel
+    return mode == MODE_FULL ? VARIANT_STATS_LDS : 0;
 }
 
 static int hip_err(hipError_t e, const char* what, std::string* err)
@@ -65,25 +86,18 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
         img[k][1] = r.dst[1];
         pitch[k] = lay.w[k];
     }
-    for (int k = 0; k < K; ++k) {
+    {
         StatsArgs sa{};
-        sa.src[0] = img[k][0];
-        sa.src[1] = img[k][1];
-        sa.dst[0] = (float4*)(ws + lay.stat[k][0]);
-        sa.dst[1] = (float4*)(ws + lay.stat[k][1]);
-        sa.views = 2;
-        sa.H = lay.h[k];
-        sa.W = lay.w[k];
-        sa.spitch = pitch[k];
-        sa.dpitch = lay.w[k];
+        for (int k = 0; k < K; ++k)
+            for (int v = 0; v < 2; ++v)
+                sa.seg[2 * k + v] = StatsSeg{img[k][v], (float4*)(ws + lay.stat[k][v]),
+                                             k == 0 ? P.dtype : MSIBM_F32, lay.h[k], lay.w[k], pitch[k],
+                                             lay.w[k], 0};
+        sa.nseg = 2 * K;
         sa.n = n;
         sa.var_eps = cfg->var_eps;
-        char lab[32];
-        snprintf(lab, sizeof(lab), "stats_l%d", k);
-        {
-            TimedLaunch t(lab, s);
-            e = launch_stats(k == 0 ? P.dtype : MSIBM_F32, sa, s);
-        }
+        TimedLaunch t("stats", s);
+        e = launch_stats(sa, s);
         if (e != hipSuccess) return hip_err(e, "stats launch", err);
     }
     for (int k = K - 1; k >= 0; --k) {
@@ -124,6 +138,7 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
                  mode == MODE_FULL ? "full" : (mode == MODE_SOFT ? "soft" : "refine"), k);
         {
             TimedLaunch t(lab, s);
+            a.variant = pick_variant(a.H, a.W, mode);
             e = launch_match(n, k == 0 ? P.dtype : MSIBM_F32, mode, nc, a, s);
         }
         if (e != hipSuccess) return hip_err(e, "match launch", err);

@@ -79,6 +79,8 @@ def lib() -> ctypes.CDLL:
         L.msibm_backward.argtypes = [ctypes.POINTER(Pair), _I32, ctypes.POINTER(Config), _PP, _PP,
                                      _PP, _PP, _VP, ctypes.c_size_t, _VP]
         L.msibm_backward.restype = _I32
+        L.msibm_force_variant.argtypes = [_I32]
+        L.msibm_force_variant.restype = _I32
         L.msibm_timing_enable.argtypes = [_I32]
         L.msibm_timing_enable.restype = _I32
         L.msibm_timing_read.argtypes = [_I32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -148,6 +150,12 @@ def auto_levels(D: int) -> int:
 def make_config(n: int, r: int, var_eps: float, soft_radius: int = 0, tau: float = 0.05,
                 flags: int = 0) -> Config:
     return Config(n, r, float(var_eps), soft_radius, float(tau), flags)
+
+
+def force_variant(v: int = -1):
+    """Pin the matching kernel shape (1: right statistics staged in LDS, 0: read
+    from global memory); -1 = automatic."""
+    _check(lib().msibm_force_variant(int(v)))
 
 
 def timing_enable(on: bool = True):

@@ -233,3 +233,22 @@ def test_soft_level_parity_diff960_crop(M):
     print("soft max |dd|", np.abs(ds - ds_o).max())
     check_level(host(out["disp"]), host(out["cost"]), L, R, n, D, p1, rs, eps,
                 ref=(dh_o, C_o, C2_o))
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_every_kernel_variant_gives_identical_results(M, variant):
+    p, cfg = synth.workload("small320")
+    K, n, r, D, eps = cfg.levels, cfg.half_window, cfg.refine_radius, cfg.max_disp, cfg.var_eps
+    Lg, Rg = dev(p.left), dev(p.right)
+    M.force_variant(-1)
+    ref = M.disparity(Lg, Rg, D, K, n, r, eps, with_prior1=True)
+    flat_ref = M.match_level(Lg, Rg, n, 40, None, 0, eps)
+    try:
+        M.force_variant(variant)
+        got = M.disparity(Lg, Rg, D, K, n, r, eps, with_prior1=True)
+        flat = M.match_level(Lg, Rg, n, 40, None, 0, eps)
+    finally:
+        M.force_variant(-1)
+    assert torch.equal(ref["disp"], got["disp"]) and torch.equal(ref["cost"], got["cost"])
+    assert torch.equal(ref["prior1"], got["prior1"])
+    assert torch.equal(flat_ref[0], flat[0]) and torch.equal(flat_ref[1], flat[1])
