@@ -1,0 +1,6 @@
+// Backward kernels for (2n+1)x(2n+1) windows with n = 2.
+#include "backward_impl.hpp"
+
+namespace msibm {
+hipError_t launch_backward_n2(int nc, const BackArgs& a, hipStream_t s) { return dispatch_backward<2>(nc, a, s); }
+}  // namespace msibm

@@ -1,0 +1,6 @@
+// Backward kernels for (2n+1)x(2n+1) windows with n = 3.
+#include "backward_impl.hpp"
+
+namespace msibm {
+hipError_t launch_backward_n3(int nc, const BackArgs& a, hipStream_t s) { return dispatch_backward<3>(nc, a, s); }
+}  // namespace msibm

@@ -96,6 +96,17 @@ hipError_t launch_match_n4(int dtype, int mode, int nc, const MatchArgs& a, hipS
 hipError_t launch_match_n5(int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
 hipError_t launch_match_n6(int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
 
+struct BackArgs;
+hipError_t launch_backward(int n, int nc, const BackArgs& a, hipStream_t s);
+hipError_t launch_backward_n1(int nc, const BackArgs& a, hipStream_t s);
+hipError_t launch_backward_n2(int nc, const BackArgs& a, hipStream_t s);
+hipError_t launch_backward_n3(int nc, const BackArgs& a, hipStream_t s);
+hipError_t launch_backward_n4(int nc, const BackArgs& a, hipStream_t s);
+hipError_t launch_backward_n5(int nc, const BackArgs& a, hipStream_t s);
+hipError_t launch_backward_n6(int nc, const BackArgs& a, hipStream_t s);
+// Zero `count` floats at each of up to two pointers (graph-capturable fill).
+hipError_t launch_zero(float* a, float* b, size_t count, hipStream_t s);
+
 // Slots evaluated per block: 2r+1, but at least 2 so that a block whose prior
 // is clipped by the left image border (pixel columns j0 and j0+1 then centre
 // on j0 and j0+1) still fits one window.

@@ -180,6 +180,22 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a)
                               h1, h2);
 }
 
+__global__ __launch_bounds__(256) void zero_kernel(float* a, float* b, size_t count)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) {
+        a[i] = 0.f;
+        if (b) b[i] = 0.f;
+    }
+}
+
+hipError_t launch_zero(float* a, float* b, size_t count, hipStream_t s)
+{
+    const size_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(zero_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, a, b,
+                       count);
+    return hipGetLastError();
+}
+
 int stats_tiles(int H, int W) { return ((W + ST_W - 1) / ST_W) * ((H + ST_H - 1) / ST_H); }
 
 hipError_t launch_reduce(int dtype, const ReduceArgs& a, hipStream_t s)

@@ -80,6 +80,9 @@ struct MatchSmem {
     unsigned mask;
 };
 
+// Position of logical column c in a split-layout row whose odd columns start at `half`.
+__device__ __forceinline__ int split_pos(int c, int half) { return (c & 1) ? half + (c >> 1) : (c >> 1); }
+
 // Stage rows [gy0, gy0+ROWS) x cols [gx0, gx0+cols) (cols <= MAXCOLS) of `src`,
 // clamped to the image, into LDS in split layout (even columns at [0, half),
 // odd ones at [half, ...)), centred by c.  Each wave takes whole rows; lane l of

@@ -1,6 +1,7 @@
 // Launch sequences of the plain (one pair at a time) forward pass.
 #include <hip/hip_runtime.h>
 
+#include "backward_impl.hpp"
 #include "common.hpp"
 #include "plan.hpp"
 #include "timing.hpp"
@@ -146,11 +147,69 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
     return MSIBM_OK;
 }
 
-int run_pair_backward(const msibm_pair&, const PairLayout&, const msibm_config*, char*, const int16_t*,
-                      const float*, float*, float*, hipStream_t, std::string* err)
+hipError_t launch_backward(int n, int nc, const BackArgs& a, hipStream_t s)
 {
-    *err = "backward not built yet";
-    return MSIBM_ERR_UNSUPPORTED;
+    switch (n) {
+        case 1: return launch_backward_n1(nc, a, s);
+        case 2: return launch_backward_n2(nc, a, s);
+        case 3: return launch_backward_n3(nc, a, s);
+        case 4: return launch_backward_n4(nc, a, s);
+        case 5: return launch_backward_n5(nc, a, s);
+        case 6: return launch_backward_n6(nc, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+// Backward of one pair: level-0 window statistics, zeroed gradients, then the
+// backward tiles (which add into the gradients).
+int run_pair_backward(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,
+                      const int16_t* prior1, const float* grad_soft, float* grad_left, float* grad_right,
+                      hipStream_t s, std::string* err)
+{
+    hipError_t e;
+    const int H = P.height, W = P.width;
+    StatsArgs sa{};
+    sa.seg[0] = StatsSeg{P.left, (float4*)(ws + lay.stat[0][0]), MSIBM_F32, H, W, P.pitch, W, 0};
+    sa.seg[1] = StatsSeg{P.right, (float4*)(ws + lay.stat[0][1]), MSIBM_F32, H, W, P.pitch, W, 0};
+    sa.nseg = 2;
+    sa.n = cfg->half_window;
+    sa.var_eps = cfg->var_eps;
+    {
+        TimedLaunch t("bwd_stats", s);
+        e = launch_stats(sa, s);
+    }
+    if (e != hipSuccess) return hip_err(e, "stats launch", err);
+    {
+        TimedLaunch t("bwd_zero", s);
+        e = launch_zero(grad_left, grad_right, (size_t)H * W, s);
+    }
+    if (e != hipSuccess) return hip_err(e, "zero launch", err);
+    BackArgs b{};
+    b.L = (const float*)P.left;
+    b.R = (const float*)P.right;
+    b.H = H;
+    b.W = W;
+    b.pitch = P.pitch;
+    b.statL = (const float4*)(ws + lay.stat[0][0]);
+    b.statR = (const float4*)(ws + lay.stat[0][1]);
+    b.spitch = W;
+    b.D = P.max_disp;
+    b.prior = prior1;
+    b.Hc = lay.h[1];
+    b.Wc = lay.w[1];
+    b.ppitch = lay.w[1];
+    b.rs = cfg->soft_radius;
+    b.inv_tau = 1.f / cfg->tau;
+    b.g = grad_soft;
+    b.gpitch = W;
+    b.gL = grad_left;
+    b.gR = grad_right;
+    {
+        TimedLaunch t("backward_l0", s);
+        e = launch_backward(cfg->half_window, slots_for_radius(cfg->soft_radius), b, s);
+    }
+    if (e != hipSuccess) return hip_err(e, "backward launch", err);
+    return MSIBM_OK;
 }
 
 size_t batch_extra_bytes(const msibm_pair*, int, const msibm_config*) { return 0; }

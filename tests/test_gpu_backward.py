@@ -1,0 +1,130 @@
+"""GPU backward of the differentiable finest level against the FP64 oracle and
+FP64 central finite differences (through the C ABI and the autograd wrapper)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1901_09593_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+REL_TOL = 1e-3
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1901_09593_amd import msibm
+    msibm.lib()
+    return msibm
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _crop_case(H=180, W=320, seed=0):
+    p, cfg = synth.workload("diff960", seed)
+    return (np.ascontiguousarray(p.left[:H, :W]), np.ascontiguousarray(p.right[:H, :W]),
+            p.disp[:H, :W], p.nonocc[:H, :W], cfg)
+
+
+@pytest.mark.parametrize("n,rs", [(3, 3), (1, 1), (5, 2), (2, 4)])
+def test_backward_matches_oracle(M, n, rs):
+    L, R, gt, vis, cfg = _crop_case(96, 200)
+    D, K, r, eps, tau = cfg.max_disp, cfg.levels, cfg.refine_radius, cfg.var_eps, cfg.tau
+    out = M.disparity(dev(L), dev(R), D, K, n, r, eps, soft_radius=rs, tau=tau)
+    p1 = host(out["prior1"])
+    g = synth.grad_seed(1, *L.shape)
+    gL, gR = M.backward(dev(L), dev(R), out["prior1"], dev(g.astype(np.float32)), D, K, n, r, eps, rs, tau)
+    oL, oR = oracle.backward(L, R, n, D, p1, rs, tau, eps, g.astype(np.float32).astype(np.float64))
+    eL, eR = rel(host(gL), oL), rel(host(gR), oR)
+    print(f"n={n} rs={rs} rel error left {eL:.2e} right {eR:.2e}")
+    assert eL <= REL_TOL and eR <= REL_TOL
+
+
+def test_backward_sum_rules_and_repeatability(M):
+    L, R, gt, vis, cfg = _crop_case(120, 256, seed=1)
+    D, K, n, r, eps, rs, tau = cfg.max_disp, cfg.levels, cfg.half_window, cfg.refine_radius, \
+        cfg.var_eps, cfg.soft_radius, cfg.tau
+    out = M.disparity(dev(L), dev(R), D, K, n, r, eps, soft_radius=rs, tau=tau)
+    g = dev(synth.grad_seed(2, *L.shape).astype(np.float32))
+    a = M.backward(dev(L), dev(R), out["prior1"], g, D, K, n, r, eps, rs, tau)
+    b = M.backward(dev(L), dev(R), out["prior1"], g, D, K, n, r, eps, rs, tau)
+    for x, y, img in ((a[0], b[0], L), (a[1], b[1], R)):
+        xs, ys = host(x).astype(np.float64), host(y).astype(np.float64)
+        assert rel(xs, ys) < 1e-5  # only the atomic summation order differs
+        scale = np.abs(xs).sum()
+        assert abs(xs.sum()) < 1e-4 * scale
+        assert abs((xs * img).sum()) < 1e-4 * scale * np.abs(img).max()
+
+
+def test_backward_against_finite_differences(M):
+    """GPU gradient vs FP64 central differences (eps 1e-6) of the oracle forward
+    on a small crop pair whose right view is shifted so true matches stay inside."""
+    p, cfg = synth.workload("diff960", 0)
+    y0, x0, h, w = 200, 400, 40, 48
+    s = int(np.floor(p.disp[y0:y0 + h, x0:x0 + w].min())) - 3
+    L = np.ascontiguousarray(p.left[y0:y0 + h, x0:x0 + w]).astype(np.float32)
+    R = np.ascontiguousarray(p.right[y0:y0 + h, x0 - s:x0 - s + w]).astype(np.float32)
+    n, D, K, r, rs, tau, eps = 3, 24, 2, 2, 3, 0.05, cfg.var_eps
+    out = M.disparity(dev(L), dev(R), D, K, n, r, eps, soft_radius=rs, tau=tau)
+    p1 = host(out["prior1"])
+    g = synth.grad_seed(3, h, w)
+    gL, gR = M.backward(dev(L), dev(R), out["prior1"], dev(g.astype(np.float32)), D, K, n, r, eps, rs, tau)
+    Ld, Rd, gd = L.astype(np.float64), R.astype(np.float64), g.astype(np.float32).astype(np.float64)
+
+    def f(Lx, Rx):
+        ds, *_ = oracle.soft_level0(Lx, Rx, n, D, p1, rs, tau, eps)
+        return float((gd * ds).sum())
+
+    hstep = 1e-6
+    rng = np.random.Generator(np.random.PCG64(4))
+    idx = [tuple(x) for x in np.stack([rng.integers(0, h, 300), rng.integers(0, w, 300)], 1)]
+    for grad, which in ((host(gL), 0), (host(gR), 1)):
+        fd = np.empty(len(idx))
+        for k, (i, j) in enumerate(idx):
+            e = np.zeros_like(Ld)
+            e[i, j] = hstep
+            if which == 0:
+                fd[k] = (f(Ld + e, Rd) - f(Ld - e, Rd)) / (2 * hstep)
+            else:
+                fd[k] = (f(Ld, Rd + e) - f(Ld, Rd - e)) / (2 * hstep)
+        got = np.array([grad[i, j] for i, j in idx], dtype=np.float64)
+        err = rel(got, fd)
+        print("view", which, "rel error vs finite differences", err)
+        assert err <= REL_TOL
+
+
+def test_autograd_loss_gradient(M):
+    """MsibmFunction + a masked L1 loss in torch, against the oracle's loss
+    gradient pushed through the oracle backward."""
+    L, R, gt, vis, cfg = _crop_case(96, 192, seed=2)
+    D, K, n, r, eps, rs, tau = cfg.max_disp, cfg.levels, cfg.half_window, cfg.refine_radius, \
+        cfg.var_eps, cfg.soft_radius, cfg.tau
+    Lt = dev(L).requires_grad_(True)
+    Rt = dev(R).requires_grad_(True)
+    dsoft, dhard = M.MsibmFunction.apply(Lt, Rt, D, K, n, r, eps, rs, tau)
+    mask = dev(oracle.loss_mask(vis, n))
+    loss = (dsoft - dev(gt.astype(np.float32))).abs()[mask].mean()
+    loss.backward()
+    p1 = M.disparity(dev(L), dev(R), D, K, n, r, eps, soft_radius=rs, tau=tau)["prior1"]
+    ds_o, *_ = oracle.soft_level0(L, R, n, D, host(p1), rs, tau, eps)
+    lo, go = oracle.l1_loss(ds_o, gt, oracle.loss_mask(vis, n))
+    assert abs(float(loss.detach()) - lo) < 1e-3 * max(1.0, lo)
+    oL, oR = oracle.backward(L, R, n, D, host(p1), rs, tau, eps, go)
+    eL, eR = rel(host(Lt.grad), oL), rel(host(Rt.grad), oR)
+    print("autograd rel error", eL, eR)
+    assert eL <= REL_TOL and eR <= REL_TOL
