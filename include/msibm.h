@@ -181,6 +181,16 @@ msibm_status msibm_disparity(const msibm_pair* pairs, int32_t n_pairs, const msi
                              void* stream);
 
 /*
+ * msibm_batch_status - after a batched msibm_disparity call with the same
+ * pairs, cfg and workspace: waits for the device to go idle and reports
+ * MSIBM_ERR_DEADLOCK if any task of the persistent launch waited longer than
+ * its bound (its results are then incomplete), MSIBM_OK otherwise.  Synchronous.
+ * Errors: INVALID_ARG, WORKSPACE, HIP, DEADLOCK.
+ */
+msibm_status msibm_batch_status(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg,
+                                const void* workspace, size_t ws_bytes);
+
+/*
  * msibm_backward - gradient of sum_{ij} g(i,j) d_soft(i,j) with respect to the
  * level-0 left and right images, with the level-1 prior held fixed (it is
  * piecewise constant in the images).  Recomputes every window statistic and

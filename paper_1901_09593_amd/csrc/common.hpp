@@ -77,6 +77,56 @@ struct ConvertArgs {
     int H, W, spitch, dpitch;
 };
 
+// ---------------------------------------------------------------- batches
+// Work of a batch of pairs is described by segments: one per (pair, stage,
+// level), each a grid of tiles of that stage's tile function.
+
+enum SegType { SEG_REDUCE = 0, SEG_STATS = 1, SEG_FULL = 2, SEG_REFINE = 3, SEG_SOFT = 4 };
+
+// One level of one pair as the persistent kernel sees it.
+struct LevelDesc {
+    const void* img[2];   // level image of both views (level 0: the caller's input)
+    int pitch, H, W;
+    float4* stat[2];      // window statistics, row pitch W
+    int16_t* map;         // winner-take-all map, row pitch W (level 0: the caller's output)
+    float* cost;          // level 0 only, nullable
+    float* soft;          // level 0 only, soft mode
+    int Dk;
+    int dtype;            // element type of img (MSIBM_U8 / MSIBM_F32)
+};
+
+struct Segment {
+    int type, pair, level;
+    int tiles_x, tiles_y;
+    int task0;            // first global task number
+    int band0;            // first band counter
+    int dep_seg[2];       // segments whose bands this one reads (-1 = none)
+};
+
+// Arguments of a launch that covers the tiles of several segments: block b of
+// the launch runs tile (b - task0) of the last segment whose task0 <= b.
+struct MultiArgs {
+    const Segment* segs;      // this launch's segments, task0 ascending from 0
+    int nseg;
+    const LevelDesc* levels;  // K entries per pair, from level_base[pair]
+    const int* level_base;
+    int n, r, rs;
+    double var_eps;
+    float inv_tau;
+};
+
+// Segment of launch block b (binary search; every thread computes it).
+__device__ __forceinline__ int segment_of(const Segment* segs, int nseg, int b)
+{
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (segs[mid].task0 <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
 template <typename T>
@@ -88,6 +138,17 @@ hipError_t launch_reduce(int dtype, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_convert(int dtype, const ConvertArgs& a, hipStream_t s);
 hipError_t launch_stats(StatsArgs a, hipStream_t s);
 hipError_t launch_match(int n, int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
+
+// Multi-segment launches (batched path); `blocks` = total tiles of the segments.
+hipError_t launch_match_multi(int n, int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_reduce_multi(int dtype, const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_stats_multi(const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_match_multi_n1(int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_match_multi_n2(int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_match_multi_n3(int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_match_multi_n4(int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_match_multi_n5(int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_match_multi_n6(int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);
 
 hipError_t launch_match_n1(int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
 hipError_t launch_match_n2(int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);

@@ -212,13 +212,4 @@ int run_pair_backward(const msibm_pair& P, const PairLayout& lay, const msibm_co
     return MSIBM_OK;
 }
 
-size_t batch_extra_bytes(const msibm_pair*, int, const msibm_config*) { return 0; }
-
-int run_batched(const msibm_pair*, int, const msibm_config*, const BatchOutputs&, void*, size_t,
-                hipStream_t, std::string* err)
-{
-    *err = "batched path not built yet";
-    return MSIBM_ERR_UNSUPPORTED;
-}
-
 }  // namespace msibm
