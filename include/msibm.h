@@ -17,6 +17,8 @@
  *     the caller sees; scratch comes from a caller-provided workspace whose size
  *     the *_workspace_size functions give.  Pointers are not retained after a
  *     call returns (except inside a captured graph, see MSIBM_FLAG_GRAPH).
+ *     Internally the batched path keeps pinned host staging, a capture stream
+ *     and cached graphs per device until the process ends.
  *   - Images are row-major with a row pitch counted in ELEMENTS (pitch >= width).
  *     Pixel (i, j) is row i, column j.
  *   - Disparity convention: left pixel (i, j) is compared with right pixel
@@ -53,7 +55,6 @@ typedef int32_t msibm_status;
 #define MSIBM_ERR_WORKSPACE (-3)   /* workspace missing or too small          */
 #define MSIBM_ERR_UNSUPPORTED (-4) /* parameter outside the compiled range    */
 #define MSIBM_ERR_HIP (-5)         /* HIP runtime error                       */
-#define MSIBM_ERR_DEADLOCK (-6)    /* batched scheduler watchdog fired        */
 
 /* element types of input images */
 #define MSIBM_U8 0  /* uint8_t, intensity range 0..255 */
@@ -66,8 +67,10 @@ typedef int32_t msibm_status;
 #define MSIBM_MAX_PAIRS 256       /* pairs per msibm_disparity call          */
 
 /* flags of msibm_config.flags */
-#define MSIBM_FLAG_BATCHED 1 /* all pairs and levels in one persistent launch */
-#define MSIBM_FLAG_GRAPH 2   /* with BATCHED: capture once, replay a hipGraph */
+#define MSIBM_FLAG_BATCHED 1    /* one launch per stage for all pairs together  */
+#define MSIBM_FLAG_GRAPH 2      /* with BATCHED: capture once, replay a hipGraph */
+#define MSIBM_FLAG_PERSISTENT 4 /* reserved: single-launch persistent scheduler;
+                                   switched off, fails with UNSUPPORTED       */
 
 /* One rectified stereo pair.  left/right are device pointers of `dtype`. */
 typedef struct msibm_pair {
@@ -168,27 +171,25 @@ size_t msibm_workspace_size(const msibm_pair* pairs, int32_t n_pairs, const msib
  *                  level-1 map (the prior of level 0) that msibm_backward needs;
  *                  unused when K == 1.
  *   workspace      device scratch of msibm_workspace_size(pairs, n_pairs, cfg).
- * Without MSIBM_FLAG_BATCHED the pairs run one after another (plain path).  With
- * it every pair and level runs in ONE persistent kernel launch with a device
- * task queue; with MSIBM_FLAG_GRAPH too, that launch (and the queue reset) is
- * captured in a hipGraph keyed by the pairs' shapes, pointers and cfg and
- * replayed on later calls with the same key.
- * Errors: INVALID_ARG, SHAPE, UNSUPPORTED, WORKSPACE, HIP, DEADLOCK.
+ * Without MSIBM_FLAG_BATCHED the pairs run one after another (plain path: 2K
+ * launches per pair).  With it the pairs advance together, one launch per stage
+ * covering every pair's tiles: the reduce of each level, one statistics launch,
+ * then per level (coarsest first) one matching launch per (mode, dtype) present;
+ * the outputs are bit-identical to the plain path.  The launches find their
+ * tiles through a small table that is copied into the workspace on `stream`
+ * from library-owned pinned host memory.  With MSIBM_FLAG_GRAPH too, the first
+ * call captures the launch sequence into a hipGraph (on a library-owned stream,
+ * with a library-owned device copy of the table) keyed by the device, the pairs
+ * (pointers, shapes, D, K), cfg, the output pointers and the workspace; later
+ * calls with the same key replay it on `stream`.  The graph keeps using those
+ * buffers: the caller keeps them alive and unchanged in size while it replays.
+ * MSIBM_FLAG_GRAPH without MSIBM_FLAG_BATCHED is INVALID_ARG.
+ * Errors: INVALID_ARG, SHAPE, UNSUPPORTED, WORKSPACE, HIP.
  */
 msibm_status msibm_disparity(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg,
                              int16_t* const* disp, float* const* cost, float* const* soft_disp,
                              int16_t* const* prior1, void* workspace, size_t ws_bytes,
                              void* stream);
-
-/*
- * msibm_batch_status - after a batched msibm_disparity call with the same
- * pairs, cfg and workspace: waits for the device to go idle and reports
- * MSIBM_ERR_DEADLOCK if any task of the persistent launch waited longer than
- * its bound (its results are then incomplete), MSIBM_OK otherwise.  Synchronous.
- * Errors: INVALID_ARG, WORKSPACE, HIP, DEADLOCK.
- */
-msibm_status msibm_batch_status(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg,
-                                const void* workspace, size_t ws_bytes);
 
 /*
  * msibm_backward - gradient of sum_{ij} g(i,j) d_soft(i,j) with respect to the

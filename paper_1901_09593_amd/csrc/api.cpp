@@ -78,8 +78,12 @@ msibm_status validate_config(const msibm_config* cfg)
                     MSIBM_MAX_RADIUS);
     if (cfg->soft_radius > 0 && (!(cfg->tau > 0.f) || !std::isfinite(cfg->tau)))
         return fail(MSIBM_ERR_INVALID_ARG, "tau must be finite and > 0");
+    if (cfg->flags & MSIBM_FLAG_PERSISTENT)
+        return fail(MSIBM_ERR_UNSUPPORTED, "the persistent single-launch scheduler is switched off");
     if (cfg->flags & ~(MSIBM_FLAG_BATCHED | MSIBM_FLAG_GRAPH))
         return fail(MSIBM_ERR_INVALID_ARG, "unknown flags 0x%x", cfg->flags);
+    if ((cfg->flags & MSIBM_FLAG_GRAPH) && !(cfg->flags & MSIBM_FLAG_BATCHED))
+        return fail(MSIBM_ERR_INVALID_ARG, "MSIBM_FLAG_GRAPH needs MSIBM_FLAG_BATCHED");
     return MSIBM_OK;
 }
 
@@ -285,9 +289,6 @@ msibm_status msibm_disparity(const msibm_pair* pairs, int32_t n_pairs, const msi
 
     hipStream_t s = (hipStream_t)stream;
     if (cfg->flags & MSIBM_FLAG_BATCHED) {
-        // The persistent scheduler hung twice on MI355X with the cause not
-        // found; it stays switched off until one is shown.
-        if (n_pairs > 0) return fail(MSIBM_ERR_UNSUPPORTED, "persistent batched scheduler is disabled");
         BatchOutputs out{disp, cost, soft_disp, prior1};
         std::string err;
         const int rc = run_batched(pairs, n_pairs, cfg, out, workspace, ws_bytes, s, &err);
@@ -306,26 +307,6 @@ msibm_status msibm_disparity(const msibm_pair* pairs, int32_t n_pairs, const msi
                                       &err);
         if (rc != MSIBM_OK) return fail(rc, "pair %d: %s", p, err.c_str());
     }
-    return ok();
-}
-
-msibm_status msibm_batch_status(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg,
-                                const void* workspace, size_t ws_bytes)
-{
-    if (!pairs || !workspace || n_pairs < 1 || n_pairs > MSIBM_MAX_PAIRS)
-        return fail(MSIBM_ERR_INVALID_ARG, "bad arguments");
-    msibm_status st = validate_config(cfg);
-    if (st != MSIBM_OK) return st;
-    if (!(cfg->flags & MSIBM_FLAG_BATCHED)) return fail(MSIBM_ERR_INVALID_ARG, "cfg is not batched");
-    const size_t need = msibm_workspace_size(pairs, n_pairs, cfg);
-    if (need == 0 || ws_bytes < need) return fail(MSIBM_ERR_WORKSPACE, "workspace too small");
-    int flag = 0;
-    hipError_t e = hipDeviceSynchronize();
-    if (e == hipSuccess)
-        e = hipMemcpy(&flag, (const char*)workspace + batch_error_offset(pairs, n_pairs, cfg), sizeof(int),
-                      hipMemcpyDeviceToHost);
-    if (e != hipSuccess) return hip_fail(e, "status read");
-    if (flag) return fail(MSIBM_ERR_DEADLOCK, "a batched task waited longer than its bound");
     return ok();
 }
 

@@ -1,297 +1,163 @@
-// Batched forward: task layout on the host, persistent-kernel launch, and the
-// cached hipGraph of [counter reset + persistent kernel].
+// Batched forward: all pairs of a call advance stage by stage, one launch per
+// stage whose grid holds the tiles of every pair at that stage.
+//
+// Stages, in stream order: the pyramid reduce of level k for k = 1..K_max-1,
+// the window statistics of every level, then the matching of level k from
+// k = K_max-1 down to 0 (a pair whose coarsest level is k does its full search
+// in that step; finer levels refine the map the previous step wrote).  Within
+// a launch no tile waits on another; the stream order between launches carries
+// every dependency.  A matching step holds one launch per (mode, element type)
+// present, since those are separate kernel instances.
+//
+// Launches find their tiles through a table of segments (one per pair and
+// level) and per-level descriptors.  Without MSIBM_FLAG_GRAPH the table is
+// uploaded into the workspace for every call from pinned host staging; with it
+// the whole sequence is captured once into a hipGraph that owns a device copy of
+// its table, and later calls with the same key replay the graph.
 #include <hip/hip_runtime.h>
 
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
 #include <vector>
 
-#include "batch_impl.hpp"
+#include "levels_impl.hpp"
 #include "plan.hpp"
 #include "timing.hpp"
 
 namespace msibm {
 
-// Window sizes, refine radii and soft radii the persistent kernel is built for.
-static bool batch_supported(const msibm_config* cfg)
-{
-    const int n = cfg->half_window, r = cfg->refine_radius, rs = cfg->soft_radius;
-    return n >= 3 && n <= 5 && (r == 2 || r == 3) && (rs == 0 || rs == 3);
-}
+static int cdiv(int a, int b) { return (a + b - 1) / b; }
+static int levels_of(const msibm_pair& p) { return p.num_levels ? p.num_levels : auto_levels(p.max_disp); }
+
+enum StageKind { STAGE_REDUCE = 0, STAGE_STATS = 1, STAGE_MATCH = 2 };
+
+struct StageLaunch {
+    int kind, level;
+    int mode, dtype, nc;  // matching only
+    int first, nseg, blocks;
+};
 
 struct BatchPlan {
     std::vector<Segment> segs;
     std::vector<LevelDesc> levels;
     std::vector<int> level_base;
-    int ntasks = 0, nbands = 0;
-    // byte offsets inside the batch region of the workspace
-    size_t off_counters, off_head, off_segs, off_levels, off_base, bytes;
+    std::vector<StageLaunch> launches;
+    size_t off_levels = 0, off_base = 0, bytes = 0;  // table layout
 };
 
-static int cdiv(int a, int b) { return (a + b - 1) / b; }
-
-// Segments in topological order: all pyramid reduces (by level), all window
-// statistics, then the matching levels from each pair's coarsest level down.
-static void build_segments(const msibm_pair* pairs, int np, const msibm_config* cfg, const int* K,
-                           BatchPlan& pl)
+// Tiles of one level: reduce and statistics tiles cover one view each, matching
+// tiles both.
+static Segment make_seg(int type, int p, int k, int h, int w, int task0)
 {
+    Segment s{};
+    s.type = type;
+    s.pair = p;
+    s.level = k;
+    if (type == SEG_REDUCE) {
+        s.tiles_x = cdiv(w, RD_W);
+        s.tiles_y = cdiv(h, RD_H);
+        s.views = 2;
+    } else if (type == SEG_STATS) {
+        s.tiles_x = cdiv(w, ST_W);
+        s.tiles_y = cdiv(h, ST_H);
+        s.views = 2;
+    } else {
+        s.tiles_x = cdiv(w, TILE_W);
+        s.tiles_y = cdiv(h, TILE_H1);
+        s.views = 1;
+    }
+    s.task0 = task0;
+    return s;
+}
+
+static int seg_tiles(const Segment& s) { return s.tiles_x * s.tiles_y * s.views; }
+
+// Segments and launches (no device pointers yet).
+static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg, BatchPlan& pl)
+{
+    std::vector<int> K(np);
     int Kmax = 0;
-    for (int p = 0; p < np; ++p) Kmax = K[p] > Kmax ? K[p] : Kmax;
-    std::vector<std::vector<int>> red(np, std::vector<int>(MSIBM_MAX_LEVELS, -1)),
-        sta(np, std::vector<int>(MSIBM_MAX_LEVELS, -1)), mat(np, std::vector<int>(MSIBM_MAX_LEVELS, -1));
-    auto add = [&](int type, int p, int k, int tx, int ty, int d0, int d1) {
-        Segment s{};
-        s.type = type;
-        s.pair = p;
-        s.level = k;
-        s.tiles_x = tx;
-        s.tiles_y = ty;
-        s.task0 = pl.ntasks;
-        s.band0 = pl.nbands;
-        s.dep_seg[0] = d0;
-        s.dep_seg[1] = d1;
-        pl.ntasks += tx * ty;
-        pl.nbands += ty;
-        pl.segs.push_back(s);
-        return (int)pl.segs.size() - 1;
+    for (int p = 0; p < np; ++p) {
+        K[p] = levels_of(pairs[p]);
+        Kmax = K[p] > Kmax ? K[p] : Kmax;
+    }
+    auto h_of = [&](int p, int k) { return level_dim(pairs[p].height, k); };
+    auto w_of = [&](int p, int k) { return level_dim(pairs[p].width, k); };
+    auto begin = [&](int kind, int level, int mode, int dtype, int nc) {
+        StageLaunch l{};
+        l.kind = kind;
+        l.level = level;
+        l.mode = mode;
+        l.dtype = dtype;
+        l.nc = nc;
+        l.first = (int)pl.segs.size();
+        pl.launches.push_back(l);
     };
-    for (int k = 1; k < Kmax; ++k)
+    auto add = [&](int type, int p, int k) {
+        StageLaunch& l = pl.launches.back();
+        const Segment s = make_seg(type, p, k, h_of(p, k), w_of(p, k), l.blocks);
+        l.blocks += seg_tiles(s);
+        l.nseg++;
+        pl.segs.push_back(s);
+    };
+    for (int k = 1; k < Kmax; ++k) {
+        begin(STAGE_REDUCE, k, 0, 0, 0);
         for (int p = 0; p < np; ++p)
-            if (k < K[p]) {
-                const int h = level_dim(pairs[p].height, k), w = level_dim(pairs[p].width, k);
-                red[p][k] = add(SEG_REDUCE, p, k, cdiv(w, RD_W), cdiv(h, RD_H), k >= 2 ? red[p][k - 1] : -1, -1);
-            }
+            if (k < K[p]) add(SEG_REDUCE, p, k);
+    }
+    begin(STAGE_STATS, -1, 0, 0, 0);
     for (int k = 0; k < Kmax; ++k)
         for (int p = 0; p < np; ++p)
-            if (k < K[p]) {
-                const int h = level_dim(pairs[p].height, k), w = level_dim(pairs[p].width, k);
-                sta[p][k] = add(SEG_STATS, p, k, cdiv(w, ST_W), cdiv(h, ST_H), k >= 1 ? red[p][k] : -1, -1);
+            if (k < K[p]) add(SEG_STATS, p, k);
+    const int modes[3] = {MODE_FULL, MODE_REFINE, MODE_SOFT};
+    const int segtype[3] = {SEG_FULL, SEG_REFINE, SEG_SOFT};
+    for (int k = Kmax - 1; k >= 0; --k)
+        for (int m = 0; m < 3; ++m)
+            for (int dt = 0; dt < 2; ++dt) {
+                bool opened = false;
+                for (int p = 0; p < np; ++p) {
+                    if (k >= K[p]) continue;
+                    const bool coarsest = (k == K[p] - 1);
+                    const int mode =
+                        coarsest ? MODE_FULL : ((k == 0 && cfg->soft_radius > 0) ? MODE_SOFT : MODE_REFINE);
+                    const int dtype = k == 0 ? pairs[p].dtype : MSIBM_F32;
+                    if (mode != modes[m] || dtype != dt) continue;
+                    if (!opened) {
+                        const int nc = mode == MODE_FULL
+                                           ? FULL_NC
+                                           : slots_for_radius(mode == MODE_SOFT ? cfg->soft_radius
+                                                                                : cfg->refine_radius);
+                        begin(STAGE_MATCH, k, mode, dt, nc);
+                        opened = true;
+                    }
+                    add(segtype[m], p, k);
+                }
             }
-    for (int d = 0; d < Kmax; ++d)
-        for (int p = 0; p < np; ++p) {
-            const int k = K[p] - 1 - d;
-            if (k < 0) continue;
-            const int h = level_dim(pairs[p].height, k), w = level_dim(pairs[p].width, k);
-            const bool coarsest = (k == K[p] - 1);
-            const int type = coarsest ? SEG_FULL : ((k == 0 && cfg->soft_radius > 0) ? SEG_SOFT : SEG_REFINE);
-            mat[p][k] = add(type, p, k, cdiv(w, TILE_W), cdiv(h, TILE_H1), sta[p][k], coarsest ? -1 : mat[p][k + 1]);
-        }
-}
-
-static void plan_layout(BatchPlan& pl, int np, int nlevels)
-{
-    size_t off = 0;
-    pl.off_counters = off;
-    off = align_up(off + sizeof(int) * (size_t)pl.nbands);
-    pl.off_head = off;  // head, error
-    off = align_up(off + 2 * sizeof(int));
-    pl.off_segs = off;
-    off = align_up(off + sizeof(Segment) * pl.segs.size());
+    size_t off = align_up(sizeof(Segment) * pl.segs.size());
     pl.off_levels = off;
-    off = align_up(off + sizeof(LevelDesc) * (size_t)nlevels);
+    int nl = 0;
+    for (int p = 0; p < np; ++p) nl += K[p];
+    off = align_up(off + sizeof(LevelDesc) * (size_t)nl);
     pl.off_base = off;
-    off = align_up(off + sizeof(int) * (size_t)np);
-    pl.bytes = off;
+    pl.bytes = align_up(off + sizeof(int) * (size_t)np);
 }
 
-static int levels_of(const msibm_pair& p) { return p.num_levels ? p.num_levels : auto_levels(p.max_disp); }
-
-size_t batch_extra_bytes(const msibm_pair* pairs, int n_pairs, const msibm_config* cfg)
+// Level descriptors of every pair, with its workspace region and outputs.
+static void plan_levels(const msibm_pair* pairs, int np, const BatchOutputs& out, char* workspace,
+                        BatchPlan& pl)
 {
-    if (!(cfg->flags & MSIBM_FLAG_BATCHED)) return 0;
-    std::vector<int> K(n_pairs);
-    int nl = 0;
-    for (int p = 0; p < n_pairs; ++p) {
-        K[p] = levels_of(pairs[p]);
-        nl += K[p];
-    }
-    BatchPlan pl;
-    build_segments(pairs, n_pairs, cfg, K.data(), pl);
-    plan_layout(pl, n_pairs, nl);
-    return pl.bytes;
-}
-
-template <int NW, int NCR, int NCS>
-static hipError_t launch_persistent_t(const BatchArgs& a, hipStream_t s)
-{
-    static int grid = 0;
-    if (!grid) {
-        int dev = 0, cus = 0, per_cu = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel<NW, NCR, NCS>, MATCH_THREADS, 0);
-        grid = cus * (per_cu > 0 ? per_cu : 1);
-    }
-    hipLaunchKernelGGL((persistent_kernel<NW, NCR, NCS>), dim3(grid), dim3(MATCH_THREADS), 0, s, a);
-    return hipGetLastError();
-}
-
-template <int NW>
-static hipError_t launch_persistent_n(int ncr, int ncs, const BatchArgs& a, hipStream_t s)
-{
-    if (ncr == 5 && ncs == 0) return launch_persistent_t<NW, 5, 0>(a, s);
-    if (ncr == 7 && ncs == 0) return launch_persistent_t<NW, 7, 0>(a, s);
-    if (ncr == 5 && ncs == 7) return launch_persistent_t<NW, 5, 7>(a, s);
-    if (ncr == 7 && ncs == 7) return launch_persistent_t<NW, 7, 7>(a, s);
-    return hipErrorInvalidValue;
-}
-
-static hipError_t launch_persistent(int n, int ncr, int ncs, const BatchArgs& a, hipStream_t s)
-{
-    switch (n) {
-        case 3: return launch_persistent_n<3>(ncr, ncs, a, s);
-        case 4: return launch_persistent_n<4>(ncr, ncs, a, s);
-        case 5: return launch_persistent_n<5>(ncr, ncs, a, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-// Two seconds of wall_clock64() ticks: far longer than any task, short enough
-// that a broken table ends the kernel promptly.
-static long long wait_ticks()
-{
-    static long long ticks = 0;
-    if (!ticks) {
-        int dev = 0, khz = 0;
-        hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
-            khz = 100000;  // 100 MHz
-        ticks = 2000LL * khz;
-    }
-    return ticks;
-}
-
-__global__ void zero_ints(int* p, int count)
-{
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) p[i] = 0;
-}
-
-// Enqueue [counter reset, persistent kernel] for a plan whose tables are in place.
-static hipError_t enqueue_batch(const BatchPlan& pl, char* bw, const msibm_config* cfg, hipStream_t s)
-{
-    BatchArgs a{};
-    a.segs = (const Segment*)(bw + pl.off_segs);
-    a.nseg = (int)pl.segs.size();
-    a.ntasks = pl.ntasks;
-    a.levels = (const LevelDesc*)(bw + pl.off_levels);
-    a.level_base = (const int*)(bw + pl.off_base);
-    a.counters = (int*)(bw + pl.off_counters);
-    a.head = (int*)(bw + pl.off_head);
-    a.error = a.head + 1;
-    a.n = cfg->half_window;
-    a.r = cfg->refine_radius;
-    a.rs = cfg->soft_radius;
-    a.var_eps = cfg->var_eps;
-    a.inv_tau = cfg->soft_radius > 0 ? 1.f / cfg->tau : 0.f;
-    a.wait_ticks = wait_ticks();
-    // counters, head and error are contiguous from off_counters up to the tables
-    const int nints = (int)((pl.off_segs - pl.off_counters) / sizeof(int));
-    hipLaunchKernelGGL(zero_ints, dim3((nints + 255) / 256 < 1024 ? (nints + 255) / 256 : 1024), dim3(256), 0, s,
-                       a.counters, nints);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    TimedLaunch t("persistent", s);
-    return launch_persistent(cfg->half_window, slots_for_radius(cfg->refine_radius),
-                             cfg->soft_radius ? slots_for_radius(cfg->soft_radius) : 0, a, s);
-}
-
-// Graph cache: one instantiated graph per (pairs, outputs, workspace, config).
-struct GraphKey {
-    std::vector<char> bytes;
-    bool operator<(const GraphKey& o) const { return bytes < o.bytes; }
-};
-struct GraphEntry {
-    hipGraphExec_t exec = nullptr;
-};
-static std::mutex g_graph_mu;
-static std::map<GraphKey, GraphEntry> g_graphs;
-
-static GraphKey make_key(const msibm_pair* pairs, int np, const msibm_config* cfg, const BatchOutputs& out,
-                         void* ws, size_t ws_bytes, hipStream_t s)
-{
-    GraphKey k;
-    auto put = [&](const void* p, size_t n) {
-        const char* c = (const char*)p;
-        k.bytes.insert(k.bytes.end(), c, c + n);
-    };
-    put(pairs, sizeof(msibm_pair) * np);
-    put(cfg, sizeof(msibm_config));
-    for (int p = 0; p < np; ++p) {
-        const void* q[4] = {out.disp[p], out.cost ? out.cost[p] : nullptr, out.soft ? out.soft[p] : nullptr,
-                            out.prior1 ? out.prior1[p] : nullptr};
-        put(q, sizeof(q));
-    }
-    put(&ws, sizeof(ws));
-    put(&ws_bytes, sizeof(ws_bytes));
-    put(&s, sizeof(s));
-    return k;
-}
-
-// Offset of the batched scheduler's error flag inside the workspace.
-size_t batch_error_offset(const msibm_pair* pairs, int np, const msibm_config* cfg)
-{
-    std::vector<int> K(np);
-    int nl = 0;
-    size_t base = 0;
-    for (int p = 0; p < np; ++p) {
-        K[p] = levels_of(pairs[p]);
-        nl += K[p];
-        base += pair_layout(pairs[p], K[p]).bytes;
-    }
-    BatchPlan pl;
-    build_segments(pairs, np, cfg, K.data(), pl);
-    plan_layout(pl, np, nl);
-    return base + pl.off_head + sizeof(int);
-}
-
-int run_batched(const msibm_pair* pairs, int np, const msibm_config* cfg, const BatchOutputs& out,
-                void* workspace, size_t ws_bytes, hipStream_t s, std::string* err)
-{
-    if (!batch_supported(cfg)) {
-        *err = "the batched launch supports half_window 3..5, refine_radius 2 or 3 and soft_radius 0 or 3";
-        return MSIBM_ERR_UNSUPPORTED;
-    }
-    for (int p = 1; p < np; ++p)
-        if (pairs[p].dtype != pairs[0].dtype) {
-            *err = "every pair of a batched call must have the same dtype";
-            return MSIBM_ERR_UNSUPPORTED;
-        }
-    const bool use_graph = (cfg->flags & MSIBM_FLAG_GRAPH) != 0;
-    GraphKey key;
-    if (use_graph) {
-        key = make_key(pairs, np, cfg, out, workspace, ws_bytes, s);
-        std::lock_guard<std::mutex> g(g_graph_mu);
-        auto it = g_graphs.find(key);
-        if (it != g_graphs.end()) {
-            TimedLaunch t("graph", s);
-            hipError_t e = hipGraphLaunch(it->second.exec, s);
-            if (e != hipSuccess) {
-                *err = std::string("graph launch: ") + hipGetErrorString(e);
-                return MSIBM_ERR_HIP;
-            }
-            return MSIBM_OK;
-        }
-    }
-    // per-pair layouts and level descriptors
-    std::vector<int> K(np);
-    int nl = 0;
-    for (int p = 0; p < np; ++p) {
-        K[p] = levels_of(pairs[p]);
-        nl += K[p];
-    }
-    BatchPlan pl;
-    build_segments(pairs, np, cfg, K.data(), pl);
-    plan_layout(pl, np, nl);
     size_t base = 0;
     for (int p = 0; p < np; ++p) {
         const msibm_pair& P = pairs[p];
-        const PairLayout lay = pair_layout(P, K[p]);
-        char* ws = (char*)workspace + base;
+        const int K = levels_of(P);
+        const PairLayout lay = pair_layout(P, K);
+        char* ws = workspace + base;
         base += lay.bytes;
         pl.level_base.push_back((int)pl.levels.size());
-        for (int k = 0; k < K[p]; ++k) {
+        for (int k = 0; k < K; ++k) {
             LevelDesc d{};
             if (k == 0) {
                 d.img[0] = P.left;
@@ -316,44 +182,241 @@ int run_batched(const msibm_pair* pairs, int np, const msibm_config* cfg, const 
             pl.levels.push_back(d);
         }
     }
-    char* bw = (char*)workspace + base;
-    // tables: one host staging buffer, copied in one transfer
-    std::vector<char> host(pl.bytes - pl.off_segs);
+}
+
+static size_t pairs_bytes(const msibm_pair* pairs, int np)
+{
+    size_t b = 0;
+    for (int p = 0; p < np; ++p) b += pair_layout(pairs[p], levels_of(pairs[p])).bytes;
+    return b;
+}
+
+size_t batch_extra_bytes(const msibm_pair* pairs, int n_pairs, const msibm_config* cfg)
+{
+    if (!(cfg->flags & MSIBM_FLAG_BATCHED)) return 0;
+    BatchPlan pl;
+    plan_stages(pairs, n_pairs, cfg, pl);
+    return pl.bytes;
+}
+
+// Host image of the table: segments, level descriptors, level bases.
+static void pack_table(const BatchPlan& pl, std::vector<char>& host)
+{
+    host.assign(pl.bytes, 0);
     std::memcpy(host.data(), pl.segs.data(), sizeof(Segment) * pl.segs.size());
-    std::memcpy(host.data() + (pl.off_levels - pl.off_segs), pl.levels.data(), sizeof(LevelDesc) * pl.levels.size());
-    std::memcpy(host.data() + (pl.off_base - pl.off_segs), pl.level_base.data(), sizeof(int) * pl.level_base.size());
-    hipError_t e = hipMemcpyAsync(bw + pl.off_segs, host.data(), host.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);  // host buffer is released on return
+    std::memcpy(host.data() + pl.off_levels, pl.levels.data(), sizeof(LevelDesc) * pl.levels.size());
+    std::memcpy(host.data() + pl.off_base, pl.level_base.data(), sizeof(int) * pl.level_base.size());
+}
+
+// Enqueue every stage launch; `table` is the device copy of the plan's table.
+static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const msibm_config* cfg, bool timed,
+                                 hipStream_t s)
+{
+    MultiArgs a{};
+    a.levels = (const LevelDesc*)(table + pl.off_levels);
+    a.level_base = (const int*)(table + pl.off_base);
+    a.r = cfg->refine_radius;
+    a.rs = cfg->soft_radius;
+    a.var_eps = cfg->var_eps;
+    a.inv_tau = cfg->soft_radius > 0 ? 1.f / cfg->tau : 0.f;
+    static const char* mode_name[3] = {"full", "refine", "soft"};
+    for (const StageLaunch& l : pl.launches) {
+        a.segs = (const Segment*)table + l.first;
+        a.nseg = l.nseg;
+        char lab[40];
+        if (l.kind == STAGE_REDUCE) snprintf(lab, sizeof(lab), "batch_reduce_l%d", l.level);
+        else if (l.kind == STAGE_STATS) snprintf(lab, sizeof(lab), "batch_stats");
+        else snprintf(lab, sizeof(lab), "batch_match_%s_l%d", mode_name[l.mode], l.level);
+        const int slot = timed ? timing_begin(lab, s) : -1;
+        hipError_t e;
+        if (l.kind == STAGE_REDUCE) e = launch_reduce_multi(a, l.blocks, s);
+        else if (l.kind == STAGE_STATS) e = launch_stats_multi(cfg->half_window, a, l.blocks, s);
+        else e = launch_match_multi(cfg->half_window, l.dtype, l.mode, l.nc, a, l.blocks, s);
+        if (timed) timing_end(slot, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------ per-device state
+// Pinned host staging for table uploads: a ring of slots, each reused only after
+// the copy that last read it has completed (its event).  A private stream per
+// device for graph capture (the caller's stream may be the null stream, which
+// cannot be captured).
+struct StagingSlot {
+    char* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool used = false;
+};
+struct DeviceState {
+    StagingSlot slot[8];
+    int next = 0;
+    hipStream_t capture = nullptr;
+};
+static std::mutex g_dev_mu;
+static std::map<int, DeviceState> g_dev;
+
+static hipError_t upload_table(int dev, char* dst, const std::vector<char>& src, hipStream_t s)
+{
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    DeviceState& st = g_dev[dev];
+    StagingSlot& sl = st.slot[st.next];
+    st.next = (st.next + 1) % 8;
+    hipError_t e = hipSuccess;
+    if (!sl.done) e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming);
+    if (e == hipSuccess && sl.used) e = hipEventSynchronize(sl.done);
+    if (e == hipSuccess && sl.cap < src.size()) {
+        if (sl.host) hipHostFree(sl.host);
+        sl.host = nullptr;
+        sl.cap = 0;
+        e = hipHostMalloc((void**)&sl.host, src.size(), hipHostMallocDefault);
+        if (e == hipSuccess) sl.cap = src.size();
+    }
+    if (e != hipSuccess) return e;
+    std::memcpy(sl.host, src.data(), src.size());
+    e = hipMemcpyAsync(dst, sl.host, src.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(sl.done, s);
+    sl.used = (e == hipSuccess);
+    return e;
+}
+
+static hipError_t capture_stream(int dev, hipStream_t* out)
+{
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    DeviceState& st = g_dev[dev];
+    if (!st.capture) {
+        hipError_t e = hipStreamCreateWithFlags(&st.capture, hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    *out = st.capture;
+    return hipSuccess;
+}
+
+// ------------------------------------------------------------------ graph cache
+// Key: device, pairs (pointers, shapes, D, K), cfg, output pointers, workspace.
+struct GraphKey {
+    std::vector<char> bytes;
+    bool operator<(const GraphKey& o) const { return bytes < o.bytes; }
+};
+struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    char* table = nullptr;  // device copy of the plan's table, owned by the entry
+};
+static std::mutex g_graph_mu;
+static std::map<GraphKey, GraphEntry> g_graphs;
+static const size_t GRAPH_CACHE_MAX = 64;
+
+static GraphKey make_key(int dev, const msibm_pair* pairs, int np, const msibm_config* cfg,
+                         const BatchOutputs& out, void* ws, size_t ws_bytes)
+{
+    GraphKey k;
+    auto put = [&](const void* p, size_t n) {
+        const char* c = (const char*)p;
+        k.bytes.insert(k.bytes.end(), c, c + n);
+    };
+    put(&dev, sizeof(dev));
+    put(pairs, sizeof(msibm_pair) * np);
+    put(cfg, sizeof(msibm_config));
+    for (int p = 0; p < np; ++p) {
+        const void* q[4] = {out.disp[p], out.cost ? out.cost[p] : nullptr, out.soft ? out.soft[p] : nullptr,
+                            out.prior1 ? out.prior1[p] : nullptr};
+        put(q, sizeof(q));
+    }
+    put(&ws, sizeof(ws));
+    put(&ws_bytes, sizeof(ws_bytes));
+    return k;
+}
+
+// Callers make sure no replay of the entry is still in flight.
+static void destroy_entry(GraphEntry& e)
+{
+    if (e.exec) hipGraphExecDestroy(e.exec);
+    if (e.table) hipFree(e.table);
+    e = GraphEntry{};
+}
+
+static int hip_fail(hipError_t e, const char* what, std::string* err)
+{
+    *err = std::string(what) + ": " + hipGetErrorString(e);
+    return MSIBM_ERR_HIP;
+}
+
+// Capture the stage sequence on the private stream, with a device table of its own.
+static int capture_graph(int dev, const BatchPlan& pl, const msibm_config* cfg, GraphEntry* ent,
+                         std::string* err)
+{
+    std::vector<char> host;
+    pack_table(pl, host);
+    hipError_t e = hipMalloc((void**)&ent->table, host.size());
+    if (e != hipSuccess) return hip_fail(e, "graph table", err);
+    e = hipMemcpy(ent->table, host.data(), host.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
-        *err = std::string("table upload: ") + hipGetErrorString(e);
-        return MSIBM_ERR_HIP;
+        destroy_entry(*ent);
+        return hip_fail(e, "graph table upload", err);
     }
-    if (!use_graph) {
-        e = enqueue_batch(pl, bw, cfg, s);
-        if (e != hipSuccess) {
-            *err = std::string("persistent launch: ") + hipGetErrorString(e);
-            return MSIBM_ERR_HIP;
-        }
-        return MSIBM_OK;
+    hipStream_t cs;
+    e = capture_stream(dev, &cs);
+    if (e != hipSuccess) {
+        destroy_entry(*ent);
+        return hip_fail(e, "capture stream", err);
     }
-    // capture [reset + persistent kernel] once, then replay
     hipGraph_t graph = nullptr;
-    e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e2 = enqueue_batch(pl, bw, cfg, s);
-        e = hipStreamEndCapture(s, &graph);
+        const hipError_t e2 = enqueue_stages(pl, ent->table, cfg, false, cs);
+        e = hipStreamEndCapture(cs, &graph);
         if (e2 != hipSuccess) e = e2;
     }
-    GraphEntry ent;
-    if (e == hipSuccess) e = hipGraphInstantiate(&ent.exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphInstantiate(&ent->exec, graph, nullptr, nullptr, 0);
     if (graph) hipGraphDestroy(graph);
-    if (e == hipSuccess) e = hipGraphLaunch(ent.exec, s);
     if (e != hipSuccess) {
-        *err = std::string("graph capture: ") + hipGetErrorString(e);
-        return MSIBM_ERR_HIP;
+        destroy_entry(*ent);
+        return hip_fail(e, "graph capture", err);
     }
-    std::lock_guard<std::mutex> g(g_graph_mu);
-    g_graphs[key] = ent;
+    return MSIBM_OK;
+}
+
+int run_batched(const msibm_pair* pairs, int np, const msibm_config* cfg, const BatchOutputs& out,
+                void* workspace, size_t ws_bytes, hipStream_t s, std::string* err)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "device", err);
+    if (cfg->flags & MSIBM_FLAG_GRAPH) {
+        const GraphKey key = make_key(dev, pairs, np, cfg, out, workspace, ws_bytes);
+        std::lock_guard<std::mutex> g(g_graph_mu);
+        auto it = g_graphs.find(key);
+        if (it == g_graphs.end()) {
+            BatchPlan pl;
+            plan_stages(pairs, np, cfg, pl);
+            plan_levels(pairs, np, out, (char*)workspace, pl);
+            GraphEntry ent;
+            const int rc = capture_graph(dev, pl, cfg, &ent, err);
+            if (rc != MSIBM_OK) return rc;
+            if (g_graphs.size() >= GRAPH_CACHE_MAX) {  // drop everything rather than track use
+                hipDeviceSynchronize();
+                for (auto& kv : g_graphs) destroy_entry(kv.second);
+                g_graphs.clear();
+            }
+            it = g_graphs.emplace(key, ent).first;
+        }
+        const int slot = timing_begin("batch_graph", s);
+        e = hipGraphLaunch(it->second.exec, s);
+        timing_end(slot, s);
+        if (e != hipSuccess) return hip_fail(e, "graph launch", err);
+        return MSIBM_OK;
+    }
+    BatchPlan pl;
+    plan_stages(pairs, np, cfg, pl);
+    plan_levels(pairs, np, out, (char*)workspace, pl);
+    char* table = (char*)workspace + pairs_bytes(pairs, np);
+    std::vector<char> host;
+    pack_table(pl, host);
+    e = upload_table(dev, table, host, s);
+    if (e != hipSuccess) return hip_fail(e, "table upload", err);
+    e = enqueue_stages(pl, table, cfg, true, s);
+    if (e != hipSuccess) return hip_fail(e, "batched launch", err);
     return MSIBM_OK;
 }
 

@@ -78,12 +78,12 @@ struct ConvertArgs {
 };
 
 // ---------------------------------------------------------------- batches
-// Work of a batch of pairs is described by segments: one per (pair, stage,
-// level), each a grid of tiles of that stage's tile function.
+// The batched forward describes its work as segments, one per (pair, stage,
+// level); a launch covers the tiles of several segments of one stage.
 
 enum SegType { SEG_REDUCE = 0, SEG_STATS = 1, SEG_FULL = 2, SEG_REFINE = 3, SEG_SOFT = 4 };
 
-// One level of one pair as the persistent kernel sees it.
+// One level of one pair.
 struct LevelDesc {
     const void* img[2];   // level image of both views (level 0: the caller's input)
     int pitch, H, W;
@@ -95,27 +95,29 @@ struct LevelDesc {
     int dtype;            // element type of img (MSIBM_U8 / MSIBM_F32)
 };
 
+// Tiles [task0, task0 + tiles_x * tiles_y * views) of a launch belong to this
+// segment; tile t is view t / (tiles_x * tiles_y) (reduce and statistics do one
+// view per tile, matching reads both).
 struct Segment {
     int type, pair, level;
-    int tiles_x, tiles_y;
-    int task0;            // first global task number
-    int band0;            // first band counter
-    int dep_seg[2];       // segments whose bands this one reads (-1 = none)
+    int tiles_x, tiles_y, views;
+    int task0;
 };
 
-// Arguments of a launch that covers the tiles of several segments: block b of
-// the launch runs tile (b - task0) of the last segment whose task0 <= b.
+// Arguments of a launch over several segments: block b runs tile b - task0 of
+// the last segment whose task0 <= b.
 struct MultiArgs {
     const Segment* segs;      // this launch's segments, task0 ascending from 0
     int nseg;
-    const LevelDesc* levels;  // K entries per pair, from level_base[pair]
+    const LevelDesc* levels;  // a pair's levels start at levels[level_base[pair]]
     const int* level_base;
-    int n, r, rs;
+    int r, rs;                // refine and soft radius
     double var_eps;
     float inv_tau;
 };
 
-// Segment of launch block b (binary search; every thread computes it).
+// Segment of launch block b: binary search over the launch's segment table
+// (block-uniform, so it runs on the scalar unit).
 __device__ __forceinline__ int segment_of(const Segment* segs, int nseg, int b)
 {
     int lo = 0, hi = nseg - 1;
@@ -141,8 +143,8 @@ hipError_t launch_match(int n, int dtype, int mode, int nc, const MatchArgs& a, 
 
 // Multi-segment launches (batched path); `blocks` = total tiles of the segments.
 hipError_t launch_match_multi(int n, int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);
-hipError_t launch_reduce_multi(int dtype, const MultiArgs& a, int blocks, hipStream_t s);
-hipError_t launch_stats_multi(const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_reduce_multi(const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_stats_multi(int n, const MultiArgs& a, int blocks, hipStream_t s);
 hipError_t launch_match_multi_n1(int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);
 hipError_t launch_match_multi_n2(int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);
 hipError_t launch_match_multi_n3(int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);

@@ -46,6 +46,48 @@ __global__ __launch_bounds__(256) void stats_kernel(StatsArgs a)
                               sm);
 }
 
+// Pyramid reduce of several (pair, level) segments in one launch; a tile reads
+// level k-1 of its pair (the caller's input at k = 1) and writes level k.
+__global__ __launch_bounds__(256) void reduce_multi_kernel(MultiArgs a)
+{
+    __shared__ ReduceSmem sm;
+    const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
+    const LevelDesc* lv = a.levels + a.level_base[s.pair];
+    const LevelDesc& P = lv[s.level - 1];
+    const LevelDesc& L = lv[s.level];
+    const int per = s.tiles_x * s.tiles_y, t = blockIdx.x - s.task0;
+    const int v = t / per, tx = (t % per) % s.tiles_x, ty = (t % per) / s.tiles_x;
+    ReduceArgs ra{};  // the tile's view only, so no dynamic indexing
+    ra.src[0] = v ? P.img[1] : P.img[0];
+    ra.dst[0] = (float*)(v ? L.img[1] : L.img[0]);
+    ra.views = 1;
+    ra.H = P.H;
+    ra.W = P.W;
+    ra.spitch = P.pitch;
+    ra.Ho = L.H;
+    ra.Wo = L.W;
+    ra.dpitch = L.pitch;
+    if (P.dtype == 0) reduce_tile<uint8_t>(ra, 0, tx, ty, sm);
+    else reduce_tile<float>(ra, 0, tx, ty, sm);
+}
+
+// Window statistics of several (pair, level) segments in one launch.
+template <int NW>
+__global__ __launch_bounds__(256) void stats_multi_kernel(MultiArgs a)
+{
+    __shared__ StatsSmem sm;
+    const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
+    const LevelDesc& L = a.levels[a.level_base[s.pair] + s.level];
+    const int per = s.tiles_x * s.tiles_y, t = blockIdx.x - s.task0;
+    const int v = t / per, x0 = ((t % per) % s.tiles_x) * ST_W, y0 = ((t % per) / s.tiles_x) * ST_H;
+    if (L.dtype == 0)
+        stats_tile<uint8_t, NW>((const uint8_t*)L.img[v], L.H, L.W, L.pitch, L.stat[v], L.W, a.var_eps, x0, y0,
+                                sm);
+    else
+        stats_tile<float, NW>((const float*)L.img[v], L.H, L.W, L.pitch, L.stat[v], L.W, a.var_eps, x0, y0,
+                              sm);
+}
+
 __global__ __launch_bounds__(256) void zero_kernel(float* a, float* b, size_t count)
 {
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) {
@@ -99,6 +141,28 @@ hipError_t launch_stats(StatsArgs a, hipStream_t s)
         case 4: hipLaunchKernelGGL(stats_kernel<4>, dim3(tiles), dim3(256), 0, s, a); break;
         case 5: hipLaunchKernelGGL(stats_kernel<5>, dim3(tiles), dim3(256), 0, s, a); break;
         case 6: hipLaunchKernelGGL(stats_kernel<6>, dim3(tiles), dim3(256), 0, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_multi(const MultiArgs& a, int blocks, hipStream_t s)
+{
+    if (blocks < 1 || a.nseg < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reduce_multi_kernel, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats_multi(int n, const MultiArgs& a, int blocks, hipStream_t s)
+{
+    if (blocks < 1 || a.nseg < 1) return hipErrorInvalidValue;
+    switch (n) {
+        case 1: hipLaunchKernelGGL(stats_multi_kernel<1>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(stats_multi_kernel<2>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 3: hipLaunchKernelGGL(stats_multi_kernel<3>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL(stats_multi_kernel<4>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 5: hipLaunchKernelGGL(stats_multi_kernel<5>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 6: hipLaunchKernelGGL(stats_multi_kernel<6>, dim3(blocks), dim3(256), 0, s, a); break;
+        default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

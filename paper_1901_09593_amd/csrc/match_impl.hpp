@@ -39,6 +39,8 @@
 // clamped to [-1, 1].
 #pragma once
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace msibm {
@@ -535,6 +537,85 @@ static hipError_t dispatch_match(int dtype, int mode, int nc, const MatchArgs& a
     if (dtype == 0 && mode == MODE_SOFT) return hipErrorInvalidValue;  // soft mode takes float images
     if (dtype == 0) return dispatch_nc<uint8_t, NW, 1>(mode, nc, a, s);
     return dispatch_nc<float, NW, 1>(mode, nc, a, s);
+}
+
+// Matching of several (pair, level) segments of one mode and element type in
+// one launch: the level's arguments come from its pair's level descriptors.
+template <typename T, int NW, int NC, int MODE, int SL>
+__global__ __launch_bounds__(MATCH_THREADS) void match_multi_kernel(MultiArgs a)
+{
+    __shared__ MatchSmem<NW, ChunkOf<MODE>::value, 1> sm;
+    const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
+    const LevelDesc* lv = a.levels + a.level_base[s.pair];
+    const LevelDesc& L = lv[s.level];
+    MatchArgs m{};
+    m.L = L.img[0];
+    m.R = L.img[1];
+    m.H = L.H;
+    m.W = L.W;
+    m.pitch = L.pitch;
+    m.statL = L.stat[0];
+    m.statR = L.stat[1];
+    m.spitch = L.W;
+    m.Dk = L.Dk;
+    if (MODE != MODE_FULL) {
+        const LevelDesc& C = lv[s.level + 1];
+        m.prior = C.map;
+        m.Hc = C.H;
+        m.Wc = C.W;
+        m.ppitch = C.W;
+    }
+    m.r = (MODE == MODE_SOFT) ? a.rs : a.r;
+    m.d_out = L.map;
+    m.c_out = L.cost;
+    m.soft_out = L.soft;
+    m.opitch = L.W;
+    m.inv_tau = a.inv_tau;
+    const int t = blockIdx.x - s.task0;
+    match_tile<T, NW, NC, MODE, 1, SL>(m, t % s.tiles_x, t / s.tiles_x, sm);
+}
+
+// Statistics placement per mode: staged in LDS for the full search (every
+// staged column serves all candidates), read from memory for restricted ones.
+template <typename T, int NW, int NC, int MODE>
+static hipError_t launch_multi_one(const MultiArgs& a, int blocks, hipStream_t s)
+{
+    constexpr int SL = (MODE == MODE_FULL) ? 1 : 0;
+    hipLaunchKernelGGL((match_multi_kernel<T, NW, NC, MODE, SL>), dim3(blocks), dim3(MATCH_THREADS), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int NW>
+static hipError_t dispatch_multi_nc(int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s)
+{
+    if (mode == MODE_FULL) return launch_multi_one<T, NW, FULL_NC, MODE_FULL>(a, blocks, s);
+    if (mode == MODE_REFINE) {
+        switch (nc) {
+            case 2: return launch_multi_one<T, NW, 2, MODE_REFINE>(a, blocks, s);
+            case 3: return launch_multi_one<T, NW, 3, MODE_REFINE>(a, blocks, s);
+            case 5: return launch_multi_one<T, NW, 5, MODE_REFINE>(a, blocks, s);
+            case 7: return launch_multi_one<T, NW, 7, MODE_REFINE>(a, blocks, s);
+            case 9: return launch_multi_one<T, NW, 9, MODE_REFINE>(a, blocks, s);
+        }
+        return hipErrorInvalidValue;
+    }
+    if constexpr (std::is_same<T, float>::value) {
+        switch (nc) {
+            case 3: return launch_multi_one<T, NW, 3, MODE_SOFT>(a, blocks, s);
+            case 5: return launch_multi_one<T, NW, 5, MODE_SOFT>(a, blocks, s);
+            case 7: return launch_multi_one<T, NW, 7, MODE_SOFT>(a, blocks, s);
+            case 9: return launch_multi_one<T, NW, 9, MODE_SOFT>(a, blocks, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int NW>
+static hipError_t dispatch_match_multi(int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s)
+{
+    if (blocks < 1 || a.nseg < 1) return hipErrorInvalidValue;
+    if (dtype == 0) return dispatch_multi_nc<uint8_t, NW>(mode, nc, a, blocks, s);
+    return dispatch_multi_nc<float, NW>(mode, nc, a, blocks, s);
 }
 
 }  // namespace msibm

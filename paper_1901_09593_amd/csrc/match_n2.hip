@@ -6,4 +6,8 @@ hipError_t launch_match_n2(int dtype, int mode, int nc, const MatchArgs& a, hipS
 {
     return dispatch_match<2>(dtype, mode, nc, a, s);
 }
+hipError_t launch_match_multi_n2(int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s)
+{
+    return dispatch_match_multi<2>(dtype, mode, nc, a, blocks, s);
+}
 }  // namespace msibm

@@ -24,6 +24,19 @@ hipError_t launch_match(int n, int dtype, int mode, int nc, const MatchArgs& a, 
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_match_multi(int n, int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s)
+{
+    switch (n) {
+        case 1: return launch_match_multi_n1(dtype, mode, nc, a, blocks, s);
+        case 2: return launch_match_multi_n2(dtype, mode, nc, a, blocks, s);
+        case 3: return launch_match_multi_n3(dtype, mode, nc, a, blocks, s);
+        case 4: return launch_match_multi_n4(dtype, mode, nc, a, blocks, s);
+        case 5: return launch_match_multi_n5(dtype, mode, nc, a, blocks, s);
+        case 6: return launch_match_multi_n6(dtype, mode, nc, a, blocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 // Kernel shape of the matching kernel for one level (VARIANT_* bits).
 // MSIBM_FORCE_VARIANT overrides the choice (tests and tuning).
 static int g_forced_variant = [] {

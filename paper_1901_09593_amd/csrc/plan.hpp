@@ -48,8 +48,6 @@ int run_pair_backward(const msibm_pair& P, const PairLayout& lay, const msibm_co
 
 size_t batch_extra_bytes(const msibm_pair* pairs, int n_pairs, const msibm_config* cfg);
 
-size_t batch_error_offset(const msibm_pair* pairs, int n_pairs, const msibm_config* cfg);
-
 int run_batched(const msibm_pair* pairs, int n_pairs, const msibm_config* cfg, const BatchOutputs& out,
                 void* workspace, size_t ws_bytes, hipStream_t s, std::string* err);
 

@@ -23,6 +23,7 @@ MSIBM_U8 = 0
 MSIBM_F32 = 1
 FLAG_BATCHED = 1
 FLAG_GRAPH = 2
+FLAG_PERSISTENT = 4  # switched off: calls with it fail with MsibmError
 MAX_LEVELS = 8
 
 
@@ -79,9 +80,6 @@ def lib() -> ctypes.CDLL:
         L.msibm_backward.argtypes = [ctypes.POINTER(Pair), _I32, ctypes.POINTER(Config), _PP, _PP,
                                      _PP, _PP, _VP, ctypes.c_size_t, _VP]
         L.msibm_backward.restype = _I32
-        L.msibm_batch_status.argtypes = [ctypes.POINTER(Pair), _I32, ctypes.POINTER(Config), _VP,
-                                         ctypes.c_size_t]
-        L.msibm_batch_status.restype = _I32
         L.msibm_force_variant.argtypes = [_I32]
         L.msibm_force_variant.restype = _I32
         L.msibm_timing_enable.argtypes = [_I32]
@@ -289,16 +287,6 @@ def disparity_many(lefts: Sequence[torch.Tensor], rights: Sequence[torch.Tensor]
                                  _ptr(workspace), workspace.numel(), _stream(dev)))
     del keep
     return outputs
-
-
-def batch_status(lefts, rights, Ds, Ks, n, r, var_eps, workspace, soft_radius=0, tau=0.05,
-                 flags=FLAG_BATCHED):
-    """Raise MsibmError if the last batched call on `workspace` timed out."""
-    pairs, keep = _pairs(lefts, rights, Ds, Ks)
-    cfg = make_config(n, r, var_eps, soft_radius, tau, flags)
-    _check(lib().msibm_batch_status(pairs, len(lefts), ctypes.byref(cfg), _ptr(workspace),
-                                    workspace.numel()))
-    del keep
 
 
 def backward(L: torch.Tensor, R: torch.Tensor, prior1: torch.Tensor, grad_soft: torch.Tensor,

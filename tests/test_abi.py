@@ -86,6 +86,15 @@ def test_config_and_pair_validation(lib):
     assert rc == -1
     rc = e.msibm_disparity(arr, 1, ctypes.byref(good), disp, None, None, None, None, 0, None)
     assert rc == -3
+    # the persistent scheduler is switched off; a graph needs the batched path
+    pers = msibm.make_config(3, 2, 0.065, flags=msibm.FLAG_PERSISTENT)
+    rc = e.msibm_disparity(arr, 1, ctypes.byref(pers), disp, None, None, None, None, 0, None)
+    assert rc == -4 and b"persistent" in e.msibm_last_error()
+    graph_only = msibm.make_config(3, 2, 0.065, flags=msibm.FLAG_GRAPH)
+    assert e.msibm_workspace_size(arr, 1, ctypes.byref(graph_only)) == 0
+    batched = msibm.make_config(3, 2, 0.065, flags=msibm.FLAG_BATCHED)
+    assert e.msibm_workspace_size(arr, 1, ctypes.byref(batched)) > \
+        e.msibm_workspace_size(arr, 1, ctypes.byref(good))
     # automatic level count: smallest K with ceil(D / 2^(K-1)) <= 32
     assert msibm.auto_levels(32) == 1 and msibm.auto_levels(33) == 2 and msibm.auto_levels(400) == 5
 

@@ -1,5 +1,5 @@
-"""Batched persistent launch (and its hipGraph replay) against the plain
-per-pair path: identical outputs, bit for bit."""
+"""Batched forward (one launch per stage for all pairs) and its hipGraph replay
+against the plain per-pair path: identical outputs, bit for bit."""
 import numpy as np
 import pytest
 
@@ -8,6 +8,9 @@ from paper_1901_09593_amd import synth
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
+
+PERSISTENT_OFF = ("persistent scheduler disabled: two runs hung on MI355X "
+                  "(at the synchronize after the launch) and the cause is not found")
 
 
 @pytest.fixture(scope="module")
@@ -23,76 +26,117 @@ def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-def _batch(dtype="u8", count=5, seed=7):
+def _batch(dtypes, count=5, seed=7, dmin=24):
+    """Pairs of assorted sizes and disparity ranges (so level counts differ)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     pairs = []
     for i in range(count):
+        dtype = dtypes[i % len(dtypes)]
         H = int(rng.integers(40, 260))
         W = int(rng.integers(60, 400))
-        D = int(rng.integers(24, 160))
+        D = int(rng.integers(dmin, 160))
         scale = 1.0 if dtype == "u8" else 1.0 / 255
         p = synth.make_pair(100 + i, H, W, 4, 0.05 * D, 0.9 * D, True, 1.0, 0.0, 2.0 * scale, dtype)
         pairs.append((p, D))
     return pairs
 
 
-PERSISTENT_OFF = ("persistent scheduler disabled: two runs hung on MI355X "
-                  "(at the synchronize after the launch) and the cause is not found")
+def _inputs(pairs):
+    L = [dev(p.left) for p, _ in pairs]
+    R = [dev(p.right) for p, _ in pairs]
+    return L, R, [D for _, D in pairs], [0] * len(pairs)
+
+
+def _equal(ref, got, tag=""):
+    for i, (a, b) in enumerate(zip(ref, got)):
+        assert set(a) == set(b)
+        for k in a:
+            assert torch.equal(a[k], b[k]), (tag, i, k)
+
+
+@pytest.mark.parametrize("dtypes,n,r,rs", [(("u8",), 4, 2, 0), (("u8",), 3, 3, 0), (("f32",), 5, 2, 0),
+                                           (("f32",), 3, 2, 3), (("u8", "f32"), 2, 1, 0),
+                                           (("f32",), 6, 4, 4), (("u8",), 1, 0, 0)])
+def test_batched_equals_plain(M, dtypes, n, r, rs):
+    pairs = _batch(dtypes, seed=n * 10 + r, dmin=33 if rs else 24)  # soft needs K >= 2
+    eps = 0.065 if dtypes == ("u8",) else 1e-6
+    L, R, Ds, Ks = _inputs(pairs)
+    print("batched call", dtypes, n, r, rs, flush=True)
+    plain = M.disparity_many(L, R, Ds, Ks, n, r, eps, soft_radius=rs, with_prior1=True)
+    batched = M.disparity_many(L, R, Ds, Ks, n, r, eps, soft_radius=rs, with_prior1=True,
+                               flags=M.FLAG_BATCHED)
+    torch.cuda.synchronize()
+    _equal(plain, batched)
+
+
+def test_batched_explicit_levels_and_single_pair(M):
+    pairs = _batch(("u8",), count=3, seed=11)
+    L, R, Ds, _ = _inputs(pairs)
+    Ks = [1, 3, 2]
+    plain = M.disparity_many(L, R, Ds, Ks, 3, 2, 0.065, with_prior1=True)
+    batched = M.disparity_many(L, R, Ds, Ks, 3, 2, 0.065, with_prior1=True, flags=M.FLAG_BATCHED)
+    one = M.disparity_many(L[1:2], R[1:2], Ds[1:2], Ks[1:2], 3, 2, 0.065, with_prior1=True,
+                           flags=M.FLAG_BATCHED)
+    torch.cuda.synchronize()
+    _equal(plain, batched)
+    _equal(plain[1:2], one)
+
+
+def test_graph_replay_equals_direct_and_repeats(M):
+    pairs = _batch(("u8",), count=6, seed=3)
+    L, R, Ds, Ks = _inputs(pairs)
+    n, r, eps = 4, 2, 0.065
+    ref = M.disparity_many(L, R, Ds, Ks, n, r, eps)
+    flags = M.FLAG_BATCHED | M.FLAG_GRAPH
+    outs = M.disparity_many(L, R, Ds, Ks, n, r, eps, flags=flags)
+    ws = torch.empty(M.workspace_bytes(M._pairs(L, R, Ds, Ks)[0], len(L), M.make_config(n, r, eps, flags=flags)),
+                     dtype=torch.uint8, device="cuda")
+    for rep in range(4):
+        # the same buffers every time: the first call captures, later calls replay;
+        # eager work and a synchronisation between replays
+        for o in outs:
+            for t in o.values():
+                t.fill_(-7 if t.dtype == torch.int16 else 7.0)
+        ws.fill_(rep)
+        M.disparity_many(L, R, Ds, Ks, n, r, eps, flags=flags, workspace=ws, outputs=outs)
+        torch.cuda.synchronize()
+        _equal(ref, outs, rep)
+
+
+def test_graph_cache_keys_on_outputs(M):
+    pairs = _batch(("f32",), count=3, seed=5, dmin=33)
+    L, R, Ds, Ks = _inputs(pairs)
+    flags = M.FLAG_BATCHED | M.FLAG_GRAPH
+    ref = M.disparity_many(L, R, Ds, Ks, 3, 2, 1e-6, soft_radius=3, with_prior1=True)
+    a = M.disparity_many(L, R, Ds, Ks, 3, 2, 1e-6, soft_radius=3, with_prior1=True, flags=flags)
+    b = M.disparity_many(L, R, Ds, Ks, 3, 2, 1e-6, soft_radius=3, with_prior1=True, flags=flags)
+    torch.cuda.synchronize()
+    _equal(ref, a, "a")
+    _equal(ref, b, "b")
 
 
 @pytest.mark.skip(reason=PERSISTENT_OFF)
 @pytest.mark.parametrize("dtype,n,r,rs", [("u8", 4, 2, 0), ("u8", 3, 3, 0), ("f32", 5, 2, 0),
                                           ("f32", 3, 2, 3)])
-def test_batched_equals_plain(M, dtype, n, r, rs):
-    pairs = _batch(dtype, seed=n * 10 + r)
+def test_persistent_equals_plain(M, dtype, n, r, rs):
+    pairs = _batch((dtype,), seed=n * 10 + r)
     eps = 0.065 if dtype == "u8" else 1e-6
-    L = [dev(p.left) for p, _ in pairs]
-    R = [dev(p.right) for p, _ in pairs]
-    Ds = [D for _, D in pairs]
-    Ks = [0] * len(pairs)  # automatic level count
+    L, R, Ds, Ks = _inputs(pairs)
     plain = M.disparity_many(L, R, Ds, Ks, n, r, eps, soft_radius=rs, with_prior1=True)
-    ws = torch.empty(M.workspace_bytes(M._pairs(L, R, Ds, Ks)[0], len(L),
-                                       M.make_config(n, r, eps, rs, flags=M.FLAG_BATCHED)),
-                     dtype=torch.uint8, device="cuda")
-    print("batched call", dtype, n, r, rs, flush=True)
-    batched = M.disparity_many(L, R, Ds, Ks, n, r, eps, soft_radius=rs, with_prior1=True,
-                               flags=M.FLAG_BATCHED, workspace=ws)
+    pers = M.disparity_many(L, R, Ds, Ks, n, r, eps, soft_radius=rs, with_prior1=True,
+                            flags=M.FLAG_PERSISTENT)
     torch.cuda.synchronize()
-    M.batch_status(L, R, Ds, Ks, n, r, eps, ws, soft_radius=rs)
-    for a, b in zip(plain, batched):
-        for k in a:
-            assert torch.equal(a[k], b[k]), k
+    _equal(plain, pers)
 
 
 @pytest.mark.skip(reason=PERSISTENT_OFF)
-def test_graph_replay_equals_direct_and_repeats(M):
-    pairs = _batch("u8", count=6, seed=3)
-    L = [dev(p.left) for p, _ in pairs]
-    R = [dev(p.right) for p, _ in pairs]
-    Ds = [D for _, D in pairs]
-    Ks = [0] * len(pairs)
-    n, r, eps = 4, 2, 0.065
-    ref = M.disparity_many(L, R, Ds, Ks, n, r, eps)
-    outs = M.disparity_many(L, R, Ds, Ks, n, r, eps, flags=M.FLAG_BATCHED | M.FLAG_GRAPH)
-    ws = torch.empty(M.workspace_bytes(M._pairs(L, R, Ds, Ks)[0], len(L),
-                                       M.make_config(n, r, eps, flags=M.FLAG_BATCHED | M.FLAG_GRAPH)),
-                     dtype=torch.uint8, device="cuda")
+def test_persistent_graph_replay_repeats(M):
+    pairs = _batch(("u8",), count=6, seed=3)
+    L, R, Ds, Ks = _inputs(pairs)
+    ref = M.disparity_many(L, R, Ds, Ks, 4, 2, 0.065)
+    flags = M.FLAG_PERSISTENT | M.FLAG_GRAPH
+    outs = M.disparity_many(L, R, Ds, Ks, 4, 2, 0.065, flags=flags)
     for rep in range(4):
-        # the same buffers every time: the first call captures, later calls replay
-        for o in outs:
-            for t in o.values():
-                t.fill_(-7 if t.dtype == torch.int16 else 7.0)
-        M.disparity_many(L, R, Ds, Ks, n, r, eps, flags=M.FLAG_BATCHED | M.FLAG_GRAPH,
-                         workspace=ws, outputs=outs)
+        M.disparity_many(L, R, Ds, Ks, 4, 2, 0.065, flags=flags, outputs=outs)
         torch.cuda.synchronize()
-        for a, b in zip(ref, outs):
-            for k in a:
-                assert torch.equal(a[k], b[k]), (rep, k)
-
-
-def test_batched_rejects_unsupported(M):
-    pairs = _batch("u8", count=2)
-    L = [dev(p.left) for p, _ in pairs]
-    R = [dev(p.right) for p, _ in pairs]
-    with pytest.raises(M.MsibmError):
-        M.disparity_many(L, R, [32, 32], [0, 0], 2, 2, 0.065, flags=M.FLAG_BATCHED)
+        _equal(ref, outs, rep)
