@@ -9,13 +9,25 @@ device memory before the timed region starts.
 
 Prints ONE JSON line.  `value` = pixel-disparity ZNCC evaluations per second
 (valid candidates actually scored, summed over levels) of the plain per-pair
-path.  Extra fields: the flat full-search comparison, per-kernel HIP-event
-timings, the dominant kernel's roofline, and the FP64 oracle timed on the host
-cores (a reported baseline, not a target).
+path.  Extra fields:
+  flat_full_search  the same pair by flat full-range block matching;
+  kernels           per-launch HIP-event timings of the timed step;
+  roofline          the dominant kernel (level-0 restricted search) against the
+                    FP32 vector peak, with HBM traffic from hardware counters;
+  batched           32 pairs of uneven sizes: 32 plain per-pair calls vs the
+                    stage-batched call vs its graph replay;
+  fwd_bwd           forward + masked-L1 loss gradient + backward of 8 x 960x540
+                    and 4 x 2880x1988 float pairs, plain vs batched graph;
+  cpu_baseline      the FP64 oracle timed on the host cores (a reported
+                    baseline, not a target).
+`python bench.py --copy-probe BYTES` only runs a plain device copy (used to
+scale hardware traffic counters) and prints nothing.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -30,41 +42,214 @@ PEAK_FP32_UNPACKED = CU * SIMD_PER_CU * LANES * 2 * CLOCK_HZ / 1e12   # 78.6 TFL
 PEAK_FP32_PUBLISHED = 157.3                                           # packed dual-issue figure
 PEAK_HBM = 8000.0                                                     # GB/s
 
-
-def flops_per_eval(n: int) -> float:
-    """FP32 operations per candidate evaluation of the matching kernel.
-
-    A thread scores one window of candidate slots for a 2x2 pixel block: per slot
-    (2n+2)^2 fused multiply-adds (2 flops each) build the block's four window
-    cross sums, plus 6 adds to combine the shared and edge parts; per evaluation
-    one subtract, one FMA and two multiplies normalise the score."""
-    return (2.0 * (2 * n + 2) ** 2 + 6.0) / 4.0 + 5.0
+METRIC = "pixel-disparity ZNCC evals/s + ms/pair, batched vs plain; fwd+bwd ms"
+DOMINANT = "match_refine_l0"
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "match_refine_l0_mid1436_traffic.md")
+# sources of the dominant kernel: a recorded traffic figure holds only while
+# these files are unchanged
+KERNEL_SOURCES = ["paper_1901_09593_amd/csrc/match_impl.hpp", "paper_1901_09593_amd/csrc/common.hpp",
+                  "paper_1901_09593_amd/csrc/match_n4.hip"]
 
 
 def direct_flops_per_eval(n: int) -> float:
-    """Direct-definition count with precomputed window statistics: N FMAs for
-    the cross sum plus normalisation (context only)."""
+    """Algorithmic FP32 operations per evaluation of a restricted search with
+    precomputed window statistics: N = (2n+1)^2 multiply-adds for the cross sum
+    (2 flops each) plus 8 to normalise and compare."""
     return 2.0 * (2 * n + 1) ** 2 + 8.0
 
 
-def level_eval_counts(maps, H, W, D, K, r):
-    """Valid candidates per level given every level's winner-take-all map."""
+def kernel_flops_per_eval(n: int) -> float:
+    """FP32 operations the matching kernel issues per evaluation: a thread scores
+    a 2x2 pixel block, sharing (2n+2)^2 multiply-adds per candidate slot over the
+    block's four windows, plus 6 adds to split them and 5 flops per evaluation to
+    normalise and compare."""
+    return (2.0 * (2 * n + 2) ** 2 + 6.0) / 4.0 + 5.0
+
+
+def kernel_sha() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary, or None when it is missing or the kernel changed since."""
+    try:
+        text = open(TRAFFIC_FILE).read()
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    h = re.search(r"kernel_sources_sha256:\s*([0-9a-f]{64})", text)
+    if not m or not h or h.group(1) != kernel_sha():
+        return None
+    return float(m.group(1))
+
+
+# --------------------------------------------------------------------------- counting
+
+def level_counts(torch, maps, D, K, r):
+    """Valid candidates scored per level, from every level's winner-take-all map
+    (the restricted interval of each pixel follows from the coarser map)."""
     counts = []
     for k in range(K):
         h, w = maps[k].shape
+        dev = maps[k].device
         Dk = -(-D // (1 << k))
-        jj = np.arange(w)[None, :]
-        top = np.minimum(Dk - 1, jj)
+        j = torch.arange(w, device=dev, dtype=torch.int64)
+        top = torch.clamp(j, max=Dk - 1)
         if k == K - 1:
-            counts.append(int(((top + 1) * np.ones((h, 1), dtype=np.int64)).sum()))
+            counts.append(int((top + 1).sum()) * h)
             continue
-        ii = np.arange(h)[:, None]
-        dh = 2 * maps[k + 1].astype(np.int64)[ii // 2, jj // 2]
-        c = np.minimum(dh, jj)
-        lo = np.maximum(0, c - r)
-        hi = np.minimum(top, c + r)
+        i = torch.arange(h, device=dev, dtype=torch.int64)
+        dh = 2 * maps[k + 1].long()[i // 2][:, j // 2]
+        c = torch.minimum(dh, j[None, :])
+        lo = torch.clamp(c - r, min=0)
+        hi = torch.minimum(top[None, :], c + r)
         counts.append(int((hi - lo + 1).sum()))
     return counts
+
+
+def hier_counts(torch, M, L, R, D, K, n, r, eps):
+    PL, PR = M.pyramid(L, K), M.pyramid(R, K)
+    maps = [None] * K
+    for k in range(K - 1, -1, -1):
+        maps[k], _ = M.match_level(L if k == 0 else PL[k], R if k == 0 else PR[k], n, -(-D // (1 << k)),
+                                   None if k == K - 1 else maps[k + 1], r, eps, with_cost=False)
+    return level_counts(torch, maps, D, K, r)
+
+
+def time_ms(torch, fn, steps, warmup):
+    """Mean milliseconds per call between HIP events on the current stream."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+# --------------------------------------------------------------------------- sections
+
+def section_batched(torch, M, synth, steps):
+    """32 uneven uint8 pairs: plain per-pair calls vs one stage-batched call."""
+    dev = torch.device("cuda:0")
+    work = synth.batch_workload(32, 1000, workers=8)
+    L = [torch.from_numpy(p.left).to(dev) for p, _ in work]
+    R = [torch.from_numpy(p.right).to(dev) for p, _ in work]
+    D = [c.max_disp for _, c in work]
+    K = [c.levels for _, c in work]
+    n, r, eps = work[0][1].half_window, work[0][1].refine_radius, work[0][1].var_eps
+    evals = sum(sum(hier_counts(torch, M, L[i], R[i], D[i], K[i], n, r, eps)) for i in range(len(L)))
+    level0_px = sum(p.left.size for p, _ in work)
+    res = {"workload": "32 uint8 pairs, W ~ U{640..2880}, H ~ U{480..1988}, D ~ U{64..400} (shape seed "
+                       "1000, pair i seed i), 8 slanted planes, noise 2; 9x9 ZNCC, refine +-2, K per pair "
+                       "(smallest with D_(K-1) <= 32)",
+           "pairs": len(L), "level0_pixels": level0_px, "evals_per_batch": evals,
+           "levels": sorted(set(K))}
+    pairs_arr = M._pairs(L, R, D, K)[0]
+    for name, flags in (("plain", 0), ("batched", M.FLAG_BATCHED),
+                        ("graph", M.FLAG_BATCHED | M.FLAG_GRAPH)):
+        ws = torch.empty(M.workspace_bytes(pairs_arr, len(L), M.make_config(n, r, eps, flags=flags)),
+                         dtype=torch.uint8, device=dev)
+        outs = M.disparity_many(L, R, D, K, n, r, eps, flags=flags, workspace=ws)
+
+        def step():
+            M.disparity_many(L, R, D, K, n, r, eps, flags=flags, workspace=ws, outputs=outs)
+        ms = time_ms(torch, step, steps, 3)
+        res[name] = {"ms_per_batch": ms, "ms_per_pair": ms / len(L), "evals_per_s": evals / (ms * 1e-3)}
+        if name == "plain":
+            ref = outs
+        else:
+            res[name]["identical_to_plain"] = all(torch.equal(a[k], b[k]) for a, b in zip(ref, outs) for k in a)
+        del ws
+    res["graph_speedup_vs_plain"] = res["plain"]["ms_per_batch"] / res["graph"]["ms_per_batch"]
+    res["batched_speedup_vs_plain"] = res["plain"]["ms_per_batch"] / res["batched"]["ms_per_batch"]
+    return res
+
+
+def section_fwd_bwd(torch, M, synth, name, count, steps):
+    """Forward + masked mean-L1 loss gradient + backward for `count` float pairs."""
+    dev = torch.device("cuda:0")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    torch.cuda.reset_peak_memory_stats(dev)
+    base = torch.cuda.memory_allocated(dev)
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(min(count, 8)) as ex:
+        work = list(ex.map(lambda i: synth.workload(name, i), range(count)))
+    cfg = work[0][1]
+    H, W, D, K, n, r, eps, rs, tau = cfg.height, cfg.width, cfg.max_disp, cfg.levels, cfg.half_window, \
+        cfg.refine_radius, cfg.var_eps, cfg.soft_radius, cfg.tau
+    L = [torch.from_numpy(p.left).to(dev) for p, _ in work]
+    R = [torch.from_numpy(p.right).to(dev) for p, _ in work]
+    gt = [torch.from_numpy(p.disp.astype(np.float32)).to(dev) for p, _ in work]
+    # loss pixels: non-occluded, window inside the image, every candidate's right
+    # window inside too (left column >= n + D-1 is a sufficient, fixed test)
+    mask = []
+    for p, _ in work:
+        m = p.nonocc.copy()
+        m[:n, :] = m[H - n:, :] = False
+        m[:, :n + D - 1] = m[:, W - n:] = False
+        mask.append(torch.from_numpy(m).to(dev))
+    cnt = [mm.sum().clamp(min=1).float() for mm in mask]
+    Ds, Ks = [D] * count, [K] * count
+    pairs_arr = M._pairs(L, R, Ds, Ks)[0]
+    res = {"workload": f"{count} x {W}x{H} float pairs ({name}), K={K}, {2 * n + 1}x{2 * n + 1} ZNCC, "
+                       f"D={D}, refine +-{r}, soft-argmax +-{rs} at level 0 (tau {tau}), masked mean L1 "
+                       "to the generator's disparity",
+           "pairs": count}
+    evals = None
+    for label, flags in (("plain", 0), ("batched_graph", M.FLAG_BATCHED | M.FLAG_GRAPH)):
+        ws = torch.empty(M.workspace_bytes(pairs_arr, count, M.make_config(n, r, eps, rs, tau, flags)),
+                         dtype=torch.uint8, device=dev)
+        outs = M.disparity_many(L, R, Ds, Ks, n, r, eps, soft_radius=rs, tau=tau, flags=flags, workspace=ws)
+        g = [torch.zeros((H, W), dtype=torch.float32, device=dev) for _ in range(count)]
+        grads = M.backward_many(L, R, [o["prior1"] for o in outs], g, Ds, Ks, n, r, eps, rs, tau, flags=flags,
+                                workspace=ws)
+
+        def fwd():
+            M.disparity_many(L, R, Ds, Ks, n, r, eps, soft_radius=rs, tau=tau, flags=flags, workspace=ws,
+                             outputs=outs)
+
+        def loss_grad():
+            for i in range(count):
+                torch.mul(torch.sign(outs[i]["soft"] - gt[i]) * mask[i], 1.0 / cnt[i], out=g[i])
+
+        def bwd():
+            M.backward_many(L, R, [o["prior1"] for o in outs], g, Ds, Ks, n, r, eps, rs, tau, flags=flags,
+                            workspace=ws, outputs=grads)
+
+        def step():
+            fwd()
+            loss_grad()
+            bwd()
+        if evals is None:
+            fwd()
+            evals = 0
+            for i in range(count):
+                c = hier_counts(torch, M, L[i], R[i], D, K, n, r, eps)
+                # the soft level scores its own +-rs interval
+                c[0] = level_counts(torch, [outs[i]["disp"], outs[i]["prior1"]], D, 2, rs)[0]
+                evals += sum(c)
+        ms_fwd = time_ms(torch, fwd, steps, 2)
+        step()
+        torch.cuda.synchronize()
+        ms_bwd = time_ms(torch, bwd, steps, 2)
+        ms_step = time_ms(torch, step, steps, 2)
+        res[label] = {"fwd_ms": ms_fwd, "bwd_ms": ms_bwd, "fwd_bwd_ms": ms_step,
+                      "fwd_bwd_ms_per_pair": ms_step / count, "workspace_bytes": ws.numel()}
+        del ws
+    res["evals_per_batch_forward"] = evals
+    res["fwd_bwd_speedup_batched_vs_plain"] = res["plain"]["fwd_bwd_ms"] / res["batched_graph"]["fwd_bwd_ms"]
+    res["peak_hbm_bytes"] = torch.cuda.max_memory_allocated(dev) - base
+    return res
 
 
 def main():
@@ -75,6 +260,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--sections", default="batched,fwd_bwd",
+                    help="extra sections beside the headline step: batched, fwd_bwd, or none")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes five times")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the method has no cross-GPU exchange on its hot "
@@ -86,34 +275,30 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_probe:
+        a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        return
+    sections = [s for s in args.sections.split(",") if s and s != "none"]
+
     p, cfg = synth.workload("mid1436")
     H, W, D, K, n, r, eps = cfg.height, cfg.width, cfg.max_disp, cfg.levels, cfg.half_window, \
         cfg.refine_radius, cfg.var_eps
     Lg = torch.from_numpy(p.left).to(dev)
     Rg = torch.from_numpy(p.right).to(dev)
-
-    # evaluation counts from the per-level maps (same kernels as the timed call)
-    PL, PR = msibm.pyramid(Lg, K), msibm.pyramid(Rg, K)
-    maps = [None] * K
-    for k in range(K - 1, -1, -1):
-        maps[k], _ = msibm.match_level(Lg if k == 0 else PL[k], Rg if k == 0 else PR[k], n,
-                                       -(-D // (1 << k)), None if k == K - 1 else maps[k + 1], r,
-                                       eps, with_cost=False)
-    torch.cuda.synchronize()
-    maps_h = [m.cpu().numpy() for m in maps]
-    counts = level_eval_counts(maps_h, H, W, D, K, r)
+    counts = hier_counts(torch, msibm, Lg, Rg, D, K, n, r, eps)
     evals = sum(counts)
 
     # resident buffers, then the timed loop
-    ws = None
-    outs = msibm.disparity_many([Lg], [Rg], [D], [K], n, r, eps, with_cost=True)
-    pairs_ws = msibm.workspace_bytes(msibm._pairs([Lg], [Rg], [D], [K])[0], 1,
-                                     msibm.make_config(n, r, eps))
+    pairs_ws = msibm.workspace_bytes(msibm._pairs([Lg], [Rg], [D], [K])[0], 1, msibm.make_config(n, r, eps))
     ws = torch.empty(pairs_ws, dtype=torch.uint8, device=dev)
+    outs = msibm.disparity_many([Lg], [Rg], [D], [K], n, r, eps, with_cost=True, workspace=ws)
 
     def step():
-        msibm.disparity_many([Lg], [Rg], [D], [K], n, r, eps, with_cost=True, workspace=ws,
-                             outputs=outs)
+        msibm.disparity_many([Lg], [Rg], [D], [K], n, r, eps, with_cost=True, workspace=ws, outputs=outs)
 
     for _ in range(args.warmup):
         step()
@@ -130,7 +315,7 @@ def main():
     value = evals / (ms_step * 1e-3)
 
     # per-kernel HIP-event timings: the same steps again with every launch
-    # bracketed by events on the launch stream
+    # bracketed by events on the stream it is launched on
     msibm.timing_enable(True)
     for _ in range(args.steps):
         step()
@@ -139,23 +324,26 @@ def main():
     msibm.timing_enable(False)
     kernels = {k: {"avg_us": 1e3 * v[0] / v[1], "launches": v[1]} for k, v in sorted(tim.items())}
 
-    dom = "match_refine_l0"
-    dom_us = kernels[dom]["avg_us"]
-    ach = flops_per_eval(n) * counts[0] / (dom_us * 1e-6) / 1e12
+    dom_us = kernels[DOMINANT]["avg_us"]
+    ach = direct_flops_per_eval(n) * counts[0] / (dom_us * 1e-6) / 1e12
+    issued = kernel_flops_per_eval(n) * counts[0] / (dom_us * 1e-6) / 1e12
+    traffic = recorded_traffic()
     roof = {
-        "kernel": dom,
+        "kernel": DOMINANT,
         "bound": "alu",
         "achieved": round(ach, 2),
         "peak": round(PEAK_FP32_UNPACKED, 1),
         "unit": "TFLOP/s",
         "frac": round(ach / PEAK_FP32_UNPACKED, 4),
-        "traffic": None,
-        "flops_per_eval": flops_per_eval(n),
+        "traffic": traffic,
+        "flops_per_eval": direct_flops_per_eval(n),
         "evals_per_launch": counts[0],
         "avg_launch_us": round(dom_us, 2),
         "frac_of_published_fp32_157_3": round(ach / PEAK_FP32_PUBLISHED, 4),
-        "direct_definition_equiv_tflops": round(direct_flops_per_eval(n) * counts[0] /
-                                                (dom_us * 1e-6) / 1e12, 2),
+        "issued_flops_per_eval": kernel_flops_per_eval(n),
+        "issued_tflops": round(issued, 2),
+        "issued_frac": round(issued / PEAK_FP32_UNPACKED, 4),
+        "hbm_gbps_from_traffic": None if traffic is None else round(traffic / (dom_us * 1e-6) / 1e9, 1),
     }
 
     # flat full search at full resolution (standard block matching) for comparison
@@ -167,17 +355,19 @@ def main():
         msibm._check(msibm.lib().msibm_match_level(
             msibm._ptr(Lg), msibm._ptr(Rg), 0, H, W, W, n, D, None, 0, 0, 0, 0, float(eps),
             msibm._ptr(dflat), None, W, msibm._ptr(wsl), wsl.numel(), msibm._stream(dev)))
+    flat_ms = time_ms(torch, flat, max(3, args.steps // 20), 3)
+    del wsl, dflat
 
-    for _ in range(3):
-        flat()
-    torch.cuda.synchronize()
-    nflat = max(3, args.steps // 20)
-    e0.record()
-    for _ in range(nflat):
-        flat()
-    e1.record()
-    torch.cuda.synchronize()
-    flat_ms = e0.elapsed_time(e1) / nflat
+    extra = {}
+    nsteps = max(3, min(args.steps, 20))
+    if "batched" in sections:
+        extra["batched"] = section_batched(torch, msibm, synth, nsteps)
+        torch.cuda.empty_cache()
+    if "fwd_bwd" in sections:
+        extra["fwd_bwd"] = {
+            "diff960x8": section_fwd_bwd(torch, msibm, synth, "diff960", 8, nsteps),
+            "hires2880x4": section_fwd_bwd(torch, msibm, synth, "hires2880", 4, max(3, nsteps // 2)),
+        }
 
     # the FP64 oracle on the host cores: whole pairs until the time budget is used
     cpu = None
@@ -195,7 +385,7 @@ def main():
                "sample": f"{reps} full hierarchical forwards of the 1436x992 pair ({el:.1f} s)"}
 
     line = {
-        "metric": "pixel-disparity ZNCC evals/s + ms/pair, batched vs plain; fwd+bwd ms",
+        "metric": METRIC,
         "value": value,
         "unit": "evals/s",
         "n_gpus": 1,
@@ -218,6 +408,7 @@ def main():
                              "hierarchical_speedup": flat_ms / ms_step},
         "kernels": kernels,
         "roofline": roof,
+        **extra,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line))

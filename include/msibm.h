@@ -206,6 +206,12 @@ msibm_status msibm_disparity(const msibm_pair* pairs, int32_t n_pairs, const msi
  *   grad_soft[p]    device float H x W (pitch W): dL/dd_soft.
  *   grad_left[p], grad_right[p]  device float H x W (pitch W), OVERWRITTEN.
  *   workspace       as for msibm_disparity.
+ * Without MSIBM_FLAG_BATCHED each pair takes three launches (level-0 statistics,
+ * gradient zeroing, backward tiles).  With it those three launches cover every
+ * pair; with MSIBM_FLAG_GRAPH too they are captured and replayed as described
+ * for msibm_disparity (keyed by pairs, cfg, the prior, gradient and workspace
+ * pointers).  Gradients are summed with float atomics, so the low bits depend
+ * on the summation order (not bit-reproducible between runs).
  * Errors: INVALID_ARG, SHAPE, UNSUPPORTED, WORKSPACE, HIP.
  */
 msibm_status msibm_backward(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg,

@@ -333,6 +333,13 @@ msibm_status msibm_backward(const msibm_pair* pairs, int32_t n_pairs, const msib
     if (!workspace || ws_bytes < need)
         return fail(MSIBM_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace ? ws_bytes : (size_t)0, need);
     hipStream_t s = (hipStream_t)stream;
+    if (cfg->flags & MSIBM_FLAG_BATCHED) {
+        BatchGrads g{prior1, grad_soft, grad_left, grad_right};
+        std::string err;
+        const int rc = run_batched_backward(pairs, n_pairs, cfg, g, workspace, ws_bytes, s, &err);
+        if (rc != MSIBM_OK) return fail(rc, "%s", err.c_str());
+        return ok();
+    }
     size_t base = 0;
     for (int p = 0; p < n_pairs; ++p) {
         const PairLayout lay = pair_layout(pairs[p], Ks[p]);

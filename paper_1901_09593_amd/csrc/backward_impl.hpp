@@ -296,4 +296,28 @@ static hipError_t dispatch_backward(int nc, const BackArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Backward tiles of several pairs in one launch (level 0 of each pair).
+template <int NW, int NC>
+__global__ __launch_bounds__(MATCH_THREADS) void backward_multi_kernel(MultiArgs a)
+{
+    __shared__ BackSmem<NW, ChunkOf<MODE_SOFT>::value> sm;
+    const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
+    const int t = blockIdx.x - s.task0;
+    backward_tile<NW, NC>(a.back[s.pair], t % s.tiles_x, t / s.tiles_x, sm);
+}
+
+template <int NW>
+static hipError_t dispatch_backward_multi(int nc, const MultiArgs& a, int blocks, hipStream_t s)
+{
+    if (blocks < 1 || a.nseg < 1) return hipErrorInvalidValue;
+    switch (nc) {
+        case 3: hipLaunchKernelGGL((backward_multi_kernel<NW, 3>), dim3(blocks), dim3(MATCH_THREADS), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((backward_multi_kernel<NW, 5>), dim3(blocks), dim3(MATCH_THREADS), 0, s, a); break;
+        case 7: hipLaunchKernelGGL((backward_multi_kernel<NW, 7>), dim3(blocks), dim3(MATCH_THREADS), 0, s, a); break;
+        case 9: hipLaunchKernelGGL((backward_multi_kernel<NW, 9>), dim3(blocks), dim3(MATCH_THREADS), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 }  // namespace msibm

@@ -3,4 +3,8 @@
 
 namespace msibm {
 hipError_t launch_backward_n2(int nc, const BackArgs& a, hipStream_t s) { return dispatch_backward<2>(nc, a, s); }
+hipError_t launch_backward_multi_n2(int nc, const MultiArgs& a, int blocks, hipStream_t s)
+{
+    return dispatch_backward_multi<2>(nc, a, blocks, s);
+}
 }  // namespace msibm

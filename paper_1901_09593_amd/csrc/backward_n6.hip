@@ -3,4 +3,8 @@
 
 namespace msibm {
 hipError_t launch_backward_n6(int nc, const BackArgs& a, hipStream_t s) { return dispatch_backward<6>(nc, a, s); }
+hipError_t launch_backward_multi_n6(int nc, const MultiArgs& a, int blocks, hipStream_t s)
+{
+    return dispatch_backward_multi<6>(nc, a, blocks, s);
+}
 }  // namespace msibm

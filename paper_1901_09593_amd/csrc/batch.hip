@@ -23,6 +23,7 @@
 #include <string>
 #include <vector>
 
+#include "backward_impl.hpp"
 #include "levels_impl.hpp"
 #include "plan.hpp"
 #include "timing.hpp"
@@ -32,7 +33,7 @@ namespace msibm {
 static int cdiv(int a, int b) { return (a + b - 1) / b; }
 static int levels_of(const msibm_pair& p) { return p.num_levels ? p.num_levels : auto_levels(p.max_disp); }
 
-enum StageKind { STAGE_REDUCE = 0, STAGE_STATS = 1, STAGE_MATCH = 2 };
+enum StageKind { STAGE_REDUCE = 0, STAGE_STATS = 1, STAGE_MATCH = 2, STAGE_ZERO = 3, STAGE_BACKWARD = 4 };
 
 struct StageLaunch {
     int kind, level;
@@ -44,9 +45,28 @@ struct BatchPlan {
     std::vector<Segment> segs;
     std::vector<LevelDesc> levels;
     std::vector<int> level_base;
+    std::vector<BackArgs> back;
     std::vector<StageLaunch> launches;
-    size_t off_levels = 0, off_base = 0, bytes = 0;  // table layout
+    size_t off_levels = 0, off_base = 0, off_back = 0, bytes = 0;  // table layout
 };
+
+// Zero both gradients of every pair of a backward launch (a fill kernel rather
+// than a memset, so the sequence can be captured into a graph).
+__global__ __launch_bounds__(256) void zero_multi_kernel(MultiArgs a)
+{
+    const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
+    const BackArgs& b = a.back[s.pair];
+    const size_t count = (size_t)b.H * b.W;
+    const size_t base = (size_t)(blockIdx.x - s.task0) * ZERO_TILE + threadIdx.x;
+#pragma unroll 4
+    for (int m = 0; m < ZERO_TILE / 256; ++m) {
+        const size_t i = base + (size_t)m * 256;
+        if (i < count) {
+            b.gL[i] = 0.f;
+            b.gR[i] = 0.f;
+        }
+    }
+}
 
 // Tiles of one level: reduce and statistics tiles cover one view each, matching
 // tiles both.
@@ -64,6 +84,10 @@ static Segment make_seg(int type, int p, int k, int h, int w, int task0)
         s.tiles_x = cdiv(w, ST_W);
         s.tiles_y = cdiv(h, ST_H);
         s.views = 2;
+    } else if (type == SEG_ZERO) {
+        s.tiles_x = (int)(((size_t)h * w + ZERO_TILE - 1) / ZERO_TILE);
+        s.tiles_y = 1;
+        s.views = 1;
     } else {
         s.tiles_x = cdiv(w, TILE_W);
         s.tiles_y = cdiv(h, TILE_H1);
@@ -74,6 +98,18 @@ static Segment make_seg(int type, int p, int k, int h, int w, int task0)
 }
 
 static int seg_tiles(const Segment& s) { return s.tiles_x * s.tiles_y * s.views; }
+
+// Table: segments, level descriptors, level bases, backward arguments.
+static void table_layout(BatchPlan& pl, int nlevels, int np, int nback)
+{
+    size_t off = align_up(sizeof(Segment) * pl.segs.size());
+    pl.off_levels = off;
+    off = align_up(off + sizeof(LevelDesc) * (size_t)nlevels);
+    pl.off_base = off;
+    off = align_up(off + sizeof(int) * (size_t)np);
+    pl.off_back = off;
+    pl.bytes = align_up(off + sizeof(BackArgs) * (size_t)nback);
+}
 
 // Segments and launches (no device pointers yet).
 static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg, BatchPlan& pl)
@@ -136,13 +172,29 @@ static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg
                     add(segtype[m], p, k);
                 }
             }
-    size_t off = align_up(sizeof(Segment) * pl.segs.size());
-    pl.off_levels = off;
     int nl = 0;
     for (int p = 0; p < np; ++p) nl += K[p];
-    off = align_up(off + sizeof(LevelDesc) * (size_t)nl);
-    pl.off_base = off;
-    pl.bytes = align_up(off + sizeof(int) * (size_t)np);
+    table_layout(pl, nl, np, 0);
+}
+
+// Backward: level-0 statistics of every pair, zeroed gradients, backward tiles.
+static void plan_backward_stages(const msibm_pair* pairs, int np, BatchPlan& pl)
+{
+    const int kinds[3] = {STAGE_STATS, STAGE_ZERO, STAGE_BACKWARD};
+    const int types[3] = {SEG_STATS, SEG_ZERO, SEG_BACKWARD};
+    for (int q = 0; q < 3; ++q) {
+        StageLaunch l{};
+        l.kind = kinds[q];
+        l.first = (int)pl.segs.size();
+        for (int p = 0; p < np; ++p) {
+            const Segment sg = make_seg(types[q], p, 0, pairs[p].height, pairs[p].width, l.blocks);
+            l.blocks += seg_tiles(sg);
+            l.nseg++;
+            pl.segs.push_back(sg);
+        }
+        pl.launches.push_back(l);
+    }
+    table_layout(pl, np, np, np);
 }
 
 // Level descriptors of every pair, with its workspace region and outputs.
@@ -194,9 +246,10 @@ static size_t pairs_bytes(const msibm_pair* pairs, int np)
 size_t batch_extra_bytes(const msibm_pair* pairs, int n_pairs, const msibm_config* cfg)
 {
     if (!(cfg->flags & MSIBM_FLAG_BATCHED)) return 0;
-    BatchPlan pl;
-    plan_stages(pairs, n_pairs, cfg, pl);
-    return pl.bytes;
+    BatchPlan fw, bw;
+    plan_stages(pairs, n_pairs, cfg, fw);
+    plan_backward_stages(pairs, n_pairs, bw);
+    return fw.bytes > bw.bytes ? fw.bytes : bw.bytes;
 }
 
 // Host image of the table: segments, level descriptors, level bases.
@@ -206,6 +259,7 @@ static void pack_table(const BatchPlan& pl, std::vector<char>& host)
     std::memcpy(host.data(), pl.segs.data(), sizeof(Segment) * pl.segs.size());
     std::memcpy(host.data() + pl.off_levels, pl.levels.data(), sizeof(LevelDesc) * pl.levels.size());
     std::memcpy(host.data() + pl.off_base, pl.level_base.data(), sizeof(int) * pl.level_base.size());
+    if (!pl.back.empty()) std::memcpy(host.data() + pl.off_back, pl.back.data(), sizeof(BackArgs) * pl.back.size());
 }
 
 // Enqueue every stage launch; `table` is the device copy of the plan's table.
@@ -215,6 +269,7 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
     MultiArgs a{};
     a.levels = (const LevelDesc*)(table + pl.off_levels);
     a.level_base = (const int*)(table + pl.off_base);
+    a.back = (const BackArgs*)(table + pl.off_back);
     a.r = cfg->refine_radius;
     a.rs = cfg->soft_radius;
     a.var_eps = cfg->var_eps;
@@ -224,13 +279,21 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
         a.segs = (const Segment*)table + l.first;
         a.nseg = l.nseg;
         char lab[40];
+        const bool bwd = !pl.back.empty();
         if (l.kind == STAGE_REDUCE) snprintf(lab, sizeof(lab), "batch_reduce_l%d", l.level);
-        else if (l.kind == STAGE_STATS) snprintf(lab, sizeof(lab), "batch_stats");
+        else if (l.kind == STAGE_STATS) snprintf(lab, sizeof(lab), bwd ? "batch_bwd_stats" : "batch_stats");
+        else if (l.kind == STAGE_ZERO) snprintf(lab, sizeof(lab), "batch_bwd_zero");
+        else if (l.kind == STAGE_BACKWARD) snprintf(lab, sizeof(lab), "batch_backward_l0");
         else snprintf(lab, sizeof(lab), "batch_match_%s_l%d", mode_name[l.mode], l.level);
         const int slot = timed ? timing_begin(lab, s) : -1;
         hipError_t e;
         if (l.kind == STAGE_REDUCE) e = launch_reduce_multi(a, l.blocks, s);
         else if (l.kind == STAGE_STATS) e = launch_stats_multi(cfg->half_window, a, l.blocks, s);
+        else if (l.kind == STAGE_ZERO) {
+            hipLaunchKernelGGL(zero_multi_kernel, dim3(l.blocks), dim3(256), 0, s, a);
+            e = hipGetLastError();
+        } else if (l.kind == STAGE_BACKWARD)
+            e = launch_backward_multi(cfg->half_window, slots_for_radius(cfg->soft_radius), a, l.blocks, s);
         else e = launch_match_multi(cfg->half_window, l.dtype, l.mode, l.nc, a, l.blocks, s);
         if (timed) timing_end(slot, s);
         if (e != hipSuccess) return e;
@@ -307,28 +370,25 @@ static std::mutex g_graph_mu;
 static std::map<GraphKey, GraphEntry> g_graphs;
 static const size_t GRAPH_CACHE_MAX = 64;
 
-static GraphKey make_key(int dev, const msibm_pair* pairs, int np, const msibm_config* cfg,
-                         const BatchOutputs& out, void* ws, size_t ws_bytes)
+// Key bytes: direction tag, device, pairs, cfg, then the call's buffer pointers.
+static GraphKey make_key(char tag, int dev, const msibm_pair* pairs, int np, const msibm_config* cfg,
+                         const std::vector<const void*>& bufs, void* ws, size_t ws_bytes)
 {
     GraphKey k;
     auto put = [&](const void* p, size_t n) {
         const char* c = (const char*)p;
         k.bytes.insert(k.bytes.end(), c, c + n);
     };
+    put(&tag, 1);
     put(&dev, sizeof(dev));
     put(pairs, sizeof(msibm_pair) * np);
     put(cfg, sizeof(msibm_config));
-    for (int p = 0; p < np; ++p) {
-        const void* q[4] = {out.disp[p], out.cost ? out.cost[p] : nullptr, out.soft ? out.soft[p] : nullptr,
-                            out.prior1 ? out.prior1[p] : nullptr};
-        put(q, sizeof(q));
-    }
+    put(bufs.data(), sizeof(void*) * bufs.size());
     put(&ws, sizeof(ws));
     put(&ws_bytes, sizeof(ws_bytes));
     return k;
 }
 
-// Callers make sure no replay of the entry is still in flight.
 static void destroy_entry(GraphEntry& e)
 {
     if (e.exec) hipGraphExecDestroy(e.exec);
@@ -377,20 +437,19 @@ static int capture_graph(int dev, const BatchPlan& pl, const msibm_config* cfg, 
     return MSIBM_OK;
 }
 
-int run_batched(const msibm_pair* pairs, int np, const msibm_config* cfg, const BatchOutputs& out,
-                void* workspace, size_t ws_bytes, hipStream_t s, std::string* err)
+// Runs a plan made by `build`: replayed from the graph cache under `key` when
+// graphs are on, else uploaded into the workspace table region and launched.
+template <class Build>
+static int run_plan(int dev, const msibm_config* cfg, const GraphKey* key, Build build, char* table,
+                    hipStream_t s, std::string* err)
 {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "device", err);
-    if (cfg->flags & MSIBM_FLAG_GRAPH) {
-        const GraphKey key = make_key(dev, pairs, np, cfg, out, workspace, ws_bytes);
+    hipError_t e;
+    if (key) {
         std::lock_guard<std::mutex> g(g_graph_mu);
-        auto it = g_graphs.find(key);
+        auto it = g_graphs.find(*key);
         if (it == g_graphs.end()) {
             BatchPlan pl;
-            plan_stages(pairs, np, cfg, pl);
-            plan_levels(pairs, np, out, (char*)workspace, pl);
+            build(pl);
             GraphEntry ent;
             const int rc = capture_graph(dev, pl, cfg, &ent, err);
             if (rc != MSIBM_OK) return rc;
@@ -399,7 +458,7 @@ int run_batched(const msibm_pair* pairs, int np, const msibm_config* cfg, const 
                 for (auto& kv : g_graphs) destroy_entry(kv.second);
                 g_graphs.clear();
             }
-            it = g_graphs.emplace(key, ent).first;
+            it = g_graphs.emplace(*key, ent).first;
         }
         const int slot = timing_begin("batch_graph", s);
         e = hipGraphLaunch(it->second.exec, s);
@@ -408,9 +467,7 @@ int run_batched(const msibm_pair* pairs, int np, const msibm_config* cfg, const 
         return MSIBM_OK;
     }
     BatchPlan pl;
-    plan_stages(pairs, np, cfg, pl);
-    plan_levels(pairs, np, out, (char*)workspace, pl);
-    char* table = (char*)workspace + pairs_bytes(pairs, np);
+    build(pl);
     std::vector<char> host;
     pack_table(pl, host);
     e = upload_table(dev, table, host, s);
@@ -418,6 +475,95 @@ int run_batched(const msibm_pair* pairs, int np, const msibm_config* cfg, const 
     e = enqueue_stages(pl, table, cfg, true, s);
     if (e != hipSuccess) return hip_fail(e, "batched launch", err);
     return MSIBM_OK;
+}
+
+int run_batched(const msibm_pair* pairs, int np, const msibm_config* cfg, const BatchOutputs& out,
+                void* workspace, size_t ws_bytes, hipStream_t s, std::string* err)
+{
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "device", err);
+    GraphKey key;
+    const bool graph = (cfg->flags & MSIBM_FLAG_GRAPH) != 0;
+    if (graph) {
+        std::vector<const void*> bufs;
+        for (int p = 0; p < np; ++p) {
+            bufs.push_back(out.disp[p]);
+            bufs.push_back(out.cost ? out.cost[p] : nullptr);
+            bufs.push_back(out.soft ? out.soft[p] : nullptr);
+            bufs.push_back(out.prior1 ? out.prior1[p] : nullptr);
+        }
+        key = make_key('F', dev, pairs, np, cfg, bufs, workspace, ws_bytes);
+    }
+    auto build = [&](BatchPlan& pl) {
+        plan_stages(pairs, np, cfg, pl);
+        plan_levels(pairs, np, out, (char*)workspace, pl);
+    };
+    return run_plan(dev, cfg, graph ? &key : nullptr, build, (char*)workspace + pairs_bytes(pairs, np), s, err);
+}
+
+int run_batched_backward(const msibm_pair* pairs, int np, const msibm_config* cfg, const BatchGrads& g,
+                         void* workspace, size_t ws_bytes, hipStream_t s, std::string* err)
+{
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "device", err);
+    GraphKey key;
+    const bool graph = (cfg->flags & MSIBM_FLAG_GRAPH) != 0;
+    if (graph) {
+        std::vector<const void*> bufs;
+        for (int p = 0; p < np; ++p) {
+            bufs.push_back(g.prior1[p]);
+            bufs.push_back(g.grad_soft[p]);
+            bufs.push_back(g.grad_left[p]);
+            bufs.push_back(g.grad_right[p]);
+        }
+        key = make_key('B', dev, pairs, np, cfg, bufs, workspace, ws_bytes);
+    }
+    auto build = [&](BatchPlan& pl) {
+        plan_backward_stages(pairs, np, pl);
+        size_t base = 0;
+        for (int p = 0; p < np; ++p) {
+            const msibm_pair& P = pairs[p];
+            const PairLayout lay = pair_layout(P, levels_of(P));
+            char* ws = (char*)workspace + base;
+            base += lay.bytes;
+            LevelDesc d{};
+            d.img[0] = P.left;
+            d.img[1] = P.right;
+            d.pitch = P.pitch;
+            d.dtype = P.dtype;
+            d.H = P.height;
+            d.W = P.width;
+            d.stat[0] = (float4*)(ws + lay.stat[0][0]);
+            d.stat[1] = (float4*)(ws + lay.stat[0][1]);
+            d.Dk = P.max_disp;
+            pl.levels.push_back(d);
+            pl.level_base.push_back(p);
+            BackArgs b{};
+            b.L = (const float*)P.left;
+            b.R = (const float*)P.right;
+            b.H = P.height;
+            b.W = P.width;
+            b.pitch = P.pitch;
+            b.statL = d.stat[0];
+            b.statR = d.stat[1];
+            b.spitch = P.width;
+            b.D = P.max_disp;
+            b.prior = g.prior1[p];
+            b.Hc = lay.h[1];
+            b.Wc = lay.w[1];
+            b.ppitch = lay.w[1];
+            b.rs = cfg->soft_radius;
+            b.inv_tau = 1.f / cfg->tau;
+            b.g = g.grad_soft[p];
+            b.gpitch = P.width;
+            b.gL = g.grad_left[p];
+            b.gR = g.grad_right[p];
+            pl.back.push_back(b);
+        }
+    };
+    return run_plan(dev, cfg, graph ? &key : nullptr, build, (char*)workspace + pairs_bytes(pairs, np), s, err);
 }
 
 }  // namespace msibm

@@ -81,7 +81,9 @@ struct ConvertArgs {
 // The batched forward describes its work as segments, one per (pair, stage,
 // level); a launch covers the tiles of several segments of one stage.
 
-enum SegType { SEG_REDUCE = 0, SEG_STATS = 1, SEG_FULL = 2, SEG_REFINE = 3, SEG_SOFT = 4 };
+enum SegType { SEG_REDUCE = 0, SEG_STATS = 1, SEG_FULL = 2, SEG_REFINE = 3, SEG_SOFT = 4, SEG_ZERO = 5, SEG_BACKWARD = 6 };
+
+struct BackArgs;
 
 // One level of one pair.
 struct LevelDesc {
@@ -111,10 +113,14 @@ struct MultiArgs {
     int nseg;
     const LevelDesc* levels;  // a pair's levels start at levels[level_base[pair]]
     const int* level_base;
+    const BackArgs* back;     // backward launches: one entry per pair
     int r, rs;                // refine and soft radius
     double var_eps;
     float inv_tau;
 };
+
+// Floats a zero-fill tile clears in each gradient (256 threads x 16).
+constexpr int ZERO_TILE = 4096;
 
 // Segment of launch block b: binary search over the launch's segment table
 // (block-uniform, so it runs on the scalar unit).
@@ -159,8 +165,15 @@ hipError_t launch_match_n4(int dtype, int mode, int nc, const MatchArgs& a, hipS
 hipError_t launch_match_n5(int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
 hipError_t launch_match_n6(int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
 
-struct BackArgs;
 hipError_t launch_backward(int n, int nc, const BackArgs& a, hipStream_t s);
+hipError_t launch_backward_multi(int n, int nc, const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_backward_multi_n1(int nc, const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_backward_multi_n2(int nc, const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_backward_multi_n3(int nc, const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_backward_multi_n4(int nc, const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_backward_multi_n5(int nc, const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_backward_multi_n6(int nc, const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_zero_multi(const MultiArgs& a, int blocks, hipStream_t s);
 hipError_t launch_backward_n1(int nc, const BackArgs& a, hipStream_t s);
 hipError_t launch_backward_n2(int nc, const BackArgs& a, hipStream_t s);
 hipError_t launch_backward_n3(int nc, const BackArgs& a, hipStream_t s);

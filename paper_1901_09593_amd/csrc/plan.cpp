@@ -173,6 +173,19 @@ hipError_t launch_backward(int n, int nc, const BackArgs& a, hipStream_t s)
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_backward_multi(int n, int nc, const MultiArgs& a, int blocks, hipStream_t s)
+{
+    switch (n) {
+        case 1: return launch_backward_multi_n1(nc, a, blocks, s);
+        case 2: return launch_backward_multi_n2(nc, a, blocks, s);
+        case 3: return launch_backward_multi_n3(nc, a, blocks, s);
+        case 4: return launch_backward_multi_n4(nc, a, blocks, s);
+        case 5: return launch_backward_multi_n5(nc, a, blocks, s);
+        case 6: return launch_backward_multi_n6(nc, a, blocks, s);
+    }
+    return hipErrorInvalidValue;
+}
+
 // Backward of one pair: level-0 window statistics, zeroed gradients, then the
 // backward tiles (which add into the gradients).
 int run_pair_backward(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,

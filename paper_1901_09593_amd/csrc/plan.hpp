@@ -51,4 +51,15 @@ size_t batch_extra_bytes(const msibm_pair* pairs, int n_pairs, const msibm_confi
 int run_batched(const msibm_pair* pairs, int n_pairs, const msibm_config* cfg, const BatchOutputs& out,
                 void* workspace, size_t ws_bytes, hipStream_t s, std::string* err);
 
+struct BatchGrads {
+    const int16_t* const* prior1;
+    const float* const* grad_soft;
+    float* const* grad_left;
+    float* const* grad_right;
+};
+
+// Batched backward: one statistics, one zero and one backward launch for all pairs.
+int run_batched_backward(const msibm_pair* pairs, int n_pairs, const msibm_config* cfg, const BatchGrads& g,
+                         void* workspace, size_t ws_bytes, hipStream_t s, std::string* err);
+
 }  // namespace msibm

@@ -293,20 +293,37 @@ def backward(L: torch.Tensor, R: torch.Tensor, prior1: torch.Tensor, grad_soft: 
              D: int, K: int, n: int, r: int, var_eps: float, soft_radius: int,
              tau: float) -> Tuple[torch.Tensor, torch.Tensor]:
     """(dLoss/dL, dLoss/dR) given dLoss/d(d_soft), the level-1 prior held fixed."""
-    pairs, keep = _pairs([L], [R], [D], [K])
-    cfg = make_config(n, r, var_eps, soft_radius, tau, 0)
-    ws_bytes = workspace_bytes(pairs, 1, cfg)
-    dev = L.device
-    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
-    g = grad_soft.contiguous().to(torch.float32)
-    gL = torch.empty(L.shape, dtype=torch.float32, device=dev)
-    gR = torch.empty(L.shape, dtype=torch.float32, device=dev)
-    p1 = prior1.contiguous()
-    _check(lib().msibm_backward(pairs, 1, ctypes.byref(cfg), _ptr_array([p1]), _ptr_array([g]),
-                                _ptr_array([gL]), _ptr_array([gR]), _ptr(ws), ws_bytes,
-                                _stream(dev)))
-    del keep
+    (gL, gR), = backward_many([L], [R], [prior1], [grad_soft], [D], [K], n, r, var_eps,
+                              soft_radius, tau)
     return gL, gR
+
+
+def backward_many(lefts: Sequence[torch.Tensor], rights: Sequence[torch.Tensor],
+                  priors: Sequence[torch.Tensor], grads: Sequence[torch.Tensor], Ds: Sequence[int],
+                  Ks: Sequence[int], n: int, r: int, var_eps: float, soft_radius: int, tau: float,
+                  flags: int = 0, workspace: Optional[torch.Tensor] = None,
+                  outputs: Optional[List[Tuple[torch.Tensor, torch.Tensor]]] = None
+                  ) -> List[Tuple[torch.Tensor, torch.Tensor]]:
+    """Backward of several pairs in one call (flags: FLAG_BATCHED, FLAG_GRAPH).
+    `workspace` and `outputs` may be passed in to reuse buffers across calls."""
+    pairs, keep = _pairs(lefts, rights, Ds, Ks)
+    npair = len(lefts)
+    cfg = make_config(n, r, var_eps, soft_radius, tau, flags)
+    ws_bytes = workspace_bytes(pairs, npair, cfg)
+    dev = lefts[0].device
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    g = [x.contiguous().to(torch.float32) for x in grads]
+    p1 = [x.contiguous() for x in priors]
+    if outputs is None:
+        outputs = [(torch.empty(L.shape, dtype=torch.float32, device=dev),
+                    torch.empty(L.shape, dtype=torch.float32, device=dev)) for L in lefts]
+    _check(lib().msibm_backward(pairs, npair, ctypes.byref(cfg), _ptr_array(p1), _ptr_array(g),
+                                _ptr_array([o[0] for o in outputs]),
+                                _ptr_array([o[1] for o in outputs]), _ptr(workspace),
+                                workspace.numel(), _stream(dev)))
+    del keep, g, p1
+    return outputs
 
 
 class MsibmFunction(torch.autograd.Function):

@@ -222,16 +222,23 @@ def batch_shapes(n_pairs: int = 32, shape_seed: int = 1000):
 
 
 def batch_workload(n_pairs: int = 32, shape_seed: int = 1000,
-                   only: Optional[List[int]] = None):
+                   only: Optional[List[int]] = None, workers: int = 1):
     """The uneven batch: pair i uses seed i, u8, 8 slanted segments with
-    d in [0.05 D, 0.9 D], noise 2; 9x9, r=2, K = auto_levels(D)."""
-    out = []
-    for i, (H, W, D) in enumerate(batch_shapes(n_pairs, shape_seed)):
-        if only is not None and i not in only:
-            continue
+    d in [0.05 D, 0.9 D], noise 2; 9x9, r=2, K = auto_levels(D).  Every pair has
+    its own generator, so `workers` threads give the same pairs."""
+    todo = [(i, H, W, D) for i, (H, W, D) in enumerate(batch_shapes(n_pairs, shape_seed))
+            if only is None or i in only]
+
+    def one(t):
+        i, H, W, D = t
         p = make_pair(i, H, W, 8, 0.05 * D, 0.9 * D, True, 1.0, 0.0, 2.0, "u8")
-        out.append((p, MatchConfig(H, W, D, auto_levels(D), 4, 2, "u8")))
-    return out
+        return p, MatchConfig(H, W, D, auto_levels(D), 4, 2, "u8")
+
+    if workers <= 1:
+        return [one(t) for t in todo]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(workers) as ex:
+        return list(ex.map(one, todo))
 
 
 def grad_seed(seed: int, H: int, W: int) -> np.ndarray:

@@ -136,3 +136,41 @@ def test_autograd_loss_gradient(M):
     eL, eR = rel(host(Lt.grad), oL), rel(host(Rt.grad), oR)
     print("autograd rel error", eL, eR)
     assert eL <= REL_TOL and eR <= REL_TOL
+
+
+def test_batched_backward_matches_plain_and_oracle(M):
+    """Three uneven crops: the batched backward (and its graph replays) against the
+    per-pair backward (same arithmetic, only the atomic order differs) and the
+    oracle."""
+    crops = [(96, 200, 0), (120, 256, 1), (64, 130, 2)]
+    L, R, D, K = [], [], [], []
+    for h, w, seed in crops:
+        l, r_, _, _, cfg = _crop_case(h, w, seed)
+        L.append(dev(l))
+        R.append(dev(r_))
+        D.append(cfg.max_disp)
+        K.append(cfg.levels)
+    n, r, eps, rs, tau = cfg.half_window, cfg.refine_radius, cfg.var_eps, cfg.soft_radius, cfg.tau
+    outs = M.disparity_many(L, R, D, K, n, r, eps, soft_radius=rs, tau=tau, flags=M.FLAG_BATCHED)
+    p1 = [o["prior1"] for o in outs]
+    g = [dev(synth.grad_seed(5 + i, *x.shape).astype(np.float32)) for i, x in enumerate(L)]
+    plain = M.backward_many(L, R, p1, g, D, K, n, r, eps, rs, tau)
+    batched = M.backward_many(L, R, p1, g, D, K, n, r, eps, rs, tau, flags=M.FLAG_BATCHED)
+    for (a, b), (c, d) in zip(plain, batched):
+        assert rel(host(c), host(a)) < 1e-5 and rel(host(d), host(b)) < 1e-5
+    flags = M.FLAG_BATCHED | M.FLAG_GRAPH
+    gouts = M.backward_many(L, R, p1, g, D, K, n, r, eps, rs, tau, flags=flags)
+    for rep in range(3):
+        for o in gouts:
+            o[0].fill_(5.0)
+            o[1].fill_(-5.0)
+        M.backward_many(L, R, p1, g, D, K, n, r, eps, rs, tau, flags=flags, outputs=gouts)
+        torch.cuda.synchronize()
+        for (a, b), (c, d) in zip(plain, gouts):
+            assert rel(host(c), host(a)) < 1e-5 and rel(host(d), host(b)) < 1e-5, rep
+    i = 2
+    oL, oR = oracle.backward(host(L[i]), host(R[i]), n, D[i], host(p1[i]), rs, tau, eps,
+                             host(g[i]).astype(np.float64))
+    eL, eR = rel(host(batched[i][0]), oL), rel(host(batched[i][1]), oR)
+    print("batched backward vs oracle", eL, eR)
+    assert eL <= REL_TOL and eR <= REL_TOL
