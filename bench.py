@@ -276,10 +276,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     if args.copy_probe:
+        # an elementwise kernel (b = a * 1) rather than copy_, which may take the
+        # DMA path: it reads and writes exactly BYTES bytes per launch
         a = torch.ones(args.copy_probe // 4, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         for _ in range(5):
-            b.copy_(a)
+            torch.mul(a, 1.0, out=b)
         torch.cuda.synchronize()
         return
     sections = [s for s in args.sections.split(",") if s and s != "none"]
