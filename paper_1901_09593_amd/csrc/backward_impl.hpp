@@ -80,9 +80,9 @@ __device__ __forceinline__ void zero_lds(float* p, int count)
 }
 
 template <int NW, int NC>
-__device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by, BackSmem<NW, ChunkOf<MODE_SOFT>::value>& sm)
+__device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by, BackSmem<NW, BACK_CHUNK>& sm)
 {
-    constexpr int CH = ChunkOf<MODE_SOFT>::value;
+    constexpr int CH = BACK_CHUNK;
     using G = Geo<NW, CH, 1>;
     constexpr int WS = 2 * NW + 1;          // window side
     constexpr float Nf = (float)(WS * WS);
@@ -278,7 +278,7 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
 template <int NW, int NC>
 __global__ __launch_bounds__(MATCH_THREADS) void backward_kernel(BackArgs a)
 {
-    __shared__ BackSmem<NW, ChunkOf<MODE_SOFT>::value> sm;
+    __shared__ BackSmem<NW, BACK_CHUNK> sm;
     backward_tile<NW, NC>(a, blockIdx.x, blockIdx.y, sm);
 }
 
@@ -300,7 +300,7 @@ static hipError_t dispatch_backward(int nc, const BackArgs& a, hipStream_t s)
 template <int NW, int NC>
 __global__ __launch_bounds__(MATCH_THREADS) void backward_multi_kernel(MultiArgs a)
 {
-    __shared__ BackSmem<NW, ChunkOf<MODE_SOFT>::value> sm;
+    __shared__ BackSmem<NW, BACK_CHUNK> sm;
     const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
     const int t = blockIdx.x - s.task0;
     backward_tile<NW, NC>(a.back[s.pair], t % s.tiles_x, t / s.tiles_x, sm);

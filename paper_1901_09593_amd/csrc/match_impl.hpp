@@ -45,12 +45,18 @@
 
 namespace msibm {
 
-// Candidates per right-image chunk: a full search streams through every
-// candidate, a restricted search normally needs one short window per tile.
+// Candidates per right-image chunk.  A full search streams through every
+// candidate 96 at a time.  A restricted search stages, in one go, the union of
+// the candidate windows of all blocks of the tile (up to 320 candidates): the
+// blocks' windows are data dependent (occluded regions give scattered priors),
+// and with short chunks a wave whose blocks fall into several chunks would run
+// the window code once per chunk with most lanes idle.
 template <int MODE>
 struct ChunkOf {
-    static constexpr int value = (MODE == MODE_FULL) ? 96 : 32;
+    static constexpr int value = (MODE == MODE_FULL) ? 96 : 320;
 };
+// The backward keeps short chunks: its LDS holds gradient tiles beside the images.
+constexpr int BACK_CHUNK = 32;
 
 template <int NW, int CH, int BY>
 struct Geo {
@@ -71,13 +77,14 @@ struct Geo {
 // LDS of one matching tile: the left tile, one chunk of the right tile, and the
 // right window statistics of the chunk's columns (window mean minus the right
 // centring constant, and 1/sd).
-template <int NW, int CH, int BY>
+template <int NW, int CH, int BY, int SL>
 struct MatchSmem {
     using G = Geo<NW, CH, BY>;
+    static constexpr int SN = SL ? G::TH * G::SSTRIDE : 1;  // statistics planes only when staged
     float Ls[G::LROWS * G::LSTRIDE];
     float Rs[G::LROWS * G::RSTRIDE];
-    float Sm[G::TH * G::SSTRIDE];
-    float Si[G::TH * G::SSTRIDE];
+    float Sm[SN];
+    float Si[SN];
     int lo, hi;
     unsigned mask;
 };
@@ -105,6 +112,7 @@ __device__ __forceinline__ void stage_tile(float* dst, int stride, int half, con
         const T* srow = src + (size_t)clampi(gy0 + rr, 0, H - 1) * pitch;
 #pragma unroll
         for (int ci = 0; ci < CI; ++ci) {
+            if (ci > 0 && 2 * MATCH_TX * ci >= cols) break;  // uniform: group beyond the staged width
             const int cc = 2 * (lane + MATCH_TX * ci);
             v0[ri][ci] = srow[clampi(gx0 + cc, 0, W - 1)];
             v1[ri][ci] = srow[clampi(gx0 + cc + 1, 0, W - 1)];
@@ -117,6 +125,7 @@ __device__ __forceinline__ void stage_tile(float* dst, int stride, int half, con
         float* drow = dst + rr * stride;
 #pragma unroll
         for (int ci = 0; ci < CI; ++ci) {
+            if (ci > 0 && 2 * MATCH_TX * ci >= cols) break;
             const int ch = lane + MATCH_TX * ci;  // column pair index
             if (2 * ch < cols) drow[ch] = to_f(v0[ri][ci]) - c;
             if (2 * ch + 1 < cols) drow[half + ch] = to_f(v1[ri][ci]) - c;
@@ -266,7 +275,7 @@ struct BlockState {
 // tile (1), or read by each thread from global memory (0).
 template <typename T, int NW, int NC, int MODE, int BY, int SL>
 __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
-                                           MatchSmem<NW, ChunkOf<MODE>::value, BY>& sm)
+                                           MatchSmem<NW, ChunkOf<MODE>::value, BY, SL>& sm)
 {
     constexpr int CH = ChunkOf<MODE>::value;
     using G = Geo<NW, CH, BY>;
@@ -274,6 +283,7 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
     constexpr int STEP = (MODE == MODE_FULL) ? CH : (CH - NC + 1);
     static_assert(MODE != MODE_FULL || CH % NC == 0, "full search steps must tile a chunk");
     static_assert(CH >= NC, "a chunk must hold one slot window");
+    static_assert(MODE == MODE_FULL || (MSIBM_MAX_DISP - 1) / STEP < 32, "chunk mask must hold every chunk");
 
     const T* __restrict__ Lg = static_cast<const T*>(a.L);
     const T* __restrict__ Rg = static_cast<const T*>(a.R);
@@ -492,7 +502,7 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
 template <typename T, int NW, int NC, int MODE, int BY, int SL>
 __global__ __launch_bounds__(MATCH_THREADS) void match_kernel(MatchArgs a)
 {
-    __shared__ MatchSmem<NW, ChunkOf<MODE>::value, BY> sm;
+    __shared__ MatchSmem<NW, ChunkOf<MODE>::value, BY, SL> sm;
     match_tile<T, NW, NC, MODE, BY, SL>(a, blockIdx.x, blockIdx.y, sm);
 }
 
@@ -501,8 +511,12 @@ static hipError_t launch_one(const MatchArgs& a, hipStream_t s)
 {
     constexpr int TH = TILE_H1 * BY;
     dim3 grid((a.W + TILE_W - 1) / TILE_W, (a.H + TH - 1) / TH, 1);
-    if (a.variant & VARIANT_STATS_LDS)
-        hipLaunchKernelGGL((match_kernel<T, NW, NC, MODE, BY, 1>), grid, dim3(MATCH_THREADS), 0, s, a);
+    // statistics staged in LDS is a full-search variant only: a restricted
+    // search reads a few statistics per pixel, and its wide right tile leaves no
+    // LDS for them
+    if (MODE == MODE_FULL && (a.variant & VARIANT_STATS_LDS))
+        hipLaunchKernelGGL((match_kernel<T, NW, NC, MODE, BY, MODE == MODE_FULL ? 1 : 0>), grid,
+                           dim3(MATCH_THREADS), 0, s, a);
     else
         hipLaunchKernelGGL((match_kernel<T, NW, NC, MODE, BY, 0>), grid, dim3(MATCH_THREADS), 0, s, a);
     return hipGetLastError();
@@ -544,7 +558,7 @@ static hipError_t dispatch_match(int dtype, int mode, int nc, const MatchArgs& a
 template <typename T, int NW, int NC, int MODE, int SL>
 __global__ __launch_bounds__(MATCH_THREADS) void match_multi_kernel(MultiArgs a)
 {
-    __shared__ MatchSmem<NW, ChunkOf<MODE>::value, 1> sm;
+    __shared__ MatchSmem<NW, ChunkOf<MODE>::value, 1, SL> sm;
     const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
     const LevelDesc* lv = a.levels + a.level_base[s.pair];
     const LevelDesc& L = lv[s.level];
