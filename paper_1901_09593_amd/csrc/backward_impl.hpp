@@ -88,6 +88,7 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
     constexpr float Nf = (float)(WS * WS);
     constexpr int STEP = CH - NC + 1;
     constexpr int RU = WS + NC - 1;         // right values a pixel's window row touches
+    static_assert((MSIBM_MAX_DISP - 1) / STEP < 32, "chunk mask must hold every chunk");
 
     const int tx = threadIdx.x & (MATCH_TX - 1), ty = threadIdx.x / MATCH_TX;
     const int x0 = bx * TILE_W, y0 = by * G::TH;
@@ -159,70 +160,87 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
                 pa = G::RHALF + (rcol0 >> 1);
                 pb = (rcol0 + 1) >> 1;
             }
+            // one pixel row at a time; its two pixels' contributions are summed in
+            // registers over the union of their windows (WS + 1 left and RU + 1
+            // right columns per row) before they are added into LDS
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                if (!act[p]) continue;
-                const int pr = p >> 1, pc = p & 1;
-                const float dl = (stl[p].x - ca) + stl[p].y;  // mu_l - ca
-                const float invl = stl[p].z;
-                // right statistics of this pixel's candidates: column jp - z
-                const float4* srow = a.statR + (size_t)ip[p] * a.spitch;
-                float mr[NC], invr[NC], rho[NC];
-                bool ok[NC];
-                float best = -3.f;
+            for (int pr = 0; pr < 2; ++pr) {
+                float k1[2][NC], kl[2], cl[2], qb[RU + 1], qc[RU + 1];
 #pragma unroll
-                for (int s = 0; s < NC; ++s) {
-                    const int z = zs + s;
-                    const float4 st = srow[clampi(jp[p] - z, 0, a.W - 1)];
-                    mr[s] = (st.x - cR) + st.y;  // mu_r - cR
-                    invr[s] = st.z;
-                    const float C = fmaf(-Nf * dl, mr[s], S[p][s]);
-                    float rr = C * invl * invr[s];
-                    rr = fminf(fmaxf(rr, -1.f), 1.f);
-                    ok[s] = (z >= lo[p]) && (z <= hi[p]);
-                    rho[s] = rr;
-                    if (ok[s] && rr > best) best = rr;
-                }
-                // soft-argmax and its derivative
-                float e[NC], se = 0.f, sz = 0.f;
-#pragma unroll
-                for (int s = 0; s < NC; ++s) {
-                    e[s] = ok[s] ? __expf((rho[s] - best) * a.inv_tau) : 0.f;
-                    se += e[s];
-                    sz = fmaf(e[s], (float)(zs + s), sz);
-                }
-                const float ds = sz / se;
-                const float gpx = a.g[(size_t)ip[p] * a.gpitch + jp[p]];
-                const float gs = gpx * a.inv_tau / se;
-                float k1[NC], k2r[NC], kl = 0.f, cl = 0.f;
-#pragma unroll
-                for (int s = 0; s < NC; ++s) {
-                    const float gz = gs * e[s] * ((float)(zs + s) - ds);
-                    k1[s] = gz * invl * invr[s];
-                    const float kls = gz * rho[s] * invl * invl;
-                    k2r[s] = gz * rho[s] * invr[s] * invr[s];
-                    kl += kls;
-                    cl = fmaf(-k1[s], mr[s], cl);
-                }
-                cl = fmaf(kl, dl, cl);
-                // per right offset u (0..RU-1 relative to this pixel's first
-                // window column at the last slot): slots touching it and their
-                // summed right coefficients
-                float qb[RU], qc[RU];
-#pragma unroll
-                for (int u = 0; u < RU; ++u) {
+                for (int u = 0; u <= RU; ++u) {
                     qb[u] = 0.f;
                     qc[u] = 0.f;
+                }
+#pragma unroll
+                for (int pc = 0; pc < 2; ++pc) {
+                    const int p = 2 * pr + pc;
+                    kl[pc] = 0.f;
+                    cl[pc] = 0.f;
+#pragma unroll
+                    for (int s = 0; s < NC; ++s) k1[pc][s] = 0.f;
+                    if (!act[p]) continue;  // contributes nothing
+                    const float dl = (stl[p].x - ca) + stl[p].y;  // mu_l - ca
+                    const float invl = stl[p].z;
+                    // right statistics of this pixel's candidates: column jp - z
+                    const float4* srow = a.statR + (size_t)ip[p] * a.spitch;
+                    float mr[NC], invr[NC], rho[NC];
+                    bool ok[NC];
+                    float best = -3.f;
 #pragma unroll
                     for (int s = 0; s < NC; ++s) {
-                        const int b = u - (NC - 1 - s);
-                        if (b >= 0 && b < WS) {
-                            qb[u] += k2r[s];
-                            qc[u] += fmaf(k2r[s], mr[s], -k1[s] * dl);
+                        const int z = zs + s;
+                        const float4 st = srow[clampi(jp[p] - z, 0, a.W - 1)];
+                        mr[s] = (st.x - cR) + st.y;  // mu_r - cR
+                        invr[s] = st.z;
+                        const float C = fmaf(-Nf * dl, mr[s], S[p][s]);
+                        float rr = C * invl * invr[s];
+                        rr = fminf(fmaxf(rr, -1.f), 1.f);
+                        ok[s] = (z >= lo[p]) && (z <= hi[p]);
+                        rho[s] = rr;
+                        if (ok[s] && rr > best) best = rr;
+                    }
+                    // soft-argmax and its derivative
+                    float e[NC], se = 0.f, sz = 0.f;
+#pragma unroll
+                    for (int s = 0; s < NC; ++s) {
+                        e[s] = ok[s] ? __expf((rho[s] - best) * a.inv_tau) : 0.f;
+                        se += e[s];
+                        sz = fmaf(e[s], (float)(zs + s), sz);
+                    }
+                    const float ds = sz / se;
+                    const float gpx = a.g[(size_t)ip[p] * a.gpitch + jp[p]];
+                    const float gs = gpx * a.inv_tau / se;
+                    float k2r[NC], klp = 0.f, clp = 0.f;
+#pragma unroll
+                    for (int s = 0; s < NC; ++s) {
+                        const float gz = gs * e[s] * ((float)(zs + s) - ds);
+                        k1[pc][s] = gz * invl * invr[s];
+                        const float kls = gz * rho[s] * invl * invl;
+                        k2r[s] = gz * rho[s] * invr[s] * invr[s];
+                        klp += kls;
+                        clp = fmaf(-k1[pc][s], mr[s], clp);
+                    }
+                    kl[pc] = klp;
+                    cl[pc] = fmaf(klp, dl, clp);
+                    // right offsets u of this pixel are union columns u + pc:
+                    // slots touching them and their summed coefficients
+#pragma unroll
+                    for (int u = 0; u < RU; ++u) {
+#pragma unroll
+                        for (int s = 0; s < NC; ++s) {
+                            const int b = u - (NC - 1 - s);
+                            if (b >= 0 && b < WS) {
+                                qb[u + pc] += k2r[s];
+                                qc[u + pc] += fmaf(k2r[s], mr[s], -k1[pc][s] * dl);
+                            }
                         }
                     }
                 }
-                // window rows
+                float k1s[NC];
+#pragma unroll
+                for (int s = 0; s < NC; ++s) k1s[s] = k1[0][s] + k1[1][s];
+                const float kls = kl[0] + kl[1], cls = cl[0] + cl[1];
+                // window rows of this pixel row
 #pragma unroll 1
                 for (int y = 0; y < WS; ++y) {
                     const int row = 2 * ty + pr + y;
@@ -230,36 +248,41 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
                     const float* rr_ = sm.Rs + row * G::RSTRIDE;
                     float* glr = sm.GLs + row * G::LSTRIDE + tx;
                     float* grr = sm.GRs + row * G::RSTRIDE;
-                    float l[WS], r[RU];
+                    float l[WS + 1], r[RU + 1];
 #pragma unroll
-                    for (int b = 0; b < WS; ++b) {
-                        const int t = pc + b;
-                        l[b] = lr_[(t & 1) ? G::LHALF + (t >> 1) : (t >> 1)] - ca;
-                    }
+                    for (int t = 0; t <= WS; ++t) l[t] = lr_[(t & 1) ? G::LHALF + (t >> 1) : (t >> 1)] - ca;
 #pragma unroll
-                    for (int u = 0; u < RU; ++u) {
-                        const int v = pc + u;  // logical offset from rcol0
-                        r[u] = (v & 1) ? rr_[pb + (v >> 1)] : rr_[pa + (v >> 1)];
-                    }
-                    // left gradient of this row: sum_s k1 r - kl l + cl
+                    for (int v = 0; v <= RU; ++v) r[v] = (v & 1) ? rr_[pb + (v >> 1)] : rr_[pa + (v >> 1)];
+                    // left gradient at union column t: pixel 0 covers t <= WS - 1,
+                    // pixel 1 covers t >= 1 (both fold into compile-time choices)
 #pragma unroll
-                    for (int b = 0; b < WS; ++b) {
-                        float acc = fmaf(-kl, l[b], cl);
-#pragma unroll
-                        for (int s = 0; s < NC; ++s) acc = fmaf(k1[s], r[b + NC - 1 - s], acc);
-                        const int t = pc + b;
-                        lds_add(glr + ((t & 1) ? G::LHALF + (t >> 1) : (t >> 1)), acc);
-                    }
-                    // right gradient: sum_s k1 l(u - o_s) - qb r(u) + qc
-#pragma unroll
-                    for (int u = 0; u < RU; ++u) {
-                        float acc = fmaf(-qb[u], r[u], qc[u]);
+                    for (int t = 0; t <= WS; ++t) {
+                        const bool v0 = t <= WS - 1, v1 = t >= 1;
+                        const float klt = (v0 && v1) ? kls : (v0 ? kl[0] : kl[1]);
+                        const float clt = (v0 && v1) ? cls : (v0 ? cl[0] : cl[1]);
+                        float acc = fmaf(-klt, l[t], clt);
 #pragma unroll
                         for (int s = 0; s < NC; ++s) {
-                            const int b = u - (NC - 1 - s);
-                            if (b >= 0 && b < WS) acc = fmaf(k1[s], l[b], acc);
+                            const float c = (v0 && v1) ? k1s[s] : (v0 ? k1[0][s] : k1[1][s]);
+                            acc = fmaf(c, r[t + NC - 1 - s], acc);
                         }
-                        const int v = pc + u;
+                        lds_add(glr + ((t & 1) ? G::LHALF + (t >> 1) : (t >> 1)), acc);
+                    }
+                    // right gradient at union column v: slot s pairs it with left
+                    // union column v - (NC - 1 - s), which pixel pc covers when that
+                    // column lies in [pc, WS - 1 + pc]
+#pragma unroll
+                    for (int v = 0; v <= RU; ++v) {
+                        float acc = fmaf(-qb[v], r[v], qc[v]);
+#pragma unroll
+                        for (int s = 0; s < NC; ++s) {
+                            const int t = v - (NC - 1 - s);
+                            const bool v0 = t >= 0 && t <= WS - 1, v1 = t >= 1 && t <= WS;
+                            if (v0 || v1) {
+                                const float c = (v0 && v1) ? k1s[s] : (v0 ? k1[0][s] : k1[1][s]);
+                                acc = fmaf(c, l[t], acc);
+                            }
+                        }
                         lds_add(grr + ((v & 1) ? pb + (v >> 1) : pa + (v >> 1)), acc);
                     }
                 }

@@ -55,22 +55,28 @@ template <int MODE>
 struct ChunkOf {
     static constexpr int value = (MODE == MODE_FULL) ? 96 : 320;
 };
-// The backward keeps short chunks: its LDS holds gradient tiles beside the images.
-constexpr int BACK_CHUNK = 32;
+// The backward's LDS also holds gradient tiles beside the images; 112 candidates
+// keep a right row (128 + 2n + 111 columns) within two 128-column groups for
+// every n <= 6, so the chunk costs no more LDS than a short one.
+constexpr int BACK_CHUNK = 112;
 
+// LDS geometry.  Each staged row keeps its even logical columns in the first
+// half and its odd ones in the second; a half holds whole groups of 64 column
+// pairs (one per lane of a staging wave), so staging stores need no per-element
+// bounds test, and one padding word separates the rows.
 template <int NW, int CH, int BY>
 struct Geo {
     static constexpr int TH = TILE_H1 * BY;       // tile height in pixels
     static constexpr int WN = 2 * NW + 2;         // rows/cols spanned by a block's windows
     static constexpr int LROWS = TH + 2 * NW;     // LDS rows (both views)
     static constexpr int LCOLS = TILE_W + 2 * NW; // left tile logical width
-    static constexpr int LHALF = (LCOLS + 1) / 2;
+    static constexpr int LHALF = MATCH_TX * ((LCOLS + 2 * MATCH_TX - 1) / (2 * MATCH_TX));
     static constexpr int LSTRIDE = 2 * LHALF + 1;
     static constexpr int RCOLS = TILE_W + 2 * NW + CH - 1;
-    static constexpr int RHALF = (RCOLS + 1) / 2;
+    static constexpr int RHALF = MATCH_TX * ((RCOLS + 2 * MATCH_TX - 1) / (2 * MATCH_TX));
     static constexpr int RSTRIDE = 2 * RHALF + 1;
     static constexpr int SCOLS = TILE_W + CH - 1;  // right statistics columns
-    static constexpr int SHALF = (SCOLS + 1) / 2;
+    static constexpr int SHALF = MATCH_TX * ((SCOLS + 2 * MATCH_TX - 1) / (2 * MATCH_TX));
     static constexpr int SSTRIDE = 2 * SHALF + 1;
 };
 
@@ -95,9 +101,11 @@ __device__ __forceinline__ int split_pos(int c, int half) { return (c & 1) ? hal
 // Stage rows [gy0, gy0+ROWS) x cols [gx0, gx0+cols) (cols <= MAXCOLS) of `src`,
 // clamped to the image, into LDS in split layout (even columns at [0, half),
 // odd ones at [half, ...)), centred by c.  Each wave takes whole rows; lane l of
-// iteration k stages columns 2(l + 64k) and 2(l + 64k) + 1.  Clamped addresses
-// are always valid, so every load of the thread is issued unconditionally
-// before any LDS store and their latencies overlap.
+// group k stages columns 2(l + 64k) and 2(l + 64k) + 1.  Only the groups that
+// hold staged columns are loaded (a wave-uniform test); within them every load
+// and store is unconditional: clamped addresses are always valid, a half holds
+// whole groups, and columns past `cols` are never read.  All loads of the thread
+// are issued before its first LDS store so that their latencies overlap.
 template <typename T, int ROWS, int MAXCOLS>
 __device__ __forceinline__ void stage_tile(float* dst, int stride, int half, const T* __restrict__ src,
                                            int pitch, int H, int W, int gy0, int gx0, int cols, float c)
@@ -105,6 +113,7 @@ __device__ __forceinline__ void stage_tile(float* dst, int stride, int half, con
     constexpr int RI = (ROWS + MATCH_TY - 1) / MATCH_TY;
     constexpr int CI = (MAXCOLS + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
+    const int groups = (cols + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     T v0[RI][CI], v1[RI][CI];
 #pragma unroll
     for (int ri = 0; ri < RI; ++ri) {
@@ -112,10 +121,11 @@ __device__ __forceinline__ void stage_tile(float* dst, int stride, int half, con
         const T* srow = src + (size_t)clampi(gy0 + rr, 0, H - 1) * pitch;
 #pragma unroll
         for (int ci = 0; ci < CI; ++ci) {
-            if (ci > 0 && 2 * MATCH_TX * ci >= cols) break;  // uniform: group beyond the staged width
-            const int cc = 2 * (lane + MATCH_TX * ci);
-            v0[ri][ci] = srow[clampi(gx0 + cc, 0, W - 1)];
-            v1[ri][ci] = srow[clampi(gx0 + cc + 1, 0, W - 1)];
+            if (ci < groups) {
+                const int cc = 2 * (lane + MATCH_TX * ci);
+                v0[ri][ci] = srow[clampi(gx0 + cc, 0, W - 1)];
+                v1[ri][ci] = srow[clampi(gx0 + cc + 1, 0, W - 1)];
+            }
         }
     }
 #pragma unroll
@@ -125,17 +135,19 @@ __device__ __forceinline__ void stage_tile(float* dst, int stride, int half, con
         float* drow = dst + rr * stride;
 #pragma unroll
         for (int ci = 0; ci < CI; ++ci) {
-            if (ci > 0 && 2 * MATCH_TX * ci >= cols) break;
-            const int ch = lane + MATCH_TX * ci;  // column pair index
-            if (2 * ch < cols) drow[ch] = to_f(v0[ri][ci]) - c;
-            if (2 * ch + 1 < cols) drow[half + ch] = to_f(v1[ri][ci]) - c;
+            if (ci < groups) {
+                const int ch = lane + MATCH_TX * ci;  // column pair index
+                drow[ch] = to_f(v0[ri][ci]) - c;
+                drow[half + ch] = to_f(v1[ri][ci]) - c;
+            }
         }
     }
 }
 
 // Stage the right statistics of rows [gy0, gy0+ROWS) x cols [gx0, gx0+cols)
 // into two split-layout LDS planes: the window mean minus c (its float value and
-// rounding remainder summed after the subtraction) and 1/sd.
+// rounding remainder summed after the subtraction) and 1/sd.  Same staging
+// scheme as stage_tile.
 template <int ROWS, int MAXCOLS>
 __device__ __forceinline__ void stage_stats(float* mc, float* is, int stride, int half,
                                             const float4* __restrict__ src, int spitch, int H, int W,
@@ -144,6 +156,7 @@ __device__ __forceinline__ void stage_stats(float* mc, float* is, int stride, in
     constexpr int RI = (ROWS + MATCH_TY - 1) / MATCH_TY;
     constexpr int CI = (MAXCOLS + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
+    const int groups = (cols + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     float4 v0[RI][CI], v1[RI][CI];
 #pragma unroll
     for (int ri = 0; ri < RI; ++ri) {
@@ -151,9 +164,11 @@ __device__ __forceinline__ void stage_stats(float* mc, float* is, int stride, in
         const float4* srow = src + (size_t)clampi(gy0 + rr, 0, H - 1) * spitch;
 #pragma unroll
         for (int ci = 0; ci < CI; ++ci) {
-            const int cc = 2 * (lane + MATCH_TX * ci);
-            v0[ri][ci] = srow[clampi(gx0 + cc, 0, W - 1)];
-            v1[ri][ci] = srow[clampi(gx0 + cc + 1, 0, W - 1)];
+            if (ci < groups) {
+                const int cc = 2 * (lane + MATCH_TX * ci);
+                v0[ri][ci] = srow[clampi(gx0 + cc, 0, W - 1)];
+                v1[ri][ci] = srow[clampi(gx0 + cc + 1, 0, W - 1)];
+            }
         }
     }
 #pragma unroll
@@ -162,12 +177,10 @@ __device__ __forceinline__ void stage_stats(float* mc, float* is, int stride, in
         if (rr >= ROWS) continue;
 #pragma unroll
         for (int ci = 0; ci < CI; ++ci) {
-            const int ch = lane + MATCH_TX * ci;
-            if (2 * ch < cols) {
+            if (ci < groups) {
+                const int ch = lane + MATCH_TX * ci;
                 mc[rr * stride + ch] = (v0[ri][ci].x - c) + v0[ri][ci].y;
                 is[rr * stride + ch] = v0[ri][ci].z;
-            }
-            if (2 * ch + 1 < cols) {
                 mc[rr * stride + half + ch] = (v1[ri][ci].x - c) + v1[ri][ci].y;
                 is[rr * stride + half + ch] = v1[ri][ci].z;
             }
