@@ -14,14 +14,22 @@
 // Flat candidates (1/sd = 0) get k1 = kL = kR = 0; clamped window reads send
 // their gradient to the edge pixel they read.
 //
-// Work split.  Same tiles, blocks and LDS staging as the forward matching
-// kernel; each thread recomputes its block's scores with the shared window sums,
-// then walks each of its pixels' window rows, forms that row's gradient values
-// in registers and adds them into LDS gradient tiles (the left tile and the
-// current right chunk) with LDS atomics.  Finished tiles are added to the
-// global gradients with hardware float atomics (tiles overlap by their window
-// halos), so the global gradients must be zeroed first.  No cost volume is
-// stored: scores are recomputed from the images and window statistics.
+// Work split.  Same tiles and LDS staging as the forward matching kernel, with
+// 8 waves per workgroup: a thread owns one pixel row of a 2x2 block (two
+// pixels).  It recomputes their scores with window sums shared by the two
+// columns, then walks their window rows, sums both pixels' gradient values in
+// registers over the union of their windows and adds them into LDS gradient
+// tiles (the left tile and the current right chunk).  Finished tiles are added
+// to the global gradients with hardware float atomics (tiles overlap by their
+// window halos), so the global gradients must be zeroed first.  No cost volume
+// is stored: scores are recomputed from the images and window statistics.
+//
+// LDS accumulation is in 64-bit fixed point: integer LDS atomics are several
+// tens of times faster than float ones on this chip.  Per chunk the workgroup
+// bounds every value it will add (from the ranges of the staged images and the
+// largest gradient coefficients) and picks a power-of-two scale that maps that
+// bound below 2^30, so each added value rounds to an int32 with a relative
+// resolution of about 2^-30 of the bound and the 64-bit sums cannot overflow.
 #pragma once
 
 #include "match_impl.hpp"
@@ -51,32 +59,98 @@ struct BackSmem {
     using G = Geo<NW, CH, 1>;
     float Ls[G::LROWS * G::LSTRIDE];
     float Rs[G::LROWS * G::RSTRIDE];
-    float GLs[G::LROWS * G::LSTRIDE];   // left gradient tile (same layout as Ls)
-    float GRs[G::LROWS * G::RSTRIDE];   // right gradient tile of the current chunk
+    long long GLs[G::LROWS * G::LSTRIDE];  // left gradient tile (same layout as Ls), fixed point
+    long long GRs[G::LROWS * G::RSTRIDE];  // right gradient tile of the current chunk, fixed point
     int lo, hi;
     unsigned mask;
+    int lmin, lmax, rmin, rmax;            // value ranges of the staged tiles (ordered float keys)
+    unsigned kmax[5];                      // largest coefficient magnitudes (float bits)
 };
 
-__device__ __forceinline__ void lds_add(float* p, float v) { atomicAdd(p, v); }
+// Order-preserving int key of a float (signed comparison), and its inverse.
+__device__ __forceinline__ int fkey(float f)
+{
+    const int b = __float_as_int(f);
+    return b >= 0 ? b : b ^ 0x7fffffff;
+}
+__device__ __forceinline__ float fval(int k) { return __int_as_float(k >= 0 ? k : k ^ 0x7fffffff); }
 
-// Add an LDS tile in split layout to a global image with float atomics;
-// logical column c of LDS row rr maps to global (clamp(gy0 + rr), clamp(gx0 + c)).
-__device__ __forceinline__ void flush_tile(const float* tile, int stride, int half, int rows, int cols,
+constexpr int BACK_WAVES = 8;
+constexpr int BACK_THREADS = BACK_WAVES * MATCH_TX;
+
+// Add v (|v * scale| <= 2^30) to a fixed-point LDS cell.
+__device__ __forceinline__ void lds_add(long long* p, float v, float scale)
+{
+    const int q = (int)rintf(v * scale);
+    if (q != 0) atomicAdd((unsigned long long*)p, (unsigned long long)(long long)q);
+}
+
+// Add a fixed-point LDS tile in split layout to a global image with float
+// atomics (value = cell / scale); logical column c of LDS row rr maps to global
+// (clamp(gy0 + rr), clamp(gx0 + c)).  The tile is zeroed behind the reads.
+__device__ __forceinline__ void flush_tile(long long* tile, int stride, int half, int rows, int cols, double inv_scale,
                                            float* dst, int dpitch, int H, int W, int gy0, int gx0)
 {
     const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
-    for (int rr = wave; rr < rows; rr += MATCH_TY) {
+    for (int rr = wave; rr < rows; rr += BACK_WAVES) {
         float* drow = dst + (size_t)clampi(gy0 + rr, 0, H - 1) * dpitch;
         for (int c = lane; c < cols; c += MATCH_TX) {
-            const float v = tile[rr * stride + split_pos(c, half)];
-            if (v != 0.f) unsafeAtomicAdd(drow + clampi(gx0 + c, 0, W - 1), v);
+            long long* cell = tile + rr * stride + split_pos(c, half);
+            const long long v = *cell;
+            if (v != 0) {
+                unsafeAtomicAdd(drow + clampi(gx0 + c, 0, W - 1), (float)((double)v * inv_scale));
+                *cell = 0;
+            }
         }
     }
 }
 
-__device__ __forceinline__ void zero_lds(float* p, int count)
+__device__ __forceinline__ void zero_lds(long long* p, int count)
 {
-    for (int i = threadIdx.x; i < count; i += MATCH_THREADS) p[i] = 0.f;
+    for (int i = threadIdx.x; i < count; i += BACK_THREADS) p[i] = 0;
+}
+
+// Min and max over the logical region rows x cols of a split-layout LDS tile,
+// folded into the workgroup's keys.
+__device__ __forceinline__ void tile_range(const float* t, int stride, int half, int rows, int cols, int* kmin,
+                                           int* kmax)
+{
+    float mn = 3.4e38f, mx = -3.4e38f;
+    for (int i = threadIdx.x; i < rows * cols; i += BACK_THREADS) {
+        const int r = i / cols, c = i - r * cols;
+        const float v = t[r * stride + split_pos(c, half)];
+        mn = fminf(mn, v);
+        mx = fmaxf(mx, v);
+    }
+    atomicMin(kmin, fkey(mn));
+    atomicMax(kmax, fkey(mx));
+}
+
+// Window cross sums of one pixel row's two pixels (columns j0, j0 + 1) for NC
+// candidate slots: per window row the products of the 2n interior columns are
+// shared by both pixels, plus one edge product each.  Same operands and
+// centring as the forward's block sums.
+template <int NW, int NC, class G>
+__device__ __forceinline__ void row_sums(const float* __restrict__ Ls, const float* __restrict__ Rs,
+                                         int lrow0, int ltx, int pa, int pb, float ca, float (&S)[2][NC])
+{
+    constexpr int WN = G::WN;
+#pragma unroll
+    for (int s = 0; s < NC; ++s) S[0][s] = S[1][s] = 0.f;
+#pragma unroll 1
+    for (int y = 0; y < WN - 1; ++y) {
+        float l[WN], r[WN + NC - 1];
+        load_row<NW, NC, G::LSTRIDE, G::LHALF, G::RSTRIDE>(Ls, Rs, lrow0 + y, ltx, pa, pb, ca, l, r);
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const int o = NC - 1 - s;
+            float c = 0.f;
+#pragma unroll
+            for (int t = 1; t < WN - 1; ++t) c = fmaf(l[t], r[t + o], c);
+            S[0][s] += fmaf(l[0], r[o], c);
+            S[1][s] += fmaf(l[WN - 1], r[WN - 1 + o], c);
+        }
+    }
 }
 
 template <int NW, int NC>
@@ -90,45 +164,51 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
     constexpr int RU = WS + NC - 1;         // right values a pixel's window row touches
     static_assert((MSIBM_MAX_DISP - 1) / STEP < 32, "chunk mask must hold every chunk");
 
-    const int tx = threadIdx.x & (MATCH_TX - 1), ty = threadIdx.x / MATCH_TX;
+    const int tx = threadIdx.x & (MATCH_TX - 1), w = threadIdx.x / MATCH_TX;
+    const int ty = w >> 1, pr = w & 1;      // block row, pixel row within the block
     const int x0 = bx * TILE_W, y0 = by * G::TH;
     const int i0 = y0 + 2 * ty, j0 = x0 + 2 * tx;
-    const bool act[4] = {i0 < a.H && j0 < a.W, i0 < a.H && j0 + 1 < a.W, i0 + 1 < a.H && j0 < a.W,
-                         i0 + 1 < a.H && j0 + 1 < a.W};
-    const int ia = min(i0, a.H - 1), ib = min(i0 + 1, a.H - 1);
-    const int ja = min(j0, a.W - 1), jb = min(j0 + 1, a.W - 1);
-    const int ip[4] = {ia, ia, ib, ib};
-    const int jp[4] = {ja, jb, ja, jb};
+    const bool blk = i0 < a.H && j0 < a.W;  // the block has pixels
+    const int ii = min(i0 + pr, a.H - 1);
+    const bool act[2] = {i0 + pr < a.H && j0 < a.W, i0 + pr < a.H && j0 + 1 < a.W};
+    const int jp[2] = {min(j0, a.W - 1), min(j0 + 1, a.W - 1)};
 
-    // candidate intervals (as in the forward soft level)
-    const int dh = clampi(2 * (int)a.prior[(size_t)(ia >> 1) * a.ppitch + (ja >> 1)], 0, a.D - 1);
+    // candidate intervals (as in the forward soft level); both pixel rows of a
+    // block share the prior
+    const int dh = clampi(2 * (int)a.prior[(size_t)(min(i0, a.H - 1) >> 1) * a.ppitch + (jp[0] >> 1)], 0, a.D - 1);
     const int zs = (dh <= j0) ? dh - a.rs : j0 + 2 - NC;
-    int lo[4], hi[4];
+    int lo[2], hi[2];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-        const int c = min(dh, jp[p]);
-        lo[p] = max(0, c - a.rs);
-        hi[p] = min(min(a.D - 1, jp[p]), c + a.rs);
+    for (int pc = 0; pc < 2; ++pc) {
+        const int c = min(dh, jp[pc]);
+        lo[pc] = max(0, c - a.rs);
+        hi[pc] = min(min(a.D - 1, jp[pc]), c + a.rs);
     }
     const int cy = min(y0 + G::TH / 2, a.H - 1), cx = min(x0 + TILE_W / 2, a.W - 1);
     const float cR = a.R[(size_t)cy * a.pitch + cx];
 
-    stage_tile<float, G::LROWS, G::LCOLS>(sm.Ls, G::LSTRIDE, G::LHALF, a.L, a.pitch, a.H, a.W, y0 - NW,
-                                          x0 - NW, G::LCOLS, 0.f);
+    stage_tile<float, G::LROWS, G::LCOLS, BACK_WAVES>(sm.Ls, G::LSTRIDE, G::LHALF, a.L, a.pitch, a.H, a.W,
+                                                      y0 - NW, x0 - NW, G::LCOLS, 0.f);
     zero_lds(sm.GLs, G::LROWS * G::LSTRIDE);
+    zero_lds(sm.GRs, G::LROWS * G::RSTRIDE);
     if (threadIdx.x == 0) {
         sm.lo = 0x7fffffff;
         sm.hi = -0x7fffffff;
         sm.mask = 0u;
+        sm.lmin = 0x7fffffff;
+        sm.lmax = -0x7fffffff - 1;
     }
     __syncthreads();
-    if (act[0]) {
+    if (blk) {
         atomicMin(&sm.lo, zs);
         atomicMax(&sm.hi, zs);
     }
+    tile_range(sm.Ls, G::LSTRIDE, G::LHALF, G::LROWS, G::LCOLS, &sm.lmin, &sm.lmax);
     __syncthreads();
     const int zlo = sm.lo, zhi = sm.hi;
-    if (act[0]) atomicOr(&sm.mask, 1u << ((zs - zlo) / STEP));
+    // |l - ca| <= the left tile's range (ca is a window mean inside it)
+    const float lrange = fval(sm.lmax) - fval(sm.lmin);
+    if (blk) atomicOr(&sm.mask, 1u << ((zs - zlo) / STEP));
     __syncthreads();
     const unsigned mask = sm.mask;
 
@@ -136,170 +216,204 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
         if (!((mask >> ci) & 1u)) continue;
         const int ztop = min(zc + CH - 1, zhi + NC - 1);
         const int rcols = TILE_W + 2 * NW + (ztop - zc);
-        if (zc != zlo) __syncthreads();
-        stage_tile<float, G::LROWS, G::RCOLS>(sm.Rs, G::RSTRIDE, G::RHALF, a.R, a.pitch, a.H, a.W, y0 - NW,
-                                              x0 - NW - ztop, rcols, cR);
-        zero_lds(sm.GRs, G::LROWS * G::RSTRIDE);
+        if (zc != zlo) __syncthreads();  // previous chunk flushed
+        stage_tile<float, G::LROWS, G::RCOLS, BACK_WAVES>(sm.Rs, G::RSTRIDE, G::RHALF, a.R, a.pitch, a.H, a.W,
+                                                          y0 - NW, x0 - NW - ztop, rcols, cR);
+        if (threadIdx.x == 0) {
+            sm.rmin = 0x7fffffff;
+            sm.rmax = -0x7fffffff - 1;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) sm.kmax[q] = 0u;
+        }
         __syncthreads();
 
-        if (act[0] && zs >= zc && zs < zc + STEP) {
-            // --- recompute the block's scores
-            float4 stl[4];
+        const bool part = blk && (act[0] || act[1]) && zs >= zc && zs < zc + STEP;
+        const float ca = a.statL[(size_t)ii * a.spitch + jp[0]].x;
+        const int rcol0 = 2 * tx + (ztop - zs) - (NC - 1);
+        // right-value base offsets (split layout) for logical column rcol0 + u
+        int pa, pb;
+        if ((rcol0 & 1) == 0) {
+            pa = rcol0 >> 1;
+            pb = G::RHALF + (rcol0 >> 1);
+        } else {
+            pa = G::RHALF + (rcol0 >> 1);
+            pb = (rcol0 + 1) >> 1;
+        }
+        // per pixel: soft-argmax derivative and the gradient coefficients; the
+        // two pixels' right coefficients summed over the union of their windows
+        // (right offset u of pixel pc is union column u + pc)
+        float k1[2][NC], kl[2], cl[2], qb[RU + 1], qc[RU + 1];
 #pragma unroll
-            for (int p = 0; p < 4; ++p) stl[p] = a.statL[(size_t)ip[p] * a.spitch + jp[p]];
-            const float ca = stl[0].x;
-            float S[4][NC];
-            const int rcol0 = 2 * tx + (ztop - zs) - (NC - 1);
-            window_sums<NW, NC, G>(sm.Ls, sm.Rs, 2 * ty, tx, rcol0, ca, S);
-            // right-value base offsets (split layout) for logical column rcol0 + u
-            int pa, pb;
-            if ((rcol0 & 1) == 0) {
-                pa = rcol0 >> 1;
-                pb = G::RHALF + (rcol0 >> 1);
-            } else {
-                pa = G::RHALF + (rcol0 >> 1);
-                pb = (rcol0 + 1) >> 1;
-            }
-            // one pixel row at a time; its two pixels' contributions are summed in
-            // registers over the union of their windows (WS + 1 left and RU + 1
-            // right columns per row) before they are added into LDS
+        for (int u = 0; u <= RU; ++u) {
+            qb[u] = 0.f;
+            qc[u] = 0.f;
+        }
 #pragma unroll
-            for (int pr = 0; pr < 2; ++pr) {
-                float k1[2][NC], kl[2], cl[2], qb[RU + 1], qc[RU + 1];
+        for (int pc = 0; pc < 2; ++pc) {
+            kl[pc] = 0.f;
+            cl[pc] = 0.f;
 #pragma unroll
-                for (int u = 0; u <= RU; ++u) {
-                    qb[u] = 0.f;
-                    qc[u] = 0.f;
+            for (int s = 0; s < NC; ++s) k1[pc][s] = 0.f;
+        }
+        if (part) {
+            float S[2][NC];
+            row_sums<NW, NC, G>(sm.Ls, sm.Rs, 2 * ty + pr, tx, pa, pb, ca, S);
+#pragma unroll
+            for (int pc = 0; pc < 2; ++pc) {
+                if (!act[pc]) continue;  // contributes nothing
+                const float4 stl = a.statL[(size_t)ii * a.spitch + jp[pc]];
+                const float dl = (stl.x - ca) + stl.y;  // mu_l - ca
+                const float invl = stl.z;
+                // right statistics of this pixel's candidates: column jp - z
+                const float4* srow = a.statR + (size_t)ii * a.spitch;
+                float mr[NC], invr[NC], rho[NC];
+                bool ok[NC];
+                float best = -3.f;
+#pragma unroll
+                for (int s = 0; s < NC; ++s) {
+                    const int z = zs + s;
+                    const float4 st = srow[clampi(jp[pc] - z, 0, a.W - 1)];
+                    mr[s] = (st.x - cR) + st.y;  // mu_r - cR
+                    invr[s] = st.z;
+                    const float C = fmaf(-Nf * dl, mr[s], S[pc][s]);
+                    float rr = C * invl * invr[s];
+                    rr = fminf(fmaxf(rr, -1.f), 1.f);
+                    ok[s] = (z >= lo[pc]) && (z <= hi[pc]);
+                    rho[s] = rr;
+                    if (ok[s] && rr > best) best = rr;
                 }
+                float e[NC], se = 0.f, sz = 0.f;
 #pragma unroll
-                for (int pc = 0; pc < 2; ++pc) {
-                    const int p = 2 * pr + pc;
-                    kl[pc] = 0.f;
-                    cl[pc] = 0.f;
-#pragma unroll
-                    for (int s = 0; s < NC; ++s) k1[pc][s] = 0.f;
-                    if (!act[p]) continue;  // contributes nothing
-                    const float dl = (stl[p].x - ca) + stl[p].y;  // mu_l - ca
-                    const float invl = stl[p].z;
-                    // right statistics of this pixel's candidates: column jp - z
-                    const float4* srow = a.statR + (size_t)ip[p] * a.spitch;
-                    float mr[NC], invr[NC], rho[NC];
-                    bool ok[NC];
-                    float best = -3.f;
-#pragma unroll
-                    for (int s = 0; s < NC; ++s) {
-                        const int z = zs + s;
-                        const float4 st = srow[clampi(jp[p] - z, 0, a.W - 1)];
-                        mr[s] = (st.x - cR) + st.y;  // mu_r - cR
-                        invr[s] = st.z;
-                        const float C = fmaf(-Nf * dl, mr[s], S[p][s]);
-                        float rr = C * invl * invr[s];
-                        rr = fminf(fmaxf(rr, -1.f), 1.f);
-                        ok[s] = (z >= lo[p]) && (z <= hi[p]);
-                        rho[s] = rr;
-                        if (ok[s] && rr > best) best = rr;
-                    }
-                    // soft-argmax and its derivative
-                    float e[NC], se = 0.f, sz = 0.f;
-#pragma unroll
-                    for (int s = 0; s < NC; ++s) {
-                        e[s] = ok[s] ? __expf((rho[s] - best) * a.inv_tau) : 0.f;
-                        se += e[s];
-                        sz = fmaf(e[s], (float)(zs + s), sz);
-                    }
-                    const float ds = sz / se;
-                    const float gpx = a.g[(size_t)ip[p] * a.gpitch + jp[p]];
-                    const float gs = gpx * a.inv_tau / se;
-                    float k2r[NC], klp = 0.f, clp = 0.f;
-#pragma unroll
-                    for (int s = 0; s < NC; ++s) {
-                        const float gz = gs * e[s] * ((float)(zs + s) - ds);
-                        k1[pc][s] = gz * invl * invr[s];
-                        const float kls = gz * rho[s] * invl * invl;
-                        k2r[s] = gz * rho[s] * invr[s] * invr[s];
-                        klp += kls;
-                        clp = fmaf(-k1[pc][s], mr[s], clp);
-                    }
-                    kl[pc] = klp;
-                    cl[pc] = fmaf(klp, dl, clp);
-                    // right offsets u of this pixel are union columns u + pc:
-                    // slots touching them and their summed coefficients
-#pragma unroll
-                    for (int u = 0; u < RU; ++u) {
-#pragma unroll
-                        for (int s = 0; s < NC; ++s) {
-                            const int b = u - (NC - 1 - s);
-                            if (b >= 0 && b < WS) {
-                                qb[u + pc] += k2r[s];
-                                qc[u + pc] += fmaf(k2r[s], mr[s], -k1[pc][s] * dl);
-                            }
-                        }
-                    }
+                for (int s = 0; s < NC; ++s) {
+                    e[s] = ok[s] ? __expf((rho[s] - best) * a.inv_tau) : 0.f;
+                    se += e[s];
+                    sz = fmaf(e[s], (float)(zs + s), sz);
                 }
-                float k1s[NC];
+                const float ds = sz / se;
+                const float gpx = a.g[(size_t)ii * a.gpitch + jp[pc]];
+                const float gs = gpx * a.inv_tau / se;
+                float k2r[NC], klp = 0.f, clp = 0.f;
 #pragma unroll
-                for (int s = 0; s < NC; ++s) k1s[s] = k1[0][s] + k1[1][s];
-                const float kls = kl[0] + kl[1], cls = cl[0] + cl[1];
-                // window rows of this pixel row
-#pragma unroll 1
-                for (int y = 0; y < WS; ++y) {
-                    const int row = 2 * ty + pr + y;
-                    const float* lr_ = sm.Ls + row * G::LSTRIDE + tx;
-                    const float* rr_ = sm.Rs + row * G::RSTRIDE;
-                    float* glr = sm.GLs + row * G::LSTRIDE + tx;
-                    float* grr = sm.GRs + row * G::RSTRIDE;
-                    float l[WS + 1], r[RU + 1];
+                for (int s = 0; s < NC; ++s) {
+                    const float gz = gs * e[s] * ((float)(zs + s) - ds);
+                    k1[pc][s] = gz * invl * invr[s];
+                    const float kls = gz * rho[s] * invl * invl;
+                    k2r[s] = gz * rho[s] * invr[s] * invr[s];
+                    klp += kls;
+                    clp = fmaf(-k1[pc][s], mr[s], clp);
+                }
+                kl[pc] = klp;
+                cl[pc] = fmaf(klp, dl, clp);
 #pragma unroll
-                    for (int t = 0; t <= WS; ++t) l[t] = lr_[(t & 1) ? G::LHALF + (t >> 1) : (t >> 1)] - ca;
+                for (int u = 0; u < RU; ++u) {
 #pragma unroll
-                    for (int v = 0; v <= RU; ++v) r[v] = (v & 1) ? rr_[pb + (v >> 1)] : rr_[pa + (v >> 1)];
-                    // left gradient at union column t: pixel 0 covers t <= WS - 1,
-                    // pixel 1 covers t >= 1 (both fold into compile-time choices)
-#pragma unroll
-                    for (int t = 0; t <= WS; ++t) {
-                        const bool v0 = t <= WS - 1, v1 = t >= 1;
-                        const float klt = (v0 && v1) ? kls : (v0 ? kl[0] : kl[1]);
-                        const float clt = (v0 && v1) ? cls : (v0 ? cl[0] : cl[1]);
-                        float acc = fmaf(-klt, l[t], clt);
-#pragma unroll
-                        for (int s = 0; s < NC; ++s) {
-                            const float c = (v0 && v1) ? k1s[s] : (v0 ? k1[0][s] : k1[1][s]);
-                            acc = fmaf(c, r[t + NC - 1 - s], acc);
+                    for (int s = 0; s < NC; ++s) {
+                        const int b = u - (NC - 1 - s);
+                        if (b >= 0 && b < WS) {
+                            qb[u + pc] += k2r[s];
+                            qc[u + pc] += fmaf(k2r[s], mr[s], -k1[pc][s] * dl);
                         }
-                        lds_add(glr + ((t & 1) ? G::LHALF + (t >> 1) : (t >> 1)), acc);
-                    }
-                    // right gradient at union column v: slot s pairs it with left
-                    // union column v - (NC - 1 - s), which pixel pc covers when that
-                    // column lies in [pc, WS - 1 + pc]
-#pragma unroll
-                    for (int v = 0; v <= RU; ++v) {
-                        float acc = fmaf(-qb[v], r[v], qc[v]);
-#pragma unroll
-                        for (int s = 0; s < NC; ++s) {
-                            const int t = v - (NC - 1 - s);
-                            const bool v0 = t >= 0 && t <= WS - 1, v1 = t >= 1 && t <= WS;
-                            if (v0 || v1) {
-                                const float c = (v0 && v1) ? k1s[s] : (v0 ? k1[0][s] : k1[1][s]);
-                                acc = fmaf(c, l[t], acc);
-                            }
-                        }
-                        lds_add(grr + ((v & 1) ? pb + (v >> 1) : pa + (v >> 1)), acc);
                     }
                 }
             }
         }
+        float k1s[NC], k1a = 0.f;
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            k1s[s] = k1[0][s] + k1[1][s];
+            k1a += fabsf(k1[0][s]) + fabsf(k1[1][s]);
+        }
+        const float kls = kl[0] + kl[1], cls = cl[0] + cl[1];
+        float qba = 0.f, qca = 0.f;
+#pragma unroll
+        for (int u = 0; u <= RU; ++u) {
+            qba = fmaxf(qba, fabsf(qb[u]));
+            qca = fmaxf(qca, fabsf(qc[u]));
+        }
+        // workgroup maxima of the coefficient magnitudes and the right range
+        tile_range(sm.Rs, G::RSTRIDE, G::RHALF, G::LROWS, rcols, &sm.rmin, &sm.rmax);
+        if (part) {
+            atomicMax(&sm.kmax[0], __float_as_uint(fabsf(kl[0]) + fabsf(kl[1])));
+            atomicMax(&sm.kmax[1], __float_as_uint(fabsf(cl[0]) + fabsf(cl[1])));
+            atomicMax(&sm.kmax[2], __float_as_uint(k1a));
+            atomicMax(&sm.kmax[3], __float_as_uint(qba));
+            atomicMax(&sm.kmax[4], __float_as_uint(qca));
+        }
         __syncthreads();
-        flush_tile(sm.GRs, G::RSTRIDE, G::RHALF, G::LROWS, rcols, a.gR, a.gpitch, a.H, a.W, y0 - NW,
+        // every added value: left |kl l + cl + sum k1 r| <= KL Lr + CL + K1 Rr,
+        // right |qb r + qc + sum k1 l| <= QB Rr + QC + K1 Lr (r centred on cR, a
+        // value of the right tile, so |r| <= its range)
+        const float rrange = fmaxf(fval(sm.rmax) - fval(sm.rmin), fmaxf(fabsf(fval(sm.rmax)), fabsf(fval(sm.rmin))));
+        const float KL = __uint_as_float(sm.kmax[0]), CL = __uint_as_float(sm.kmax[1]),
+                    K1 = __uint_as_float(sm.kmax[2]), QB = __uint_as_float(sm.kmax[3]),
+                    QC = __uint_as_float(sm.kmax[4]);
+        const float bound = 2.f * fmaxf(KL * lrange + CL + K1 * rrange, QB * rrange + QC + K1 * lrange);
+        int be = 0;
+        frexpf(bound, &be);  // bound < 2^be
+        const int sh = (bound > 0.f && isfinite(bound)) ? 30 - be : 0;
+        const float scale = ldexpf(1.f, sh);
+        const double inv_scale = ldexp(1.0, -sh);
+
+        if (part && bound > 0.f && isfinite(bound)) {
+            // window rows of the pixel row
+#pragma unroll 1
+            for (int y = 0; y < WS; ++y) {
+                const int row = 2 * ty + pr + y;
+                const float* lr_ = sm.Ls + row * G::LSTRIDE + tx;
+                const float* rr_ = sm.Rs + row * G::RSTRIDE;
+                long long* glr = sm.GLs + row * G::LSTRIDE + tx;
+                long long* grr = sm.GRs + row * G::RSTRIDE;
+                float l[WS + 1], r[RU + 1];
+#pragma unroll
+                for (int t = 0; t <= WS; ++t) l[t] = lr_[(t & 1) ? G::LHALF + (t >> 1) : (t >> 1)] - ca;
+#pragma unroll
+                for (int v = 0; v <= RU; ++v) r[v] = (v & 1) ? rr_[pb + (v >> 1)] : rr_[pa + (v >> 1)];
+                // left gradient at union column t: pixel 0 covers t <= WS - 1,
+                // pixel 1 covers t >= 1 (compile-time choices once unrolled)
+#pragma unroll
+                for (int t = 0; t <= WS; ++t) {
+                    const bool v0 = t <= WS - 1, v1 = t >= 1;
+                    const float klt = (v0 && v1) ? kls : (v0 ? kl[0] : kl[1]);
+                    const float clt = (v0 && v1) ? cls : (v0 ? cl[0] : cl[1]);
+                    float acc = fmaf(-klt, l[t], clt);
+#pragma unroll
+                    for (int s = 0; s < NC; ++s) {
+                        const float c = (v0 && v1) ? k1s[s] : (v0 ? k1[0][s] : k1[1][s]);
+                        acc = fmaf(c, r[t + NC - 1 - s], acc);
+                    }
+                    lds_add(glr + ((t & 1) ? G::LHALF + (t >> 1) : (t >> 1)), acc, scale);
+                }
+                // right gradient at union column v: slot s pairs it with left union
+                // column v - (NC - 1 - s), which pixel pc covers when that column
+                // lies in [pc, WS - 1 + pc]
+#pragma unroll
+                for (int v = 0; v <= RU; ++v) {
+                    float acc = fmaf(-qb[v], r[v], qc[v]);
+#pragma unroll
+                    for (int s = 0; s < NC; ++s) {
+                        const int t = v - (NC - 1 - s);
+                        const bool v0 = t >= 0 && t <= WS - 1, v1 = t >= 1 && t <= WS;
+                        if (v0 || v1) {
+                            const float c = (v0 && v1) ? k1s[s] : (v0 ? k1[0][s] : k1[1][s]);
+                            acc = fmaf(c, l[t], acc);
+                        }
+                    }
+                    lds_add(grr + ((v & 1) ? pb + (v >> 1) : pa + (v >> 1)), acc, scale);
+                }
+            }
+        }
+        __syncthreads();
+        // both tiles carry this chunk's scale: flush (and clear) them now
+        flush_tile(sm.GRs, G::RSTRIDE, G::RHALF, G::LROWS, rcols, inv_scale, a.gR, a.gpitch, a.H, a.W, y0 - NW,
                    x0 - NW - ztop);
+        flush_tile(sm.GLs, G::LSTRIDE, G::LHALF, G::LROWS, G::LCOLS, inv_scale, a.gL, a.gpitch, a.H, a.W, y0 - NW,
+                   x0 - NW);
     }
-    __syncthreads();
-    flush_tile(sm.GLs, G::LSTRIDE, G::LHALF, G::LROWS, G::LCOLS, a.gL, a.gpitch, a.H, a.W, y0 - NW,
-               x0 - NW);
-    __syncthreads();
+    __syncthreads();  // LDS may be reused by the caller's next tile
 }
 
 template <int NW, int NC>
-__global__ __launch_bounds__(MATCH_THREADS) void backward_kernel(BackArgs a)
+__global__ __launch_bounds__(BACK_THREADS) void backward_kernel(BackArgs a)
 {
     __shared__ BackSmem<NW, BACK_CHUNK> sm;
     backward_tile<NW, NC>(a, blockIdx.x, blockIdx.y, sm);
@@ -310,10 +424,10 @@ static hipError_t dispatch_backward(int nc, const BackArgs& a, hipStream_t s)
 {
     dim3 grid((a.W + TILE_W - 1) / TILE_W, (a.H + TILE_H1 - 1) / TILE_H1, 1);
     switch (nc) {
-        case 3: hipLaunchKernelGGL((backward_kernel<NW, 3>), grid, dim3(MATCH_THREADS), 0, s, a); break;
-        case 5: hipLaunchKernelGGL((backward_kernel<NW, 5>), grid, dim3(MATCH_THREADS), 0, s, a); break;
-        case 7: hipLaunchKernelGGL((backward_kernel<NW, 7>), grid, dim3(MATCH_THREADS), 0, s, a); break;
-        case 9: hipLaunchKernelGGL((backward_kernel<NW, 9>), grid, dim3(MATCH_THREADS), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((backward_kernel<NW, 3>), grid, dim3(BACK_THREADS), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((backward_kernel<NW, 5>), grid, dim3(BACK_THREADS), 0, s, a); break;
+        case 7: hipLaunchKernelGGL((backward_kernel<NW, 7>), grid, dim3(BACK_THREADS), 0, s, a); break;
+        case 9: hipLaunchKernelGGL((backward_kernel<NW, 9>), grid, dim3(BACK_THREADS), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -321,7 +435,7 @@ static hipError_t dispatch_backward(int nc, const BackArgs& a, hipStream_t s)
 
 // Backward tiles of several pairs in one launch (level 0 of each pair).
 template <int NW, int NC>
-__global__ __launch_bounds__(MATCH_THREADS) void backward_multi_kernel(MultiArgs a)
+__global__ __launch_bounds__(BACK_THREADS) void backward_multi_kernel(MultiArgs a)
 {
     __shared__ BackSmem<NW, BACK_CHUNK> sm;
     const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
@@ -334,10 +448,10 @@ static hipError_t dispatch_backward_multi(int nc, const MultiArgs& a, int blocks
 {
     if (blocks < 1 || a.nseg < 1) return hipErrorInvalidValue;
     switch (nc) {
-        case 3: hipLaunchKernelGGL((backward_multi_kernel<NW, 3>), dim3(blocks), dim3(MATCH_THREADS), 0, s, a); break;
-        case 5: hipLaunchKernelGGL((backward_multi_kernel<NW, 5>), dim3(blocks), dim3(MATCH_THREADS), 0, s, a); break;
-        case 7: hipLaunchKernelGGL((backward_multi_kernel<NW, 7>), dim3(blocks), dim3(MATCH_THREADS), 0, s, a); break;
-        case 9: hipLaunchKernelGGL((backward_multi_kernel<NW, 9>), dim3(blocks), dim3(MATCH_THREADS), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((backward_multi_kernel<NW, 3>), dim3(blocks), dim3(BACK_THREADS), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((backward_multi_kernel<NW, 5>), dim3(blocks), dim3(BACK_THREADS), 0, s, a); break;
+        case 7: hipLaunchKernelGGL((backward_multi_kernel<NW, 7>), dim3(blocks), dim3(BACK_THREADS), 0, s, a); break;
+        case 9: hipLaunchKernelGGL((backward_multi_kernel<NW, 9>), dim3(blocks), dim3(BACK_THREADS), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

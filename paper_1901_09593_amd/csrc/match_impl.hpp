@@ -106,18 +106,18 @@ __device__ __forceinline__ int split_pos(int c, int half) { return (c & 1) ? hal
 // and store is unconditional: clamped addresses are always valid, a half holds
 // whole groups, and columns past `cols` are never read.  All loads of the thread
 // are issued before its first LDS store so that their latencies overlap.
-template <typename T, int ROWS, int MAXCOLS>
+template <typename T, int ROWS, int MAXCOLS, int NWAVES = MATCH_TY>
 __device__ __forceinline__ void stage_tile(float* dst, int stride, int half, const T* __restrict__ src,
                                            int pitch, int H, int W, int gy0, int gx0, int cols, float c)
 {
-    constexpr int RI = (ROWS + MATCH_TY - 1) / MATCH_TY;
+    constexpr int RI = (ROWS + NWAVES - 1) / NWAVES;
     constexpr int CI = (MAXCOLS + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
     const int groups = (cols + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     T v0[RI][CI], v1[RI][CI];
 #pragma unroll
     for (int ri = 0; ri < RI; ++ri) {
-        const int rr = wave + MATCH_TY * ri;
+        const int rr = wave + NWAVES * ri;
         const T* srow = src + (size_t)clampi(gy0 + rr, 0, H - 1) * pitch;
 #pragma unroll
         for (int ci = 0; ci < CI; ++ci) {
@@ -130,7 +130,7 @@ __device__ __forceinline__ void stage_tile(float* dst, int stride, int half, con
     }
 #pragma unroll
     for (int ri = 0; ri < RI; ++ri) {
-        const int rr = wave + MATCH_TY * ri;
+        const int rr = wave + NWAVES * ri;
         if (rr >= ROWS) continue;
         float* drow = dst + rr * stride;
 #pragma unroll
