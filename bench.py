@@ -121,6 +121,24 @@ def hier_counts(torch, M, L, R, D, K, n, r, eps):
     return level_counts(torch, maps, D, K, r)
 
 
+def tune_summary(table, H, W, K):
+    """Kernel shapes the autotuner chose for the headline pair's levels, and how
+    often each shape won over every measured level shape."""
+    dims = set()
+    h, w = H, W
+    for _ in range(K):
+        dims.add((h, w))
+        h, w = (h + 1) // 2, (w + 1) // 2
+    mode = ["full", "refine", "soft"]
+    head = [{"mode": mode[t[0]], "dtype": ["u8", "f32"][t[3]], "H": t[4], "W": t[5], "Dk": t[6],
+             "variant": t[7], "us": round(t[8], 2)} for t in table if (t[4], t[5]) in dims and t[1] == 4]
+    wins = {}
+    for t in table:
+        wins[str(t[7])] = wins.get(str(t[7]), 0) + 1
+    return {"variant_bits": "1 = statistics in LDS (full search), 2 = XCD-aware tile order",
+            "headline_levels": head, "wins_over_all_shapes": wins, "shapes_measured": len(table)}
+
+
 def time_ms(torch, fn, steps, warmup):
     """Mean milliseconds per call between HIP events on the current stream."""
     for _ in range(warmup):
@@ -262,6 +280,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--sections", default="batched,fwd_bwd",
                     help="extra sections beside the headline step: batched, fwd_bwd, or none")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="use the default kernel shapes instead of measuring them first")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes five times")
     args = ap.parse_args()
@@ -286,6 +306,8 @@ def main():
         return
     sections = [s for s in args.sections.split(",") if s and s != "none"]
 
+    if not args.no_tune:
+        msibm.autotune(True)  # first use of each level shape measures its kernel shapes
     p, cfg = synth.workload("mid1436")
     H, W, D, K, n, r, eps = cfg.height, cfg.width, cfg.max_disp, cfg.levels, cfg.half_window, \
         cfg.refine_radius, cfg.var_eps
@@ -409,6 +431,7 @@ def main():
                              "evals_per_s": flat_evals / (flat_ms * 1e-3),
                              "hierarchical_speedup": flat_ms / ms_step},
         "kernels": kernels,
+        "autotune": tune_summary(msibm.autotune_table(), H, W, K),
         "roofline": roof,
         **extra,
         "cpu_baseline": cpu,

@@ -104,13 +104,35 @@ const char* msibm_last_error(void);
 const char* msibm_version(void);
 
 /*
- * msibm_force_variant - pin the matching kernel's shape for every later call in
- * this process (for tests and tuning): 1 = right window statistics staged in
- * LDS with the right tile, 0 = read by each thread from global memory; -1
- * restores the automatic choice.  Results do not depend on the variant.
- * Errors: INVALID_ARG (outside -1..1).
+ * Kernel shapes of the matching kernel (bits of a variant):
+ *   1  right window statistics staged in LDS with the right tile (full
+ *      searches only; otherwise each thread reads them from global memory),
+ *   2  XCD-aware tile order (each of the 8 XCDs takes one contiguous run of
+ *      tiles, so neighbouring tiles share their halos in one L2).
+ * Results do not depend on the shape.
+ *
+ * msibm_force_variant - pin the shape for every later call in this process
+ * (bits that do not apply to a launch are ignored); -1 restores the automatic
+ * choice.  Errors: INVALID_ARG (outside -1..3).
  */
 msibm_status msibm_force_variant(int32_t variant);
+
+/*
+ * msibm_autotune - with enable != 0, the first launch of each matching shape
+ * (mode, n, candidates per window, dtype, H, W, D_k) not yet in the table is
+ * timed in every applicable kernel shape (one warm-up and three launches each,
+ * synchronising the caller's stream; never while the stream is being captured)
+ * and the fastest is used from then on.  cache_path (may be NULL) names a text
+ * file read now and rewritten after each new measurement, one line per shape:
+ * "mode n nc dtype H W Dk variant microseconds".  The environment variables
+ * MSIBM_AUTOTUNE=1 and MSIBM_TUNE_CACHE=<path> do the same at load time.
+ * Errors: INVALID_ARG (cache file present but not a tuning table).
+ */
+msibm_status msibm_autotune(int32_t enable, const char* cache_path);
+
+/* The tuning table as text (format above); copies at most len - 1 bytes and a
+ * terminating NUL into buf (may be NULL) and returns the full length. */
+int64_t msibm_autotune_table(char* buf, size_t len);
 
 /*
  * msibm_pyramid - the K-level Gaussian pyramid of one image (Section III).

@@ -4,12 +4,14 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstring>
 #include <string>
 #include <vector>
 
 #include "common.hpp"
 #include "msibm.h"
 #include "plan.hpp"
+#include "tune.hpp"
 
 using namespace msibm;
 
@@ -148,9 +150,28 @@ const char* msibm_version(void) { return "msibm 0.1 gfx950"; }
 
 msibm_status msibm_force_variant(int32_t variant)
 {
-    if (variant < -1 || variant > 1) return fail(MSIBM_ERR_INVALID_ARG, "variant %d outside -1..1", variant);
+    if (variant < -1 || variant > VARIANT_MASK)
+        return fail(MSIBM_ERR_INVALID_ARG, "variant %d outside -1..%d", variant, VARIANT_MASK);
     force_variant(variant);
     return ok();
+}
+
+msibm_status msibm_autotune(int32_t enable, const char* cache_path)
+{
+    std::string err;
+    if (!set_autotune(enable != 0, cache_path ? cache_path : "", &err)) return fail(MSIBM_ERR_INVALID_ARG, "%s", err.c_str());
+    return ok();
+}
+
+int64_t msibm_autotune_table(char* buf, size_t len)
+{
+    const std::string t = autotune_table();
+    if (buf && len > 0) {
+        const size_t n = t.size() < len - 1 ? t.size() : len - 1;
+        memcpy(buf, t.data(), n);
+        buf[n] = '\0';
+    }
+    return (int64_t)t.size();
 }
 
 msibm_status msibm_pyramid(const void* img, int32_t dtype, int32_t H, int32_t W, int32_t pitch,
@@ -246,8 +267,9 @@ msibm_status msibm_match_level(const void* L, const void* R, int32_t dtype, int3
     a.opitch = out_pitch;
     a.inv_tau = 0.f;
     const int mode = prior ? MODE_REFINE : MODE_FULL;
-    a.variant = pick_variant(H, W, mode);
-    e = launch_match(n, dtype, mode, prior ? slots_for_radius(r) : FULL_NC, a, s);
+    const int nc = prior ? slots_for_radius(r) : FULL_NC;
+    a.variant = select_variant(a, n, dtype, mode, nc, s);
+    e = launch_match(n, dtype, mode, nc, a, s);
     if (e != hipSuccess) return hip_fail(e, "match launch");
     return ok();
 }

@@ -45,8 +45,25 @@ struct MatchArgs {
     int variant;              // VARIANT_* bits (kernel shape chosen by the tuner)
 };
 
-// Kernel shape variants of the matching kernel.
-constexpr int VARIANT_STATS_LDS = 1;  // right statistics staged in LDS
+// Kernel shape variants of the matching kernel (bits of MatchArgs::variant).
+constexpr int VARIANT_STATS_LDS = 1;  // right statistics staged in LDS (full search only)
+constexpr int VARIANT_XCD = 2;        // XCD-aware tile order
+constexpr int VARIANT_MASK = 3;
+
+// Tile of block b in a grid of gx x gy tiles.  The hardware deals consecutive
+// workgroups round-robin to the 8 XCDs, each with its own L2; the XCD-aware
+// order gives every XCD one contiguous, row-major run of tiles, so neighbouring
+// tiles (which share window halos) meet in the same L2.
+__device__ __forceinline__ void tile_of(int variant, int* bx, int* by)
+{
+    if (!(variant & VARIANT_XCD)) return;
+    const int gx = gridDim.x, total = gx * gridDim.y;
+    const int b = *by * gx + *bx, xcd = b & 7, k = b >> 3;
+    const int per = total >> 3, rem = total & 7;
+    const int t = xcd * per + min(xcd, rem) + k;
+    *bx = t % gx;
+    *by = t / gx;
+}
 
 struct ReduceArgs {
     const void* src[2];

@@ -516,7 +516,9 @@ template <typename T, int NW, int NC, int MODE, int BY, int SL>
 __global__ __launch_bounds__(MATCH_THREADS) void match_kernel(MatchArgs a)
 {
     __shared__ MatchSmem<NW, ChunkOf<MODE>::value, BY, SL> sm;
-    match_tile<T, NW, NC, MODE, BY, SL>(a, blockIdx.x, blockIdx.y, sm);
+    int bx = blockIdx.x, by = blockIdx.y;
+    tile_of(a.variant, &bx, &by);
+    match_tile<T, NW, NC, MODE, BY, SL>(a, bx, by, sm);
 }
 
 template <typename T, int NW, int NC, int MODE, int BY>

@@ -5,6 +5,7 @@
 #include "common.hpp"
 #include "plan.hpp"
 #include "timing.hpp"
+#include "tune.hpp"
 
 #include <cstdio>
 #include <cstdlib>
@@ -35,26 +36,6 @@ hipError_t launch_match_multi(int n, int dtype, int mode, int nc, const MultiArg
         case 6: return launch_match_multi_n6(dtype, mode, nc, a, blocks, s);
     }
     return hipErrorInvalidValue;
-}
-
-// Kernel shape of the matching kernel for one level (VARIANT_* bits).
-// MSIBM_FORCE_VARIANT overrides the choice (tests and tuning).
-static int g_forced_variant = [] {
-    const char* v = getenv("MSIBM_FORCE_VARIANT");
-    return v ? atoi(v) : -1;
-}();
-
-void force_variant(int v) { g_forced_variant = v; }
-
-int pick_variant(int H, int W, int mode)
-{
-    const int forced = g_forced_variant;
-    if (forced >= 0) return forced & VARIANT_STATS_LDS;
-    (void)H;
-    (void)W;
-    // measured on MI355X: a full search reuses each staged statistics column for
-    // every candidate, a restricted search reads only a few per pixel
-    return mode == MODE_FULL ? VARIANT_STATS_LDS : 0;
 }
 
 static int hip_err(hipError_t e, const char* what, std::string* err)
@@ -152,7 +133,7 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
                  mode == MODE_FULL ? "full" : (mode == MODE_SOFT ? "soft" : "refine"), k);
         {
             TimedLaunch t(lab, s);
-            a.variant = pick_variant(a.H, a.W, mode);
+            a.variant = select_variant(a, n, k == 0 ? P.dtype : MSIBM_F32, mode, nc, s);
             e = launch_match(n, k == 0 ? P.dtype : MSIBM_F32, mode, nc, a, s);
         }
         if (e != hipSuccess) return hip_err(e, "match launch", err);

@@ -13,8 +13,6 @@ int level_dim(int v, int k);
 int level_range(int D, int k);
 int auto_levels(int D);
 size_t align_up(size_t v);
-int pick_variant(int H, int W, int mode);
-void force_variant(int v);
 
 // Workspace offsets of one pair.  Level k (k >= 1) holds both views' pyramid
 // images (float, W_k pitch); every level holds both views' window statistics

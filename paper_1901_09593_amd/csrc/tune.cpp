@@ -1,0 +1,178 @@
+// Kernel-shape selection (see tune.hpp).
+#include "tune.hpp"
+
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <tuple>
+
+namespace msibm {
+
+hipError_t launch_match(int n, int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
+
+namespace {
+
+using Key = std::tuple<int, int, int, int, int, int, int>;  // mode n nc dtype H W Dk
+struct Entry {
+    int variant;
+    float us;
+};
+
+struct Tuner {
+    std::mutex mu;
+    int forced = -1;
+    bool on = false;
+    std::string path;
+    std::map<Key, Entry> table;
+};
+
+Tuner& tuner()
+{
+    static Tuner t;
+    static bool init = [] {
+        if (const char* v = getenv("MSIBM_FORCE_VARIANT")) t.forced = atoi(v);
+        if (const char* v = getenv("MSIBM_AUTOTUNE")) {
+            std::string err;
+            const char* f = getenv("MSIBM_TUNE_CACHE");
+            t.on = atoi(v) != 0;
+            if (t.on && f) {
+                t.path = f;
+                std::ifstream in(f);
+                std::string line;
+                while (std::getline(in, line)) {
+                    std::istringstream ls(line);
+                    int m, n, nc, dt, H, W, Dk, var;
+                    float us;
+                    if (ls >> m >> n >> nc >> dt >> H >> W >> Dk >> var >> us)
+                        t.table[Key(m, n, nc, dt, H, W, Dk)] = Entry{var & VARIANT_MASK, us};
+                }
+            }
+        }
+        return true;
+    }();
+    (void)init;
+    return t;
+}
+
+// Default shapes, from measurements on MI355X: a full search reuses each staged
+// statistics column for every candidate, a restricted search reads only a few.
+int default_variant(int mode) { return mode == MODE_FULL ? VARIANT_STATS_LDS : 0; }
+
+std::string table_text(const Tuner& t)
+{
+    std::ostringstream o;
+    for (const auto& kv : t.table) {
+        const Key& k = kv.first;
+        o << std::get<0>(k) << ' ' << std::get<1>(k) << ' ' << std::get<2>(k) << ' ' << std::get<3>(k) << ' '
+          << std::get<4>(k) << ' ' << std::get<5>(k) << ' ' << std::get<6>(k) << ' ' << kv.second.variant << ' '
+          << kv.second.us << '\n';
+    }
+    return o.str();
+}
+
+void save(const Tuner& t)
+{
+    if (t.path.empty()) return;
+    std::ofstream out(t.path, std::ios::trunc);
+    out << table_text(t);
+}
+
+// Mean microseconds of three launches of shape v (after one warm-up), or a
+// negative value on a launch error.
+float time_variant(MatchArgs a, int v, int n, int dtype, int mode, int nc, hipStream_t s)
+{
+    a.variant = v;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.f;
+    if (hipEventCreate(&e1) != hipSuccess) {
+        hipEventDestroy(e0);
+        return -1.f;
+    }
+    float ms = -1.f;
+    hipError_t e = launch_match(n, dtype, mode, nc, a, s);
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    for (int i = 0; i < 3 && e == hipSuccess; ++i) e = launch_match(n, dtype, mode, nc, a, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    return e == hipSuccess ? 1e3f * ms / 3.f : -1.f;
+}
+
+}  // namespace
+
+void force_variant(int v)
+{
+    Tuner& t = tuner();
+    std::lock_guard<std::mutex> g(t.mu);
+    t.forced = v;
+}
+
+bool set_autotune(bool on, const std::string& path, std::string* err)
+{
+    Tuner& t = tuner();
+    std::lock_guard<std::mutex> g(t.mu);
+    t.on = on;
+    t.path = path;
+    if (!on || path.empty()) return true;
+    std::ifstream in(path);
+    if (!in) return true;  // created on the first measurement
+    std::string line;
+    int ln = 0;
+    while (std::getline(in, line)) {
+        ++ln;
+        if (line.empty()) continue;
+        std::istringstream ls(line);
+        int m, n, nc, dt, H, W, Dk, var;
+        float us;
+        if (!(ls >> m >> n >> nc >> dt >> H >> W >> Dk >> var >> us)) {
+            *err = path + ": line " + std::to_string(ln) + " is not a tuning entry";
+            return false;
+        }
+        t.table[Key(m, n, nc, dt, H, W, Dk)] = Entry{var & VARIANT_MASK, us};
+    }
+    return true;
+}
+
+std::string autotune_table()
+{
+    Tuner& t = tuner();
+    std::lock_guard<std::mutex> g(t.mu);
+    return table_text(t);
+}
+
+int select_variant(const MatchArgs& a, int n, int dtype, int mode, int nc, hipStream_t s)
+{
+    Tuner& t = tuner();
+    std::lock_guard<std::mutex> g(t.mu);
+    const int valid = mode == MODE_FULL ? VARIANT_MASK : VARIANT_XCD;  // statistics in LDS: full search only
+    if (t.forced >= 0) return t.forced & valid;
+    const Key key(mode, n, nc, dtype, a.H, a.W, a.Dk);
+    auto it = t.table.find(key);
+    if (it != t.table.end()) return it->second.variant & valid;
+    if (!t.on) return default_variant(mode);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
+        return default_variant(mode);
+    int best = default_variant(mode);
+    float best_us = -1.f;
+    for (int v = 0; v <= VARIANT_MASK; ++v) {
+        if (v & ~valid) continue;
+        const float us = time_variant(a, v, n, dtype, mode, nc, s);
+        if (us >= 0.f && (best_us < 0.f || us < best_us)) {
+            best_us = us;
+            best = v;
+        }
+    }
+    if (best_us >= 0.f) {
+        t.table[key] = Entry{best, best_us};
+        save(t);
+    }
+    return best;
+}
+
+}  // namespace msibm

@@ -82,6 +82,10 @@ def lib() -> ctypes.CDLL:
         L.msibm_backward.restype = _I32
         L.msibm_force_variant.argtypes = [_I32]
         L.msibm_force_variant.restype = _I32
+        L.msibm_autotune.argtypes = [_I32, ctypes.c_char_p]
+        L.msibm_autotune.restype = _I32
+        L.msibm_autotune_table.argtypes = [ctypes.c_char_p, ctypes.c_size_t]
+        L.msibm_autotune_table.restype = ctypes.c_int64
         L.msibm_timing_enable.argtypes = [_I32]
         L.msibm_timing_enable.restype = _I32
         L.msibm_timing_read.argtypes = [_I32, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
@@ -154,9 +158,27 @@ def make_config(n: int, r: int, var_eps: float, soft_radius: int = 0, tau: float
 
 
 def force_variant(v: int = -1):
-    """Pin the matching kernel shape (1: right statistics staged in LDS, 0: read
-    from global memory); -1 = automatic."""
+    """Pin the matching kernel shape (bit 1: right statistics staged in LDS for
+    full searches, bit 2: XCD-aware tile order); -1 = automatic."""
     _check(lib().msibm_force_variant(int(v)))
+
+
+def autotune(enable: bool = True, cache_path: Optional[str] = None):
+    """Measure every matching kernel shape on first use of each level shape and
+    keep the fastest (optionally persisted in a text cache)."""
+    _check(lib().msibm_autotune(1 if enable else 0, cache_path.encode() if cache_path else None))
+
+
+def autotune_table() -> List[Tuple[int, ...]]:
+    """The tuning table: (mode, n, nc, dtype, H, W, Dk, variant, microseconds)."""
+    n = lib().msibm_autotune_table(None, 0)
+    buf = ctypes.create_string_buffer(int(n) + 1)
+    lib().msibm_autotune_table(buf, len(buf))
+    rows = []
+    for line in buf.value.decode().splitlines():
+        f = line.split()
+        rows.append(tuple(int(x) for x in f[:8]) + (float(f[8]),))
+    return rows
 
 
 def timing_enable(on: bool = True):

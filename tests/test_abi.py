@@ -110,3 +110,19 @@ def test_workspace_grows_with_levels(lib):
     assert sizes[0] < sizes[1] < sizes[2]
     # stats of both views at level 0 dominate: 16 bytes per pixel
     assert sizes[0] >= 992 * 1436 * 16
+
+
+def test_autotune_cache_parsing_from_host(lib, tmp_path):
+    from paper_1901_09593_amd import msibm
+    e = msibm.lib()
+    bad = tmp_path / "bad.txt"
+    bad.write_text("not a table\n")
+    assert e.msibm_autotune(1, str(bad).encode()) == -1
+    assert b"not a tuning entry" in e.msibm_last_error()
+    good = tmp_path / "good.txt"
+    good.write_text("1 4 5 0 992 1436 256 2 38.5\n")
+    assert e.msibm_autotune(1, str(good).encode()) == 0
+    rows = msibm.autotune_table()
+    assert (1, 4, 5, 0, 992, 1436, 256, 2) in [r[:8] for r in rows]
+    assert e.msibm_autotune(0, None) == 0
+    assert e.msibm_force_variant(4) == -1 and e.msibm_force_variant(3) == 0 and e.msibm_force_variant(-1) == 0

@@ -235,7 +235,7 @@ def test_soft_level_parity_diff960_crop(M):
                 ref=(dh_o, C_o, C2_o))
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 def test_every_kernel_variant_gives_identical_results(M, variant):
     p, cfg = synth.workload("small320")
     K, n, r, D, eps = cfg.levels, cfg.half_window, cfg.refine_radius, cfg.max_disp, cfg.var_eps
@@ -252,3 +252,34 @@ def test_every_kernel_variant_gives_identical_results(M, variant):
     assert torch.equal(ref["disp"], got["disp"]) and torch.equal(ref["cost"], got["cost"])
     assert torch.equal(ref["prior1"], got["prior1"])
     assert torch.equal(flat_ref[0], flat[0]) and torch.equal(flat_ref[1], flat[1])
+
+
+def test_autotune_picks_per_shape_and_keeps_results(M, tmp_path):
+    """The autotuner measures each level shape once, records it in its cache
+    file, reloads it, and its choices leave every output unchanged."""
+    p, cfg = synth.workload("small320")
+    K, n, r, D, eps = cfg.levels, cfg.half_window, cfg.refine_radius, cfg.max_disp, cfg.var_eps
+    Lg, Rg = dev(p.left), dev(p.right)
+    ref = M.disparity(Lg, Rg, D, K, n, r, eps, with_prior1=True)
+    cache = tmp_path / "tune.txt"
+    try:
+        M.autotune(True, str(cache))
+        got = M.disparity(Lg, Rg, D, K, n, r, eps, with_prior1=True)
+        table = M.autotune_table()
+        again = M.disparity(Lg, Rg, D, K, n, r, eps, with_prior1=True)
+    finally:
+        M.autotune(False)
+    torch.cuda.synchronize()
+    for out in (got, again):
+        assert torch.equal(ref["disp"], out["disp"]) and torch.equal(ref["cost"], out["cost"])
+        assert torch.equal(ref["prior1"], out["prior1"])
+    shapes = {(row[4], row[5]) for row in table}
+    for k in range(K):
+        assert (M.level_dim(240, k), M.level_dim(320, k)) in shapes
+    assert all(0 <= row[7] <= 3 and row[8] > 0 for row in table)
+    # modes: one full search (mode 0) at the coarsest level, restricted below
+    assert {row[0] for row in table} == {0, 1}
+    lines = cache.read_text().splitlines()
+    assert len(lines) == len(table)
+    M.autotune(True, str(cache))  # the cache parses back
+    M.autotune(False)
