@@ -108,12 +108,16 @@ const char* msibm_version(void);
  *   1  right window statistics staged in LDS with the right tile (full
  *      searches only; otherwise each thread reads them from global memory),
  *   2  XCD-aware tile order (each of the 8 XCDs takes one contiguous run of
- *      tiles, so neighbouring tiles share their halos in one L2).
+ *      tiles, so neighbouring tiles share their halos in one L2),
+ *   4  candidate split (full searches only): 2-row tiles whose 4 waves score
+ *      every 4th window of candidates for the same pixels and combine their
+ *      winners; four times the workgroups, a quarter of each thread's work
+ *      (for small levels).
  * Results do not depend on the shape.
  *
  * msibm_force_variant - pin the shape for every later call in this process
  * (bits that do not apply to a launch are ignored); -1 restores the automatic
- * choice.  Errors: INVALID_ARG (outside -1..3).
+ * choice.  Errors: INVALID_ARG (outside -1..7).
  */
 msibm_status msibm_force_variant(int32_t variant);
 

@@ -56,7 +56,7 @@ struct BackArgs {
 
 template <int NW, int CH>
 struct BackSmem {
-    using G = Geo<NW, CH, 1>;
+    using G = Geo<NW, CH, TILE_H1>;
     float Ls[G::LROWS * G::LSTRIDE];
     float Rs[G::LROWS * G::RSTRIDE];
     long long GLs[G::LROWS * G::LSTRIDE];  // left gradient tile (same layout as Ls), fixed point
@@ -157,7 +157,7 @@ template <int NW, int NC>
 __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by, BackSmem<NW, BACK_CHUNK>& sm)
 {
     constexpr int CH = BACK_CHUNK;
-    using G = Geo<NW, CH, 1>;
+    using G = Geo<NW, CH, TILE_H1>;
     constexpr int WS = 2 * NW + 1;          // window side
     constexpr float Nf = (float)(WS * WS);
     constexpr int STEP = CH - NC + 1;

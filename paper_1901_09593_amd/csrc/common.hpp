@@ -48,7 +48,8 @@ struct MatchArgs {
 // Kernel shape variants of the matching kernel (bits of MatchArgs::variant).
 constexpr int VARIANT_STATS_LDS = 1;  // right statistics staged in LDS (full search only)
 constexpr int VARIANT_XCD = 2;        // XCD-aware tile order
-constexpr int VARIANT_MASK = 3;
+constexpr int VARIANT_SPLIT = 4;      // full search: 2-row tiles, the 4 waves split the candidates
+constexpr int VARIANT_MASK = 7;
 
 // Tile of block b in a grid of gx x gy tiles.  The hardware deals consecutive
 // workgroups round-robin to the 8 XCDs, each with its own L2; the XCD-aware

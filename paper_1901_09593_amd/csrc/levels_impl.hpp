@@ -86,9 +86,15 @@ constexpr int ST_RH = ST_H + 2 * ST_MAXN;               // 28 rows with halo
 // in double precision (running sums over 8 outputs per thread, read straight from
 // global memory), then vertical running sums over 4 outputs per thread.  Values
 // are centred on the tile's first pixel before squaring, so the sums stay small.
+// The horizontal sums sit in LDS with each 8-column segment padded to 9 entries
+// and rows to 73, so that the horizontal pass (a wave spans 8 rows x 8
+// segments) spreads its stores over the banks instead of hitting two.
+constexpr int ST_HS = 73;  // row stride (doubles)
+__device__ __forceinline__ int st_idx(int row, int col) { return row * ST_HS + (col >> 3) * 9 + (col & 7); }
+
 struct StatsSmem {
-    double h1[ST_RH][ST_W];
-    double h2[ST_RH][ST_W];
+    double h1[ST_RH * ST_HS];
+    double h2[ST_RH * ST_HS];
 };
 
 template <typename T, int NW>
@@ -96,8 +102,8 @@ __device__ __forceinline__ void stats_tile(const T* __restrict__ src, int H, int
                                            float4* __restrict__ dst, int dpitch, double var_eps,
                                            int x0, int y0, StatsSmem& sm)
 {
-    double (*h1)[ST_W] = sm.h1;
-    double (*h2)[ST_W] = sm.h2;
+    double* h1 = sm.h1;
+    double* h2 = sm.h2;
     constexpr int n = NW, wn = 2 * NW + 1, rows = ST_H + 2 * NW;
     const double c = (double)to_f(src[(size_t)min(y0, H - 1) * spitch + min(x0, W - 1)]);
     // horizontal pass: thread = (row, 8-column segment)
@@ -118,15 +124,15 @@ __device__ __forceinline__ void stats_tile(const T* __restrict__ src, int H, int
                 s1 += v[t];
                 s2 = fma(v[t], v[t], s2);
             }
-            h1[rr][ST_SEG * seg] = s1;
-            h2[rr][ST_SEG * seg] = s2;
+            h1[st_idx(rr, ST_SEG * seg)] = s1;
+            h2[st_idx(rr, ST_SEG * seg)] = s2;
 #pragma unroll
             for (int k = 1; k < ST_SEG; ++k) {
                 const double add = v[k - 1 + wn], drop = v[k - 1];
                 s1 += add - drop;
                 s2 += fma(add, add, -drop * drop);
-                h1[rr][ST_SEG * seg + k] = s1;
-                h2[rr][ST_SEG * seg + k] = s2;
+                h1[st_idx(rr, ST_SEG * seg + k)] = s1;
+                h2[st_idx(rr, ST_SEG * seg + k)] = s2;
             }
         }
     }
@@ -137,14 +143,14 @@ __device__ __forceinline__ void stats_tile(const T* __restrict__ src, int H, int
     double s1 = 0.0, s2 = 0.0;
 #pragma unroll
     for (int t = 0; t < wn; ++t) {
-        s1 += h1[rs + t][col];
-        s2 += h2[rs + t][col];
+        s1 += h1[st_idx(rs + t, col)];
+        s2 += h2[st_idx(rs + t, col)];
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         if (k > 0) {
-            s1 += h1[rs + k - 1 + wn][col] - h1[rs + k - 1][col];
-            s2 += h2[rs + k - 1 + wn][col] - h2[rs + k - 1][col];
+            s1 += h1[st_idx(rs + k - 1 + wn, col)] - h1[st_idx(rs + k - 1, col)];
+            s2 += h2[st_idx(rs + k - 1 + wn, col)] - h2[st_idx(rs + k - 1, col)];
         }
         const int gy = y0 + rs + k, gx = x0 + col;
         if (gy < H && gx < W) {

@@ -64,9 +64,9 @@ constexpr int BACK_CHUNK = 112;
 // half and its odd ones in the second; a half holds whole groups of 64 column
 // pairs (one per lane of a staging wave), so staging stores need no per-element
 // bounds test, and one padding word separates the rows.
-template <int NW, int CH, int BY>
+template <int NW, int CH, int TH_>
 struct Geo {
-    static constexpr int TH = TILE_H1 * BY;       // tile height in pixels
+    static constexpr int TH = TH_;                // tile height in pixels
     static constexpr int WN = 2 * NW + 2;         // rows/cols spanned by a block's windows
     static constexpr int LROWS = TH + 2 * NW;     // LDS rows (both views)
     static constexpr int LCOLS = TILE_W + 2 * NW; // left tile logical width
@@ -83,14 +83,18 @@ struct Geo {
 // LDS of one matching tile: the left tile, one chunk of the right tile, and the
 // right window statistics of the chunk's columns (window mean minus the right
 // centring constant, and 1/sd).
-template <int NW, int CH, int BY, int SL>
+template <int NW, int CH, int TH, int SL>
 struct MatchSmem {
-    using G = Geo<NW, CH, BY>;
+    using G = Geo<NW, CH, TH>;
     static constexpr int SN = SL ? G::TH * G::SSTRIDE : 1;  // statistics planes only when staged
     float Ls[G::LROWS * G::LSTRIDE];
     float Rs[G::LROWS * G::RSTRIDE];
     float Sm[SN];
     float Si[SN];
+    // candidate-split tiles (fewer rows than a block row per wave): per wave,
+    // pixel and lane, the best score and its z
+    static constexpr int CN = (TH < TILE_H1) ? 2 * 4 * MATCH_THREADS : 1;
+    float cmb[CN];
     int lo, hi;
     unsigned mask;
 };
@@ -286,12 +290,19 @@ struct BlockState {
 // thread of the workgroup must call it (it synchronises the workgroup).
 // SL selects where the right statistics come from: staged in LDS with the right
 // tile (1), or read by each thread from global memory (0).
-template <typename T, int NW, int NC, int MODE, int BY, int SL>
+template <int SPLIT>
+struct TileRows {
+    static constexpr int value = SPLIT ? 2 : TILE_H1;
+};
+
+template <typename T, int NW, int NC, int MODE, int SPLIT, int SL>
 __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
-                                           MatchSmem<NW, ChunkOf<MODE>::value, BY, SL>& sm)
+                                           MatchSmem<NW, ChunkOf<MODE>::value, TileRows<SPLIT>::value, SL>& sm)
 {
     constexpr int CH = ChunkOf<MODE>::value;
-    using G = Geo<NW, CH, BY>;
+    constexpr int BY = 1;
+    using G = Geo<NW, CH, TileRows<SPLIT>::value>;
+    static_assert(!SPLIT || MODE == MODE_FULL, "only a full search splits its candidates over the waves");
     constexpr float Nf = (float)((2 * NW + 1) * (2 * NW + 1));
     constexpr int STEP = (MODE == MODE_FULL) ? CH : (CH - NC + 1);
     static_assert(MODE != MODE_FULL || CH % NC == 0, "full search steps must tile a chunk");
@@ -301,6 +312,9 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
     const T* __restrict__ Lg = static_cast<const T*>(a.L);
     const T* __restrict__ Rg = static_cast<const T*>(a.R);
     const int tx = threadIdx.x & (MATCH_TX - 1), ty = threadIdx.x / MATCH_TX;
+    // block row of the thread: one per wave, or (SPLIT) the tile's single block
+    // row shared by all waves, which then take every 4th candidate window
+    const int tyb = SPLIT ? 0 : ty;
     const int x0 = bx * TILE_W, y0 = by * G::TH;
     const int j0 = x0 + 2 * tx;
 
@@ -309,7 +323,7 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
 #pragma unroll
     for (int b = 0; b < BY; ++b) {
         BlockState& q = bs[b];
-        const int i0 = y0 + 2 * ty + TILE_H1 * b;
+        const int i0 = y0 + 2 * tyb + TILE_H1 * b;
         q.act[0] = i0 < a.H && j0 < a.W;
         q.act[1] = i0 < a.H && j0 + 1 < a.W;
         q.act[2] = i0 + 1 < a.H && j0 < a.W;
@@ -341,7 +355,9 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
             }
         }
     }
-    const int cy = min(y0 + G::TH / 2, a.H - 1), cx = min(x0 + TILE_W / 2, a.W - 1);
+    // right centring value: one pixel per 8-row band of tiles, whatever the tile
+    // height, so that every kernel shape rounds the scores identically
+    const int cy = min((y0 & ~(TILE_H1 - 1)) + TILE_H1 / 2, a.H - 1), cx = min(x0 + TILE_W / 2, a.W - 1);
     const float cR = to_f(Rg[(size_t)cy * a.pitch + cx]);
 
     // left tile (uncentred: each thread centres its own windows)
@@ -432,8 +448,8 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
                 ndl[p] = -Nf * ((stl[p].x - ca) + stl[p].y);
                 invl[p] = stl[p].z;
             }
-            const int lrow0 = 2 * ty + TILE_H1 * b;
-            for (int wz = w_first; wz <= w_last; wz += NC) {
+            const int lrow0 = 2 * tyb + TILE_H1 * b;
+            for (int wz = w_first + (SPLIT ? ty * NC : 0); wz <= w_last; wz += NC * (SPLIT ? MATCH_TY : 1)) {
                 float S[4][NC];
                 const int rcol0 = 2 * tx + (ztop - wz) - (NC - 1);
                 window_sums<NW, NC, G>(sm.Ls, sm.Rs, lrow0, tx, rcol0, ca, S);
@@ -486,8 +502,34 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
             }
         }
     }
+    if (SPLIT) {
+        // every wave scored a disjoint set of candidate windows for the same
+        // pixels: combine in LDS, highest score, then lowest z
+        float* cb = sm.cmb;                                 // [wave][pixel][lane]
+        int* cz = reinterpret_cast<int*>(sm.cmb) + MATCH_THREADS * 4;
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            cb[(ty * 4 + p) * MATCH_TX + tx] = best[0][p];
+            cz[(ty * 4 + p) * MATCH_TX + tx] = bz[0][p];
+        }
+        __syncthreads();
+        if (ty == 0) {
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+#pragma unroll
+                for (int w = 1; w < MATCH_TY; ++w) {
+                    const float v = cb[(w * 4 + p) * MATCH_TX + tx];
+                    const int z = cz[(w * 4 + p) * MATCH_TX + tx];
+                    if (v > best[0][p] || (v == best[0][p] && z < bz[0][p])) {
+                        best[0][p] = v;
+                        bz[0][p] = z;
+                    }
+                }
+        }
+    }
 #pragma unroll
     for (int b = 0; b < BY; ++b) {
+        if (SPLIT && ty != 0) break;
         const BlockState& q = bs[b];
         const int ip[4] = {q.ia, q.ia, q.ib, q.ib};
         const int jp[4] = {q.ja, q.jb, q.ja, q.jb};
@@ -512,50 +554,58 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
     __syncthreads();  // LDS may be reused by the caller's next tile
 }
 
-template <typename T, int NW, int NC, int MODE, int BY, int SL>
+template <typename T, int NW, int NC, int MODE, int SPLIT, int SL>
 __global__ __launch_bounds__(MATCH_THREADS) void match_kernel(MatchArgs a)
 {
-    __shared__ MatchSmem<NW, ChunkOf<MODE>::value, BY, SL> sm;
+    __shared__ MatchSmem<NW, ChunkOf<MODE>::value, TileRows<SPLIT>::value, SL> sm;
     int bx = blockIdx.x, by = blockIdx.y;
     tile_of(a.variant, &bx, &by);
-    match_tile<T, NW, NC, MODE, BY, SL>(a, bx, by, sm);
+    match_tile<T, NW, NC, MODE, SPLIT, SL>(a, bx, by, sm);
 }
 
-template <typename T, int NW, int NC, int MODE, int BY>
-static hipError_t launch_one(const MatchArgs& a, hipStream_t s)
+template <typename T, int NW, int NC, int MODE, int SPLIT>
+static hipError_t launch_shape(const MatchArgs& a, hipStream_t s)
 {
-    constexpr int TH = TILE_H1 * BY;
+    constexpr int TH = TileRows<SPLIT>::value;
     dim3 grid((a.W + TILE_W - 1) / TILE_W, (a.H + TH - 1) / TH, 1);
-    // statistics staged in LDS is a full-search variant only: a restricted
-    // search reads a few statistics per pixel, and its wide right tile leaves no
-    // LDS for them
+    // statistics staged in LDS is a full-search shape only: a restricted search
+    // reads a few statistics per pixel, and its wide right tile leaves no LDS for
+    // them
     if (MODE == MODE_FULL && (a.variant & VARIANT_STATS_LDS))
-        hipLaunchKernelGGL((match_kernel<T, NW, NC, MODE, BY, MODE == MODE_FULL ? 1 : 0>), grid,
+        hipLaunchKernelGGL((match_kernel<T, NW, NC, MODE, SPLIT, MODE == MODE_FULL ? 1 : 0>), grid,
                            dim3(MATCH_THREADS), 0, s, a);
     else
-        hipLaunchKernelGGL((match_kernel<T, NW, NC, MODE, BY, 0>), grid, dim3(MATCH_THREADS), 0, s, a);
+        hipLaunchKernelGGL((match_kernel<T, NW, NC, MODE, SPLIT, 0>), grid, dim3(MATCH_THREADS), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int NW, int BY>
+template <typename T, int NW, int NC, int MODE>
+static hipError_t launch_one(const MatchArgs& a, hipStream_t s)
+{
+    if (MODE == MODE_FULL && (a.variant & VARIANT_SPLIT))
+        return launch_shape<T, NW, NC, MODE, MODE == MODE_FULL ? 1 : 0>(a, s);
+    return launch_shape<T, NW, NC, MODE, 0>(a, s);
+}
+
+template <typename T, int NW>
 static hipError_t dispatch_nc(int mode, int nc, const MatchArgs& a, hipStream_t s)
 {
-    if (mode == MODE_FULL) return launch_one<T, NW, FULL_NC, MODE_FULL, BY>(a, s);
+    if (mode == MODE_FULL) return launch_one<T, NW, FULL_NC, MODE_FULL>(a, s);
     if (mode == MODE_REFINE) {
         switch (nc) {
-            case 2: return launch_one<T, NW, 2, MODE_REFINE, BY>(a, s);
-            case 3: return launch_one<T, NW, 3, MODE_REFINE, BY>(a, s);
-            case 5: return launch_one<T, NW, 5, MODE_REFINE, BY>(a, s);
-            case 7: return launch_one<T, NW, 7, MODE_REFINE, BY>(a, s);
-            case 9: return launch_one<T, NW, 9, MODE_REFINE, BY>(a, s);
+            case 2: return launch_one<T, NW, 2, MODE_REFINE>(a, s);
+            case 3: return launch_one<T, NW, 3, MODE_REFINE>(a, s);
+            case 5: return launch_one<T, NW, 5, MODE_REFINE>(a, s);
+            case 7: return launch_one<T, NW, 7, MODE_REFINE>(a, s);
+            case 9: return launch_one<T, NW, 9, MODE_REFINE>(a, s);
         }
         return hipErrorInvalidValue;
     }
     switch (nc) {
-        case 3: return launch_one<T, NW, 3, MODE_SOFT, BY>(a, s);
-        case 5: return launch_one<T, NW, 5, MODE_SOFT, BY>(a, s);
-        case 7: return launch_one<T, NW, 7, MODE_SOFT, BY>(a, s);
-        case 9: return launch_one<T, NW, 9, MODE_SOFT, BY>(a, s);
+        case 3: return launch_one<T, NW, 3, MODE_SOFT>(a, s);
+        case 5: return launch_one<T, NW, 5, MODE_SOFT>(a, s);
+        case 7: return launch_one<T, NW, 7, MODE_SOFT>(a, s);
+        case 9: return launch_one<T, NW, 9, MODE_SOFT>(a, s);
     }
     return hipErrorInvalidValue;
 }
@@ -564,8 +614,8 @@ template <int NW>
 static hipError_t dispatch_match(int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s)
 {
     if (dtype == 0 && mode == MODE_SOFT) return hipErrorInvalidValue;  // soft mode takes float images
-    if (dtype == 0) return dispatch_nc<uint8_t, NW, 1>(mode, nc, a, s);
-    return dispatch_nc<float, NW, 1>(mode, nc, a, s);
+    if (dtype == 0) return dispatch_nc<uint8_t, NW>(mode, nc, a, s);
+    return dispatch_nc<float, NW>(mode, nc, a, s);
 }
 
 // Matching of several (pair, level) segments of one mode and element type in
@@ -573,7 +623,7 @@ static hipError_t dispatch_match(int dtype, int mode, int nc, const MatchArgs& a
 template <typename T, int NW, int NC, int MODE, int SL>
 __global__ __launch_bounds__(MATCH_THREADS) void match_multi_kernel(MultiArgs a)
 {
-    __shared__ MatchSmem<NW, ChunkOf<MODE>::value, 1, SL> sm;
+    __shared__ MatchSmem<NW, ChunkOf<MODE>::value, TILE_H1, SL> sm;
     const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
     const LevelDesc* lv = a.levels + a.level_base[s.pair];
     const LevelDesc& L = lv[s.level];
@@ -601,7 +651,7 @@ __global__ __launch_bounds__(MATCH_THREADS) void match_multi_kernel(MultiArgs a)
     m.opitch = L.W;
     m.inv_tau = a.inv_tau;
     const int t = blockIdx.x - s.task0;
-    match_tile<T, NW, NC, MODE, 1, SL>(m, t % s.tiles_x, t / s.tiles_x, sm);
+    match_tile<T, NW, NC, MODE, 0, SL>(m, t % s.tiles_x, t / s.tiles_x, sm);
 }
 
 // Statistics placement per mode: staged in LDS for the full search (every
