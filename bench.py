@@ -117,7 +117,7 @@ def hier_counts(torch, M, L, R, D, K, n, r, eps):
     maps = [None] * K
     for k in range(K - 1, -1, -1):
         maps[k], _ = M.match_level(L if k == 0 else PL[k], R if k == 0 else PR[k], n, -(-D // (1 << k)),
-                                   None if k == K - 1 else maps[k + 1], r, eps, with_cost=False)
+                                   None if k == K - 1 else maps[k + 1], r, eps, with_cost=True)
     return level_counts(torch, maps, D, K, r)
 
 
