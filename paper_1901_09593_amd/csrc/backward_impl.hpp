@@ -256,23 +256,35 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
             for (int s = 0; s < NC; ++s) k1[pc][s] = 0.f;
         }
         if (part) {
+            // statistics and upstream gradients of both pixels, loaded before the
+            // window sums so that their latency overlaps them
+            float4 stl2[2], str2[2][NC];
+            float gpx2[2];
+            const float4* srow = a.statR + (size_t)ii * a.spitch;
+#pragma unroll
+            for (int pc = 0; pc < 2; ++pc) {
+                stl2[pc] = a.statL[(size_t)ii * a.spitch + jp[pc]];
+                gpx2[pc] = a.g[(size_t)ii * a.gpitch + jp[pc]];
+#pragma unroll
+                for (int s = 0; s < NC; ++s) str2[pc][s] = srow[clampi(jp[pc] - (zs + s), 0, a.W - 1)];
+            }
+            asm volatile("" ::: "memory");  // keep the loads ahead of the window sums
             float S[2][NC];
             row_sums<NW, NC, G>(sm.Ls, sm.Rs, 2 * ty + pr, tx, pa, pb, ca, S);
 #pragma unroll
             for (int pc = 0; pc < 2; ++pc) {
                 if (!act[pc]) continue;  // contributes nothing
-                const float4 stl = a.statL[(size_t)ii * a.spitch + jp[pc]];
+                const float4 stl = stl2[pc];
                 const float dl = (stl.x - ca) + stl.y;  // mu_l - ca
                 const float invl = stl.z;
                 // right statistics of this pixel's candidates: column jp - z
-                const float4* srow = a.statR + (size_t)ii * a.spitch;
                 float mr[NC], invr[NC], rho[NC];
                 bool ok[NC];
                 float best = -3.f;
 #pragma unroll
                 for (int s = 0; s < NC; ++s) {
                     const int z = zs + s;
-                    const float4 st = srow[clampi(jp[pc] - z, 0, a.W - 1)];
+                    const float4 st = str2[pc][s];
                     mr[s] = (st.x - cR) + st.y;  // mu_r - cR
                     invr[s] = st.z;
                     const float C = fmaf(-Nf * dl, mr[s], S[pc][s]);
@@ -290,7 +302,7 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
                     sz = fmaf(e[s], (float)(zs + s), sz);
                 }
                 const float ds = sz / se;
-                const float gpx = a.g[(size_t)ii * a.gpitch + jp[pc]];
+                const float gpx = gpx2[pc];
                 const float gs = gpx * a.inv_tau / se;
                 float k2r[NC], klp = 0.f, clp = 0.f;
 #pragma unroll

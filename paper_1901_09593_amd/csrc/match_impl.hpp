@@ -105,11 +105,12 @@ __device__ __forceinline__ int split_pos(int c, int half) { return (c & 1) ? hal
 // Stage rows [gy0, gy0+ROWS) x cols [gx0, gx0+cols) (cols <= MAXCOLS) of `src`,
 // clamped to the image, into LDS in split layout (even columns at [0, half),
 // odd ones at [half, ...)), centred by c.  Each wave takes whole rows; lane l of
-// group k stages columns 2(l + 64k) and 2(l + 64k) + 1.  Only the groups that
-// hold staged columns are loaded (a wave-uniform test); within them every load
-// and store is unconditional: clamped addresses are always valid, a half holds
-// whole groups, and columns past `cols` are never read.  All loads of the thread
-// are issued before its first LDS store so that their latencies overlap.
+// group k stages columns 2(l + 64k) and 2(l + 64k) + 1.  Every load of the
+// thread is issued, unconditionally, before its first LDS store so that their
+// latencies overlap (a load under a branch would be waited for inside it):
+// columns past `cols` re-read the last staged column, and only the groups that
+// hold staged columns are stored (a wave-uniform test).  A half holds whole
+// groups, and columns past `cols` are never read.
 template <typename T, int ROWS, int MAXCOLS, int NWAVES = MATCH_TY>
 __device__ __forceinline__ void stage_tile(float* dst, int stride, int half, const T* __restrict__ src,
                                            int pitch, int H, int W, int gy0, int gx0, int cols, float c)
@@ -125,11 +126,9 @@ __device__ __forceinline__ void stage_tile(float* dst, int stride, int half, con
         const T* srow = src + (size_t)clampi(gy0 + rr, 0, H - 1) * pitch;
 #pragma unroll
         for (int ci = 0; ci < CI; ++ci) {
-            if (ci < groups) {
-                const int cc = 2 * (lane + MATCH_TX * ci);
-                v0[ri][ci] = srow[clampi(gx0 + cc, 0, W - 1)];
-                v1[ri][ci] = srow[clampi(gx0 + cc + 1, 0, W - 1)];
-            }
+            const int cc = 2 * (lane + MATCH_TX * ci);
+            v0[ri][ci] = srow[clampi(gx0 + min(cc, cols - 1), 0, W - 1)];
+            v1[ri][ci] = srow[clampi(gx0 + min(cc + 1, cols - 1), 0, W - 1)];
         }
     }
 #pragma unroll
@@ -168,11 +167,9 @@ __device__ __forceinline__ void stage_stats(float* mc, float* is, int stride, in
         const float4* srow = src + (size_t)clampi(gy0 + rr, 0, H - 1) * spitch;
 #pragma unroll
         for (int ci = 0; ci < CI; ++ci) {
-            if (ci < groups) {
-                const int cc = 2 * (lane + MATCH_TX * ci);
-                v0[ri][ci] = srow[clampi(gx0 + cc, 0, W - 1)];
-                v1[ri][ci] = srow[clampi(gx0 + cc + 1, 0, W - 1)];
-            }
+            const int cc = 2 * (lane + MATCH_TX * ci);
+            v0[ri][ci] = srow[clampi(gx0 + min(cc, cols - 1), 0, W - 1)];
+            v1[ri][ci] = srow[clampi(gx0 + min(cc + 1, cols - 1), 0, W - 1)];
         }
     }
 #pragma unroll
@@ -459,6 +456,19 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
                 const int c0 = 2 * tx + (ztop - wz) + 1;
                 const int be = (c0 & 1) ? G::SHALF + (c0 >> 1) : (c0 >> 1);      // q even
                 const int bo = (c0 & 1) ? (c0 >> 1) : G::SHALF + (c0 >> 1) - 1;  // q odd
+                // right statistics from global memory: every load of the window
+                // issued before the first use, so they share one latency
+                float4 stg[2][SL ? 1 : NC + 1];
+                if (!SL) {
+#pragma unroll
+                    for (int rowp = 0; rowp < 2; ++rowp) {
+                        // columns j0 + 1 - wz - q of pixel row ia or ib
+                        const float4* srow = a.statR + (size_t)(rowp ? q.ib : q.ia) * a.spitch;
+#pragma unroll
+                        for (int qq = 0; qq <= NC; ++qq) stg[rowp][SL ? 0 : qq] = srow[clampi(j0 + 1 - wz - qq, 0, a.W - 1)];
+                    }
+                    asm volatile("" ::: "memory");  // keep the loads ahead of their uses
+                }
 #pragma unroll
                 for (int rowp = 0; rowp < 2; ++rowp) {
                     float smc[NC + 1], sis[NC + 1];
@@ -471,11 +481,9 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
                             sis[qq] = sm.Si[o];
                         }
                     } else {
-                        // columns j0 + 1 - wz - q of pixel row ia or ib
-                        const float4* srow = a.statR + (size_t)(rowp ? q.ib : q.ia) * a.spitch;
 #pragma unroll
                         for (int qq = 0; qq <= NC; ++qq) {
-                            const float4 st = srow[clampi(j0 + 1 - wz - qq, 0, a.W - 1)];
+                            const float4 st = stg[rowp][SL ? 0 : qq];
                             smc[qq] = (st.x - cR) + st.y;
                             sis[qq] = st.z;
                         }
