@@ -135,7 +135,7 @@ def tune_summary(table, H, W, K):
     wins = {}
     for t in table:
         wins[str(t[7])] = wins.get(str(t[7]), 0) + 1
-    return {"variant_bits": "1 = statistics in LDS (full search), 2 = XCD-aware tile order, 4 = candidates split over waves (full search)",
+    return {"variant_bits": "1 = statistics in LDS (full search), 2 = XCD-aware tile order, 4 = candidates split over waves (full search), 8 = fixed candidate window (restricted search)",
             "headline_levels": head, "wins_over_all_shapes": wins, "shapes_measured": len(table)}
 
 

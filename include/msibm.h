@@ -112,12 +112,15 @@ const char* msibm_version(void);
  *   4  candidate split (full searches only): 2-row tiles whose 4 waves score
  *      every 4th window of candidates for the same pixels and combine their
  *      winners; four times the workgroups, a quarter of each thread's work
- *      (for small levels).
+ *      (for small levels),
+ *   8  fixed window (restricted searches whose whole candidate range, about
+ *      D_k candidates, fits one staged chunk of 320): both tiles are staged
+ *      at once before any prior is read, with no workgroup-wide range step.
  * Results do not depend on the shape.
  *
  * msibm_force_variant - pin the shape for every later call in this process
  * (bits that do not apply to a launch are ignored); -1 restores the automatic
- * choice.  Errors: INVALID_ARG (outside -1..7).
+ * choice.  Errors: INVALID_ARG (outside -1..15).
  */
 msibm_status msibm_force_variant(int32_t variant);
 

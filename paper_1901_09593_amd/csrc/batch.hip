@@ -274,6 +274,9 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
     a.rs = cfg->soft_radius;
     a.var_eps = cfg->var_eps;
     a.inv_tau = cfg->soft_radius > 0 ? 1.f / cfg->tau : 0.f;
+    // restricted searches stage their whole candidate range at once wherever it
+    // fits one chunk (decided per segment by the kernel)
+    a.variant = VARIANT_FIXW;
     static const char* mode_name[3] = {"full", "refine", "soft"};
     for (const StageLaunch& l : pl.launches) {
         a.segs = (const Segment*)table + l.first;

@@ -49,7 +49,8 @@ struct MatchArgs {
 constexpr int VARIANT_STATS_LDS = 1;  // right statistics staged in LDS (full search only)
 constexpr int VARIANT_XCD = 2;        // XCD-aware tile order
 constexpr int VARIANT_SPLIT = 4;      // full search: 2-row tiles, the 4 waves split the candidates
-constexpr int VARIANT_MASK = 7;
+constexpr int VARIANT_FIXW = 8;       // restricted search: stage the whole candidate range up front
+constexpr int VARIANT_MASK = 15;
 
 // Tile of block b in a grid of gx x gy tiles.  The hardware deals consecutive
 // workgroups round-robin to the 8 XCDs, each with its own L2; the XCD-aware
@@ -134,6 +135,7 @@ struct MultiArgs {
     const LevelDesc* levels;  // a pair's levels start at levels[level_base[pair]]
     const int* level_base;
     const BackArgs* back;     // backward launches: one entry per pair
+    int variant;              // matching kernel shape bits that apply per segment
     int r, rs;                // refine and soft radius
     double var_eps;
     float inv_tau;

@@ -147,6 +147,60 @@ __device__ __forceinline__ void stage_tile(float* dst, int stride, int half, con
     }
 }
 
+// Both tiles of a fixed-window restricted search in one go: every load of the
+// left and the right tile is issued before the first LDS store, so the two
+// stagings share one memory latency.
+template <typename T, int ROWS, int LMAX, int RMAX>
+__device__ __forceinline__ void stage_pair(float* ldst, int lstride, int lhalf, float* rdst, int rstride,
+                                           int rhalf, const T* __restrict__ lsrc, const T* __restrict__ rsrc,
+                                           int pitch, int H, int W, int gy0, int lx0, int lcols, int rx0,
+                                           int rcols, float c)
+{
+    constexpr int RI = (ROWS + MATCH_TY - 1) / MATCH_TY;
+    constexpr int LI = (LMAX + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
+    constexpr int CI = (RMAX + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
+    const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
+    const int lgroups = (lcols + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
+    const int rgroups = (rcols + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
+    T l0[RI][LI], l1[RI][LI], r0[RI][CI], r1[RI][CI];
+#pragma unroll
+    for (int ri = 0; ri < RI; ++ri) {
+        const int rr = wave + MATCH_TY * ri;
+        const size_t ro = (size_t)clampi(gy0 + rr, 0, H - 1) * pitch;
+#pragma unroll
+        for (int ci = 0; ci < LI; ++ci) {
+            const int cc = 2 * (lane + MATCH_TX * ci);
+            l0[ri][ci] = lsrc[ro + clampi(lx0 + min(cc, lcols - 1), 0, W - 1)];
+            l1[ri][ci] = lsrc[ro + clampi(lx0 + min(cc + 1, lcols - 1), 0, W - 1)];
+        }
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci) {
+            const int cc = 2 * (lane + MATCH_TX * ci);
+            r0[ri][ci] = rsrc[ro + clampi(rx0 + min(cc, rcols - 1), 0, W - 1)];
+            r1[ri][ci] = rsrc[ro + clampi(rx0 + min(cc + 1, rcols - 1), 0, W - 1)];
+        }
+    }
+#pragma unroll
+    for (int ri = 0; ri < RI; ++ri) {
+        const int rr = wave + MATCH_TY * ri;
+        if (rr >= ROWS) continue;
+#pragma unroll
+        for (int ci = 0; ci < LI; ++ci)
+            if (ci < lgroups) {
+                const int ch = lane + MATCH_TX * ci;
+                ldst[rr * lstride + ch] = to_f(l0[ri][ci]);
+                ldst[rr * lstride + lhalf + ch] = to_f(l1[ri][ci]);
+            }
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci)
+            if (ci < rgroups) {
+                const int ch = lane + MATCH_TX * ci;
+                rdst[rr * rstride + ch] = to_f(r0[ri][ci]) - c;
+                rdst[rr * rstride + rhalf + ch] = to_f(r1[ri][ci]) - c;
+            }
+    }
+}
+
 // Stage the right statistics of rows [gy0, gy0+ROWS) x cols [gx0, gx0+cols)
 // into two split-layout LDS planes: the window mean minus c (its float value and
 // rounding remainder summed after the subtraction) and 1/sd.  Same staging
@@ -357,12 +411,26 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
     const int cy = min((y0 & ~(TILE_H1 - 1)) + TILE_H1 / 2, a.H - 1), cx = min(x0 + TILE_W / 2, a.W - 1);
     const float cR = to_f(Rg[(size_t)cy * a.pitch + cx]);
 
-    // left tile (uncentred: each thread centres its own windows)
-    stage_tile<T, G::LROWS, G::LCOLS>(sm.Ls, G::LSTRIDE, G::LHALF, Lg, a.pitch, a.H, a.W, y0 - NW,
-                                      x0 - NW, G::LCOLS, 0.f);
+    // Fixed window (restricted searches whose whole candidate range fits one
+    // chunk): every block's slots lie in [zlo_f, zhi_f], so both tiles are
+    // staged at once, before any block's prior is known, and no workgroup-wide
+    // range is needed.
+    const int zlo_f = min(-a.r, 2 - NC), zhi_f = a.Dk - 1 - a.r;
+    const bool fixw = MODE != MODE_FULL && (a.variant & VARIANT_FIXW) && zhi_f - zlo_f + 1 <= STEP;
+    if (fixw) {
+        const int ztop = zhi_f + NC - 1;
+        stage_pair<T, G::LROWS, G::LCOLS, G::RCOLS>(sm.Ls, G::LSTRIDE, G::LHALF, sm.Rs, G::RSTRIDE, G::RHALF, Lg,
+                                                    Rg, a.pitch, a.H, a.W, y0 - NW, x0 - NW, G::LCOLS,
+                                                    x0 - NW - ztop, TILE_W + 2 * NW + (ztop - zlo_f), cR);
+    } else {
+        // left tile (uncentred: each thread centres its own windows)
+        stage_tile<T, G::LROWS, G::LCOLS>(sm.Ls, G::LSTRIDE, G::LHALF, Lg, a.pitch, a.H, a.W, y0 - NW,
+                                          x0 - NW, G::LCOLS, 0.f);
+    }
 
     // workgroup-wide candidate range; for a restricted search also the set of
     // right-image chunks some block of the tile needs
+    if (!fixw) {
     if (threadIdx.x == 0) {
         sm.lo = 0x7fffffff;
         sm.hi = -0x7fffffff;
@@ -383,14 +451,15 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
             }
     }
     __syncthreads();
-    const int zlo = sm.lo, zhi = sm.hi;
     if (MODE != MODE_FULL) {
 #pragma unroll
         for (int b = 0; b < BY; ++b)
-            if (bs[b].act[0]) atomicOr(&sm.mask, 1u << ((bs[b].zs - zlo) / STEP));
+            if (bs[b].act[0]) atomicOr(&sm.mask, 1u << ((bs[b].zs - sm.lo) / STEP));
     }
     __syncthreads();
-    const unsigned mask = (MODE == MODE_FULL) ? 0xffffffffu : sm.mask;
+    }
+    const int zlo = fixw ? zlo_f : sm.lo, zhi = fixw ? zhi_f : sm.hi;
+    const unsigned mask = (MODE == MODE_FULL || fixw) ? 0xffffffffu : sm.mask;
 
     constexpr int SB = (MODE == MODE_SOFT) ? BY : 1, SN = (MODE == MODE_SOFT) ? NC : 1;
     float best[BY][4], rho_keep[SB][4][SN];
@@ -410,8 +479,9 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
         // the window centre of the tile's first pixel column at that slot
         const int ztop = min(zc + CH - 1, zhi + NC - 1);
         if (zc != zlo) __syncthreads();  // previous chunk fully consumed
-        stage_tile<T, G::LROWS, G::RCOLS>(sm.Rs, G::RSTRIDE, G::RHALF, Rg, a.pitch, a.H, a.W, y0 - NW,
-                                          x0 - NW - ztop, TILE_W + 2 * NW + (ztop - zc), cR);
+        if (!fixw)
+            stage_tile<T, G::LROWS, G::RCOLS>(sm.Rs, G::RSTRIDE, G::RHALF, Rg, a.pitch, a.H, a.W, y0 - NW,
+                                              x0 - NW - ztop, TILE_W + 2 * NW + (ztop - zc), cR);
         if (SL)
             stage_stats<G::TH, G::SCOLS>(sm.Sm, sm.Si, G::SSTRIDE, G::SHALF, a.statR, a.spitch, a.H, a.W,
                                          y0, x0 - ztop, TILE_W + (ztop - zc), cR);
@@ -658,6 +728,7 @@ __global__ __launch_bounds__(MATCH_THREADS) void match_multi_kernel(MultiArgs a)
     m.soft_out = L.soft;
     m.opitch = L.W;
     m.inv_tau = a.inv_tau;
+    m.variant = a.variant;
     const int t = blockIdx.x - s.task0;
     match_tile<T, NW, NC, MODE, 0, SL>(m, t % s.tiles_x, t / s.tiles_x, sm);
 }

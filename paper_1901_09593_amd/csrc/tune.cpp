@@ -8,6 +8,7 @@
 #include <mutex>
 #include <sstream>
 #include <tuple>
+#include <algorithm>
 
 namespace msibm {
 
@@ -57,9 +58,24 @@ Tuner& tuner()
     return t;
 }
 
-// Default shapes, from measurements on MI355X: a full search reuses each staged
-// statistics column for every candidate, a restricted search reads only a few.
-int default_variant(int mode) { return mode == MODE_FULL ? VARIANT_STATS_LDS : 0; }
+// Whether a restricted search's whole candidate range fits one staged chunk
+// (the condition the kernel applies to the fixed-window shape).
+bool fixed_window_fits(const MatchArgs& a, int nc)
+{
+    const int zlo = std::min(-a.r, 2 - nc), zhi = a.Dk - 1 - a.r;
+    return zhi - zlo + 1 <= 320 - nc + 1;
+}
+
+// Default shapes, from the autotuner's choices on MI355X: restricted searches
+// stage their whole candidate range at once (where it fits) in XCD order; full
+// searches stage statistics in LDS and, on small levels (fewer tiles than
+// twice the CUs), split their candidates over the waves.
+int default_variant(const MatchArgs& a, int mode)
+{
+    if (mode != MODE_FULL) return VARIANT_FIXW | VARIANT_XCD;
+    const int tiles = ((a.W + TILE_W - 1) / TILE_W) * ((a.H + TILE_H1 - 1) / TILE_H1);
+    return tiles < 512 ? (VARIANT_STATS_LDS | VARIANT_SPLIT) : (VARIANT_STATS_LDS | VARIANT_XCD);
+}
 
 std::string table_text(const Tuner& t)
 {
@@ -149,16 +165,19 @@ int select_variant(const MatchArgs& a, int n, int dtype, int mode, int nc, hipSt
 {
     Tuner& t = tuner();
     std::lock_guard<std::mutex> g(t.mu);
-    const int valid = mode == MODE_FULL ? VARIANT_MASK : VARIANT_XCD;  // statistics in LDS: full search only
+    // statistics in LDS and candidate split: full search only; fixed window:
+    // restricted searches whose candidate range fits one staged chunk
+    const int valid = mode == MODE_FULL ? (VARIANT_STATS_LDS | VARIANT_XCD | VARIANT_SPLIT)
+                                        : (VARIANT_XCD | (fixed_window_fits(a, nc) ? VARIANT_FIXW : 0));
     if (t.forced >= 0) return t.forced & valid;
     const Key key(mode, n, nc, dtype, a.H, a.W, a.Dk);
     auto it = t.table.find(key);
     if (it != t.table.end()) return it->second.variant & valid;
-    if (!t.on) return default_variant(mode);
+    if (!t.on) return default_variant(a, mode) & valid;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
-        return default_variant(mode);
-    int best = default_variant(mode);
+        return default_variant(a, mode) & valid;
+    int best = default_variant(a, mode) & valid;
     float best_us = -1.f;
     for (int v = 0; v <= VARIANT_MASK; ++v) {
         if (v & ~valid) continue;

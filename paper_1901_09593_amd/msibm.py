@@ -160,7 +160,8 @@ def make_config(n: int, r: int, var_eps: float, soft_radius: int = 0, tau: float
 def force_variant(v: int = -1):
     """Pin the matching kernel shape (bit 1: right statistics staged in LDS for
     full searches, bit 2: XCD-aware tile order, bit 4: candidates split over the
-    waves of 2-row tiles for full searches); -1 = automatic."""
+    waves of 2-row tiles for full searches, bit 8: fixed candidate window for
+    restricted searches); -1 = automatic."""
     _check(lib().msibm_force_variant(int(v)))
 
 
