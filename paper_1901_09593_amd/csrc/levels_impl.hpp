@@ -28,17 +28,19 @@ __device__ __forceinline__ void reduce_tile(const ReduceArgs& a, int view, int b
     const int ox0 = bx * RD_W, oy0 = by * RD_H;
     const int ix0 = 2 * ox0 - 2, iy0 = 2 * oy0 - 2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    // stage: every load of the thread issued before the LDS stores
+    // stage: every load of the thread issued, unconditionally, before the LDS
+    // stores (positions past the region re-read its last row or column), so
+    // that the loads share one latency
     constexpr int RI = (RD_IH + 3) / 4, CI = (RD_IW + 63) / 64;
     T v[RI][CI];
 #pragma unroll
     for (int ri = 0; ri < RI; ++ri) {
-        const int rr = wave + 4 * ri;
+        const int rr = min(wave + 4 * ri, RD_IH - 1);
         const T* srow = src + (size_t)clampi(iy0 + rr, 0, a.H - 1) * a.spitch;
 #pragma unroll
         for (int ci = 0; ci < CI; ++ci) {
-            const int cc = lane + 64 * ci;
-            if (rr < RD_IH && cc < RD_IW) v[ri][ci] = srow[clampi(ix0 + cc, 0, a.W - 1)];
+            const int cc = min(lane + 64 * ci, RD_IW - 1);
+            v[ri][ci] = srow[clampi(ix0 + cc, 0, a.W - 1)];
         }
     }
 #pragma unroll
