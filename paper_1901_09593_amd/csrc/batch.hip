@@ -33,7 +33,7 @@ namespace msibm {
 static int cdiv(int a, int b) { return (a + b - 1) / b; }
 static int levels_of(const msibm_pair& p) { return p.num_levels ? p.num_levels : auto_levels(p.max_disp); }
 
-enum StageKind { STAGE_REDUCE = 0, STAGE_STATS = 1, STAGE_MATCH = 2, STAGE_ZERO = 3, STAGE_BACKWARD = 4 };
+enum StageKind { STAGE_LEVELS = 0, STAGE_STATS = 1, STAGE_MATCH = 2, STAGE_ZERO = 3, STAGE_BACKWARD = 4 };
 
 struct StageLaunch {
     int kind, level;
@@ -68,8 +68,8 @@ __global__ __launch_bounds__(256) void zero_multi_kernel(MultiArgs a)
     }
 }
 
-// Tiles of one level: reduce and statistics tiles cover one view each, matching
-// tiles both.
+// Tiles of one level: reduce tiles cover one view each, statistics and
+// matching tiles both.
 static Segment make_seg(int type, int p, int k, int h, int w, int task0)
 {
     Segment s{};
@@ -80,10 +80,10 @@ static Segment make_seg(int type, int p, int k, int h, int w, int task0)
         s.tiles_x = cdiv(w, RD_W);
         s.tiles_y = cdiv(h, RD_H);
         s.views = 2;
-    } else if (type == SEG_STATS) {
+    } else if (type == SEG_STATS) {  // a statistics tile covers both views
         s.tiles_x = cdiv(w, ST_W);
         s.tiles_y = cdiv(h, ST_H);
-        s.views = 2;
+        s.views = 1;
     } else if (type == SEG_ZERO) {
         s.tiles_x = (int)(((size_t)h * w + ZERO_TILE - 1) / ZERO_TILE);
         s.tiles_y = 1;
@@ -139,15 +139,15 @@ static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg
         l.nseg++;
         pl.segs.push_back(s);
     };
-    for (int k = 1; k < Kmax; ++k) {
-        begin(STAGE_REDUCE, k, 0, 0, 0);
-        for (int p = 0; p < np; ++p)
-            if (k < K[p]) add(SEG_REDUCE, p, k);
-    }
-    begin(STAGE_STATS, -1, 0, 0, 0);
-    for (int k = 0; k < Kmax; ++k)
+    // pyramid step k: level k's statistics (heavier tiles first) side by side
+    // with the reduce that makes level k + 1
+    for (int k = 0; k < Kmax; ++k) {
+        begin(STAGE_LEVELS, k, 0, 0, 0);
         for (int p = 0; p < np; ++p)
             if (k < K[p]) add(SEG_STATS, p, k);
+        for (int p = 0; p < np; ++p)
+            if (k + 1 < K[p]) add(SEG_REDUCE, p, k + 1);
+    }
     const int modes[3] = {MODE_FULL, MODE_REFINE, MODE_SOFT};
     const int segtype[3] = {SEG_FULL, SEG_REFINE, SEG_SOFT};
     for (int k = Kmax - 1; k >= 0; --k)
@@ -283,14 +283,14 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
         a.nseg = l.nseg;
         char lab[40];
         const bool bwd = !pl.back.empty();
-        if (l.kind == STAGE_REDUCE) snprintf(lab, sizeof(lab), "batch_reduce_l%d", l.level);
+        if (l.kind == STAGE_LEVELS) snprintf(lab, sizeof(lab), "batch_levels_l%d", l.level);
         else if (l.kind == STAGE_STATS) snprintf(lab, sizeof(lab), bwd ? "batch_bwd_stats" : "batch_stats");
         else if (l.kind == STAGE_ZERO) snprintf(lab, sizeof(lab), "batch_bwd_zero");
         else if (l.kind == STAGE_BACKWARD) snprintf(lab, sizeof(lab), "batch_backward_l0");
         else snprintf(lab, sizeof(lab), "batch_match_%s_l%d", mode_name[l.mode], l.level);
         const int slot = timed ? timing_begin(lab, s) : -1;
         hipError_t e;
-        if (l.kind == STAGE_REDUCE) e = launch_reduce_multi(a, l.blocks, s);
+        if (l.kind == STAGE_LEVELS) e = launch_levels_multi(cfg->half_window, a, l.blocks, s);
         else if (l.kind == STAGE_STATS) e = launch_stats_multi(cfg->half_window, a, l.blocks, s);
         else if (l.kind == STAGE_ZERO) {
             hipLaunchKernelGGL(zero_multi_kernel, dim3(l.blocks), dim3(256), 0, s, a);

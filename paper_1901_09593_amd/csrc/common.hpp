@@ -92,6 +92,17 @@ struct StatsArgs {
     double var_eps;
 };
 
+// Two or three pyramid steps in one launch: source level (the caller's input or
+// a float level) to levels +1 .. +steps, both views.
+constexpr int TW_MAXS = 3;
+struct TowerArgs {
+    const void* src[2];
+    float* dst[TW_MAXS][2];   // level +1+j of each view (float, pitch W[j])
+    int Hs, Ws, spitch;       // source level
+    int H[TW_MAXS], W[TW_MAXS];  // levels +1 .. +steps
+    int steps;                // 2 or 3
+};
+
 struct ConvertArgs {
     const void* src;
     float* dst;
@@ -167,11 +178,12 @@ __device__ __forceinline__ float to_f(T v) { return static_cast<float>(v); }
 hipError_t launch_reduce(int dtype, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_convert(int dtype, const ConvertArgs& a, hipStream_t s);
 hipError_t launch_stats(StatsArgs a, hipStream_t s);
+hipError_t launch_tower(int dtype, const TowerArgs& a, hipStream_t s);
 hipError_t launch_match(int n, int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
 
 // Multi-segment launches (batched path); `blocks` = total tiles of the segments.
 hipError_t launch_match_multi(int n, int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);
-hipError_t launch_reduce_multi(const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_levels_multi(int n, const MultiArgs& a, int blocks, hipStream_t s);
 hipError_t launch_stats_multi(int n, const MultiArgs& a, int blocks, hipStream_t s);
 hipError_t launch_match_multi_n1(int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);
 hipError_t launch_match_multi_n2(int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);

@@ -27,35 +27,52 @@ __global__ __launch_bounds__(256) void convert_kernel(ConvertArgs a)
     a.dst[(size_t)y * a.dpitch + x] = to_f(static_cast<const T*>(a.src)[(size_t)y * a.spitch + x]);
 }
 
-// Statistics of every (level, view) segment listed in the arguments, one launch.
+// Statistics tile b of a list of segment pairs (the two views of one level);
+// a tile covers both views.
 template <int NW>
-__global__ __launch_bounds__(256) void stats_kernel(StatsArgs a)
+__device__ __forceinline__ void stats_block(const StatsArgs& a, int b, StatsSmem<NW>& sm)
 {
-    __shared__ StatsSmem sm;
-    int b = blockIdx.x, sgi = 0;
-    while (sgi + 1 < a.nseg && b >= a.seg[sgi + 1].tile0) ++sgi;
+    int sgi = 0;
+    while (sgi + 2 < a.nseg && b >= a.seg[sgi + 2].tile0) sgi += 2;
     const StatsSeg& g = a.seg[sgi];
+    const StatsSeg& h = a.seg[sgi + 1];
     const int t = b - g.tile0;
     const int tw = (g.W + ST_W - 1) / ST_W;
     const int x0 = (t % tw) * ST_W, y0 = (t / tw) * ST_H;
     if (g.dtype == 0)
-        stats_tile<uint8_t, NW>((const uint8_t*)g.src, g.H, g.W, g.spitch, g.dst, g.dpitch, a.var_eps, x0,
-                                y0, sm);
+        stats_tile<uint8_t, NW>((const uint8_t*)g.src, g.dst, (const uint8_t*)h.src, h.dst, g.H, g.W, g.spitch,
+                                g.dpitch, a.var_eps, x0, y0, sm);
     else
-        stats_tile<float, NW>((const float*)g.src, g.H, g.W, g.spitch, g.dst, g.dpitch, a.var_eps, x0, y0,
-                              sm);
+        stats_tile<float, NW>((const float*)g.src, g.dst, (const float*)h.src, h.dst, g.H, g.W, g.spitch,
+                              g.dpitch, a.var_eps, x0, y0, sm);
 }
 
-// Pyramid reduce of several (pair, level) segments in one launch; a tile reads
-// level k-1 of its pair (the caller's input at k = 1) and writes level k.
-__global__ __launch_bounds__(256) void reduce_multi_kernel(MultiArgs a)
+// Statistics of every level listed in the arguments, one launch.
+template <int NW>
+__global__ __launch_bounds__(256) void stats_kernel(StatsArgs a)
 {
-    __shared__ ReduceSmem sm;
-    const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
+    __shared__ StatsSmem<NW> sm;
+    stats_block<NW>(a, blockIdx.x, sm);
+}
+
+// Two or three pyramid steps of both views in one launch (grid: last-level
+// tiles x 2 views); the small levels' reduces alone would each be a launch
+// whose few workgroups leave most of the chip idle.
+template <typename T, int S>
+__global__ __launch_bounds__(TW_THREADS) void tower_kernel(TowerArgs a)
+{
+    __shared__ TowerSmem<T, S> sm;
+    tower_tile<T, S>(a, blockIdx.z, blockIdx.x, blockIdx.y, sm);
+}
+
+// Tile t of a reduce segment: reads level k-1 of its pair (the caller's input
+// at k = 1) and writes level k of one view.
+__device__ __forceinline__ void reduce_seg_tile(const MultiArgs& a, const Segment& s, int t, ReduceSmem& sm)
+{
     const LevelDesc* lv = a.levels + a.level_base[s.pair];
     const LevelDesc& P = lv[s.level - 1];
     const LevelDesc& L = lv[s.level];
-    const int per = s.tiles_x * s.tiles_y, t = blockIdx.x - s.task0;
+    const int per = s.tiles_x * s.tiles_y;
     const int v = t / per, tx = (t % per) % s.tiles_x, ty = (t % per) / s.tiles_x;
     ReduceArgs ra{};  // the tile's view only, so no dynamic indexing
     ra.src[0] = v ? P.img[1] : P.img[0];
@@ -71,21 +88,41 @@ __global__ __launch_bounds__(256) void reduce_multi_kernel(MultiArgs a)
     else reduce_tile<float>(ra, 0, tx, ty, sm);
 }
 
+// Tile t of a statistics segment: both views of one level of its pair.
+template <int NW>
+__device__ __forceinline__ void stats_seg_tile(const MultiArgs& a, const Segment& s, int t, StatsSmem<NW>& sm)
+{
+    const LevelDesc& L = a.levels[a.level_base[s.pair] + s.level];
+    const int x0 = (t % s.tiles_x) * ST_W, y0 = (t / s.tiles_x) * ST_H;
+    if (L.dtype == 0)
+        stats_tile<uint8_t, NW>((const uint8_t*)L.img[0], L.stat[0], (const uint8_t*)L.img[1], L.stat[1], L.H, L.W,
+                                L.pitch, L.W, a.var_eps, x0, y0, sm);
+    else
+        stats_tile<float, NW>((const float*)L.img[0], L.stat[0], (const float*)L.img[1], L.stat[1], L.H, L.W,
+                              L.pitch, L.W, a.var_eps, x0, y0, sm);
+}
+
 // Window statistics of several (pair, level) segments in one launch.
 template <int NW>
 __global__ __launch_bounds__(256) void stats_multi_kernel(MultiArgs a)
 {
-    __shared__ StatsSmem sm;
+    __shared__ StatsSmem<NW> sm;
     const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
-    const LevelDesc& L = a.levels[a.level_base[s.pair] + s.level];
-    const int per = s.tiles_x * s.tiles_y, t = blockIdx.x - s.task0;
-    const int v = t / per, x0 = ((t % per) % s.tiles_x) * ST_W, y0 = ((t % per) / s.tiles_x) * ST_H;
-    if (L.dtype == 0)
-        stats_tile<uint8_t, NW>((const uint8_t*)L.img[v], L.H, L.W, L.pitch, L.stat[v], L.W, a.var_eps, x0, y0,
-                                sm);
-    else
-        stats_tile<float, NW>((const float*)L.img[v], L.H, L.W, L.pitch, L.stat[v], L.W, a.var_eps, x0, y0,
-                              sm);
+    stats_seg_tile<NW>(a, s, blockIdx.x - s.task0, sm);
+}
+
+// Statistics and reduce segments side by side in one launch (one pyramid step
+// of every pair of a batch).
+template <int NW>
+__global__ __launch_bounds__(256) void levels_multi_kernel(MultiArgs a)
+{
+    __shared__ union {
+        StatsSmem<NW> st;
+        ReduceSmem rd;
+    } sm;
+    const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
+    if (s.type == SEG_STATS) stats_seg_tile<NW>(a, s, blockIdx.x - s.task0, sm.st);
+    else reduce_seg_tile(a, s, blockIdx.x - s.task0, sm.rd);
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(float* a, float* b, size_t count)
@@ -126,14 +163,42 @@ hipError_t launch_convert(int dtype, const ConvertArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Checks the segment pairs and numbers their tiles; returns the tile count, or
+// -1 when the list is invalid.
+static int number_stats_tiles(StatsArgs& a)
+{
+    if (a.n < 1 || a.n > ST_MAXN || a.nseg < 2 || a.nseg > STATS_MAX_SEG || (a.nseg & 1)) return -1;
+    int tiles = 0;
+    for (int i = 0; i < a.nseg; i += 2) {
+        const StatsSeg& g = a.seg[i];
+        const StatsSeg& h = a.seg[i + 1];
+        if (g.H != h.H || g.W != h.W || g.dtype != h.dtype || g.spitch != h.spitch || g.dpitch != h.dpitch)
+            return -1;  // a tile covers both views of one level
+        a.seg[i].tile0 = a.seg[i + 1].tile0 = tiles;
+        tiles += stats_tiles(g.H, g.W);
+    }
+    return tiles;
+}
+
+hipError_t launch_tower(int dtype, const TowerArgs& a, hipStream_t s)
+{
+    if (a.steps < 2 || a.steps > TW_MAXS) return hipErrorInvalidValue;
+    const int Hl = a.H[a.steps - 1], Wl = a.W[a.steps - 1];
+    dim3 grid((Wl + TW_FW - 1) / TW_FW, (Hl + TW_FH - 1) / TW_FH, 2);
+    if (dtype == 0) {
+        if (a.steps == 2) hipLaunchKernelGGL((tower_kernel<uint8_t, 2>), grid, dim3(TW_THREADS), 0, s, a);
+        else hipLaunchKernelGGL((tower_kernel<uint8_t, 3>), grid, dim3(TW_THREADS), 0, s, a);
+    } else {
+        if (a.steps == 2) hipLaunchKernelGGL((tower_kernel<float, 2>), grid, dim3(TW_THREADS), 0, s, a);
+        else hipLaunchKernelGGL((tower_kernel<float, 3>), grid, dim3(TW_THREADS), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_stats(StatsArgs a, hipStream_t s)
 {
-    if (a.n < 1 || a.n > ST_MAXN || a.nseg < 1 || a.nseg > STATS_MAX_SEG) return hipErrorInvalidValue;
-    int tiles = 0;
-    for (int i = 0; i < a.nseg; ++i) {
-        a.seg[i].tile0 = tiles;
-        tiles += stats_tiles(a.seg[i].H, a.seg[i].W);
-    }
+    const int tiles = number_stats_tiles(a);
+    if (tiles < 0) return hipErrorInvalidValue;
     switch (a.n) {
         case 1: hipLaunchKernelGGL(stats_kernel<1>, dim3(tiles), dim3(256), 0, s, a); break;
         case 2: hipLaunchKernelGGL(stats_kernel<2>, dim3(tiles), dim3(256), 0, s, a); break;
@@ -145,10 +210,18 @@ hipError_t launch_stats(StatsArgs a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_reduce_multi(const MultiArgs& a, int blocks, hipStream_t s)
+hipError_t launch_levels_multi(int n, const MultiArgs& a, int blocks, hipStream_t s)
 {
     if (blocks < 1 || a.nseg < 1) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(reduce_multi_kernel, dim3(blocks), dim3(256), 0, s, a);
+    switch (n) {
+        case 1: hipLaunchKernelGGL(levels_multi_kernel<1>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(levels_multi_kernel<2>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 3: hipLaunchKernelGGL(levels_multi_kernel<3>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 4: hipLaunchKernelGGL(levels_multi_kernel<4>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 5: hipLaunchKernelGGL(levels_multi_kernel<5>, dim3(blocks), dim3(256), 0, s, a); break;
+        case 6: hipLaunchKernelGGL(levels_multi_kernel<6>, dim3(blocks), dim3(256), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -80,9 +80,139 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
     reduce_tile<T>(a, blockIdx.z, blockIdx.x, blockIdx.y, sm);
 }
 
+// Several pyramid steps in one workgroup ("tower"): the tile of the last level
+// (TW_FH x TW_FW pixels) together with every level's region that it depends on.
+// Step j maps the region of level j-1 to that of level j: region rows
+// R_{j-1} = 2 R_j + 3 (the 5-tap halo at stride 2), origin o_{j-1} = 2 o_j - 2.
+// Region row r of level j holds level row clamp(o_j + r), so the clamp-to-edge
+// reads of a plain reduce become reads at clamped region indices, and every
+// value is computed with the same operations in the same order as reduce_tile:
+// the results are identical.  The tile writes the part of each level it owns
+// (the last-level tile scaled by 2^(S-j)).
+constexpr int TW_FH = 8, TW_FW = 16, TW_THREADS = 512;
+constexpr int tw_rows(int S, int j) { return j >= S ? TW_FH : 2 * tw_rows(S, j + 1) + 3; }
+constexpr int tw_cols(int S, int j) { return j >= S ? TW_FW : 2 * tw_cols(S, j + 1) + 3; }
+constexpr int tw_level_floats(int S)  // regions of levels 1 .. S-1
+{
+    int f = 0;
+    for (int j = 1; j < S; ++j) f += tw_rows(S, j) * tw_cols(S, j);
+    return f;
+}
+constexpr int tw_max(int a, int b) { return a > b ? a : b; }
+
+template <typename T, int S>
+struct TowerSmem {
+    static constexpr int IR = tw_rows(S, 0), IC = tw_cols(S, 0);
+    static constexpr int A_BYTES = tw_max(IR * IC * (int)sizeof(T), tw_level_floats(S) * 4);
+    // area a: the staged source region, then the regions of levels 1 .. S-1
+    alignas(16) unsigned char a[(A_BYTES + 15) / 16 * 16];
+    // area b: horizontal sums of the current step
+    float b[IR * tw_cols(S, 1)];
+};
+
+// Step j of a tower: horizontal 5-tap sums at even region columns of the level
+// j-1 region `in` (IR x 2 OC + 3), then vertical sums at even rows into the
+// level j region (OR x OC), stored to `out` (LDS) or, for the last step, only to
+// global memory; a pixel the tile owns also goes to `dst`.
+template <typename Tin, int IR, int OR, int OC>
+__device__ __forceinline__ void tower_step(const Tin* in, float* hs, float* out, int o_r, int o_c, int Ho, int Wo,
+                                           int own_r, int own_c, int own_n_r, int own_n_c, float* __restrict__ dst,
+                                           int dpitch)
+{
+    constexpr int IC = 2 * OC + 3;
+    const float w[5] = {1.f, 4.f, 6.f, 4.f, 1.f};
+#pragma unroll 4
+    for (int idx = threadIdx.x; idx < IR * OC; idx += TW_THREADS) {
+        const int r = idx / OC, c = idx - r * OC;
+        const int cc = 2 * (clampi(o_c + c, 0, Wo - 1) - o_c);
+        const Tin* row = in + r * IC + cc;
+        float h = 0.f;
+#pragma unroll
+        for (int b = 0; b < 5; ++b) h = fmaf(w[b], to_f(row[b]), h);
+        hs[idx] = h;
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int idx = threadIdx.x; idx < OR * OC; idx += TW_THREADS) {
+        const int r = idx / OC, c = idx - r * OC;
+        const int rr = 2 * (clampi(o_r + r, 0, Ho - 1) - o_r);
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) acc = fmaf(w[t], hs[(rr + t) * OC + c], acc);
+        acc *= (1.f / 256.f);
+        if (out) out[idx] = acc;
+        const int gy = o_r + r, gx = o_c + c;
+        if (r >= own_r && r < own_r + own_n_r && c >= own_c && c < own_c + own_n_c && gy < Ho && gx < Wo)
+            dst[(size_t)gy * dpitch + gx] = acc;
+    }
+    __syncthreads();  // the next step overwrites hs, and reads out
+}
+
+// One tower tile of one view: S pyramid steps from the source level.
+template <typename T, int S>
+__device__ __forceinline__ void tower_tile(const TowerArgs& a, int view, int tx, int ty, TowerSmem<T, S>& sm)
+{
+    static_assert(S >= 2 && S <= TW_MAXS, "tower of 2 or 3 steps");
+    constexpr int IR = tw_rows(S, 0), IC = tw_cols(S, 0);
+    // region origins, last level first
+    int o_r[S + 1], o_c[S + 1];
+    o_r[S] = ty * TW_FH;
+    o_c[S] = tx * TW_FW;
+#pragma unroll
+    for (int j = S; j > 0; --j) {
+        o_r[j - 1] = 2 * o_r[j] - 2;
+        o_c[j - 1] = 2 * o_c[j] - 2;
+    }
+    // stage the source region: lanes along columns (64-column groups), waves
+    // down the rows; every load issued before the LDS stores, so that they share
+    // one latency (positions past the region re-read its last row or column)
+    const T* __restrict__ src = static_cast<const T*>(a.src[view]);
+    T* in = reinterpret_cast<T*>(sm.a);
+    constexpr int NWV = TW_THREADS / 64, RI = (IR + NWV - 1) / NWV, CI = (IC + 63) / 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    {
+        int col[CI];
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci) col[ci] = clampi(o_c[0] + min(lane + 64 * ci, IC - 1), 0, a.Ws - 1);
+        T v[RI][CI];
+#pragma unroll
+        for (int ri = 0; ri < RI; ++ri) {
+            const T* srow = src + (size_t)clampi(o_r[0] + min(wave + NWV * ri, IR - 1), 0, a.Hs - 1) * a.spitch;
+#pragma unroll
+            for (int ci = 0; ci < CI; ++ci) v[ri][ci] = srow[col[ci]];
+        }
+#pragma unroll
+        for (int ri = 0; ri < RI; ++ri) {
+            const int r = wave + NWV * ri;
+#pragma unroll
+            for (int ci = 0; ci < CI; ++ci) {
+                const int c = lane + 64 * ci;
+                if (r < IR && c < IC) in[r * IC + c] = v[ri][ci];
+            }
+        }
+    }
+    __syncthreads();
+    float* lev = reinterpret_cast<float*>(sm.a);
+    constexpr int L1 = tw_rows(S, 1) * tw_cols(S, 1);
+    // step 1 reads the source (area a) and writes level 1 into area a: the
+    // horizontal pass has consumed the source before the vertical pass writes
+    tower_step<T, IR, tw_rows(S, 1), tw_cols(S, 1)>(in, sm.b, lev, o_r[1], o_c[1], a.H[0], a.W[0],
+                                                    2 * (1 << (S - 1)) - 2, 2 * (1 << (S - 1)) - 2,
+                                                    TW_FH << (S - 1), TW_FW << (S - 1), a.dst[0][view], a.W[0]);
+    if (S == 3) {
+        tower_step<float, tw_rows(S, 1), tw_rows(S, 2), tw_cols(S, 2)>(lev, sm.b, lev + L1, o_r[2], o_c[2], a.H[1],
+                                                                       a.W[1], 2, 2, TW_FH << 1, TW_FW << 1,
+                                                                       a.dst[1][view], a.W[1]);
+        tower_step<float, tw_rows(S, 2), TW_FH, TW_FW>(lev + L1, sm.b, nullptr, o_r[3], o_c[3], a.H[2], a.W[2], 0, 0,
+                                                       TW_FH, TW_FW, a.dst[2][view], a.W[2]);
+    } else {
+        tower_step<float, tw_rows(S, 1), TW_FH, TW_FW>(lev, sm.b, nullptr, o_r[2], o_c[2], a.H[1], a.W[1], 0, 0,
+                                                       TW_FH, TW_FW, a.dst[1][view], a.W[1]);
+    }
+}
+
 constexpr int ST_W = 64, ST_H = 16, ST_MAXN = 6;
 constexpr int ST_SEG = 8;                               // outputs per thread, horizontal pass
-constexpr int ST_RH = ST_H + 2 * ST_MAXN;               // 28 rows with halo
 
 // One 16 x 64 tile of one view of one level.  Horizontal window sums of x and x^2
 // in double precision (running sums over 8 outputs per thread, read straight from
@@ -94,32 +224,45 @@ constexpr int ST_RH = ST_H + 2 * ST_MAXN;               // 28 rows with halo
 constexpr int ST_HS = 73;  // row stride (doubles)
 __device__ __forceinline__ int st_idx(int row, int col) { return row * ST_HS + (col >> 3) * 9 + (col & 7); }
 
-struct StatsSmem {
-    double h1[ST_RH * ST_HS];
-    double h2[ST_RH * ST_HS];
+template <int NW>
+struct StatsSmem {  // horizontal sums of the tile's rows with their window halo
+    double h1[(ST_H + 2 * NW) * ST_HS];
+    double h2[(ST_H + 2 * NW) * ST_HS];
 };
 
+// Statistics of one 16 x 64 tile of both views (A and B) of one level.  Every
+// input load of both views is issued first, so view B's loads are in flight
+// while view A is computed.
 template <typename T, int NW>
-__device__ __forceinline__ void stats_tile(const T* __restrict__ src, int H, int W, int spitch,
-                                           float4* __restrict__ dst, int dpitch, double var_eps,
-                                           int x0, int y0, StatsSmem& sm)
+__device__ __forceinline__ void stats_tile(const T* __restrict__ srcA, float4* __restrict__ dstA,
+                                           const T* __restrict__ srcB, float4* __restrict__ dstB, int H, int W,
+                                           int spitch, int dpitch, double var_eps, int x0, int y0, StatsSmem<NW>& sm)
 {
     double* h1 = sm.h1;
     double* h2 = sm.h2;
-    constexpr int n = NW, wn = 2 * NW + 1, rows = ST_H + 2 * NW;
-    const double c = (double)to_f(src[(size_t)min(y0, H - 1) * spitch + min(x0, W - 1)]);
-    // horizontal pass: thread = (row, 8-column segment)
-    {
-        const int seg = threadIdx.x & 7, rr = threadIdx.x >> 3;  // 32 rows x 8 segments
+    constexpr int n = NW, wn = 2 * NW + 1, rows = ST_H + 2 * NW, NF = ST_SEG + 2 * NW;
+    const size_t corner = (size_t)min(y0, H - 1) * spitch + min(x0, W - 1);
+    const double cv[2] = {(double)to_f(srcA[corner]), (double)to_f(srcB[corner])};
+    // horizontal pass inputs: thread = (row, 8-column segment)
+    const int seg = threadIdx.x & 7, rr = threadIdx.x >> 3;  // 32 rows x 8 segments
+    const size_t ro = (size_t)clampi(y0 - n + min(rr, rows - 1), 0, H - 1) * spitch;
+    const int cx = x0 + ST_SEG * seg - n;
+    float f[2][NF];
+#pragma unroll
+    for (int t = 0; t < NF; ++t) {
+        f[0][t] = to_f(srcA[ro + clampi(cx + t, 0, W - 1)]);
+        f[1][t] = to_f(srcB[ro + clampi(cx + t, 0, W - 1)]);
+    }
+    const int col = threadIdx.x & 63, rs = (threadIdx.x >> 6) * 4;
+    const double N = (double)(wn * wn), invN = 1.0 / N;
+#pragma unroll
+    for (int vw = 0; vw < 2; ++vw) {
+        const double c = cv[vw];
+        float4* __restrict__ dst = vw ? dstB : dstA;
         if (rr < rows) {
-            const T* srow = src + (size_t)clampi(y0 - n + rr, 0, H - 1) * spitch;
-            const int cx = x0 + ST_SEG * seg - n;
-            float f[ST_SEG + 2 * NW];
+            double v[NF];
 #pragma unroll
-            for (int t = 0; t < ST_SEG + 2 * NW; ++t) f[t] = to_f(srow[clampi(cx + t, 0, W - 1)]);
-            double v[ST_SEG + 2 * NW];
-#pragma unroll
-            for (int t = 0; t < ST_SEG + 2 * NW; ++t) v[t] = (double)f[t] - c;
+            for (int t = 0; t < NF; ++t) v[t] = (double)f[vw][t] - c;
             double s1 = 0.0, s2 = 0.0;
 #pragma unroll
             for (int t = 0; t < wn; ++t) {
@@ -137,33 +280,31 @@ __device__ __forceinline__ void stats_tile(const T* __restrict__ src, int H, int
                 h2[st_idx(rr, ST_SEG * seg + k)] = s2;
             }
         }
-    }
-    __syncthreads();
-    // vertical pass: thread = (column, 4-row segment)
-    const int col = threadIdx.x & 63, rs = (threadIdx.x >> 6) * 4;
-    const double N = (double)(wn * wn), invN = 1.0 / N;
-    double s1 = 0.0, s2 = 0.0;
+        __syncthreads();
+        // vertical pass: thread = (column, 4-row segment)
+        double s1 = 0.0, s2 = 0.0;
 #pragma unroll
-    for (int t = 0; t < wn; ++t) {
-        s1 += h1[st_idx(rs + t, col)];
-        s2 += h2[st_idx(rs + t, col)];
-    }
+        for (int t = 0; t < wn; ++t) {
+            s1 += h1[st_idx(rs + t, col)];
+            s2 += h2[st_idx(rs + t, col)];
+        }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        if (k > 0) {
-            s1 += h1[st_idx(rs + k - 1 + wn, col)] - h1[st_idx(rs + k - 1, col)];
-            s2 += h2[st_idx(rs + k - 1 + wn, col)] - h2[st_idx(rs + k - 1, col)];
+        for (int k = 0; k < 4; ++k) {
+            if (k > 0) {
+                s1 += h1[st_idx(rs + k - 1 + wn, col)] - h1[st_idx(rs + k - 1, col)];
+                s2 += h2[st_idx(rs + k - 1 + wn, col)] - h2[st_idx(rs + k - 1, col)];
+            }
+            const int gy = y0 + rs + k, gx = x0 + col;
+            if (gy < H && gx < W) {
+                const double A = s2 - s1 * s1 * invN;
+                const float inv = (A <= N * var_eps) ? 0.f : rsqrtf((float)A);
+                const double mu = c + s1 * invN;
+                const float hi = (float)mu;
+                dst[(size_t)gy * dpitch + gx] = make_float4(hi, (float)(mu - (double)hi), inv, 0.f);
+            }
         }
-        const int gy = y0 + rs + k, gx = x0 + col;
-        if (gy < H && gx < W) {
-            const double A = s2 - s1 * s1 * invN;
-            const float inv = (A <= N * var_eps) ? 0.f : rsqrtf((float)A);
-            const double mu = c + s1 * invN;
-            const float hi = (float)mu;
-            dst[(size_t)gy * dpitch + gx] = make_float4(hi, (float)(mu - (double)hi), inv, 0.f);
-        }
+        __syncthreads();  // LDS is reused by the next view and the caller's next tile
     }
-    __syncthreads();  // LDS may be reused by the caller's next tile
 }
 
 }  // namespace msibm

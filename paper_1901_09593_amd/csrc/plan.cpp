@@ -57,29 +57,50 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
     img[0][0] = P.left;
     img[0][1] = P.right;
     pitch[0] = P.pitch;
-    for (int k = 1; k < K; ++k) {
-        ReduceArgs r{};
-        r.src[0] = img[k - 1][0];
-        r.src[1] = img[k - 1][1];
-        r.dst[0] = (float*)(ws + lay.img[k][0]);
-        r.dst[1] = (float*)(ws + lay.img[k][1]);
-        r.views = 2;
-        r.H = lay.h[k - 1];
-        r.W = lay.w[k - 1];
-        r.spitch = pitch[k - 1];
-        r.Ho = lay.h[k];
-        r.Wo = lay.w[k];
-        r.dpitch = lay.w[k];
-        char lab[32];
-        snprintf(lab, sizeof(lab), "reduce_l%d", k);
-        {
-            TimedLaunch t(lab, s);
-            e = launch_reduce(k == 1 ? P.dtype : MSIBM_F32, r, s);
+    // the pyramid: up to three steps per launch
+    for (int k = 1; k < K;) {
+        const int steps = K - k < TW_MAXS ? K - k : TW_MAXS;
+        const int dt = k == 1 ? P.dtype : MSIBM_F32;
+        for (int j = 0; j < steps; ++j) {
+            img[k + j][0] = ws + lay.img[k + j][0];
+            img[k + j][1] = ws + lay.img[k + j][1];
+            pitch[k + j] = lay.w[k + j];
         }
-        if (e != hipSuccess) return hip_err(e, "reduce launch", err);
-        img[k][0] = r.dst[0];
-        img[k][1] = r.dst[1];
-        pitch[k] = lay.w[k];
+        char lab[32];
+        snprintf(lab, sizeof(lab), steps == 1 ? "reduce_l%d" : "pyramid_l%d", k);
+        TimedLaunch t(lab, s);
+        if (steps == 1) {
+            ReduceArgs r{};
+            r.src[0] = img[k - 1][0];
+            r.src[1] = img[k - 1][1];
+            r.dst[0] = (float*)img[k][0];
+            r.dst[1] = (float*)img[k][1];
+            r.views = 2;
+            r.H = lay.h[k - 1];
+            r.W = lay.w[k - 1];
+            r.spitch = pitch[k - 1];
+            r.Ho = lay.h[k];
+            r.Wo = lay.w[k];
+            r.dpitch = lay.w[k];
+            e = launch_reduce(dt, r, s);
+        } else {
+            TowerArgs ta{};
+            ta.src[0] = img[k - 1][0];
+            ta.src[1] = img[k - 1][1];
+            ta.Hs = lay.h[k - 1];
+            ta.Ws = lay.w[k - 1];
+            ta.spitch = pitch[k - 1];
+            for (int j = 0; j < steps; ++j) {
+                ta.dst[j][0] = (float*)img[k + j][0];
+                ta.dst[j][1] = (float*)img[k + j][1];
+                ta.H[j] = lay.h[k + j];
+                ta.W[j] = lay.w[k + j];
+            }
+            ta.steps = steps;
+            e = launch_tower(dt, ta, s);
+        }
+        if (e != hipSuccess) return hip_err(e, "pyramid launch", err);
+        k += steps;
     }
     {
         StatsArgs sa{};
