@@ -70,7 +70,7 @@ __global__ __launch_bounds__(256) void zero_multi_kernel(MultiArgs a)
 
 // Tiles of one level: reduce tiles cover one view each, statistics and
 // matching tiles both.
-static Segment make_seg(int type, int p, int k, int h, int w, int task0)
+static Segment make_seg(int type, int p, int k, int h, int w, int dtype, int task0)
 {
     Segment s{};
     s.type = type;
@@ -82,7 +82,7 @@ static Segment make_seg(int type, int p, int k, int h, int w, int task0)
         s.views = 2;
     } else if (type == SEG_STATS) {  // a statistics tile covers both views
         s.tiles_x = cdiv(w, ST_W);
-        s.tiles_y = cdiv(h, ST_H);
+        s.tiles_y = cdiv(h, stats_tile_h(dtype));
         s.views = 1;
     } else if (type == SEG_ZERO) {
         s.tiles_x = (int)(((size_t)h * w + ZERO_TILE - 1) / ZERO_TILE);
@@ -134,7 +134,7 @@ static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg
     };
     auto add = [&](int type, int p, int k) {
         StageLaunch& l = pl.launches.back();
-        const Segment s = make_seg(type, p, k, h_of(p, k), w_of(p, k), l.blocks);
+        const Segment s = make_seg(type, p, k, h_of(p, k), w_of(p, k), k == 0 ? pairs[p].dtype : MSIBM_F32, l.blocks);
         l.blocks += seg_tiles(s);
         l.nseg++;
         pl.segs.push_back(s);
@@ -187,7 +187,7 @@ static void plan_backward_stages(const msibm_pair* pairs, int np, BatchPlan& pl)
         l.kind = kinds[q];
         l.first = (int)pl.segs.size();
         for (int p = 0; p < np; ++p) {
-            const Segment sg = make_seg(types[q], p, 0, pairs[p].height, pairs[p].width, l.blocks);
+            const Segment sg = make_seg(types[q], p, 0, pairs[p].height, pairs[p].width, pairs[p].dtype, l.blocks);
             l.blocks += seg_tiles(sg);
             l.nseg++;
             pl.segs.push_back(sg);

@@ -38,10 +38,10 @@ __device__ __forceinline__ void stats_block(const StatsArgs& a, int b, StatsSmem
     const StatsSeg& h = a.seg[sgi + 1];
     const int t = b - g.tile0;
     const int tw = (g.W + ST_W - 1) / ST_W;
-    const int x0 = (t % tw) * ST_W, y0 = (t / tw) * ST_H;
+    const int x0 = (t % tw) * ST_W, y0 = (t / tw) * stats_tile_h(g.dtype);
     if (g.dtype == 0)
-        stats_tile<uint8_t, NW>((const uint8_t*)g.src, g.dst, (const uint8_t*)h.src, h.dst, g.H, g.W, g.spitch,
-                                g.dpitch, a.var_eps, x0, y0, sm);
+        stats_tile_u8<NW>((const uint8_t*)g.src, g.dst, (const uint8_t*)h.src, h.dst, g.H, g.W, g.spitch, g.dpitch,
+                          a.var_eps, x0, y0, sm);
     else
         stats_tile<float, NW>((const float*)g.src, g.dst, (const float*)h.src, h.dst, g.H, g.W, g.spitch,
                               g.dpitch, a.var_eps, x0, y0, sm);
@@ -93,10 +93,10 @@ template <int NW>
 __device__ __forceinline__ void stats_seg_tile(const MultiArgs& a, const Segment& s, int t, StatsSmem<NW>& sm)
 {
     const LevelDesc& L = a.levels[a.level_base[s.pair] + s.level];
-    const int x0 = (t % s.tiles_x) * ST_W, y0 = (t / s.tiles_x) * ST_H;
+    const int x0 = (t % s.tiles_x) * ST_W, y0 = (t / s.tiles_x) * stats_tile_h(L.dtype);
     if (L.dtype == 0)
-        stats_tile<uint8_t, NW>((const uint8_t*)L.img[0], L.stat[0], (const uint8_t*)L.img[1], L.stat[1], L.H, L.W,
-                                L.pitch, L.W, a.var_eps, x0, y0, sm);
+        stats_tile_u8<NW>((const uint8_t*)L.img[0], L.stat[0], (const uint8_t*)L.img[1], L.stat[1], L.H, L.W,
+                          L.pitch, L.W, a.var_eps, x0, y0, sm);
     else
         stats_tile<float, NW>((const float*)L.img[0], L.stat[0], (const float*)L.img[1], L.stat[1], L.H, L.W,
                               L.pitch, L.W, a.var_eps, x0, y0, sm);
@@ -141,7 +141,11 @@ hipError_t launch_zero(float* a, float* b, size_t count, hipStream_t s)
     return hipGetLastError();
 }
 
-int stats_tiles(int H, int W) { return ((W + ST_W - 1) / ST_W) * ((H + ST_H - 1) / ST_H); }
+int stats_tiles(int H, int W, int dtype)
+{
+    const int th = stats_tile_h(dtype);
+    return ((W + ST_W - 1) / ST_W) * ((H + th - 1) / th);
+}
 
 hipError_t launch_reduce(int dtype, const ReduceArgs& a, hipStream_t s)
 {
@@ -175,7 +179,7 @@ static int number_stats_tiles(StatsArgs& a)
         if (g.H != h.H || g.W != h.W || g.dtype != h.dtype || g.spitch != h.spitch || g.dpitch != h.dpitch)
             return -1;  // a tile covers both views of one level
         a.seg[i].tile0 = a.seg[i + 1].tile0 = tiles;
-        tiles += stats_tiles(g.H, g.W);
+        tiles += stats_tiles(g.H, g.W, g.dtype);
     }
     return tiles;
 }

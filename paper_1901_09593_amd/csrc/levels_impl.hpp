@@ -224,11 +224,31 @@ constexpr int ST_SEG = 8;                               // outputs per thread, h
 constexpr int ST_HS = 73;  // row stride (doubles)
 __device__ __forceinline__ int st_idx(int row, int col) { return row * ST_HS + (col >> 3) * 9 + (col & 7); }
 
+// uint8 levels use 32-row tiles with integer sums: centred pixel values, their
+// squares and every window sum are exact integers (below 2^24 for n <= 6), and
+// the tile's sums fit the LDS space of a 16-row double tile.  The int sums sit
+// in rows of 65, so that a wave's horizontal stores (8 rows x 8 segments at one
+// offset) fall in distinct banks.
+constexpr int SU_H = 32, SU_HS = 65;
+__host__ __device__ inline int stats_tile_h(int dtype) { return dtype == 0 ? SU_H : ST_H; }
+
 template <int NW>
-struct StatsSmem {  // horizontal sums of the tile's rows with their window halo
+struct StatsSmemD {  // horizontal sums of the tile's rows with their window halo
     double h1[(ST_H + 2 * NW) * ST_HS];
     double h2[(ST_H + 2 * NW) * ST_HS];
 };
+template <int NW>
+struct StatsSmemI {
+    int h1[(SU_H + 2 * NW) * SU_HS];
+    int h2[(SU_H + 2 * NW) * SU_HS];
+};
+template <int NW>
+union StatsSmem {
+    StatsSmemD<NW> d;
+    StatsSmemI<NW> i;
+};
+static_assert(sizeof(StatsSmemI<1>) <= sizeof(StatsSmemD<1>) && sizeof(StatsSmemI<6>) <= sizeof(StatsSmemD<6>),
+              "uint8 tiles fit the double tiles' space");
 
 // Statistics of one 16 x 64 tile of both views (A and B) of one level.  Every
 // input load of both views is issued first, so view B's loads are in flight
@@ -238,8 +258,8 @@ __device__ __forceinline__ void stats_tile(const T* __restrict__ srcA, float4* _
                                            const T* __restrict__ srcB, float4* __restrict__ dstB, int H, int W,
                                            int spitch, int dpitch, double var_eps, int x0, int y0, StatsSmem<NW>& sm)
 {
-    double* h1 = sm.h1;
-    double* h2 = sm.h2;
+    double* h1 = sm.d.h1;
+    double* h2 = sm.d.h2;
     constexpr int n = NW, wn = 2 * NW + 1, rows = ST_H + 2 * NW, NF = ST_SEG + 2 * NW;
     const size_t corner = (size_t)min(y0, H - 1) * spitch + min(x0, W - 1);
     const double cv[2] = {(double)to_f(srcA[corner]), (double)to_f(srcB[corner])};
@@ -299,6 +319,117 @@ __device__ __forceinline__ void stats_tile(const T* __restrict__ srcA, float4* _
                 const double A = s2 - s1 * s1 * invN;
                 const float inv = (A <= N * var_eps) ? 0.f : rsqrtf((float)A);
                 const double mu = c + s1 * invN;
+                const float hi = (float)mu;
+                dst[(size_t)gy * dpitch + gx] = make_float4(hi, (float)(mu - (double)hi), inv, 0.f);
+            }
+        }
+        __syncthreads();  // LDS is reused by the next view and the caller's next tile
+    }
+}
+
+// Statistics of one 32 x 64 tile of both views of a uint8 level: the same
+// quantities as stats_tile, from exact integer window sums.
+template <int NW>
+__device__ __forceinline__ void stats_tile_u8(const uint8_t* __restrict__ srcA, float4* __restrict__ dstA,
+                                              const uint8_t* __restrict__ srcB, float4* __restrict__ dstB, int H,
+                                              int W, int spitch, int dpitch, double var_eps, int x0, int y0,
+                                              StatsSmem<NW>& sm)
+{
+    int* h1 = sm.i.h1;
+    int* h2 = sm.i.h2;
+    constexpr int n = NW, wn = 2 * NW + 1, rows = SU_H + 2 * NW, NF = ST_SEG + 2 * NW;
+    constexpr int TASKS = rows * 8, NT = (TASKS + 255) / 256;  // (row, 8-column segment) tasks
+    const size_t corner = (size_t)min(y0, H - 1) * spitch + min(x0, W - 1);
+    const int cv[2] = {srcA[corner], srcB[corner]};
+    // interior tiles of images with 4-byte aligned rows load whole words: a
+    // thread's bytes start at the same offset SH within a word in every row
+    constexpr int SH = (4 - n % 4) % 4, NDW = (SH + NF + 3) / 4;
+    const bool words = x0 - n - SH >= 0 && x0 + ST_W + n + 3 < W && (spitch & 3) == 0 &&
+                       ((reinterpret_cast<uintptr_t>(srcA) | reinterpret_cast<uintptr_t>(srcB)) & 3) == 0;
+    int f[NT][2][NF];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) {
+        const int task = min((int)threadIdx.x + 256 * q, TASKS - 1);
+        const int tr = task >> 3, seg = task & 7;
+        const size_t ro = (size_t)clampi(y0 - n + tr, 0, H - 1) * spitch;
+        const int cx = x0 + ST_SEG * seg - n;
+        if (words) {
+            const uint32_t* pa = reinterpret_cast<const uint32_t*>(srcA + ro + cx - SH);
+            const uint32_t* pb = reinterpret_cast<const uint32_t*>(srcB + ro + cx - SH);
+            uint32_t wa[NDW], wb[NDW];
+#pragma unroll
+            for (int d = 0; d < NDW; ++d) {
+                wa[d] = pa[d];
+                wb[d] = pb[d];
+            }
+#pragma unroll
+            for (int t = 0; t < NF; ++t) {
+                f[q][0][t] = (wa[(t + SH) >> 2] >> (8 * ((t + SH) & 3))) & 0xff;
+                f[q][1][t] = (wb[(t + SH) >> 2] >> (8 * ((t + SH) & 3))) & 0xff;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < NF; ++t) {
+                const int cc = clampi(cx + t, 0, W - 1);
+                f[q][0][t] = srcA[ro + cc];
+                f[q][1][t] = srcB[ro + cc];
+            }
+        }
+    }
+    const int col = threadIdx.x & 63, rs = (threadIdx.x >> 6) * 8;
+    const double N = (double)(wn * wn), invN = 1.0 / N;
+#pragma unroll
+    for (int vw = 0; vw < 2; ++vw) {
+        const int c = cv[vw];
+        float4* __restrict__ dst = vw ? dstB : dstA;
+#pragma unroll
+        for (int q = 0; q < NT; ++q) {
+            const int task = threadIdx.x + 256 * q;
+            if (task < TASKS) {
+                int v[NF], sq[NF];
+#pragma unroll
+                for (int t = 0; t < NF; ++t) {
+                    v[t] = f[q][vw][t] - c;
+                    sq[t] = v[t] * v[t];
+                }
+                int s1 = 0, s2 = 0;
+#pragma unroll
+                for (int t = 0; t < wn; ++t) {
+                    s1 += v[t];
+                    s2 += sq[t];
+                }
+                const int base = (task >> 3) * SU_HS + ST_SEG * (task & 7);
+                h1[base] = s1;
+                h2[base] = s2;
+#pragma unroll
+                for (int k = 1; k < ST_SEG; ++k) {
+                    s1 += v[k - 1 + wn] - v[k - 1];
+                    s2 += sq[k - 1 + wn] - sq[k - 1];
+                    h1[base + k] = s1;
+                    h2[base + k] = s2;
+                }
+            }
+        }
+        __syncthreads();
+        // vertical pass: thread = (column, 8-row segment)
+        int s1 = 0, s2 = 0;
+#pragma unroll
+        for (int t = 0; t < wn; ++t) {
+            s1 += h1[(rs + t) * SU_HS + col];
+            s2 += h2[(rs + t) * SU_HS + col];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            if (k > 0) {
+                s1 += h1[(rs + k - 1 + wn) * SU_HS + col] - h1[(rs + k - 1) * SU_HS + col];
+                s2 += h2[(rs + k - 1 + wn) * SU_HS + col] - h2[(rs + k - 1) * SU_HS + col];
+            }
+            const int gy = y0 + rs + k, gx = x0 + col;
+            if (gy < H && gx < W) {
+                const double d1 = (double)s1, d2 = (double)s2;
+                const double A = d2 - d1 * d1 * invN;
+                const float inv = (A <= N * var_eps) ? 0.f : rsqrtf((float)A);
+                const double mu = (double)c + d1 * invN;
                 const float hi = (float)mu;
                 dst[(size_t)gy * dpitch + gx] = make_float4(hi, (float)(mu - (double)hi), inv, 0.f);
             }
