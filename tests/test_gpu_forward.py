@@ -204,17 +204,21 @@ def test_degenerate_shapes(M, H, W, K):
         assert np.all((d == ref[0][0]) | (gap <= TOL_ZNCC))
 
 
-def test_pitched_input(M):
+@pytest.mark.parametrize("pitch,offset", [(384, 0), (331, 0), (384, 1), (331, 3)])
+def test_pitched_input(M, pitch, offset):
+    """Views with a wider row pitch, odd pitches and unaligned first pixels
+    (uint8 rows then start off word boundaries) give the same maps and scores
+    as a contiguous copy."""
     p, cfg = synth.workload("small320")
-    big_l = torch.zeros((240, 384), dtype=torch.uint8, device="cuda")
-    big_r = torch.zeros((240, 384), dtype=torch.uint8, device="cuda")
-    big_l[:, :320] = dev(p.left)
-    big_r[:, :320] = dev(p.right)
-    a = M.disparity(big_l[:, :320], big_r[:, :320], cfg.max_disp, cfg.levels, cfg.half_window,
-                    cfg.refine_radius, cfg.var_eps)
+    big_l = torch.zeros((240, pitch), dtype=torch.uint8, device="cuda")
+    big_r = torch.zeros((240, pitch), dtype=torch.uint8, device="cuda")
+    big_l[:, offset:offset + 320] = dev(p.left)
+    big_r[:, offset:offset + 320] = dev(p.right)
+    a = M.disparity(big_l[:, offset:offset + 320], big_r[:, offset:offset + 320], cfg.max_disp, cfg.levels,
+                    cfg.half_window, cfg.refine_radius, cfg.var_eps)
     b = M.disparity(dev(p.left), dev(p.right), cfg.max_disp, cfg.levels, cfg.half_window,
                     cfg.refine_radius, cfg.var_eps)
-    assert torch.equal(a["disp"], b["disp"])
+    assert torch.equal(a["disp"], b["disp"]) and torch.equal(a["cost"], b["cost"])
 
 
 # ------------------------------------------------------------------ soft level
