@@ -78,11 +78,12 @@ __device__ __forceinline__ float fval(int k) { return __int_as_float(k >= 0 ? k 
 constexpr int BACK_WAVES = 8;
 constexpr int BACK_THREADS = BACK_WAVES * MATCH_TX;
 
-// Add v (|v * scale| <= 2^30) to a fixed-point LDS cell.
+// Add v (|v * scale| <= 2^30) to a fixed-point LDS cell.  Zeros are added too:
+// a test per value costs more than the add.
 __device__ __forceinline__ void lds_add(long long* p, float v, float scale)
 {
     const int q = (int)rintf(v * scale);
-    if (q != 0) atomicAdd((unsigned long long*)p, (unsigned long long)(long long)q);
+    atomicAdd((unsigned long long*)p, (unsigned long long)(long long)q);
 }
 
 // Add a fixed-point LDS tile in split layout to a global image with float
