@@ -28,8 +28,8 @@
 // tens of times faster than float ones on this chip.  Per chunk the workgroup
 // bounds every value it will add (from the ranges of the staged images and the
 // largest gradient coefficients) and picks a power-of-two scale that maps that
-// bound below 2^30, so each added value rounds to an int32 with a relative
-// resolution of about 2^-30 of the bound and the 64-bit sums cannot overflow.
+// bound below 2^30, so each added value becomes an int32 (truncated) with a
+// resolution of 2^-30 of the bound, and the 64-bit sums cannot overflow.
 #pragma once
 
 #include "match_impl.hpp"
@@ -78,12 +78,13 @@ __device__ __forceinline__ float fval(int k) { return __int_as_float(k >= 0 ? k 
 constexpr int BACK_WAVES = 8;
 constexpr int BACK_THREADS = BACK_WAVES * MATCH_TX;
 
-// Add v (|v * scale| <= 2^30) to a fixed-point LDS cell.  Zeros are added too:
-// a test per value costs more than the add.
+// Add v (|v * scale| <= 2^30) to a fixed-point LDS cell, truncated toward zero:
+// an error below 2^-30 of the chunk's bound per value, far inside the gradient
+// tolerance, one instruction cheaper than rounding.  Zeros are added too: a
+// test per value costs more than the add.
 __device__ __forceinline__ void lds_add(long long* p, float v, float scale)
 {
-    const int q = (int)rintf(v * scale);
-    atomicAdd((unsigned long long*)p, (unsigned long long)(long long)q);
+    atomicAdd((unsigned long long*)p, (unsigned long long)(long long)(int)(v * scale));
 }
 
 // Add a fixed-point LDS tile in split layout to a global image with float
@@ -363,7 +364,8 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
         const float bound = 2.f * fmaxf(KL * lrange + CL + K1 * rrange, QB * rrange + QC + K1 * lrange);
         int be = 0;
         frexpf(bound, &be);  // bound < 2^be
-        const int sh = (bound > 0.f && isfinite(bound)) ? 30 - be : 0;
+        // (at most 2^100, a finite float, for vanishing bounds)
+        const int sh = (bound > 0.f && isfinite(bound)) ? min(30 - be, 100) : 0;
         const float scale = ldexpf(1.f, sh);
         const double inv_scale = ldexp(1.0, -sh);
 
