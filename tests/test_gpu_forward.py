@@ -154,6 +154,28 @@ def test_hierarchy_small320_per_level_and_end_to_end(M):
     assert mism < 0.01
 
 
+@pytest.mark.parametrize("dtype,K", [("u8", 2), ("u8", 3), ("u8", 5), ("u8", 7), ("f32", 3), ("f32", 4),
+                                     ("f32", 6)])
+def test_pyramid_launches_match_level_by_level(M, dtype, K):
+    """The forward builds its pyramid with up to three reduce steps per launch;
+    its maps and scores equal those of single-step pyramids matched level by
+    level (every step count of a launch, both element types)."""
+    p = _tex_pair(40 + K, 150, 262, 8, dtype)
+    D, n, r = 200, 2, 1
+    eps = 0.065 if dtype == "u8" else 1e-6
+    Lg, Rg = dev(p.left), dev(p.right)
+    out = M.disparity(Lg, Rg, D, K, n, r, eps, with_prior1=True)
+    PL, PR = M.pyramid(Lg, K), M.pyramid(Rg, K)
+    maps, costs = [None] * K, [None] * K
+    for k in range(K - 1, -1, -1):
+        Lk = Lg if k == 0 else PL[k]
+        Rk = Rg if k == 0 else PR[k]
+        prior = None if k == K - 1 else maps[k + 1]
+        maps[k], costs[k] = M.match_level(Lk, Rk, n, -(-D // (1 << k)), prior, r, eps)
+    assert torch.equal(maps[0], out["disp"]) and torch.equal(costs[0], out["cost"])
+    assert torch.equal(maps[1], out["prior1"])
+
+
 def test_mid1436_full_size_sampled(M):
     """The benchmark workload at full size, in the launch configuration the
     benchmark times; level 0 checked on sampled pixels against the oracle fed
