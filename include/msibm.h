@@ -200,10 +200,12 @@ size_t msibm_workspace_size(const msibm_pair* pairs, int32_t n_pairs, const msib
  *                  level-1 map (the prior of level 0) that msibm_backward needs;
  *                  unused when K == 1.
  *   workspace      device scratch of msibm_workspace_size(pairs, n_pairs, cfg).
- * Without MSIBM_FLAG_BATCHED the pairs run one after another (plain path: 2K
- * launches per pair).  With it the pairs advance together, one launch per stage
- * covering every pair's tiles: the reduce of each level, one statistics launch,
- * then per level (coarsest first) one matching launch per (mode, dtype) present;
+ * Without MSIBM_FLAG_BATCHED the pairs run one after another (plain path, per
+ * pair: one launch per three pyramid steps, one statistics launch, one matching
+ * launch per level).  With it the pairs advance together, one launch per stage
+ * covering every pair's tiles: per pyramid step the level's statistics beside
+ * the reduce to the next level, then per level (coarsest first) one matching
+ * launch per (mode, dtype) present;
  * the outputs are bit-identical to the plain path.  The launches find their
  * tiles through a small table that is copied into the workspace on `stream`
  * from library-owned pinned host memory.  With MSIBM_FLAG_GRAPH too, the first

@@ -127,7 +127,7 @@ PairLayout pair_layout(const msibm_pair& p, int K)
                 off = align_up(off + px * sizeof(float));
             }
             L.stat[k][v] = off;
-            off = align_up(off + px * sizeof(float4));
+            off = align_up(off + px * sizeof(WinStat));
         }
         if (k > 0) {
             L.map[k] = off;
@@ -210,7 +210,7 @@ msibm_status msibm_pyramid(const void* img, int32_t dtype, int32_t H, int32_t W,
 size_t msibm_level_workspace_size(int32_t H, int32_t W)
 {
     if (H < 1 || W < 1) return 0;
-    return 2 * align_up((size_t)H * W * sizeof(float4));
+    return 2 * align_up((size_t)H * W * sizeof(WinStat));
 }
 
 msibm_status msibm_match_level(const void* L, const void* R, int32_t dtype, int32_t H, int32_t W,
@@ -236,8 +236,8 @@ msibm_status msibm_match_level(const void* L, const void* R, int32_t dtype, int3
     if (!workspace || ws_bytes < need)
         return fail(MSIBM_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace ? ws_bytes : (size_t)0, need);
     hipStream_t s = (hipStream_t)stream;
-    float4* st = (float4*)workspace;
-    float4* st_r = (float4*)((char*)workspace + align_up((size_t)H * W * sizeof(float4)));
+    WinStat* st = (WinStat*)workspace;
+    WinStat* st_r = (WinStat*)((char*)workspace + align_up((size_t)H * W * sizeof(WinStat)));
     StatsArgs sa{};
     sa.seg[0] = StatsSeg{L, st, dtype, H, W, pitch, W, 0};
     sa.seg[1] = StatsSeg{R, st_r, dtype, H, W, pitch, W, 0};

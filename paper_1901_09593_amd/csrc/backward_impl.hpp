@@ -40,8 +40,8 @@ struct BackArgs {
     const float* L;
     const float* R;
     int H, W, pitch;
-    const float4* statL;
-    const float4* statR;
+    const WinStat* statL;
+    const WinStat* statR;
     int spitch;
     int D;                    // candidates at level 0
     const int16_t* prior;     // level-1 map
@@ -260,9 +260,9 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
         if (part) {
             // statistics and upstream gradients of both pixels, loaded before the
             // window sums so that their latency overlaps them
-            float4 stl2[2], str2[2][NC];
+            WinStat stl2[2], str2[2][NC];
             float gpx2[2];
-            const float4* srow = a.statR + (size_t)ii * a.spitch;
+            const WinStat* srow = a.statR + (size_t)ii * a.spitch;
 #pragma unroll
             for (int pc = 0; pc < 2; ++pc) {
                 stl2[pc] = a.statL[(size_t)ii * a.spitch + jp[pc]];
@@ -276,7 +276,7 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
 #pragma unroll
             for (int pc = 0; pc < 2; ++pc) {
                 if (!act[pc]) continue;  // contributes nothing
-                const float4 stl = stl2[pc];
+                const WinStat stl = stl2[pc];
                 const float dl = (stl.x - ca) + stl.y;  // mu_l - ca
                 const float invl = stl.z;
                 // right statistics of this pixel's candidates: column jp - z
@@ -286,7 +286,7 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
 #pragma unroll
                 for (int s = 0; s < NC; ++s) {
                     const int z = zs + s;
-                    const float4 st = str2[pc][s];
+                    const WinStat st = str2[pc][s];
                     mr[s] = (st.x - cR) + st.y;  // mu_r - cR
                     invr[s] = st.z;
                     const float C = fmaf(-Nf * dl, mr[s], S[pc][s]);

@@ -228,8 +228,8 @@ static void plan_levels(const msibm_pair* pairs, int np, const BatchOutputs& out
             }
             d.H = lay.h[k];
             d.W = lay.w[k];
-            d.stat[0] = (float4*)(ws + lay.stat[k][0]);
-            d.stat[1] = (float4*)(ws + lay.stat[k][1]);
+            d.stat[0] = (WinStat*)(ws + lay.stat[k][0]);
+            d.stat[1] = (WinStat*)(ws + lay.stat[k][1]);
             d.Dk = level_range(P.max_disp, k);
             pl.levels.push_back(d);
         }
@@ -538,8 +538,8 @@ int run_batched_backward(const msibm_pair* pairs, int np, const msibm_config* cf
             d.dtype = P.dtype;
             d.H = P.height;
             d.W = P.width;
-            d.stat[0] = (float4*)(ws + lay.stat[0][0]);
-            d.stat[1] = (float4*)(ws + lay.stat[0][1]);
+            d.stat[0] = (WinStat*)(ws + lay.stat[0][0]);
+            d.stat[1] = (WinStat*)(ws + lay.stat[0][1]);
             d.Dk = P.max_disp;
             pl.levels.push_back(d);
             pl.level_base.push_back(p);

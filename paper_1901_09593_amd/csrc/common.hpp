@@ -22,16 +22,20 @@ constexpr int FULL_NC = 8;                 // slots per step of a full search
 
 enum MatchMode { MODE_FULL = 0, MODE_REFINE = 1, MODE_SOFT = 2 };
 
-// Per-pixel window statistics of one view at one level (float4): x + y = the
+// Per-pixel window statistics of one view at one level (12 bytes): x + y = the
 // window mean as an unevaluated sum of two floats (x = the mean rounded to
 // float, y = the rounding remainder), z = 1/sqrt(sum of squared deviations) or 0
-// for a flat window, w unused.
+// for a flat window.
+struct WinStat {
+    float x, y, z;
+};
+
 struct MatchArgs {
     const void* L;
     const void* R;
     int H, W, pitch;          // level image size and row pitch (elements)
-    const float4* statL;      // H x W, row pitch spitch
-    const float4* statR;
+    const WinStat* statL;      // H x W, row pitch spitch
+    const WinStat* statR;
     int spitch;
     int Dk;                   // candidates at this level
     const int16_t* prior;     // level k+1 map (refine / soft), else unused
@@ -78,7 +82,7 @@ struct ReduceArgs {
 // One (level, view) image whose window statistics a stats launch computes.
 struct StatsSeg {
     const void* src;
-    float4* dst;
+    WinStat* dst;
     int dtype;                // MSIBM_U8 / MSIBM_F32 element type of src
     int H, W, spitch, dpitch;
     int tile0;                // first tile index (filled by the launcher)
@@ -121,7 +125,7 @@ struct BackArgs;
 struct LevelDesc {
     const void* img[2];   // level image of both views (level 0: the caller's input)
     int pitch, H, W;
-    float4* stat[2];      // window statistics, row pitch W
+    WinStat* stat[2];      // window statistics, row pitch W
     int16_t* map;         // winner-take-all map, row pitch W (level 0: the caller's output)
     float* cost;          // level 0 only, nullable
     float* soft;          // level 0 only, soft mode

@@ -254,8 +254,8 @@ static_assert(sizeof(StatsSmemI<1>) <= sizeof(StatsSmemD<1>) && sizeof(StatsSmem
 // input load of both views is issued first, so view B's loads are in flight
 // while view A is computed.
 template <typename T, int NW>
-__device__ __forceinline__ void stats_tile(const T* __restrict__ srcA, float4* __restrict__ dstA,
-                                           const T* __restrict__ srcB, float4* __restrict__ dstB, int H, int W,
+__device__ __forceinline__ void stats_tile(const T* __restrict__ srcA, WinStat* __restrict__ dstA,
+                                           const T* __restrict__ srcB, WinStat* __restrict__ dstB, int H, int W,
                                            int spitch, int dpitch, double var_eps, int x0, int y0, StatsSmem<NW>& sm)
 {
     double* h1 = sm.d.h1;
@@ -278,7 +278,7 @@ __device__ __forceinline__ void stats_tile(const T* __restrict__ srcA, float4* _
 #pragma unroll
     for (int vw = 0; vw < 2; ++vw) {
         const double c = cv[vw];
-        float4* __restrict__ dst = vw ? dstB : dstA;
+        WinStat* __restrict__ dst = vw ? dstB : dstA;
         if (rr < rows) {
             double v[NF];
 #pragma unroll
@@ -320,7 +320,7 @@ __device__ __forceinline__ void stats_tile(const T* __restrict__ srcA, float4* _
                 const float inv = (A <= N * var_eps) ? 0.f : rsqrtf((float)A);
                 const double mu = c + s1 * invN;
                 const float hi = (float)mu;
-                dst[(size_t)gy * dpitch + gx] = make_float4(hi, (float)(mu - (double)hi), inv, 0.f);
+                dst[(size_t)gy * dpitch + gx] = WinStat{hi, (float)(mu - (double)hi), inv};
             }
         }
         __syncthreads();  // LDS is reused by the next view and the caller's next tile
@@ -330,8 +330,8 @@ __device__ __forceinline__ void stats_tile(const T* __restrict__ srcA, float4* _
 // Statistics of one 32 x 64 tile of both views of a uint8 level: the same
 // quantities as stats_tile, from exact integer window sums.
 template <int NW>
-__device__ __forceinline__ void stats_tile_u8(const uint8_t* __restrict__ srcA, float4* __restrict__ dstA,
-                                              const uint8_t* __restrict__ srcB, float4* __restrict__ dstB, int H,
+__device__ __forceinline__ void stats_tile_u8(const uint8_t* __restrict__ srcA, WinStat* __restrict__ dstA,
+                                              const uint8_t* __restrict__ srcB, WinStat* __restrict__ dstB, int H,
                                               int W, int spitch, int dpitch, double var_eps, int x0, int y0,
                                               StatsSmem<NW>& sm)
 {
@@ -381,7 +381,7 @@ __device__ __forceinline__ void stats_tile_u8(const uint8_t* __restrict__ srcA, 
 #pragma unroll
     for (int vw = 0; vw < 2; ++vw) {
         const int c = cv[vw];
-        float4* __restrict__ dst = vw ? dstB : dstA;
+        WinStat* __restrict__ dst = vw ? dstB : dstA;
 #pragma unroll
         for (int q = 0; q < NT; ++q) {
             const int task = threadIdx.x + 256 * q;
@@ -431,7 +431,7 @@ __device__ __forceinline__ void stats_tile_u8(const uint8_t* __restrict__ srcA, 
                 const float inv = (A <= N * var_eps) ? 0.f : rsqrtf((float)A);
                 const double mu = (double)c + d1 * invN;
                 const float hi = (float)mu;
-                dst[(size_t)gy * dpitch + gx] = make_float4(hi, (float)(mu - (double)hi), inv, 0.f);
+                dst[(size_t)gy * dpitch + gx] = WinStat{hi, (float)(mu - (double)hi), inv};
             }
         }
         __syncthreads();  // LDS is reused by the next view and the caller's next tile

@@ -207,18 +207,18 @@ __device__ __forceinline__ void stage_pair(float* ldst, int lstride, int lhalf, 
 // scheme as stage_tile.
 template <int ROWS, int MAXCOLS>
 __device__ __forceinline__ void stage_stats(float* mc, float* is, int stride, int half,
-                                            const float4* __restrict__ src, int spitch, int H, int W,
+                                            const WinStat* __restrict__ src, int spitch, int H, int W,
                                             int gy0, int gx0, int cols, float c)
 {
     constexpr int RI = (ROWS + MATCH_TY - 1) / MATCH_TY;
     constexpr int CI = (MAXCOLS + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
     const int groups = (cols + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
-    float4 v0[RI][CI], v1[RI][CI];
+    WinStat v0[RI][CI], v1[RI][CI];
 #pragma unroll
     for (int ri = 0; ri < RI; ++ri) {
         const int rr = wave + MATCH_TY * ri;
-        const float4* srow = src + (size_t)clampi(gy0 + rr, 0, H - 1) * spitch;
+        const WinStat* srow = src + (size_t)clampi(gy0 + rr, 0, H - 1) * spitch;
 #pragma unroll
         for (int ci = 0; ci < CI; ++ci) {
             const int cc = 2 * (lane + MATCH_TX * ci);
@@ -503,7 +503,7 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
             if (w_first > w_last) continue;
             // left statistics; the block's left windows are centred on its
             // first pixel's window mean
-            float4 stl[4];
+            WinStat stl[4];
             stl[0] = a.statL[(size_t)q.ia * a.spitch + q.ja];
             stl[1] = a.statL[(size_t)q.ia * a.spitch + q.jb];
             stl[2] = a.statL[(size_t)q.ib * a.spitch + q.ja];
@@ -528,12 +528,12 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
                 const int bo = (c0 & 1) ? (c0 >> 1) : G::SHALF + (c0 >> 1) - 1;  // q odd
                 // right statistics from global memory: every load of the window
                 // issued before the first use, so they share one latency
-                float4 stg[2][SL ? 1 : NC + 1];
+                WinStat stg[2][SL ? 1 : NC + 1];
                 if (!SL) {
 #pragma unroll
                     for (int rowp = 0; rowp < 2; ++rowp) {
                         // columns j0 + 1 - wz - q of pixel row ia or ib
-                        const float4* srow = a.statR + (size_t)(rowp ? q.ib : q.ia) * a.spitch;
+                        const WinStat* srow = a.statR + (size_t)(rowp ? q.ib : q.ia) * a.spitch;
 #pragma unroll
                         for (int qq = 0; qq <= NC; ++qq) stg[rowp][SL ? 0 : qq] = srow[clampi(j0 + 1 - wz - qq, 0, a.W - 1)];
                     }
@@ -553,7 +553,7 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
                     } else {
 #pragma unroll
                         for (int qq = 0; qq <= NC; ++qq) {
-                            const float4 st = stg[rowp][SL ? 0 : qq];
+                            const WinStat st = stg[rowp][SL ? 0 : qq];
                             smc[qq] = (st.x - cR) + st.y;
                             sis[qq] = st.z;
                         }

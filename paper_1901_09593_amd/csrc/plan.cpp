@@ -106,7 +106,7 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
         StatsArgs sa{};
         for (int k = 0; k < K; ++k)
             for (int v = 0; v < 2; ++v)
-                sa.seg[2 * k + v] = StatsSeg{img[k][v], (float4*)(ws + lay.stat[k][v]),
+                sa.seg[2 * k + v] = StatsSeg{img[k][v], (WinStat*)(ws + lay.stat[k][v]),
                                              k == 0 ? P.dtype : MSIBM_F32, lay.h[k], lay.w[k], pitch[k],
                                              lay.w[k], 0};
         sa.nseg = 2 * K;
@@ -123,8 +123,8 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
         a.H = lay.h[k];
         a.W = lay.w[k];
         a.pitch = pitch[k];
-        a.statL = (const float4*)(ws + lay.stat[k][0]);
-        a.statR = (const float4*)(ws + lay.stat[k][1]);
+        a.statL = (const WinStat*)(ws + lay.stat[k][0]);
+        a.statR = (const WinStat*)(ws + lay.stat[k][1]);
         a.spitch = lay.w[k];
         a.Dk = level_range(P.max_disp, k);
         const bool coarsest = (k == K - 1);
@@ -197,8 +197,8 @@ int run_pair_backward(const msibm_pair& P, const PairLayout& lay, const msibm_co
     hipError_t e;
     const int H = P.height, W = P.width;
     StatsArgs sa{};
-    sa.seg[0] = StatsSeg{P.left, (float4*)(ws + lay.stat[0][0]), MSIBM_F32, H, W, P.pitch, W, 0};
-    sa.seg[1] = StatsSeg{P.right, (float4*)(ws + lay.stat[0][1]), MSIBM_F32, H, W, P.pitch, W, 0};
+    sa.seg[0] = StatsSeg{P.left, (WinStat*)(ws + lay.stat[0][0]), MSIBM_F32, H, W, P.pitch, W, 0};
+    sa.seg[1] = StatsSeg{P.right, (WinStat*)(ws + lay.stat[0][1]), MSIBM_F32, H, W, P.pitch, W, 0};
     sa.nseg = 2;
     sa.n = cfg->half_window;
     sa.var_eps = cfg->var_eps;
@@ -218,8 +218,8 @@ int run_pair_backward(const msibm_pair& P, const PairLayout& lay, const msibm_co
     b.H = H;
     b.W = W;
     b.pitch = P.pitch;
-    b.statL = (const float4*)(ws + lay.stat[0][0]);
-    b.statR = (const float4*)(ws + lay.stat[0][1]);
+    b.statL = (const WinStat*)(ws + lay.stat[0][0]);
+    b.statR = (const WinStat*)(ws + lay.stat[0][1]);
     b.spitch = W;
     b.D = P.max_disp;
     b.prior = prior1;

@@ -16,7 +16,7 @@ size_t align_up(size_t v);
 
 // Workspace offsets of one pair.  Level k (k >= 1) holds both views' pyramid
 // images (float, W_k pitch); every level holds both views' window statistics
-// (float4 per pixel); levels k >= 1 hold the winner-take-all map (int16).
+// (12 bytes per pixel); levels k >= 1 hold the winner-take-all map (int16).
 struct PairLayout {
     int K;
     int h[MSIBM_MAX_LEVELS], w[MSIBM_MAX_LEVELS];
