@@ -109,9 +109,11 @@ const char* msibm_version(void);
  *      searches only; otherwise each thread reads them from global memory),
  *   2  XCD-aware tile order (each of the 8 XCDs takes one contiguous run of
  *      tiles, so neighbouring tiles share their halos in one L2),
- *   4  candidate split (full searches only): 2-row tiles whose 4 waves score
- *      every 4th window of candidates for the same pixels and combine their
- *      winners; four times the workgroups, a quarter of each thread's work
+ *   4  candidate split (full and restricted searches, not the soft level):
+ *      2-row tiles whose 4 waves score disjoint windows of candidates for the
+ *      same pixels (every 4th window of a full search; a quarter of each
+ *      block's 2r + 1 candidates in a restricted one) and combine their
+ *      winners; four times the workgroups, a fraction of each thread's work
  *      (for small levels),
  *   8  fixed window (restricted searches whose whole candidate range, about
  *      D_k candidates, fits one staged chunk of 320): both tiles are staged

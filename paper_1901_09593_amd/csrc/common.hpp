@@ -52,7 +52,7 @@ struct MatchArgs {
 // Kernel shape variants of the matching kernel (bits of MatchArgs::variant).
 constexpr int VARIANT_STATS_LDS = 1;  // right statistics staged in LDS (full search only)
 constexpr int VARIANT_XCD = 2;        // XCD-aware tile order
-constexpr int VARIANT_SPLIT = 4;      // full search: 2-row tiles, the 4 waves split the candidates
+constexpr int VARIANT_SPLIT = 4;      // full / restricted search: 2-row tiles, the 4 waves split the candidates
 constexpr int VARIANT_FIXW = 8;       // restricted search: stage the whole candidate range up front
 constexpr int VARIANT_MASK = 15;
 
@@ -224,6 +224,6 @@ hipError_t launch_zero(float* a, float* b, size_t count, hipStream_t s);
 // Slots evaluated per block: 2r+1, but at least 2 so that a block whose prior
 // is clipped by the left image border (pixel columns j0 and j0+1 then centre
 // on j0 and j0+1) still fits one window.
-inline int slots_for_radius(int r) { return 2 * r + 1 < 2 ? 2 : 2 * r + 1; }
+__host__ __device__ inline int slots_for_radius(int r) { return 2 * r + 1 < 2 ? 2 : 2 * r + 1; }
 
 }  // namespace msibm

@@ -353,12 +353,21 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
     constexpr int CH = ChunkOf<MODE>::value;
     constexpr int BY = 1;
     using G = Geo<NW, CH, TileRows<SPLIT>::value>;
-    static_assert(!SPLIT || MODE == MODE_FULL, "only a full search splits its candidates over the waves");
+    static_assert(!SPLIT || MODE != MODE_SOFT, "the soft level needs every slot of a block in one thread");
     constexpr float Nf = (float)((2 * NW + 1) * (2 * NW + 1));
-    constexpr int STEP = (MODE == MODE_FULL) ? CH : (CH - NC + 1);
+    // A block of a restricted search scores the candidate slots [zs, zs + NCF).
+    // Unsplit, that is one window of NC = NCF slots; split (RSPLIT), the span is
+    // covered by windows of NC slots, one per wave (NCX: the span rounded up to
+    // whole windows), so every wave's chain is a fraction of the block's.
+    // Each slot's score is computed by the same operations either way.
+    constexpr bool RSPLIT = SPLIT && MODE == MODE_REFINE;
+    const int NCF = RSPLIT ? slots_for_radius(a.r) : NC;
+    const int NCX = RSPLIT ? (NCF + NC - 1) / NC * NC : NC;
+    const int STEP = (MODE == MODE_FULL) ? CH : (CH - NCX + 1);
     static_assert(MODE != MODE_FULL || CH % NC == 0, "full search steps must tile a chunk");
     static_assert(CH >= NC, "a chunk must hold one slot window");
-    static_assert(MODE == MODE_FULL || (MSIBM_MAX_DISP - 1) / STEP < 32, "chunk mask must hold every chunk");
+    static_assert(MODE == MODE_FULL || (MSIBM_MAX_DISP - 1) / (CH - 4 * NC + 1) < 32,
+                  "chunk mask must hold every chunk");
 
     const T* __restrict__ Lg = static_cast<const T*>(a.L);
     const T* __restrict__ Rg = static_cast<const T*>(a.R);
@@ -397,7 +406,7 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
             // out-of-range prior values (never produced by the coarser level)
             // are clamped so that every index below stays inside its buffer
             const int dh = clampi(2 * (int)a.prior[(size_t)(q.ia >> 1) * a.ppitch + (q.ja >> 1)], 0, a.Dk - 1);
-            q.zs = (dh <= j0) ? dh - a.r : j0 + 2 - NC;
+            q.zs = (dh <= j0) ? dh - a.r : j0 + 2 - NCF;
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 const int c = min(dh, jp[p]);
@@ -415,10 +424,10 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
     // chunk): every block's slots lie in [zlo_f, zhi_f], so both tiles are
     // staged at once, before any block's prior is known, and no workgroup-wide
     // range is needed.
-    const int zlo_f = min(-a.r, 2 - NC), zhi_f = a.Dk - 1 - a.r;
+    const int zlo_f = min(-a.r, 2 - NCF), zhi_f = a.Dk - 1 - a.r;
     const bool fixw = MODE != MODE_FULL && (a.variant & VARIANT_FIXW) && zhi_f - zlo_f + 1 <= STEP;
     if (fixw) {
-        const int ztop = zhi_f + NC - 1;
+        const int ztop = zhi_f + NCX - 1;
         stage_pair<T, G::LROWS, G::LCOLS, G::RCOLS>(sm.Ls, G::LSTRIDE, G::LHALF, sm.Rs, G::RSTRIDE, G::RHALF, Lg,
                                                     Rg, a.pitch, a.H, a.W, y0 - NW, x0 - NW, G::LCOLS,
                                                     x0 - NW - ztop, TILE_W + 2 * NW + (ztop - zlo_f), cR);
@@ -477,7 +486,7 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
         // largest candidate slot of this chunk: the right tile's column 0 pairs
         // with the first window column of that slot, and statistics column 0 is
         // the window centre of the tile's first pixel column at that slot
-        const int ztop = min(zc + CH - 1, zhi + NC - 1);
+        const int ztop = min(zc + CH - 1, zhi + NCX - 1);
         if (zc != zlo) __syncthreads();  // previous chunk fully consumed
         if (!fixw)
             stage_tile<T, G::LROWS, G::RCOLS>(sm.Rs, G::RSTRIDE, G::RHALF, Rg, a.pitch, a.H, a.W, y0 - NW,
@@ -498,7 +507,7 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
                 w_last = min(zc + CH - 1, max(q.hi[0], q.hi[1]));
             } else {
                 w_first = q.zs;
-                w_last = (q.zs >= zc && q.zs < zc + STEP) ? q.zs : q.zs - 1;
+                w_last = (q.zs >= zc && q.zs < zc + STEP) ? q.zs + NCX - NC : q.zs - 1;
             }
             if (w_first > w_last) continue;
             // left statistics; the block's left windows are centred on its
@@ -657,11 +666,19 @@ static hipError_t launch_shape(const MatchArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Slots per wave of a split restricted search: a quarter of the block's span,
+// rounded up, so the four waves cover it with one window each.
+constexpr int split_slots(int nc) { return (nc + MATCH_TY - 1) / MATCH_TY; }
+
 template <typename T, int NW, int NC, int MODE>
 static hipError_t launch_one(const MatchArgs& a, hipStream_t s)
 {
     if (MODE == MODE_FULL && (a.variant & VARIANT_SPLIT))
         return launch_shape<T, NW, NC, MODE, MODE == MODE_FULL ? 1 : 0>(a, s);
+    if (MODE == MODE_REFINE && (a.variant & VARIANT_SPLIT)) {
+        if (slots_for_radius(a.r) != NC) return hipErrorInvalidValue;  // the span the kernel splits
+        return launch_shape<T, NW, split_slots(NC), MODE, MODE == MODE_REFINE ? 1 : 0>(a, s);
+    }
     return launch_shape<T, NW, NC, MODE, 0>(a, s);
 }
 

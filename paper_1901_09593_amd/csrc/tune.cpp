@@ -165,10 +165,13 @@ int select_variant(const MatchArgs& a, int n, int dtype, int mode, int nc, hipSt
 {
     Tuner& t = tuner();
     std::lock_guard<std::mutex> g(t.mu);
-    // statistics in LDS and candidate split: full search only; fixed window:
-    // restricted searches whose candidate range fits one staged chunk
-    const int valid = mode == MODE_FULL ? (VARIANT_STATS_LDS | VARIANT_XCD | VARIANT_SPLIT)
-                                        : (VARIANT_XCD | (fixed_window_fits(a, nc) ? VARIANT_FIXW : 0));
+    // statistics in LDS: full search only; candidate split: full and restricted
+    // (not soft) searches; fixed window: restricted searches whose candidate
+    // range fits one staged chunk
+    const int valid = mode == MODE_FULL
+                          ? (VARIANT_STATS_LDS | VARIANT_XCD | VARIANT_SPLIT)
+                          : (VARIANT_XCD | (mode == MODE_REFINE ? VARIANT_SPLIT : 0) |
+                             (fixed_window_fits(a, nc) ? VARIANT_FIXW : 0));
     if (t.forced >= 0) return t.forced & valid;
     const Key key(mode, n, nc, dtype, a.H, a.W, a.Dk);
     auto it = t.table.find(key);
