@@ -13,7 +13,7 @@
 //   variance A/N is at most var_eps (flat window).  Separable running box sums
 //   accumulated in double precision, so the flat test and A match the
 //   double-precision definition; every level and view of a pair in one launch.
-//   HBM-bound: 1 or 4 bytes read and 16 bytes written per pixel.
+//   HBM-bound: 1 or 4 bytes read and 12 bytes written per pixel.
 #include "levels_impl.hpp"
 
 namespace msibm {
