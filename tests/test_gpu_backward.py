@@ -174,3 +174,41 @@ def test_batched_backward_matches_plain_and_oracle(M):
     eL, eR = rel(host(batched[i][0]), oL), rel(host(batched[i][1]), oR)
     print("batched backward vs oracle", eL, eR)
     assert eL <= REL_TOL and eR <= REL_TOL
+
+
+def test_hires2880_full_size_forward_backward(M):
+    """The 4 x 2880x1988 forward + backward at full size, in the launch
+    configuration the benchmark times (stage-batched, graph): pair 0's soft
+    disparities against the oracle fed the GPU's level-1 map; every pair's
+    batched gradients against its per-pair ones and against the invariances of
+    ZNCC to the offset and scale of each image (properties at any size: the
+    oracle's full-size backward takes tens of seconds)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(4) as ex:
+        work = list(ex.map(lambda i: synth.workload("hires2880", i), range(4)))
+    cfg = work[0][1]
+    n, r, eps, rs, tau, D, K = cfg.half_window, cfg.refine_radius, cfg.var_eps, cfg.soft_radius, cfg.tau, \
+        cfg.max_disp, cfg.levels
+    L = [dev(p.left) for p, _ in work]
+    R = [dev(p.right) for p, _ in work]
+    Ds, Ks = [D] * 4, [K] * 4
+    flags = M.FLAG_BATCHED | M.FLAG_GRAPH
+    print("hires2880 full size, batched graph", flush=True)
+    outs = M.disparity_many(L, R, Ds, Ks, n, r, eps, soft_radius=rs, tau=tau, flags=flags)
+    p1 = [o["prior1"] for o in outs]
+    g = [dev(synth.grad_seed(20 + i, *x.shape).astype(np.float32)) for i, x in enumerate(L)]
+    grads = M.backward_many(L, R, p1, g, Ds, Ks, n, r, eps, rs, tau, flags=flags)
+    plain = M.backward_many(L, R, p1, g, Ds, Ks, n, r, eps, rs, tau)
+    for i, ((a, b), (c, d)) in enumerate(zip(grads, plain)):
+        for x, y, img in ((a, c, work[i][0].left), (b, d, work[i][0].right)):
+            xs = host(x).astype(np.float64)
+            assert np.isfinite(xs).all()
+            assert rel(xs, host(y)) < 1e-5, i  # only the atomic summation order differs
+            scale = np.abs(xs).sum()
+            assert abs(xs.sum()) < 1e-4 * scale
+            assert abs((xs * img).sum()) < 1e-4 * scale * np.abs(img).max()
+    l0, r0, q1 = host(L[0]), host(R[0]), host(p1[0])
+    ds_o, dh_o, C_o, C2_o = oracle.soft_level0(l0, r0, n, D, q1, rs, tau, eps)
+    err = float(np.abs(host(outs[0]["soft"]).astype(np.float64) - ds_o).max())
+    print("hires2880 soft max |dd|", err)
+    assert err <= 1e-2

@@ -140,3 +140,37 @@ def test_persistent_graph_replay_repeats(M):
         M.disparity_many(L, R, Ds, Ks, 4, 2, 0.065, flags=flags, outputs=outs)
         torch.cuda.synchronize()
         _equal(ref, outs, rep)
+
+
+def test_batch32_full_size_sampled(M):
+    """The 32-pair uneven batch at full size in the launch configuration the
+    benchmark times (stage-batched, graph): identical to the per-pair path, and
+    level 0 of four pairs (one per level count) checked on sampled pixels against
+    the oracle fed the GPU's level-1 map."""
+    import oracle
+    from parity import check_pixels
+    work = synth.batch_workload(32, 1000, workers=8)
+    L = [dev(p.left) for p, _ in work]
+    R = [dev(p.right) for p, _ in work]
+    D = [c.max_disp for _, c in work]
+    K = [c.levels for _, c in work]
+    n, r, eps = work[0][1].half_window, work[0][1].refine_radius, work[0][1].var_eps
+    print("batch32 full size, batched graph", flush=True)
+    got = M.disparity_many(L, R, D, K, n, r, eps, with_prior1=True, flags=M.FLAG_BATCHED | M.FLAG_GRAPH)
+    ref = M.disparity_many(L, R, D, K, n, r, eps, with_prior1=True)
+    torch.cuda.synchronize()
+    _equal(ref, got)
+    picks = {}
+    for i, k in enumerate(K):
+        picks.setdefault(k, i)
+    rng = np.random.Generator(np.random.PCG64(7))
+    for k, i in sorted(picks.items()):
+        if k < 2:
+            continue
+        p = work[i][0]
+        H, W = p.left.shape
+        ii = rng.integers(0, H, 1500)
+        jj = rng.integers(0, W, 1500)
+        d, C, p1 = (got[i][x].cpu().numpy() for x in ("disp", "cost", "prior1"))
+        st = check_pixels(d, C, p.left, p.right, n, D[i], p1, r, eps, ii, jj)
+        print(f"batch32 pair {i} ({W}x{H}, D={D[i]}, K={k})", st)
