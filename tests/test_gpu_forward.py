@@ -69,6 +69,7 @@ FULL_CASES = [
     (1, 40, 2, 8, "u8", 5),        # one row
     (33, 1, 1, 4, "f32", 6),       # one column
     (16, 130, 5, 1, "u8", 7),      # a single candidate
+    (6, 2100, 2, 2048, "u8", 8),   # the largest D: 22 candidate chunks
 ]
 
 
@@ -101,6 +102,7 @@ REFINE_CASES = [
     (40, 100, 1, 40, 4, "f32", 14),
     (17, 45, 6, 30, 2, "u8", 15),
     (25, 257, 5, 128, 2, "f32", 16),
+    (20, 2100, 3, 2048, 4, "u8", 17),  # the largest D and radius: priors over 7 chunks
 ]
 
 
@@ -278,6 +280,27 @@ def test_every_kernel_variant_gives_identical_results(M, variant):
     assert torch.equal(ref["disp"], got["disp"]) and torch.equal(ref["cost"], got["cost"])
     assert torch.equal(ref["prior1"], got["prior1"])
     assert torch.equal(flat_ref[0], flat[0]) and torch.equal(flat_ref[1], flat[1])
+
+
+def test_restricted_shapes_identical_at_largest_range(M):
+    """Every restricted-search shape (candidate split or not, fixed window or
+    chunked, tile order) gives the same maps and scores where the candidate
+    range spans several chunks (D_k = 2048, r = 4, priors over the whole
+    range)."""
+    H, W, n, Dk, r = 20, 2100, 3, 2048, 4
+    p = _tex_pair(18, H, W, 1500, "u8")
+    rng = np.random.Generator(np.random.PCG64(18))
+    prior = dev(rng.integers(0, Dk // 2, size=((H + 1) // 2, (W + 1) // 2)).astype(np.int16))
+    Lg, Rg = dev(p.left), dev(p.right)
+    outs = []
+    try:
+        for v in (0, 2, 4, 6, 8, 12, 14):
+            M.force_variant(v)
+            outs.append(M.match_level(Lg, Rg, n, Dk, prior, r, 0.065))
+    finally:
+        M.force_variant(-1)
+    for d, C in outs[1:]:
+        assert torch.equal(outs[0][0], d) and torch.equal(outs[0][1], C)
 
 
 def test_autotune_picks_per_shape_and_keeps_results(M, tmp_path):
