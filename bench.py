@@ -378,7 +378,7 @@ def main():
     def flat():
         msibm._check(msibm.lib().msibm_match_level(
             msibm._ptr(Lg), msibm._ptr(Rg), 0, H, W, W, n, D, None, 0, 0, 0, 0, float(eps),
-            msibm._ptr(dflat), None, W, msibm._ptr(wsl), wsl.numel(), msibm._stream(dev)))
+            msibm._ptr(dflat), None, W, None, msibm._ptr(wsl), wsl.numel(), msibm._stream(dev)))
     flat_ms = time_ms(torch, flat, max(3, args.steps // 20), 3)
     del wsl, dflat
 

@@ -174,6 +174,9 @@ size_t msibm_level_workspace_size(int32_t H, int32_t W);
  *   L, R       device images of `dtype` (MSIBM_U8 or MSIBM_F32), H x W, pitch.
  *   d_out      device int16 H x W (row pitch out_pitch): lowest z of the best score.
  *   cost_out   device float H x W or NULL: the best score (Eq. 4 / Eq. 9).
+ *   costvol    NULL, or (for testing) device float H x W x D_k, entry
+ *              (i W + j) D_k + z: the clamped score of every candidate the
+ *              search scores, -2 for every other z (the buffer is filled first).
  *   workspace  device scratch of msibm_level_workspace_size(H, W) bytes.
  * Errors: INVALID_ARG, SHAPE (sizes, pitches, prior shape), UNSUPPORTED (n, r,
  *         D_k out of range), WORKSPACE, HIP.
@@ -182,7 +185,7 @@ msibm_status msibm_match_level(const void* L, const void* R, int32_t dtype, int3
                                int32_t pitch, int32_t n, int32_t Dk, const int16_t* prior,
                                int32_t Hc, int32_t Wc, int32_t prior_pitch, int32_t r,
                                float var_eps, int16_t* d_out, float* cost_out, int32_t out_pitch,
-                               void* workspace, size_t ws_bytes, void* stream);
+                               float* costvol, void* workspace, size_t ws_bytes, void* stream);
 
 /* Bytes of workspace msibm_disparity / msibm_backward need for these pairs. */
 size_t msibm_workspace_size(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg);

@@ -216,8 +216,8 @@ size_t msibm_level_workspace_size(int32_t H, int32_t W)
 msibm_status msibm_match_level(const void* L, const void* R, int32_t dtype, int32_t H, int32_t W,
                                int32_t pitch, int32_t n, int32_t Dk, const int16_t* prior, int32_t Hc,
                                int32_t Wc, int32_t prior_pitch, int32_t r, float var_eps, int16_t* d_out,
-                               float* cost_out, int32_t out_pitch, void* workspace, size_t ws_bytes,
-                               void* stream)
+                               float* cost_out, int32_t out_pitch, float* costvol, void* workspace,
+                               size_t ws_bytes, void* stream)
 {
     if (!L || !R || !d_out) return fail(MSIBM_ERR_INVALID_ARG, "NULL image or output");
     if (dtype != MSIBM_U8 && dtype != MSIBM_F32) return fail(MSIBM_ERR_INVALID_ARG, "dtype %d", dtype);
@@ -269,6 +269,11 @@ msibm_status msibm_match_level(const void* L, const void* R, int32_t dtype, int3
     const int mode = prior ? MODE_REFINE : MODE_FULL;
     const int nc = prior ? slots_for_radius(r) : FULL_NC;
     a.variant = select_variant(a, n, dtype, mode, nc, s);
+    if (costvol) {
+        e = launch_fill(costvol, -2.f, (size_t)H * W * Dk, s);
+        if (e != hipSuccess) return hip_fail(e, "cost volume fill launch");
+        a.costvol = costvol;
+    }
     e = launch_match(n, dtype, mode, nc, a, s);
     if (e != hipSuccess) return hip_fail(e, "match launch");
     return ok();

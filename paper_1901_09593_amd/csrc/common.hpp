@@ -47,6 +47,7 @@ struct MatchArgs {
     int opitch;
     float inv_tau;
     int variant;              // VARIANT_* bits (kernel shape chosen by the tuner)
+    float* costvol;           // nullable: H x W x Dk scores of every scored candidate
 };
 
 // Kernel shape variants of the matching kernel (bits of MatchArgs::variant).
@@ -220,6 +221,7 @@ hipError_t launch_backward_n5(int nc, const BackArgs& a, hipStream_t s);
 hipError_t launch_backward_n6(int nc, const BackArgs& a, hipStream_t s);
 // Zero `count` floats at each of up to two pointers (graph-capturable fill).
 hipError_t launch_zero(float* a, float* b, size_t count, hipStream_t s);
+hipError_t launch_fill(float* a, float v, size_t count, hipStream_t s);
 
 // Slots evaluated per block: 2r+1, but at least 2 so that a block whose prior
 // is clipped by the left image border (pixel columns j0 and j0+1 then centre

@@ -133,6 +133,18 @@ __global__ __launch_bounds__(256) void zero_kernel(float* a, float* b, size_t co
     }
 }
 
+__global__ __launch_bounds__(256) void fill_kernel(float* a, float v, size_t count)
+{
+    for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < count; i += (size_t)gridDim.x * 256) a[i] = v;
+}
+
+hipError_t launch_fill(float* a, float v, size_t count, hipStream_t s)
+{
+    const size_t blocks = (count + 255) / 256;
+    hipLaunchKernelGGL(fill_kernel, dim3((unsigned)(blocks < 4096 ? blocks : 4096)), dim3(256), 0, s, a, v, count);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero(float* a, float* b, size_t count, hipStream_t s)
 {
     const size_t blocks = (count + 255) / 256;

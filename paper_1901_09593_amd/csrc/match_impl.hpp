@@ -346,7 +346,7 @@ struct TileRows {
     static constexpr int value = SPLIT ? 2 : TILE_H1;
 };
 
-template <typename T, int NW, int NC, int MODE, int SPLIT, int SL>
+template <typename T, int NW, int NC, int MODE, int SPLIT, int SL, bool CV = false>
 __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
                                            MatchSmem<NW, ChunkOf<MODE>::value, TileRows<SPLIT>::value, SL>& sm)
 {
@@ -578,6 +578,8 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
                             float rho = C * invl[p] * sis[qq];
                             rho = fminf(fmaxf(rho, -1.f), 1.f);
                             const bool ok = (z >= q.lo[p]) && (z <= q.hi[p]);
+                            if (CV && ok && q.act[p])
+                                a.costvol[((size_t)(rowp ? q.ib : q.ia) * a.W + (cp ? q.jb : q.ja)) * a.Dk + z] = rho;
                             if (MODE == MODE_SOFT) rho_keep[MODE == MODE_SOFT ? b : 0][p][MODE == MODE_SOFT ? s : 0] = ok ? rho : -1e30f;
                             if (ok && rho > best[b][p]) {
                                 best[b][p] = rho;
@@ -650,6 +652,16 @@ __global__ __launch_bounds__(MATCH_THREADS) void match_kernel(MatchArgs a)
     match_tile<T, NW, NC, MODE, SPLIT, SL>(a, bx, by, sm);
 }
 
+// The same search writing every scored candidate's score to a.costvol (a
+// testing aid: its own instantiation, so the production kernels carry no trace
+// of it).
+template <typename T, int NW, int NC, int MODE>
+__global__ __launch_bounds__(MATCH_THREADS) void match_costvol_kernel(MatchArgs a)
+{
+    __shared__ MatchSmem<NW, ChunkOf<MODE>::value, TILE_H1, 0> sm;
+    match_tile<T, NW, NC, MODE, 0, 0, true>(a, blockIdx.x, blockIdx.y, sm);
+}
+
 template <typename T, int NW, int NC, int MODE, int SPLIT>
 static hipError_t launch_shape(const MatchArgs& a, hipStream_t s)
 {
@@ -673,6 +685,13 @@ constexpr int split_slots(int nc) { return (nc + MATCH_TY - 1) / MATCH_TY; }
 template <typename T, int NW, int NC, int MODE>
 static hipError_t launch_one(const MatchArgs& a, hipStream_t s)
 {
+    if (a.costvol) {
+        if (MODE == MODE_SOFT) return hipErrorInvalidValue;
+        dim3 grid((a.W + TILE_W - 1) / TILE_W, (a.H + TILE_H1 - 1) / TILE_H1, 1);
+        hipLaunchKernelGGL((match_costvol_kernel<T, NW, NC, MODE == MODE_SOFT ? MODE_REFINE : MODE>), grid,
+                           dim3(MATCH_THREADS), 0, s, a);
+        return hipGetLastError();
+    }
     if (MODE == MODE_FULL && (a.variant & VARIANT_SPLIT))
         return launch_shape<T, NW, NC, MODE, MODE == MODE_FULL ? 1 : 0>(a, s);
     if (MODE == MODE_REFINE && (a.variant & VARIANT_SPLIT)) {

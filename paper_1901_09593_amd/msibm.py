@@ -69,7 +69,7 @@ def lib() -> ctypes.CDLL:
         L.msibm_level_workspace_size.argtypes = [_I32, _I32]
         L.msibm_level_workspace_size.restype = ctypes.c_size_t
         L.msibm_match_level.argtypes = [_VP, _VP, _I32, _I32, _I32, _I32, _I32, _I32, _VP, _I32,
-                                        _I32, _I32, _I32, ctypes.c_float, _VP, _VP, _I32, _VP,
+                                        _I32, _I32, _I32, ctypes.c_float, _VP, _VP, _I32, _VP, _VP,
                                         ctypes.c_size_t, _VP]
         L.msibm_match_level.restype = _I32
         L.msibm_workspace_size.argtypes = [ctypes.POINTER(Pair), _I32, ctypes.POINTER(Config)]
@@ -219,8 +219,10 @@ def pyramid(img: torch.Tensor, K: int) -> List[torch.Tensor]:
 
 def match_level(L: torch.Tensor, R: torch.Tensor, n: int, Dk: int,
                 prior: Optional[torch.Tensor] = None, r: int = 2, var_eps: float = 0.065,
-                with_cost: bool = True) -> Tuple[torch.Tensor, Optional[torch.Tensor]]:
-    """Winner-take-all of one level; prior = level k+1 map (int16) or None."""
+                with_cost: bool = True, with_costvol: bool = False):
+    """Winner-take-all of one level; prior = level k+1 map (int16) or None.
+    Returns (d, C), or (d, C, V) with V the H x W x D_k scores of every scored
+    candidate (-2 elsewhere) when with_costvol."""
     L = _image(L)
     R = _image(R)
     if L.shape != R.shape or L.dtype != R.dtype or L.stride(0) != R.stride(0):
@@ -236,10 +238,11 @@ def match_level(L: torch.Tensor, R: torch.Tensor, n: int, Dk: int,
         Hc, Wc, pp = prior.shape[0], prior.shape[1], prior.stride(0)
     else:
         Hc = Wc = pp = 0
+    V = torch.empty((H, W, Dk), dtype=torch.float32, device=dev) if with_costvol else None
     _check(lib().msibm_match_level(_ptr(L), _ptr(R), _dtype_code(L), H, W, L.stride(0), n, Dk,
                                    _ptr(prior), Hc, Wc, pp, r, float(var_eps), _ptr(d), _ptr(C), W,
-                                   _ptr(ws), ws_bytes, _stream(dev)))
-    return d, C
+                                   _ptr(V), _ptr(ws), ws_bytes, _stream(dev)))
+    return (d, C, V) if with_costvol else (d, C)
 
 
 def _pairs(lefts, rights, Ds, Ks) -> Tuple[ctypes.Array, list]:

@@ -48,13 +48,13 @@ def test_validation_errors_from_host(lib):
     assert b"level_pitch" in e.msibm_last_error()
     # match_level: window, range, prior shape, workspace
     args = dict(L=fake, R=fake, dtype=0, H=8, W=8, pitch=8, n=2, Dk=4, prior=None, Hc=0, Wc=0,
-                pp=0, r=1, eps=0.1, d=fake, c=None, op=8, ws=fake, wsb=10 ** 6, s=None)
+                pp=0, r=1, eps=0.1, d=fake, c=None, op=8, cv=None, ws=fake, wsb=10 ** 6, s=None)
 
     def call(**kw):
         a = dict(args, **kw)
         return e.msibm_match_level(a["L"], a["R"], a["dtype"], a["H"], a["W"], a["pitch"], a["n"],
                                    a["Dk"], a["prior"], a["Hc"], a["Wc"], a["pp"], a["r"], a["eps"],
-                                   a["d"], a["c"], a["op"], a["ws"], a["wsb"], a["s"])
+                                   a["d"], a["c"], a["op"], a["cv"], a["ws"], a["wsb"], a["s"])
     assert call(n=0) == -4 and call(n=7) == -4
     assert call(Dk=0) == -4 and call(Dk=5000) == -4
     assert call(d=None) == -1

@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 from paper_1901_09593_amd import synth
-from parity import TOL_ZNCC, check_level, check_pixels
+from parity import TOL_ZNCC, cand_bounds, check_level, check_pixels
 
 pytestmark = pytest.mark.gpu
 
@@ -121,6 +121,38 @@ def test_restricted_search_parity(M, H, W, n, Dk, r, dtype, seed):
     d, C = M.match_level(dev(p.left), dev(p.right), n, Dk, dev(prior), r, eps)
     st = check_level(host(d), host(C), p.left, p.right, n, Dk, prior, r, eps)
     assert st["mismatch"] <= 0.01
+
+
+@pytest.mark.parametrize("H,W,n,Dk,r,dtype,restricted", [(37, 150, 2, 40, 0, "u8", False),
+                                                       (23, 301, 4, 200, 0, "f32", False),
+                                                       (64, 200, 3, 60, 2, "u8", True),
+                                                       (31, 133, 5, 64, 4, "f32", True)])
+def test_every_scored_candidate_matches_oracle(M, H, W, n, Dk, r, dtype, restricted):
+    """The score of every candidate a search scores (not only the winner's),
+    against the oracle's score of the same (pixel, candidate); exactly the
+    candidate set of each pixel is scored."""
+    p = _tex_pair(60 + Dk, H, W, max(2, Dk // 2), dtype)
+    eps = 0.065 if dtype == "u8" else 1e-6
+    prior = None
+    if restricted:
+        rng = np.random.Generator(np.random.PCG64(Dk))
+        prior = rng.integers(0, -(-Dk // 2), size=((H + 1) // 2, (W + 1) // 2)).astype(np.int16)
+    d, C, V = M.match_level(dev(p.left), dev(p.right), n, Dk, None if prior is None else dev(prior), r, eps,
+                            with_costvol=True)
+    V = host(V)
+    lo, hi = cand_bounds(H, W, Dk, prior, r)
+    zz = np.arange(Dk)[None, None, :]
+    scored = (zz >= lo[:, :, None]) & (zz <= hi[:, :, None])
+    assert np.all(V[~scored] == -2.0)
+    ii, jj, kk = np.nonzero(scored)
+    rho = oracle.zncc_many(p.left, p.right, n, ii, jj, kk, eps)
+    err = np.abs(V[ii, jj, kk].astype(np.float64) - rho)
+    print("all scored candidates", ii.size, "max |dZNCC|", err.max())
+    assert err.max() <= TOL_ZNCC
+    # the winner is the lowest z of the best score among them
+    best = np.where(scored, V, -3.0).max(axis=2)
+    first = np.argmax(np.where(scored, V, -3.0) == best[:, :, None], axis=2)
+    assert np.array_equal(host(d), first) and np.array_equal(host(C), best)
 
 
 # ------------------------------------------------------------------ hierarchy
