@@ -95,6 +95,11 @@ typedef struct msibm_config {
                               its hard WTA is taken over that interval          */
     float tau;             /* soft-argmax temperature, > 0 when soft_radius > 0 */
     int32_t flags;         /* MSIBM_FLAG_*                                      */
+    int32_t half_window_levels[MSIBM_MAX_LEVELS];
+                           /* per-level n: entry k (1 <= n_k <= 6) replaces
+                              half_window at level k, 0 keeps half_window; for
+                              the block size that shrinks by 2 per level
+                              (Section III), e.g. {5, 2, 1}                    */
 } msibm_config;
 
 /* Thread-local description of the last error of this thread ("" if none). */

@@ -184,23 +184,28 @@ def match_level(L: np.ndarray, R: np.ndarray, n: int, Dk: int,
     return d, C, C2
 
 
-def disparity(left: np.ndarray, right: np.ndarray, D: int, K: int, n: int, r: int,
+def disparity(left: np.ndarray, right: np.ndarray, D: int, K: int, n, r: int,
               eps: float, priors: Optional[List[Optional[np.ndarray]]] = None):
     """The hierarchical forward pass (Section III, hot path).
 
-    Returns a list, index k = level, of (d_k, C_k, C2_k).  `priors[k]`, if given,
-    replaces the map that feeds level k (teacher forcing: the level-(k+1) map
-    used as the prior of level k)."""
+    n is the window half-width of every level, or a sequence of per-level
+    half-widths (level 0 first, its last entry for the levels past its end): the
+    block size that Section III shrinks level by level.  Returns a list, index
+    k = level, of (d_k, C_k, C2_k).  `priors[k]`, if given, replaces the map that
+    feeds level k (teacher forcing: the level-(k+1) map used as the prior of
+    level k)."""
+    def nk(k):
+        return n if isinstance(n, (int, np.integer)) else n[min(k, len(n) - 1)]
     PL = pyramid(left, K)
     PR = pyramid(right, K)
     out: List = [None] * K
     kc = K - 1
-    out[kc] = match_level(PL[kc], PR[kc], n, level_range(D, kc), None, r, eps)
+    out[kc] = match_level(PL[kc], PR[kc], nk(kc), level_range(D, kc), None, r, eps)
     for k in range(K - 2, -1, -1):
         prior = out[k + 1][0]
         if priors is not None and priors[k] is not None:
             prior = priors[k]
-        out[k] = match_level(PL[k], PR[k], n, level_range(D, k), prior, r, eps)
+        out[k] = match_level(PL[k], PR[k], nk(k), level_range(D, k), prior, r, eps)
     return out
 
 

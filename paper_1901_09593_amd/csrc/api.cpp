@@ -70,6 +70,12 @@ msibm_status validate_config(const msibm_config* cfg)
     if (cfg->half_window < 1 || cfg->half_window > MSIBM_MAX_HALF_WINDOW)
         return fail(MSIBM_ERR_UNSUPPORTED, "half_window %d outside 1..%d", cfg->half_window,
                     MSIBM_MAX_HALF_WINDOW);
+    for (int k = 0; k < MSIBM_MAX_LEVELS; ++k) {
+        const int v = cfg->half_window_levels[k];
+        if (v < 0 || v > MSIBM_MAX_HALF_WINDOW)
+            return fail(MSIBM_ERR_UNSUPPORTED, "half_window_levels[%d] = %d outside 0..%d", k, v,
+                        MSIBM_MAX_HALF_WINDOW);
+    }
     if (cfg->refine_radius < 0 || cfg->refine_radius > MSIBM_MAX_RADIUS)
         return fail(MSIBM_ERR_UNSUPPORTED, "refine_radius %d outside 0..%d", cfg->refine_radius,
                     MSIBM_MAX_RADIUS);

@@ -290,14 +290,14 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
         else snprintf(lab, sizeof(lab), "batch_match_%s_l%d", mode_name[l.mode], l.level);
         const int slot = timed ? timing_begin(lab, s) : -1;
         hipError_t e;
-        if (l.kind == STAGE_LEVELS) e = launch_levels_multi(cfg->half_window, a, l.blocks, s);
-        else if (l.kind == STAGE_STATS) e = launch_stats_multi(cfg->half_window, a, l.blocks, s);
+        if (l.kind == STAGE_LEVELS) e = launch_levels_multi(level_n(cfg, l.level), a, l.blocks, s);
+        else if (l.kind == STAGE_STATS) e = launch_stats_multi(level_n(cfg, 0), a, l.blocks, s);
         else if (l.kind == STAGE_ZERO) {
             hipLaunchKernelGGL(zero_multi_kernel, dim3(l.blocks), dim3(256), 0, s, a);
             e = hipGetLastError();
         } else if (l.kind == STAGE_BACKWARD)
-            e = launch_backward_multi(cfg->half_window, slots_for_radius(cfg->soft_radius), a, l.blocks, s);
-        else e = launch_match_multi(cfg->half_window, l.dtype, l.mode, l.nc, a, l.blocks, s);
+            e = launch_backward_multi(level_n(cfg, 0), slots_for_radius(cfg->soft_radius), a, l.blocks, s);
+        else e = launch_match_multi(level_n(cfg, l.level), l.dtype, l.mode, l.nc, a, l.blocks, s);
         if (timed) timing_end(slot, s);
         if (e != hipSuccess) return e;
     }

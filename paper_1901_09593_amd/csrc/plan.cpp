@@ -49,7 +49,6 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
                    std::string* err)
 {
     const int K = lay.K;
-    const int n = cfg->half_window;
     hipError_t e;
     // image pointers per level and view (level 0 is the caller's input)
     const void* img[MSIBM_MAX_LEVELS][2];
@@ -102,15 +101,20 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
         if (e != hipSuccess) return hip_err(e, "pyramid launch", err);
         k += steps;
     }
-    {
+    // statistics: one launch per distinct window size (one for a common n)
+    for (int k0 = 0; k0 < K; ++k0) {
+        bool first = true;
+        for (int k = 0; k < k0; ++k) first = first && level_n(cfg, k) != level_n(cfg, k0);
+        if (!first) continue;
         StatsArgs sa{};
-        for (int k = 0; k < K; ++k)
+        for (int k = k0; k < K; ++k) {
+            if (level_n(cfg, k) != level_n(cfg, k0)) continue;
             for (int v = 0; v < 2; ++v)
-                sa.seg[2 * k + v] = StatsSeg{img[k][v], (WinStat*)(ws + lay.stat[k][v]),
+                sa.seg[sa.nseg++] = StatsSeg{img[k][v], (WinStat*)(ws + lay.stat[k][v]),
                                              k == 0 ? P.dtype : MSIBM_F32, lay.h[k], lay.w[k], pitch[k],
                                              lay.w[k], 0};
-        sa.nseg = 2 * K;
-        sa.n = n;
+        }
+        sa.n = level_n(cfg, k0);
         sa.var_eps = cfg->var_eps;
         TimedLaunch t("stats", s);
         e = launch_stats(sa, s);
@@ -154,6 +158,7 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
                  mode == MODE_FULL ? "full" : (mode == MODE_SOFT ? "soft" : "refine"), k);
         {
             TimedLaunch t(lab, s);
+            const int n = level_n(cfg, k);
             a.variant = select_variant(a, n, k == 0 ? P.dtype : MSIBM_F32, mode, nc, s);
             e = launch_match(n, k == 0 ? P.dtype : MSIBM_F32, mode, nc, a, s);
         }
@@ -200,7 +205,7 @@ int run_pair_backward(const msibm_pair& P, const PairLayout& lay, const msibm_co
     sa.seg[0] = StatsSeg{P.left, (WinStat*)(ws + lay.stat[0][0]), MSIBM_F32, H, W, P.pitch, W, 0};
     sa.seg[1] = StatsSeg{P.right, (WinStat*)(ws + lay.stat[0][1]), MSIBM_F32, H, W, P.pitch, W, 0};
     sa.nseg = 2;
-    sa.n = cfg->half_window;
+    sa.n = level_n(cfg, 0);
     sa.var_eps = cfg->var_eps;
     {
         TimedLaunch t("bwd_stats", s);
@@ -234,7 +239,7 @@ int run_pair_backward(const msibm_pair& P, const PairLayout& lay, const msibm_co
     b.gR = grad_right;
     {
         TimedLaunch t("backward_l0", s);
-        e = launch_backward(cfg->half_window, slots_for_radius(cfg->soft_radius), b, s);
+        e = launch_backward(level_n(cfg, 0), slots_for_radius(cfg->soft_radius), b, s);
     }
     if (e != hipSuccess) return hip_err(e, "backward launch", err);
     return MSIBM_OK;

@@ -14,6 +14,13 @@ int level_range(int D, int k);
 int auto_levels(int D);
 size_t align_up(size_t v);
 
+// Window half-width n_k of level k: the per-level entry, or the common one.
+inline int level_n(const msibm_config* cfg, int k)
+{
+    const int v = (k >= 0 && k < MSIBM_MAX_LEVELS) ? cfg->half_window_levels[k] : 0;
+    return v ? v : cfg->half_window;
+}
+
 // Workspace offsets of one pair.  Level k (k >= 1) holds both views' pyramid
 // images (float, W_k pitch); every level holds both views' window statistics
 // (12 bytes per pixel); levels k >= 1 hold the winner-take-all map (int16).

@@ -41,10 +41,14 @@ class Pair(ctypes.Structure):
                 ("max_disp", ctypes.c_int32), ("num_levels", ctypes.c_int32)]
 
 
+MAX_LEVELS = 8
+
+
 class Config(ctypes.Structure):
     _fields_ = [("half_window", ctypes.c_int32), ("refine_radius", ctypes.c_int32),
                 ("var_eps", ctypes.c_float), ("soft_radius", ctypes.c_int32),
-                ("tau", ctypes.c_float), ("flags", ctypes.c_int32)]
+                ("tau", ctypes.c_float), ("flags", ctypes.c_int32),
+                ("half_window_levels", ctypes.c_int32 * MAX_LEVELS)]
 
 
 _lib = None
@@ -152,9 +156,17 @@ def auto_levels(D: int) -> int:
     return k
 
 
-def make_config(n: int, r: int, var_eps: float, soft_radius: int = 0, tau: float = 0.05,
+def make_config(n, r: int, var_eps: float, soft_radius: int = 0, tau: float = 0.05,
                 flags: int = 0) -> Config:
-    return Config(n, r, float(var_eps), soft_radius, float(tau), flags)
+    """n: the window half-width, or a sequence of per-level half-widths (level 0
+    first; levels past its end keep its last entry)."""
+    if isinstance(n, int):
+        return Config(n, r, float(var_eps), soft_radius, float(tau), flags)
+    ns = [int(v) for v in n]
+    if not ns or len(ns) > MAX_LEVELS:
+        raise ValueError(f"1..{MAX_LEVELS} per-level half-widths")
+    per = (ctypes.c_int32 * MAX_LEVELS)(*(ns + [ns[-1]] * (MAX_LEVELS - len(ns))))
+    return Config(ns[0], r, float(var_eps), soft_radius, float(tau), flags, per)
 
 
 def force_variant(v: int = -1):

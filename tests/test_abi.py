@@ -72,10 +72,18 @@ def test_config_and_pair_validation(lib):
     arr = (msibm.Pair * 1)(P)
     good = msibm.make_config(3, 2, 0.065)
     assert e.msibm_workspace_size(arr, 1, ctypes.byref(good)) > 0
+    disp_probe = (ctypes.c_void_p * 1)(0x3000)
     for bad in (msibm.make_config(0, 2, 0.065), msibm.make_config(3, 5, 0.065),
                 msibm.make_config(3, 2, -1.0), msibm.make_config(3, 2, 0.1, 2, 0.0),
                 msibm.make_config(3, 2, 0.1, 0, 0.05, 64)):
         assert e.msibm_workspace_size(arr, 1, ctypes.byref(bad)) == 0
+    # per-level window half-widths: 1..6, or 0 for the common one
+    assert e.msibm_workspace_size(arr, 1, ctypes.byref(msibm.make_config([5, 2, 1], 2, 0.065))) > 0
+    for per in ([3, 7], [3, 2, -1]):
+        cfg = msibm.make_config(per, 2, 0.065)
+        assert e.msibm_workspace_size(arr, 1, ctypes.byref(cfg)) == 0
+        rc = e.msibm_disparity(arr, 1, ctypes.byref(cfg), disp_probe, None, None, None, None, 0, None)
+        assert rc == -4 and b"half_window_levels" in e.msibm_last_error()
     # the soft level needs float images
     soft = msibm.make_config(3, 2, 0.065, 3, 0.05)
     assert e.msibm_workspace_size(arr, 1, ctypes.byref(soft)) == 0

@@ -210,6 +210,38 @@ def test_pyramid_launches_match_level_by_level(M, dtype, K):
     assert torch.equal(maps[1], out["prior1"])
 
 
+@pytest.mark.parametrize("dtype,ns", [("u8", [4, 2, 1]), ("f32", [3, 3, 2, 1])])
+def test_per_level_windows(M, dtype, ns):
+    """Per-level window sizes (the block size that shrinks with the level): the
+    forward equals level-by-level matching with each level's window, each level
+    agrees with the oracle fed the GPU's coarser map, and the batched path
+    (with its graph) gives the same maps."""
+    K = len(ns)
+    p = _tex_pair(70 + K, 120, 200, 16, dtype)
+    D, r = 64, 2
+    eps = 0.065 if dtype == "u8" else 1e-6
+    Lg, Rg = dev(p.left), dev(p.right)
+    out = M.disparity(Lg, Rg, D, K, ns, r, eps, with_prior1=True)
+    PL, PR = M.pyramid(Lg, K), M.pyramid(Rg, K)
+    maps, costs = [None] * K, [None] * K
+    for k in range(K - 1, -1, -1):
+        Lk = Lg if k == 0 else PL[k]
+        Rk = Rg if k == 0 else PR[k]
+        prior = None if k == K - 1 else maps[k + 1]
+        maps[k], costs[k] = M.match_level(Lk, Rk, ns[k], -(-D // (1 << k)), prior, r, eps)
+    assert torch.equal(maps[0], out["disp"]) and torch.equal(costs[0], out["cost"])
+    assert torch.equal(maps[1], out["prior1"])
+    for k in range(K):
+        Lk, Rk = host(PL[k]).astype(np.float64), host(PR[k]).astype(np.float64)
+        prior = None if k == K - 1 else host(maps[k + 1])
+        st = check_level(host(maps[k]), host(costs[k]), Lk, Rk, ns[k], -(-D // (1 << k)), prior, r, eps)
+        print(f"level {k} n={ns[k]}", st)
+    for flags in (M.FLAG_BATCHED, M.FLAG_BATCHED | M.FLAG_GRAPH):
+        got = M.disparity_many([Lg], [Rg], [D], [K], ns, r, eps, with_prior1=True, flags=flags)[0]
+        assert torch.equal(got["disp"], out["disp"]) and torch.equal(got["prior1"], out["prior1"])
+        assert torch.equal(got["cost"], out["cost"])
+
+
 def test_mid1436_full_size_sampled(M):
     """The benchmark workload at full size, in the launch configuration the
     benchmark times; level 0 checked on sampled pixels against the oracle fed

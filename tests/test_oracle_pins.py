@@ -205,6 +205,24 @@ def test_constant_shift_recovered_at_every_level(K, s):
         assert np.all(inner == s >> k), (k, np.unique(inner))
 
 
+def test_constant_shift_recovered_with_halving_windows():
+    # Section III's block size halving per level (n = 4, 2, 1): the shift is still
+    # recovered at every level, and the coarsest level's search is the flat
+    # search of that level with its own window
+    H, W, D, K, s = 64, 96, 40, 3, 8
+    ns = [4, 2, 1]
+    L, R = _shifted_pair(H, W, s, seed=5)
+    out = oracle.disparity(L, R, D, K, ns, 1, 0.065)
+    for k in range(K):
+        dk = out[k][0]
+        m = 3 * (1 << (K - 1 - k)) + ns[k] + 3
+        inner = dk[m:-m, s // (1 << k) + m:-m]
+        assert np.all(inner == s >> k), (k, np.unique(inner))
+    top = oracle.flat_bm(oracle.pyramid(L, K)[K - 1], oracle.pyramid(R, K)[K - 1], oracle.level_range(D, K - 1),
+                         ns[K - 1], 0.065)
+    assert np.array_equal(top[0], out[K - 1][0])
+
+
 def test_odd_shift_recovered_at_level_zero():
     H, W, n, D = 48, 80, 2, 30
     L, R = _shifted_pair(H, W, 7, seed=11)
