@@ -53,6 +53,8 @@ def _load():
         c_int, c_double = ctypes.c_int, ctypes.c_double
         lib.orc_reduce.argtypes = [_D, c_int, c_int, _D]
         lib.orc_reduce.restype = None
+        lib.orc_blur.argtypes = [_D, c_int, c_int, _D]
+        lib.orc_blur.restype = None
         lib.orc_zncc.argtypes = [_D, _D, c_int, c_int, c_int, c_int, c_int, c_int, c_double]
         lib.orc_zncc.restype = c_double
         lib.orc_match_level.argtypes = [_D, _D, c_int, c_int, c_int, c_int, _I16, c_int, c_int,
@@ -97,6 +99,16 @@ def reduce(img: np.ndarray) -> np.ndarray:
     H, W = x.shape
     out = np.empty(((H + 1) // 2, (W + 1) // 2), dtype=np.float64)
     _load().orc_reduce(_p(x, _D), H, W, _p(out, _D))
+    return out
+
+
+def blur(img: np.ndarray) -> np.ndarray:
+    """The pyramid's 5x5 binomial blur at every pixel, clamp-to-edge (the blur of
+    the original image that Section IV credits for robustness to noise)."""
+    x = _f64(img)
+    H, W = x.shape
+    out = np.empty((H, W), dtype=np.float64)
+    _load().orc_blur(_p(x, _D), H, W, _p(out, _D))
     return out
 
 
@@ -185,7 +197,7 @@ def match_level(L: np.ndarray, R: np.ndarray, n: int, Dk: int,
 
 
 def disparity(left: np.ndarray, right: np.ndarray, D: int, K: int, n, r: int,
-              eps: float, priors: Optional[List[Optional[np.ndarray]]] = None):
+              eps: float, priors: Optional[List[Optional[np.ndarray]]] = None, preblur: bool = False):
     """The hierarchical forward pass (Section III, hot path).
 
     n is the window half-width of every level, or a sequence of per-level
@@ -193,11 +205,15 @@ def disparity(left: np.ndarray, right: np.ndarray, D: int, K: int, n, r: int,
     block size that Section III shrinks level by level.  Returns a list, index
     k = level, of (d_k, C_k, C2_k).  `priors[k]`, if given, replaces the map that
     feeds level k (teacher forcing: the level-(k+1) map used as the prior of
-    level k)."""
+    level k).  With `preblur`, level 0 is matched on the blurred input (the
+    pyramid is still built from the input itself)."""
     def nk(k):
         return n if isinstance(n, (int, np.integer)) else n[min(k, len(n) - 1)]
     PL = pyramid(left, K)
     PR = pyramid(right, K)
+    if preblur:
+        PL[0] = blur(left)
+        PR[0] = blur(right)
     out: List = [None] * K
     kc = K - 1
     out[kc] = match_level(PL[kc], PR[kc], nk(kc), level_range(D, kc), None, r, eps)

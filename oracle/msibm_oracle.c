@@ -44,6 +44,24 @@ void orc_reduce(const double* in, int H, int W, double* out)
     }
 }
 
+/* The same 5x5 binomial blur at every pixel, the "Gaussian blur over the original
+ * image" of Section IV (matching on a blurred level 0 is the pre-blur variant):
+ * out(y, x) = sum_{a,b} w_a w_b in(clamp(y + a), clamp(x + b)). */
+void orc_blur(const double* in, int H, int W, double* out)
+{
+    static const double w[5] = {1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16};
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            double s = 0.0;
+            for (int a = -2; a <= 2; ++a)
+                for (int b = -2; b <= 2; ++b)
+                    s += w[a + 2] * w[b + 2] * in[(size_t)clampi(y + a, 0, H - 1) * W + clampi(x + b, 0, W - 1)];
+            out[(size_t)y * W + x] = s;
+        }
+    }
+}
+
 /* Zero-mean normalised cross-correlation of the (2n+1)^2 window of L centred at
  * (i, j) and the window of R centred at (i, j - z) (Eq. 2, with the matching
  * cost of Eq. 1).  Readings: each view is centred by its own window mean and the

@@ -223,6 +223,37 @@ def test_constant_shift_recovered_with_halving_windows():
     assert np.array_equal(top[0], out[K - 1][0])
 
 
+def test_blur_pins():
+    # kernel sums to 1 (a constant stays constant), an impulse spreads into the
+    # outer product of the binomial weights, linear functions pass unchanged and
+    # x^2 + y^2 gains the kernel's second moment (1 per axis) away from the borders
+    w = np.array([1, 4, 6, 4, 1], dtype=np.float64) / 16
+    assert np.array_equal(oracle.blur(np.full((9, 11), 37.0)), np.full((9, 11), 37.0))
+    imp = np.zeros((11, 13))
+    imp[5, 6] = 1.0
+    b = oracle.blur(imp)
+    assert np.allclose(b[3:8, 4:9], np.outer(w, w), atol=0, rtol=1e-15) and b.sum() == 1.0
+    yy, xx = np.mgrid[0:20, 0:24].astype(np.float64)
+    lin = oracle.blur(3 * xx - 2 * yy + 5)
+    assert np.allclose(lin[2:-2, 2:-2], (3 * xx - 2 * yy + 5)[2:-2, 2:-2], atol=1e-12)
+    quad = oracle.blur(xx ** 2 + yy ** 2)
+    assert np.allclose(quad[2:-2, 2:-2], (xx ** 2 + yy ** 2 + 2)[2:-2, 2:-2], atol=1e-9)
+    # one pyramid step is the blur kept at even rows and columns
+    img = _rng(21).integers(0, 256, size=(17, 22)).astype(np.float64)
+    assert np.array_equal(oracle.reduce(img), oracle.blur(img)[::2, ::2])
+
+
+def test_preblur_matches_blurred_level_zero():
+    # the pre-blur variant matches level 0 on the blurred images and leaves the
+    # coarser levels alone
+    p = synth.make_pair(6, 40, 72, 4, 2, 20, True, 1.0, 0.0, 2.0, "u8")
+    a = oracle.disparity(p.left, p.right, 24, 2, 2, 2, 0.065)
+    b = oracle.disparity(p.left, p.right, 24, 2, 2, 2, 0.065, preblur=True)
+    assert np.array_equal(a[1][0], b[1][0])
+    ref = oracle.match_level(oracle.blur(p.left), oracle.blur(p.right), 2, 24, a[1][0], 2, 0.065)
+    assert np.array_equal(ref[0], b[0][0])
+
+
 def test_odd_shift_recovered_at_level_zero():
     H, W, n, D = 48, 80, 2, 30
     L, R = _shifted_pair(H, W, 7, seed=11)
