@@ -192,6 +192,44 @@ def section_batched(torch, M, synth, steps):
     return res
 
 
+def section_accuracy(torch, M, synth, steps):
+    """Disparity error against the generator's ground truth (the synthetic
+    stand-in for the paper's accuracy table): the configured hierarchy, the
+    paper's own parameters (refine +-1, block size halving per level from 11x11,
+    level 0 pre-blurred) and flat block matching, on non-occluded pixels away
+    from the borders."""
+    dev = torch.device("cuda:0")
+    res = {}
+    for name in ("small320", "mid1436"):
+        p, cfg = synth.workload(name)
+        H, W, D, K, n, r, eps = cfg.height, cfg.width, cfg.max_disp, cfg.levels, cfg.half_window, \
+            cfg.refine_radius, cfg.var_eps
+        Lg, Rg = torch.from_numpy(p.left).to(dev), torch.from_numpy(p.right).to(dev)
+        halving = [max(1, 5 >> k) for k in range(K)]  # 11x11, 5x5, 3x3, 3x3 ...
+        b = max(halving[0], n) + 1
+        vis = p.nonocc.copy()
+        vis[:b, :] = vis[H - b:, :] = False
+        vis[:, :b] = vis[:, W - b:] = False
+        runs = {
+            "hierarchy": dict(n=n, r=r, preblur=False, K=K),
+            "paper_parameters": dict(n=halving, r=1, preblur=True, K=K),
+            "flat_block_matching": dict(n=n, r=0, preblur=False, K=1),
+        }
+        out = {"workload": f"{W}x{H} uint8 pair ({name}), D={D}", "pixels_scored": int(vis.sum()),
+               "paper_parameters": f"refine +-1, windows {[2 * v + 1 for v in halving]} by level, level 0 "
+                                   "pre-blurred"}
+        for label, c in runs.items():
+            def fwd():
+                return M.disparity(Lg, Rg, D, c["K"], c["n"], c["r"], eps, preblur=c["preblur"])
+            d = fwd()["disp"].cpu().numpy().astype(np.float64)
+            err = np.abs(d - p.disp)[vis]
+            ms = time_ms(torch, fwd, steps, 2)
+            out[label] = {"mean_abs_err_px": float(err.mean()), "bad_1px": float((err > 1).mean()),
+                          "bad_2px": float((err > 2).mean()), "ms_per_pair": ms}
+        res[name] = out
+    return res
+
+
 def section_fwd_bwd(torch, M, synth, name, count, steps):
     """Forward + masked mean-L1 loss gradient + backward for `count` float pairs."""
     dev = torch.device("cuda:0")
@@ -278,8 +316,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="batched,fwd_bwd",
-                    help="extra sections beside the headline step: batched, fwd_bwd, or none")
+    ap.add_argument("--sections", default="batched,fwd_bwd,accuracy",
+                    help="extra sections beside the headline step: batched, fwd_bwd, accuracy, or none")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the default kernel shapes instead of measuring them first")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -392,6 +430,9 @@ def main():
             "diff960x8": section_fwd_bwd(torch, msibm, synth, "diff960", 8, nsteps),
             "hires2880x4": section_fwd_bwd(torch, msibm, synth, "hires2880", 4, max(3, nsteps // 2)),
         }
+
+    if "accuracy" in sections:
+        extra["accuracy"] = section_accuracy(torch, msibm, synth, nsteps)
 
     # the FP64 oracle on the host cores: whole pairs until the time budget is used
     cpu = None

@@ -88,8 +88,10 @@ msibm_status validate_config(const msibm_config* cfg)
         return fail(MSIBM_ERR_INVALID_ARG, "tau must be finite and > 0");
     if (cfg->flags & MSIBM_FLAG_PERSISTENT)
         return fail(MSIBM_ERR_UNSUPPORTED, "the persistent single-launch scheduler is switched off");
-    if (cfg->flags & ~(MSIBM_FLAG_BATCHED | MSIBM_FLAG_GRAPH))
+    if (cfg->flags & ~(MSIBM_FLAG_BATCHED | MSIBM_FLAG_GRAPH | MSIBM_FLAG_PREBLUR))
         return fail(MSIBM_ERR_INVALID_ARG, "unknown flags 0x%x", cfg->flags);
+    if ((cfg->flags & MSIBM_FLAG_PREBLUR) && (cfg->flags & MSIBM_FLAG_BATCHED))
+        return fail(MSIBM_ERR_UNSUPPORTED, "MSIBM_FLAG_PREBLUR runs on the plain path only");
     if ((cfg->flags & MSIBM_FLAG_GRAPH) && !(cfg->flags & MSIBM_FLAG_BATCHED))
         return fail(MSIBM_ERR_INVALID_ARG, "MSIBM_FLAG_GRAPH needs MSIBM_FLAG_BATCHED");
     return MSIBM_OK;
@@ -118,7 +120,7 @@ msibm_status validate_pair(const msibm_pair& p, int idx, const msibm_config* cfg
 }
 
 // Workspace layout of one pair (offsets from the pair's base).
-PairLayout pair_layout(const msibm_pair& p, int K)
+PairLayout pair_layout(const msibm_pair& p, int K, bool preblur)
 {
     PairLayout L{};
     L.K = K;
@@ -140,6 +142,11 @@ PairLayout pair_layout(const msibm_pair& p, int K)
             off = align_up(off + px * sizeof(int16_t));
         }
     }
+    if (preblur)
+        for (int v = 0; v < 2; ++v) {
+            L.blur[v] = off;
+            off = align_up(off + (size_t)p.height * p.width * sizeof(float));
+        }
     L.bytes = off;
     return L;
 }
@@ -293,7 +300,7 @@ size_t msibm_workspace_size(const msibm_pair* pairs, int32_t n_pairs, const msib
     for (int p = 0; p < n_pairs; ++p) {
         int K;
         if (validate_pair(pairs[p], p, cfg, &K) != MSIBM_OK) return 0;
-        tot += pair_layout(pairs[p], K).bytes;
+        tot += pair_layout(pairs[p], K, (cfg->flags & MSIBM_FLAG_PREBLUR) != 0).bytes;
     }
     tot += batch_extra_bytes(pairs, n_pairs, cfg);
     return tot;
@@ -331,7 +338,7 @@ msibm_status msibm_disparity(const msibm_pair* pairs, int32_t n_pairs, const msi
     size_t base = 0;
     for (int p = 0; p < n_pairs; ++p) {
         const msibm_pair& P = pairs[p];
-        const PairLayout lay = pair_layout(P, Ks[p]);
+        const PairLayout lay = pair_layout(P, Ks[p], (cfg->flags & MSIBM_FLAG_PREBLUR) != 0);
         char* ws = (char*)workspace + base;
         base += lay.bytes;
         std::string err;
@@ -355,6 +362,8 @@ msibm_status msibm_backward(const msibm_pair* pairs, int32_t n_pairs, const msib
     msibm_status st = validate_config(cfg);
     if (st != MSIBM_OK) return st;
     if (cfg->soft_radius < 1) return fail(MSIBM_ERR_INVALID_ARG, "backward needs soft_radius >= 1");
+    if (cfg->flags & MSIBM_FLAG_PREBLUR)
+        return fail(MSIBM_ERR_UNSUPPORTED, "MSIBM_FLAG_PREBLUR is a forward-only variant");
     std::vector<int> Ks(n_pairs);
     for (int p = 0; p < n_pairs; ++p) {
         st = validate_pair(pairs[p], p, cfg, &Ks[p]);

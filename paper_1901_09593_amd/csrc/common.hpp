@@ -99,6 +99,13 @@ struct StatsArgs {
 
 // Two or three pyramid steps in one launch: source level (the caller's input or
 // a float level) to levels +1 .. +steps, both views.
+// Full-resolution binomial blur of both views (the pre-blur variant's level 0).
+struct BlurArgs {
+    const void* src[2];
+    float* dst[2];
+    int H, W, spitch, dpitch;
+};
+
 constexpr int TW_MAXS = 3;
 struct TowerArgs {
     const void* src[2];
@@ -184,6 +191,7 @@ hipError_t launch_reduce(int dtype, const ReduceArgs& a, hipStream_t s);
 hipError_t launch_convert(int dtype, const ConvertArgs& a, hipStream_t s);
 hipError_t launch_stats(StatsArgs a, hipStream_t s);
 hipError_t launch_tower(int dtype, const TowerArgs& a, hipStream_t s);
+hipError_t launch_blur(int dtype, const BlurArgs& a, hipStream_t s);
 hipError_t launch_match(int n, int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
 
 // Multi-segment launches (batched path); `blocks` = total tiles of the segments.

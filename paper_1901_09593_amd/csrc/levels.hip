@@ -196,6 +196,23 @@ static int number_stats_tiles(StatsArgs& a)
     return tiles;
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void blur_kernel(BlurArgs a)
+{
+    __shared__ BlurSmem sm;
+    const int v = blockIdx.z;
+    blur_tile<T>(static_cast<const T*>(v ? a.src[1] : a.src[0]), v ? a.dst[1] : a.dst[0], a.H, a.W, a.spitch,
+                 a.dpitch, blockIdx.x, blockIdx.y, sm);
+}
+
+hipError_t launch_blur(int dtype, const BlurArgs& a, hipStream_t s)
+{
+    dim3 grid((a.W + BL_W - 1) / BL_W, (a.H + BL_H - 1) / BL_H, 2);
+    if (dtype == 0) hipLaunchKernelGGL(blur_kernel<uint8_t>, grid, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(blur_kernel<float>, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_tower(int dtype, const TowerArgs& a, hipStream_t s)
 {
     if (a.steps < 2 || a.steps > TW_MAXS) return hipErrorInvalidValue;

@@ -80,6 +80,59 @@ __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
     reduce_tile<T>(a, blockIdx.z, blockIdx.x, blockIdx.y, sm);
 }
 
+// One 16 x 64 tile of the same binomial blur at every pixel (stride 1) of one
+// view, with the arithmetic of reduce_tile: h = sum_b w_b x, out = 2^-8 sum_t
+// w_t h_t with integer weights (exact for uint8 input).  256 threads.
+constexpr int BL_W = 64, BL_H = 16, BL_IW = BL_W + 4, BL_IH = BL_H + 4;
+struct BlurSmem {
+    float in[BL_IH][BL_IW + 1];
+    float hs[BL_IH][BL_W + 1];
+};
+
+template <typename T>
+__device__ __forceinline__ void blur_tile(const T* __restrict__ src, float* __restrict__ dst, int H, int W,
+                                          int spitch, int dpitch, int bx, int by, BlurSmem& sm)
+{
+    const int x0 = bx * BL_W, y0 = by * BL_H;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    // stage: every load issued before the LDS stores
+    constexpr int RI = (BL_IH + 3) / 4, CI = (BL_IW + 63) / 64;
+    T v[RI][CI];
+#pragma unroll
+    for (int ri = 0; ri < RI; ++ri) {
+        const T* srow = src + (size_t)clampi(y0 - 2 + min(wave + 4 * ri, BL_IH - 1), 0, H - 1) * spitch;
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci) v[ri][ci] = srow[clampi(x0 - 2 + min(lane + 64 * ci, BL_IW - 1), 0, W - 1)];
+    }
+#pragma unroll
+    for (int ri = 0; ri < RI; ++ri) {
+        const int rr = wave + 4 * ri;
+#pragma unroll
+        for (int ci = 0; ci < CI; ++ci) {
+            const int cc = lane + 64 * ci;
+            if (rr < BL_IH && cc < BL_IW) sm.in[rr][cc] = to_f(v[ri][ci]);
+        }
+    }
+    __syncthreads();
+    const float w[5] = {1.f, 4.f, 6.f, 4.f, 1.f};
+    for (int rr = wave; rr < BL_IH; rr += 4) {
+        float h = 0.f;
+#pragma unroll
+        for (int b = 0; b < 5; ++b) h = fmaf(w[b], sm.in[rr][lane + b], h);
+        sm.hs[rr][lane] = h;
+    }
+    __syncthreads();
+    const int x = x0 + lane;
+#pragma unroll
+    for (int k = 0; k < BL_H / 4; ++k) {
+        const int oy = wave + 4 * k, y = y0 + oy;
+        float acc = 0.f;
+#pragma unroll
+        for (int t = 0; t < 5; ++t) acc = fmaf(w[t], sm.hs[oy + t][lane], acc);
+        if (x < W && y < H) dst[(size_t)y * dpitch + x] = acc * (1.f / 256.f);
+    }
+}
+
 // Several pyramid steps in one workgroup ("tower"): the tile of the last level
 // (TW_FH x TW_FW pixels) together with every level's region that it depends on.
 // Step j maps the region of level j-1 to that of level j: region rows

@@ -101,6 +101,28 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
         if (e != hipSuccess) return hip_err(e, "pyramid launch", err);
         k += steps;
     }
+    // pre-blur variant: level 0 is matched on the blurred input (the pyramid
+    // above was built from the input itself)
+    const bool preblur = (cfg->flags & MSIBM_FLAG_PREBLUR) != 0;
+    if (preblur) {
+        BlurArgs b{};
+        for (int v = 0; v < 2; ++v) {
+            b.src[v] = img[0][v];
+            b.dst[v] = (float*)(ws + lay.blur[v]);
+        }
+        b.H = P.height;
+        b.W = P.width;
+        b.spitch = P.pitch;
+        b.dpitch = P.width;
+        TimedLaunch t("preblur_l0", s);
+        e = launch_blur(P.dtype, b, s);
+        if (e != hipSuccess) return hip_err(e, "blur launch", err);
+        img[0][0] = b.dst[0];
+        img[0][1] = b.dst[1];
+        pitch[0] = P.width;
+    }
+    // element type of level k's images
+    auto dtype_of = [&](int k) { return (k == 0 && !preblur) ? P.dtype : MSIBM_F32; };
     // statistics: one launch per distinct window size (one for a common n)
     for (int k0 = 0; k0 < K; ++k0) {
         bool first = true;
@@ -110,9 +132,8 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
         for (int k = k0; k < K; ++k) {
             if (level_n(cfg, k) != level_n(cfg, k0)) continue;
             for (int v = 0; v < 2; ++v)
-                sa.seg[sa.nseg++] = StatsSeg{img[k][v], (WinStat*)(ws + lay.stat[k][v]),
-                                             k == 0 ? P.dtype : MSIBM_F32, lay.h[k], lay.w[k], pitch[k],
-                                             lay.w[k], 0};
+                sa.seg[sa.nseg++] = StatsSeg{img[k][v], (WinStat*)(ws + lay.stat[k][v]), dtype_of(k), lay.h[k],
+                                             lay.w[k], pitch[k], lay.w[k], 0};
         }
         sa.n = level_n(cfg, k0);
         sa.var_eps = cfg->var_eps;
@@ -159,8 +180,8 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
         {
             TimedLaunch t(lab, s);
             const int n = level_n(cfg, k);
-            a.variant = select_variant(a, n, k == 0 ? P.dtype : MSIBM_F32, mode, nc, s);
-            e = launch_match(n, k == 0 ? P.dtype : MSIBM_F32, mode, nc, a, s);
+            a.variant = select_variant(a, n, dtype_of(k), mode, nc, s);
+            e = launch_match(n, dtype_of(k), mode, nc, a, s);
         }
         if (e != hipSuccess) return hip_err(e, "match launch", err);
     }

@@ -30,10 +30,11 @@ struct PairLayout {
     size_t img[MSIBM_MAX_LEVELS][2];
     size_t stat[MSIBM_MAX_LEVELS][2];
     size_t map[MSIBM_MAX_LEVELS];
+    size_t blur[2];           // pre-blurred level 0 (float, pitch W), when asked for
     size_t bytes;
 };
 
-PairLayout pair_layout(const msibm_pair& p, int K);
+PairLayout pair_layout(const msibm_pair& p, int K, bool preblur = false);
 
 struct BatchOutputs {
     int16_t* const* disp;

@@ -24,6 +24,7 @@ MSIBM_F32 = 1
 FLAG_BATCHED = 1
 FLAG_GRAPH = 2
 FLAG_PERSISTENT = 4  # switched off: calls with it fail with MsibmError
+FLAG_PREBLUR = 8     # plain forward: level 0 matched on the blurred input
 MAX_LEVELS = 8
 
 
@@ -281,12 +282,13 @@ def workspace_bytes(pairs_arr, n: int, cfg: Config) -> int:
 
 def disparity(L: torch.Tensor, R: torch.Tensor, D: int, K: int, n: int, r: int, var_eps: float,
               soft_radius: int = 0, tau: float = 0.05, with_cost: bool = True,
-              with_prior1: bool = False) -> Dict[str, torch.Tensor]:
+              with_prior1: bool = False, preblur: bool = False) -> Dict[str, torch.Tensor]:
     """Hierarchical forward pass of one pair.  Returns a dict with 'disp'
     (int16), 'cost' (float, optional), 'soft' (float, if soft_radius > 0) and
-    'prior1' (int16 level-1 map, if requested or soft)."""
+    'prior1' (int16 level-1 map, if requested or soft).  preblur: match level 0
+    on the input blurred with the pyramid's kernel."""
     out = disparity_many([L], [R], [D], [K], n, r, var_eps, soft_radius, tau, with_cost,
-                         with_prior1)
+                         with_prior1, flags=FLAG_PREBLUR if preblur else 0)
     return out[0]
 
 
@@ -295,7 +297,8 @@ def disparity_many(lefts: Sequence[torch.Tensor], rights: Sequence[torch.Tensor]
                    tau: float = 0.05, with_cost: bool = True, with_prior1: bool = False,
                    flags: int = 0, workspace: Optional[torch.Tensor] = None,
                    outputs: Optional[List[Dict[str, torch.Tensor]]] = None) -> List[Dict[str, torch.Tensor]]:
-    """Forward pass of several pairs in one call (flags: FLAG_BATCHED, FLAG_GRAPH).
+    """Forward pass of several pairs in one call (flags: FLAG_BATCHED, FLAG_GRAPH,
+    or FLAG_PREBLUR on the plain path).
     `workspace` and `outputs` may be passed in to reuse buffers across calls."""
     pairs, keep = _pairs(lefts, rights, Ds, Ks)
     npair = len(lefts)

@@ -242,6 +242,24 @@ def test_per_level_windows(M, dtype, ns):
         assert torch.equal(got["cost"], out["cost"])
 
 
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_preblur_level_zero(M, dtype):
+    """The pre-blur variant: level 0 is matched on the blurred input (checked
+    against the oracle on its own blurred images, fed the GPU's level-1 map);
+    the coarser levels are those of the plain forward."""
+    p = _tex_pair(81, 96, 170, 12, dtype)
+    D, K, n, r = 48, 3, 3, 2
+    eps = 0.065 if dtype == "u8" else 1e-6
+    Lg, Rg = dev(p.left), dev(p.right)
+    plain = M.disparity(Lg, Rg, D, K, n, r, eps, with_prior1=True)
+    out = M.disparity(Lg, Rg, D, K, n, r, eps, with_prior1=True, preblur=True)
+    assert torch.equal(plain["prior1"], out["prior1"])
+    Lb, Rb = oracle.blur(p.left), oracle.blur(p.right)
+    st = check_level(host(out["disp"]), host(out["cost"]), Lb, Rb, n, D, host(out["prior1"]), r, eps)
+    print("preblur level 0", st)
+    assert st["mismatch"] <= 0.01
+
+
 def test_mid1436_full_size_sampled(M):
     """The benchmark workload at full size, in the launch configuration the
     benchmark times; level 0 checked on sampled pixels against the oracle fed
