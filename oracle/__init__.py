@@ -55,6 +55,8 @@ def _load():
         lib.orc_reduce.restype = None
         lib.orc_blur.argtypes = [_D, c_int, c_int, _D]
         lib.orc_blur.restype = None
+        lib.orc_median.argtypes = [_I16, _D, c_int, c_int, c_double, _I16]
+        lib.orc_median.restype = None
         lib.orc_zncc.argtypes = [_D, _D, c_int, c_int, c_int, c_int, c_int, c_int, c_double]
         lib.orc_zncc.restype = c_double
         lib.orc_match_level.argtypes = [_D, _D, c_int, c_int, c_int, c_int, _I16, c_int, c_int,
@@ -196,8 +198,21 @@ def match_level(L: np.ndarray, R: np.ndarray, n: int, Dk: int,
     return d, C, C2
 
 
+def median_filter(d: np.ndarray, C: np.ndarray, alpha: float) -> np.ndarray:
+    """Selective median filtering (Eq. 10): pixels with C <= alpha take the lower
+    median disparity of the good (C > alpha) pixels of their 5x5 patch."""
+    dd = np.ascontiguousarray(d, dtype=np.int16)
+    CC = _f64(C)
+    H, W = dd.shape
+    assert CC.shape == dd.shape
+    out = np.empty_like(dd)
+    _load().orc_median(_p(dd, _I16), _p(CC, _D), H, W, float(alpha), _p(out, _I16))
+    return out
+
+
 def disparity(left: np.ndarray, right: np.ndarray, D: int, K: int, n, r: int,
-              eps: float, priors: Optional[List[Optional[np.ndarray]]] = None, preblur: bool = False):
+              eps: float, priors: Optional[List[Optional[np.ndarray]]] = None, preblur: bool = False,
+              median_alpha: Optional[float] = None):
     """The hierarchical forward pass (Section III, hot path).
 
     n is the window half-width of every level, or a sequence of per-level
@@ -206,7 +221,9 @@ def disparity(left: np.ndarray, right: np.ndarray, D: int, K: int, n, r: int,
     k = level, of (d_k, C_k, C2_k).  `priors[k]`, if given, replaces the map that
     feeds level k (teacher forcing: the level-(k+1) map used as the prior of
     level k).  With `preblur`, level 0 is matched on the blurred input (the
-    pyramid is still built from the input itself)."""
+    pyramid is still built from the input itself).  With `median_alpha`, every
+    level's map goes through the selective median filter (Eq. 10) before it is
+    returned and propagated; C is the matched cost before the filter."""
     def nk(k):
         return n if isinstance(n, (int, np.integer)) else n[min(k, len(n) - 1)]
     PL = pyramid(left, K)
@@ -214,14 +231,18 @@ def disparity(left: np.ndarray, right: np.ndarray, D: int, K: int, n, r: int,
     if preblur:
         PL[0] = blur(left)
         PR[0] = blur(right)
+    def filtered(res):
+        if median_alpha is None:
+            return res
+        return (median_filter(res[0], res[1], median_alpha),) + tuple(res[1:])
     out: List = [None] * K
     kc = K - 1
-    out[kc] = match_level(PL[kc], PR[kc], nk(kc), level_range(D, kc), None, r, eps)
+    out[kc] = filtered(match_level(PL[kc], PR[kc], nk(kc), level_range(D, kc), None, r, eps))
     for k in range(K - 2, -1, -1):
         prior = out[k + 1][0]
         if priors is not None and priors[k] is not None:
             prior = priors[k]
-        out[k] = match_level(PL[k], PR[k], nk(k), level_range(D, k), prior, r, eps)
+        out[k] = filtered(match_level(PL[k], PR[k], nk(k), level_range(D, k), prior, r, eps))
     return out
 
 

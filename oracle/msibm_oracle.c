@@ -319,3 +319,37 @@ void orc_match_pixels(const double* L, const double* R, int H, int W, int n, int
         C2[q] = second;
     }
 }
+
+/* Selective median filtering (Section III.D, Eq. 10).  A pixel whose matched
+ * cost is good (C > alpha) keeps its disparity; any other pixel takes the median
+ * of the disparities of the good pixels of the 5x5 patch around it.  Readings:
+ * the patch holds only pixels inside the image; the median of an even count is
+ * the lower one; with no good pixel in the patch the disparity is kept; every
+ * pixel reads the unfiltered map (d_in), so the order of the pixels does not
+ * matter.  Values are sorted by insertion, the plainest correct way. */
+void orc_median(const int16_t* d_in, const double* C, int H, int W, double alpha, int16_t* d_out)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < H; ++i) {
+        for (int j = 0; j < W; ++j) {
+            const size_t o = (size_t)i * W + j;
+            d_out[o] = d_in[o];
+            if (C[o] > alpha) continue;
+            int v[25], m = 0;
+            for (int a = -2; a <= 2; ++a)
+                for (int b = -2; b <= 2; ++b) {
+                    const int y = i + a, x = j + b;
+                    if (y < 0 || y >= H || x < 0 || x >= W) continue;
+                    const size_t q = (size_t)y * W + x;
+                    if (!(C[q] > alpha)) continue;
+                    int t = m++;
+                    while (t > 0 && v[t - 1] > d_in[q]) {
+                        v[t] = v[t - 1];
+                        --t;
+                    }
+                    v[t] = d_in[q];
+                }
+            if (m > 0) d_out[o] = (int16_t)v[(m - 1) / 2];
+        }
+    }
+}

@@ -254,6 +254,51 @@ def test_preblur_matches_blurred_level_zero():
     assert np.array_equal(ref[0], b[0][0])
 
 
+def test_selective_median_pins():
+    rng = _rng(31)
+    d = rng.integers(0, 40, size=(9, 12)).astype(np.int16)
+    C = rng.uniform(-1, 1, size=(9, 12))
+    # every pixel good (C > -2) or every pixel bad (no good neighbour): unchanged
+    assert np.array_equal(oracle.median_filter(d, C, -2.0), d)
+    assert np.array_equal(oracle.median_filter(d, C, 2.0), d)
+    # a bad pixel among good ones takes the lower median of its good 5x5 patch,
+    # read from the unfiltered map; good pixels keep their value
+    C = np.full((9, 12), 0.95)
+    C[4, 5] = C[4, 6] = 0.2       # two bad neighbours
+    C[2, 3] = 0.5                  # a bad pixel inside the patch of (4, 5)
+    out = oracle.median_filter(d, C, 0.9)
+    good = C > 0.9
+    for (i, j) in ((4, 5), (4, 6), (2, 3)):
+        ys, xs = np.mgrid[max(0, i - 2):min(9, i + 3), max(0, j - 2):min(12, j + 3)]
+        vals = np.sort(d[ys, xs][good[ys, xs]])
+        assert out[i, j] == vals[(len(vals) - 1) // 2], (i, j)
+    keep = np.ones_like(good)
+    keep[4, 5] = keep[4, 6] = keep[2, 3] = False
+    assert np.array_equal(out[keep], d[keep])
+    # patches are clipped at the image: a corner pixel sees only its 3x3 in-image part
+    C2 = np.full((9, 12), 0.95)
+    C2[0, 0] = 0.0
+    out2 = oracle.median_filter(d, C2, 0.9)
+    vals = np.sort(np.delete(d[0:3, 0:3].ravel(), 0))
+    assert out2[0, 0] == vals[(len(vals) - 1) // 2]
+
+
+def test_median_in_the_hierarchy():
+    # with the filter, each level's map is the filtered matching result and C is
+    # the cost before filtering; a threshold below every score changes nothing
+    p = synth.make_pair(7, 48, 80, 4, 2, 20, True, 1.0, 0.0, 6.0, "u8")
+    a = oracle.disparity(p.left, p.right, 24, 2, 2, 2, 0.065)
+    b = oracle.disparity(p.left, p.right, 24, 2, 2, 2, 0.065, median_alpha=-2.0)
+    for k in range(2):
+        assert np.array_equal(a[k][0], b[k][0])
+    c = oracle.disparity(p.left, p.right, 24, 2, 2, 2, 0.065, median_alpha=0.9)
+    top = oracle.median_filter(a[1][0], a[1][1], 0.9)
+    assert np.array_equal(c[1][0], top) and np.array_equal(c[1][1], a[1][1])
+    PL, PR = oracle.pyramid(p.left, 2), oracle.pyramid(p.right, 2)
+    l0 = oracle.match_level(PL[0], PR[0], 2, 24, top, 2, 0.065)
+    assert np.array_equal(c[0][0], oracle.median_filter(l0[0], l0[1], 0.9))
+
+
 def test_odd_shift_recovered_at_level_zero():
     H, W, n, D = 48, 80, 2, 30
     L, R = _shifted_pair(H, W, 7, seed=11)
