@@ -73,6 +73,9 @@ typedef int32_t msibm_status;
                                    input blurred with the pyramid's 5x5 binomial
                                    kernel (every pixel, clamp-to-edge; the blur
                                    of the original image of Section IV)         */
+#define MSIBM_FLAG_MEDIAN 16    /* plain forward only: every level's hard map goes
+                                   through the selective median filter (Eq. 10)
+                                   with threshold median_alpha                  */
 #define MSIBM_FLAG_PERSISTENT 4 /* reserved: single-launch persistent scheduler;
                                    switched off, fails with UNSUPPORTED       */
 
@@ -104,6 +107,8 @@ typedef struct msibm_config {
                               half_window at level k, 0 keeps half_window; for
                               the block size that shrinks by 2 per level
                               (Section III), e.g. {5, 2, 1}                    */
+    float median_alpha;    /* with MSIBM_FLAG_MEDIAN: pixels with matched cost
+                              <= median_alpha are filtered (the paper: 0.9)      */
 } msibm_config;
 
 /* Thread-local description of the last error of this thread ("" if none). */
@@ -167,6 +172,22 @@ int64_t msibm_autotune_table(char* buf, size_t len);
 msibm_status msibm_pyramid(const void* img, int32_t dtype, int32_t H, int32_t W, int32_t pitch,
                            int32_t K, float* const* levels, const int32_t* level_pitch,
                            void* stream);
+
+/*
+ * msibm_median_filter - selective median filtering (Section III.D, Eq. 10): a
+ * pixel whose matched cost is at most alpha takes the median disparity of the
+ * pixels of its 5x5 patch (only those inside the image) whose cost exceeds
+ * alpha; the lower median for an even count; without such pixels it keeps its
+ * disparity.  Costs are compared with alpha in double precision.
+ *   d_in     device int16 H x W (row pitch in_pitch), the unfiltered map.
+ *   cost     device float H x W (row pitch cost_pitch), the matched costs.
+ *   d_out    device int16 H x W (row pitch out_pitch); must not overlap d_in.
+ * Errors: INVALID_ARG (null pointers, overlapping maps, non-finite alpha),
+ *         SHAPE (sizes, pitches), HIP.
+ */
+msibm_status msibm_median_filter(const int16_t* d_in, int32_t in_pitch, const float* cost, int32_t cost_pitch,
+                                 int32_t H, int32_t W, double alpha, int16_t* d_out, int32_t out_pitch,
+                                 void* stream);
 
 /* Bytes of workspace msibm_match_level needs for an H x W level. */
 size_t msibm_level_workspace_size(int32_t H, int32_t W);

@@ -88,10 +88,14 @@ msibm_status validate_config(const msibm_config* cfg)
         return fail(MSIBM_ERR_INVALID_ARG, "tau must be finite and > 0");
     if (cfg->flags & MSIBM_FLAG_PERSISTENT)
         return fail(MSIBM_ERR_UNSUPPORTED, "the persistent single-launch scheduler is switched off");
-    if (cfg->flags & ~(MSIBM_FLAG_BATCHED | MSIBM_FLAG_GRAPH | MSIBM_FLAG_PREBLUR))
+    if (cfg->flags & ~(MSIBM_FLAG_BATCHED | MSIBM_FLAG_GRAPH | MSIBM_FLAG_PREBLUR | MSIBM_FLAG_MEDIAN))
         return fail(MSIBM_ERR_INVALID_ARG, "unknown flags 0x%x", cfg->flags);
     if ((cfg->flags & MSIBM_FLAG_PREBLUR) && (cfg->flags & MSIBM_FLAG_BATCHED))
         return fail(MSIBM_ERR_UNSUPPORTED, "MSIBM_FLAG_PREBLUR runs on the plain path only");
+    if ((cfg->flags & MSIBM_FLAG_MEDIAN) && (cfg->flags & MSIBM_FLAG_BATCHED))
+        return fail(MSIBM_ERR_UNSUPPORTED, "MSIBM_FLAG_MEDIAN runs on the plain path only");
+    if ((cfg->flags & MSIBM_FLAG_MEDIAN) && !std::isfinite(cfg->median_alpha))
+        return fail(MSIBM_ERR_INVALID_ARG, "median_alpha must be finite");
     if ((cfg->flags & MSIBM_FLAG_GRAPH) && !(cfg->flags & MSIBM_FLAG_BATCHED))
         return fail(MSIBM_ERR_INVALID_ARG, "MSIBM_FLAG_GRAPH needs MSIBM_FLAG_BATCHED");
     return MSIBM_OK;
@@ -120,7 +124,7 @@ msibm_status validate_pair(const msibm_pair& p, int idx, const msibm_config* cfg
 }
 
 // Workspace layout of one pair (offsets from the pair's base).
-PairLayout pair_layout(const msibm_pair& p, int K, bool preblur)
+PairLayout pair_layout(const msibm_pair& p, int K, bool preblur, bool median)
 {
     PairLayout L{};
     L.K = K;
@@ -147,6 +151,12 @@ PairLayout pair_layout(const msibm_pair& p, int K, bool preblur)
             L.blur[v] = off;
             off = align_up(off + (size_t)p.height * p.width * sizeof(float));
         }
+    if (median) {
+        L.dtmp = off;
+        off = align_up(off + (size_t)p.height * p.width * sizeof(int16_t));
+        L.ctmp = off;
+        off = align_up(off + (size_t)p.height * p.width * sizeof(float));
+    }
     L.bytes = off;
     return L;
 }
@@ -217,6 +227,25 @@ msibm_status msibm_pyramid(const void* img, int32_t dtype, int32_t H, int32_t W,
         e = launch_reduce(MSIBM_F32, r, s);
         if (e != hipSuccess) return hip_fail(e, "pyramid reduce launch");
     }
+    return ok();
+}
+
+msibm_status msibm_median_filter(const int16_t* d_in, int32_t in_pitch, const float* cost, int32_t cost_pitch,
+                                 int32_t H, int32_t W, double alpha, int16_t* d_out, int32_t out_pitch,
+                                 void* stream)
+{
+    if (!d_in || !cost || !d_out) return fail(MSIBM_ERR_INVALID_ARG, "NULL map or cost");
+    if (H < 1 || W < 1 || in_pitch < W || cost_pitch < W || out_pitch < W)
+        return fail(MSIBM_ERR_SHAPE, "size %dx%d pitches %d %d %d", H, W, in_pitch, cost_pitch, out_pitch);
+    if (!std::isfinite(alpha)) return fail(MSIBM_ERR_INVALID_ARG, "alpha must be finite");
+    const char* a0 = (const char*)d_in;
+    const char* a1 = a0 + ((size_t)(H - 1) * in_pitch + W) * sizeof(int16_t);
+    const char* b0 = (const char*)d_out;
+    const char* b1 = b0 + ((size_t)(H - 1) * out_pitch + W) * sizeof(int16_t);
+    if (a0 < b1 && b0 < a1) return fail(MSIBM_ERR_INVALID_ARG, "d_out overlaps d_in");
+    MedianArgs m{d_in, cost, d_out, H, W, in_pitch, cost_pitch, out_pitch, alpha};
+    const hipError_t e = launch_median(m, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "median launch");
     return ok();
 }
 
@@ -300,7 +329,8 @@ size_t msibm_workspace_size(const msibm_pair* pairs, int32_t n_pairs, const msib
     for (int p = 0; p < n_pairs; ++p) {
         int K;
         if (validate_pair(pairs[p], p, cfg, &K) != MSIBM_OK) return 0;
-        tot += pair_layout(pairs[p], K, (cfg->flags & MSIBM_FLAG_PREBLUR) != 0).bytes;
+        tot += pair_layout(pairs[p], K, (cfg->flags & MSIBM_FLAG_PREBLUR) != 0,
+                           (cfg->flags & MSIBM_FLAG_MEDIAN) != 0).bytes;
     }
     tot += batch_extra_bytes(pairs, n_pairs, cfg);
     return tot;
@@ -338,7 +368,8 @@ msibm_status msibm_disparity(const msibm_pair* pairs, int32_t n_pairs, const msi
     size_t base = 0;
     for (int p = 0; p < n_pairs; ++p) {
         const msibm_pair& P = pairs[p];
-        const PairLayout lay = pair_layout(P, Ks[p], (cfg->flags & MSIBM_FLAG_PREBLUR) != 0);
+        const PairLayout lay = pair_layout(P, Ks[p], (cfg->flags & MSIBM_FLAG_PREBLUR) != 0,
+                                           (cfg->flags & MSIBM_FLAG_MEDIAN) != 0);
         char* ws = (char*)workspace + base;
         base += lay.bytes;
         std::string err;

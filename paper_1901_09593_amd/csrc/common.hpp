@@ -99,6 +99,15 @@ struct StatsArgs {
 
 // Two or three pyramid steps in one launch: source level (the caller's input or
 // a float level) to levels +1 .. +steps, both views.
+// Selective median filtering of one map (Eq. 10).
+struct MedianArgs {
+    const int16_t* d_in;
+    const float* cost;
+    int16_t* d_out;
+    int H, W, ipitch, cpitch, opitch;
+    double alpha;
+};
+
 // Full-resolution binomial blur of both views (the pre-blur variant's level 0).
 struct BlurArgs {
     const void* src[2];
@@ -192,6 +201,7 @@ hipError_t launch_convert(int dtype, const ConvertArgs& a, hipStream_t s);
 hipError_t launch_stats(StatsArgs a, hipStream_t s);
 hipError_t launch_tower(int dtype, const TowerArgs& a, hipStream_t s);
 hipError_t launch_blur(int dtype, const BlurArgs& a, hipStream_t s);
+hipError_t launch_median(const MedianArgs& a, hipStream_t s);
 hipError_t launch_match(int n, int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
 
 // Multi-segment launches (batched path); `blocks` = total tiles of the segments.

@@ -213,6 +213,64 @@ hipError_t launch_blur(int dtype, const BlurArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
+// Selective median filter (Eq. 10), one pixel per thread.  A filtered pixel
+// gathers the disparities of the good pixels of its 5x5 patch (32767 for the
+// others), sorts the 32 values with a bitonic network in registers and takes
+// the lower median of the good ones.
+__device__ __forceinline__ void cswap(int& a, int& b)
+{
+    const int lo = min(a, b), hi = max(a, b);
+    a = lo;
+    b = hi;
+}
+
+__global__ __launch_bounds__(256) void median_kernel(MedianArgs a)
+{
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63), i = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= a.H || j >= a.W) return;
+    const int d0 = a.d_in[(size_t)i * a.ipitch + j];
+    int out = d0;
+    if (!((double)a.cost[(size_t)i * a.cpitch + j] > a.alpha)) {
+        int v[32], m = 0;
+#pragma unroll
+        for (int t = 0; t < 32; ++t) v[t] = 32767;
+#pragma unroll
+        for (int q = 0; q < 25; ++q) {
+            const int y = i + q / 5 - 2, x = j + q % 5 - 2;
+            const bool in = y >= 0 && y < a.H && x >= 0 && x < a.W;
+            const int yy = min(max(y, 0), a.H - 1), xx = min(max(x, 0), a.W - 1);
+            const bool good = in && (double)a.cost[(size_t)yy * a.cpitch + xx] > a.alpha;
+            v[q] = good ? (int)a.d_in[(size_t)yy * a.ipitch + xx] : 32767;
+            m += good ? 1 : 0;
+        }
+#pragma unroll
+        for (int k = 2; k <= 32; k <<= 1)
+#pragma unroll
+            for (int jj = k >> 1; jj > 0; jj >>= 1)
+#pragma unroll
+                for (int t = 0; t < 32; ++t) {
+                    const int l = t ^ jj;
+                    if (l > t) {
+                        if ((t & k) == 0) cswap(v[t], v[l]);
+                        else cswap(v[l], v[t]);
+                    }
+                }
+        const int want = (m - 1) / 2;
+        int med = d0;
+#pragma unroll
+        for (int t = 0; t < 25; ++t) med = (t == want) ? v[t] : med;
+        if (m > 0) out = med;
+    }
+    a.d_out[(size_t)i * a.opitch + j] = (int16_t)out;
+}
+
+hipError_t launch_median(const MedianArgs& a, hipStream_t s)
+{
+    dim3 grid((a.W + 63) / 64, (a.H + 3) / 4, 1);
+    hipLaunchKernelGGL(median_kernel, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_tower(int dtype, const TowerArgs& a, hipStream_t s)
 {
     if (a.steps < 2 || a.steps > TW_MAXS) return hipErrorInvalidValue;

@@ -177,6 +177,14 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
         char lab[32];
         snprintf(lab, sizeof(lab), "match_%s_l%d",
                  mode == MODE_FULL ? "full" : (mode == MODE_SOFT ? "soft" : "refine"), k);
+        // with the selective median, a hard level's map is matched into a
+        // scratch map and filtered into its place
+        int16_t* const dest = a.d_out;
+        const bool filt = (cfg->flags & MSIBM_FLAG_MEDIAN) && mode != MODE_SOFT;
+        if (filt) {
+            a.d_out = (int16_t*)(ws + lay.dtmp);
+            if (!a.c_out) a.c_out = (float*)(ws + lay.ctmp);
+        }
         {
             TimedLaunch t(lab, s);
             const int n = level_n(cfg, k);
@@ -184,6 +192,13 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
             e = launch_match(n, dtype_of(k), mode, nc, a, s);
         }
         if (e != hipSuccess) return hip_err(e, "match launch", err);
+        if (filt) {
+            MedianArgs m{a.d_out, a.c_out, dest, lay.h[k], lay.w[k], lay.w[k], lay.w[k], lay.w[k],
+                         (double)cfg->median_alpha};
+            TimedLaunch t("median", s);
+            e = launch_median(m, s);
+            if (e != hipSuccess) return hip_err(e, "median launch", err);
+        }
     }
     return MSIBM_OK;
 }

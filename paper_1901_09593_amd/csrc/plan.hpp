@@ -31,10 +31,11 @@ struct PairLayout {
     size_t stat[MSIBM_MAX_LEVELS][2];
     size_t map[MSIBM_MAX_LEVELS];
     size_t blur[2];           // pre-blurred level 0 (float, pitch W), when asked for
+    size_t dtmp, ctmp;        // unfiltered map (int16) and cost (float) of a level, with the median
     size_t bytes;
 };
 
-PairLayout pair_layout(const msibm_pair& p, int K, bool preblur = false);
+PairLayout pair_layout(const msibm_pair& p, int K, bool preblur = false, bool median = false);
 
 struct BatchOutputs {
     int16_t* const* disp;

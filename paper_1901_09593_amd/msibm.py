@@ -25,6 +25,7 @@ FLAG_BATCHED = 1
 FLAG_GRAPH = 2
 FLAG_PERSISTENT = 4  # switched off: calls with it fail with MsibmError
 FLAG_PREBLUR = 8     # plain forward: level 0 matched on the blurred input
+FLAG_MEDIAN = 16     # plain forward: selective median filter (Eq. 10) at every hard level
 MAX_LEVELS = 8
 
 
@@ -49,7 +50,8 @@ class Config(ctypes.Structure):
     _fields_ = [("half_window", ctypes.c_int32), ("refine_radius", ctypes.c_int32),
                 ("var_eps", ctypes.c_float), ("soft_radius", ctypes.c_int32),
                 ("tau", ctypes.c_float), ("flags", ctypes.c_int32),
-                ("half_window_levels", ctypes.c_int32 * MAX_LEVELS)]
+                ("half_window_levels", ctypes.c_int32 * MAX_LEVELS),
+                ("median_alpha", ctypes.c_float)]
 
 
 _lib = None
@@ -71,6 +73,9 @@ def lib() -> ctypes.CDLL:
         L.msibm_pyramid.argtypes = [_VP, _I32, _I32, _I32, _I32, _I32, _PP,
                                     ctypes.POINTER(_I32), _VP]
         L.msibm_pyramid.restype = _I32
+        L.msibm_median_filter.argtypes = [_VP, _I32, _VP, _I32, _I32, _I32, ctypes.c_double, _VP,
+                                          _I32, _VP]
+        L.msibm_median_filter.restype = _I32
         L.msibm_level_workspace_size.argtypes = [_I32, _I32]
         L.msibm_level_workspace_size.restype = ctypes.c_size_t
         L.msibm_match_level.argtypes = [_VP, _VP, _I32, _I32, _I32, _I32, _I32, _I32, _VP, _I32,
@@ -158,16 +163,21 @@ def auto_levels(D: int) -> int:
 
 
 def make_config(n, r: int, var_eps: float, soft_radius: int = 0, tau: float = 0.05,
-                flags: int = 0) -> Config:
+                flags: int = 0, median_alpha: Optional[float] = None) -> Config:
     """n: the window half-width, or a sequence of per-level half-widths (level 0
-    first; levels past its end keep its last entry)."""
+    first; levels past its end keep its last entry).  median_alpha: switch on the
+    selective median filter with that threshold."""
+    if median_alpha is not None:
+        flags |= FLAG_MEDIAN
+    alpha = float(median_alpha) if median_alpha is not None else 0.0
     if isinstance(n, int):
-        return Config(n, r, float(var_eps), soft_radius, float(tau), flags)
+        return Config(n, r, float(var_eps), soft_radius, float(tau), flags, (ctypes.c_int32 * MAX_LEVELS)(),
+                      alpha)
     ns = [int(v) for v in n]
     if not ns or len(ns) > MAX_LEVELS:
         raise ValueError(f"1..{MAX_LEVELS} per-level half-widths")
     per = (ctypes.c_int32 * MAX_LEVELS)(*(ns + [ns[-1]] * (MAX_LEVELS - len(ns))))
-    return Config(ns[0], r, float(var_eps), soft_radius, float(tau), flags, per)
+    return Config(ns[0], r, float(var_eps), soft_radius, float(tau), flags, per, alpha)
 
 
 def force_variant(v: int = -1):
@@ -258,6 +268,19 @@ def match_level(L: torch.Tensor, R: torch.Tensor, n: int, Dk: int,
     return (d, C, V) if with_costvol else (d, C)
 
 
+def median_filter(d: torch.Tensor, cost: torch.Tensor, alpha: float) -> torch.Tensor:
+    """Selective median filter (Eq. 10) of one int16 map given its float costs."""
+    if d.dtype != torch.int16 or cost.dtype != torch.float32 or d.shape != cost.shape or d.dim() != 2:
+        raise ValueError("an int16 map and a float cost map of one shape")
+    if d.stride(1) != 1 or cost.stride(1) != 1:
+        raise ValueError("rows must be contiguous")
+    H, W = d.shape
+    out = torch.empty((H, W), dtype=torch.int16, device=d.device)
+    _check(lib().msibm_median_filter(_ptr(d), d.stride(0), _ptr(cost), cost.stride(0), H, W,
+                                     float(alpha), _ptr(out), W, _stream(d.device)))
+    return out
+
+
 def _pairs(lefts, rights, Ds, Ks) -> Tuple[ctypes.Array, list]:
     n = len(lefts)
     arr = (Pair * n)()
@@ -282,13 +305,16 @@ def workspace_bytes(pairs_arr, n: int, cfg: Config) -> int:
 
 def disparity(L: torch.Tensor, R: torch.Tensor, D: int, K: int, n: int, r: int, var_eps: float,
               soft_radius: int = 0, tau: float = 0.05, with_cost: bool = True,
-              with_prior1: bool = False, preblur: bool = False) -> Dict[str, torch.Tensor]:
+              with_prior1: bool = False, preblur: bool = False,
+              median_alpha: Optional[float] = None) -> Dict[str, torch.Tensor]:
     """Hierarchical forward pass of one pair.  Returns a dict with 'disp'
     (int16), 'cost' (float, optional), 'soft' (float, if soft_radius > 0) and
     'prior1' (int16 level-1 map, if requested or soft).  preblur: match level 0
-    on the input blurred with the pyramid's kernel."""
+    on the input blurred with the pyramid's kernel.  median_alpha: run the
+    selective median filter with that threshold after every hard level."""
     out = disparity_many([L], [R], [D], [K], n, r, var_eps, soft_radius, tau, with_cost,
-                         with_prior1, flags=FLAG_PREBLUR if preblur else 0)
+                         with_prior1, flags=FLAG_PREBLUR if preblur else 0,
+                         median_alpha=median_alpha)
     return out[0]
 
 
@@ -296,13 +322,14 @@ def disparity_many(lefts: Sequence[torch.Tensor], rights: Sequence[torch.Tensor]
                    Ks: Sequence[int], n: int, r: int, var_eps: float, soft_radius: int = 0,
                    tau: float = 0.05, with_cost: bool = True, with_prior1: bool = False,
                    flags: int = 0, workspace: Optional[torch.Tensor] = None,
-                   outputs: Optional[List[Dict[str, torch.Tensor]]] = None) -> List[Dict[str, torch.Tensor]]:
+                   outputs: Optional[List[Dict[str, torch.Tensor]]] = None,
+                   median_alpha: Optional[float] = None) -> List[Dict[str, torch.Tensor]]:
     """Forward pass of several pairs in one call (flags: FLAG_BATCHED, FLAG_GRAPH,
-    or FLAG_PREBLUR on the plain path).
+    or FLAG_PREBLUR / a median_alpha on the plain path).
     `workspace` and `outputs` may be passed in to reuse buffers across calls."""
     pairs, keep = _pairs(lefts, rights, Ds, Ks)
     npair = len(lefts)
-    cfg = make_config(n, r, var_eps, soft_radius, tau, flags)
+    cfg = make_config(n, r, var_eps, soft_radius, tau, flags, median_alpha)
     ws_bytes = workspace_bytes(pairs, npair, cfg)
     dev = lefts[0].device
     if workspace is None or workspace.numel() < ws_bytes:

@@ -69,6 +69,7 @@ def test_config_and_pair_validation(lib):
     from paper_1901_09593_amd import msibm
     e = msibm.lib()
     P = msibm.Pair(0x1000, 0x2000, 0, 64, 80, 80, 32, 0)
+    fake = ctypes.c_void_p(0x1000)
     arr = (msibm.Pair * 1)(P)
     good = msibm.make_config(3, 2, 0.065)
     assert e.msibm_workspace_size(arr, 1, ctypes.byref(good)) > 0
@@ -91,6 +92,24 @@ def test_config_and_pair_validation(lib):
     pre_b = msibm.make_config(3, 2, 0.065, flags=msibm.FLAG_PREBLUR | msibm.FLAG_BATCHED)
     rc = e.msibm_disparity(arr, 1, ctypes.byref(pre_b), disp_probe, None, None, None, None, 0, None)
     assert rc == -4 and b"PREBLUR" in e.msibm_last_error()
+    # the selective median runs on the plain forward only, with a finite threshold,
+    # and keeps an unfiltered map and cost of level 0 in the workspace
+    med = msibm.make_config(3, 2, 0.065, median_alpha=0.9)
+    assert med.flags & msibm.FLAG_MEDIAN
+    assert e.msibm_workspace_size(arr, 1, ctypes.byref(med)) >= \
+        e.msibm_workspace_size(arr, 1, ctypes.byref(good)) + 64 * 80 * 6
+    for bad in (msibm.make_config(3, 2, 0.065, flags=msibm.FLAG_BATCHED, median_alpha=0.9),
+                msibm.make_config(3, 2, 0.065, median_alpha=float("inf"))):
+        assert e.msibm_workspace_size(arr, 1, ctypes.byref(bad)) == 0
+        rc = e.msibm_disparity(arr, 1, ctypes.byref(bad), disp_probe, None, None, None, None, 0, None)
+        assert rc in (-1, -4) and b"median" in e.msibm_last_error().lower()
+    # median filter: null pointers, sizes, pitches and overlap rejected before any launch
+    assert e.msibm_median_filter(None, 8, fake, 8, 8, 8, 0.5, fake, 8, None) == -1
+    assert e.msibm_median_filter(fake, 8, fake, 8, 0, 8, 0.5, ctypes.c_void_p(0x9000000), 8, None) == -2
+    assert e.msibm_median_filter(fake, 7, fake, 8, 8, 8, 0.5, ctypes.c_void_p(0x9000000), 8, None) == -2
+    assert e.msibm_median_filter(fake, 8, fake, 8, 8, 8, 0.5, fake, 8, None) == -1
+    assert e.msibm_median_filter(fake, 8, fake, 8, 8, 8, float("nan"), ctypes.c_void_p(0x9000000), 8,
+                                 None) == -1
     # the soft level needs float images
     soft = msibm.make_config(3, 2, 0.065, 3, 0.05)
     assert e.msibm_workspace_size(arr, 1, ctypes.byref(soft)) == 0

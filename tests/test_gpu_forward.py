@@ -260,6 +260,93 @@ def test_preblur_level_zero(M, dtype):
     assert st["mismatch"] <= 0.01
 
 
+@pytest.mark.parametrize("H,W,alpha", [(61, 90, 0.9), (37, 150, 0.97), (1, 1, 0.9), (5, 300, 0.5),
+                                         (70, 65, -5.0), (70, 65, 5.0)])
+def test_median_filter_matches_oracle_bit_exact(M, H, W, alpha):
+    """The selective median filter (Eq. 10) on the GPU's own level map and
+    costs equals the oracle's filter on the same values, pixel for pixel
+    (alpha below every cost filters nothing; above every cost there are no
+    good pixels, so every pixel keeps its disparity)."""
+    p = _tex_pair(90 + H, max(H, 8), max(W, 8), 12)
+    Lg, Rg = dev(p.left[:H, :W]), dev(p.right[:H, :W])
+    d, C = M.match_level(Lg, Rg, 2, 40, None, 0, 0.065)
+    got = host(M.median_filter(d, C, alpha))
+    ref = oracle.median_filter(host(d), host(C).astype(np.float64), alpha)
+    assert np.array_equal(got, ref)
+    changed = float((got != host(d)).mean())
+    print(f"{H}x{W} alpha={alpha}: {changed:.3f} of the pixels changed")
+    if alpha < -1 or alpha > 1:
+        assert changed == 0
+
+
+def test_median_filter_any_int16_and_pitched_rows(M):
+    """Arbitrary int16 values (negative, the int16 extremes, ties) and costs
+    around the threshold, read from row-pitched views."""
+    rng = np.random.Generator(np.random.PCG64(5))
+    H, W = 83, 131
+    d = rng.integers(-32768, 32768, (H, W + 7)).astype(np.int16)
+    d[::3, ::2] = 32767
+    d[1::4, 1::3] = -32768
+    d[10:20, 10:30] = 4
+    C = rng.choice(np.array([-1.0, 0.3, 0.5, np.float32(0.5) + 1e-7, 0.9, 1.0], np.float32),
+                   (H, W + 5)).astype(np.float32)
+    dg = dev(d)[:, :W]
+    Cg = dev(C)[:, :W]
+    got = host(M.median_filter(dg, Cg, 0.5))
+    ref = oracle.median_filter(d[:, :W], C[:, :W].astype(np.float64), 0.5)
+    assert np.array_equal(got, ref)
+    assert (got != d[:, :W]).mean() > 0.2
+
+
+def test_median_filter_rejects_bad_calls(M):
+    d = torch.zeros((8, 8), dtype=torch.int16, device="cuda")
+    C = torch.zeros((8, 8), dtype=torch.float32, device="cuda")
+    e = M.lib()
+    assert e.msibm_median_filter(d.data_ptr(), 8, C.data_ptr(), 8, 8, 8, 0.5, d.data_ptr(), 8, None) == -1
+    assert b"overlaps" in e.msibm_last_error()
+    out = torch.empty_like(d)
+    assert e.msibm_median_filter(d.data_ptr(), 8, C.data_ptr(), 8, 8, 8, float("nan"), out.data_ptr(), 8,
+                                 None) == -1
+    assert e.msibm_median_filter(d.data_ptr(), 7, C.data_ptr(), 8, 8, 8, 0.5, out.data_ptr(), 8, None) == -2
+    assert e.msibm_median_filter(None, 8, C.data_ptr(), 8, 8, 8, 0.5, out.data_ptr(), 8, None) == -1
+
+
+@pytest.mark.parametrize("dtype,K,alpha", [("u8", 3, 0.9), ("u8", 4, 0.95), ("f32", 3, 0.9)])
+def test_median_in_the_hierarchy(M, dtype, K, alpha):
+    """With the selective median after every level, the forward equals the
+    level-by-level chain of match_level and median_filter (the filtered map is
+    the prior of the next level, the cost stays the matched one), and follows
+    the oracle's filtered hierarchy up to near-ties."""
+    p = _tex_pair(110 + K, 130, 230, 14, dtype, noise=6.0)
+    D, n, r = 80, 3, 2
+    eps = 0.065 if dtype == "u8" else 1e-6
+    Lg, Rg = dev(p.left), dev(p.right)
+    out = M.disparity(Lg, Rg, D, K, n, r, eps, with_prior1=True, median_alpha=alpha)
+    PL, PR = M.pyramid(Lg, K), M.pyramid(Rg, K)
+    maps, costs, raw = [None] * K, [None] * K, [None] * K
+    for k in range(K - 1, -1, -1):
+        Lk = Lg if k == 0 else PL[k]
+        Rk = Rg if k == 0 else PR[k]
+        prior = None if k == K - 1 else maps[k + 1]
+        raw[k], costs[k] = M.match_level(Lk, Rk, n, -(-D // (1 << k)), prior, r, eps)
+        maps[k] = M.median_filter(raw[k], costs[k], alpha)
+    assert torch.equal(maps[0], out["disp"]) and torch.equal(costs[0], out["cost"])
+    assert torch.equal(maps[1], out["prior1"])
+    changed = [float((maps[k] != raw[k]).float().mean()) for k in range(K)]
+    print("fraction changed by the filter per level", changed)
+    assert max(changed) > 0
+    # no cost output: the filter reads the scratch cost map
+    nocost = M.disparity(Lg, Rg, D, K, n, r, eps, with_cost=False, median_alpha=alpha)
+    assert torch.equal(nocost["disp"], out["disp"])
+    ref = oracle.disparity(p.left, p.right, D, K, n, r, eps, median_alpha=alpha)
+    mism = float((host(out["disp"]) != ref[0][0]).mean())
+    print("end-to-end level-0 mismatch rate with the median", mism)
+    assert mism < 0.01
+    # the batched path does not take the filter
+    with pytest.raises(M.MsibmError):
+        M.disparity_many([Lg], [Rg], [D], [K], n, r, eps, flags=M.FLAG_BATCHED, median_alpha=alpha)
+
+
 def test_mid1436_full_size_sampled(M):
     """The benchmark workload at full size, in the launch configuration the
     benchmark times; level 0 checked on sampled pixels against the oracle fed
