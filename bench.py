@@ -41,6 +41,7 @@ CU, SIMD_PER_CU, LANES, CLOCK_HZ = 256, 4, 16, 2.4e9
 PEAK_FP32_UNPACKED = CU * SIMD_PER_CU * LANES * 2 * CLOCK_HZ / 1e12   # 78.6 TFLOP/s (FMA = 2)
 PEAK_FP32_PUBLISHED = 157.3                                           # packed dual-issue figure
 PEAK_HBM = 8000.0                                                     # GB/s
+MEDIAN_ALPHA = 0.9  # the threshold of the selective median filter that Section IV reports
 
 METRIC = "pixel-disparity ZNCC evals/s + ms/pair, batched vs plain; fwd+bwd ms"
 DOMINANT = "match_refine_l0"
@@ -194,10 +195,13 @@ def section_batched(torch, M, synth, steps):
 
 def section_accuracy(torch, M, synth, steps):
     """Disparity error against the generator's ground truth (the synthetic
-    stand-in for the paper's accuracy table): the configured hierarchy, the
-    paper's own parameters (refine +-1, block size halving per level from 11x11,
-    level 0 pre-blurred) and flat block matching, on non-occluded pixels away
-    from the borders."""
+    stand-in for the paper's accuracy table): the configured hierarchy, with
+    and without the selective median filter, the paper's own parameters (refine
+    +-1, block size halving per level from 11x11, level 0 pre-blurred, the
+    median filter at alpha 0.9) and flat block matching, on non-occluded pixels
+    away from the borders.  Also the median kernel's own time at level 0 and its
+    bandwidth (8 algorithmic bytes per pixel: the map and cost read, the map
+    written)."""
     dev = torch.device("cuda:0")
     res = {}
     for name in ("small320", "mid1436"):
@@ -211,21 +215,34 @@ def section_accuracy(torch, M, synth, steps):
         vis[:b, :] = vis[H - b:, :] = False
         vis[:, :b] = vis[:, W - b:] = False
         runs = {
-            "hierarchy": dict(n=n, r=r, preblur=False, K=K),
-            "paper_parameters": dict(n=halving, r=1, preblur=True, K=K),
-            "flat_block_matching": dict(n=n, r=0, preblur=False, K=1),
+            "hierarchy": dict(n=n, r=r, preblur=False, K=K, alpha=None),
+            "hierarchy_median": dict(n=n, r=r, preblur=False, K=K, alpha=MEDIAN_ALPHA),
+            "paper_parameters": dict(n=halving, r=1, preblur=True, K=K, alpha=MEDIAN_ALPHA),
+            "flat_block_matching": dict(n=n, r=0, preblur=False, K=1, alpha=None),
         }
         out = {"workload": f"{W}x{H} uint8 pair ({name}), D={D}", "pixels_scored": int(vis.sum()),
                "paper_parameters": f"refine +-1, windows {[2 * v + 1 for v in halving]} by level, level 0 "
-                                   "pre-blurred"}
+                                   f"pre-blurred, selective median at alpha {MEDIAN_ALPHA}"}
         for label, c in runs.items():
             def fwd():
-                return M.disparity(Lg, Rg, D, c["K"], c["n"], c["r"], eps, preblur=c["preblur"])
+                return M.disparity(Lg, Rg, D, c["K"], c["n"], c["r"], eps, preblur=c["preblur"],
+                                   median_alpha=c["alpha"])
             d = fwd()["disp"].cpu().numpy().astype(np.float64)
             err = np.abs(d - p.disp)[vis]
             ms = time_ms(torch, fwd, steps, 2)
             out[label] = {"mean_abs_err_px": float(err.mean()), "bad_1px": float((err > 1).mean()),
                           "bad_2px": float((err > 2).mean()), "ms_per_pair": ms}
+            if label == "hierarchy_median":
+                M.timing_enable(True)
+                for _ in range(steps):
+                    fwd()
+                torch.cuda.synchronize()
+                tim = M.timing_read()
+                M.timing_enable(False)
+                tot, cnt = tim["median_l0"]
+                us = 1e3 * tot / cnt
+                out["median_l0_kernel"] = {"avg_us": us, "GB_per_s": 8.0 * H * W / (us * 1e-6) / 1e9,
+                                           "frac_of_hbm_peak": 8.0 * H * W / (us * 1e-6) / 1e9 / PEAK_HBM}
         res[name] = out
     return res
 

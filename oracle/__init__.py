@@ -13,6 +13,11 @@ functions into the method's steps in the paper's order (Section III):
   3. for each finer level, a search restricted to +-r around the doubled,
      nearest-neighbour-upsampled coarser map (Eqs. 8-9, first branch).
 
+Optional steps of the paper: the confidence gating (the full search where the
+bicubic-upsampled coarser cost is low, Eqs. 8-9 second branch; the re-pick of
+low-cost pixels by the neighbourhood-averaged DSI, Eqs. 5-7), the selective
+median filter (Eq. 10) and matching on a blurred level 0.
+
 Plus the differentiable finest level (soft-argmax) and its gradient, which the
 paper does not have.
 """
@@ -32,6 +37,7 @@ _lib = None
 
 _D = ctypes.POINTER(ctypes.c_double)
 _I16 = ctypes.POINTER(ctypes.c_int16)
+_U8 = ctypes.POINTER(ctypes.c_uint8)
 
 
 def build(force: bool = True) -> str:
@@ -57,6 +63,14 @@ def _load():
         lib.orc_blur.restype = None
         lib.orc_median.argtypes = [_I16, _D, c_int, c_int, c_double, _I16]
         lib.orc_median.restype = None
+        lib.orc_bicubic_up.argtypes = [_D, c_int, c_int, c_int, c_int, c_double, _D]
+        lib.orc_bicubic_up.restype = None
+        lib.orc_match_gated.argtypes = [_D, _D, c_int, c_int, c_int, c_int, _I16, _D, c_int, c_int,
+                                        c_int, c_double, c_double, _I16, _D, _D, _U8]
+        lib.orc_match_gated.restype = None
+        lib.orc_aggregate.argtypes = [_D, _D, c_int, c_int, c_int, c_int, _I16, _D, c_double,
+                                      c_double, _I16, _D, _D]
+        lib.orc_aggregate.restype = None
         lib.orc_zncc.argtypes = [_D, _D, c_int, c_int, c_int, c_int, c_int, c_int, c_double]
         lib.orc_zncc.restype = c_double
         lib.orc_match_level.argtypes = [_D, _D, c_int, c_int, c_int, c_int, _I16, c_int, c_int,
@@ -210,9 +224,57 @@ def median_filter(d: np.ndarray, C: np.ndarray, alpha: float) -> np.ndarray:
     return out
 
 
+def bicubic_up(Cc: np.ndarray, H: int, W: int, a: float = -0.5) -> np.ndarray:
+    """A coarse cost map doubled to H x W by bicubic interpolation (Section III.C)."""
+    CC = _f64(Cc)
+    Hc, Wc = CC.shape
+    assert Hc <= H <= 2 * Hc and Wc <= W <= 2 * Wc
+    out = np.empty((H, W), dtype=np.float64)
+    _load().orc_bicubic_up(_p(CC, _D), Hc, Wc, H, W, float(a), _p(out, _D))
+    return out
+
+
+def match_gated(L: np.ndarray, R: np.ndarray, n: int, Dk: int, coarse: np.ndarray,
+                coarse_cost: np.ndarray, r: int, beta: float, eps: float):
+    """Eqs. 8-9: restricted search where the upsampled coarse cost exceeds beta,
+    full search elsewhere.  Returns (d', C', C2', full mask)."""
+    L = _f64(L)
+    R = _f64(R)
+    H, W = L.shape
+    cz = np.ascontiguousarray(coarse, dtype=np.int16)
+    cc = _f64(coarse_cost)
+    Hc, Wc = cz.shape
+    assert Hc == (H + 1) // 2 and Wc == (W + 1) // 2 and cc.shape == cz.shape, "prior shape"
+    d = np.empty((H, W), dtype=np.int16)
+    C = np.empty((H, W), dtype=np.float64)
+    C2 = np.empty((H, W), dtype=np.float64)
+    full = np.empty((H, W), dtype=np.uint8)
+    _load().orc_match_gated(_p(L, _D), _p(R, _D), H, W, n, Dk, _p(cz, _I16), _p(cc, _D), Hc, Wc, r,
+                            float(beta), eps, _p(d, _I16), _p(C, _D), _p(C2, _D), _p(full, _U8))
+    return d, C, C2, full.astype(bool)
+
+
+def aggregate(L: np.ndarray, R: np.ndarray, n: int, Dk: int, d1: np.ndarray, C1: np.ndarray,
+              alpha: float, eps: float):
+    """Eqs. 5-7: pixels with C' <= alpha re-picked by the 5x5-averaged DSI.
+    Returns (d, C, C2), C2 the runner-up averaged score of a re-picked pixel."""
+    L = _f64(L)
+    R = _f64(R)
+    H, W = L.shape
+    dd = np.ascontiguousarray(d1, dtype=np.int16)
+    CC = _f64(C1)
+    assert dd.shape == (H, W) and CC.shape == (H, W)
+    d = np.empty((H, W), dtype=np.int16)
+    C = np.empty((H, W), dtype=np.float64)
+    C2 = np.empty((H, W), dtype=np.float64)
+    _load().orc_aggregate(_p(L, _D), _p(R, _D), H, W, n, Dk, _p(dd, _I16), _p(CC, _D), float(alpha),
+                          eps, _p(d, _I16), _p(C, _D), _p(C2, _D))
+    return d, C, C2
+
+
 def disparity(left: np.ndarray, right: np.ndarray, D: int, K: int, n, r: int,
               eps: float, priors: Optional[List[Optional[np.ndarray]]] = None, preblur: bool = False,
-              median_alpha: Optional[float] = None):
+              median_alpha: Optional[float] = None, gate: Optional[tuple] = None):
     """The hierarchical forward pass (Section III, hot path).
 
     n is the window half-width of every level, or a sequence of per-level
@@ -223,7 +285,12 @@ def disparity(left: np.ndarray, right: np.ndarray, D: int, K: int, n, r: int,
     level k).  With `preblur`, level 0 is matched on the blurred input (the
     pyramid is still built from the input itself).  With `median_alpha`, every
     level's map goes through the selective median filter (Eq. 10) before it is
-    returned and propagated; C is the matched cost before the filter."""
+    returned and propagated; C is the matched cost before the filter.  With
+    `gate` = (alpha, beta), the paper's confidence gating: every level below the
+    coarsest takes the full search where the bicubic-upsampled coarser cost is at
+    most beta (Eqs. 8-9), and every level re-picks its pixels with cost at most
+    alpha by the neighbourhood-averaged DSI (Eqs. 5-7); the cost propagated and
+    returned is that of Eq. 7."""
     def nk(k):
         return n if isinstance(n, (int, np.integer)) else n[min(k, len(n) - 1)]
     PL = pyramid(left, K)
@@ -235,14 +302,23 @@ def disparity(left: np.ndarray, right: np.ndarray, D: int, K: int, n, r: int,
         if median_alpha is None:
             return res
         return (median_filter(res[0], res[1], median_alpha),) + tuple(res[1:])
+    def refined(k, res):
+        if gate is None:
+            return res
+        return aggregate(PL[k], PR[k], nk(k), level_range(D, k), res[0], res[1], gate[0], eps)
     out: List = [None] * K
     kc = K - 1
-    out[kc] = filtered(match_level(PL[kc], PR[kc], nk(kc), level_range(D, kc), None, r, eps))
+    out[kc] = filtered(refined(kc, match_level(PL[kc], PR[kc], nk(kc), level_range(D, kc), None, r, eps)))
     for k in range(K - 2, -1, -1):
         prior = out[k + 1][0]
         if priors is not None and priors[k] is not None:
             prior = priors[k]
-        out[k] = filtered(match_level(PL[k], PR[k], nk(k), level_range(D, k), prior, r, eps))
+        if gate is None:
+            res = match_level(PL[k], PR[k], nk(k), level_range(D, k), prior, r, eps)
+        else:
+            res = match_gated(PL[k], PR[k], nk(k), level_range(D, k), prior, out[k + 1][1], r, gate[1],
+                              eps)[:3]
+        out[k] = filtered(refined(k, res))
     return out
 
 

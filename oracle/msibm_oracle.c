@@ -353,3 +353,129 @@ void orc_median(const int16_t* d_in, const double* C, int H, int W, double alpha
         }
     }
 }
+
+/* Keys' cubic convolution kernel with parameter a; a = -1/2 is the classical
+ * bicubic interpolant, which reproduces polynomials up to degree two. */
+static double keys_cubic(double x, double a)
+{
+    x = fabs(x);
+    if (x <= 1.0) return (a + 2.0) * x * x * x - (a + 3.0) * x * x + 1.0;
+    if (x < 2.0) return a * x * x * x - 5.0 * a * x * x + 8.0 * a * x - 4.0 * a;
+    return 0.0;
+}
+
+/* Bicubic doubling of a coarse cost map (Section III.C: the cost map is carried
+ * to the next finer level by bicubic interpolation).  Readings: the scale is
+ * exactly 2 with pixel centres aligned, so fine pixel (i, j) sits at the coarse
+ * position u = (i + 1/2)/2 - 1/2, v = (j + 1/2)/2 - 1/2; the kernel is Keys'
+ * cubic with parameter a (a = -1/2 for the method); taps clamp to the nearest
+ * edge sample.  Written as the full 16-tap sum.  Output H x W, the finer level
+ * (H <= 2 Hc, W <= 2 Wc). */
+void orc_bicubic_up(const double* Cc, int Hc, int Wc, int H, int W, double a, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < H; ++i) {
+        const double u = (i + 0.5) / 2.0 - 0.5;
+        const int i0 = (int)floor(u);
+        for (int j = 0; j < W; ++j) {
+            const double v = (j + 0.5) / 2.0 - 0.5;
+            const int j0 = (int)floor(v);
+            double s = 0.0;
+            for (int m = i0 - 1; m <= i0 + 2; ++m)
+                for (int q = j0 - 1; q <= j0 + 2; ++q)
+                    s += keys_cubic(u - m, a) * keys_cubic(v - q, a) *
+                         Cc[(size_t)clampi(m, 0, Hc - 1) * Wc + clampi(q, 0, Wc - 1)];
+            out[(size_t)i * W + j] = s;
+        }
+    }
+}
+
+/* Confidence-gated matching of a finer level (Eqs. 8-9).  With the coarser map
+ * d^{k+1} and its cost C^{k+1}: where the upsampled cost C^ = bicubic(C^{k+1})
+ * exceeds beta, the search is restricted to the radius-r interval around the
+ * doubled nearest-neighbour prior (first branch, the same interval as
+ * orc_match_level); elsewhere it covers the full interval [0, min(D_k - 1, j)]
+ * (second branch).  Outputs d', C', C2 as orc_match_level, plus full[p] = 1
+ * where the second branch was taken. */
+void orc_match_gated(const double* L, const double* R, int H, int W, int n, int Dk,
+                     const int16_t* coarse, const double* coarse_cost, int Hc, int Wc, int r,
+                     double beta, double eps, int16_t* d, double* C, double* C2, uint8_t* full)
+{
+    double* up = (double*)malloc(sizeof(double) * (size_t)H * W);
+    orc_bicubic_up(coarse_cost, Hc, Wc, H, W, -0.5, up);
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int i = 0; i < H; ++i) {
+        for (int j = 0; j < W; ++j) {
+            const size_t o = (size_t)i * W + j;
+            const int restricted = up[o] > beta;
+            int lo, hi;
+            cand_range(i, j, Dk, restricted ? coarse : NULL, Wc, r, &lo, &hi);
+            double best = -INFINITY, second = -INFINITY;
+            int bz = lo;
+            for (int z = lo; z <= hi; ++z) {
+                const double rho = orc_zncc(L, R, H, W, n, i, j, z, eps);
+                if (rho > best) {
+                    second = best;
+                    best = rho;
+                    bz = z;
+                } else if (rho > second) {
+                    second = rho;
+                }
+            }
+            d[o] = (int16_t)bz;
+            C[o] = best;
+            C2[o] = second;
+            full[o] = (uint8_t)!restricted;
+        }
+    }
+    free(up);
+}
+
+/* Disparity refinement by the neighbourhood-averaged disparity search image
+ * (Eqs. 5-7).  A pixel whose matched cost C' is at most alpha takes the z that
+ * maximises E^(z), the mean over its 5x5 neighbourhood of the neighbours'
+ * scores at z, and C = max E^; other pixels keep d' and C'.  Readings: the
+ * neighbourhood is the 5x5 box of the median step, clipped to the image; z runs
+ * over the pixel's own full interval [0, min(D_k - 1, j)]; a neighbour (m, q)
+ * contributes at z only where z is one of its own candidates (z <= q), and the
+ * mean divides by the number of contributors; ties go to the lowest z.  C2 is
+ * the second-largest E^ of a re-picked pixel (-inf otherwise). */
+void orc_aggregate(const double* L, const double* R, int H, int W, int n, int Dk,
+                   const int16_t* d_in, const double* C_in, double alpha, double eps,
+                   int16_t* d, double* C, double* C2)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < H; ++i) {
+        for (int j = 0; j < W; ++j) {
+            const size_t o = (size_t)i * W + j;
+            d[o] = d_in[o];
+            C[o] = C_in[o];
+            C2[o] = -INFINITY;
+            if (C_in[o] > alpha) continue;
+            const int top = Dk - 1 < j ? Dk - 1 : j;
+            double best = -INFINITY, second = -INFINITY;
+            int bz = 0;
+            for (int z = 0; z <= top; ++z) {
+                double s = 0.0;
+                int cnt = 0;
+                for (int m = i - 2; m <= i + 2; ++m)
+                    for (int q = j - 2; q <= j + 2; ++q) {
+                        if (m < 0 || m >= H || q < 0 || q >= W || z > q) continue;
+                        s += orc_zncc(L, R, H, W, n, m, q, z, eps);
+                        ++cnt;
+                    }
+                const double e = s / cnt;
+                if (e > best) {
+                    second = best;
+                    best = e;
+                    bz = z;
+                } else if (e > second) {
+                    second = e;
+                }
+            }
+            d[o] = (int16_t)bz;
+            C[o] = best;
+            C2[o] = second;
+        }
+    }
+}

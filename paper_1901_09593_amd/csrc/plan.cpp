@@ -195,7 +195,9 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
         if (filt) {
             MedianArgs m{a.d_out, a.c_out, dest, lay.h[k], lay.w[k], lay.w[k], lay.w[k], lay.w[k],
                          (double)cfg->median_alpha};
-            TimedLaunch t("median", s);
+            char mlab[32];
+            snprintf(mlab, sizeof(mlab), "median_l%d", k);
+            TimedLaunch t(mlab, s);
             e = launch_median(m, s);
             if (e != hipSuccess) return hip_err(e, "median launch", err);
         }

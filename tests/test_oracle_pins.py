@@ -428,3 +428,150 @@ def test_l1_loss_gradient():
         e[idx] = h
         fd = (oracle.l1_loss(ds + e, gt, m)[0] - oracle.l1_loss(ds - e, gt, m)[0]) / (2 * h)
         assert abs(fd - g[idx]) < 1e-6
+
+
+# ------------------------------------------- confidence gating (Eqs. 5-9)
+
+@pytest.mark.parametrize("Hc,Wc,H,W", [(5, 7, 10, 14), (6, 9, 11, 17), (1, 3, 2, 5), (4, 4, 7, 8)])
+def test_bicubic_up_equals_torch_bicubic_with_its_parameter(Hc, Wc, H, W):
+    # torch's bicubic (Keys' kernel with a = -0.75, clamped taps, half-pixel
+    # centres) at scale factor 2: the oracle with the same parameter agrees
+    torch = pytest.importorskip("torch")
+    Cc = _rng(31).random((Hc, Wc)) * 2 - 1
+    ref = torch.nn.functional.interpolate(torch.from_numpy(Cc)[None, None], scale_factor=2, mode="bicubic",
+                                          align_corners=False)[0, 0].numpy()[:H, :W]
+    np.testing.assert_allclose(oracle.bicubic_up(Cc, H, W, a=-0.75), ref, atol=1e-12)
+
+
+def test_bicubic_up_reproduces_quadratics_and_constants():
+    # Keys' kernel with a = -1/2 reproduces polynomials up to degree two wherever
+    # no tap is clamped; weights sum to one, so constants survive everywhere
+    Hc, Wc = 9, 12
+    yy, xx = np.mgrid[0:Hc, 0:Wc].astype(np.float64)
+
+    def q(y, x):
+        return 0.3 + 0.7 * y - 0.2 * x + 0.05 * y * y - 0.03 * x * y + 0.02 * x * x
+    up = oracle.bicubic_up(q(yy, xx), 2 * Hc, 2 * Wc)
+    fy, fx = np.mgrid[0:2 * Hc, 0:2 * Wc].astype(np.float64)
+    exact = q((fy + 0.5) / 2 - 0.5, (fx + 0.5) / 2 - 0.5)
+    inner = (slice(4, 2 * Hc - 4), slice(4, 2 * Wc - 4))
+    np.testing.assert_allclose(up[inner], exact[inner], atol=1e-12)
+    assert np.abs(up - exact).max() > 1e-3  # the clamped border is not exact
+    np.testing.assert_allclose(oracle.bicubic_up(np.full((3, 5), 0.625), 5, 10), 0.625, atol=1e-15)
+    # a single coarse impulse spreads over eight fine rows with Keys' weights at
+    # distances 7/4, 5/4, 3/4, 1/4, ... : (-3, -9, 29, 111, 111, 29, -9, -3)/128
+    imp = np.zeros((7, 7))
+    imp[3, 3] = 1.0
+    up = oracle.bicubic_up(imp, 14, 14)
+    w = np.array([-3, -9, 29, 111, 111, 29, -9, -3]) / 128.0
+    np.testing.assert_allclose(up[3:11, 7], w * (111 / 128.0), atol=1e-15)
+    np.testing.assert_allclose(up[7, 3:11], w * (111 / 128.0), atol=1e-15)
+    assert np.all(up[:3, :] == 0) and np.all(up[11:, :] == 0)
+
+
+def _brute_gated(L, R, n, Dk, coarse, ccost, r, beta, eps):
+    up = oracle.bicubic_up(ccost, *L.shape)
+    dr, Cr = _brute_level(L, R, n, Dk, coarse, r, eps)
+    df, Cf = _brute_level(L, R, n, Dk, None, 0, eps)
+    full = ~(up > beta)
+    return np.where(full, df, dr), np.where(full, Cf, Cr), full
+
+
+@pytest.mark.parametrize("beta", [-2.0, 0.1, 2.0])
+def test_gated_search_branches(beta):
+    rng = _rng(32)
+    H, W, D, n, r = 11, 14, 8, 1, 1
+    L = rng.random((H, W))
+    R = rng.random((H, W))
+    coarse = rng.integers(0, (D + 1) // 2, size=((H + 1) // 2, (W + 1) // 2)).astype(np.int16)
+    ccost = rng.random(coarse.shape) * 0.6 - 0.2
+    d, C, C2, full = oracle.match_gated(L, R, n, D, coarse, ccost, r, beta, 1e-9)
+    bd, bC, bfull = _brute_gated(L, R, n, D, coarse, ccost, r, beta, 1e-9)
+    assert np.array_equal(full, bfull) and np.array_equal(d, bd)
+    np.testing.assert_allclose(C, bC, atol=1e-12)
+    if beta < -1:
+        assert not full.any()
+    if beta > 1:
+        assert full.all()
+    if beta == 0.1:
+        assert 0 < full.mean() < 1
+
+
+def _brute_aggregate(L, R, n, Dk, d1, C1, alpha, eps):
+    """Eqs. 5-7 with numpy Pearson scores: mean over the in-image 5x5 neighbours
+    for which z is a candidate, lowest z on ties."""
+    H, W = L.shape
+
+    def E(i, j, z):
+        lw, rw = _window(L, i, j, n), _window(R, i, j - z, n)
+        return 0.0 if (lw.var() <= eps or rw.var() <= eps) else _pearson(lw, rw)
+    d, C = d1.copy(), C1.copy()
+    for i in range(H):
+        for j in range(W):
+            if C1[i, j] > alpha:
+                continue
+            best, bz = -np.inf, 0
+            for z in range(min(Dk - 1, j) + 1):
+                vals = [E(m, q, z) for m in range(i - 2, i + 3) for q in range(j - 2, j + 3)
+                        if 0 <= m < H and 0 <= q < W and z <= q]
+                e = float(np.mean(vals))
+                if e > best:
+                    best, bz = e, z
+            d[i, j], C[i, j] = bz, best
+    return d, C
+
+
+@pytest.mark.parametrize("alpha", [-2.0, 0.3, 2.0])
+def test_aggregate_brute_force(alpha):
+    rng = _rng(33)
+    H, W, D, n = 9, 13, 6, 1
+    L = rng.integers(0, 256, (H, W)).astype(np.float64)
+    R = rng.integers(0, 256, (H, W)).astype(np.float64)
+    L[:3, :4] = 7.0  # flat windows score 0
+    d1, C1, _ = oracle.match_level(L, R, n, D, None, 0, 0.065)
+    d, C, C2 = oracle.aggregate(L, R, n, D, d1, C1, alpha, 0.065)
+    bd, bC = _brute_aggregate(L, R, n, D, d1, C1, alpha, 0.065)
+    assert np.array_equal(d, bd)
+    np.testing.assert_allclose(C, bC, atol=1e-12)
+    picked = ~(C1 > alpha)
+    assert np.all(np.isneginf(C2[~picked])) and np.all(C[picked] >= C2[picked])
+    if alpha < -1:
+        assert np.array_equal(d, d1) and np.array_equal(C, C1)
+    if alpha > 1:
+        assert picked.all()
+
+
+def test_aggregate_recovers_a_constant_shift_with_perfect_score():
+    # a pure shift: away from the borders every neighbour scores 1 at the true
+    # disparity, so the averaged DSI picks it with C = 1 even when every pixel is
+    # re-picked
+    H, W, n, s = 24, 48, 2, 5
+    L, R = _shifted_pair(H, W, s, seed=34)
+    d1 = np.zeros((H, W), np.int16)
+    C1 = np.full((H, W), -1.0)
+    d, C, _ = oracle.aggregate(L, R, n, 12, d1, C1, 0.9, 0.065)
+    inner = (slice(n + 2, -n - 2), slice(s + n + 4, -n - 2))
+    assert np.all(d[inner] == s)
+    np.testing.assert_allclose(C[inner], 1.0, atol=1e-12)
+
+
+def test_gated_hierarchy_limits():
+    p = synth.make_pair(35, 40, 72, 3, 2, 12, True, 0.9, 5.0, 3.0, "u8")
+    D, K, n, r, eps = 24, 3, 2, 1, 0.065
+    plain = oracle.disparity(p.left, p.right, D, K, n, r, eps)
+    # nothing gated: the plain hierarchy
+    off = oracle.disparity(p.left, p.right, D, K, n, r, eps, gate=(-2.0, -2.0))
+    for k in range(K):
+        assert np.array_equal(off[k][0], plain[k][0]) and np.array_equal(off[k][1], plain[k][1])
+    # beta above every cost: every finer level is a full search, so level 0 is
+    # flat block matching whatever the coarser levels found
+    full = oracle.disparity(p.left, p.right, D, K, n, r, eps, gate=(-2.0, 2.0))
+    flat = oracle.flat_bm(p.left, p.right, D, n, eps)
+    assert np.array_equal(full[0][0], flat[0]) and np.array_equal(full[0][1], flat[1])
+    # the paper's thresholds: each level is the chain of its steps
+    g = oracle.disparity(p.left, p.right, D, K, n, r, eps, gate=(0.9, 0.9))
+    PL, PR = oracle.pyramid(p.left, K), oracle.pyramid(p.right, K)
+    d1, C1, _, _ = oracle.match_gated(PL[0], PR[0], n, D, g[1][0], g[1][1], r, 0.9, eps)
+    d, C, _ = oracle.aggregate(PL[0], PR[0], n, D, d1, C1, 0.9, eps)
+    assert np.array_equal(d, g[0][0]) and np.array_equal(C, g[0][1])
+    assert (d != d1).any()
