@@ -76,6 +76,14 @@ typedef int32_t msibm_status;
 #define MSIBM_FLAG_MEDIAN 16    /* plain forward only: every level's hard map goes
                                    through the selective median filter (Eq. 10)
                                    with threshold median_alpha                  */
+#define MSIBM_FLAG_GATED 32     /* plain forward only: the confidence gating of
+                                   Sections III.B-C at every hard level: below the
+                                   coarsest level, the full search where the
+                                   bicubic-doubled coarser cost is <= gate_beta
+                                   (Eqs. 8-9); then the re-pick of pixels with
+                                   cost <= gate_alpha by the 5x5-averaged scores
+                                   (Eqs. 5-7); the cost carried down and returned
+                                   is that of Eq. 7                             */
 #define MSIBM_FLAG_PERSISTENT 4 /* reserved: single-launch persistent scheduler;
                                    switched off, fails with UNSUPPORTED       */
 
@@ -109,6 +117,9 @@ typedef struct msibm_config {
                               (Section III), e.g. {5, 2, 1}                    */
     float median_alpha;    /* with MSIBM_FLAG_MEDIAN: pixels with matched cost
                               <= median_alpha are filtered (the paper: 0.9)      */
+    float gate_alpha;      /* with MSIBM_FLAG_GATED: re-pick threshold alpha    */
+    float gate_beta;       /* with MSIBM_FLAG_GATED: full-search threshold beta
+                              (the paper: alpha = beta = 0.9)                   */
 } msibm_config;
 
 /* Thread-local description of the last error of this thread ("" if none). */
@@ -189,6 +200,20 @@ msibm_status msibm_median_filter(const int16_t* d_in, int32_t in_pitch, const fl
                                  int32_t H, int32_t W, double alpha, int16_t* d_out, int32_t out_pitch,
                                  void* stream);
 
+/*
+ * msibm_upsample_cost - bicubic doubling of a coarser cost map (Section III.C),
+ * the map the gated search compares with beta.  Fine pixel (i, j) sits at the
+ * coarse position ((i + 1/2)/2 - 1/2, (j + 1/2)/2 - 1/2); Keys' cubic kernel
+ * with a = -1/2 over the 4 x 4 nearest taps, clamped to the map; evaluated in
+ * double as a fixed-order 16-term sum.
+ *   coarse   device float Hc x Wc (row pitch coarse_pitch).
+ *   out      device double H x W (row pitch out_pitch) with Hc = ceil(H/2),
+ *            Wc = ceil(W/2).
+ * Errors: INVALID_ARG (null pointers), SHAPE (sizes, pitches), HIP.
+ */
+msibm_status msibm_upsample_cost(const float* coarse, int32_t Hc, int32_t Wc, int32_t coarse_pitch, int32_t H,
+                                 int32_t W, double* out, int32_t out_pitch, void* stream);
+
 /* Bytes of workspace msibm_match_level needs for an H x W level. */
 size_t msibm_level_workspace_size(int32_t H, int32_t W);
 
@@ -216,6 +241,44 @@ msibm_status msibm_match_level(const void* L, const void* R, int32_t dtype, int3
                                int32_t Hc, int32_t Wc, int32_t prior_pitch, int32_t r,
                                float var_eps, int16_t* d_out, float* cost_out, int32_t out_pitch,
                                float* costvol, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * msibm_match_level_gated - confidence-gated matching of a finer level (Eqs.
+ * 8-9): the restricted search of msibm_match_level around `prior`, except at
+ * pixels whose bicubic-doubled coarser cost (msibm_upsample_cost of
+ * prior_cost, compared in double) is <= beta, which take the full search of z
+ * in [0, min(D_k - 1, j)].  Ties go to the lowest z in both branches.
+ *   prior, prior_cost  device int16 and float Hc x Wc maps of level k+1 (its
+ *                      disparities and costs), Hc = ceil(H/2), Wc = ceil(W/2),
+ *                      both with row pitch prior_pitch.
+ *   d_out, cost_out    device int16 / float H x W, row pitch out_pitch (both
+ *                      required).
+ *   workspace          msibm_level_workspace_size(H, W) bytes.
+ * Errors: as msibm_match_level; INVALID_ARG for a NULL prior, prior_cost or
+ *         cost_out, or a non-finite beta.
+ */
+msibm_status msibm_match_level_gated(const void* L, const void* R, int32_t dtype, int32_t H, int32_t W,
+                                     int32_t pitch, int32_t n, int32_t Dk, const int16_t* prior,
+                                     const float* prior_cost, int32_t Hc, int32_t Wc, int32_t prior_pitch,
+                                     int32_t r, double beta, float var_eps, int16_t* d_out, float* cost_out,
+                                     int32_t out_pitch, void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * msibm_aggregate_refine - disparity refinement by the neighbourhood-averaged
+ * disparity search image (Eqs. 5-7), in place.  A pixel whose cost is <= alpha
+ * (compared in double) takes the z of [0, min(D_k - 1, j)] that maximises the
+ * mean over its 5x5 neighbourhood (clipped to the image) of the neighbours'
+ * scores at z, a neighbour in column q counting only for z <= q; its cost
+ * becomes that maximum (ties to the lowest z).  Other pixels keep d and cost.
+ *   d, cost    device int16 / float H x W, row pitch dc_pitch (read and written).
+ *   workspace  msibm_level_workspace_size(H, W) bytes.
+ * Errors: INVALID_ARG (null pointers, non-finite alpha, var_eps), SHAPE,
+ *         UNSUPPORTED (n, D_k), WORKSPACE, HIP.
+ */
+msibm_status msibm_aggregate_refine(const void* L, const void* R, int32_t dtype, int32_t H, int32_t W,
+                                    int32_t pitch, int32_t n, int32_t Dk, int16_t* d, float* cost,
+                                    int32_t dc_pitch, double alpha, float var_eps, void* workspace,
+                                    size_t ws_bytes, void* stream);
 
 /* Bytes of workspace msibm_disparity / msibm_backward need for these pairs. */
 size_t msibm_workspace_size(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg);

@@ -71,6 +71,12 @@ def _load():
         lib.orc_aggregate.argtypes = [_D, _D, c_int, c_int, c_int, c_int, _I16, _D, c_double,
                                       c_double, _I16, _D, _D]
         lib.orc_aggregate.restype = None
+        _I32 = ctypes.POINTER(ctypes.c_int32)
+        lib.orc_aggregate_pixels.argtypes = [_D, _D, c_int, c_int, c_int, c_int, _I16, _D, c_double,
+                                             c_double, _I32, _I32, c_int, _I16, _D, _D]
+        lib.orc_aggregate_pixels.restype = None
+        lib.orc_avg_score_many.argtypes = [_D, _D, c_int, c_int, c_int, c_double, _I32, _I32, _I32, c_int, _D]
+        lib.orc_avg_score_many.restype = None
         lib.orc_zncc.argtypes = [_D, _D, c_int, c_int, c_int, c_int, c_int, c_int, c_double]
         lib.orc_zncc.restype = c_double
         lib.orc_match_level.argtypes = [_D, _D, c_int, c_int, c_int, c_int, _I16, c_int, c_int,
@@ -270,6 +276,41 @@ def aggregate(L: np.ndarray, R: np.ndarray, n: int, Dk: int, d1: np.ndarray, C1:
     _load().orc_aggregate(_p(L, _D), _p(R, _D), H, W, n, Dk, _p(dd, _I16), _p(CC, _D), float(alpha),
                           eps, _p(d, _I16), _p(C, _D), _p(C2, _D))
     return d, C, C2
+
+
+def aggregate_pixels(L: np.ndarray, R: np.ndarray, n: int, Dk: int, d1: np.ndarray, C1: np.ndarray,
+                     alpha: float, eps: float, ii, jj):
+    """aggregate() at the listed pixels only: (d, C, C2) per pixel."""
+    L = _f64(L)
+    R = _f64(R)
+    H, W = L.shape
+    dd = np.ascontiguousarray(d1, dtype=np.int16)
+    CC = _f64(C1)
+    i32 = np.ascontiguousarray(ii, dtype=np.int32)
+    j32 = np.ascontiguousarray(jj, dtype=np.int32)
+    m = len(i32)
+    d = np.empty(m, dtype=np.int16)
+    C = np.empty(m, dtype=np.float64)
+    C2 = np.empty(m, dtype=np.float64)
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    _load().orc_aggregate_pixels(_p(L, _D), _p(R, _D), H, W, n, Dk, _p(dd, _I16), _p(CC, _D), float(alpha),
+                                 eps, _p(i32, P32), _p(j32, P32), m, _p(d, _I16), _p(C, _D), _p(C2, _D))
+    return d, C, C2
+
+
+def avg_score_many(L: np.ndarray, R: np.ndarray, n: int, ii, jj, zz, eps: float) -> np.ndarray:
+    """The 5x5-averaged score (Eq. 5) at (i, j, z) triples."""
+    L = _f64(L)
+    R = _f64(R)
+    H, W = L.shape
+    i32 = np.ascontiguousarray(ii, dtype=np.int32)
+    j32 = np.ascontiguousarray(jj, dtype=np.int32)
+    z32 = np.ascontiguousarray(zz, dtype=np.int32)
+    out = np.empty(len(i32), dtype=np.float64)
+    P32 = ctypes.POINTER(ctypes.c_int32)
+    _load().orc_avg_score_many(_p(L, _D), _p(R, _D), H, W, n, eps, _p(i32, P32), _p(j32, P32), _p(z32, P32),
+                               len(i32), _p(out, _D))
+    return out
 
 
 def disparity(left: np.ndarray, right: np.ndarray, D: int, K: int, n, r: int,

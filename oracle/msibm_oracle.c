@@ -431,51 +431,83 @@ void orc_match_gated(const double* L, const double* R, int H, int W, int n, int 
     free(up);
 }
 
+/* The neighbourhood-averaged score of pixel (i, j) at candidate z (Eq. 5, read
+ * as a mean): the scores at z of the pixels of the 5x5 box around (i, j) that
+ * lie inside the image and have z among their own candidates (z <= q for
+ * column q), divided by their number. */
+double orc_avg_score(const double* L, const double* R, int H, int W, int n, int i, int j, int z, double eps)
+{
+    double s = 0.0;
+    int cnt = 0;
+    for (int m = i - 2; m <= i + 2; ++m)
+        for (int q = j - 2; q <= j + 2; ++q) {
+            if (m < 0 || m >= H || q < 0 || q >= W || z > q) continue;
+            s += orc_zncc(L, R, H, W, n, m, q, z, eps);
+            ++cnt;
+        }
+    return s / cnt;
+}
+
 /* Disparity refinement by the neighbourhood-averaged disparity search image
  * (Eqs. 5-7).  A pixel whose matched cost C' is at most alpha takes the z that
- * maximises E^(z), the mean over its 5x5 neighbourhood of the neighbours'
- * scores at z, and C = max E^; other pixels keep d' and C'.  Readings: the
- * neighbourhood is the 5x5 box of the median step, clipped to the image; z runs
- * over the pixel's own full interval [0, min(D_k - 1, j)]; a neighbour (m, q)
- * contributes at z only where z is one of its own candidates (z <= q), and the
- * mean divides by the number of contributors; ties go to the lowest z.  C2 is
- * the second-largest E^ of a re-picked pixel (-inf otherwise). */
+ * maximises E^(z) = orc_avg_score over its own full interval
+ * [0, min(D_k - 1, j)] (a reading: Eq. 6 names d_max, and this level's range is
+ * D_k), and C = max E^; other pixels keep d' and C'.  Readings: the
+ * neighbourhood is the 5x5 box of the median step; ties go to the lowest z.  C2
+ * is the second-largest E^ of a re-picked pixel (-inf otherwise). */
+static void aggregate_pixel(const double* L, const double* R, int H, int W, int n, int Dk,
+                            const int16_t* d_in, const double* C_in, double alpha, double eps, int i, int j,
+                            int16_t* d, double* C, double* C2)
+{
+    const size_t o = (size_t)i * W + j;
+    *d = d_in[o];
+    *C = C_in[o];
+    *C2 = -INFINITY;
+    if (C_in[o] > alpha) return;
+    const int top = Dk - 1 < j ? Dk - 1 : j;
+    double best = -INFINITY, second = -INFINITY;
+    int bz = 0;
+    for (int z = 0; z <= top; ++z) {
+        const double e = orc_avg_score(L, R, H, W, n, i, j, z, eps);
+        if (e > best) {
+            second = best;
+            best = e;
+            bz = z;
+        } else if (e > second) {
+            second = e;
+        }
+    }
+    *d = (int16_t)bz;
+    *C = best;
+    *C2 = second;
+}
+
 void orc_aggregate(const double* L, const double* R, int H, int W, int n, int Dk,
                    const int16_t* d_in, const double* C_in, double alpha, double eps,
                    int16_t* d, double* C, double* C2)
 {
 #pragma omp parallel for schedule(dynamic, 1)
-    for (int i = 0; i < H; ++i) {
+    for (int i = 0; i < H; ++i)
         for (int j = 0; j < W; ++j) {
             const size_t o = (size_t)i * W + j;
-            d[o] = d_in[o];
-            C[o] = C_in[o];
-            C2[o] = -INFINITY;
-            if (C_in[o] > alpha) continue;
-            const int top = Dk - 1 < j ? Dk - 1 : j;
-            double best = -INFINITY, second = -INFINITY;
-            int bz = 0;
-            for (int z = 0; z <= top; ++z) {
-                double s = 0.0;
-                int cnt = 0;
-                for (int m = i - 2; m <= i + 2; ++m)
-                    for (int q = j - 2; q <= j + 2; ++q) {
-                        if (m < 0 || m >= H || q < 0 || q >= W || z > q) continue;
-                        s += orc_zncc(L, R, H, W, n, m, q, z, eps);
-                        ++cnt;
-                    }
-                const double e = s / cnt;
-                if (e > best) {
-                    second = best;
-                    best = e;
-                    bz = z;
-                } else if (e > second) {
-                    second = e;
-                }
-            }
-            d[o] = (int16_t)bz;
-            C[o] = best;
-            C2[o] = second;
+            aggregate_pixel(L, R, H, W, n, Dk, d_in, C_in, alpha, eps, i, j, d + o, C + o, C2 + o);
         }
-    }
+}
+
+/* orc_aggregate restricted to a list of pixels (one output per pixel). */
+void orc_aggregate_pixels(const double* L, const double* R, int H, int W, int n, int Dk,
+                          const int16_t* d_in, const double* C_in, double alpha, double eps,
+                          const int32_t* ii, const int32_t* jj, int count, int16_t* d, double* C, double* C2)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int q = 0; q < count; ++q)
+        aggregate_pixel(L, R, H, W, n, Dk, d_in, C_in, alpha, eps, ii[q], jj[q], d + q, C + q, C2 + q);
+}
+
+/* orc_avg_score at a list of (i, j, z) triples. */
+void orc_avg_score_many(const double* L, const double* R, int H, int W, int n, double eps,
+                        const int32_t* ii, const int32_t* jj, const int32_t* zz, int count, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int q = 0; q < count; ++q) out[q] = orc_avg_score(L, R, H, W, n, ii[q], jj[q], zz[q], eps);
 }

@@ -88,7 +88,8 @@ msibm_status validate_config(const msibm_config* cfg)
         return fail(MSIBM_ERR_INVALID_ARG, "tau must be finite and > 0");
     if (cfg->flags & MSIBM_FLAG_PERSISTENT)
         return fail(MSIBM_ERR_UNSUPPORTED, "the persistent single-launch scheduler is switched off");
-    if (cfg->flags & ~(MSIBM_FLAG_BATCHED | MSIBM_FLAG_GRAPH | MSIBM_FLAG_PREBLUR | MSIBM_FLAG_MEDIAN))
+    if (cfg->flags &
+        ~(MSIBM_FLAG_BATCHED | MSIBM_FLAG_GRAPH | MSIBM_FLAG_PREBLUR | MSIBM_FLAG_MEDIAN | MSIBM_FLAG_GATED))
         return fail(MSIBM_ERR_INVALID_ARG, "unknown flags 0x%x", cfg->flags);
     if ((cfg->flags & MSIBM_FLAG_PREBLUR) && (cfg->flags & MSIBM_FLAG_BATCHED))
         return fail(MSIBM_ERR_UNSUPPORTED, "MSIBM_FLAG_PREBLUR runs on the plain path only");
@@ -96,6 +97,10 @@ msibm_status validate_config(const msibm_config* cfg)
         return fail(MSIBM_ERR_UNSUPPORTED, "MSIBM_FLAG_MEDIAN runs on the plain path only");
     if ((cfg->flags & MSIBM_FLAG_MEDIAN) && !std::isfinite(cfg->median_alpha))
         return fail(MSIBM_ERR_INVALID_ARG, "median_alpha must be finite");
+    if ((cfg->flags & MSIBM_FLAG_GATED) && (cfg->flags & MSIBM_FLAG_BATCHED))
+        return fail(MSIBM_ERR_UNSUPPORTED, "MSIBM_FLAG_GATED runs on the plain path only");
+    if ((cfg->flags & MSIBM_FLAG_GATED) && (!std::isfinite(cfg->gate_alpha) || !std::isfinite(cfg->gate_beta)))
+        return fail(MSIBM_ERR_INVALID_ARG, "gate_alpha and gate_beta must be finite");
     if ((cfg->flags & MSIBM_FLAG_GRAPH) && !(cfg->flags & MSIBM_FLAG_BATCHED))
         return fail(MSIBM_ERR_INVALID_ARG, "MSIBM_FLAG_GRAPH needs MSIBM_FLAG_BATCHED");
     return MSIBM_OK;
@@ -124,7 +129,7 @@ msibm_status validate_pair(const msibm_pair& p, int idx, const msibm_config* cfg
 }
 
 // Workspace layout of one pair (offsets from the pair's base).
-PairLayout pair_layout(const msibm_pair& p, int K, bool preblur, bool median)
+PairLayout pair_layout(const msibm_pair& p, int K, bool preblur, bool median, bool gated)
 {
     PairLayout L{};
     L.K = K;
@@ -145,6 +150,10 @@ PairLayout pair_layout(const msibm_pair& p, int K, bool preblur, bool median)
             L.map[k] = off;
             off = align_up(off + px * sizeof(int16_t));
         }
+        if (k > 0 && gated) {
+            L.cmap[k] = off;
+            off = align_up(off + px * sizeof(float));
+        }
     }
     if (preblur)
         for (int v = 0; v < 2; ++v) {
@@ -154,6 +163,8 @@ PairLayout pair_layout(const msibm_pair& p, int K, bool preblur, bool median)
     if (median) {
         L.dtmp = off;
         off = align_up(off + (size_t)p.height * p.width * sizeof(int16_t));
+    }
+    if (median || gated) {
         L.ctmp = off;
         off = align_up(off + (size_t)p.height * p.width * sizeof(float));
     }
@@ -321,6 +332,93 @@ msibm_status msibm_match_level(const void* L, const void* R, int32_t dtype, int3
     return ok();
 }
 
+msibm_status msibm_upsample_cost(const float* coarse, int32_t Hc, int32_t Wc, int32_t coarse_pitch, int32_t H,
+                                 int32_t W, double* out, int32_t out_pitch, void* stream)
+{
+    if (!coarse || !out) return fail(MSIBM_ERR_INVALID_ARG, "NULL map");
+    if (H < 1 || W < 1 || Hc != (H + 1) / 2 || Wc != (W + 1) / 2 || coarse_pitch < Wc || out_pitch < W)
+        return fail(MSIBM_ERR_SHAPE, "coarse %dx%d (pitch %d) for %dx%d (pitch %d)", Hc, Wc, coarse_pitch, H, W,
+                    out_pitch);
+    const hipError_t e = launch_upsample_cost(coarse, Hc, Wc, coarse_pitch, H, W, out, out_pitch,
+                                              (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "upsample launch");
+    return ok();
+}
+
+static GateArgs gate_args(const void* L, const void* R, int H, int W, int pitch, int Dk, void* workspace,
+                          int16_t* d, float* c, int opitch, double thresh)
+{
+    GateArgs g{};
+    g.L = L;
+    g.R = R;
+    g.pitch = pitch;
+    g.H = H;
+    g.W = W;
+    g.Dk = Dk;
+    g.statL = (const WinStat*)workspace;
+    g.statR = (const WinStat*)((char*)workspace + align_up((size_t)H * W * sizeof(WinStat)));
+    g.spitch = W;
+    g.d = d;
+    g.c = c;
+    g.opitch = opitch;
+    g.thresh = thresh;
+    return g;
+}
+
+msibm_status msibm_match_level_gated(const void* L, const void* R, int32_t dtype, int32_t H, int32_t W,
+                                     int32_t pitch, int32_t n, int32_t Dk, const int16_t* prior,
+                                     const float* prior_cost, int32_t Hc, int32_t Wc, int32_t prior_pitch,
+                                     int32_t r, double beta, float var_eps, int16_t* d_out, float* cost_out,
+                                     int32_t out_pitch, void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!prior || !prior_cost || !cost_out) return fail(MSIBM_ERR_INVALID_ARG, "NULL prior, prior cost or cost");
+    if (!std::isfinite(beta)) return fail(MSIBM_ERR_INVALID_ARG, "beta must be finite");
+    // statistics and the restricted search of every pixel
+    const msibm_status st = msibm_match_level(L, R, dtype, H, W, pitch, n, Dk, prior, Hc, Wc, prior_pitch, r,
+                                              var_eps, d_out, cost_out, out_pitch, nullptr, workspace, ws_bytes,
+                                              stream);
+    if (st != MSIBM_OK) return st;
+    GateArgs g = gate_args(L, R, H, W, pitch, Dk, workspace, d_out, cost_out, out_pitch, beta);
+    g.ccost = prior_cost;
+    g.Hc = Hc;
+    g.Wc = Wc;
+    g.cpitch = prior_pitch;
+    const hipError_t e = launch_gate(n, dtype, false, g, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gated full search launch");
+    return ok();
+}
+
+msibm_status msibm_aggregate_refine(const void* L, const void* R, int32_t dtype, int32_t H, int32_t W,
+                                    int32_t pitch, int32_t n, int32_t Dk, int16_t* d, float* cost,
+                                    int32_t dc_pitch, double alpha, float var_eps, void* workspace,
+                                    size_t ws_bytes, void* stream)
+{
+    if (!L || !R || !d || !cost) return fail(MSIBM_ERR_INVALID_ARG, "NULL image, map or cost");
+    if (dtype != MSIBM_U8 && dtype != MSIBM_F32) return fail(MSIBM_ERR_INVALID_ARG, "dtype %d", dtype);
+    if (!std::isfinite(alpha)) return fail(MSIBM_ERR_INVALID_ARG, "alpha must be finite");
+    if (!(var_eps >= 0.f) || !std::isfinite(var_eps)) return fail(MSIBM_ERR_INVALID_ARG, "var_eps");
+    if (H < 1 || W < 1 || pitch < W || dc_pitch < W)
+        return fail(MSIBM_ERR_SHAPE, "size %dx%d pitch %d map pitch %d", H, W, pitch, dc_pitch);
+    if (n < 1 || n > MSIBM_MAX_HALF_WINDOW) return fail(MSIBM_ERR_UNSUPPORTED, "n %d outside 1..%d", n, MSIBM_MAX_HALF_WINDOW);
+    if (Dk < 1 || Dk > MSIBM_MAX_DISP) return fail(MSIBM_ERR_UNSUPPORTED, "D_k %d outside 1..%d", Dk, MSIBM_MAX_DISP);
+    const size_t need = msibm_level_workspace_size(H, W);
+    if (!workspace || ws_bytes < need)
+        return fail(MSIBM_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace ? ws_bytes : (size_t)0, need);
+    hipStream_t s = (hipStream_t)stream;
+    GateArgs g = gate_args(L, R, H, W, pitch, Dk, workspace, d, cost, dc_pitch, alpha);
+    StatsArgs sa{};
+    sa.seg[0] = StatsSeg{L, (WinStat*)g.statL, dtype, H, W, pitch, W, 0};
+    sa.seg[1] = StatsSeg{R, (WinStat*)g.statR, dtype, H, W, pitch, W, 0};
+    sa.nseg = 2;
+    sa.n = n;
+    sa.var_eps = var_eps;
+    hipError_t e = launch_stats(sa, s);
+    if (e != hipSuccess) return hip_fail(e, "stats launch");
+    e = launch_gate(n, dtype, true, g, s);
+    if (e != hipSuccess) return hip_fail(e, "re-pick launch");
+    return ok();
+}
+
 size_t msibm_workspace_size(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg)
 {
     if (!pairs || n_pairs < 1 || n_pairs > MSIBM_MAX_PAIRS || !cfg) return 0;
@@ -330,7 +428,7 @@ size_t msibm_workspace_size(const msibm_pair* pairs, int32_t n_pairs, const msib
         int K;
         if (validate_pair(pairs[p], p, cfg, &K) != MSIBM_OK) return 0;
         tot += pair_layout(pairs[p], K, (cfg->flags & MSIBM_FLAG_PREBLUR) != 0,
-                           (cfg->flags & MSIBM_FLAG_MEDIAN) != 0).bytes;
+                           (cfg->flags & MSIBM_FLAG_MEDIAN) != 0, (cfg->flags & MSIBM_FLAG_GATED) != 0).bytes;
     }
     tot += batch_extra_bytes(pairs, n_pairs, cfg);
     return tot;
@@ -369,7 +467,8 @@ msibm_status msibm_disparity(const msibm_pair* pairs, int32_t n_pairs, const msi
     for (int p = 0; p < n_pairs; ++p) {
         const msibm_pair& P = pairs[p];
         const PairLayout lay = pair_layout(P, Ks[p], (cfg->flags & MSIBM_FLAG_PREBLUR) != 0,
-                                           (cfg->flags & MSIBM_FLAG_MEDIAN) != 0);
+                                           (cfg->flags & MSIBM_FLAG_MEDIAN) != 0,
+                                           (cfg->flags & MSIBM_FLAG_GATED) != 0);
         char* ws = (char*)workspace + base;
         base += lay.bytes;
         std::string err;

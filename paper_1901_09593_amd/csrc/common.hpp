@@ -108,6 +108,26 @@ struct MedianArgs {
     double alpha;
 };
 
+// Confidence gating of one level (Eqs. 5-9), in place on its map d and cost c.
+// Full-search mode: pixels whose bicubic-upsampled coarser cost is at most
+// `thresh` (beta) take the full search.  Re-pick mode: pixels whose cost is at
+// most `thresh` (alpha) take the argmax of the 5x5-averaged scores.
+struct GateArgs {
+    const void* L;
+    const void* R;
+    int pitch;                  // image row pitch (elements)
+    int H, W, Dk;
+    const WinStat* statL;
+    const WinStat* statR;
+    int spitch;
+    int16_t* d;
+    float* c;
+    int opitch;
+    const float* ccost;         // coarser level's cost (full-search mode)
+    int Hc, Wc, cpitch;
+    double thresh;
+};
+
 // Full-resolution binomial blur of both views (the pre-blur variant's level 0).
 struct BlurArgs {
     const void* src[2];
@@ -202,6 +222,9 @@ hipError_t launch_stats(StatsArgs a, hipStream_t s);
 hipError_t launch_tower(int dtype, const TowerArgs& a, hipStream_t s);
 hipError_t launch_blur(int dtype, const BlurArgs& a, hipStream_t s);
 hipError_t launch_median(const MedianArgs& a, hipStream_t s);
+hipError_t launch_gate(int n, int dtype, bool repick, const GateArgs& a, hipStream_t s);
+hipError_t launch_upsample_cost(const float* cc, int Hc, int Wc, int cpitch, int H, int W, double* out,
+                                int opitch, hipStream_t s);
 hipError_t launch_match(int n, int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);
 
 // Multi-segment launches (batched path); `blocks` = total tiles of the segments.

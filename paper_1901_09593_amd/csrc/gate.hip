@@ -1,0 +1,304 @@
+// Confidence gating of one level (Section III.B Eqs. 5-7, Section III.C Eqs.
+// 8-9) and the bicubic doubling of a coarser cost map that drives it.
+//
+// Both gating steps need, for a tile of pixels, the score of every candidate
+// z of the full interval: the fallback full search (pixels whose upsampled
+// coarser cost is at most beta) takes each pixel's best z, and the re-pick
+// (pixels whose cost is at most alpha) takes the best z of the scores averaged
+// over each pixel's 5x5 neighbourhood.  One workgroup handles an 8 x 64 tile
+// and walks z upwards; at each z it scores a region (the tile, plus the 5x5
+// halo for the re-pick) with box sums instead of per-window loops:
+//   V(y, e) = sum over the 2n+1 window rows of L(v, e) R(v, e - z)   (columns)
+//   S(y, u) = sum over the 2n+1 window columns of V                  (rows)
+// so a score costs O(1) instead of O((2n+1)^2) multiply-adds.  The sums run in
+// double: with the window means of the statistics kernel the cross term is
+//   C = S - N mu_l mu_r   (= sum (l - mu_l)(r - mu_r))
+// whose cancellation double absorbs, and rho = C * invsd_l * invsd_r clamped to
+// [-1, 1], 0 for a flat window (invsd = 0).  Tiles without a gated pixel leave
+// at once; the z range stops at the rightmost gated pixel's last candidate.
+#include "common.hpp"
+
+namespace msibm {
+
+namespace {
+
+constexpr int GT_H = 8;        // tile rows
+constexpr int GT_W = 64;       // tile columns
+constexpr int GT_ZC = 32;      // candidates per staged right chunk
+constexpr int GT_THREADS = 256;
+
+// Keys' cubic weights (a = -1/2) of the four coarse taps around fine index i
+// at scale 2 with aligned pixel centres: the fine pixel sits 3/4 (even i) or
+// 1/4 (odd i) past its second tap.  All are multiples of 1/128.
+__device__ __forceinline__ double cubic_w(int odd, int m)
+{
+    const int t = odd ? 3 - m : m;
+    return t == 0 ? -3.0 / 128 : t == 1 ? 29.0 / 128 : t == 2 ? 111.0 / 128 : -9.0 / 128;
+}
+
+// Bicubic value of the coarser cost at fine pixel (i, j): the 16-tap sum in a
+// fixed order with separately rounded products and sums (no contraction), so
+// the result does not depend on how the compiler schedules it.
+__device__ double upsampled_cost(const float* cc, int Hc, int Wc, int cpitch, int i, int j)
+{
+    const int i0 = (i >> 1) - 1 + (i & 1), j0 = (j >> 1) - 1 + (j & 1);
+    double s = 0.0;
+    for (int m = 0; m < 4; ++m) {
+        const float* row = cc + (size_t)clampi(i0 - 1 + m, 0, Hc - 1) * cpitch;
+        const double wm = cubic_w(i & 1, m);
+        for (int q = 0; q < 4; ++q) {
+            const double w = __dmul_rn(wm, cubic_w(j & 1, q));
+            s = __dadd_rn(s, __dmul_rn(w, (double)row[clampi(j0 - 1 + q, 0, Wc - 1)]));
+        }
+    }
+    return s;
+}
+
+__global__ __launch_bounds__(256) void upsample_kernel(const float* cc, int Hc, int Wc, int cpitch, int H,
+                                                       int W, double* out, int opitch)
+{
+    const int j = blockIdx.x * 64 + (threadIdx.x & 63), i = blockIdx.y * 4 + (threadIdx.x >> 6);
+    if (i >= H || j >= W) return;
+    out[(size_t)i * opitch + j] = upsampled_cost(cc, Hc, Wc, cpitch, i, j);
+}
+
+template <typename T>
+__device__ __forceinline__ float pix(const void* img, int pitch, int y, int x)
+{
+    return (float)((const T*)img)[(size_t)y * pitch + x];
+}
+
+template <typename T, int NW, bool REPICK>
+__global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
+{
+    constexpr int HB = REPICK ? 2 : 0;                 // halo of the averaged scores
+    constexpr int RR = GT_H + 2 * HB;                  // region scored at each z
+    constexpr int RC = GT_W + 2 * HB;
+    constexpr int ER = RR + 2 * NW;                    // plus the windows' halo
+    constexpr int EC = RC + 2 * NW;
+    constexpr int RSW = EC + GT_ZC - 1;                // staged right columns per chunk
+    constexpr int SSW = RC + GT_ZC - 1;                // staged right statistics per chunk
+    constexpr double NN = (double)((2 * NW + 1) * (2 * NW + 1));
+    constexpr int VG = 4;                              // rows of column sums per thread
+    constexpr int NVG = RR / VG;
+    constexpr int RUN = REPICK ? 4 : 2;                // region columns scored per thread
+    constexpr int NRUN = (RC + RUN - 1) / RUN;
+    static_assert(RR % VG == 0, "row groups");
+    static_assert(EC * NVG <= GT_THREADS && RR * NRUN <= GT_THREADS, "one item per thread");
+
+    __shared__ float Ls[ER][EC];
+    __shared__ float Rs[ER][RSW];
+    __shared__ double V[RR][EC];
+    __shared__ double Smu[RR][SSW];
+    __shared__ float Sis[RR][SSW];
+    __shared__ float Es[REPICK ? RR : 1][REPICK ? RC : 1];
+    __shared__ int s_xmax;
+
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * GT_W, y0 = blockIdx.y * GT_H;
+    const int ry0 = y0 - HB, rx0 = x0 - HB;            // region origin
+    const int ey0 = ry0 - NW, ex0 = rx0 - NW;          // extended origin
+    const int H = a.H, W = a.W;
+
+    // owned output pixels: the re-pick gives thread t column t % 64 and rows
+    // 2 (t / 64) + {0, 1}; the full search owns the pixels it scores itself
+    int oy[2], ox[2];
+    if constexpr (REPICK) {
+        ox[0] = ox[1] = tid & 63;
+        oy[0] = 2 * (tid >> 6);
+        oy[1] = oy[0] + 1;
+    } else {
+        oy[0] = oy[1] = tid >> 5;
+        ox[0] = 2 * (tid & 31);
+        ox[1] = ox[0] + 1;
+    }
+    bool act[2];
+    double best[2] = {-1e300, -1e300};
+    int bz[2] = {0, 0};
+    if (tid == 0) s_xmax = -1;
+    __syncthreads();
+    for (int p = 0; p < 2; ++p) {
+        const int i = y0 + oy[p], j = x0 + ox[p];
+        act[p] = false;
+        if (i < H && j < W) {
+            if constexpr (REPICK)
+                act[p] = !((double)a.c[(size_t)i * a.opitch + j] > a.thresh);
+            else
+                act[p] = !(upsampled_cost(a.ccost, a.Hc, a.Wc, a.cpitch, i, j) > a.thresh);
+            if (act[p]) atomicMax(&s_xmax, j);
+        }
+    }
+    __syncthreads();
+    const int xmax = s_xmax;
+    if (xmax < 0) return;  // uniform: no gated pixel in the tile
+    const int zmax = min(a.Dk - 1, xmax);
+
+    for (int idx = tid; idx < ER * EC; idx += GT_THREADS) {
+        const int v = idx / EC, e = idx - v * EC;
+        Ls[v][e] = pix<T>(a.L, a.pitch, clampi(ey0 + v, 0, H - 1), clampi(ex0 + e, 0, W - 1));
+    }
+
+    // the region pixels this thread scores, with their left statistics
+    const int sy = tid / NRUN, su = (tid - sy * NRUN) * RUN;
+    const bool scorer = tid < RR * NRUN;
+    double mul[RUN];
+    float isl[RUN];
+    int sxa[RUN];     // region pixel column, or -1 outside the image
+#pragma unroll
+    for (int q = 0; q < RUN; ++q) {
+        const int yy = ry0 + sy, xx = rx0 + su + q;
+        const bool in = scorer && su + q < RC && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        sxa[q] = in ? xx : -1;
+        mul[q] = 0.0;
+        isl[q] = 0.f;
+        if (in) {
+            const WinStat st = a.statL[(size_t)yy * a.spitch + xx];
+            mul[q] = (double)st.x + (double)st.y;
+            isl[q] = st.z;
+        }
+    }
+    // neighbours of an owned pixel inside the image: rows, and columns at or
+    // right of it (every z <= j is a candidate of those)
+    int rows_in[2], cols_r[2];
+    for (int p = 0; p < 2; ++p) {
+        const int i = y0 + oy[p], j = x0 + ox[p];
+        rows_in[p] = min(i + 2, H - 1) - max(i - 2, 0) + 1;
+        cols_r[p] = min(j + 2, W - 1) - j + 1;
+    }
+
+    for (int z0 = 0; z0 <= zmax; z0 += GT_ZC) {
+        const int zhi = z0 + GT_ZC - 1;
+        __syncthreads();  // the previous chunk's staged data is consumed
+        for (int idx = tid; idx < ER * RSW; idx += GT_THREADS) {
+            const int v = idx / RSW, w = idx - v * RSW;
+            Rs[v][w] = pix<T>(a.R, a.pitch, clampi(ey0 + v, 0, H - 1), clampi(ex0 - zhi + w, 0, W - 1));
+        }
+        for (int idx = tid; idx < RR * SSW; idx += GT_THREADS) {
+            const int y = idx / SSW, w = idx - y * SSW;
+            const WinStat st = a.statR[(size_t)clampi(ry0 + y, 0, H - 1) * a.spitch +
+                                       clampi(rx0 - zhi + w, 0, W - 1)];
+            Smu[y][w] = (double)st.x + (double)st.y;
+            Sis[y][w] = st.z;
+        }
+        __syncthreads();
+        const int zend = min(zhi, zmax);
+        for (int z = z0; z <= zend; ++z) {
+            const int zz = zhi - z;
+            // column sums of the products over each window's rows
+            if (tid < EC * NVG) {
+                const int g = tid / EC, e = tid - g * EC;
+                double pr[VG + 2 * NW];
+#pragma unroll
+                for (int t = 0; t < VG + 2 * NW; ++t)
+                    pr[t] = (double)Ls[g * VG + t][e] * (double)Rs[g * VG + t][e + zz];
+                double s = 0.0;
+#pragma unroll
+                for (int t = 0; t <= 2 * NW; ++t) s += pr[t];
+                V[g * VG][e] = s;
+#pragma unroll
+                for (int t = 1; t < VG; ++t) {
+                    s += pr[t + 2 * NW] - pr[t - 1];
+                    V[g * VG + t][e] = s;
+                }
+            }
+            __syncthreads();
+            // row sums, then the scores of the region pixels
+            if (scorer) {
+                double s = 0.0;
+#pragma unroll
+                for (int b = 0; b <= 2 * NW; ++b) s += (su + b < EC) ? V[sy][su + b] : 0.0;
+#pragma unroll
+                for (int q = 0; q < RUN; ++q) {
+                    if (q > 0) {
+                        const int hi = su + q + 2 * NW;
+                        s += (hi < EC ? V[sy][hi] : 0.0) - V[sy][su + q - 1];
+                    }
+                    float e = 0.f;
+                    const bool valid = sxa[q] >= z;
+                    if (valid) {
+                        const int w = su + q + zz;
+                        const double c = s - NN * mul[q] * Smu[sy][w];
+                        double rho = c * (double)isl[q] * (double)Sis[sy][w];
+                        rho = fmin(1.0, fmax(-1.0, rho));
+                        e = (float)rho;
+                    }
+                    if constexpr (REPICK) {
+                        if (su + q < RC) Es[sy][su + q] = e;
+                    } else {
+                        // the scorer of (sy, su + q) owns it
+                        if (act[q] && valid && (double)e > best[q]) {
+                            best[q] = e;
+                            bz[q] = z;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            if constexpr (REPICK) {
+                // 5x5 sums of the scores (0 where a neighbour does not count)
+                const int c0 = ox[0], r0 = oy[0];
+                float rs[6];
+#pragma unroll
+                for (int t = 0; t < 6; ++t)
+                    rs[t] = Es[r0 + t][c0] + Es[r0 + t][c0 + 1] + Es[r0 + t][c0 + 2] + Es[r0 + t][c0 + 3] +
+                            Es[r0 + t][c0 + 4];
+                const float sum[2] = {rs[0] + rs[1] + rs[2] + rs[3] + rs[4], rs[1] + rs[2] + rs[3] + rs[4] + rs[5]};
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    const int j = x0 + ox[p];
+                    if (act[p] && z <= j) {
+                        const int cnt = rows_in[p] * (cols_r[p] + (j - 1 >= z) + (j - 2 >= z));
+                        const float ebar = sum[p] / (float)cnt;
+                        if ((double)ebar > best[p]) {
+                            best[p] = ebar;
+                            bz[p] = z;
+                        }
+                    }
+                }
+            }
+        }
+    }
+    for (int p = 0; p < 2; ++p) {
+        if (!act[p]) continue;
+        const size_t o = (size_t)(y0 + oy[p]) * a.opitch + (x0 + ox[p]);
+        a.d[o] = (int16_t)bz[p];
+        a.c[o] = (float)best[p];
+    }
+}
+
+template <typename T, bool REPICK>
+hipError_t launch_gate_t(int n, const GateArgs& a, hipStream_t s)
+{
+    dim3 grid((a.W + GT_W - 1) / GT_W, (a.H + GT_H - 1) / GT_H, 1);
+    switch (n) {
+        case 1: hipLaunchKernelGGL((gate_kernel<T, 1, REPICK>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((gate_kernel<T, 2, REPICK>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((gate_kernel<T, 3, REPICK>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((gate_kernel<T, 4, REPICK>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((gate_kernel<T, 5, REPICK>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((gate_kernel<T, 6, REPICK>), grid, dim3(GT_THREADS), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_gate(int n, int dtype, bool repick, const GateArgs& a, hipStream_t s)
+{
+    if (a.H < 1 || a.W < 1 || a.Dk < 1) return hipErrorInvalidValue;
+    if (!repick && (a.Hc != (a.H + 1) / 2 || a.Wc != (a.W + 1) / 2)) return hipErrorInvalidValue;
+    if (dtype == MSIBM_U8)
+        return repick ? launch_gate_t<uint8_t, true>(n, a, s) : launch_gate_t<uint8_t, false>(n, a, s);
+    return repick ? launch_gate_t<float, true>(n, a, s) : launch_gate_t<float, false>(n, a, s);
+}
+
+hipError_t launch_upsample_cost(const float* cc, int Hc, int Wc, int cpitch, int H, int W, double* out,
+                                int opitch, hipStream_t s)
+{
+    dim3 grid((W + 63) / 64, (H + 3) / 4, 1);
+    hipLaunchKernelGGL(upsample_kernel, grid, dim3(256), 0, s, cc, Hc, Wc, cpitch, H, W, out, opitch);
+    return hipGetLastError();
+}
+
+}  // namespace msibm

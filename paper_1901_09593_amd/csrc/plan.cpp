@@ -178,20 +178,56 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
         snprintf(lab, sizeof(lab), "match_%s_l%d",
                  mode == MODE_FULL ? "full" : (mode == MODE_SOFT ? "soft" : "refine"), k);
         // with the selective median, a hard level's map is matched into a
-        // scratch map and filtered into its place
+        // scratch map and filtered into its place; the gating keeps every
+        // level's cost (the next finer level reads it) and revises the map and
+        // cost in place before the filter
         int16_t* const dest = a.d_out;
         const bool filt = (cfg->flags & MSIBM_FLAG_MEDIAN) && mode != MODE_SOFT;
-        if (filt) {
-            a.d_out = (int16_t*)(ws + lay.dtmp);
-            if (!a.c_out) a.c_out = (float*)(ws + lay.ctmp);
-        }
+        const bool gated = (cfg->flags & MSIBM_FLAG_GATED) && mode != MODE_SOFT;
+        if (gated && k > 0) a.c_out = (float*)(ws + lay.cmap[k]);
+        if (filt) a.d_out = (int16_t*)(ws + lay.dtmp);
+        if ((filt || gated) && !a.c_out) a.c_out = (float*)(ws + lay.ctmp);
+        const int n = level_n(cfg, k);
         {
             TimedLaunch t(lab, s);
-            const int n = level_n(cfg, k);
             a.variant = select_variant(a, n, dtype_of(k), mode, nc, s);
             e = launch_match(n, dtype_of(k), mode, nc, a, s);
         }
         if (e != hipSuccess) return hip_err(e, "match launch", err);
+        if (gated) {
+            GateArgs g{};
+            g.L = a.L;
+            g.R = a.R;
+            g.pitch = a.pitch;
+            g.H = a.H;
+            g.W = a.W;
+            g.Dk = a.Dk;
+            g.statL = a.statL;
+            g.statR = a.statR;
+            g.spitch = a.spitch;
+            g.d = a.d_out;
+            g.c = a.c_out;
+            g.opitch = a.opitch;
+            char glab[32];
+            if (!coarsest) {
+                // Eqs. 8-9: the full search where the doubled coarser cost is low
+                g.ccost = (const float*)(ws + lay.cmap[k + 1]);
+                g.Hc = lay.h[k + 1];
+                g.Wc = lay.w[k + 1];
+                g.cpitch = lay.w[k + 1];
+                g.thresh = cfg->gate_beta;
+                snprintf(glab, sizeof(glab), "gate_full_l%d", k);
+                TimedLaunch t(glab, s);
+                e = launch_gate(n, dtype_of(k), false, g, s);
+                if (e != hipSuccess) return hip_err(e, "gated full search launch", err);
+            }
+            // Eqs. 5-7: the re-pick of low-cost pixels
+            g.thresh = cfg->gate_alpha;
+            snprintf(glab, sizeof(glab), "gate_repick_l%d", k);
+            TimedLaunch t(glab, s);
+            e = launch_gate(n, dtype_of(k), true, g, s);
+            if (e != hipSuccess) return hip_err(e, "re-pick launch", err);
+        }
         if (filt) {
             MedianArgs m{a.d_out, a.c_out, dest, lay.h[k], lay.w[k], lay.w[k], lay.w[k], lay.w[k],
                          (double)cfg->median_alpha};

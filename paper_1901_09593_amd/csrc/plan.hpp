@@ -31,11 +31,14 @@ struct PairLayout {
     size_t stat[MSIBM_MAX_LEVELS][2];
     size_t map[MSIBM_MAX_LEVELS];
     size_t blur[2];           // pre-blurred level 0 (float, pitch W), when asked for
-    size_t dtmp, ctmp;        // unfiltered map (int16) and cost (float) of a level, with the median
+    size_t cmap[MSIBM_MAX_LEVELS]; // levels k >= 1: the cost map (float), with the gating
+    size_t dtmp;              // unfiltered map of a level (int16), with the median
+    size_t ctmp;              // level 0's cost (float) when the caller takes none
     size_t bytes;
 };
 
-PairLayout pair_layout(const msibm_pair& p, int K, bool preblur = false, bool median = false);
+PairLayout pair_layout(const msibm_pair& p, int K, bool preblur = false, bool median = false,
+                       bool gated = false);
 
 struct BatchOutputs {
     int16_t* const* disp;

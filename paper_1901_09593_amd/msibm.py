@@ -26,6 +26,7 @@ FLAG_GRAPH = 2
 FLAG_PERSISTENT = 4  # switched off: calls with it fail with MsibmError
 FLAG_PREBLUR = 8     # plain forward: level 0 matched on the blurred input
 FLAG_MEDIAN = 16     # plain forward: selective median filter (Eq. 10) at every hard level
+FLAG_GATED = 32      # plain forward: confidence gating (Eqs. 5-9) at every hard level
 MAX_LEVELS = 8
 
 
@@ -51,7 +52,9 @@ class Config(ctypes.Structure):
                 ("var_eps", ctypes.c_float), ("soft_radius", ctypes.c_int32),
                 ("tau", ctypes.c_float), ("flags", ctypes.c_int32),
                 ("half_window_levels", ctypes.c_int32 * MAX_LEVELS),
-                ("median_alpha", ctypes.c_float)]
+                ("median_alpha", ctypes.c_float),
+                ("gate_alpha", ctypes.c_float),
+                ("gate_beta", ctypes.c_float)]
 
 
 _lib = None
@@ -76,6 +79,16 @@ def lib() -> ctypes.CDLL:
         L.msibm_median_filter.argtypes = [_VP, _I32, _VP, _I32, _I32, _I32, ctypes.c_double, _VP,
                                           _I32, _VP]
         L.msibm_median_filter.restype = _I32
+        L.msibm_upsample_cost.argtypes = [_VP, _I32, _I32, _I32, _I32, _I32, _VP, _I32, _VP]
+        L.msibm_upsample_cost.restype = _I32
+        L.msibm_match_level_gated.argtypes = [_VP, _VP, _I32, _I32, _I32, _I32, _I32, _I32, _VP, _VP,
+                                              _I32, _I32, _I32, _I32, ctypes.c_double, ctypes.c_float,
+                                              _VP, _VP, _I32, _VP, ctypes.c_size_t, _VP]
+        L.msibm_match_level_gated.restype = _I32
+        L.msibm_aggregate_refine.argtypes = [_VP, _VP, _I32, _I32, _I32, _I32, _I32, _I32, _VP, _VP,
+                                             _I32, ctypes.c_double, ctypes.c_float, _VP, ctypes.c_size_t,
+                                             _VP]
+        L.msibm_aggregate_refine.restype = _I32
         L.msibm_level_workspace_size.argtypes = [_I32, _I32]
         L.msibm_level_workspace_size.restype = ctypes.c_size_t
         L.msibm_match_level.argtypes = [_VP, _VP, _I32, _I32, _I32, _I32, _I32, _I32, _VP, _I32,
@@ -163,21 +176,28 @@ def auto_levels(D: int) -> int:
 
 
 def make_config(n, r: int, var_eps: float, soft_radius: int = 0, tau: float = 0.05,
-                flags: int = 0, median_alpha: Optional[float] = None) -> Config:
+                flags: int = 0, median_alpha: Optional[float] = None,
+                gate: Optional[Tuple[float, float]] = None) -> Config:
     """n: the window half-width, or a sequence of per-level half-widths (level 0
     first; levels past its end keep its last entry).  median_alpha: switch on the
-    selective median filter with that threshold."""
+    selective median filter with that threshold.  gate = (alpha, beta): switch on
+    the confidence gating with those thresholds."""
     if median_alpha is not None:
         flags |= FLAG_MEDIAN
+    if gate is not None:
+        flags |= FLAG_GATED
     alpha = float(median_alpha) if median_alpha is not None else 0.0
+    ga, gb = (float(gate[0]), float(gate[1])) if gate is not None else (0.0, 0.0)
     if isinstance(n, int):
-        return Config(n, r, float(var_eps), soft_radius, float(tau), flags, (ctypes.c_int32 * MAX_LEVELS)(),
-                      alpha)
-    ns = [int(v) for v in n]
-    if not ns or len(ns) > MAX_LEVELS:
-        raise ValueError(f"1..{MAX_LEVELS} per-level half-widths")
-    per = (ctypes.c_int32 * MAX_LEVELS)(*(ns + [ns[-1]] * (MAX_LEVELS - len(ns))))
-    return Config(ns[0], r, float(var_eps), soft_radius, float(tau), flags, per, alpha)
+        per = (ctypes.c_int32 * MAX_LEVELS)()
+        n0 = n
+    else:
+        ns = [int(v) for v in n]
+        if not ns or len(ns) > MAX_LEVELS:
+            raise ValueError(f"1..{MAX_LEVELS} per-level half-widths")
+        per = (ctypes.c_int32 * MAX_LEVELS)(*(ns + [ns[-1]] * (MAX_LEVELS - len(ns))))
+        n0 = ns[0]
+    return Config(n0, r, float(var_eps), soft_radius, float(tau), flags, per, alpha, ga, gb)
 
 
 def force_variant(v: int = -1):
@@ -281,6 +301,62 @@ def median_filter(d: torch.Tensor, cost: torch.Tensor, alpha: float) -> torch.Te
     return out
 
 
+def upsample_cost(coarse: torch.Tensor, H: int, W: int) -> torch.Tensor:
+    """The bicubic doubling (float64, H x W) of a coarser float cost map."""
+    coarse = coarse.contiguous()
+    out = torch.empty((H, W), dtype=torch.float64, device=coarse.device)
+    _check(lib().msibm_upsample_cost(_ptr(coarse), coarse.shape[0], coarse.shape[1], coarse.stride(0), H, W,
+                                     _ptr(out), W, _stream(coarse.device)))
+    return out
+
+
+def match_level_gated(L: torch.Tensor, R: torch.Tensor, n: int, Dk: int, prior: torch.Tensor,
+                      prior_cost: torch.Tensor, r: int, beta: float, var_eps: float):
+    """Eqs. 8-9: the restricted search around the doubled prior, the full search
+    where the bicubic-doubled prior cost is <= beta.  Returns (d, C)."""
+    L = _image(L)
+    R = _image(R)
+    if L.shape != R.shape or L.dtype != R.dtype or L.stride(0) != R.stride(0):
+        raise ValueError("left and right must share shape, dtype and pitch")
+    prior = prior.contiguous()
+    prior_cost = prior_cost.contiguous()
+    if prior.shape != prior_cost.shape or prior_cost.dtype != torch.float32:
+        raise ValueError("prior and prior_cost: one shape, int16 and float")
+    H, W = L.shape
+    dev = L.device
+    d = torch.empty((H, W), dtype=torch.int16, device=dev)
+    C = torch.empty((H, W), dtype=torch.float32, device=dev)
+    ws_bytes = lib().msibm_level_workspace_size(H, W)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    _check(lib().msibm_match_level_gated(_ptr(L), _ptr(R), _dtype_code(L), H, W, L.stride(0), n, Dk,
+                                         _ptr(prior), _ptr(prior_cost), prior.shape[0], prior.shape[1],
+                                         prior.stride(0), r, float(beta), float(var_eps), _ptr(d), _ptr(C), W,
+                                         _ptr(ws), ws_bytes, _stream(dev)))
+    return d, C
+
+
+def aggregate_refine(L: torch.Tensor, R: torch.Tensor, n: int, Dk: int, d: torch.Tensor, C: torch.Tensor,
+                     alpha: float, var_eps: float):
+    """Eqs. 5-7 on copies of (d, C): pixels with C <= alpha re-picked by the
+    5x5-averaged scores.  Returns the new (d, C)."""
+    L = _image(L)
+    R = _image(R)
+    if L.shape != R.shape or L.dtype != R.dtype or L.stride(0) != R.stride(0):
+        raise ValueError("left and right must share shape, dtype and pitch")
+    H, W = L.shape
+    dev = L.device
+    d = d.to(torch.int16).contiguous().clone()
+    C = C.to(torch.float32).contiguous().clone()
+    if d.shape != (H, W) or C.shape != (H, W):
+        raise ValueError("map and cost must have the image's shape")
+    ws_bytes = lib().msibm_level_workspace_size(H, W)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    _check(lib().msibm_aggregate_refine(_ptr(L), _ptr(R), _dtype_code(L), H, W, L.stride(0), n, Dk, _ptr(d),
+                                        _ptr(C), W, float(alpha), float(var_eps), _ptr(ws), ws_bytes,
+                                        _stream(dev)))
+    return d, C
+
+
 def _pairs(lefts, rights, Ds, Ks) -> Tuple[ctypes.Array, list]:
     n = len(lefts)
     arr = (Pair * n)()
@@ -306,15 +382,17 @@ def workspace_bytes(pairs_arr, n: int, cfg: Config) -> int:
 def disparity(L: torch.Tensor, R: torch.Tensor, D: int, K: int, n: int, r: int, var_eps: float,
               soft_radius: int = 0, tau: float = 0.05, with_cost: bool = True,
               with_prior1: bool = False, preblur: bool = False,
-              median_alpha: Optional[float] = None) -> Dict[str, torch.Tensor]:
+              median_alpha: Optional[float] = None,
+              gate: Optional[Tuple[float, float]] = None) -> Dict[str, torch.Tensor]:
     """Hierarchical forward pass of one pair.  Returns a dict with 'disp'
     (int16), 'cost' (float, optional), 'soft' (float, if soft_radius > 0) and
     'prior1' (int16 level-1 map, if requested or soft).  preblur: match level 0
     on the input blurred with the pyramid's kernel.  median_alpha: run the
-    selective median filter with that threshold after every hard level."""
+    selective median filter with that threshold after every hard level.
+    gate = (alpha, beta): the confidence gating of Eqs. 5-9 at every hard level."""
     out = disparity_many([L], [R], [D], [K], n, r, var_eps, soft_radius, tau, with_cost,
                          with_prior1, flags=FLAG_PREBLUR if preblur else 0,
-                         median_alpha=median_alpha)
+                         median_alpha=median_alpha, gate=gate)
     return out[0]
 
 
@@ -323,13 +401,14 @@ def disparity_many(lefts: Sequence[torch.Tensor], rights: Sequence[torch.Tensor]
                    tau: float = 0.05, with_cost: bool = True, with_prior1: bool = False,
                    flags: int = 0, workspace: Optional[torch.Tensor] = None,
                    outputs: Optional[List[Dict[str, torch.Tensor]]] = None,
-                   median_alpha: Optional[float] = None) -> List[Dict[str, torch.Tensor]]:
+                   median_alpha: Optional[float] = None,
+                   gate: Optional[Tuple[float, float]] = None) -> List[Dict[str, torch.Tensor]]:
     """Forward pass of several pairs in one call (flags: FLAG_BATCHED, FLAG_GRAPH,
     or FLAG_PREBLUR / a median_alpha on the plain path).
     `workspace` and `outputs` may be passed in to reuse buffers across calls."""
     pairs, keep = _pairs(lefts, rights, Ds, Ks)
     npair = len(lefts)
-    cfg = make_config(n, r, var_eps, soft_radius, tau, flags, median_alpha)
+    cfg = make_config(n, r, var_eps, soft_radius, tau, flags, median_alpha, gate)
     ws_bytes = workspace_bytes(pairs, npair, cfg)
     dev = lefts[0].device
     if workspace is None or workspace.numel() < ws_bytes:

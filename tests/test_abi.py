@@ -110,6 +110,32 @@ def test_config_and_pair_validation(lib):
     assert e.msibm_median_filter(fake, 8, fake, 8, 8, 8, 0.5, fake, 8, None) == -1
     assert e.msibm_median_filter(fake, 8, fake, 8, 8, 8, float("nan"), ctypes.c_void_p(0x9000000), 8,
                                  None) == -1
+    # the confidence gating: plain path only, finite thresholds, a cost map per level
+    gated = msibm.make_config(3, 2, 0.065, gate=(0.9, 0.9))
+    assert gated.flags & msibm.FLAG_GATED
+    assert e.msibm_workspace_size(arr, 1, ctypes.byref(gated)) > e.msibm_workspace_size(arr, 1, ctypes.byref(good))
+    for bad in (msibm.make_config(3, 2, 0.065, flags=msibm.FLAG_BATCHED, gate=(0.9, 0.9)),
+                msibm.make_config(3, 2, 0.065, gate=(0.9, float("nan")))):
+        assert e.msibm_workspace_size(arr, 1, ctypes.byref(bad)) == 0
+        rc = e.msibm_disparity(arr, 1, ctypes.byref(bad), disp_probe, None, None, None, None, 0, None)
+        assert rc in (-1, -4) and b"gat" in e.msibm_last_error().lower()
+    far = ctypes.c_void_p(0x9000000)
+    assert e.msibm_upsample_cost(None, 2, 2, 2, 4, 4, far, 4, None) == -1
+    assert e.msibm_upsample_cost(fake, 3, 2, 2, 4, 4, far, 4, None) == -2
+    assert e.msibm_upsample_cost(fake, 2, 2, 2, 4, 4, far, 3, None) == -2
+    ws = ctypes.c_void_p(0x4000000)
+    assert e.msibm_match_level_gated(fake, fake, 0, 8, 8, 8, 2, 4, None, fake, 4, 4, 4, 1, 0.9, 0.065, far, far,
+                                     8, ws, 10 ** 6, None) == -1
+    assert e.msibm_match_level_gated(fake, fake, 0, 8, 8, 8, 2, 4, fake, fake, 4, 4, 4, 1, float("inf"), 0.065,
+                                     far, far, 8, ws, 10 ** 6, None) == -1
+    assert e.msibm_match_level_gated(fake, fake, 0, 8, 8, 8, 2, 4, fake, fake, 3, 4, 4, 1, 0.9, 0.065, far, far,
+                                     8, ws, 10 ** 6, None) == -2
+    assert e.msibm_aggregate_refine(fake, fake, 0, 8, 8, 8, 2, 4, far, None, 8, 0.9, 0.065, ws, 10 ** 6,
+                                    None) == -1
+    assert e.msibm_aggregate_refine(fake, fake, 0, 8, 8, 8, 9, 4, far, far, 8, 0.9, 0.065, ws, 10 ** 6,
+                                    None) == -4
+    assert e.msibm_aggregate_refine(fake, fake, 0, 8, 8, 8, 2, 4, far, far, 8, 0.9, 0.065, ws, 10,
+                                    None) == -3
     # the soft level needs float images
     soft = msibm.make_config(3, 2, 0.065, 3, 0.05)
     assert e.msibm_workspace_size(arr, 1, ctypes.byref(soft)) == 0

@@ -575,3 +575,18 @@ def test_gated_hierarchy_limits():
     d, C, _ = oracle.aggregate(PL[0], PR[0], n, D, d1, C1, 0.9, eps)
     assert np.array_equal(d, g[0][0]) and np.array_equal(C, g[0][1])
     assert (d != d1).any()
+
+
+def test_aggregate_pixel_list_and_scores_agree_with_the_map():
+    rng = _rng(36)
+    H, W, D, n = 10, 15, 7, 1
+    L = rng.random((H, W))
+    R = rng.random((H, W))
+    d1, C1, _ = oracle.match_level(L, R, n, D, None, 0, 1e-9)
+    d, C, C2 = oracle.aggregate(L, R, n, D, d1, C1, 0.5, 1e-9)
+    ii, jj = np.nonzero(np.ones((H, W), bool))
+    pd, pC, pC2 = oracle.aggregate_pixels(L, R, n, D, d1, C1, 0.5, 1e-9, ii, jj)
+    assert np.array_equal(pd, d.ravel()) and np.array_equal(pC, C.ravel()) and np.array_equal(pC2, C2.ravel())
+    picked = ~(C1 > 0.5)
+    s = oracle.avg_score_many(L, R, n, ii[picked.ravel()], jj[picked.ravel()], d[picked], 1e-9)
+    np.testing.assert_array_equal(s, C[picked])
