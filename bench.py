@@ -42,6 +42,7 @@ PEAK_FP32_UNPACKED = CU * SIMD_PER_CU * LANES * 2 * CLOCK_HZ / 1e12   # 78.6 TFL
 PEAK_FP32_PUBLISHED = 157.3                                           # packed dual-issue figure
 PEAK_HBM = 8000.0                                                     # GB/s
 MEDIAN_ALPHA = 0.9  # the threshold of the selective median filter that Section IV reports
+GATE_ALPHA = GATE_BETA = 0.9  # the gating thresholds Section IV reports
 
 METRIC = "pixel-disparity ZNCC evals/s + ms/pair, batched vs plain; fwd+bwd ms"
 DOMINANT = "match_refine_l0"
@@ -214,33 +215,38 @@ def section_accuracy(torch, M, synth, steps):
         vis = p.nonocc.copy()
         vis[:b, :] = vis[H - b:, :] = False
         vis[:, :b] = vis[:, W - b:] = False
+        gate = (GATE_ALPHA, GATE_BETA)
         runs = {
-            "hierarchy": dict(n=n, r=r, preblur=False, K=K, alpha=None),
-            "hierarchy_median": dict(n=n, r=r, preblur=False, K=K, alpha=MEDIAN_ALPHA),
-            "paper_parameters": dict(n=halving, r=1, preblur=True, K=K, alpha=MEDIAN_ALPHA),
-            "flat_block_matching": dict(n=n, r=0, preblur=False, K=1, alpha=None),
+            "hierarchy": dict(n=n, r=r, preblur=False, K=K, alpha=None, gate=None),
+            "hierarchy_median": dict(n=n, r=r, preblur=False, K=K, alpha=MEDIAN_ALPHA, gate=None),
+            "hierarchy_gated": dict(n=n, r=r, preblur=False, K=K, alpha=None, gate=gate),
+            "hierarchy_gated_median": dict(n=n, r=r, preblur=False, K=K, alpha=MEDIAN_ALPHA, gate=gate),
+            "paper_parameters": dict(n=halving, r=1, preblur=True, K=K, alpha=MEDIAN_ALPHA, gate=gate),
+            "flat_block_matching": dict(n=n, r=0, preblur=False, K=1, alpha=None, gate=None),
         }
         out = {"workload": f"{W}x{H} uint8 pair ({name}), D={D}", "pixels_scored": int(vis.sum()),
                "paper_parameters": f"refine +-1, windows {[2 * v + 1 for v in halving]} by level, level 0 "
-                                   f"pre-blurred, selective median at alpha {MEDIAN_ALPHA}"}
+                                   f"pre-blurred, gating alpha {GATE_ALPHA} beta {GATE_BETA}, selective "
+                                   f"median at alpha {MEDIAN_ALPHA}"}
         for label, c in runs.items():
             def fwd():
                 return M.disparity(Lg, Rg, D, c["K"], c["n"], c["r"], eps, preblur=c["preblur"],
-                                   median_alpha=c["alpha"])
+                                   median_alpha=c["alpha"], gate=c["gate"])
             d = fwd()["disp"].cpu().numpy().astype(np.float64)
             err = np.abs(d - p.disp)[vis]
             ms = time_ms(torch, fwd, steps, 2)
             out[label] = {"mean_abs_err_px": float(err.mean()), "bad_1px": float((err > 1).mean()),
                           "bad_2px": float((err > 2).mean()), "ms_per_pair": ms}
-            if label == "hierarchy_median":
+            if label in ("hierarchy_median", "hierarchy_gated"):
                 M.timing_enable(True)
                 for _ in range(steps):
                     fwd()
                 torch.cuda.synchronize()
                 tim = M.timing_read()
                 M.timing_enable(False)
-                tot, cnt = tim["median_l0"]
-                us = 1e3 * tot / cnt
+                out[label]["kernels_us"] = {k: 1e3 * v[0] / v[1] for k, v in sorted(tim.items())}
+            if label == "hierarchy_median":
+                us = out[label]["kernels_us"]["median_l0"]
                 out["median_l0_kernel"] = {"avg_us": us, "GB_per_s": 8.0 * H * W / (us * 1e-6) / 1e9,
                                            "frac_of_hbm_peak": 8.0 * H * W / (us * 1e-6) / 1e9 / PEAK_HBM}
         res[name] = out

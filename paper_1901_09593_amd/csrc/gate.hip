@@ -81,8 +81,11 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
     constexpr double NN = (double)((2 * NW + 1) * (2 * NW + 1));
     constexpr int VG = 4;                              // rows of column sums per thread
     constexpr int NVG = RR / VG;
-    constexpr int RUN = REPICK ? 4 : 2;                // region columns scored per thread
+    // region columns scored per thread: an odd run keeps the lanes' row-sum
+    // reads (stride RUN doubles) on distinct LDS banks
+    constexpr int RUN = REPICK ? 5 : 3;
     constexpr int NRUN = (RC + RUN - 1) / RUN;
+    constexpr int OWN = REPICK ? 2 : RUN;              // output pixels per thread
     static_assert(RR % VG == 0, "row groups");
     static_assert(EC * NVG <= GT_THREADS && RR * NRUN <= GT_THREADS, "one item per thread");
 
@@ -100,27 +103,35 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
     const int ey0 = ry0 - NW, ex0 = rx0 - NW;          // extended origin
     const int H = a.H, W = a.W;
 
+    // the region pixels this thread scores: row sy, columns su .. su + RUN - 1
+    const int sy = tid / NRUN, su = (tid - sy * NRUN) * RUN;
+    const bool scorer = tid < RR * NRUN;
+
     // owned output pixels: the re-pick gives thread t column t % 64 and rows
     // 2 (t / 64) + {0, 1}; the full search owns the pixels it scores itself
-    int oy[2], ox[2];
-    if constexpr (REPICK) {
-        ox[0] = ox[1] = tid & 63;
-        oy[0] = 2 * (tid >> 6);
-        oy[1] = oy[0] + 1;
-    } else {
-        oy[0] = oy[1] = tid >> 5;
-        ox[0] = 2 * (tid & 31);
-        ox[1] = ox[0] + 1;
+    int oy[OWN], ox[OWN];
+#pragma unroll
+    for (int p = 0; p < OWN; ++p) {
+        if constexpr (REPICK) {
+            ox[p] = tid & 63;
+            oy[p] = 2 * (tid >> 6) + p;
+        } else {
+            oy[p] = scorer ? sy : GT_H;  // GT_H: owns nothing
+            ox[p] = su + p;
+        }
     }
-    bool act[2];
-    double best[2] = {-1e300, -1e300};
-    int bz[2] = {0, 0};
+    bool act[OWN];
+    double best[OWN];
+    int bz[OWN];
     if (tid == 0) s_xmax = -1;
     __syncthreads();
-    for (int p = 0; p < 2; ++p) {
+#pragma unroll
+    for (int p = 0; p < OWN; ++p) {
         const int i = y0 + oy[p], j = x0 + ox[p];
         act[p] = false;
-        if (i < H && j < W) {
+        best[p] = -1e300;
+        bz[p] = 0;
+        if (oy[p] < GT_H && ox[p] < GT_W && i < H && j < W) {
             if constexpr (REPICK)
                 act[p] = !((double)a.c[(size_t)i * a.opitch + j] > a.thresh);
             else
@@ -138,9 +149,7 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
         Ls[v][e] = pix<T>(a.L, a.pitch, clampi(ey0 + v, 0, H - 1), clampi(ex0 + e, 0, W - 1));
     }
 
-    // the region pixels this thread scores, with their left statistics
-    const int sy = tid / NRUN, su = (tid - sy * NRUN) * RUN;
-    const bool scorer = tid < RR * NRUN;
+    // left statistics of the scored region pixels
     double mul[RUN];
     float isl[RUN];
     int sxa[RUN];     // region pixel column, or -1 outside the image
@@ -159,8 +168,9 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
     }
     // neighbours of an owned pixel inside the image: rows, and columns at or
     // right of it (every z <= j is a candidate of those)
-    int rows_in[2], cols_r[2];
-    for (int p = 0; p < 2; ++p) {
+    int rows_in[OWN], cols_r[OWN];
+#pragma unroll
+    for (int p = 0; p < OWN; ++p) {
         const int i = y0 + oy[p], j = x0 + ox[p];
         rows_in[p] = min(i + 2, H - 1) - max(i - 2, 0) + 1;
         cols_r[p] = min(j + 2, W - 1) - j + 1;
@@ -258,7 +268,8 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
             }
         }
     }
-    for (int p = 0; p < 2; ++p) {
+#pragma unroll
+    for (int p = 0; p < OWN; ++p) {
         if (!act[p]) continue;
         const size_t o = (size_t)(y0 + oy[p]) * a.opitch + (x0 + ox[p]);
         a.d[o] = (int16_t)bz[p];
