@@ -253,6 +253,62 @@ def section_accuracy(torch, M, synth, steps):
     return res
 
 
+def section_gated(torch, M, synth, steps):
+    """The paper's confidence gating (Eqs. 5-9) on the 1436x992 pair: time per
+    pair, per-kernel times, and the work of the two level-0 gate launches.  A
+    gate launch scores, for every tile (8 x 64 pixels) holding a gated pixel,
+    every region pixel (the tile, plus a 2-pixel ring for the re-pick) at every
+    candidate up to the tile's last gated column's range; the scores per launch
+    are counted here from the same inputs the launch sees."""
+    dev = torch.device("cuda:0")
+    p, cfg = synth.workload("mid1436")
+    H, W, D, K, n, r, eps = cfg.height, cfg.width, cfg.max_disp, cfg.levels, cfg.half_window, \
+        cfg.refine_radius, cfg.var_eps
+    gate = (GATE_ALPHA, GATE_BETA)
+    Lg, Rg = torch.from_numpy(p.left).to(dev), torch.from_numpy(p.right).to(dev)
+
+    def fwd():
+        return M.disparity(Lg, Rg, D, K, n, r, eps, gate=gate)
+    out = fwd()
+    ms = time_ms(torch, fwd, steps, 2)
+    M.timing_enable(True)
+    for _ in range(steps):
+        fwd()
+    torch.cuda.synchronize()
+    tim = M.timing_read()
+    M.timing_enable(False)
+    kern = {k: 1e3 * v[0] / v[1] for k, v in sorted(tim.items())}
+    # the level-0 launches' inputs: level 1's map and Eq. 7 cost, then the gated search
+    PL, PR = M.pyramid(Lg, 2), M.pyramid(Rg, 2)
+    lvl1 = M.disparity(PL[1], PR[1], -(-D // 2), K - 1, n, r, eps, gate=gate)
+    assert torch.equal(lvl1["disp"], M.disparity(Lg, Rg, D, K, n, r, eps, gate=gate, with_prior1=True)["prior1"])
+    up = M.upsample_cost(lvl1["cost"], H, W)
+    d1, C1 = M.match_level_gated(Lg, Rg, n, D, lvl1["disp"], lvl1["cost"], r, gate[1], eps)
+    full_mask = (~(up > gate[1])).cpu().numpy()
+    pick_mask = (~(C1.double() > gate[0])).cpu().numpy()
+
+    def scores(mask, halo):
+        th, tw = 8, 64
+        total = 0
+        for y0 in range(0, H, th):
+            for x0 in range(0, W, tw):
+                m = mask[y0:y0 + th, x0:x0 + tw]
+                if not m.any():
+                    continue
+                xmax = x0 + int(np.nonzero(m.any(axis=0))[0].max())
+                total += (th + 2 * halo) * (tw + 2 * halo) * (min(D - 1, xmax) + 1)
+        return total
+    res = {"workload": f"{W}x{H} uint8 pair (mid1436), K={K}, {2 * n + 1}x{2 * n + 1} ZNCC, D={D}, "
+                       f"refine +-{r}, gating alpha {gate[0]} beta {gate[1]}",
+           "ms_per_pair": ms, "kernels_us": kern,
+           "level0_full_search_fraction": float(full_mask.mean()), "level0_repick_fraction": float(pick_mask.mean())}
+    for label, mask, halo in (("gate_full_l0", full_mask, 0), ("gate_repick_l0", pick_mask, 2)):
+        sc = scores(mask, halo)
+        us = kern[label]
+        res[label] = {"avg_us": us, "region_scores_per_launch": sc, "scores_per_s": sc / (us * 1e-6)}
+    return res
+
+
 def section_fwd_bwd(torch, M, synth, name, count, steps):
     """Forward + masked mean-L1 loss gradient + backward for `count` float pairs."""
     dev = torch.device("cuda:0")
@@ -339,8 +395,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="batched,fwd_bwd,accuracy",
-                    help="extra sections beside the headline step: batched, fwd_bwd, accuracy, or none")
+    ap.add_argument("--sections", default="batched,fwd_bwd,accuracy,gated",
+                    help="extra sections beside the headline step: batched, fwd_bwd, accuracy, gated, or none")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the default kernel shapes instead of measuring them first")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -456,6 +512,8 @@ def main():
 
     if "accuracy" in sections:
         extra["accuracy"] = section_accuracy(torch, msibm, synth, nsteps)
+    if "gated" in sections:
+        extra["gated"] = section_gated(torch, msibm, synth, nsteps)
 
     # the FP64 oracle on the host cores: whole pairs until the time budget is used
     cpu = None

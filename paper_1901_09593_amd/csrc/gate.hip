@@ -11,11 +11,17 @@
 //   V(y, e) = sum over the 2n+1 window rows of L(v, e) R(v, e - z)   (columns)
 //   S(y, u) = sum over the 2n+1 window columns of V                  (rows)
 // so a score costs O(1) instead of O((2n+1)^2) multiply-adds.  The sums run in
-// double: with the window means of the statistics kernel the cross term is
+// double for float levels; for a uint8 level every product (<= 255^2), column
+// sum (<= 13 products) and row sum (<= 13 column sums, below 2^24) is an
+// integer that float holds exactly, so those sums run in float at no loss.
+// With the window means of the statistics kernel the cross term is
 //   C = S - N mu_l mu_r   (= sum (l - mu_l)(r - mu_r))
-// whose cancellation double absorbs, and rho = C * invsd_l * invsd_r clamped to
-// [-1, 1], 0 for a flat window (invsd = 0).  Tiles without a gated pixel leave
+// formed in double (its cancellation is what needs the precision), and
+// rho = C * invsd_l * invsd_r clamped to [-1, 1], 0 for a flat window
+// (invsd = 0).  Tiles without a gated pixel leave
 // at once; the z range stops at the rightmost gated pixel's last candidate.
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace msibm {
@@ -86,12 +92,14 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
     constexpr int RUN = REPICK ? 5 : 3;
     constexpr int NRUN = (RC + RUN - 1) / RUN;
     constexpr int OWN = REPICK ? 2 : RUN;              // output pixels per thread
+    // box-sum type: exact float sums of integer products for uint8 levels
+    using acc_t = typename std::conditional<std::is_same<T, uint8_t>::value, float, double>::type;
     static_assert(RR % VG == 0, "row groups");
     static_assert(EC * NVG <= GT_THREADS && RR * NRUN <= GT_THREADS, "one item per thread");
 
     __shared__ float Ls[ER][EC];
     __shared__ float Rs[ER][RSW];
-    __shared__ double V[RR][EC];
+    __shared__ acc_t V[RR][EC];
     __shared__ double Smu[RR][SSW];
     __shared__ float Sis[RR][SSW];
     __shared__ float Es[REPICK ? RR : 1][REPICK ? RC : 1];
@@ -149,8 +157,8 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
         Ls[v][e] = pix<T>(a.L, a.pitch, clampi(ey0 + v, 0, H - 1), clampi(ex0 + e, 0, W - 1));
     }
 
-    // left statistics of the scored region pixels
-    double mul[RUN];
+    // left statistics of the scored region pixels (N mu_l, 1/sqrt(A_l))
+    double nmul[RUN];
     float isl[RUN];
     int sxa[RUN];     // region pixel column, or -1 outside the image
 #pragma unroll
@@ -158,22 +166,26 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
         const int yy = ry0 + sy, xx = rx0 + su + q;
         const bool in = scorer && su + q < RC && yy >= 0 && yy < H && xx >= 0 && xx < W;
         sxa[q] = in ? xx : -1;
-        mul[q] = 0.0;
+        nmul[q] = 0.0;
         isl[q] = 0.f;
         if (in) {
             const WinStat st = a.statL[(size_t)yy * a.spitch + xx];
-            mul[q] = (double)st.x + (double)st.y;
+            nmul[q] = NN * ((double)st.x + (double)st.y);
             isl[q] = st.z;
         }
     }
     // neighbours of an owned pixel inside the image: rows, and columns at or
     // right of it (every z <= j is a candidate of those)
-    int rows_in[OWN], cols_r[OWN];
+    // (reciprocal counts for 2, 1 and 0 contributing columns left of the pixel)
+    float rcp5[OWN], rcp4[OWN], rcp3[OWN];
 #pragma unroll
     for (int p = 0; p < OWN; ++p) {
         const int i = y0 + oy[p], j = x0 + ox[p];
-        rows_in[p] = min(i + 2, H - 1) - max(i - 2, 0) + 1;
-        cols_r[p] = min(j + 2, W - 1) - j + 1;
+        const int rows_in = min(i + 2, H - 1) - max(i - 2, 0) + 1;
+        const int cols_r = min(j + 2, W - 1) - j + 1;
+        rcp5[p] = 1.f / (float)(rows_in * (cols_r + 2));
+        rcp4[p] = 1.f / (float)(rows_in * (cols_r + 1));
+        rcp3[p] = 1.f / (float)(rows_in * cols_r);
     }
 
     for (int z0 = 0; z0 <= zmax; z0 += GT_ZC) {
@@ -197,11 +209,11 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
             // column sums of the products over each window's rows
             if (tid < EC * NVG) {
                 const int g = tid / EC, e = tid - g * EC;
-                double pr[VG + 2 * NW];
+                acc_t pr[VG + 2 * NW];
 #pragma unroll
                 for (int t = 0; t < VG + 2 * NW; ++t)
-                    pr[t] = (double)Ls[g * VG + t][e] * (double)Rs[g * VG + t][e + zz];
-                double s = 0.0;
+                    pr[t] = (acc_t)Ls[g * VG + t][e] * (acc_t)Rs[g * VG + t][e + zz];
+                acc_t s = 0;
 #pragma unroll
                 for (int t = 0; t <= 2 * NW; ++t) s += pr[t];
                 V[g * VG][e] = s;
@@ -214,23 +226,23 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
             __syncthreads();
             // row sums, then the scores of the region pixels
             if (scorer) {
-                double s = 0.0;
+                acc_t s = 0;
 #pragma unroll
-                for (int b = 0; b <= 2 * NW; ++b) s += (su + b < EC) ? V[sy][su + b] : 0.0;
+                for (int b = 0; b <= 2 * NW; ++b) s += (su + b < EC) ? V[sy][su + b] : (acc_t)0;
 #pragma unroll
                 for (int q = 0; q < RUN; ++q) {
                     if (q > 0) {
                         const int hi = su + q + 2 * NW;
-                        s += (hi < EC ? V[sy][hi] : 0.0) - V[sy][su + q - 1];
+                        s += (hi < EC ? V[sy][hi] : (acc_t)0) - V[sy][su + q - 1];
                     }
                     float e = 0.f;
                     const bool valid = sxa[q] >= z;
                     if (valid) {
+                        // C in double; its float rounding (relative 6e-8) is
+                        // far below the score tolerance
                         const int w = su + q + zz;
-                        const double c = s - NN * mul[q] * Smu[sy][w];
-                        double rho = c * (double)isl[q] * (double)Sis[sy][w];
-                        rho = fmin(1.0, fmax(-1.0, rho));
-                        e = (float)rho;
+                        const float c = (float)fma(-nmul[q], Smu[sy][w], (double)s);
+                        e = fminf(1.f, fmaxf(-1.f, c * isl[q] * Sis[sy][w]));
                     }
                     if constexpr (REPICK) {
                         if (su + q < RC) Es[sy][su + q] = e;
@@ -257,8 +269,9 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
                 for (int p = 0; p < 2; ++p) {
                     const int j = x0 + ox[p];
                     if (act[p] && z <= j) {
-                        const int cnt = rows_in[p] * (cols_r[p] + (j - 1 >= z) + (j - 2 >= z));
-                        const float ebar = sum[p] / (float)cnt;
+                        // the count changes only where z passes j - 2 and j - 1
+                        const float rc = (z <= j - 2) ? rcp5[p] : (z == j - 1 ? rcp4[p] : rcp3[p]);
+                        const float ebar = sum[p] * rc;
                         if ((double)ebar > best[p]) {
                             best[p] = ebar;
                             bz[p] = z;
