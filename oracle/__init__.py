@@ -59,6 +59,8 @@ def _load():
         c_int, c_double = ctypes.c_int, ctypes.c_double
         lib.orc_reduce.argtypes = [_D, c_int, c_int, _D]
         lib.orc_reduce.restype = None
+        lib.orc_reduce_adjoint.argtypes = [_D, c_int, c_int, _D]
+        lib.orc_reduce_adjoint.restype = None
         lib.orc_blur.argtypes = [_D, c_int, c_int, _D]
         lib.orc_blur.restype = None
         lib.orc_median.argtypes = [_I16, _D, c_int, c_int, c_double, _I16]
@@ -131,6 +133,16 @@ def blur(img: np.ndarray) -> np.ndarray:
     H, W = x.shape
     out = np.empty((H, W), dtype=np.float64)
     _load().orc_blur(_p(x, _D), H, W, _p(out, _D))
+    return out
+
+
+def reduce_adjoint(G: np.ndarray, H: int, W: int) -> np.ndarray:
+    """The transpose of reduce(): an H x W gradient from the ceil(H/2) x ceil(W/2)
+    gradient of the reduced image."""
+    GG = _f64(G)
+    assert GG.shape == ((H + 1) // 2, (W + 1) // 2)
+    out = np.empty((H, W), dtype=np.float64)
+    _load().orc_reduce_adjoint(_p(GG, _D), H, W, _p(out, _D))
     return out
 
 
@@ -428,3 +440,42 @@ def l1_loss(dsoft: np.ndarray, dgt: np.ndarray, mask: np.ndarray):
     loss = float(np.abs(diff[mask]).sum() / max(cnt, 1))
     g = np.where(mask, np.sign(diff), 0.0) / max(cnt, 1)
     return loss, g
+
+
+def soft_levels(left: np.ndarray, right: np.ndarray, D: int, K: int, n: int, rs: int, tau: float,
+                eps: float):
+    """Soft output at every level below the coarsest (an extension of the
+    paper): the coarsest level is the hard full search; every finer level k takes
+    the soft-argmax over the radius-rs interval around the doubled hard map of
+    level k+1, and its hard winner over the same interval is the next level's
+    prior.  Returns a list, index k = level: (d_soft, d_hard, C, C2) for k < K-1,
+    (None, d, C, C2) at the coarsest level."""
+    PL = pyramid(left, K)
+    PR = pyramid(right, K)
+    out: List = [None] * K
+    d, C, C2 = match_level(PL[K - 1], PR[K - 1], n, level_range(D, K - 1), None, 0, eps)
+    out[K - 1] = (None, d, C, C2)
+    for k in range(K - 2, -1, -1):
+        out[k] = soft_level0(PL[k], PR[k], n, level_range(D, k), out[k + 1][1], rs, tau, eps)
+    return out
+
+
+def backward_levels(left: np.ndarray, right: np.ndarray, D: int, K: int, n: int, rs: int, tau: float,
+                    eps: float, maps: List[np.ndarray], grads: List[Optional[np.ndarray]]):
+    """Gradient of sum_k sum g_k d_soft^k with respect to both level-0 images,
+    every level's prior (maps[k + 1]) held fixed: each level's gradient with
+    respect to its own pyramid images (the soft level's backward), carried down
+    by the adjoint of the reduce (the chain rule through the pyramid)."""
+    PL = pyramid(left, K)
+    PR = pyramid(right, K)
+    gL = np.zeros_like(PL[K - 2]) if K >= 2 else None
+    gR = np.zeros_like(PR[K - 2]) if K >= 2 else None
+    for k in range(K - 2, -1, -1):
+        if gL.shape != PL[k].shape:
+            gL = reduce_adjoint(gL, *PL[k].shape)
+            gR = reduce_adjoint(gR, *PR[k].shape)
+        if grads[k] is not None:
+            a, b = backward(PL[k], PR[k], n, level_range(D, k), maps[k + 1], rs, tau, eps, grads[k])
+            gL = gL + a
+            gR = gR + b
+    return gL, gR

@@ -44,6 +44,23 @@ void orc_reduce(const double* in, int H, int W, double* out)
     }
 }
 
+/* The adjoint (transpose) of orc_reduce, for carrying an image gradient from a
+ * pyramid level to the level below: every coarse value is scattered with its
+ * 25 binomial weights onto the clamped fine positions its reduce read from.
+ * out (H x W) is overwritten. */
+void orc_reduce_adjoint(const double* G, int H, int W, double* out)
+{
+    static const double w[5] = {1.0 / 16, 4.0 / 16, 6.0 / 16, 4.0 / 16, 1.0 / 16};
+    const int Ho = (H + 1) / 2, Wo = (W + 1) / 2;
+    memset(out, 0, sizeof(double) * (size_t)H * W);
+    for (int y = 0; y < Ho; ++y)
+        for (int x = 0; x < Wo; ++x)
+            for (int a = -2; a <= 2; ++a)
+                for (int b = -2; b <= 2; ++b)
+                    out[(size_t)clampi(2 * y + a, 0, H - 1) * W + clampi(2 * x + b, 0, W - 1)] +=
+                        w[a + 2] * w[b + 2] * G[(size_t)y * Wo + x];
+}
+
 /* The same 5x5 binomial blur at every pixel, the "Gaussian blur over the original
  * image" of Section IV (matching on a blurred level 0 is the pre-blur variant):
  * out(y, x) = sum_{a,b} w_a w_b in(clamp(y + a), clamp(x + b)). */

@@ -44,15 +44,13 @@ static int hip_err(hipError_t e, const char* what, std::string* err)
     return MSIBM_ERR_HIP;
 }
 
-int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,
-                   int16_t* disp, float* cost, float* soft, int16_t* prior1, hipStream_t s,
-                   std::string* err)
+// Level images of a pair: level 0 is the caller's input, levels k >= 1 are
+// built into the workspace, up to three reduce steps per launch.
+static int build_pyramid(const msibm_pair& P, const PairLayout& lay, char* ws, const void* img[][2], int* pitch,
+                         hipStream_t s, std::string* err)
 {
     const int K = lay.K;
-    hipError_t e;
-    // image pointers per level and view (level 0 is the caller's input)
-    const void* img[MSIBM_MAX_LEVELS][2];
-    int pitch[MSIBM_MAX_LEVELS];
+    hipError_t e = hipSuccess;
     img[0][0] = P.left;
     img[0][1] = P.right;
     pitch[0] = P.pitch;
@@ -101,6 +99,47 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
         if (e != hipSuccess) return hip_err(e, "pyramid launch", err);
         k += steps;
     }
+    return MSIBM_OK;
+}
+
+// Window statistics of every level: one launch per distinct window size.
+static int build_stats(const PairLayout& lay, const msibm_config* cfg, char* ws, const void* const img[][2],
+                       const int* pitch, const int* dtype, hipStream_t s, std::string* err)
+{
+    const int K = lay.K;
+    for (int k0 = 0; k0 < K; ++k0) {
+        bool first = true;
+        for (int k = 0; k < k0; ++k) first = first && level_n(cfg, k) != level_n(cfg, k0);
+        if (!first) continue;
+        StatsArgs sa{};
+        for (int k = k0; k < K; ++k) {
+            if (level_n(cfg, k) != level_n(cfg, k0)) continue;
+            for (int v = 0; v < 2; ++v)
+                sa.seg[sa.nseg++] = StatsSeg{img[k][v], (WinStat*)(ws + lay.stat[k][v]), dtype[k], lay.h[k],
+                                             lay.w[k], pitch[k], lay.w[k], 0};
+        }
+        sa.n = level_n(cfg, k0);
+        sa.var_eps = cfg->var_eps;
+        TimedLaunch t("stats", s);
+        const hipError_t e = launch_stats(sa, s);
+        if (e != hipSuccess) return hip_err(e, "stats launch", err);
+    }
+    return MSIBM_OK;
+}
+
+int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,
+                   int16_t* disp, float* cost, float* soft, int16_t* prior1, hipStream_t s,
+                   std::string* err)
+{
+    const int K = lay.K;
+    hipError_t e;
+    // image pointers per level and view (level 0 is the caller's input)
+    const void* img[MSIBM_MAX_LEVELS][2];
+    int pitch[MSIBM_MAX_LEVELS];
+    {
+        const int st = build_pyramid(P, lay, ws, img, pitch, s, err);
+        if (st != MSIBM_OK) return st;
+    }
     // pre-blur variant: level 0 is matched on the blurred input (the pyramid
     // above was built from the input itself)
     const bool preblur = (cfg->flags & MSIBM_FLAG_PREBLUR) != 0;
@@ -124,22 +163,11 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
     // element type of level k's images
     auto dtype_of = [&](int k) { return (k == 0 && !preblur) ? P.dtype : MSIBM_F32; };
     // statistics: one launch per distinct window size (one for a common n)
-    for (int k0 = 0; k0 < K; ++k0) {
-        bool first = true;
-        for (int k = 0; k < k0; ++k) first = first && level_n(cfg, k) != level_n(cfg, k0);
-        if (!first) continue;
-        StatsArgs sa{};
-        for (int k = k0; k < K; ++k) {
-            if (level_n(cfg, k) != level_n(cfg, k0)) continue;
-            for (int v = 0; v < 2; ++v)
-                sa.seg[sa.nseg++] = StatsSeg{img[k][v], (WinStat*)(ws + lay.stat[k][v]), dtype_of(k), lay.h[k],
-                                             lay.w[k], pitch[k], lay.w[k], 0};
-        }
-        sa.n = level_n(cfg, k0);
-        sa.var_eps = cfg->var_eps;
-        TimedLaunch t("stats", s);
-        e = launch_stats(sa, s);
-        if (e != hipSuccess) return hip_err(e, "stats launch", err);
+    {
+        int dts[MSIBM_MAX_LEVELS];
+        for (int k = 0; k < K; ++k) dts[k] = dtype_of(k);
+        const int st = build_stats(lay, cfg, ws, img, pitch, dts, s, err);
+        if (st != MSIBM_OK) return st;
     }
     for (int k = K - 1; k >= 0; --k) {
         MatchArgs a{};

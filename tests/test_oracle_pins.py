@@ -590,3 +590,62 @@ def test_aggregate_pixel_list_and_scores_agree_with_the_map():
     picked = ~(C1 > 0.5)
     s = oracle.avg_score_many(L, R, n, ii[picked.ravel()], jj[picked.ravel()], d[picked], 1e-9)
     np.testing.assert_array_equal(s, C[picked])
+
+
+# ----------------------------- soft output at every level (an extension)
+
+@pytest.mark.parametrize("H,W", [(9, 14), (10, 7), (1, 5), (16, 16)])
+def test_reduce_adjoint_is_the_transpose(H, W):
+    rng = _rng(40 + H)
+    x = rng.random((H, W))
+    y = rng.random(((H + 1) // 2, (W + 1) // 2))
+    lhs = float((oracle.reduce(x) * y).sum())
+    rhs = float((x * oracle.reduce_adjoint(y, H, W)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * max(1.0, abs(lhs))
+    # the reduce's weights sum to one per output, so the adjoint keeps the total
+    assert abs(oracle.reduce_adjoint(y, H, W).sum() - y.sum()) <= 1e-12 * y.size
+
+
+def test_soft_levels_hard_maps_are_the_hierarchy_with_the_soft_radius():
+    p = synth.make_pair(41, 40, 64, 3, 2, 12, True, 0.9, 0.02, 2 / 255, "f32")
+    D, K, n, rs = 24, 3, 2, 2
+    out = oracle.soft_levels(p.left, p.right, D, K, n, rs, 0.05, 1e-6)
+    ref = oracle.disparity(p.left, p.right, D, K, n, rs, 1e-6)
+    for k in range(K):
+        assert np.array_equal(out[k][1], ref[k][0]) and np.allclose(out[k][2], ref[k][1])
+    # a tiny temperature makes each soft output the hard one
+    cold = oracle.soft_levels(p.left, p.right, D, K, n, rs, 1e-5, 1e-6)
+    for k in range(K - 1):
+        near = (cold[k][2] - cold[k][3]) < 1e-3
+        assert np.allclose(cold[k][0][~near], cold[k][1][~near], atol=1e-6)
+
+
+def test_backward_levels_matches_central_differences():
+    rng = _rng(42)
+    H, W, D, K, n, rs, tau, eps = 18, 26, 10, 3, 1, 1, 0.2, 1e-6
+    L = synth.texture(rng, H, W + 4)[:, 4:].copy()
+    R = synth.texture(rng, H, W + 4)[:, :W].copy()
+    fwd = oracle.soft_levels(L, R, D, K, n, rs, tau, eps)
+    maps = [o[1] for o in fwd]
+    grads = [rng.standard_normal(fwd[k][0].shape) for k in range(K - 1)] + [None]
+    gL, gR = oracle.backward_levels(L, R, D, K, n, rs, tau, eps, maps, grads)
+
+    def loss(Lx, Rx):
+        PL, PR = oracle.pyramid(Lx, K), oracle.pyramid(Rx, K)
+        tot = 0.0
+        for k in range(K - 1):
+            ds = oracle.soft_level0(PL[k], PR[k], n, oracle.level_range(D, k), maps[k + 1], rs, tau, eps)[0]
+            tot += float((grads[k] * ds).sum())
+        return tot
+    h = 1e-6
+    for (i, j) in [(5, 7), (9, 12), (0, 0), (17, 25), (8, 3)]:
+        for which, G in (("L", gL), ("R", gR)):
+            Lp, Rp, Lm, Rm = L.copy(), R.copy(), L.copy(), R.copy()
+            if which == "L":
+                Lp[i, j] += h
+                Lm[i, j] -= h
+            else:
+                Rp[i, j] += h
+                Rm[i, j] -= h
+            fd = (loss(Lp, Rp) - loss(Lm, Rm)) / (2 * h)
+            assert abs(fd - G[i, j]) <= 1e-5 * max(1.0, abs(fd)), (which, i, j, fd, G[i, j])
