@@ -214,6 +214,50 @@ msibm_status msibm_median_filter(const int16_t* d_in, int32_t in_pitch, const fl
 msibm_status msibm_upsample_cost(const float* coarse, int32_t Hc, int32_t Wc, int32_t coarse_pitch, int32_t H,
                                  int32_t W, double* out, int32_t out_pitch, void* stream);
 
+/*
+ * msibm_pyramid_adjoint - the transpose of one pyramid reduction (the chain rule
+ * through the binomial reduce of Section III): g_fine += R^T g_coarse, where
+ * R maps an H x W image to its ceil(H/2) x ceil(W/2) reduction.  Each fine pixel
+ * gathers, from at most 3 x 3 coarse pixels, the binomial weights of the taps
+ * that read it (clamped taps at the border add up).  Accumulates into g_fine.
+ *   g_coarse  device float Hc x Wc (row pitch coarse_pitch), Hc = ceil(H/2).
+ *   g_fine    device float H x W (row pitch fine_pitch), read and written.
+ * Errors: INVALID_ARG (null pointers), SHAPE (sizes, pitches), HIP.
+ */
+msibm_status msibm_pyramid_adjoint(const float* g_coarse, int32_t Hc, int32_t Wc, int32_t coarse_pitch,
+                                   float* g_fine, int32_t H, int32_t W, int32_t fine_pitch, void* stream);
+
+/*
+ * Soft output at every level (an extension of the paper).  The coarsest level
+ * is the hard full search; every finer level k takes the soft-argmax of
+ * msibm_disparity's soft level (radius soft_radius, temperature tau) around its
+ * doubled prior, the hard map of level k+1, and its hard winner over the same
+ * interval is the prior of level k-1.  One pair; config flags must be 0,
+ * soft_radius >= 1, K >= 2.
+ *
+ * msibm_levels_workspace_size - workspace bytes of both calls below (0 if the
+ *   pair or config is invalid).
+ * msibm_disparity_levels - the forward.
+ *   soft[k]   k = 0..K-2: device float H_k x W_k (pitch W_k), d_soft of level k.
+ *   maps[k]   k = 0..K-1: device int16 H_k x W_k (pitch W_k), the hard maps.
+ * msibm_backward_levels - gradient of sum_k sum_p grad_soft[k](p) d_soft^k(p)
+ *   with respect to both level-0 images (float pairs only), every level's prior
+ *   held fixed: each level's soft-level backward on its own pyramid images, and
+ *   the sum carried down level by level with msibm_pyramid_adjoint.
+ *   maps[k]        k = 1..K-1: the forward's hard maps (maps[0] is not read).
+ *   grad_soft[k]   k = 0..K-2: device float H_k x W_k (pitch W_k), or NULL for a
+ *                  level without loss.
+ *   grad_left/right device float H x W (pitch W), overwritten.
+ * Errors: INVALID_ARG, SHAPE, UNSUPPORTED (flags, K < 2, non-float backward),
+ *         WORKSPACE, HIP.
+ */
+size_t msibm_levels_workspace_size(const msibm_pair* pair, const msibm_config* cfg);
+msibm_status msibm_disparity_levels(const msibm_pair* pair, const msibm_config* cfg, float* const* soft,
+                                    int16_t* const* maps, void* workspace, size_t ws_bytes, void* stream);
+msibm_status msibm_backward_levels(const msibm_pair* pair, const msibm_config* cfg, const int16_t* const* maps,
+                                   const float* const* grad_soft, float* grad_left, float* grad_right,
+                                   void* workspace, size_t ws_bytes, void* stream);
+
 /* Bytes of workspace msibm_match_level needs for an H x W level. */
 size_t msibm_level_workspace_size(int32_t H, int32_t W);
 

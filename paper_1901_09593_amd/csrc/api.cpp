@@ -129,7 +129,7 @@ msibm_status validate_pair(const msibm_pair& p, int idx, const msibm_config* cfg
 }
 
 // Workspace layout of one pair (offsets from the pair's base).
-PairLayout pair_layout(const msibm_pair& p, int K, bool preblur, bool median, bool gated)
+PairLayout pair_layout(const msibm_pair& p, int K, bool preblur, bool median, bool gated, bool level_grads)
 {
     PairLayout L{};
     L.K = K;
@@ -168,6 +168,12 @@ PairLayout pair_layout(const msibm_pair& p, int K, bool preblur, bool median, bo
         L.ctmp = off;
         off = align_up(off + (size_t)p.height * p.width * sizeof(float));
     }
+    if (level_grads)
+        for (int k = 1; k <= K - 2; ++k)
+            for (int v = 0; v < 2; ++v) {
+                L.grad[k][v] = off;
+                off = align_up(off + (size_t)L.h[k] * L.w[k] * sizeof(float));
+            }
     L.bytes = off;
     return L;
 }
@@ -492,8 +498,8 @@ msibm_status msibm_backward(const msibm_pair* pairs, int32_t n_pairs, const msib
     msibm_status st = validate_config(cfg);
     if (st != MSIBM_OK) return st;
     if (cfg->soft_radius < 1) return fail(MSIBM_ERR_INVALID_ARG, "backward needs soft_radius >= 1");
-    if (cfg->flags & MSIBM_FLAG_PREBLUR)
-        return fail(MSIBM_ERR_UNSUPPORTED, "MSIBM_FLAG_PREBLUR is a forward-only variant");
+    if (cfg->flags & (MSIBM_FLAG_PREBLUR | MSIBM_FLAG_MEDIAN | MSIBM_FLAG_GATED))
+        return fail(MSIBM_ERR_UNSUPPORTED, "PREBLUR, MEDIAN and GATED are forward-only variants");
     std::vector<int> Ks(n_pairs);
     for (int p = 0; p < n_pairs; ++p) {
         st = validate_pair(pairs[p], p, cfg, &Ks[p]);
@@ -522,6 +528,93 @@ msibm_status msibm_backward(const msibm_pair* pairs, int32_t n_pairs, const msib
                                          grad_right[p], s, &err);
         if (rc != MSIBM_OK) return fail(rc, "pair %d: %s", p, err.c_str());
     }
+    return ok();
+}
+
+msibm_status msibm_pyramid_adjoint(const float* g_coarse, int32_t Hc, int32_t Wc, int32_t coarse_pitch,
+                                   float* g_fine, int32_t H, int32_t W, int32_t fine_pitch, void* stream)
+{
+    if (!g_coarse || !g_fine) return fail(MSIBM_ERR_INVALID_ARG, "NULL gradient");
+    if (H < 1 || W < 1 || Hc != (H + 1) / 2 || Wc != (W + 1) / 2 || coarse_pitch < Wc || fine_pitch < W)
+        return fail(MSIBM_ERR_SHAPE, "coarse %dx%d (pitch %d) for fine %dx%d (pitch %d)", Hc, Wc, coarse_pitch, H,
+                    W, fine_pitch);
+    AdjArgs a{};
+    a.g[0] = g_coarse;
+    a.out[0] = g_fine;
+    a.views = 1;
+    a.Hc = Hc;
+    a.Wc = Wc;
+    a.gpitch = coarse_pitch;
+    a.H = H;
+    a.W = W;
+    a.opitch = fine_pitch;
+    const hipError_t e = launch_adjoint(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "adjoint launch");
+    return ok();
+}
+
+// Shared checks of the every-level soft path: one float pair, K >= 2, a soft
+// radius, no variant flags.
+static msibm_status validate_levels(const msibm_pair* pair, const msibm_config* cfg, int* K)
+{
+    if (!pair || !cfg) return fail(MSIBM_ERR_INVALID_ARG, "NULL pair or config");
+    msibm_status st = validate_config(cfg);
+    if (st != MSIBM_OK) return st;
+    if (cfg->flags) return fail(MSIBM_ERR_UNSUPPORTED, "the every-level soft path takes no flags");
+    if (cfg->soft_radius < 1) return fail(MSIBM_ERR_INVALID_ARG, "soft_radius must be >= 1");
+    st = validate_pair(*pair, 0, cfg, K);
+    if (st != MSIBM_OK) return st;
+    if (*K < 2) return fail(MSIBM_ERR_UNSUPPORTED, "the every-level soft path needs K >= 2");
+    return MSIBM_OK;
+}
+
+size_t msibm_levels_workspace_size(const msibm_pair* pair, const msibm_config* cfg)
+{
+    int K;
+    if (validate_levels(pair, cfg, &K) != MSIBM_OK) return 0;
+    return pair_layout(*pair, K, false, false, false, true).bytes;
+}
+
+msibm_status msibm_disparity_levels(const msibm_pair* pair, const msibm_config* cfg, float* const* soft,
+                                    int16_t* const* maps, void* workspace, size_t ws_bytes, void* stream)
+{
+    int K;
+    msibm_status st = validate_levels(pair, cfg, &K);
+    if (st != MSIBM_OK) return st;
+    if (!soft || !maps) return fail(MSIBM_ERR_INVALID_ARG, "NULL output arrays");
+    for (int k = 0; k < K; ++k) {
+        if (!maps[k]) return fail(MSIBM_ERR_INVALID_ARG, "maps[%d] is NULL", k);
+        if (k < K - 1 && !soft[k]) return fail(MSIBM_ERR_INVALID_ARG, "soft[%d] is NULL", k);
+    }
+    const PairLayout lay = pair_layout(*pair, K, false, false, false, true);
+    if (!workspace || ws_bytes < lay.bytes)
+        return fail(MSIBM_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace ? ws_bytes : (size_t)0,
+                    lay.bytes);
+    std::string err;
+    const int rc = run_pair_levels(*pair, lay, cfg, (char*)workspace, soft, maps, (hipStream_t)stream, &err);
+    if (rc != MSIBM_OK) return fail(rc, "%s", err.c_str());
+    return ok();
+}
+
+msibm_status msibm_backward_levels(const msibm_pair* pair, const msibm_config* cfg, const int16_t* const* maps,
+                                   const float* const* grad_soft, float* grad_left, float* grad_right,
+                                   void* workspace, size_t ws_bytes, void* stream)
+{
+    int K;
+    msibm_status st = validate_levels(pair, cfg, &K);
+    if (st != MSIBM_OK) return st;
+    if (pair->dtype != MSIBM_F32) return fail(MSIBM_ERR_UNSUPPORTED, "the backward takes float images");
+    if (!maps || !grad_soft || !grad_left || !grad_right) return fail(MSIBM_ERR_INVALID_ARG, "NULL argument");
+    for (int k = 1; k < K; ++k)
+        if (!maps[k]) return fail(MSIBM_ERR_INVALID_ARG, "maps[%d] is NULL", k);
+    const PairLayout lay = pair_layout(*pair, K, false, false, false, true);
+    if (!workspace || ws_bytes < lay.bytes)
+        return fail(MSIBM_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace ? ws_bytes : (size_t)0,
+                    lay.bytes);
+    std::string err;
+    const int rc = run_pair_backward_levels(*pair, lay, cfg, (char*)workspace, maps, grad_soft, grad_left,
+                                            grad_right, (hipStream_t)stream, &err);
+    if (rc != MSIBM_OK) return fail(rc, "%s", err.c_str());
     return ok();
 }
 

@@ -128,6 +128,16 @@ struct GateArgs {
     double thresh;
 };
 
+// Adjoint of one pyramid step for up to two views: out (fine, H x W) +=
+// reduce^T(g) (coarse, ceil(H/2) x ceil(W/2)).
+struct AdjArgs {
+    const float* g[2];
+    float* out[2];
+    int views;
+    int Hc, Wc, gpitch;
+    int H, W, opitch;
+};
+
 // Full-resolution binomial blur of both views (the pre-blur variant's level 0).
 struct BlurArgs {
     const void* src[2];
@@ -222,6 +232,7 @@ hipError_t launch_stats(StatsArgs a, hipStream_t s);
 hipError_t launch_tower(int dtype, const TowerArgs& a, hipStream_t s);
 hipError_t launch_blur(int dtype, const BlurArgs& a, hipStream_t s);
 hipError_t launch_median(const MedianArgs& a, hipStream_t s);
+hipError_t launch_adjoint(const AdjArgs& a, hipStream_t s);
 hipError_t launch_gate(int n, int dtype, bool repick, const GateArgs& a, hipStream_t s);
 hipError_t launch_upsample_cost(const float* cc, int Hc, int Wc, int cpitch, int H, int W, double* out,
                                 int opitch, hipStream_t s);

@@ -264,6 +264,48 @@ __global__ __launch_bounds__(256) void median_kernel(MedianArgs a)
     a.d_out[(size_t)i * a.opitch + j] = (int16_t)out;
 }
 
+// Weight with which coarse row (or column) y of a reduce step reads fine row p:
+// the binomial taps a with clamp(2y + a) = p, summed (several taps clamp to the
+// same edge row).
+__device__ __forceinline__ float adj_weight(int p, int y, int H)
+{
+    const float w[5] = {1.f / 16, 4.f / 16, 6.f / 16, 4.f / 16, 1.f / 16};
+    float s = 0.f;
+#pragma unroll
+    for (int a = -2; a <= 2; ++a) s += (clampi(2 * y + a, 0, H - 1) == p) ? w[a + 2] : 0.f;
+    return s;
+}
+
+// out(p, q) += sum over the coarse pixels that read fine pixel (p, q) of their
+// weight times g: at most 3 coarse rows (y in [ceil((p-2)/2), floor((p+2)/2)])
+// and 3 coarse columns.  One thread per fine pixel, no atomics.
+__global__ __launch_bounds__(256) void adjoint_kernel(AdjArgs a)
+{
+    const int q = blockIdx.x * 64 + (threadIdx.x & 63), p = blockIdx.y * 4 + (threadIdx.x >> 6);
+    const int v = blockIdx.z;
+    if (p >= a.H || q >= a.W) return;
+    const int y0 = max(0, (p - 1) / 2), y1 = min(a.Hc - 1, (p + 2) / 2);
+    const int x0 = max(0, (q - 1) / 2), x1 = min(a.Wc - 1, (q + 2) / 2);
+    const float* g = a.g[v];
+    float s = 0.f;
+    for (int y = y0; y <= y1; ++y) {
+        const float wy = adj_weight(p, y, a.H);
+        float r = 0.f;
+        for (int x = x0; x <= x1; ++x) r += adj_weight(q, x, a.W) * g[(size_t)y * a.gpitch + x];
+        s += wy * r;
+    }
+    float* o = a.out[v] + (size_t)p * a.opitch + q;
+    *o += s;
+}
+
+hipError_t launch_adjoint(const AdjArgs& a, hipStream_t s)
+{
+    if (a.views < 1 || a.views > 2 || a.Hc != (a.H + 1) / 2 || a.Wc != (a.W + 1) / 2) return hipErrorInvalidValue;
+    dim3 grid((a.W + 63) / 64, (a.H + 3) / 4, a.views);
+    hipLaunchKernelGGL(adjoint_kernel, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_median(const MedianArgs& a, hipStream_t s)
 {
     dim3 grid((a.W + 63) / 64, (a.H + 3) / 4, 1);

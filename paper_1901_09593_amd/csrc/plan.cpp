@@ -269,6 +269,136 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
     return MSIBM_OK;
 }
 
+int run_pair_levels(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,
+                    float* const* soft, int16_t* const* maps, hipStream_t s, std::string* err)
+{
+    const int K = lay.K;
+    const void* img[MSIBM_MAX_LEVELS][2];
+    int pitch[MSIBM_MAX_LEVELS];
+    int st = build_pyramid(P, lay, ws, img, pitch, s, err);
+    if (st != MSIBM_OK) return st;
+    int dts[MSIBM_MAX_LEVELS];
+    for (int k = 0; k < K; ++k) dts[k] = MSIBM_F32;
+    st = build_stats(lay, cfg, ws, img, pitch, dts, s, err);
+    if (st != MSIBM_OK) return st;
+    for (int k = K - 1; k >= 0; --k) {
+        const bool coarsest = (k == K - 1);
+        MatchArgs a{};
+        a.L = img[k][0];
+        a.R = img[k][1];
+        a.H = lay.h[k];
+        a.W = lay.w[k];
+        a.pitch = pitch[k];
+        a.statL = (const WinStat*)(ws + lay.stat[k][0]);
+        a.statR = (const WinStat*)(ws + lay.stat[k][1]);
+        a.spitch = lay.w[k];
+        a.Dk = level_range(P.max_disp, k);
+        if (!coarsest) {
+            a.prior = maps[k + 1];
+            a.Hc = lay.h[k + 1];
+            a.Wc = lay.w[k + 1];
+            a.ppitch = lay.w[k + 1];
+        }
+        a.r = coarsest ? 0 : cfg->soft_radius;
+        a.d_out = maps[k];
+        a.c_out = nullptr;
+        a.soft_out = coarsest ? nullptr : soft[k];
+        a.opitch = lay.w[k];
+        a.inv_tau = coarsest ? 0.f : 1.f / cfg->tau;
+        const int mode = coarsest ? MODE_FULL : MODE_SOFT;
+        const int nc = coarsest ? FULL_NC : slots_for_radius(a.r);
+        const int n = level_n(cfg, k);
+        char lab[32];
+        snprintf(lab, sizeof(lab), "match_%s_l%d", coarsest ? "full" : "soft", k);
+        TimedLaunch t(lab, s);
+        a.variant = select_variant(a, n, MSIBM_F32, mode, nc, s);
+        const hipError_t e = launch_match(n, MSIBM_F32, mode, nc, a, s);
+        if (e != hipSuccess) return hip_err(e, "match launch", err);
+    }
+    return MSIBM_OK;
+}
+
+int run_pair_backward_levels(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,
+                             const int16_t* const* maps, const float* const* grad_soft, float* grad_left,
+                             float* grad_right, hipStream_t s, std::string* err)
+{
+    const int K = lay.K;
+    const void* img[MSIBM_MAX_LEVELS][2];
+    int pitch[MSIBM_MAX_LEVELS];
+    int st = build_pyramid(P, lay, ws, img, pitch, s, err);
+    if (st != MSIBM_OK) return st;
+    int dts[MSIBM_MAX_LEVELS];
+    for (int k = 0; k < K; ++k) dts[k] = MSIBM_F32;
+    st = build_stats(lay, cfg, ws, img, pitch, dts, s, err);
+    if (st != MSIBM_OK) return st;
+    // image gradients per level: the caller's at level 0, the workspace's above
+    float* gl[MSIBM_MAX_LEVELS];
+    float* gr[MSIBM_MAX_LEVELS];
+    gl[0] = grad_left;
+    gr[0] = grad_right;
+    for (int k = 1; k <= K - 2; ++k) {
+        gl[k] = (float*)(ws + lay.grad[k][0]);
+        gr[k] = (float*)(ws + lay.grad[k][1]);
+    }
+    hipError_t e;
+    for (int k = 0; k <= K - 2; ++k) {
+        TimedLaunch t("bwd_zero", s);
+        e = launch_zero(gl[k], gr[k], (size_t)lay.h[k] * lay.w[k], s);
+        if (e != hipSuccess) return hip_err(e, "zero launch", err);
+    }
+    // from the coarsest soft level down: each level's own gradient, then its
+    // total carried one level down through the reduce's adjoint
+    for (int k = K - 2; k >= 0; --k) {
+        if (grad_soft[k]) {
+            BackArgs b{};
+            b.L = (const float*)img[k][0];
+            b.R = (const float*)img[k][1];
+            b.H = lay.h[k];
+            b.W = lay.w[k];
+            b.pitch = pitch[k];
+            b.statL = (const WinStat*)(ws + lay.stat[k][0]);
+            b.statR = (const WinStat*)(ws + lay.stat[k][1]);
+            b.spitch = lay.w[k];
+            b.D = level_range(P.max_disp, k);
+            b.prior = maps[k + 1];
+            b.Hc = lay.h[k + 1];
+            b.Wc = lay.w[k + 1];
+            b.ppitch = lay.w[k + 1];
+            b.rs = cfg->soft_radius;
+            b.inv_tau = 1.f / cfg->tau;
+            b.g = grad_soft[k];
+            b.gpitch = lay.w[k];
+            b.gL = gl[k];
+            b.gR = gr[k];
+            char lab[32];
+            snprintf(lab, sizeof(lab), "backward_l%d", k);
+            TimedLaunch t(lab, s);
+            e = launch_backward(level_n(cfg, k), slots_for_radius(cfg->soft_radius), b, s);
+            if (e != hipSuccess) return hip_err(e, "backward launch", err);
+        }
+        if (k >= 1) {
+            AdjArgs ad{};
+            ad.g[0] = gl[k];
+            ad.g[1] = gr[k];
+            ad.out[0] = gl[k - 1];
+            ad.out[1] = gr[k - 1];
+            ad.views = 2;
+            ad.Hc = lay.h[k];
+            ad.Wc = lay.w[k];
+            ad.gpitch = lay.w[k];
+            ad.H = lay.h[k - 1];
+            ad.W = lay.w[k - 1];
+            ad.opitch = lay.w[k - 1];
+            char lab[32];
+            snprintf(lab, sizeof(lab), "adjoint_l%d", k);
+            TimedLaunch t(lab, s);
+            e = launch_adjoint(ad, s);
+            if (e != hipSuccess) return hip_err(e, "adjoint launch", err);
+        }
+    }
+    return MSIBM_OK;
+}
+
 hipError_t launch_backward(int n, int nc, const BackArgs& a, hipStream_t s)
 {
     switch (n) {

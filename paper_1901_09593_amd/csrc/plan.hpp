@@ -34,11 +34,22 @@ struct PairLayout {
     size_t cmap[MSIBM_MAX_LEVELS]; // levels k >= 1: the cost map (float), with the gating
     size_t dtmp;              // unfiltered map of a level (int16), with the median
     size_t ctmp;              // level 0's cost (float) when the caller takes none
+    size_t grad[MSIBM_MAX_LEVELS][2]; // levels 1..K-2: both views' image gradients (float),
+                                      // for the backward through every level
     size_t bytes;
 };
 
 PairLayout pair_layout(const msibm_pair& p, int K, bool preblur = false, bool median = false,
-                       bool gated = false);
+                       bool gated = false, bool level_grads = false);
+
+// Forward with a soft output at every level below the coarsest.
+int run_pair_levels(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,
+                    float* const* soft, int16_t* const* maps, hipStream_t s, std::string* err);
+
+// Backward of a loss on every level's soft output down to the level-0 images.
+int run_pair_backward_levels(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,
+                             const int16_t* const* maps, const float* const* grad_soft, float* grad_left,
+                             float* grad_right, hipStream_t s, std::string* err);
 
 struct BatchOutputs {
     int16_t* const* disp;

@@ -89,6 +89,16 @@ def lib() -> ctypes.CDLL:
                                              _I32, ctypes.c_double, ctypes.c_float, _VP, ctypes.c_size_t,
                                              _VP]
         L.msibm_aggregate_refine.restype = _I32
+        L.msibm_pyramid_adjoint.argtypes = [_VP, _I32, _I32, _I32, _VP, _I32, _I32, _I32, _VP]
+        L.msibm_pyramid_adjoint.restype = _I32
+        L.msibm_levels_workspace_size.argtypes = [ctypes.POINTER(Pair), ctypes.POINTER(Config)]
+        L.msibm_levels_workspace_size.restype = ctypes.c_size_t
+        L.msibm_disparity_levels.argtypes = [ctypes.POINTER(Pair), ctypes.POINTER(Config), _PP, _PP, _VP,
+                                             ctypes.c_size_t, _VP]
+        L.msibm_disparity_levels.restype = _I32
+        L.msibm_backward_levels.argtypes = [ctypes.POINTER(Pair), ctypes.POINTER(Config), _PP, _PP, _VP, _VP,
+                                            _VP, ctypes.c_size_t, _VP]
+        L.msibm_backward_levels.restype = _I32
         L.msibm_level_workspace_size.argtypes = [_I32, _I32]
         L.msibm_level_workspace_size.restype = ctypes.c_size_t
         L.msibm_match_level.argtypes = [_VP, _VP, _I32, _I32, _I32, _I32, _I32, _I32, _VP, _I32,
@@ -498,3 +508,57 @@ class MsibmFunction(torch.autograd.Function):
             grad_soft = torch.zeros_like(L)
         gL, gR = backward(L, R, p1, grad_soft, D, K, n, r, var_eps, soft_radius, tau)
         return gL, gR, None, None, None, None, None, None, None
+
+
+# ------------------------------------------------ soft output at every level
+
+def pyramid_adjoint(g_coarse: torch.Tensor, H: int, W: int,
+                    g_fine: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """g_fine + reduce^T(g_coarse) (g_fine = zeros when not given)."""
+    g_coarse = g_coarse.contiguous()
+    if g_fine is None:
+        g_fine = torch.zeros((H, W), dtype=torch.float32, device=g_coarse.device)
+    _check(lib().msibm_pyramid_adjoint(_ptr(g_coarse), g_coarse.shape[0], g_coarse.shape[1], g_coarse.stride(0),
+                                       _ptr(g_fine), H, W, g_fine.stride(0), _stream(g_coarse.device)))
+    return g_fine
+
+
+def _levels_setup(L, R, D, K, n, var_eps, soft_radius, tau):
+    pairs, keep = _pairs([L], [R], [D], [K])
+    cfg = make_config(n, 0, var_eps, soft_radius, tau)
+    b = lib().msibm_levels_workspace_size(pairs, ctypes.byref(cfg))
+    if b == 0:
+        raise MsibmError(-1, "invalid pair or config: " + lib().msibm_last_error().decode())
+    ws = torch.empty(b, dtype=torch.uint8, device=L.device)
+    Kr = K or auto_levels(D)
+    shapes = [(level_dim(L.shape[0], k), level_dim(L.shape[1], k)) for k in range(Kr)]
+    return pairs, keep, cfg, ws, Kr, shapes
+
+
+def disparity_levels(L: torch.Tensor, R: torch.Tensor, D: int, K: int, n, var_eps: float, soft_radius: int,
+                     tau: float):
+    """Soft output at every level below the coarsest.  Returns (soft, maps):
+    soft[k] (float, k < K-1) and maps[k] (int16, every level)."""
+    pairs, keep, cfg, ws, K, shapes = _levels_setup(L, R, D, K, n, var_eps, soft_radius, tau)
+    dev = L.device
+    soft = [torch.empty(sh, dtype=torch.float32, device=dev) for sh in shapes[:-1]]
+    maps = [torch.empty(sh, dtype=torch.int16, device=dev) for sh in shapes]
+    _check(lib().msibm_disparity_levels(pairs, ctypes.byref(cfg), _ptr_array(soft + [None]), _ptr_array(maps),
+                                        _ptr(ws), ws.numel(), _stream(dev)))
+    del keep
+    return soft, maps
+
+
+def backward_levels(L: torch.Tensor, R: torch.Tensor, maps: Sequence[torch.Tensor],
+                    grad_soft: Sequence[Optional[torch.Tensor]], D: int, K: int, n, var_eps: float,
+                    soft_radius: int, tau: float) -> Tuple[torch.Tensor, torch.Tensor]:
+    """(dLoss/dL, dLoss/dR) for Loss = sum_k sum grad_soft[k] d_soft^k, the maps fixed."""
+    pairs, keep, cfg, ws, K, shapes = _levels_setup(L, R, D, K, n, var_eps, soft_radius, tau)
+    dev = L.device
+    gs = [g.contiguous() if g is not None else None for g in grad_soft]
+    gL = torch.empty(shapes[0], dtype=torch.float32, device=dev)
+    gR = torch.empty(shapes[0], dtype=torch.float32, device=dev)
+    _check(lib().msibm_backward_levels(pairs, ctypes.byref(cfg), _ptr_array(list(maps)), _ptr_array(gs + [None]),
+                                       _ptr(gL), _ptr(gR), _ptr(ws), ws.numel(), _stream(dev)))
+    del keep
+    return gL, gR
