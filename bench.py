@@ -309,6 +309,30 @@ def section_gated(torch, M, synth, steps):
     return res
 
 
+def section_levels(torch, M, synth, steps):
+    """Soft output at every level (an extension): forward and backward through
+    every level and the pyramid for the 960x540 float pairs, per pair."""
+    dev = torch.device("cuda:0")
+    p, cfg = synth.workload("diff960", 0)
+    H, W, D, K, n, eps, rs, tau = cfg.height, cfg.width, cfg.max_disp, cfg.levels, cfg.half_window, \
+        cfg.var_eps, cfg.soft_radius, cfg.tau
+    Lg, Rg = torch.from_numpy(p.left).to(dev), torch.from_numpy(p.right).to(dev)
+    soft, maps = M.disparity_levels(Lg, Rg, D, K, n, eps, rs, tau)
+    grads = [torch.ones_like(s) / s.numel() for s in soft]
+    fwd_ms = time_ms(torch, lambda: M.disparity_levels(Lg, Rg, D, K, n, eps, rs, tau), steps, 2)
+    bwd_ms = time_ms(torch, lambda: M.backward_levels(Lg, Rg, maps, grads, D, K, n, eps, rs, tau), steps, 2)
+    M.timing_enable(True)
+    for _ in range(steps):
+        M.backward_levels(Lg, Rg, maps, grads, D, K, n, eps, rs, tau)
+    torch.cuda.synchronize()
+    tim = M.timing_read()
+    M.timing_enable(False)
+    return {"workload": f"{W}x{H} float pair (diff960), K={K}, {2 * n + 1}x{2 * n + 1} ZNCC, D={D}, soft-argmax "
+                        f"+-{rs} (tau {tau}) at levels 0..{K - 2}, loss = mean of every level's soft output",
+            "fwd_ms": fwd_ms, "bwd_ms": bwd_ms,
+            "bwd_kernels_us": {k: 1e3 * v[0] / v[1] for k, v in sorted(tim.items())}}
+
+
 def section_fwd_bwd(torch, M, synth, name, count, steps):
     """Forward + masked mean-L1 loss gradient + backward for `count` float pairs."""
     dev = torch.device("cuda:0")
@@ -395,8 +419,9 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--sections", default="batched,fwd_bwd,accuracy,gated",
-                    help="extra sections beside the headline step: batched, fwd_bwd, accuracy, gated, or none")
+    ap.add_argument("--sections", default="batched,fwd_bwd,accuracy,gated,levels",
+                    help="extra sections beside the headline step: batched, fwd_bwd, accuracy, gated, levels, "
+                         "or none")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the default kernel shapes instead of measuring them first")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -514,6 +539,8 @@ def main():
         extra["accuracy"] = section_accuracy(torch, msibm, synth, nsteps)
     if "gated" in sections:
         extra["gated"] = section_gated(torch, msibm, synth, nsteps)
+    if "levels" in sections:
+        extra["levels"] = section_levels(torch, msibm, synth, nsteps)
 
     # the FP64 oracle on the host cores: whole pairs until the time budget is used
     cpu = None

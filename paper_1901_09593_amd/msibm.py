@@ -562,3 +562,25 @@ def backward_levels(L: torch.Tensor, R: torch.Tensor, maps: Sequence[torch.Tenso
                                        _ptr(gL), _ptr(gR), _ptr(ws), ws.numel(), _stream(dev)))
     del keep
     return gL, gR
+
+
+class MsibmLevelsFunction(torch.autograd.Function):
+    """softs = MsibmLevelsFunction.apply(L, R, D, K, n, var_eps, soft_radius, tau).
+
+    Forward: the soft output of every level below the coarsest (a tuple, level 0
+    first).  Backward: dLoss/dL and dLoss/dR through every level's scores and the
+    pyramid, each level's prior (the next coarser hard map) held fixed."""
+
+    @staticmethod
+    def forward(ctx, L, R, D, K, n, var_eps, soft_radius, tau):
+        soft, maps = disparity_levels(L, R, D, K, n, var_eps, soft_radius, tau)
+        ctx.save_for_backward(L, R, *maps)
+        ctx.params = (D, K, n, var_eps, soft_radius, tau)
+        return tuple(soft)
+
+    @staticmethod
+    def backward(ctx, *grad_soft):
+        L, R, *maps = ctx.saved_tensors
+        D, K, n, var_eps, soft_radius, tau = ctx.params
+        gL, gR = backward_levels(L, R, maps, list(grad_soft), D, K, n, var_eps, soft_radius, tau)
+        return gL, gR, None, None, None, None, None, None

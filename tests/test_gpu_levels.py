@@ -118,3 +118,19 @@ def test_levels_reject_bad_calls(M):
     Lu = torch.zeros((32, 48), dtype=torch.uint8, device="cuda")
     with pytest.raises(M.MsibmError):
         M.disparity_levels(Lu, Lu, 16, 3, 2, 0.065, 1, 0.05)  # the soft levels take float images
+
+
+def test_autograd_every_level_loss(M):
+    """A loss on all levels' soft outputs through torch autograd equals the
+    oracle's gradient of the same loss."""
+    L, R, cfg = _case(3, 80, 144)
+    D, K, n, rs, eps, tau = 40, 3, 2, 2, cfg.var_eps, cfg.tau
+    Lt = dev(L).requires_grad_(True)
+    Rt = dev(R).requires_grad_(True)
+    softs = M.MsibmLevelsFunction.apply(Lt, Rt, D, K, n, eps, rs, tau)
+    loss = sum((w * s).sum() for w, s in zip((1.0, 0.5), softs))
+    loss.backward()
+    _, maps = M.disparity_levels(dev(L), dev(R), D, K, n, eps, rs, tau)
+    grads = [np.full(tuple(s.shape), w) for w, s in zip((1.0, 0.5), softs)] + [None]
+    oL, oR = oracle.backward_levels(L, R, D, K, n, rs, tau, eps, [host(m) for m in maps], grads)
+    assert rel(host(Lt.grad), oL) <= REL_TOL and rel(host(Rt.grad), oR) <= REL_TOL
