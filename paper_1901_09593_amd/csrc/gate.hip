@@ -32,6 +32,7 @@ constexpr int GT_H = 8;        // tile rows
 constexpr int GT_W = 64;       // tile columns
 constexpr int GT_ZC = 32;      // candidates per staged right chunk
 constexpr int GT_THREADS = 256;
+constexpr int ZU = 1;          // candidates scored per round of barriers (divides GT_ZC)
 
 // Keys' cubic weights (a = -1/2) of the four coarse taps around fine index i
 // at scale 2 with aligned pixel centres: the fine pixel sits 3/4 (even i) or
@@ -99,10 +100,11 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
 
     __shared__ float Ls[ER][EC];
     __shared__ float Rs[ER][RSW];
-    __shared__ acc_t V[RR][EC];
+    __shared__ acc_t V[ZU][RR][EC];
     __shared__ double Smu[RR][SSW];
     __shared__ float Sis[RR][SSW];
-    __shared__ float Es[REPICK ? RR : 1][REPICK ? RC : 1];
+    __shared__ float Es[ZU][REPICK ? RR : 1][REPICK ? RC : 1];
+    __shared__ float Hs[ZU][REPICK ? RR : 1][REPICK ? GT_W : 1];  // 5-column sums of the scores
     __shared__ int s_xmax;
 
     const int tid = threadIdx.x;
@@ -129,7 +131,7 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
         }
     }
     bool act[OWN];
-    double best[OWN];
+    float best[OWN];
     int bz[OWN];
     if (tid == 0) s_xmax = -1;
     __syncthreads();
@@ -137,7 +139,7 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
     for (int p = 0; p < OWN; ++p) {
         const int i = y0 + oy[p], j = x0 + ox[p];
         act[p] = false;
-        best[p] = -1e300;
+        best[p] = -3.0f;  // below every score
         bz[p] = 0;
         if (oy[p] < GT_H && ox[p] < GT_W && i < H && j < W) {
             if constexpr (REPICK)
@@ -188,6 +190,18 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
         rcp3[p] = 1.f / (float)(rows_in * cols_r);
     }
 
+    double rmu[RUN];  // right window means and 1/sqrt(A) of the scored run
+    float ris[RUN];
+    // the left column a column-sum thread multiplies at every candidate, kept
+    // in registers (the left tile does not move with z)
+    float lcol[VG + 2 * NW];
+    __syncthreads();
+    {
+        const int g = tid / EC, e = tid - g * EC;
+#pragma unroll
+        for (int t = 0; t < VG + 2 * NW; ++t) lcol[t] = tid < EC * NVG ? Ls[g * VG + t][e] : 0.f;
+    }
+
     for (int z0 = 0; z0 <= zmax; z0 += GT_ZC) {
         const int zhi = z0 + GT_ZC - 1;
         __syncthreads();  // the previous chunk's staged data is consumed
@@ -204,78 +218,109 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
         }
         __syncthreads();
         const int zend = min(zhi, zmax);
-        for (int z = z0; z <= zend; ++z) {
-            const int zz = zhi - z;
+        // ZU candidates per round of barriers (two per round measured no faster)
+        for (int z = z0; z <= zend; z += ZU) {
             // column sums of the products over each window's rows
             if (tid < EC * NVG) {
                 const int g = tid / EC, e = tid - g * EC;
-                acc_t pr[VG + 2 * NW];
 #pragma unroll
-                for (int t = 0; t < VG + 2 * NW; ++t)
-                    pr[t] = (acc_t)Ls[g * VG + t][e] * (acc_t)Rs[g * VG + t][e + zz];
-                acc_t s = 0;
+                for (int u = 0; u < ZU; ++u) {
+                    const int zz = max(zhi - (z + u), 0);  // a candidate past zend is scored, not used
+                    acc_t pr[VG + 2 * NW];
 #pragma unroll
-                for (int t = 0; t <= 2 * NW; ++t) s += pr[t];
-                V[g * VG][e] = s;
+                    for (int t = 0; t < VG + 2 * NW; ++t)
+                        pr[t] = (acc_t)lcol[t] * (acc_t)Rs[g * VG + t][e + zz];
+                    acc_t sv = 0;
 #pragma unroll
-                for (int t = 1; t < VG; ++t) {
-                    s += pr[t + 2 * NW] - pr[t - 1];
-                    V[g * VG + t][e] = s;
+                    for (int t = 0; t <= 2 * NW; ++t) sv += pr[t];
+                    V[u][g * VG][e] = sv;
+#pragma unroll
+                    for (int t = 1; t < VG; ++t) {
+                        sv += pr[t + 2 * NW] - pr[t - 1];
+                        V[u][g * VG + t][e] = sv;
+                    }
                 }
             }
             __syncthreads();
             // row sums, then the scores of the region pixels
             if (scorer) {
-                acc_t s = 0;
 #pragma unroll
-                for (int b = 0; b <= 2 * NW; ++b) s += (su + b < EC) ? V[sy][su + b] : (acc_t)0;
+                for (int u = 0; u < ZU; ++u) {
+                    const int zu = z + u, zz = max(zhi - zu, 0);
+                    // right statistics of the run: column q at candidate z is
+                    // column q - 1 at z - 1, so one new value per candidate
+                    if (zu == 0) {
 #pragma unroll
-                for (int q = 0; q < RUN; ++q) {
-                    if (q > 0) {
-                        const int hi = su + q + 2 * NW;
-                        s += (hi < EC ? V[sy][hi] : (acc_t)0) - V[sy][su + q - 1];
-                    }
-                    float e = 0.f;
-                    const bool valid = sxa[q] >= z;
-                    if (valid) {
-                        // C in double; its float rounding (relative 6e-8) is
-                        // far below the score tolerance
-                        const int w = su + q + zz;
-                        const float c = (float)fma(-nmul[q], Smu[sy][w], (double)s);
-                        e = fminf(1.f, fmaxf(-1.f, c * isl[q] * Sis[sy][w]));
-                    }
-                    if constexpr (REPICK) {
-                        if (su + q < RC) Es[sy][su + q] = e;
+                        for (int q = 0; q < RUN; ++q) {
+                            const int w = min(su + q + zz, SSW - 1);
+                            rmu[q] = Smu[sy][w];
+                            ris[q] = Sis[sy][w];
+                        }
                     } else {
-                        // the scorer of (sy, su + q) owns it
-                        if (act[q] && valid && (double)e > best[q]) {
-                            best[q] = e;
-                            bz[q] = z;
+#pragma unroll
+                        for (int q = RUN - 1; q > 0; --q) {
+                            rmu[q] = rmu[q - 1];
+                            ris[q] = ris[q - 1];
+                        }
+                        const int w = min(su + zz, SSW - 1);
+                        rmu[0] = Smu[sy][w];
+                        ris[0] = Sis[sy][w];
+                    }
+                    acc_t sr = 0;
+#pragma unroll
+                    for (int b = 0; b <= 2 * NW; ++b) sr += (su + b < EC) ? V[u][sy][su + b] : (acc_t)0;
+#pragma unroll
+                    for (int q = 0; q < RUN; ++q) {
+                        if (q > 0) {
+                            const int hi = su + q + 2 * NW;
+                            sr += (hi < EC ? V[u][sy][hi] : (acc_t)0) - V[u][sy][su + q - 1];
+                        }
+                        // computed for every column of the run, kept where
+                        // valid: no branch per column.  C in double; its float
+                        // rounding (relative 6e-8) is far below the score
+                        // tolerance
+                        const bool valid = sxa[q] >= zu && zu <= zend;
+                        const float c = (float)fma(-nmul[q], rmu[q], (double)sr);
+                        const float e = valid ? fminf(1.f, fmaxf(-1.f, c * isl[q] * ris[q])) : 0.f;
+                        if constexpr (REPICK) {
+                            if (su + q < RC) Es[u][sy][su + q] = e;
+                        } else {
+                            // the scorer of (sy, su + q) owns it
+                            const bool better = act[q] && valid && e > best[q];
+                            best[q] = better ? e : best[q];
+                            bz[q] = better ? zu : bz[q];
                         }
                     }
                 }
             }
             __syncthreads();
             if constexpr (REPICK) {
-                // 5x5 sums of the scores (0 where a neighbour does not count)
-                const int c0 = ox[0], r0 = oy[0];
-                float rs[6];
+                // 5x5 sums of the scores (0 where a neighbour does not count):
+                // each wave forms the 5-column sums of 3 region rows, then each
+                // thread the 5-row sums of its two output pixels
+                const int c0 = tid & 63, w3 = 3 * (tid >> 6);
 #pragma unroll
-                for (int t = 0; t < 6; ++t)
-                    rs[t] = Es[r0 + t][c0] + Es[r0 + t][c0 + 1] + Es[r0 + t][c0 + 2] + Es[r0 + t][c0 + 3] +
-                            Es[r0 + t][c0 + 4];
-                const float sum[2] = {rs[0] + rs[1] + rs[2] + rs[3] + rs[4], rs[1] + rs[2] + rs[3] + rs[4] + rs[5]};
+                for (int u = 0; u < ZU; ++u)
 #pragma unroll
-                for (int p = 0; p < 2; ++p) {
-                    const int j = x0 + ox[p];
-                    if (act[p] && z <= j) {
+                    for (int t = 0; t < 3; ++t)
+                        Hs[u][w3 + t][c0] = Es[u][w3 + t][c0] + Es[u][w3 + t][c0 + 1] + Es[u][w3 + t][c0 + 2] +
+                                            Es[u][w3 + t][c0 + 3] + Es[u][w3 + t][c0 + 4];
+                __syncthreads();
+                const int r0 = oy[0];
+#pragma unroll
+                for (int u = 0; u < ZU; ++u) {
+                    const int zu = z + u;
+                    const float mid = Hs[u][r0 + 1][c0] + Hs[u][r0 + 2][c0] + Hs[u][r0 + 3][c0] + Hs[u][r0 + 4][c0];
+                    const float sum[2] = {Hs[u][r0][c0] + mid, mid + Hs[u][r0 + 5][c0]};
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        const int j = x0 + ox[p];
                         // the count changes only where z passes j - 2 and j - 1
-                        const float rc = (z <= j - 2) ? rcp5[p] : (z == j - 1 ? rcp4[p] : rcp3[p]);
+                        const float rc = (zu <= j - 2) ? rcp5[p] : (zu == j - 1 ? rcp4[p] : rcp3[p]);
                         const float ebar = sum[p] * rc;
-                        if ((double)ebar > best[p]) {
-                            best[p] = ebar;
-                            bz[p] = z;
-                        }
+                        const bool better = act[p] && zu <= j && zu <= zend && ebar > best[p];
+                        best[p] = better ? ebar : best[p];
+                        bz[p] = better ? zu : bz[p];
                     }
                 }
             }
@@ -286,7 +331,7 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
         if (!act[p]) continue;
         const size_t o = (size_t)(y0 + oy[p]) * a.opitch + (x0 + ox[p]);
         a.d[o] = (int16_t)bz[p];
-        a.c[o] = (float)best[p];
+        a.c[o] = best[p];
     }
 }
 
