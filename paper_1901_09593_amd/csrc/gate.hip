@@ -103,8 +103,9 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
     __shared__ acc_t V[ZU][RR][EC];
     __shared__ double Smu[RR][SSW];
     __shared__ float Sis[RR][SSW];
-    __shared__ float Es[ZU][REPICK ? RR : 1][REPICK ? RC : 1];
-    __shared__ float Hs[ZU][REPICK ? RR : 1][REPICK ? GT_W : 1];  // 5-column sums of the scores
+    // suffix and prefix sums of the scores along each scoring run (re-pick)
+    __shared__ float SUF[ZU][REPICK ? RR : 1][REPICK ? NRUN * RUN : 1];
+    __shared__ float PRE[ZU][REPICK ? RR : 1][REPICK ? NRUN * RUN : 1];
     __shared__ int s_xmax;
 
     const int tid = threadIdx.x;
@@ -267,6 +268,7 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
                         ris[0] = Sis[sy][w];
                     }
                     acc_t sr = 0;
+                    float ev[RUN];
 #pragma unroll
                     for (int b = 0; b <= 2 * NW; ++b) sr += (su + b < EC) ? V[u][sy][su + b] : (acc_t)0;
 #pragma unroll
@@ -282,13 +284,30 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
                         const bool valid = sxa[q] >= zu && zu <= zend;
                         const float c = (float)fma(-nmul[q], rmu[q], (double)sr);
                         const float e = valid ? fminf(1.f, fmaxf(-1.f, c * isl[q] * ris[q])) : 0.f;
-                        if constexpr (REPICK) {
-                            if (su + q < RC) Es[u][sy][su + q] = e;
-                        } else {
+                        ev[q] = e;
+                        if constexpr (!REPICK) {
                             // the scorer of (sy, su + q) owns it
                             const bool better = act[q] && valid && e > best[q];
                             best[q] = better ? e : best[q];
                             bz[q] = better ? zu : bz[q];
+                        }
+                    }
+                    if constexpr (REPICK) {
+                        // the run's suffix sums (SUF[c] = e[c] + .. + e[end of
+                        // run]) and prefix sums (PRE[start + k] = the run's
+                        // first k scores): a 5-column sum starting at c is
+                        // SUF[c] + PRE[c + 5]
+                        float acc = 0.f;
+#pragma unroll
+                        for (int q = RUN - 1; q >= 0; --q) {
+                            acc += ev[q];
+                            SUF[u][sy][su + q] = acc;
+                        }
+                        acc = 0.f;
+#pragma unroll
+                        for (int q = 0; q < RUN; ++q) {
+                            PRE[u][sy][su + q] = acc;
+                            acc += ev[q];
                         }
                     }
                 }
@@ -296,22 +315,17 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
             __syncthreads();
             if constexpr (REPICK) {
                 // 5x5 sums of the scores (0 where a neighbour does not count):
-                // each wave forms the 5-column sums of 3 region rows, then each
-                // thread the 5-row sums of its two output pixels
-                const int c0 = tid & 63, w3 = 3 * (tid >> 6);
-#pragma unroll
-                for (int u = 0; u < ZU; ++u)
-#pragma unroll
-                    for (int t = 0; t < 3; ++t)
-                        Hs[u][w3 + t][c0] = Es[u][w3 + t][c0] + Es[u][w3 + t][c0 + 1] + Es[u][w3 + t][c0 + 2] +
-                                            Es[u][w3 + t][c0 + 3] + Es[u][w3 + t][c0 + 4];
-                __syncthreads();
-                const int r0 = oy[0];
+                // the 5-column sums of six region rows, then the 5-row sums of
+                // the thread's two output pixels
+                const int c0 = tid & 63, r0 = oy[0];
 #pragma unroll
                 for (int u = 0; u < ZU; ++u) {
                     const int zu = z + u;
-                    const float mid = Hs[u][r0 + 1][c0] + Hs[u][r0 + 2][c0] + Hs[u][r0 + 3][c0] + Hs[u][r0 + 4][c0];
-                    const float sum[2] = {Hs[u][r0][c0] + mid, mid + Hs[u][r0 + 5][c0]};
+                    float hs[6];
+#pragma unroll
+                    for (int t = 0; t < 6; ++t) hs[t] = SUF[u][r0 + t][c0] + PRE[u][r0 + t][c0 + 5];
+                    const float mid = hs[1] + hs[2] + hs[3] + hs[4];
+                    const float sum[2] = {hs[0] + mid, mid + hs[5]};
 #pragma unroll
                     for (int p = 0; p < 2; ++p) {
                         const int j = x0 + ox[p];
