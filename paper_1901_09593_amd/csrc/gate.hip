@@ -98,7 +98,6 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
     static_assert(RR % VG == 0, "row groups");
     static_assert(EC * NVG <= GT_THREADS && RR * NRUN <= GT_THREADS, "one item per thread");
 
-    __shared__ float Ls[ER][EC];
     __shared__ float Rs[ER][RSW];
     __shared__ acc_t V[ZU][RR][EC];
     __shared__ double Smu[RR][SSW];
@@ -155,9 +154,14 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
     if (xmax < 0) return;  // uniform: no gated pixel in the tile
     const int zmax = min(a.Dk - 1, xmax);
 
-    for (int idx = tid; idx < ER * EC; idx += GT_THREADS) {
-        const int v = idx / EC, e = idx - v * EC;
-        Ls[v][e] = pix<T>(a.L, a.pitch, clampi(ey0 + v, 0, H - 1), clampi(ex0 + e, 0, W - 1));
+    // the left column a column-sum thread multiplies at every candidate, held
+    // in registers (the left tile does not move with z; clamped reads)
+    float lcol[VG + 2 * NW];
+    {
+        const int g = min(tid / EC, NVG - 1), e = tid - (tid / EC) * EC;
+#pragma unroll
+        for (int t = 0; t < VG + 2 * NW; ++t)
+            lcol[t] = pix<T>(a.L, a.pitch, clampi(ey0 + g * VG + t, 0, H - 1), clampi(ex0 + e, 0, W - 1));
     }
 
     // left statistics of the scored region pixels (N mu_l, 1/sqrt(A_l))
@@ -193,15 +197,6 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
 
     double rmu[RUN];  // right window means and 1/sqrt(A) of the scored run
     float ris[RUN];
-    // the left column a column-sum thread multiplies at every candidate, kept
-    // in registers (the left tile does not move with z)
-    float lcol[VG + 2 * NW];
-    __syncthreads();
-    {
-        const int g = tid / EC, e = tid - g * EC;
-#pragma unroll
-        for (int t = 0; t < VG + 2 * NW; ++t) lcol[t] = tid < EC * NVG ? Ls[g * VG + t][e] : 0.f;
-    }
 
     for (int z0 = 0; z0 <= zmax; z0 += GT_ZC) {
         const int zhi = z0 + GT_ZC - 1;
