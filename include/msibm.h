@@ -154,9 +154,11 @@ msibm_status msibm_force_variant(int32_t variant);
 /*
  * msibm_autotune - with enable != 0, the first launch of each matching shape
  * (mode, n, candidates per window, dtype, H, W, D_k) not yet in the table is
- * timed in every applicable kernel shape (one warm-up and three launches each,
- * synchronising the caller's stream; never while the stream is being captured)
- * and the fastest is used from then on.  cache_path (may be NULL) names a text
+ * timed in every applicable kernel shape (three interleaved rounds of one
+ * warm-up and three launches each, synchronising the caller's stream; never
+ * while the stream is being captured); the default shape is kept unless
+ * another's best round is at least 2% faster, and the choice is used from then
+ * on.  cache_path (may be NULL) names a text
  * file read now and rewritten after each new measurement, one line per shape:
  * "mode n nc dtype H W Dk variant microseconds".  The environment variables
  * MSIBM_AUTOTUNE=1 and MSIBM_TUNE_CACHE=<path> do the same at load time.

@@ -180,13 +180,23 @@ int select_variant(const MatchArgs& a, int n, int dtype, int mode, int nc, hipSt
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
         return default_variant(a, mode) & valid;
+    // three interleaved rounds, the fastest time of each shape; the default
+    // shape is kept unless another is at least 2% faster (single timings
+    // differ by about that much from run to run)
+    float t_min[VARIANT_MASK + 1];
+    for (int v = 0; v <= VARIANT_MASK; ++v) t_min[v] = -1.f;
+    for (int round = 0; round < 3; ++round)
+        for (int v = 0; v <= VARIANT_MASK; ++v) {
+            if (v & ~valid) continue;
+            const float us = time_variant(a, v, n, dtype, mode, nc, s);
+            if (us >= 0.f && (t_min[v] < 0.f || us < t_min[v])) t_min[v] = us;
+        }
     int best = default_variant(a, mode) & valid;
-    float best_us = -1.f;
+    float best_us = t_min[best];
     for (int v = 0; v <= VARIANT_MASK; ++v) {
-        if (v & ~valid) continue;
-        const float us = time_variant(a, v, n, dtype, mode, nc, s);
-        if (us >= 0.f && (best_us < 0.f || us < best_us)) {
-            best_us = us;
+        if (t_min[v] < 0.f) continue;
+        if (best_us < 0.f || t_min[v] < 0.98f * best_us) {
+            best_us = t_min[v];
             best = v;
         }
     }
