@@ -228,3 +228,69 @@ def test_gated_mid1436_level0_sampled(M):
     vis = p.nonocc
     err = np.abs(hd.astype(np.float64) - p.disp)
     print("gated mid1436 bad>2px", float((err[vis] > 2).mean()))
+
+
+@pytest.mark.parametrize("H,W,D,n", [(1, 1, 4, 2), (2, 3, 5, 1), (1, 70, 30, 3), (70, 1, 8, 2), (9, 130, 1, 6)])
+def test_gating_degenerate_shapes(M, H, W, D, n):
+    """Single pixels, single rows and columns, one candidate, the largest window:
+    both gating steps follow the oracle."""
+    rng = np.random.Generator(np.random.PCG64(H * 100 + W))
+    L = rng.integers(0, 256, (H, W)).astype(np.uint8)
+    R = rng.integers(0, 256, (H, W)).astype(np.uint8)
+    Lg, Rg = dev(L), dev(R)
+    Hc, Wc = (H + 1) // 2, (W + 1) // 2
+    prior = rng.integers(0, max(1, (D + 1) // 2), (Hc, Wc)).astype(np.int16)
+    pcost = (rng.random((Hc, Wc)) * 2 - 1).astype(np.float32)
+    for beta in (0.0, 2.0):
+        d, C = M.match_level_gated(Lg, Rg, n, D, dev(prior), dev(pcost), 1, beta, 0.065)
+        _check_gated(host(d), host(C), L.astype(np.float64), R.astype(np.float64), n, D, prior, pcost, 1, beta,
+                     0.065)
+    d1, C1 = M.match_level(Lg, Rg, n, D, None, 0, 0.065)
+    for alpha in (0.3, 2.0):
+        d, C = M.aggregate_refine(Lg, Rg, n, D, d1, C1, alpha, 0.065)
+        _check_repick(host(d), host(C), L.astype(np.float64), R.astype(np.float64), n, D, host(d1), host(C1),
+                      alpha, 0.065)
+
+
+def test_gating_pitched_images_and_largest_range(M):
+    """Row-pitched inputs, and a range of 2048 candidates (every tile walks up
+    to 2048 candidates; the right-most pixels checked against the oracle)."""
+    rng = np.random.Generator(np.random.PCG64(77))
+    H, W, D, n = 12, 2100, 2048, 2
+    base = synth.texture(rng, H, W + 40) * 255
+    wide_L = np.zeros((H, W + 11), np.float32)
+    wide_R = np.zeros((H, W + 11), np.float32)
+    wide_L[:, :W] = base[:, :W]          # a shift of 40: R(x - 40) = L(x)
+    wide_R[:, :W] = base[:, 40:40 + W]
+    Lg, Rg = dev(wide_L)[:, :W], dev(wide_R)[:, :W]
+    assert Lg.stride(0) == W + 11
+    d1, C1 = M.match_level(Lg, Rg, n, D, None, 0, 1e-6)
+    C1 = torch.where(torch.arange(W, device="cuda")[None, :] % 97 == 0, torch.full_like(C1, -1.0), C1)
+    d, C = M.aggregate_refine(Lg, Rg, n, D, d1, C1, 0.9, 1e-6)
+    L64, R64 = wide_L[:, :W].astype(np.float64), wide_R[:, :W].astype(np.float64)
+    picked = ~(host(C1).astype(np.float64) > 0.9)
+    ii, jj = np.nonzero(picked)
+    sel = np.argsort(-jj)[:40]  # the largest columns: the longest candidate walks
+    ii, jj = ii[sel], jj[sel]
+    do, Co, C2o = oracle.aggregate_pixels(L64, R64, n, D, host(d1), host(C1).astype(np.float64), 0.9, 1e-6, ii, jj)
+    hd, hC = host(d), host(C)
+    e_at = oracle.avg_score_many(L64, R64, n, ii, jj, hd[ii, jj], 1e-6)
+    assert np.abs(hC[ii, jj] - e_at).max() <= TOL_ZNCC
+    assert not ((hd[ii, jj] != do) & ((Co - C2o) > TOL_ZNCC)).any()
+    # the same on contiguous copies
+    d2, C2 = M.aggregate_refine(Lg.contiguous(), Rg.contiguous(), n, D, d1, C1, 0.9, 1e-6)
+    assert torch.equal(d2, d) and torch.equal(C2, C)
+
+
+def test_gated_forward_tiny_and_single_level(M):
+    """The gated forward on a single level (only the re-pick runs) and on an
+    image smaller than one tile, against the oracle's gated hierarchy."""
+    for (H, W, D, K) in ((5, 7, 6, 1), (30, 50, 16, 3), (1, 9, 4, 2)):
+        rng = np.random.Generator(np.random.PCG64(H + W))
+        p = synth.make_pair(H + W, max(H, 8), max(W, 8), 2, 1, max(2, D // 2), False, 1.0, 0.0, 2.0, "u8")
+        L, R = np.ascontiguousarray(p.left[:H, :W]), np.ascontiguousarray(p.right[:H, :W])
+        out = M.disparity(dev(L), dev(R), D, K, 1, 1, 0.065, gate=(0.9, 0.9))
+        ref = oracle.disparity(L, R, D, K, 1, 1, 0.065, gate=(0.9, 0.9))
+        mism = float((host(out["disp"]) != ref[0][0]).mean())
+        print(H, W, D, K, "mismatch", mism)
+        assert mism <= 0.05

@@ -134,3 +134,25 @@ def test_autograd_every_level_loss(M):
     grads = [np.full(tuple(s.shape), w) for w, s in zip((1.0, 0.5), softs)] + [None]
     oL, oR = oracle.backward_levels(L, R, D, K, n, rs, tau, eps, [host(m) for m in maps], grads)
     assert rel(host(Lt.grad), oL) <= REL_TOL and rel(host(Rt.grad), oR) <= REL_TOL
+
+
+@pytest.mark.parametrize("H,W,K", [(1, 1, 2), (3, 2, 3), (200, 300, 8)])
+def test_levels_degenerate_and_deepest(M, H, W, K):
+    """One pixel, tiny levels, and the deepest pyramid (levels down to 2 x 3):
+    the soft levels and the gradient against the oracle."""
+    rng = np.random.Generator(np.random.PCG64(H * W + K))
+    L = rng.random((H, W)).astype(np.float32)
+    R = rng.random((H, W)).astype(np.float32)
+    D, n, rs, tau, eps = 40, 1, 1, 0.1, 1e-6
+    soft, maps = M.disparity_levels(dev(L), dev(R), D, K, n, eps, rs, tau)
+    PL, PR = M.pyramid(dev(L), K), M.pyramid(dev(R), K)
+    for k in range(K - 1):
+        ds_o = oracle.soft_level0(host(PL[k]).astype(np.float64), host(PR[k]).astype(np.float64), n,
+                                  -(-D // (1 << k)), host(maps[k + 1]), rs, tau, eps)[0]
+        assert np.abs(host(soft[k]) - ds_o).max() <= 1e-2, k
+    grads = [rng.standard_normal(tuple(s.shape)).astype(np.float32) for s in soft]
+    gL, gR = M.backward_levels(dev(L), dev(R), maps, [dev(g) for g in grads], D, K, n, eps, rs, tau)
+    oL, oR = oracle.backward_levels(L, R, D, K, n, rs, tau, eps, [host(m) for m in maps],
+                                    [g.astype(np.float64) for g in grads] + [None])
+    scale = max(np.linalg.norm(oL), np.linalg.norm(oR), 1e-12)
+    assert np.linalg.norm(host(gL) - oL) <= REL_TOL * scale and np.linalg.norm(host(gR) - oR) <= REL_TOL * scale
