@@ -8,8 +8,13 @@
  * winner-take-all search of the zero-mean normalised cross-correlation (ZNCC,
  * Eq. 2) over the disparity search image of Eq. 1 (Eqs. 3-4), then at each finer
  * level search only a small interval around the nearest-neighbour-upsampled
- * coarser disparity (Eqs. 8-9, first branch).  The confidence gates and the
- * median filter (Eqs. 5-7, 10) are not part of this library.
+ * coarser disparity (Eqs. 8-9, first branch).  On the plain per-pair forward
+ * the library also runs the paper's optional steps: the confidence gating
+ * (the full search where the bicubic-doubled coarser cost is low, Eqs. 8-9
+ * second branch; the re-pick by neighbourhood-averaged scores, Eqs. 5-7), the
+ * selective median filter (Eq. 10) and a blurred level 0.  Two additions are not
+ * in the paper: a differentiable finest level (soft-argmax with its backward)
+ * and a soft output at every level with the backward through the pyramid.
  *
  * Conventions used by every entry point
  *   - All image, map and gradient pointers are DEVICE pointers allocated by the
