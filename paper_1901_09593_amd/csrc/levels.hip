@@ -224,44 +224,91 @@ __device__ __forceinline__ void cswap(int& a, int& b)
     b = hi;
 }
 
+// Selective median (Eq. 10), one 64 x 4 tile per workgroup (one pixel per
+// thread: the small levels need the workgroups).  The tile and its
+// 2-pixel ring are staged in LDS once as sort keys: a neighbour's disparity
+// where it lies in the image and its cost exceeds alpha (a good pixel), else
+// INT_MAX.  A filtered pixel sorts its 25 keys (with 7 more INT_MAX, a 32-key
+// bitonic network; comparators against the constant INT_MAX padding fold away
+// at compile time) and takes the lower median of the good ones, the keys below
+// INT_MAX; disparities are int16, so no disparity equals INT_MAX.
+constexpr int MD_W = 64, MD_H = 4;
 __global__ __launch_bounds__(256) void median_kernel(MedianArgs a)
 {
-    const int j = blockIdx.x * 64 + (threadIdx.x & 63), i = blockIdx.y * 4 + (threadIdx.x >> 6);
-    if (i >= a.H || j >= a.W) return;
-    const int d0 = a.d_in[(size_t)i * a.ipitch + j];
-    int out = d0;
-    if (!((double)a.cost[(size_t)i * a.cpitch + j] > a.alpha)) {
-        int v[32], m = 0;
-#pragma unroll
-        for (int t = 0; t < 32; ++t) v[t] = 32767;
-#pragma unroll
-        for (int q = 0; q < 25; ++q) {
-            const int y = i + q / 5 - 2, x = j + q % 5 - 2;
-            const bool in = y >= 0 && y < a.H && x >= 0 && x < a.W;
-            const int yy = min(max(y, 0), a.H - 1), xx = min(max(x, 0), a.W - 1);
-            const bool good = in && (double)a.cost[(size_t)yy * a.cpitch + xx] > a.alpha;
-            v[q] = good ? (int)a.d_in[(size_t)yy * a.ipitch + xx] : 32767;
-            m += good ? 1 : 0;
-        }
-#pragma unroll
-        for (int k = 2; k <= 32; k <<= 1)
-#pragma unroll
-            for (int jj = k >> 1; jj > 0; jj >>= 1)
-#pragma unroll
-                for (int t = 0; t < 32; ++t) {
-                    const int l = t ^ jj;
-                    if (l > t) {
-                        if ((t & k) == 0) cswap(v[t], v[l]);
-                        else cswap(v[l], v[t]);
-                    }
-                }
-        const int want = (m - 1) / 2;
-        int med = d0;
-#pragma unroll
-        for (int t = 0; t < 25; ++t) med = (t == want) ? v[t] : med;
-        if (m > 0) out = med;
+    __shared__ int key[MD_H + 4][MD_W + 4];
+    __shared__ int any_filtered;
+    const int x0 = blockIdx.x * MD_W, y0 = blockIdx.y * MD_H;
+    const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;  // the thread's pixel
+    if (threadIdx.x == 0) any_filtered = 0;
+    for (int idx = threadIdx.x; idx < (MD_H + 4) * (MD_W + 4); idx += 256) {
+        const int rr = idx / (MD_W + 4), cc = idx - rr * (MD_W + 4);
+        const int y = y0 - 2 + rr, x = x0 - 2 + cc;
+        int k = INT_MAX;
+        if (y >= 0 && y < a.H && x >= 0 && x < a.W && (double)a.cost[(size_t)y * a.cpitch + x] > a.alpha)
+            k = a.d_in[(size_t)y * a.ipitch + x];
+        key[rr][cc] = k;
     }
-    a.d_out[(size_t)i * a.opitch + j] = (int16_t)out;
+    __syncthreads();
+    constexpr int Q = MD_H / 4;  // pixels per thread
+    int dv[Q];
+    bool filt[Q];
+    bool some = false;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int i = y0 + r0 + q, j = x0 + c;
+        filt[q] = false;
+        dv[q] = 0;
+        if (i < a.H && j < a.W) {
+            dv[q] = a.d_in[(size_t)i * a.ipitch + j];
+            filt[q] = !((double)a.cost[(size_t)i * a.cpitch + j] > a.alpha);
+        }
+        some = some || filt[q];
+    }
+    if (some) any_filtered = 1;
+    __syncthreads();
+    if (!any_filtered) {
+        // no pixel of the tile is filtered: copy
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int i = y0 + r0 + q, j = x0 + c;
+            if (i < a.H && j < a.W) a.d_out[(size_t)i * a.opitch + j] = (int16_t)dv[q];
+        }
+        return;
+    }
+#pragma unroll 1
+    for (int q = 0; q < Q; ++q) {
+        const int i = y0 + r0 + q, j = x0 + c;
+        if (i >= a.H || j >= a.W) continue;
+        int out = dv[q];
+        if (filt[q]) {
+            int v[32];
+#pragma unroll
+            for (int t = 0; t < 25; ++t) v[t] = key[r0 + q + t / 5][c + t % 5];
+#pragma unroll
+            for (int t = 25; t < 32; ++t) v[t] = INT_MAX;
+#pragma unroll
+            for (int k = 2; k <= 32; k <<= 1)
+#pragma unroll
+                for (int jj = k >> 1; jj > 0; jj >>= 1)
+#pragma unroll
+                    for (int t = 0; t < 32; ++t) {
+                        const int l = t ^ jj;
+                        if (l > t) {
+                            if ((t & k) == 0) cswap(v[t], v[l]);
+                            else cswap(v[l], v[t]);
+                        }
+                    }
+            int m = 0;
+#pragma unroll
+            for (int t = 0; t < 25; ++t) m += v[t] != INT_MAX;
+            const int want = (m - 1) / 2;
+            int med = out;
+#pragma unroll
+            for (int t = 0; t < 13; ++t) med = (t == want) ? v[t] : med;
+            if (m > 0) out = med;
+        }
+        a.d_out[(size_t)i * a.opitch + j] = (int16_t)out;
+    }
 }
 
 // Weight with which coarse row (or column) y of a reduce step reads fine row p:
@@ -308,7 +355,7 @@ hipError_t launch_adjoint(const AdjArgs& a, hipStream_t s)
 
 hipError_t launch_median(const MedianArgs& a, hipStream_t s)
 {
-    dim3 grid((a.W + 63) / 64, (a.H + 3) / 4, 1);
+    dim3 grid((a.W + MD_W - 1) / MD_W, (a.H + MD_H - 1) / MD_H, 1);
     hipLaunchKernelGGL(median_kernel, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
