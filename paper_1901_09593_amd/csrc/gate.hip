@@ -84,7 +84,6 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
     constexpr int ER = RR + 2 * NW;                    // plus the windows' halo
     constexpr int EC = RC + 2 * NW;
     constexpr int RSW = EC + GT_ZC - 1;                // staged right columns per chunk
-    constexpr int SSW = RC + GT_ZC - 1;                // staged right statistics per chunk
     constexpr double NN = (double)((2 * NW + 1) * (2 * NW + 1));
     constexpr int VG = 4;                              // rows of column sums per thread
     constexpr int NVG = RR / VG;
@@ -100,8 +99,6 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
 
     __shared__ float Rs[ER][RSW];
     __shared__ acc_t V[ZU][RR][EC];
-    __shared__ double Smu[RR][SSW];
-    __shared__ float Sis[RR][SSW];
     // suffix and prefix sums of the scores along each scoring run (re-pick)
     __shared__ float SUF[ZU][REPICK ? RR : 1][REPICK ? NRUN * RUN : 1];
     __shared__ float PRE[ZU][REPICK ? RR : 1][REPICK ? NRUN * RUN : 1];
@@ -195,8 +192,20 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
         rcp3[p] = 1.f / (float)(rows_in * cols_r);
     }
 
-    double rmu[RUN];  // right window means and 1/sqrt(A) of the scored run
+    // right window means and 1/sqrt(A) of the scored run at the current
+    // candidate (read from global memory: one new value per candidate)
+    double rmu[RUN];
     float ris[RUN];
+    const WinStat* srow = a.statR + (size_t)clampi(ry0 + sy, 0, H - 1) * a.spitch;
+    WinStat nxt{};
+    if (scorer) {
+#pragma unroll
+        for (int q = 0; q < RUN; ++q) {
+            const WinStat st = srow[clampi(rx0 + su + q, 0, W - 1)];
+            rmu[q] = (double)st.x + (double)st.y;
+            ris[q] = st.z;
+        }
+    }
 
     for (int z0 = 0; z0 <= zmax; z0 += GT_ZC) {
         const int zhi = z0 + GT_ZC - 1;
@@ -204,13 +213,6 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
         for (int idx = tid; idx < ER * RSW; idx += GT_THREADS) {
             const int v = idx / RSW, w = idx - v * RSW;
             Rs[v][w] = pix<T>(a.R, a.pitch, clampi(ey0 + v, 0, H - 1), clampi(ex0 - zhi + w, 0, W - 1));
-        }
-        for (int idx = tid; idx < RR * SSW; idx += GT_THREADS) {
-            const int y = idx / SSW, w = idx - y * SSW;
-            const WinStat st = a.statR[(size_t)clampi(ry0 + y, 0, H - 1) * a.spitch +
-                                       clampi(rx0 - zhi + w, 0, W - 1)];
-            Smu[y][w] = (double)st.x + (double)st.y;
-            Sis[y][w] = st.z;
         }
         __syncthreads();
         const int zend = min(zhi, zmax);
@@ -242,26 +244,20 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
             if (scorer) {
 #pragma unroll
                 for (int u = 0; u < ZU; ++u) {
-                    const int zu = z + u, zz = max(zhi - zu, 0);
+                    const int zu = z + u;
                     // right statistics of the run: column q at candidate z is
-                    // column q - 1 at z - 1, so one new value per candidate
-                    if (zu == 0) {
-#pragma unroll
-                        for (int q = 0; q < RUN; ++q) {
-                            const int w = min(su + q + zz, SSW - 1);
-                            rmu[q] = Smu[sy][w];
-                            ris[q] = Sis[sy][w];
-                        }
-                    } else {
+                    // column q - 1 at z - 1, so one new value per candidate,
+                    // loaded one candidate ahead
+                    if (zu > 0) {
 #pragma unroll
                         for (int q = RUN - 1; q > 0; --q) {
                             rmu[q] = rmu[q - 1];
                             ris[q] = ris[q - 1];
                         }
-                        const int w = min(su + zz, SSW - 1);
-                        rmu[0] = Smu[sy][w];
-                        ris[0] = Sis[sy][w];
+                        rmu[0] = (double)nxt.x + (double)nxt.y;
+                        ris[0] = nxt.z;
                     }
+                    nxt = srow[clampi(rx0 + su - (zu + 1), 0, W - 1)];
                     acc_t sr = 0;
                     float ev[RUN];
 #pragma unroll
