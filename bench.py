@@ -255,11 +255,13 @@ def section_accuracy(torch, M, synth, steps):
 
 def section_gated(torch, M, synth, steps):
     """The paper's confidence gating (Eqs. 5-9) on the 1436x992 pair: time per
-    pair, per-kernel times, and the work of the two level-0 gate launches.  A
-    gate launch scores, for every tile (8 x 64 pixels) holding a gated pixel,
-    every region pixel (the tile, plus a 2-pixel ring for the re-pick) at every
-    candidate up to the tile's last gated column's range; the scores per launch
-    are counted here from the same inputs the launch sees."""
+    pair, per-kernel times, and the work of the level-0 gate launch (the
+    fallback full search and the re-pick fused in one walk).  It scores, for
+    every tile (8 x 64 pixels) holding a pixel that takes the fallback search
+    or whose restricted-search cost is at most alpha, every region pixel (the
+    tile plus a 2-pixel ring) at every candidate up to the tile's last such
+    column's range; the scores per launch are counted here from the same inputs
+    the launch sees."""
     dev = torch.device("cuda:0")
     p, cfg = synth.workload("mid1436")
     H, W, D, K, n, r, eps = cfg.height, cfg.width, cfg.max_disp, cfg.levels, cfg.half_window, \
@@ -284,8 +286,10 @@ def section_gated(torch, M, synth, steps):
     assert torch.equal(lvl1["disp"], M.disparity(Lg, Rg, D, K, n, r, eps, gate=gate, with_prior1=True)["prior1"])
     up = M.upsample_cost(lvl1["cost"], H, W)
     d1, C1 = M.match_level_gated(Lg, Rg, n, D, lvl1["disp"], lvl1["cost"], r, gate[1], eps)
+    _, Cr = M.match_level(Lg, Rg, n, D, lvl1["disp"], r, eps)
     full_mask = (~(up > gate[1])).cpu().numpy()
     pick_mask = (~(C1.double() > gate[0])).cpu().numpy()
+    walk_mask = full_mask | (~(Cr.double() > gate[0])).cpu().numpy()
 
     def scores(mask, halo):
         th, tw = 8, 64
@@ -302,10 +306,9 @@ def section_gated(torch, M, synth, steps):
                        f"refine +-{r}, gating alpha {gate[0]} beta {gate[1]}",
            "ms_per_pair": ms, "kernels_us": kern,
            "level0_full_search_fraction": float(full_mask.mean()), "level0_repick_fraction": float(pick_mask.mean())}
-    for label, mask, halo in (("gate_full_l0", full_mask, 0), ("gate_repick_l0", pick_mask, 2)):
-        sc = scores(mask, halo)
-        us = kern[label]
-        res[label] = {"avg_us": us, "region_scores_per_launch": sc, "scores_per_s": sc / (us * 1e-6)}
+    sc = scores(walk_mask, 2)
+    us = kern["gate_fused_l0"]
+    res["gate_fused_l0"] = {"avg_us": us, "region_scores_per_launch": sc, "scores_per_s": sc / (us * 1e-6)}
     return res
 
 
@@ -419,6 +422,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="wall time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tune-cache", default=None,
+                    help="kernel-shape table to read and extend (profiling runs reuse a plain run's choices)")
     ap.add_argument("--sections", default="batched,fwd_bwd,accuracy,gated,levels",
                     help="extra sections beside the headline step: batched, fwd_bwd, accuracy, gated, levels, "
                          "or none")
@@ -449,7 +454,9 @@ def main():
     sections = [s for s in args.sections.split(",") if s and s != "none"]
 
     if not args.no_tune:
-        msibm.autotune(True)  # first use of each level shape measures its kernel shapes
+        # first use of each level shape measures its kernel shapes (or takes
+        # them from the cache file, which profiling runs share with a plain one)
+        msibm.autotune(True, args.tune_cache)
     p, cfg = synth.workload("mid1436")
     H, W, D, K, n, r, eps = cfg.height, cfg.width, cfg.max_disp, cfg.levels, cfg.half_window, \
         cfg.refine_radius, cfg.var_eps

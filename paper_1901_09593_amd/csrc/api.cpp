@@ -389,7 +389,7 @@ msibm_status msibm_match_level_gated(const void* L, const void* R, int32_t dtype
     g.Hc = Hc;
     g.Wc = Wc;
     g.cpitch = prior_pitch;
-    const hipError_t e = launch_gate(n, dtype, false, g, (hipStream_t)stream);
+    const hipError_t e = launch_gate(n, dtype, GATE_MODE_FULL, g, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "gated full search launch");
     return ok();
 }
@@ -420,7 +420,7 @@ msibm_status msibm_aggregate_refine(const void* L, const void* R, int32_t dtype,
     sa.var_eps = var_eps;
     hipError_t e = launch_stats(sa, s);
     if (e != hipSuccess) return hip_fail(e, "stats launch");
-    e = launch_gate(n, dtype, true, g, s);
+    e = launch_gate(n, dtype, GATE_MODE_REPICK, g, s);
     if (e != hipSuccess) return hip_fail(e, "re-pick launch");
     return ok();
 }

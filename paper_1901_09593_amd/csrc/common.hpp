@@ -111,7 +111,10 @@ struct MedianArgs {
 // Confidence gating of one level (Eqs. 5-9), in place on its map d and cost c.
 // Full-search mode: pixels whose bicubic-upsampled coarser cost is at most
 // `thresh` (beta) take the full search.  Re-pick mode: pixels whose cost is at
-// most `thresh` (alpha) take the argmax of the 5x5-averaged scores.
+// most `thresh` (alpha) take the argmax of the 5x5-averaged scores.  Fused
+// mode: both, the full search where the doubled cost is at most `thresh2`
+// (beta), then the re-pick where the resulting cost is at most `thresh`.
+enum GateMode { GATE_MODE_FULL = 0, GATE_MODE_REPICK = 1, GATE_MODE_FUSED = 2 };
 struct GateArgs {
     const void* L;
     const void* R;
@@ -126,6 +129,7 @@ struct GateArgs {
     const float* ccost;         // coarser level's cost (full-search mode)
     int Hc, Wc, cpitch;
     double thresh;
+    double thresh2;
 };
 
 // Adjoint of one pyramid step for up to two views: out (fine, H x W) +=
@@ -233,7 +237,7 @@ hipError_t launch_tower(int dtype, const TowerArgs& a, hipStream_t s);
 hipError_t launch_blur(int dtype, const BlurArgs& a, hipStream_t s);
 hipError_t launch_median(const MedianArgs& a, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& a, hipStream_t s);
-hipError_t launch_gate(int n, int dtype, bool repick, const GateArgs& a, hipStream_t s);
+hipError_t launch_gate(int n, int dtype, int mode, const GateArgs& a, hipStream_t s);
 hipError_t launch_upsample_cost(const float* cc, int Hc, int Wc, int cpitch, int H, int W, double* out,
                                 int opitch, hipStream_t s);
 hipError_t launch_match(int n, int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);

@@ -75,9 +75,17 @@ __device__ __forceinline__ float pix(const void* img, int pitch, int y, int x)
     return (float)((const T*)img)[(size_t)y * pitch + x];
 }
 
-template <typename T, int NW, bool REPICK>
+// MODE: GATE_FULL (the fallback full search), GATE_REPICK (the averaged-score
+// re-pick), GATE_FUSED (both in one walk: the fallback search's scores of the
+// tile pixels are region scores of the re-pick, and the re-pick decision needs
+// the fallback's result only at the end).
+constexpr int GATE_FULL = GATE_MODE_FULL, GATE_REPICK = GATE_MODE_REPICK, GATE_FUSED = GATE_MODE_FUSED;
+
+template <typename T, int NW, int MODE>
 __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
 {
+    constexpr bool REPICK = MODE != GATE_FULL;
+    constexpr bool FUSED = MODE == GATE_FUSED;
     constexpr int HB = REPICK ? 2 : 0;                 // halo of the averaged scores
     constexpr int RR = GT_H + 2 * HB;                  // region scored at each z
     constexpr int RC = GT_W + 2 * HB;
@@ -103,6 +111,10 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
     __shared__ float SUF[ZU][REPICK ? RR : 1][REPICK ? NRUN * RUN : 1];
     __shared__ float PRE[ZU][REPICK ? RR : 1][REPICK ? NRUN * RUN : 1];
     __shared__ int s_xmax;
+    // fused: which tile pixels take the fallback search, and its results
+    __shared__ int fgs[FUSED ? GT_H : 1][FUSED ? GT_W : 1];
+    __shared__ float fbe[FUSED ? GT_H : 1][FUSED ? GT_W : 1];
+    __shared__ int fbz[FUSED ? GT_H : 1][FUSED ? GT_W : 1];
 
     const int tid = threadIdx.x;
     const int x0 = blockIdx.x * GT_W, y0 = blockIdx.y * GT_H;
@@ -128,6 +140,7 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
         }
     }
     bool act[OWN];
+    bool fg[OWN];     // fused: the pixel takes the fallback search
     float best[OWN];
     int bz[OWN];
     if (tid == 0) s_xmax = -1;
@@ -136,15 +149,22 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
     for (int p = 0; p < OWN; ++p) {
         const int i = y0 + oy[p], j = x0 + ox[p];
         act[p] = false;
+        fg[p] = false;
         best[p] = -3.0f;  // below every score
         bz[p] = 0;
         if (oy[p] < GT_H && ox[p] < GT_W && i < H && j < W) {
-            if constexpr (REPICK)
+            if constexpr (MODE == GATE_REPICK) {
                 act[p] = !((double)a.c[(size_t)i * a.opitch + j] > a.thresh);
-            else
+            } else if constexpr (MODE == GATE_FULL) {
                 act[p] = !(upsampled_cost(a.ccost, a.Hc, a.Wc, a.cpitch, i, j) > a.thresh);
+            } else {
+                // a fallback pixel may end up re-picked, so it walks too
+                fg[p] = !(upsampled_cost(a.ccost, a.Hc, a.Wc, a.cpitch, i, j) > a.thresh2);
+                act[p] = fg[p] || !((double)a.c[(size_t)i * a.opitch + j] > a.thresh);
+            }
             if (act[p]) atomicMax(&s_xmax, j);
         }
+        if constexpr (FUSED) fgs[oy[p]][ox[p]] = fg[p];
     }
     __syncthreads();
     const int xmax = s_xmax;
@@ -190,6 +210,20 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
         rcp5[p] = 1.f / (float)(rows_in * (cols_r + 2));
         rcp4[p] = 1.f / (float)(rows_in * (cols_r + 1));
         rcp3[p] = 1.f / (float)(rows_in * cols_r);
+    }
+
+    // fused: the scorer tracks the fallback search of the tile pixels it scores
+    bool sfg[RUN];
+    float fbest[RUN];
+    int fbzv[RUN];
+#pragma unroll
+    for (int q = 0; q < RUN; ++q) {
+        const int ty = sy - HB, tx = su + q - HB;
+        sfg[q] = false;
+        if constexpr (FUSED)
+            sfg[q] = scorer && ty >= 0 && ty < GT_H && tx >= 0 && tx < GT_W && fgs[ty][tx];
+        fbest[q] = -3.0f;
+        fbzv[q] = 0;
     }
 
     // right window means and 1/sqrt(A) of the scored run at the current
@@ -276,6 +310,11 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
                         const float c = (float)fma(-nmul[q], rmu[q], (double)sr);
                         const float e = valid ? fminf(1.f, fmaxf(-1.f, c * isl[q] * ris[q])) : 0.f;
                         ev[q] = e;
+                        if constexpr (FUSED) {
+                            const bool better = sfg[q] && valid && e > fbest[q];
+                            fbest[q] = better ? e : fbest[q];
+                            fbzv[q] = better ? zu : fbzv[q];
+                        }
                         if constexpr (!REPICK) {
                             // the scorer of (sy, su + q) owns it
                             const bool better = act[q] && valid && e > best[q];
@@ -331,26 +370,46 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
             }
         }
     }
+    if constexpr (FUSED) {
+        // the fallback results to their owners
+#pragma unroll
+        for (int q = 0; q < RUN; ++q)
+            if (sfg[q]) {
+                fbe[sy - HB][su + q - HB] = fbest[q];
+                fbz[sy - HB][su + q - HB] = fbzv[q];
+            }
+        __syncthreads();
+    }
 #pragma unroll
     for (int p = 0; p < OWN; ++p) {
         if (!act[p]) continue;
         const size_t o = (size_t)(y0 + oy[p]) * a.opitch + (x0 + ox[p]);
-        a.d[o] = (int16_t)bz[p];
-        a.c[o] = best[p];
+        if constexpr (FUSED) {
+            // Eqs. 8-9 (the fallback or the restricted search's result), then
+            // Eqs. 5-7 on that cost
+            const int d1 = fg[p] ? fbz[oy[p]][ox[p]] : (int)a.d[o];
+            const float c1 = fg[p] ? fbe[oy[p]][ox[p]] : a.c[o];
+            const bool pick = !((double)c1 > a.thresh);
+            a.d[o] = (int16_t)(pick ? bz[p] : d1);
+            a.c[o] = pick ? best[p] : c1;
+        } else {
+            a.d[o] = (int16_t)bz[p];
+            a.c[o] = best[p];
+        }
     }
 }
 
-template <typename T, bool REPICK>
+template <typename T, int MODE>
 hipError_t launch_gate_t(int n, const GateArgs& a, hipStream_t s)
 {
     dim3 grid((a.W + GT_W - 1) / GT_W, (a.H + GT_H - 1) / GT_H, 1);
     switch (n) {
-        case 1: hipLaunchKernelGGL((gate_kernel<T, 1, REPICK>), grid, dim3(GT_THREADS), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((gate_kernel<T, 2, REPICK>), grid, dim3(GT_THREADS), 0, s, a); break;
-        case 3: hipLaunchKernelGGL((gate_kernel<T, 3, REPICK>), grid, dim3(GT_THREADS), 0, s, a); break;
-        case 4: hipLaunchKernelGGL((gate_kernel<T, 4, REPICK>), grid, dim3(GT_THREADS), 0, s, a); break;
-        case 5: hipLaunchKernelGGL((gate_kernel<T, 5, REPICK>), grid, dim3(GT_THREADS), 0, s, a); break;
-        case 6: hipLaunchKernelGGL((gate_kernel<T, 6, REPICK>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((gate_kernel<T, 1, MODE>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((gate_kernel<T, 2, MODE>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((gate_kernel<T, 3, MODE>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((gate_kernel<T, 4, MODE>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((gate_kernel<T, 5, MODE>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((gate_kernel<T, 6, MODE>), grid, dim3(GT_THREADS), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -358,13 +417,18 @@ hipError_t launch_gate_t(int n, const GateArgs& a, hipStream_t s)
 
 }  // namespace
 
-hipError_t launch_gate(int n, int dtype, bool repick, const GateArgs& a, hipStream_t s)
+hipError_t launch_gate(int n, int dtype, int mode, const GateArgs& a, hipStream_t s)
 {
     if (a.H < 1 || a.W < 1 || a.Dk < 1) return hipErrorInvalidValue;
-    if (!repick && (a.Hc != (a.H + 1) / 2 || a.Wc != (a.W + 1) / 2)) return hipErrorInvalidValue;
-    if (dtype == MSIBM_U8)
-        return repick ? launch_gate_t<uint8_t, true>(n, a, s) : launch_gate_t<uint8_t, false>(n, a, s);
-    return repick ? launch_gate_t<float, true>(n, a, s) : launch_gate_t<float, false>(n, a, s);
+    if (mode != GATE_REPICK && (a.Hc != (a.H + 1) / 2 || a.Wc != (a.W + 1) / 2)) return hipErrorInvalidValue;
+    if (dtype == MSIBM_U8) {
+        if (mode == GATE_FULL) return launch_gate_t<uint8_t, GATE_FULL>(n, a, s);
+        if (mode == GATE_REPICK) return launch_gate_t<uint8_t, GATE_REPICK>(n, a, s);
+        return launch_gate_t<uint8_t, GATE_FUSED>(n, a, s);
+    }
+    if (mode == GATE_FULL) return launch_gate_t<float, GATE_FULL>(n, a, s);
+    if (mode == GATE_REPICK) return launch_gate_t<float, GATE_REPICK>(n, a, s);
+    return launch_gate_t<float, GATE_FUSED>(n, a, s);
 }
 
 hipError_t launch_upsample_cost(const float* cc, int Hc, int Wc, int cpitch, int H, int W, double* out,

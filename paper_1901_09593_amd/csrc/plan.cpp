@@ -236,25 +236,22 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
             g.d = a.d_out;
             g.c = a.c_out;
             g.opitch = a.opitch;
-            char glab[32];
+            // below the coarsest level one walk does both: the full search
+            // where the doubled coarser cost is low (Eqs. 8-9), then the
+            // re-pick of low-cost pixels (Eqs. 5-7); the coarsest re-picks only
+            g.thresh = cfg->gate_alpha;
+            g.thresh2 = cfg->gate_beta;
             if (!coarsest) {
-                // Eqs. 8-9: the full search where the doubled coarser cost is low
                 g.ccost = (const float*)(ws + lay.cmap[k + 1]);
                 g.Hc = lay.h[k + 1];
                 g.Wc = lay.w[k + 1];
                 g.cpitch = lay.w[k + 1];
-                g.thresh = cfg->gate_beta;
-                snprintf(glab, sizeof(glab), "gate_full_l%d", k);
-                TimedLaunch t(glab, s);
-                e = launch_gate(n, dtype_of(k), false, g, s);
-                if (e != hipSuccess) return hip_err(e, "gated full search launch", err);
             }
-            // Eqs. 5-7: the re-pick of low-cost pixels
-            g.thresh = cfg->gate_alpha;
-            snprintf(glab, sizeof(glab), "gate_repick_l%d", k);
+            char glab[32];
+            snprintf(glab, sizeof(glab), coarsest ? "gate_repick_l%d" : "gate_fused_l%d", k);
             TimedLaunch t(glab, s);
-            e = launch_gate(n, dtype_of(k), true, g, s);
-            if (e != hipSuccess) return hip_err(e, "re-pick launch", err);
+            e = launch_gate(n, dtype_of(k), coarsest ? GATE_MODE_REPICK : GATE_MODE_FUSED, g, s);
+            if (e != hipSuccess) return hip_err(e, "gating launch", err);
         }
         if (filt) {
             MedianArgs m{a.d_out, a.c_out, dest, lay.h[k], lay.w[k], lay.w[k], lay.w[k], lay.w[k],
