@@ -294,3 +294,42 @@ def test_gated_forward_tiny_and_single_level(M):
         mism = float((host(out["disp"]) != ref[0][0]).mean())
         print(H, W, D, K, "mismatch", mism)
         assert mism <= 0.05
+
+
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_paper_parameters_all_options_together(M, dtype):
+    """Every plain-path option at once, as the benchmark's paper-parameter row
+    runs it (halving windows, refine +-1, pre-blurred level 0, gating and the
+    median): the forward against the oracle's hierarchy with the same options,
+    and against the level-by-level chain of the entry points."""
+    p = _pair(500, 90, 180, 30, dtype, noise=6.0)
+    D, K, r = 48, 3, 1
+    ns = [5, 2, 1]
+    eps = _eps(dtype)
+    ab, malpha = (0.9, 0.9), 0.9
+    Lg, Rg = dev(p.left), dev(p.right)
+    out = M.disparity(Lg, Rg, D, K, ns, r, eps, with_prior1=True, preblur=True, gate=ab, median_alpha=malpha)
+    ref = oracle.disparity(p.left, p.right, D, K, ns, r, eps, preblur=True, gate=ab, median_alpha=malpha)
+    mism = float((host(out["disp"]) != ref[0][0]).mean())
+    print(dtype, "all options: level-0 mismatch rate against the oracle", mism)
+    assert mism < 0.02
+    # the chain: pyramid of the input, level 0 on the blurred input
+    PL, PR = M.pyramid(Lg, K), M.pyramid(Rg, K)
+    Lb = dev(oracle.blur(p.left).astype(np.float32))
+    Rb = dev(oracle.blur(p.right).astype(np.float32))
+    maps, costs = [None] * K, [None] * K
+    for k in range(K - 1, -1, -1):
+        Lk, Rk = (PL[k], PR[k]) if k > 0 else (Lb, Rb)
+        Dk = -(-D // (1 << k))
+        if k == K - 1:
+            d1, C1 = M.match_level(Lk, Rk, ns[k], Dk, None, r, eps)
+        else:
+            d1, C1 = M.match_level_gated(Lk, Rk, ns[k], Dk, maps[k + 1], costs[k + 1], r, ab[1], eps)
+        d, C = M.aggregate_refine(Lk, Rk, ns[k], Dk, d1, C1, ab[0], eps)
+        maps[k], costs[k] = M.median_filter(d, C, malpha), C
+    assert torch.equal(maps[1], out["prior1"])
+    # level 0 of the chain ran on the oracle's blur (FP64, rounded to float):
+    # compare with the oracle's tolerance rule instead of bit for bit
+    agree = float((maps[0] == out["disp"]).float().mean())
+    print(dtype, "level-0 agreement with the chain on the FP64 blur", agree)
+    assert agree > 0.98
