@@ -560,9 +560,30 @@ def main():
             el = time.perf_counter() - t0
             if el >= args.cpu_seconds:
                 break
+        # one core, on the small pair (the paper's CPU setting is one process)
+        ps, cs = synth.workload("small320")
+        oracle.set_threads(1)
+        reps1, t1 = 0, time.perf_counter()
+        while True:
+            oracle.disparity(ps.left, ps.right, cs.max_disp, cs.levels, cs.half_window, cs.refine_radius,
+                             cs.var_eps)
+            reps1 += 1
+            el1 = time.perf_counter() - t1
+            if el1 >= min(5.0, args.cpu_seconds):
+                break
+        oracle.set_threads(oracle.num_threads())
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
         cpu = {"value": evals * reps / el, "unit": "evals/s", "cores": oracle.num_threads(),
                "kind": "oracle", "ms_per_pair": 1e3 * el / reps,
-               "sample": f"{reps} full hierarchical forwards of the 1436x992 pair ({el:.1f} s)"}
+               "sample": f"{reps} full hierarchical forwards of the 1436x992 pair ({el:.1f} s)",
+               "cpu_model": model,
+               "one_core_small320_ms_per_pair": 1e3 * el1 / reps1,
+               "one_core_sample": f"{reps1} forwards of the 320x240 pair on one thread ({el1:.1f} s)"}
 
     line = {
         "metric": METRIC,

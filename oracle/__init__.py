@@ -109,6 +109,14 @@ def _p(a, t):
     return a.ctypes.data_as(t)
 
 
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on (for timing)."""
+    lib = _load()
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_threads.restype = None
+    lib.orc_set_threads(int(n))
+
+
 def num_threads() -> int:
     """OpenMP threads the oracle will use (OMP_NUM_THREADS, else the CPU count)."""
     v = os.environ.get("OMP_NUM_THREADS")

@@ -23,6 +23,10 @@
 
 static int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+/* Threads of the OpenMP loops below (for timing the oracle on one core). */
+void omp_set_num_threads(int);
+void orc_set_threads(int n) { omp_set_num_threads(n < 1 ? 1 : n); }
+
 /* One Gaussian-pyramid step (Section III, K-level Gaussian pyramid).  The paper
  * does not name the blur; the reading is the 5-tap binomial [1 4 6 4 1]/16 in
  * each direction, sampled at even positions, output size ceil(H/2) x ceil(W/2),
