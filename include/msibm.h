@@ -78,7 +78,7 @@ typedef int32_t msibm_status;
                                    input blurred with the pyramid's 5x5 binomial
                                    kernel (every pixel, clamp-to-edge; the blur
                                    of the original image of Section IV)         */
-#define MSIBM_FLAG_MEDIAN 16    /* plain forward only: every level's hard map goes
+#define MSIBM_FLAG_MEDIAN 16    /* plain and batched forward: every level's hard map goes
                                    through the selective median filter (Eq. 10)
                                    with threshold median_alpha                  */
 #define MSIBM_FLAG_GATED 32     /* plain forward only: the confidence gating of

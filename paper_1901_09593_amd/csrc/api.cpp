@@ -93,8 +93,6 @@ msibm_status validate_config(const msibm_config* cfg)
         return fail(MSIBM_ERR_INVALID_ARG, "unknown flags 0x%x", cfg->flags);
     if ((cfg->flags & MSIBM_FLAG_PREBLUR) && (cfg->flags & MSIBM_FLAG_BATCHED))
         return fail(MSIBM_ERR_UNSUPPORTED, "MSIBM_FLAG_PREBLUR runs on the plain path only");
-    if ((cfg->flags & MSIBM_FLAG_MEDIAN) && (cfg->flags & MSIBM_FLAG_BATCHED))
-        return fail(MSIBM_ERR_UNSUPPORTED, "MSIBM_FLAG_MEDIAN runs on the plain path only");
     if ((cfg->flags & MSIBM_FLAG_MEDIAN) && !std::isfinite(cfg->median_alpha))
         return fail(MSIBM_ERR_INVALID_ARG, "median_alpha must be finite");
     if ((cfg->flags & MSIBM_FLAG_GATED) && (cfg->flags & MSIBM_FLAG_BATCHED))

@@ -33,7 +33,7 @@ namespace msibm {
 static int cdiv(int a, int b) { return (a + b - 1) / b; }
 static int levels_of(const msibm_pair& p) { return p.num_levels ? p.num_levels : auto_levels(p.max_disp); }
 
-enum StageKind { STAGE_LEVELS = 0, STAGE_STATS = 1, STAGE_MATCH = 2, STAGE_ZERO = 3, STAGE_BACKWARD = 4 };
+enum StageKind { STAGE_LEVELS = 0, STAGE_STATS = 1, STAGE_MATCH = 2, STAGE_ZERO = 3, STAGE_BACKWARD = 4, STAGE_MEDIAN = 5 };
 
 struct StageLaunch {
     int kind, level;
@@ -83,6 +83,10 @@ static Segment make_seg(int type, int p, int k, int h, int w, int dtype, int tas
     } else if (type == SEG_STATS) {  // a statistics tile covers both views
         s.tiles_x = cdiv(w, ST_W);
         s.tiles_y = cdiv(h, stats_tile_h(dtype));
+        s.views = 1;
+    } else if (type == SEG_MEDIAN) {
+        s.tiles_x = cdiv(w, MD_W);
+        s.tiles_y = cdiv(h, MD_H);
         s.views = 1;
     } else if (type == SEG_ZERO) {
         s.tiles_x = (int)(((size_t)h * w + ZERO_TILE - 1) / ZERO_TILE);
@@ -150,15 +154,16 @@ static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg
     }
     const int modes[3] = {MODE_FULL, MODE_REFINE, MODE_SOFT};
     const int segtype[3] = {SEG_FULL, SEG_REFINE, SEG_SOFT};
-    for (int k = Kmax - 1; k >= 0; --k)
+    auto mode_of = [&](int p, int k) {
+        return (k == K[p] - 1) ? MODE_FULL : ((k == 0 && cfg->soft_radius > 0) ? MODE_SOFT : MODE_REFINE);
+    };
+    for (int k = Kmax - 1; k >= 0; --k) {
         for (int m = 0; m < 3; ++m)
             for (int dt = 0; dt < 2; ++dt) {
                 bool opened = false;
                 for (int p = 0; p < np; ++p) {
                     if (k >= K[p]) continue;
-                    const bool coarsest = (k == K[p] - 1);
-                    const int mode =
-                        coarsest ? MODE_FULL : ((k == 0 && cfg->soft_radius > 0) ? MODE_SOFT : MODE_REFINE);
+                    const int mode = mode_of(p, k);
                     const int dtype = k == 0 ? pairs[p].dtype : MSIBM_F32;
                     if (mode != modes[m] || dtype != dt) continue;
                     if (!opened) {
@@ -172,6 +177,20 @@ static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg
                     add(segtype[m], p, k);
                 }
             }
+        // with the selective median: every pair's hard map of this level is
+        // filtered before the next finer level reads it as its prior
+        if (cfg->flags & MSIBM_FLAG_MEDIAN) {
+            bool opened = false;
+            for (int p = 0; p < np; ++p) {
+                if (k >= K[p] || mode_of(p, k) == MODE_SOFT) continue;
+                if (!opened) {
+                    begin(STAGE_MEDIAN, k, 0, 0, 0);
+                    opened = true;
+                }
+                add(SEG_MEDIAN, p, k);
+            }
+        }
+    }
     int nl = 0;
     for (int p = 0; p < np; ++p) nl += K[p];
     table_layout(pl, nl, np, 0);
@@ -197,15 +216,22 @@ static void plan_backward_stages(const msibm_pair* pairs, int np, BatchPlan& pl)
     table_layout(pl, np, np, np);
 }
 
+// Workspace layout of one pair on the batched path (the same as the size query's).
+static PairLayout batch_layout(const msibm_pair& P, const msibm_config* cfg)
+{
+    return pair_layout(P, levels_of(P), false, (cfg->flags & MSIBM_FLAG_MEDIAN) != 0, false);
+}
+
 // Level descriptors of every pair, with its workspace region and outputs.
-static void plan_levels(const msibm_pair* pairs, int np, const BatchOutputs& out, char* workspace,
-                        BatchPlan& pl)
+static void plan_levels(const msibm_pair* pairs, int np, const msibm_config* cfg, const BatchOutputs& out,
+                        char* workspace, BatchPlan& pl)
 {
     size_t base = 0;
+    const bool median = (cfg->flags & MSIBM_FLAG_MEDIAN) != 0;
     for (int p = 0; p < np; ++p) {
         const msibm_pair& P = pairs[p];
         const int K = levels_of(P);
-        const PairLayout lay = pair_layout(P, K);
+        const PairLayout lay = batch_layout(P, cfg);
         char* ws = workspace + base;
         base += lay.bytes;
         pl.level_base.push_back((int)pl.levels.size());
@@ -231,15 +257,22 @@ static void plan_levels(const msibm_pair* pairs, int np, const BatchOutputs& out
             d.stat[0] = (WinStat*)(ws + lay.stat[k][0]);
             d.stat[1] = (WinStat*)(ws + lay.stat[k][1]);
             d.Dk = level_range(P.max_disp, k);
+            // the median filters every hard level: the search writes the
+            // pair's scratch map (reused level after level) and its cost
+            const bool soft_level = (k == 0 && K >= 2 && cfg->soft_radius > 0);
+            if (median && !soft_level) {
+                d.raw = (int16_t*)(ws + lay.dtmp);
+                d.mcost = (k == 0 && d.cost) ? d.cost : (float*)(ws + lay.ctmp);
+            }
             pl.levels.push_back(d);
         }
     }
 }
 
-static size_t pairs_bytes(const msibm_pair* pairs, int np)
+static size_t pairs_bytes(const msibm_pair* pairs, int np, const msibm_config* cfg)
 {
     size_t b = 0;
-    for (int p = 0; p < np; ++p) b += pair_layout(pairs[p], levels_of(pairs[p])).bytes;
+    for (int p = 0; p < np; ++p) b += batch_layout(pairs[p], cfg).bytes;
     return b;
 }
 
@@ -274,6 +307,7 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
     a.rs = cfg->soft_radius;
     a.var_eps = cfg->var_eps;
     a.inv_tau = cfg->soft_radius > 0 ? 1.f / cfg->tau : 0.f;
+    a.median_alpha = cfg->median_alpha;
     // restricted searches stage their whole candidate range at once wherever it
     // fits one chunk (decided per segment by the kernel)
     a.variant = VARIANT_FIXW;
@@ -287,6 +321,7 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
         else if (l.kind == STAGE_STATS) snprintf(lab, sizeof(lab), bwd ? "batch_bwd_stats" : "batch_stats");
         else if (l.kind == STAGE_ZERO) snprintf(lab, sizeof(lab), "batch_bwd_zero");
         else if (l.kind == STAGE_BACKWARD) snprintf(lab, sizeof(lab), "batch_backward_l0");
+        else if (l.kind == STAGE_MEDIAN) snprintf(lab, sizeof(lab), "batch_median_l%d", l.level);
         else snprintf(lab, sizeof(lab), "batch_match_%s_l%d", mode_name[l.mode], l.level);
         const int slot = timed ? timing_begin(lab, s) : -1;
         hipError_t e;
@@ -297,6 +332,8 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
             e = hipGetLastError();
         } else if (l.kind == STAGE_BACKWARD)
             e = launch_backward_multi(level_n(cfg, 0), slots_for_radius(cfg->soft_radius), a, l.blocks, s);
+        else if (l.kind == STAGE_MEDIAN)
+            e = launch_median_multi(a, l.blocks, s);
         else e = launch_match_multi(level_n(cfg, l.level), l.dtype, l.mode, l.nc, a, l.blocks, s);
         if (timed) timing_end(slot, s);
         if (e != hipSuccess) return e;
@@ -500,9 +537,10 @@ int run_batched(const msibm_pair* pairs, int np, const msibm_config* cfg, const 
     }
     auto build = [&](BatchPlan& pl) {
         plan_stages(pairs, np, cfg, pl);
-        plan_levels(pairs, np, out, (char*)workspace, pl);
+        plan_levels(pairs, np, cfg, out, (char*)workspace, pl);
     };
-    return run_plan(dev, cfg, graph ? &key : nullptr, build, (char*)workspace + pairs_bytes(pairs, np), s, err);
+    return run_plan(dev, cfg, graph ? &key : nullptr, build, (char*)workspace + pairs_bytes(pairs, np, cfg), s,
+                    err);
 }
 
 int run_batched_backward(const msibm_pair* pairs, int np, const msibm_config* cfg, const BatchGrads& g,
@@ -528,7 +566,7 @@ int run_batched_backward(const msibm_pair* pairs, int np, const msibm_config* cf
         size_t base = 0;
         for (int p = 0; p < np; ++p) {
             const msibm_pair& P = pairs[p];
-            const PairLayout lay = pair_layout(P, levels_of(P));
+            const PairLayout lay = batch_layout(P, cfg);
             char* ws = (char*)workspace + base;
             base += lay.bytes;
             LevelDesc d{};
@@ -566,7 +604,8 @@ int run_batched_backward(const msibm_pair* pairs, int np, const msibm_config* cf
             pl.back.push_back(b);
         }
     };
-    return run_plan(dev, cfg, graph ? &key : nullptr, build, (char*)workspace + pairs_bytes(pairs, np), s, err);
+    return run_plan(dev, cfg, graph ? &key : nullptr, build, (char*)workspace + pairs_bytes(pairs, np, cfg), s,
+                    err);
 }
 
 }  // namespace msibm

@@ -168,7 +168,10 @@ struct ConvertArgs {
 // The batched forward describes its work as segments, one per (pair, stage,
 // level); a launch covers the tiles of several segments of one stage.
 
-enum SegType { SEG_REDUCE = 0, SEG_STATS = 1, SEG_FULL = 2, SEG_REFINE = 3, SEG_SOFT = 4, SEG_ZERO = 5, SEG_BACKWARD = 6 };
+enum SegType {
+    SEG_REDUCE = 0, SEG_STATS = 1, SEG_FULL = 2, SEG_REFINE = 3, SEG_SOFT = 4, SEG_ZERO = 5, SEG_BACKWARD = 6,
+    SEG_MEDIAN = 7
+};
 
 struct BackArgs;
 
@@ -178,6 +181,8 @@ struct LevelDesc {
     int pitch, H, W;
     WinStat* stat[2];      // window statistics, row pitch W
     int16_t* map;         // winner-take-all map, row pitch W (level 0: the caller's output)
+    int16_t* raw;         // with the median: the unfiltered map the search writes (else NULL)
+    float* mcost;         // with the median: the cost the search writes and the filter reads
     float* cost;          // level 0 only, nullable
     float* soft;          // level 0 only, soft mode
     int Dk;
@@ -205,7 +210,11 @@ struct MultiArgs {
     int r, rs;                // refine and soft radius
     double var_eps;
     float inv_tau;
+    double median_alpha;      // median launches
 };
+
+// Tile of the selective median filter.
+constexpr int MD_W = 64, MD_H = 4;
 
 // Floats a zero-fill tile clears in each gradient (256 threads x 16).
 constexpr int ZERO_TILE = 4096;
@@ -236,6 +245,7 @@ hipError_t launch_stats(StatsArgs a, hipStream_t s);
 hipError_t launch_tower(int dtype, const TowerArgs& a, hipStream_t s);
 hipError_t launch_blur(int dtype, const BlurArgs& a, hipStream_t s);
 hipError_t launch_median(const MedianArgs& a, hipStream_t s);
+hipError_t launch_median_multi(const MultiArgs& a, int blocks, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& a, hipStream_t s);
 hipError_t launch_gate(int n, int dtype, int mode, const GateArgs& a, hipStream_t s);
 hipError_t launch_upsample_cost(const float* cc, int Hc, int Wc, int cpitch, int H, int W, double* out,

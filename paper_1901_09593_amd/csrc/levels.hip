@@ -232,12 +232,11 @@ __device__ __forceinline__ void cswap(int& a, int& b)
 // bitonic network; comparators against the constant INT_MAX padding fold away
 // at compile time) and takes the lower median of the good ones, the keys below
 // INT_MAX; disparities are int16, so no disparity equals INT_MAX.
-constexpr int MD_W = 64, MD_H = 4;
-__global__ __launch_bounds__(256) void median_kernel(MedianArgs a)
+__device__ __forceinline__ void median_tile(const MedianArgs& a, int bx, int by)
 {
     __shared__ int key[MD_H + 4][MD_W + 4];
     __shared__ int any_filtered;
-    const int x0 = blockIdx.x * MD_W, y0 = blockIdx.y * MD_H;
+    const int x0 = bx * MD_W, y0 = by * MD_H;
     const int c = threadIdx.x & 63, r0 = threadIdx.x >> 6;  // the thread's pixel
     if (threadIdx.x == 0) any_filtered = 0;
     for (int idx = threadIdx.x; idx < (MD_H + 4) * (MD_W + 4); idx += 256) {
@@ -311,6 +310,18 @@ __global__ __launch_bounds__(256) void median_kernel(MedianArgs a)
     }
 }
 
+__global__ __launch_bounds__(256) void median_kernel(MedianArgs a) { median_tile(a, blockIdx.x, blockIdx.y); }
+
+// The median of several (pair, level) maps in one launch.
+__global__ __launch_bounds__(256) void median_multi_kernel(MultiArgs a)
+{
+    const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
+    const LevelDesc& L = a.levels[a.level_base[s.pair] + s.level];
+    const MedianArgs m{L.raw, L.mcost, L.map, L.H, L.W, L.W, L.W, L.W, a.median_alpha};
+    const int t = blockIdx.x - s.task0;
+    median_tile(m, t % s.tiles_x, t / s.tiles_x);
+}
+
 // Weight with which coarse row (or column) y of a reduce step reads fine row p:
 // the binomial taps a with clamp(2y + a) = p, summed (several taps clamp to the
 // same edge row).
@@ -350,6 +361,13 @@ hipError_t launch_adjoint(const AdjArgs& a, hipStream_t s)
     if (a.views < 1 || a.views > 2 || a.Hc != (a.H + 1) / 2 || a.Wc != (a.W + 1) / 2) return hipErrorInvalidValue;
     dim3 grid((a.W + 63) / 64, (a.H + 3) / 4, a.views);
     hipLaunchKernelGGL(adjoint_kernel, grid, dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_median_multi(const MultiArgs& a, int blocks, hipStream_t s)
+{
+    if (blocks < 1 || a.nseg < 1) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(median_multi_kernel, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

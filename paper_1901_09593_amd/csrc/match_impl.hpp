@@ -759,8 +759,8 @@ __global__ __launch_bounds__(MATCH_THREADS) void match_multi_kernel(MultiArgs a)
         m.ppitch = C.W;
     }
     m.r = (MODE == MODE_SOFT) ? a.rs : a.r;
-    m.d_out = L.map;
-    m.c_out = L.cost;
+    m.d_out = L.raw ? L.raw : L.map;  // with the median the filter fills L.map
+    m.c_out = L.raw ? L.mcost : L.cost;
     m.soft_out = L.soft;
     m.opitch = L.W;
     m.inv_tau = a.inv_tau;

@@ -414,7 +414,7 @@ def disparity_many(lefts: Sequence[torch.Tensor], rights: Sequence[torch.Tensor]
                    median_alpha: Optional[float] = None,
                    gate: Optional[Tuple[float, float]] = None) -> List[Dict[str, torch.Tensor]]:
     """Forward pass of several pairs in one call (flags: FLAG_BATCHED, FLAG_GRAPH,
-    or FLAG_PREBLUR / a median_alpha on the plain path).
+    a median_alpha on either path, FLAG_PREBLUR or a gate on the plain path).
     `workspace` and `outputs` may be passed in to reuse buffers across calls."""
     pairs, keep = _pairs(lefts, rights, Ds, Ks)
     npair = len(lefts)

@@ -92,14 +92,15 @@ def test_config_and_pair_validation(lib):
     pre_b = msibm.make_config(3, 2, 0.065, flags=msibm.FLAG_PREBLUR | msibm.FLAG_BATCHED)
     rc = e.msibm_disparity(arr, 1, ctypes.byref(pre_b), disp_probe, None, None, None, None, 0, None)
     assert rc == -4 and b"PREBLUR" in e.msibm_last_error()
-    # the selective median runs on the plain forward only, with a finite threshold,
-    # and keeps an unfiltered map and cost of level 0 in the workspace
+    # the selective median takes a finite threshold and keeps an unfiltered map
+    # and cost of level 0 in the workspace (plain and batched paths)
     med = msibm.make_config(3, 2, 0.065, median_alpha=0.9)
     assert med.flags & msibm.FLAG_MEDIAN
     assert e.msibm_workspace_size(arr, 1, ctypes.byref(med)) >= \
         e.msibm_workspace_size(arr, 1, ctypes.byref(good)) + 64 * 80 * 6
-    for bad in (msibm.make_config(3, 2, 0.065, flags=msibm.FLAG_BATCHED, median_alpha=0.9),
-                msibm.make_config(3, 2, 0.065, median_alpha=float("inf"))):
+    med_b = msibm.make_config(3, 2, 0.065, flags=msibm.FLAG_BATCHED, median_alpha=0.9)
+    assert e.msibm_workspace_size(arr, 1, ctypes.byref(med_b)) >= e.msibm_workspace_size(arr, 1, ctypes.byref(med))
+    for bad in (msibm.make_config(3, 2, 0.065, median_alpha=float("inf")),):
         assert e.msibm_workspace_size(arr, 1, ctypes.byref(bad)) == 0
         rc = e.msibm_disparity(arr, 1, ctypes.byref(bad), disp_probe, None, None, None, None, 0, None)
         assert rc in (-1, -4) and b"median" in e.msibm_last_error().lower()

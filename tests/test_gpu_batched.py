@@ -174,3 +174,37 @@ def test_batch32_full_size_sampled(M):
         d, C, p1 = (got[i][x].cpu().numpy() for x in ("disp", "cost", "prior1"))
         st = check_pixels(d, C, p.left, p.right, n, D[i], p1, r, eps, ii, jj)
         print(f"batch32 pair {i} ({W}x{H}, D={D[i]}, K={k})", st)
+
+
+def test_batched_median_uneven_pairs_equals_plain(M):
+    """The selective median on the batched path, uneven pairs and depths, with
+    and without the graph, with a soft level on float pairs: every output equals
+    the plain path's."""
+    import numpy as np
+    from paper_1901_09593_amd import synth
+    shapes = [(96, 150, 48, 0), (61, 200, 100, 0), (130, 90, 20, 2)]
+    pairs = [synth.make_pair(700 + i, h, w, 3, 2, max(3, D // 2), True, 0.9, 5.0, 4.0, "u8")
+             for i, (h, w, D, K) in enumerate(shapes)]
+    L = [torch.from_numpy(p.left).cuda() for p in pairs]
+    R = [torch.from_numpy(p.right).cuda() for p in pairs]
+    Ds = [s[2] for s in shapes]
+    Ks = [s[3] for s in shapes]
+    plain = M.disparity_many(L, R, Ds, Ks, 3, 2, 0.065, with_prior1=True, median_alpha=0.9)
+    for flags in (M.FLAG_BATCHED, M.FLAG_BATCHED | M.FLAG_GRAPH):
+        for rep in range(2):
+            got = M.disparity_many(L, R, Ds, Ks, 3, 2, 0.065, with_prior1=True, flags=flags, median_alpha=0.9)
+            for a, b in zip(got, plain):
+                assert torch.equal(a["disp"], b["disp"]) and torch.equal(a["cost"], b["cost"])
+                if "prior1" in b:
+                    assert torch.equal(a["prior1"], b["prior1"])
+    # float pairs with the soft level: the median runs on the hard levels only
+    fp = [synth.make_pair(710 + i, 80, 120, 3, 2, 12, True, 0.9, 0.02, 2 / 255, "f32") for i in range(2)]
+    Lf = [torch.from_numpy(p.left).cuda() for p in fp]
+    Rf = [torch.from_numpy(p.right).cuda() for p in fp]
+    plain = M.disparity_many(Lf, Rf, [32, 32], [3, 3], 2, 2, 1e-6, soft_radius=2, tau=0.05, with_prior1=True,
+                             median_alpha=0.9)
+    got = M.disparity_many(Lf, Rf, [32, 32], [3, 3], 2, 2, 1e-6, soft_radius=2, tau=0.05, with_prior1=True,
+                           flags=M.FLAG_BATCHED | M.FLAG_GRAPH, median_alpha=0.9)
+    for a, b in zip(got, plain):
+        for key in ("disp", "cost", "soft", "prior1"):
+            assert torch.equal(a[key], b[key]), key

@@ -342,9 +342,12 @@ def test_median_in_the_hierarchy(M, dtype, K, alpha):
     mism = float((host(out["disp"]) != ref[0][0]).mean())
     print("end-to-end level-0 mismatch rate with the median", mism)
     assert mism < 0.01
-    # the batched path does not take the filter
-    with pytest.raises(M.MsibmError):
-        M.disparity_many([Lg], [Rg], [D], [K], n, r, eps, flags=M.FLAG_BATCHED, median_alpha=alpha)
+    # the batched path (and its graph) filters the same way
+    for flags in (M.FLAG_BATCHED, M.FLAG_BATCHED | M.FLAG_GRAPH):
+        got = M.disparity_many([Lg], [Rg], [D], [K], n, r, eps, flags=flags, with_prior1=True,
+                               median_alpha=alpha)[0]
+        assert torch.equal(got["disp"], out["disp"]) and torch.equal(got["cost"], out["cost"])
+        assert torch.equal(got["prior1"], out["prior1"])
 
 
 def test_mid1436_full_size_sampled(M):
