@@ -191,6 +191,24 @@ def section_batched(torch, M, synth, steps):
         del ws
     res["graph_speedup_vs_plain"] = res["plain"]["ms_per_batch"] / res["graph"]["ms_per_batch"]
     res["batched_speedup_vs_plain"] = res["plain"]["ms_per_batch"] / res["batched"]["ms_per_batch"]
+    # the same batch with the selective median (Eq. 10) at every level
+    med = {}
+    for name, flags in (("plain", 0), ("graph", M.FLAG_BATCHED | M.FLAG_GRAPH)):
+        ws = torch.empty(M.workspace_bytes(pairs_arr, len(L),
+                                           M.make_config(n, r, eps, flags=flags, median_alpha=MEDIAN_ALPHA)),
+                         dtype=torch.uint8, device=dev)
+        outs = M.disparity_many(L, R, D, K, n, r, eps, flags=flags, workspace=ws, median_alpha=MEDIAN_ALPHA)
+
+        def step():
+            M.disparity_many(L, R, D, K, n, r, eps, flags=flags, workspace=ws, outputs=outs,
+                             median_alpha=MEDIAN_ALPHA)
+        med[name] = {"ms_per_batch": time_ms(torch, step, steps, 3)}
+        if name == "plain":
+            mref = outs
+        else:
+            med[name]["identical_to_plain"] = all(torch.equal(a[k], b[k]) for a, b in zip(mref, outs) for k in a)
+        del ws
+    res["with_median"] = med
     return res
 
 
