@@ -95,8 +95,6 @@ msibm_status validate_config(const msibm_config* cfg)
         return fail(MSIBM_ERR_UNSUPPORTED, "MSIBM_FLAG_PREBLUR runs on the plain path only");
     if ((cfg->flags & MSIBM_FLAG_MEDIAN) && !std::isfinite(cfg->median_alpha))
         return fail(MSIBM_ERR_INVALID_ARG, "median_alpha must be finite");
-    if ((cfg->flags & MSIBM_FLAG_GATED) && (cfg->flags & MSIBM_FLAG_BATCHED))
-        return fail(MSIBM_ERR_UNSUPPORTED, "MSIBM_FLAG_GATED runs on the plain path only");
     if ((cfg->flags & MSIBM_FLAG_GATED) && (!std::isfinite(cfg->gate_alpha) || !std::isfinite(cfg->gate_beta)))
         return fail(MSIBM_ERR_INVALID_ARG, "gate_alpha and gate_beta must be finite");
     if ((cfg->flags & MSIBM_FLAG_GRAPH) && !(cfg->flags & MSIBM_FLAG_BATCHED))

@@ -33,7 +33,10 @@ namespace msibm {
 static int cdiv(int a, int b) { return (a + b - 1) / b; }
 static int levels_of(const msibm_pair& p) { return p.num_levels ? p.num_levels : auto_levels(p.max_disp); }
 
-enum StageKind { STAGE_LEVELS = 0, STAGE_STATS = 1, STAGE_MATCH = 2, STAGE_ZERO = 3, STAGE_BACKWARD = 4, STAGE_MEDIAN = 5 };
+enum StageKind {
+    STAGE_LEVELS = 0, STAGE_STATS = 1, STAGE_MATCH = 2, STAGE_ZERO = 3, STAGE_BACKWARD = 4, STAGE_MEDIAN = 5,
+    STAGE_GATE = 6
+};
 
 struct StageLaunch {
     int kind, level;
@@ -83,6 +86,10 @@ static Segment make_seg(int type, int p, int k, int h, int w, int dtype, int tas
     } else if (type == SEG_STATS) {  // a statistics tile covers both views
         s.tiles_x = cdiv(w, ST_W);
         s.tiles_y = cdiv(h, stats_tile_h(dtype));
+        s.views = 1;
+    } else if (type == SEG_GATE) {
+        s.tiles_x = cdiv(w, GATE_TW);
+        s.tiles_y = cdiv(h, GATE_TH);
         s.views = 1;
     } else if (type == SEG_MEDIAN) {
         s.tiles_x = cdiv(w, MD_W);
@@ -177,6 +184,27 @@ static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg
                     add(segtype[m], p, k);
                 }
             }
+        // with the gating: the coarsest level of a pair re-picks, a finer one
+        // runs the fused fallback search and re-pick (one launch per mode and
+        // element type)
+        if (cfg->flags & MSIBM_FLAG_GATED) {
+            for (int gm = 0; gm < 2; ++gm)
+                for (int dt = 0; dt < 2; ++dt) {
+                    const int want = gm == 0 ? GATE_MODE_REPICK : GATE_MODE_FUSED;
+                    bool opened = false;
+                    for (int p = 0; p < np; ++p) {
+                        if (k >= K[p] || mode_of(p, k) == MODE_SOFT) continue;
+                        const int gmode = (k == K[p] - 1) ? GATE_MODE_REPICK : GATE_MODE_FUSED;
+                        const int dtype = k == 0 ? pairs[p].dtype : MSIBM_F32;
+                        if (gmode != want || dtype != dt) continue;
+                        if (!opened) {
+                            begin(STAGE_GATE, k, want, dt, 0);
+                            opened = true;
+                        }
+                        add(SEG_GATE, p, k);
+                    }
+                }
+        }
         // with the selective median: every pair's hard map of this level is
         // filtered before the next finer level reads it as its prior
         if (cfg->flags & MSIBM_FLAG_MEDIAN) {
@@ -219,7 +247,8 @@ static void plan_backward_stages(const msibm_pair* pairs, int np, BatchPlan& pl)
 // Workspace layout of one pair on the batched path (the same as the size query's).
 static PairLayout batch_layout(const msibm_pair& P, const msibm_config* cfg)
 {
-    return pair_layout(P, levels_of(P), false, (cfg->flags & MSIBM_FLAG_MEDIAN) != 0, false);
+    return pair_layout(P, levels_of(P), false, (cfg->flags & MSIBM_FLAG_MEDIAN) != 0,
+                       (cfg->flags & MSIBM_FLAG_GATED) != 0);
 }
 
 // Level descriptors of every pair, with its workspace region and outputs.
@@ -228,6 +257,7 @@ static void plan_levels(const msibm_pair* pairs, int np, const msibm_config* cfg
 {
     size_t base = 0;
     const bool median = (cfg->flags & MSIBM_FLAG_MEDIAN) != 0;
+    const bool gated = (cfg->flags & MSIBM_FLAG_GATED) != 0;
     for (int p = 0; p < np; ++p) {
         const msibm_pair& P = pairs[p];
         const int K = levels_of(P);
@@ -257,12 +287,16 @@ static void plan_levels(const msibm_pair* pairs, int np, const msibm_config* cfg
             d.stat[0] = (WinStat*)(ws + lay.stat[k][0]);
             d.stat[1] = (WinStat*)(ws + lay.stat[k][1]);
             d.Dk = level_range(P.max_disp, k);
-            // the median filters every hard level: the search writes the
-            // pair's scratch map (reused level after level) and its cost
+            // the gating keeps every hard level's cost (the next finer level's
+            // gate reads it); the median filters every hard level: the search
+            // writes the pair's scratch map (reused level after level) and the
+            // cost, which the filter reads
             const bool soft_level = (k == 0 && K >= 2 && cfg->soft_radius > 0);
+            if (gated && !soft_level && !d.cost)
+                d.cost = k == 0 ? (float*)(ws + lay.ctmp) : (float*)(ws + lay.cmap[k]);
             if (median && !soft_level) {
                 d.raw = (int16_t*)(ws + lay.dtmp);
-                d.mcost = (k == 0 && d.cost) ? d.cost : (float*)(ws + lay.ctmp);
+                d.mcost = d.cost ? d.cost : (float*)(ws + lay.ctmp);
             }
             pl.levels.push_back(d);
         }
@@ -308,6 +342,8 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
     a.var_eps = cfg->var_eps;
     a.inv_tau = cfg->soft_radius > 0 ? 1.f / cfg->tau : 0.f;
     a.median_alpha = cfg->median_alpha;
+    a.gate_alpha = cfg->gate_alpha;
+    a.gate_beta = cfg->gate_beta;
     // restricted searches stage their whole candidate range at once wherever it
     // fits one chunk (decided per segment by the kernel)
     a.variant = VARIANT_FIXW;
@@ -322,6 +358,9 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
         else if (l.kind == STAGE_ZERO) snprintf(lab, sizeof(lab), "batch_bwd_zero");
         else if (l.kind == STAGE_BACKWARD) snprintf(lab, sizeof(lab), "batch_backward_l0");
         else if (l.kind == STAGE_MEDIAN) snprintf(lab, sizeof(lab), "batch_median_l%d", l.level);
+        else if (l.kind == STAGE_GATE)
+            snprintf(lab, sizeof(lab), l.mode == GATE_MODE_FUSED ? "batch_gate_fused_l%d" : "batch_gate_repick_l%d",
+                     l.level);
         else snprintf(lab, sizeof(lab), "batch_match_%s_l%d", mode_name[l.mode], l.level);
         const int slot = timed ? timing_begin(lab, s) : -1;
         hipError_t e;
@@ -334,6 +373,8 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
             e = launch_backward_multi(level_n(cfg, 0), slots_for_radius(cfg->soft_radius), a, l.blocks, s);
         else if (l.kind == STAGE_MEDIAN)
             e = launch_median_multi(a, l.blocks, s);
+        else if (l.kind == STAGE_GATE)
+            e = launch_gate_multi(level_n(cfg, l.level), l.dtype, l.mode, a, l.blocks, s);
         else e = launch_match_multi(level_n(cfg, l.level), l.dtype, l.mode, l.nc, a, l.blocks, s);
         if (timed) timing_end(slot, s);
         if (e != hipSuccess) return e;

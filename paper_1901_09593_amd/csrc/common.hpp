@@ -170,7 +170,7 @@ struct ConvertArgs {
 
 enum SegType {
     SEG_REDUCE = 0, SEG_STATS = 1, SEG_FULL = 2, SEG_REFINE = 3, SEG_SOFT = 4, SEG_ZERO = 5, SEG_BACKWARD = 6,
-    SEG_MEDIAN = 7
+    SEG_MEDIAN = 7, SEG_GATE = 8
 };
 
 struct BackArgs;
@@ -211,7 +211,11 @@ struct MultiArgs {
     double var_eps;
     float inv_tau;
     double median_alpha;      // median launches
+    double gate_alpha, gate_beta;  // gating launches
 };
+
+// Tile of the gating kernel.
+constexpr int GATE_TH = 8, GATE_TW = 64;
 
 // Tile of the selective median filter.
 constexpr int MD_W = 64, MD_H = 4;
@@ -248,6 +252,7 @@ hipError_t launch_median(const MedianArgs& a, hipStream_t s);
 hipError_t launch_median_multi(const MultiArgs& a, int blocks, hipStream_t s);
 hipError_t launch_adjoint(const AdjArgs& a, hipStream_t s);
 hipError_t launch_gate(int n, int dtype, int mode, const GateArgs& a, hipStream_t s);
+hipError_t launch_gate_multi(int n, int dtype, int mode, const MultiArgs& a, int blocks, hipStream_t s);
 hipError_t launch_upsample_cost(const float* cc, int Hc, int Wc, int cpitch, int H, int W, double* out,
                                 int opitch, hipStream_t s);
 hipError_t launch_match(int n, int dtype, int mode, int nc, const MatchArgs& a, hipStream_t s);

@@ -28,8 +28,8 @@ namespace msibm {
 
 namespace {
 
-constexpr int GT_H = 8;        // tile rows
-constexpr int GT_W = 64;       // tile columns
+constexpr int GT_H = GATE_TH;  // tile rows
+constexpr int GT_W = GATE_TW;  // tile columns
 constexpr int GT_ZC = 32;      // candidates per staged right chunk
 constexpr int GT_THREADS = 256;
 constexpr int ZU = 1;          // candidates scored per round of barriers (divides GT_ZC)
@@ -82,7 +82,7 @@ __device__ __forceinline__ float pix(const void* img, int pitch, int y, int x)
 constexpr int GATE_FULL = GATE_MODE_FULL, GATE_REPICK = GATE_MODE_REPICK, GATE_FUSED = GATE_MODE_FUSED;
 
 template <typename T, int NW, int MODE>
-__global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
+__device__ __forceinline__ void gate_tile(const GateArgs& a, int bx, int by)
 {
     constexpr bool REPICK = MODE != GATE_FULL;
     constexpr bool FUSED = MODE == GATE_FUSED;
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
     __shared__ int fbz[FUSED ? GT_H : 1][FUSED ? GT_W : 1];
 
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * GT_W, y0 = blockIdx.y * GT_H;
+    const int x0 = bx * GT_W, y0 = by * GT_H;
     const int ry0 = y0 - HB, rx0 = x0 - HB;            // region origin
     const int ey0 = ry0 - NW, ex0 = rx0 - NW;          // extended origin
     const int H = a.H, W = a.W;
@@ -399,6 +399,62 @@ __global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
     }
 }
 
+template <typename T, int NW, int MODE>
+__global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
+{
+    gate_tile<T, NW, MODE>(a, blockIdx.x, blockIdx.y);
+}
+
+// Gating of several (pair, level) segments of one mode and element type in one
+// launch; a level's map and cost are those its search wrote (the scratch map
+// with the median), the coarser level's cost that of its own gating.
+template <typename T, int NW, int MODE>
+__global__ __launch_bounds__(GT_THREADS) void gate_multi_kernel(MultiArgs m)
+{
+    const Segment s = m.segs[segment_of(m.segs, m.nseg, blockIdx.x)];
+    const LevelDesc* lv = m.levels + m.level_base[s.pair];
+    const LevelDesc& L = lv[s.level];
+    GateArgs g{};
+    g.L = L.img[0];
+    g.R = L.img[1];
+    g.pitch = L.pitch;
+    g.H = L.H;
+    g.W = L.W;
+    g.Dk = L.Dk;
+    g.statL = L.stat[0];
+    g.statR = L.stat[1];
+    g.spitch = L.W;
+    g.d = L.raw ? L.raw : L.map;
+    g.c = L.raw ? L.mcost : L.cost;
+    g.opitch = L.W;
+    g.thresh = m.gate_alpha;
+    g.thresh2 = m.gate_beta;
+    if (MODE != GATE_REPICK) {
+        const LevelDesc& C = lv[s.level + 1];
+        g.ccost = C.raw ? C.mcost : C.cost;
+        g.Hc = C.H;
+        g.Wc = C.W;
+        g.cpitch = C.W;
+    }
+    const int t = blockIdx.x - s.task0;
+    gate_tile<T, NW, MODE>(g, t % s.tiles_x, t / s.tiles_x);
+}
+
+template <typename T, int MODE>
+hipError_t launch_gate_multi_t(int n, const MultiArgs& a, int blocks, hipStream_t s)
+{
+    switch (n) {
+        case 1: hipLaunchKernelGGL((gate_multi_kernel<T, 1, MODE>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((gate_multi_kernel<T, 2, MODE>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((gate_multi_kernel<T, 3, MODE>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((gate_multi_kernel<T, 4, MODE>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((gate_multi_kernel<T, 5, MODE>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((gate_multi_kernel<T, 6, MODE>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename T, int MODE>
 hipError_t launch_gate_t(int n, const GateArgs& a, hipStream_t s)
 {
@@ -429,6 +485,16 @@ hipError_t launch_gate(int n, int dtype, int mode, const GateArgs& a, hipStream_
     if (mode == GATE_FULL) return launch_gate_t<float, GATE_FULL>(n, a, s);
     if (mode == GATE_REPICK) return launch_gate_t<float, GATE_REPICK>(n, a, s);
     return launch_gate_t<float, GATE_FUSED>(n, a, s);
+}
+
+hipError_t launch_gate_multi(int n, int dtype, int mode, const MultiArgs& a, int blocks, hipStream_t s)
+{
+    if (blocks < 1 || a.nseg < 1 || (mode != GATE_REPICK && mode != GATE_FUSED)) return hipErrorInvalidValue;
+    if (dtype == MSIBM_U8)
+        return mode == GATE_REPICK ? launch_gate_multi_t<uint8_t, GATE_REPICK>(n, a, blocks, s)
+                                   : launch_gate_multi_t<uint8_t, GATE_FUSED>(n, a, blocks, s);
+    return mode == GATE_REPICK ? launch_gate_multi_t<float, GATE_REPICK>(n, a, blocks, s)
+                               : launch_gate_multi_t<float, GATE_FUSED>(n, a, blocks, s);
 }
 
 hipError_t launch_upsample_cost(const float* cc, int Hc, int Wc, int cpitch, int H, int W, double* out,

@@ -111,12 +111,13 @@ def test_config_and_pair_validation(lib):
     assert e.msibm_median_filter(fake, 8, fake, 8, 8, 8, 0.5, fake, 8, None) == -1
     assert e.msibm_median_filter(fake, 8, fake, 8, 8, 8, float("nan"), ctypes.c_void_p(0x9000000), 8,
                                  None) == -1
-    # the confidence gating: plain path only, finite thresholds, a cost map per level
+    # the confidence gating: finite thresholds, a cost map per level
     gated = msibm.make_config(3, 2, 0.065, gate=(0.9, 0.9))
     assert gated.flags & msibm.FLAG_GATED
     assert e.msibm_workspace_size(arr, 1, ctypes.byref(gated)) > e.msibm_workspace_size(arr, 1, ctypes.byref(good))
-    for bad in (msibm.make_config(3, 2, 0.065, flags=msibm.FLAG_BATCHED, gate=(0.9, 0.9)),
-                msibm.make_config(3, 2, 0.065, gate=(0.9, float("nan")))):
+    gated_b = msibm.make_config(3, 2, 0.065, flags=msibm.FLAG_BATCHED, gate=(0.9, 0.9))
+    assert e.msibm_workspace_size(arr, 1, ctypes.byref(gated_b)) > 0
+    for bad in (msibm.make_config(3, 2, 0.065, gate=(0.9, float("nan"))),):
         assert e.msibm_workspace_size(arr, 1, ctypes.byref(bad)) == 0
         rc = e.msibm_disparity(arr, 1, ctypes.byref(bad), disp_probe, None, None, None, None, 0, None)
         assert rc in (-1, -4) and b"gat" in e.msibm_last_error().lower()

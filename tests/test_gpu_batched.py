@@ -208,3 +208,39 @@ def test_batched_median_uneven_pairs_equals_plain(M):
     for a, b in zip(got, plain):
         for key in ("disp", "cost", "soft", "prior1"):
             assert torch.equal(a[key], b[key]), key
+
+
+@pytest.mark.parametrize("median", [False, True])
+def test_batched_gating_uneven_pairs_equals_plain(M, median):
+    """The confidence gating (with and without the median) on the batched path
+    and its graph, uneven pairs and depths (single-level pairs re-pick only):
+    every output equals the plain path's."""
+    import numpy as np
+    from paper_1901_09593_amd import synth
+    shapes = [(96, 150, 48, 0), (61, 200, 100, 0), (40, 70, 16, 1), (130, 90, 20, 2)]
+    pairs = [synth.make_pair(720 + i, h, w, 3, 2, max(3, D // 2), True, 0.9, 5.0, 6.0, "u8")
+             for i, (h, w, D, K) in enumerate(shapes)]
+    L = [torch.from_numpy(p.left).cuda() for p in pairs]
+    R = [torch.from_numpy(p.right).cuda() for p in pairs]
+    Ds = [s[2] for s in shapes]
+    Ks = [s[3] for s in shapes]
+    ma = 0.9 if median else None
+    plain = M.disparity_many(L, R, Ds, Ks, 3, 2, 0.065, with_prior1=True, gate=(0.9, 0.9), median_alpha=ma)
+    for flags in (M.FLAG_BATCHED, M.FLAG_BATCHED | M.FLAG_GRAPH):
+        for rep in range(2):
+            got = M.disparity_many(L, R, Ds, Ks, 3, 2, 0.065, with_prior1=True, flags=flags, gate=(0.9, 0.9),
+                                   median_alpha=ma)
+            for a, b in zip(got, plain):
+                assert torch.equal(a["disp"], b["disp"]) and torch.equal(a["cost"], b["cost"])
+                if "prior1" in b:
+                    assert torch.equal(a["prior1"], b["prior1"])
+    # float pairs with the soft level: the gating runs on the hard levels only
+    fp = [synth.make_pair(730 + i, 80, 120, 3, 2, 12, True, 0.9, 0.02, 4 / 255, "f32") for i in range(2)]
+    Lf = [torch.from_numpy(p.left).cuda() for p in fp]
+    Rf = [torch.from_numpy(p.right).cuda() for p in fp]
+    kw = dict(soft_radius=2, tau=0.05, with_prior1=True, gate=(0.9, 0.9), median_alpha=ma)
+    plain = M.disparity_many(Lf, Rf, [32, 32], [3, 3], 2, 2, 1e-6, **kw)
+    got = M.disparity_many(Lf, Rf, [32, 32], [3, 3], 2, 2, 1e-6, flags=M.FLAG_BATCHED | M.FLAG_GRAPH, **kw)
+    for a, b in zip(got, plain):
+        for key in ("disp", "cost", "soft", "prior1"):
+            assert torch.equal(a[key], b[key]), key

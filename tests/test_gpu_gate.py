@@ -176,11 +176,15 @@ def test_gated_hierarchy_equals_level_chain_and_oracle(M, dtype, K, median):
     mism = float((host(out["disp"]) != ref[0][0]).mean())
     print("gated end-to-end level-0 mismatch rate", mism)
     assert mism < 0.02
-    # the gating changes the result, and the batched path does not take it
+    # the gating changes the result; the batched path (and its graph) gives the
+    # plain path's
     plain = M.disparity(Lg, Rg, D, K, n, r, eps)
     assert not torch.equal(plain["disp"], out["disp"])
-    with pytest.raises(M.MsibmError):
-        M.disparity_many([Lg], [Rg], [D], [K], n, r, eps, flags=M.FLAG_BATCHED, gate=ab)
+    for flags in (M.FLAG_BATCHED, M.FLAG_BATCHED | M.FLAG_GRAPH):
+        got = M.disparity_many([Lg], [Rg], [D], [K], n, r, eps, flags=flags, with_prior1=True, gate=ab,
+                               median_alpha=malpha)[0]
+        for key in ("disp", "cost", "prior1"):
+            assert torch.equal(got[key], out[key]), key
 
 
 def test_gated_mid1436_level0_sampled(M):
