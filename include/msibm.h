@@ -81,7 +81,7 @@ typedef int32_t msibm_status;
 #define MSIBM_FLAG_MEDIAN 16    /* plain and batched forward: every level's hard map goes
                                    through the selective median filter (Eq. 10)
                                    with threshold median_alpha                  */
-#define MSIBM_FLAG_GATED 32     /* plain forward only: the confidence gating of
+#define MSIBM_FLAG_GATED 32     /* plain and batched forward: the confidence gating of
                                    Sections III.B-C at every hard level: below the
                                    coarsest level, the full search where the
                                    bicubic-doubled coarser cost is <= gate_beta
