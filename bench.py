@@ -191,24 +191,27 @@ def section_batched(torch, M, synth, steps):
         del ws
     res["graph_speedup_vs_plain"] = res["plain"]["ms_per_batch"] / res["graph"]["ms_per_batch"]
     res["batched_speedup_vs_plain"] = res["plain"]["ms_per_batch"] / res["batched"]["ms_per_batch"]
-    # the same batch with the selective median (Eq. 10) at every level
-    med = {}
-    for name, flags in (("plain", 0), ("graph", M.FLAG_BATCHED | M.FLAG_GRAPH)):
-        ws = torch.empty(M.workspace_bytes(pairs_arr, len(L),
-                                           M.make_config(n, r, eps, flags=flags, median_alpha=MEDIAN_ALPHA)),
-                         dtype=torch.uint8, device=dev)
-        outs = M.disparity_many(L, R, D, K, n, r, eps, flags=flags, workspace=ws, median_alpha=MEDIAN_ALPHA)
+    # the same batch with the selective median (Eq. 10), and with the
+    # confidence gating (Eqs. 5-9), at every level
+    for key, opts in (("with_median", {"median_alpha": MEDIAN_ALPHA}),
+                      ("with_gating", {"gate": (GATE_ALPHA, GATE_BETA)})):
+        var = {}
+        for name, flags in (("plain", 0), ("graph", M.FLAG_BATCHED | M.FLAG_GRAPH)):
+            cfg = M.make_config(n, r, eps, flags=flags, **opts)
+            ws = torch.empty(M.workspace_bytes(pairs_arr, len(L), cfg), dtype=torch.uint8, device=dev)
+            outs = M.disparity_many(L, R, D, K, n, r, eps, flags=flags, workspace=ws, **opts)
 
-        def step():
-            M.disparity_many(L, R, D, K, n, r, eps, flags=flags, workspace=ws, outputs=outs,
-                             median_alpha=MEDIAN_ALPHA)
-        med[name] = {"ms_per_batch": time_ms(torch, step, steps, 3)}
-        if name == "plain":
-            mref = outs
-        else:
-            med[name]["identical_to_plain"] = all(torch.equal(a[k], b[k]) for a, b in zip(mref, outs) for k in a)
-        del ws
-    res["with_median"] = med
+            def step():
+                M.disparity_many(L, R, D, K, n, r, eps, flags=flags, workspace=ws, outputs=outs, **opts)
+            var[name] = {"ms_per_batch": time_ms(torch, step, steps, 3)}
+            if name == "plain":
+                vref = outs
+            else:
+                var[name]["identical_to_plain"] = all(torch.equal(a[k], b[k]) for a, b in zip(vref, outs)
+                                                      for k in a)
+            del ws
+        var["graph_speedup_vs_plain"] = var["plain"]["ms_per_batch"] / var["graph"]["ms_per_batch"]
+        res[key] = var
     return res
 
 

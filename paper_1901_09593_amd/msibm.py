@@ -25,8 +25,8 @@ FLAG_BATCHED = 1
 FLAG_GRAPH = 2
 FLAG_PERSISTENT = 4  # switched off: calls with it fail with MsibmError
 FLAG_PREBLUR = 8     # plain forward: level 0 matched on the blurred input
-FLAG_MEDIAN = 16     # plain forward: selective median filter (Eq. 10) at every hard level
-FLAG_GATED = 32      # plain forward: confidence gating (Eqs. 5-9) at every hard level
+FLAG_MEDIAN = 16     # plain and batched forward: selective median filter (Eq. 10) at every hard level
+FLAG_GATED = 32      # plain and batched forward: confidence gating (Eqs. 5-9) at every hard level
 MAX_LEVELS = 8
 
 
