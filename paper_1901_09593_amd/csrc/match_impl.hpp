@@ -337,7 +337,7 @@ struct BlockState {
 };
 
 // One TILE_H x TILE_W tile (tile column bx, tile row by) of one level.  Called
-// by the per-level kernel below and by the persistent batched kernel; every
+// by the per-level kernel below and by the stage-batched kernel; every
 // thread of the workgroup must call it (it synchronises the workgroup).
 // SL selects where the right statistics come from: staged in LDS with the right
 // tile (1), or read by each thread from global memory (0).

@@ -49,7 +49,7 @@ def _crop_case(H=180, W=320, seed=0):
             p.disp[:H, :W], p.nonocc[:H, :W], cfg)
 
 
-@pytest.mark.parametrize("n,rs", [(3, 3), (1, 1), (5, 2), (2, 4)])
+@pytest.mark.parametrize("n,rs", [(3, 3), (1, 1), (5, 2), (2, 4), (4, 3), (6, 1), (6, 3)])
 def test_backward_matches_oracle(M, n, rs):
     L, R, gt, vis, cfg = _crop_case(96, 200)
     D, K, r, eps, tau = cfg.max_disp, cfg.levels, cfg.refine_radius, cfg.var_eps, cfg.tau
