@@ -413,8 +413,8 @@ def disparity_many(lefts: Sequence[torch.Tensor], rights: Sequence[torch.Tensor]
                    outputs: Optional[List[Dict[str, torch.Tensor]]] = None,
                    median_alpha: Optional[float] = None,
                    gate: Optional[Tuple[float, float]] = None) -> List[Dict[str, torch.Tensor]]:
-    """Forward pass of several pairs in one call (flags: FLAG_BATCHED, FLAG_GRAPH,
-    a median_alpha on either path, FLAG_PREBLUR or a gate on the plain path).
+    """Forward pass of several pairs in one call (flags: FLAG_BATCHED, FLAG_GRAPH;
+    a median_alpha or a gate on either path, FLAG_PREBLUR on the plain path).
     `workspace` and `outputs` may be passed in to reuse buffers across calls."""
     pairs, keep = _pairs(lefts, rights, Ds, Ks)
     npair = len(lefts)
