@@ -212,3 +212,35 @@ def test_hires2880_full_size_forward_backward(M):
     err = float(np.abs(host(outs[0]["soft"]).astype(np.float64) - ds_o).max())
     print("hires2880 soft max |dd|", err)
     assert err <= 1e-2
+
+
+def test_backward_linearity_zero_and_locality(M):
+    """The gradient is linear in the upstream gradient g: power-of-two scalings
+    of g (2^40 and 2^-40) pass through the per-chunk fixed-point scale, g = 0
+    gives exactly zero, and a single-pixel g reaches only that pixel's window
+    (left) and its windows at the candidates (right)."""
+    L, R, gt, vis, cfg = _crop_case(64, 160, seed=4)
+    D, K, n, r, eps, rs, tau = cfg.max_disp, cfg.levels, cfg.half_window, cfg.refine_radius, \
+        cfg.var_eps, cfg.soft_radius, cfg.tau
+    out = M.disparity(dev(L), dev(R), D, K, n, r, eps, soft_radius=rs, tau=tau)
+    g = synth.grad_seed(5, *L.shape).astype(np.float32)
+
+    def bw(gg):
+        gL, gR = M.backward(dev(L), dev(R), out["prior1"], dev(gg), D, K, n, r, eps, rs, tau)
+        return host(gL).astype(np.float64), host(gR).astype(np.float64)
+    aL, aR = bw(g)
+    for k in (40, -40):
+        bL, bR = bw((g * np.float32(2.0 ** k)).astype(np.float32))
+        assert rel(bL * 2.0 ** -k, aL) < 1e-5 and rel(bR * 2.0 ** -k, aR) < 1e-5, k
+    zL, zR = bw(np.zeros_like(g))
+    assert not zL.any() and not zR.any()
+    i, j = 30, 100
+    one = np.zeros_like(g)
+    one[i, j] = 1.0
+    sL, sR = bw(one)
+    ys, xs = np.nonzero(sL)
+    assert len(ys) > 0
+    assert ys.min() >= i - n and ys.max() <= i + n and xs.min() >= j - n and xs.max() <= j + n
+    ys, xs = np.nonzero(sR)
+    assert len(ys) > 0
+    assert ys.min() >= i - n and ys.max() <= i + n and xs.min() >= j - (D - 1) - n and xs.max() <= j + n
