@@ -454,8 +454,8 @@ def main():
                     help="only run a plain device copy of BYTES bytes five times")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the method has no cross-GPU exchange on its hot "
-              "path and this build runs on a single MI355X (use --gpus 1).", file=sys.stderr)
+        print("bench.py measures one GPU only: the method's hot path has no cross-GPU exchange, and the library "
+              "runs on a single MI355X (use --gpus 1).", file=sys.stderr)
         sys.exit(2)
 
     import torch
