@@ -188,3 +188,41 @@ def test_autotune_cache_parsing_from_host(lib, tmp_path):
     assert (1, 4, 5, 0, 992, 1436, 256, 2) in [r[:8] for r in rows]
     assert e.msibm_autotune(0, None) == 0
     assert e.msibm_force_variant(16) == -1 and e.msibm_force_variant(15) == 0 and e.msibm_force_variant(-1) == 0
+
+
+def test_header_is_plain_c_and_links(lib, tmp_path):
+    """include/msibm.h compiles as strict C99 on its own, every declared entry
+    point links against libmsibm.so, and host-side calls run from C: the
+    version string, and a bad call rejected with its error message before any
+    device work."""
+    import shutil
+    import subprocess
+    from paper_1901_09593_amd import msibm
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    names = _declared()
+    src = ["#include <stdio.h>", "#include <string.h>", '#include "msibm.h"', "typedef void (*fn_t)(void);",
+           "int main(void) {", "    fn_t volatile fns[] = {"]
+    src += [f"        (fn_t)&{n}," for n in names]
+    src += ["    };",
+            "    (void)fns;",
+            "    msibm_config cfg;",
+            "    memset(&cfg, 0, sizeof cfg);",
+            "    cfg.half_window = 99;  /* outside the compiled range */",
+            "    const int st = msibm_disparity(NULL, 1, &cfg, NULL, NULL, NULL, NULL, NULL, 0, NULL);",
+            '    printf("%s|%d|%s\\n", msibm_version(), st, msibm_last_error());',
+            "    return st < 0 ? 0 : 1;",
+            "}"]
+    c = tmp_path / "use_abi.c"
+    c.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "use_abi"
+    libdir = os.path.dirname(msibm.LIB_PATH)
+    cmd = [gcc, "-std=c99", "-Wall", "-Wextra", "-pedantic", "-Werror", "-I", os.path.join(ROOT, "include"),
+           str(c), "-o", str(exe), "-L", libdir, "-lmsibm", f"-Wl,-rpath,{libdir}"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    version, status, message = r.stdout.strip().split("|", 2)
+    assert version == msibm.version() and int(status) < 0 and message
