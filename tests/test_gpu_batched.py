@@ -174,6 +174,14 @@ def test_batch32_full_size_sampled(M):
         d, C, p1 = (got[i][x].cpu().numpy() for x in ("disp", "cost", "prior1"))
         st = check_pixels(d, C, p.left, p.right, n, D[i], p1, r, eps, ii, jj)
         print(f"batch32 pair {i} ({W}x{H}, D={D[i]}, K={k})", st)
+    # the same batch with the confidence gating and the median (the paper's
+    # thresholds): the batched graph equals the per-pair path on every pair
+    print("batch32 full size, gated + median, batched graph", flush=True)
+    opts = dict(with_prior1=True, gate=(0.9, 0.9), median_alpha=0.9)
+    got = M.disparity_many(L, R, D, K, n, r, eps, flags=M.FLAG_BATCHED | M.FLAG_GRAPH, **opts)
+    ref = M.disparity_many(L, R, D, K, n, r, eps, **opts)
+    torch.cuda.synchronize()
+    _equal(ref, got)
 
 
 def test_batched_median_uneven_pairs_equals_plain(M):
