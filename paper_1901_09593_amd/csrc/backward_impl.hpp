@@ -458,6 +458,48 @@ __global__ __launch_bounds__(BACK_THREADS) void backward_multi_kernel(MultiArgs 
     backward_tile<NW, NC>(a.back[s.pair], t % s.tiles_x, t / s.tiles_x, sm);
 }
 
+// Backward tiles of several soft levels of one pair in one launch.  Their
+// backwards are independent (each adds into its own level's gradients), so the
+// small levels' few tiles run beside level 0's instead of after them.  The
+// arguments travel by value: entry i owns blocks [task0[i], task0[i + 1]).
+struct BackLevels {
+    BackArgs lev[MSIBM_MAX_LEVELS];
+    int task0[MSIBM_MAX_LEVELS];
+    int tiles_x[MSIBM_MAX_LEVELS];
+    int n;
+};
+
+template <int NW, int NC>
+__global__ __launch_bounds__(BACK_THREADS) void backward_levels_kernel(BackLevels a)
+{
+    __shared__ BackSmem<NW, BACK_CHUNK> sm;
+    int i = 0;
+    while (i + 1 < a.n && a.task0[i + 1] <= (int)blockIdx.x) ++i;
+    const int t = (int)blockIdx.x - a.task0[i];
+    backward_tile<NW, NC>(a.lev[i], t % a.tiles_x[i], t / a.tiles_x[i], sm);
+}
+
+template <int NW>
+static hipError_t dispatch_backward_levels(int nc, const BackLevels& a, int blocks, hipStream_t s)
+{
+    if (blocks < 1 || a.n < 1 || a.n > MSIBM_MAX_LEVELS) return hipErrorInvalidValue;
+    switch (nc) {
+        case 3: hipLaunchKernelGGL((backward_levels_kernel<NW, 3>), dim3(blocks), dim3(BACK_THREADS), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((backward_levels_kernel<NW, 5>), dim3(blocks), dim3(BACK_THREADS), 0, s, a); break;
+        case 7: hipLaunchKernelGGL((backward_levels_kernel<NW, 7>), dim3(blocks), dim3(BACK_THREADS), 0, s, a); break;
+        case 9: hipLaunchKernelGGL((backward_levels_kernel<NW, 9>), dim3(blocks), dim3(BACK_THREADS), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_backward_levels_n1(int nc, const BackLevels& a, int blocks, hipStream_t s);
+hipError_t launch_backward_levels_n2(int nc, const BackLevels& a, int blocks, hipStream_t s);
+hipError_t launch_backward_levels_n3(int nc, const BackLevels& a, int blocks, hipStream_t s);
+hipError_t launch_backward_levels_n4(int nc, const BackLevels& a, int blocks, hipStream_t s);
+hipError_t launch_backward_levels_n5(int nc, const BackLevels& a, int blocks, hipStream_t s);
+hipError_t launch_backward_levels_n6(int nc, const BackLevels& a, int blocks, hipStream_t s);
+
 template <int NW>
 static hipError_t dispatch_backward_multi(int nc, const MultiArgs& a, int blocks, hipStream_t s)
 {

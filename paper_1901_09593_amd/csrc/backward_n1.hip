@@ -7,4 +7,8 @@ hipError_t launch_backward_multi_n1(int nc, const MultiArgs& a, int blocks, hipS
 {
     return dispatch_backward_multi<1>(nc, a, blocks, s);
 }
+hipError_t launch_backward_levels_n1(int nc, const BackLevels& a, int blocks, hipStream_t s)
+{
+    return dispatch_backward_levels<1>(nc, a, blocks, s);
+}
 }  // namespace msibm

@@ -7,4 +7,8 @@ hipError_t launch_backward_multi_n3(int nc, const MultiArgs& a, int blocks, hipS
 {
     return dispatch_backward_multi<3>(nc, a, blocks, s);
 }
+hipError_t launch_backward_levels_n3(int nc, const BackLevels& a, int blocks, hipStream_t s)
+{
+    return dispatch_backward_levels<3>(nc, a, blocks, s);
+}
 }  // namespace msibm

@@ -44,6 +44,8 @@ static int hip_err(hipError_t e, const char* what, std::string* err)
     return MSIBM_ERR_HIP;
 }
 
+hipError_t launch_backward_levels(int n, int nc, const BackLevels& a, int blocks, hipStream_t s);
+
 // Level images of a pair: level 0 is the caller's input, levels k >= 1 are
 // built into the workspace, up to three reduce steps per launch.
 static int build_pyramid(const msibm_pair& P, const PairLayout& lay, char* ws, const void* img[][2], int* pitch,
@@ -343,11 +345,19 @@ int run_pair_backward_levels(const msibm_pair& P, const PairLayout& lay, const m
         e = launch_zero(gl[k], gr[k], (size_t)lay.h[k] * lay.w[k], s);
         if (e != hipSuccess) return hip_err(e, "zero launch", err);
     }
-    // from the coarsest soft level down: each level's own gradient, then its
-    // total carried one level down through the reduce's adjoint
-    for (int k = K - 2; k >= 0; --k) {
-        if (grad_soft[k]) {
-            BackArgs b{};
+    // every soft level's own gradient, all levels' tiles in one launch per
+    // window size (the levels' backwards are independent: each adds into its
+    // own level's gradients) ...
+    for (int k0 = 0; k0 <= K - 2; ++k0) {
+        if (!grad_soft[k0]) continue;
+        bool first = true;
+        for (int k = 0; k < k0; ++k) first = first && !(grad_soft[k] && level_n(cfg, k) == level_n(cfg, k0));
+        if (!first) continue;
+        BackLevels bl{};
+        int blocks = 0;
+        for (int k = k0; k <= K - 2; ++k) {
+            if (!grad_soft[k] || level_n(cfg, k) != level_n(cfg, k0)) continue;
+            BackArgs& b = bl.lev[bl.n];
             b.L = (const float*)img[k][0];
             b.R = (const float*)img[k][1];
             b.H = lay.h[k];
@@ -367,31 +377,35 @@ int run_pair_backward_levels(const msibm_pair& P, const PairLayout& lay, const m
             b.gpitch = lay.w[k];
             b.gL = gl[k];
             b.gR = gr[k];
-            char lab[32];
-            snprintf(lab, sizeof(lab), "backward_l%d", k);
-            TimedLaunch t(lab, s);
-            e = launch_backward(level_n(cfg, k), slots_for_radius(cfg->soft_radius), b, s);
-            if (e != hipSuccess) return hip_err(e, "backward launch", err);
+            bl.task0[bl.n] = blocks;
+            bl.tiles_x[bl.n] = (lay.w[k] + TILE_W - 1) / TILE_W;
+            blocks += bl.tiles_x[bl.n] * ((lay.h[k] + TILE_H1 - 1) / TILE_H1);
+            ++bl.n;
         }
-        if (k >= 1) {
-            AdjArgs ad{};
-            ad.g[0] = gl[k];
-            ad.g[1] = gr[k];
-            ad.out[0] = gl[k - 1];
-            ad.out[1] = gr[k - 1];
-            ad.views = 2;
-            ad.Hc = lay.h[k];
-            ad.Wc = lay.w[k];
-            ad.gpitch = lay.w[k];
-            ad.H = lay.h[k - 1];
-            ad.W = lay.w[k - 1];
-            ad.opitch = lay.w[k - 1];
-            char lab[32];
-            snprintf(lab, sizeof(lab), "adjoint_l%d", k);
-            TimedLaunch t(lab, s);
-            e = launch_adjoint(ad, s);
-            if (e != hipSuccess) return hip_err(e, "adjoint launch", err);
-        }
+        TimedLaunch t("backward_levels", s);
+        e = launch_backward_levels(level_n(cfg, k0), slots_for_radius(cfg->soft_radius), bl, blocks, s);
+        if (e != hipSuccess) return hip_err(e, "backward launch", err);
+    }
+    // ... then, from the coarsest soft level down, each level's total carried
+    // one level down through the reduce's adjoint
+    for (int k = K - 2; k >= 1; --k) {
+        AdjArgs ad{};
+        ad.g[0] = gl[k];
+        ad.g[1] = gr[k];
+        ad.out[0] = gl[k - 1];
+        ad.out[1] = gr[k - 1];
+        ad.views = 2;
+        ad.Hc = lay.h[k];
+        ad.Wc = lay.w[k];
+        ad.gpitch = lay.w[k];
+        ad.H = lay.h[k - 1];
+        ad.W = lay.w[k - 1];
+        ad.opitch = lay.w[k - 1];
+        char lab[32];
+        snprintf(lab, sizeof(lab), "adjoint_l%d", k);
+        TimedLaunch t(lab, s);
+        e = launch_adjoint(ad, s);
+        if (e != hipSuccess) return hip_err(e, "adjoint launch", err);
     }
     return MSIBM_OK;
 }
@@ -405,6 +419,19 @@ hipError_t launch_backward(int n, int nc, const BackArgs& a, hipStream_t s)
         case 4: return launch_backward_n4(nc, a, s);
         case 5: return launch_backward_n5(nc, a, s);
         case 6: return launch_backward_n6(nc, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_backward_levels(int n, int nc, const BackLevels& a, int blocks, hipStream_t s)
+{
+    switch (n) {
+        case 1: return launch_backward_levels_n1(nc, a, blocks, s);
+        case 2: return launch_backward_levels_n2(nc, a, blocks, s);
+        case 3: return launch_backward_levels_n3(nc, a, blocks, s);
+        case 4: return launch_backward_levels_n4(nc, a, blocks, s);
+        case 5: return launch_backward_levels_n5(nc, a, blocks, s);
+        case 6: return launch_backward_levels_n6(nc, a, blocks, s);
     }
     return hipErrorInvalidValue;
 }
