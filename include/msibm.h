@@ -74,7 +74,7 @@ typedef int32_t msibm_status;
 /* flags of msibm_config.flags */
 #define MSIBM_FLAG_BATCHED 1    /* one launch per stage for all pairs together  */
 #define MSIBM_FLAG_GRAPH 2      /* with BATCHED: capture once, replay a hipGraph */
-#define MSIBM_FLAG_PREBLUR 8    /* plain forward only: level 0 is matched on the
+#define MSIBM_FLAG_PREBLUR 8    /* plain and batched forward: level 0 is matched on the
                                    input blurred with the pyramid's 5x5 binomial
                                    kernel (every pixel, clamp-to-edge; the blur
                                    of the original image of Section IV)         */

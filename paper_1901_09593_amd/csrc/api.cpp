@@ -91,8 +91,6 @@ msibm_status validate_config(const msibm_config* cfg)
     if (cfg->flags &
         ~(MSIBM_FLAG_BATCHED | MSIBM_FLAG_GRAPH | MSIBM_FLAG_PREBLUR | MSIBM_FLAG_MEDIAN | MSIBM_FLAG_GATED))
         return fail(MSIBM_ERR_INVALID_ARG, "unknown flags 0x%x", cfg->flags);
-    if ((cfg->flags & MSIBM_FLAG_PREBLUR) && (cfg->flags & MSIBM_FLAG_BATCHED))
-        return fail(MSIBM_ERR_UNSUPPORTED, "MSIBM_FLAG_PREBLUR runs on the plain path only");
     if ((cfg->flags & MSIBM_FLAG_MEDIAN) && !std::isfinite(cfg->median_alpha))
         return fail(MSIBM_ERR_INVALID_ARG, "median_alpha must be finite");
     if ((cfg->flags & MSIBM_FLAG_GATED) && (!std::isfinite(cfg->gate_alpha) || !std::isfinite(cfg->gate_beta)))

@@ -35,7 +35,7 @@ static int levels_of(const msibm_pair& p) { return p.num_levels ? p.num_levels :
 
 enum StageKind {
     STAGE_LEVELS = 0, STAGE_STATS = 1, STAGE_MATCH = 2, STAGE_ZERO = 3, STAGE_BACKWARD = 4, STAGE_MEDIAN = 5,
-    STAGE_GATE = 6
+    STAGE_GATE = 6, STAGE_BLUR = 7
 };
 
 struct StageLaunch {
@@ -133,6 +133,10 @@ static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg
     }
     auto h_of = [&](int p, int k) { return level_dim(pairs[p].height, k); };
     auto w_of = [&](int p, int k) { return level_dim(pairs[p].width, k); };
+    // element type of the image level k is matched on (the pre-blur matches
+    // level 0 on a float copy)
+    const bool preblur = (cfg->flags & MSIBM_FLAG_PREBLUR) != 0;
+    auto dtype_at = [&](int p, int k) { return (k == 0 && !preblur) ? pairs[p].dtype : MSIBM_F32; };
     auto begin = [&](int kind, int level, int mode, int dtype, int nc) {
         StageLaunch l{};
         l.kind = kind;
@@ -145,11 +149,13 @@ static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg
     };
     auto add = [&](int type, int p, int k) {
         StageLaunch& l = pl.launches.back();
-        const Segment s = make_seg(type, p, k, h_of(p, k), w_of(p, k), k == 0 ? pairs[p].dtype : MSIBM_F32, l.blocks);
+        const Segment s = make_seg(type, p, k, h_of(p, k), w_of(p, k), dtype_at(p, k), l.blocks);
         l.blocks += seg_tiles(s);
         l.nseg++;
         pl.segs.push_back(s);
     };
+    // the pre-blur: one blur launch per pair (no segments) before everything
+    if (preblur) begin(STAGE_BLUR, 0, 0, 0, 0);
     // pyramid step k: level k's statistics (heavier tiles first) side by side
     // with the reduce that makes level k + 1
     for (int k = 0; k < Kmax; ++k) {
@@ -171,7 +177,7 @@ static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg
                 for (int p = 0; p < np; ++p) {
                     if (k >= K[p]) continue;
                     const int mode = mode_of(p, k);
-                    const int dtype = k == 0 ? pairs[p].dtype : MSIBM_F32;
+                    const int dtype = dtype_at(p, k);
                     if (mode != modes[m] || dtype != dt) continue;
                     if (!opened) {
                         const int nc = mode == MODE_FULL
@@ -195,7 +201,7 @@ static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg
                     for (int p = 0; p < np; ++p) {
                         if (k >= K[p] || mode_of(p, k) == MODE_SOFT) continue;
                         const int gmode = (k == K[p] - 1) ? GATE_MODE_REPICK : GATE_MODE_FUSED;
-                        const int dtype = k == 0 ? pairs[p].dtype : MSIBM_F32;
+                        const int dtype = dtype_at(p, k);
                         if (gmode != want || dtype != dt) continue;
                         if (!opened) {
                             begin(STAGE_GATE, k, want, dt, 0);
@@ -247,8 +253,8 @@ static void plan_backward_stages(const msibm_pair* pairs, int np, BatchPlan& pl)
 // Workspace layout of one pair on the batched path (the same as the size query's).
 static PairLayout batch_layout(const msibm_pair& P, const msibm_config* cfg)
 {
-    return pair_layout(P, levels_of(P), false, (cfg->flags & MSIBM_FLAG_MEDIAN) != 0,
-                       (cfg->flags & MSIBM_FLAG_GATED) != 0);
+    return pair_layout(P, levels_of(P), (cfg->flags & MSIBM_FLAG_PREBLUR) != 0,
+                       (cfg->flags & MSIBM_FLAG_MEDIAN) != 0, (cfg->flags & MSIBM_FLAG_GATED) != 0);
 }
 
 // Level descriptors of every pair, with its workspace region and outputs.
@@ -258,6 +264,7 @@ static void plan_levels(const msibm_pair* pairs, int np, const msibm_config* cfg
     size_t base = 0;
     const bool median = (cfg->flags & MSIBM_FLAG_MEDIAN) != 0;
     const bool gated = (cfg->flags & MSIBM_FLAG_GATED) != 0;
+    const bool preblur = (cfg->flags & MSIBM_FLAG_PREBLUR) != 0;
     for (int p = 0; p < np; ++p) {
         const msibm_pair& P = pairs[p];
         const int K = levels_of(P);
@@ -275,6 +282,17 @@ static void plan_levels(const msibm_pair* pairs, int np, const msibm_config* cfg
                 d.map = out.disp[p];
                 d.cost = out.cost ? out.cost[p] : nullptr;
                 d.soft = out.soft ? out.soft[p] : nullptr;
+                if (preblur) {
+                    // matched on the blurred copy; the pyramid reads the input
+                    d.src[0] = P.left;
+                    d.src[1] = P.right;
+                    d.spitch = P.pitch;
+                    d.sdtype = P.dtype;
+                    d.img[0] = ws + lay.blur[0];
+                    d.img[1] = ws + lay.blur[1];
+                    d.pitch = lay.w[0];
+                    d.dtype = MSIBM_F32;
+                }
             } else {
                 d.img[0] = ws + lay.img[k][0];
                 d.img[1] = ws + lay.img[k][1];
@@ -361,10 +379,26 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
         else if (l.kind == STAGE_GATE)
             snprintf(lab, sizeof(lab), l.mode == GATE_MODE_FUSED ? "batch_gate_fused_l%d" : "batch_gate_repick_l%d",
                      l.level);
+        else if (l.kind == STAGE_BLUR) snprintf(lab, sizeof(lab), "batch_preblur_l0");
         else snprintf(lab, sizeof(lab), "batch_match_%s_l%d", mode_name[l.mode], l.level);
         const int slot = timed ? timing_begin(lab, s) : -1;
-        hipError_t e;
-        if (l.kind == STAGE_LEVELS) e = launch_levels_multi(level_n(cfg, l.level), a, l.blocks, s);
+        hipError_t e = hipSuccess;
+        if (l.kind == STAGE_BLUR) {
+            // level 0 of every pair: its input blurred into the float copy it is matched on
+            for (size_t p = 0; p < pl.level_base.size() && e == hipSuccess; ++p) {
+                const LevelDesc& d = pl.levels[pl.level_base[p]];
+                BlurArgs b{};
+                for (int v = 0; v < 2; ++v) {
+                    b.src[v] = d.src[v];
+                    b.dst[v] = (float*)d.img[v];
+                }
+                b.H = d.H;
+                b.W = d.W;
+                b.spitch = d.spitch;
+                b.dpitch = d.pitch;
+                e = launch_blur(d.sdtype, b, s);
+            }
+        } else if (l.kind == STAGE_LEVELS) e = launch_levels_multi(level_n(cfg, l.level), a, l.blocks, s);
         else if (l.kind == STAGE_STATS) e = launch_stats_multi(level_n(cfg, 0), a, l.blocks, s);
         else if (l.kind == STAGE_ZERO) {
             hipLaunchKernelGGL(zero_multi_kernel, dim3(l.blocks), dim3(256), 0, s, a);

@@ -187,6 +187,10 @@ struct LevelDesc {
     float* soft;          // level 0 only, soft mode
     int Dk;
     int dtype;            // element type of img (MSIBM_U8 / MSIBM_F32)
+    // level 0 matched on another image than the pyramid is built from (the
+    // pre-blur): the pyramid's source (the caller's input), else src[0] = NULL
+    const void* src[2];
+    int spitch, sdtype;
 };
 
 // Tiles [task0, task0 + tiles_x * tiles_y * views) of a launch belong to this

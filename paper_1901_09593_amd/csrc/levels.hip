@@ -66,7 +66,8 @@ __global__ __launch_bounds__(TW_THREADS) void tower_kernel(TowerArgs a)
 }
 
 // Tile t of a reduce segment: reads level k-1 of its pair (the caller's input
-// at k = 1) and writes level k of one view.
+// at k = 1, also where level 0 is matched on its blurred copy) and writes
+// level k of one view.
 __device__ __forceinline__ void reduce_seg_tile(const MultiArgs& a, const Segment& s, int t, ReduceSmem& sm)
 {
     const LevelDesc* lv = a.levels + a.level_base[s.pair];
@@ -75,16 +76,17 @@ __device__ __forceinline__ void reduce_seg_tile(const MultiArgs& a, const Segmen
     const int per = s.tiles_x * s.tiles_y;
     const int v = t / per, tx = (t % per) % s.tiles_x, ty = (t % per) / s.tiles_x;
     ReduceArgs ra{};  // the tile's view only, so no dynamic indexing
-    ra.src[0] = v ? P.img[1] : P.img[0];
+    const bool own = P.src[0] != nullptr;
+    ra.src[0] = own ? (v ? P.src[1] : P.src[0]) : (v ? P.img[1] : P.img[0]);
     ra.dst[0] = (float*)(v ? L.img[1] : L.img[0]);
     ra.views = 1;
     ra.H = P.H;
     ra.W = P.W;
-    ra.spitch = P.pitch;
+    ra.spitch = own ? P.spitch : P.pitch;
     ra.Ho = L.H;
     ra.Wo = L.W;
     ra.dpitch = L.pitch;
-    if (P.dtype == 0) reduce_tile<uint8_t>(ra, 0, tx, ty, sm);
+    if ((own ? P.sdtype : P.dtype) == 0) reduce_tile<uint8_t>(ra, 0, tx, ty, sm);
     else reduce_tile<float>(ra, 0, tx, ty, sm);
 }
 

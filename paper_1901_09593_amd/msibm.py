@@ -24,7 +24,7 @@ MSIBM_F32 = 1
 FLAG_BATCHED = 1
 FLAG_GRAPH = 2
 FLAG_PERSISTENT = 4  # switched off: calls with it fail with MsibmError
-FLAG_PREBLUR = 8     # plain forward: level 0 matched on the blurred input
+FLAG_PREBLUR = 8     # plain and batched forward: level 0 matched on the blurred input
 FLAG_MEDIAN = 16     # plain and batched forward: selective median filter (Eq. 10) at every hard level
 FLAG_GATED = 32      # plain and batched forward: confidence gating (Eqs. 5-9) at every hard level
 MAX_LEVELS = 8
@@ -413,8 +413,8 @@ def disparity_many(lefts: Sequence[torch.Tensor], rights: Sequence[torch.Tensor]
                    outputs: Optional[List[Dict[str, torch.Tensor]]] = None,
                    median_alpha: Optional[float] = None,
                    gate: Optional[Tuple[float, float]] = None) -> List[Dict[str, torch.Tensor]]:
-    """Forward pass of several pairs in one call (flags: FLAG_BATCHED, FLAG_GRAPH;
-    a median_alpha or a gate on either path, FLAG_PREBLUR on the plain path).
+    """Forward pass of several pairs in one call (flags: FLAG_BATCHED, FLAG_GRAPH,
+    FLAG_PREBLUR; a median_alpha or a gate, on either path).
     `workspace` and `outputs` may be passed in to reuse buffers across calls."""
     pairs, keep = _pairs(lefts, rights, Ds, Ks)
     npair = len(lefts)

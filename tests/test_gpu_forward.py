@@ -258,6 +258,36 @@ def test_preblur_level_zero(M, dtype):
     st = check_level(host(out["disp"]), host(out["cost"]), Lb, Rb, n, D, host(out["prior1"]), r, eps)
     print("preblur level 0", st)
     assert st["mismatch"] <= 0.01
+    # the batched path and its graph give the plain path's outputs
+    for flags in (M.FLAG_BATCHED, M.FLAG_BATCHED | M.FLAG_GRAPH):
+        got = M.disparity_many([Lg], [Rg], [D], [K], n, r, eps, with_prior1=True,
+                               flags=flags | M.FLAG_PREBLUR)[0]
+        for key in ("disp", "cost", "prior1"):
+            assert torch.equal(got[key], out[key]), key
+
+
+def test_batched_preblur_uneven_pairs_equals_plain(M):
+    """The pre-blur on the batched path with uneven pairs and depths (one of
+    them a single level), uint8 and float, alone and with the paper's other
+    options (gating, median, per-level windows, refine +-1): every output
+    equals the plain path's."""
+    shapes = [(96, 150, 48, 0), (61, 200, 100, 0), (40, 70, 16, 1), (130, 90, 20, 2)]
+    Ds = [s[2] for s in shapes]
+    Ks = [s[3] for s in shapes]
+    for dt, eps, n, r, opts in (("u8", 0.065, 3, 2, {}), ("f32", 1e-6, 3, 2, {}),
+                                ("u8", 0.065, [5, 2, 1, 1], 1, dict(gate=(0.9, 0.9), median_alpha=0.9)),
+                                ("f32", 1e-6, [5, 2, 1, 1], 1, dict(gate=(0.9, 0.9), median_alpha=0.9))):
+        pairs = [_tex_pair(760 + i, h, w, max(3, D // 2), dt) for i, (h, w, D, K) in enumerate(shapes)]
+        L = [dev(p.left) for p in pairs]
+        R = [dev(p.right) for p in pairs]
+        plain = M.disparity_many(L, R, Ds, Ks, n, r, eps, with_prior1=True, flags=M.FLAG_PREBLUR, **opts)
+        for flags in (M.FLAG_BATCHED, M.FLAG_BATCHED | M.FLAG_GRAPH):
+            got = M.disparity_many(L, R, Ds, Ks, n, r, eps, with_prior1=True, flags=flags | M.FLAG_PREBLUR,
+                                   **opts)
+            for a, b in zip(got, plain):
+                assert set(a) == set(b)
+                for key in a:
+                    assert torch.equal(a[key], b[key]), (key, flags, opts)
 
 
 @pytest.mark.parametrize("H,W,alpha", [(61, 90, 0.9), (37, 150, 0.97), (1, 1, 0.9), (5, 300, 0.5),
