@@ -191,18 +191,22 @@ def section_batched(torch, M, synth, steps):
         del ws
     res["graph_speedup_vs_plain"] = res["plain"]["ms_per_batch"] / res["graph"]["ms_per_batch"]
     res["batched_speedup_vs_plain"] = res["plain"]["ms_per_batch"] / res["batched"]["ms_per_batch"]
-    # the same batch with the selective median (Eq. 10), and with the
-    # confidence gating (Eqs. 5-9), at every level
-    for key, opts in (("with_median", {"median_alpha": MEDIAN_ALPHA}),
-                      ("with_gating", {"gate": (GATE_ALPHA, GATE_BETA)})):
+    # the same batch with the selective median (Eq. 10), with the confidence
+    # gating (Eqs. 5-9), and with the paper's whole method (pre-blur, gating,
+    # median, windows halved from 11 x 11 level by level, refine +-1)
+    gate = {"gate": (GATE_ALPHA, GATE_BETA)}
+    for key, opts, vflags, vn, vr in (
+            ("with_median", {"median_alpha": MEDIAN_ALPHA}, 0, n, r),
+            ("with_gating", gate, 0, n, r),
+            ("with_paper_method", dict(gate, median_alpha=MEDIAN_ALPHA), M.FLAG_PREBLUR, [5, 2, 1, 1, 1], 1)):
         var = {}
-        for name, flags in (("plain", 0), ("graph", M.FLAG_BATCHED | M.FLAG_GRAPH)):
-            cfg = M.make_config(n, r, eps, flags=flags, **opts)
+        for name, flags in (("plain", vflags), ("graph", vflags | M.FLAG_BATCHED | M.FLAG_GRAPH)):
+            cfg = M.make_config(vn, vr, eps, flags=flags, **opts)
             ws = torch.empty(M.workspace_bytes(pairs_arr, len(L), cfg), dtype=torch.uint8, device=dev)
-            outs = M.disparity_many(L, R, D, K, n, r, eps, flags=flags, workspace=ws, **opts)
+            outs = M.disparity_many(L, R, D, K, vn, vr, eps, flags=flags, workspace=ws, **opts)
 
             def step():
-                M.disparity_many(L, R, D, K, n, r, eps, flags=flags, workspace=ws, outputs=outs, **opts)
+                M.disparity_many(L, R, D, K, vn, vr, eps, flags=flags, workspace=ws, outputs=outs, **opts)
             var[name] = {"ms_per_batch": time_ms(torch, step, steps, 3)}
             if name == "plain":
                 vref = outs
