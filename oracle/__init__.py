@@ -428,18 +428,6 @@ def backward(L0: np.ndarray, R0: np.ndarray, n: int, D: int, coarse1: np.ndarray
     return gL, gR
 
 
-def loss_mask(nonocc: np.ndarray, n: int) -> np.ndarray:
-    """Pixels that enter the loss: visible in the right view and at least n pixels
-    from every border (a reading; the paper has no loss)."""
-    H, W = nonocc.shape
-    m = nonocc.copy()
-    m[:n, :] = False
-    m[H - n:, :] = False
-    m[:, :n] = False
-    m[:, W - n:] = False
-    return m
-
-
 def l1_loss(dsoft: np.ndarray, dgt: np.ndarray, mask: np.ndarray):
     """Masked mean absolute error and its gradient with respect to d_soft
     (sign(0) = 0)."""

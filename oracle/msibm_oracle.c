@@ -65,8 +65,8 @@ void orc_reduce_adjoint(const double* G, int H, int W, double* out)
                         w[a + 2] * w[b + 2] * G[(size_t)y * Wo + x];
 }
 
-/* The same 5x5 binomial blur at every pixel, the "Gaussian blur over the original
- * image" of Section IV (matching on a blurred level 0 is the pre-blur variant):
+/* The same 5x5 binomial blur at every pixel: Section IV blurs the input image
+ * before matching (matching on a blurred level 0 is the pre-blur variant):
  * out(y, x) = sum_{a,b} w_a w_b in(clamp(y + a), clamp(x + b)). */
 void orc_blur(const double* in, int H, int W, double* out)
 {

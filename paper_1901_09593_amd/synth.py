@@ -30,6 +30,7 @@ __all__ = [
     "batch_workload",
     "auto_levels",
     "grad_seed",
+    "loss_mask",
 ]
 
 
@@ -245,6 +246,22 @@ def grad_seed(seed: int, H: int, W: int) -> np.ndarray:
     """Seeded upstream gradient dL/d(d_soft) for backward tests (float64)."""
     rng = np.random.Generator(np.random.PCG64(10_000 + seed))
     return rng.standard_normal((H, W))
+
+
+def loss_mask(nonocc: np.ndarray, n: int, max_disp: int) -> np.ndarray:
+    """Pixels that enter the masked mean-L1 training loss (the paper has no loss;
+    this is the reading of the differentiable workloads): visible in the right
+    view, the (2n+1)^2 window inside the image (n <= i <= H-1-n, n <= j <= W-1-n),
+    and j >= n + D - 1, so that the right window of every candidate z <= D-1
+    lies inside the image too (a fixed sufficient condition: no loss pixel
+    reaches a clamped read, whatever its candidate interval)."""
+    H, W = nonocc.shape
+    m = np.asarray(nonocc, dtype=bool).copy()
+    m[:n, :] = False
+    m[max(H - n, 0):, :] = False
+    m[:, :min(W, n + max_disp - 1)] = False
+    m[:, max(W - n, 0):] = False
+    return m
 
 
 def level_sizes(H: int, W: int, K: int):

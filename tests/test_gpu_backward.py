@@ -35,21 +35,13 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _mask(vis, n):
-    """Loss pixels: visible in the right view, at least n pixels from the border."""
-    m = vis.copy()
-    m[:n, :] = m[-n:, :] = False
-    m[:, :n] = m[:, -n:] = False
-    return m
-
-
 def _crop_case(H=180, W=320, seed=0):
     p, cfg = synth.workload("diff960", seed)
     return (np.ascontiguousarray(p.left[:H, :W]), np.ascontiguousarray(p.right[:H, :W]),
             p.disp[:H, :W], p.nonocc[:H, :W], cfg)
 
 
-@pytest.mark.parametrize("n,rs", [(3, 3), (1, 1), (5, 2), (2, 4), (4, 3), (6, 1), (6, 3)])
+@pytest.mark.parametrize("n,rs", [(3, 3), (1, 1), (5, 2), (5, 3), (2, 4), (4, 3), (6, 1), (6, 3)])
 def test_backward_matches_oracle(M, n, rs):
     L, R, gt, vis, cfg = _crop_case(96, 200)
     D, K, r, eps, tau = cfg.max_disp, cfg.levels, cfg.refine_radius, cfg.var_eps, cfg.tau
@@ -79,41 +71,85 @@ def test_backward_sum_rules_and_repeatability(M):
         assert abs((xs * img).sum()) < 1e-4 * scale * np.abs(img).max()
 
 
+def _planar_crop(p, h, w, step=16):
+    """First crop (even corner, scanning rows then columns) whose ground truth is
+    one exact plane (inside one slanted segment, unclipped) and fully visible."""
+    H, W = p.disp.shape
+    yy, xx = np.mgrid[0:h, 0:w].astype(np.float64)
+    A = np.stack([np.ones(h * w), xx.ravel(), yy.ravel()], 1)
+    for y0 in range(32, H - h - 32, step):
+        for x0 in range(160, W - w - 32, step):
+            d = p.disp[y0:y0 + h, x0:x0 + w]
+            if not p.nonocc[y0:y0 + h, x0:x0 + w].all():
+                continue
+            coef, *_ = np.linalg.lstsq(A, d.ravel(), rcond=None)
+            if np.abs(A @ coef - d.ravel()).max() < 1e-9:
+                return y0, x0
+    raise AssertionError("no planar crop")
+
+
 def test_backward_against_finite_differences(M):
-    """GPU gradient vs FP64 central differences (eps 1e-6) of the oracle forward
-    on a small crop pair whose right view is shifted so true matches stay inside."""
+    """The gradient pin of the differentiable workload: on a 64 x 48 crop pair of
+    the 960x540 float pair 0, the GPU gradient of the masked mean-L1 loss against
+    FP64 central differences (step 1e-6) of the oracle forward at every one of
+    the 2 x 3072 inputs.  The left crop lies inside one planar segment; the right
+    crop is shifted by s (even, at least the soft radius below the smallest
+    doubled prior) so the true matches stay inside it; the prior is the
+    full-image run's level-1 map shifted by s / 2 (clipped per pixel by the
+    candidate-interval rule)."""
     p, cfg = synth.workload("diff960", 0)
-    y0, x0, h, w = 200, 400, 40, 48
-    s = int(np.floor(p.disp[y0:y0 + h, x0:x0 + w].min())) - 3
-    L = np.ascontiguousarray(p.left[y0:y0 + h, x0:x0 + w]).astype(np.float32)
-    R = np.ascontiguousarray(p.right[y0:y0 + h, x0 - s:x0 - s + w]).astype(np.float32)
-    n, D, K, r, rs, tau, eps = 3, 24, 2, 2, 3, 0.05, cfg.var_eps
-    out = M.disparity(dev(L), dev(R), D, K, n, r, eps, soft_radius=rs, tau=tau)
-    p1 = host(out["prior1"])
-    g = synth.grad_seed(3, h, w)
-    gL, gR = M.backward(dev(L), dev(R), out["prior1"], dev(g.astype(np.float32)), D, K, n, r, eps, rs, tau)
-    Ld, Rd, gd = L.astype(np.float64), R.astype(np.float64), g.astype(np.float32).astype(np.float64)
+    D, K, n, r, rs, tau, eps = cfg.max_disp, cfg.levels, cfg.half_window, cfg.refine_radius, \
+        cfg.soft_radius, cfg.tau, cfg.var_eps
+    full = M.disparity(dev(p.left), dev(p.right), D, K, n, r, eps, soft_radius=rs, tau=tau)
+    P1 = host(full["prior1"]).astype(np.int64)
+    h, w = 48, 64
+    y0, x0 = _planar_crop(p, h, w)
+    d1 = P1[y0 // 2:(y0 + h) // 2, x0 // 2:(x0 + w) // 2]
+    s = 2 * int(d1.min()) - rs - 1          # even: the doubled prior minus rs + 1
+    assert s % 2 == 0 and s > 0 and x0 - s >= 0
+    p1 = (d1 - s // 2).astype(np.int16)
+    Dc = int(2 * p1.max()) + rs + 1          # no candidate clipped by the range
+    L = np.ascontiguousarray(p.left[y0:y0 + h, x0:x0 + w])
+    R = np.ascontiguousarray(p.right[y0:y0 + h, x0 - s:x0 - s + w])
+    gt = p.disp[y0:y0 + h, x0:x0 + w] - s
+    mask = synth.loss_mask(np.ones((h, w), bool), n, Dc)
+    assert mask.sum() > h * w // 2
+    Ld, Rd = L.astype(np.float64), R.astype(np.float64)
+    ds_o, *_ = oracle.soft_level0(Ld, Rd, n, Dc, p1, rs, tau, eps)
+    loss, gd = oracle.l1_loss(ds_o, gt, mask)
+    assert np.abs(ds_o - gt)[mask].min() > 1e-5  # the sign pattern is locally constant
+    gL, gR = M.backward(dev(L), dev(R), dev(p1), dev(gd.astype(np.float32)), Dc, K, n, r, eps, rs, tau)
+    gd32 = gd.astype(np.float32).astype(np.float64)
 
     def f(Lx, Rx):
-        ds, *_ = oracle.soft_level0(Lx, Rx, n, D, p1, rs, tau, eps)
-        return float((gd * ds).sum())
+        ds, *_ = oracle.soft_level0(Lx, Rx, n, Dc, p1, rs, tau, eps)
+        return float((gd32 * ds).sum())
 
     hstep = 1e-6
-    rng = np.random.Generator(np.random.PCG64(4))
-    idx = [tuple(x) for x in np.stack([rng.integers(0, h, 300), rng.integers(0, w, 300)], 1)]
-    for grad, which in ((host(gL), 0), (host(gR), 1)):
-        fd = np.empty(len(idx))
-        for k, (i, j) in enumerate(idx):
+
+    def column(which, i):
+        out = np.empty(w)
+        for j in range(w):
             e = np.zeros_like(Ld)
             e[i, j] = hstep
             if which == 0:
-                fd[k] = (f(Ld + e, Rd) - f(Ld - e, Rd)) / (2 * hstep)
+                out[j] = (f(Ld + e, Rd) - f(Ld - e, Rd)) / (2 * hstep)
             else:
-                fd[k] = (f(Ld, Rd + e) - f(Ld, Rd - e)) / (2 * hstep)
-        got = np.array([grad[i, j] for i, j in idx], dtype=np.float64)
-        err = rel(got, fd)
-        print("view", which, "rel error vs finite differences", err)
+                out[j] = (f(Ld, Rd + e) - f(Ld, Rd - e)) / (2 * hstep)
+        return out
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(16, initializer=oracle.set_threads, initargs=(1,)) as ex:
+        fdL = np.stack(list(ex.map(lambda i: column(0, i), range(h))))
+        fdR = np.stack(list(ex.map(lambda i: column(1, i), range(h))))
+    oracle.set_threads(oracle.num_threads())
+    for grad, fd, which in ((host(gL), fdL, "left"), (host(gR), fdR, "right")):
+        err = rel(grad.astype(np.float64), fd)
+        print(f"crop at ({y0}, {x0}), shift {s}: {which} rel error vs finite differences {err:.2e} "
+              f"over {fd.size} inputs")
         assert err <= REL_TOL
+    # and the oracle's own gradient agrees with its finite differences
+    oL, oR = oracle.backward(Ld, Rd, n, Dc, p1, rs, tau, eps, gd32)
+    assert rel(oL, fdL) < 1e-6 and rel(oR, fdR) < 1e-6
 
 
 def test_autograd_loss_gradient(M):
@@ -125,12 +161,12 @@ def test_autograd_loss_gradient(M):
     Lt = dev(L).requires_grad_(True)
     Rt = dev(R).requires_grad_(True)
     dsoft, dhard = M.MsibmFunction.apply(Lt, Rt, D, K, n, r, eps, rs, tau)
-    mask = dev(_mask(vis, n))
+    mask = dev(synth.loss_mask(vis, n, D))
     loss = (dsoft - dev(gt.astype(np.float32))).abs()[mask].mean()
     loss.backward()
     p1 = M.disparity(dev(L), dev(R), D, K, n, r, eps, soft_radius=rs, tau=tau)["prior1"]
     ds_o, *_ = oracle.soft_level0(L, R, n, D, host(p1), rs, tau, eps)
-    lo, go = oracle.l1_loss(ds_o, gt, oracle.loss_mask(vis, n))
+    lo, go = oracle.l1_loss(ds_o, gt, synth.loss_mask(vis, n, D))
     assert abs(float(loss.detach()) - lo) < 1e-3 * max(1.0, lo)
     oL, oR = oracle.backward(L, R, n, D, host(p1), rs, tau, eps, go)
     eL, eR = rel(host(Lt.grad), oL), rel(host(Rt.grad), oR)
@@ -176,6 +212,13 @@ def test_batched_backward_matches_plain_and_oracle(M):
     assert eL <= REL_TOL and eR <= REL_TOL
 
 
+def _band_rows(i0, i1, n, H):
+    """Output rows whose gradient comes only from source rows [i0, i1): a source
+    row's windows span n rows either side, and clamped reads at the top and
+    bottom edges land on rows 0 and H - 1."""
+    return (0 if i0 == 0 else i0 + n), (H if i1 >= H else i1 - n)
+
+
 def test_hires2880_full_size_forward_backward(M):
     """The 4 x 2880x1988 forward + backward at full size, in the launch
     configuration the benchmark times (stage-batched, graph): pair 0's soft
@@ -212,6 +255,62 @@ def test_hires2880_full_size_forward_backward(M):
     err = float(np.abs(host(outs[0]["soft"]).astype(np.float64) - ds_o).max())
     print("hires2880 soft max |dd|", err)
     assert err <= 1e-2
+    # gradient rows against the oracle: a band of source rows [i0, i1) fixes the
+    # gradient exactly on the rows whose windows reach no other source row
+    for i, (i0, i1) in ((0, (980, 1040)), (3, (0, 44))):
+        li, ri, qi, gi = host(L[i]), host(R[i]), host(p1[i]), host(g[i]).astype(np.float64)
+        oL, oR = oracle.backward(li, ri, n, D, qi, rs, tau, eps, gi, rows=(i0, i1))
+        a, b = _band_rows(i0, i1, n, li.shape[0])
+        eL = rel(host(grads[i][0])[a:b].astype(np.float64), oL[a:b])
+        eR = rel(host(grads[i][1])[a:b].astype(np.float64), oR[a:b])
+        print(f"hires2880 pair {i} gradient rows {a}..{b - 1}: rel error left {eL:.2e} right {eR:.2e}")
+        assert eL <= REL_TOL and eR <= REL_TOL
+
+
+def test_diff960x8_full_size_forward_loss_backward(M):
+    """The 8 x 960x540 forward, masked mean-L1 loss gradient and backward at full
+    size, in the launch configuration the benchmark times (stage-batched,
+    graph): every pair's soft disparities against the oracle fed the GPU's
+    level-1 map, the loss gradient against the oracle's, and bands of gradient
+    rows of three pairs against the oracle's backward of the same upstream
+    gradient restricted to the band's source rows."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(8) as ex:
+        work = list(ex.map(lambda i: synth.workload("diff960", i), range(8)))
+    cfg = work[0][1]
+    n, r, eps, rs, tau, D, K = cfg.half_window, cfg.refine_radius, cfg.var_eps, cfg.soft_radius, cfg.tau, \
+        cfg.max_disp, cfg.levels
+    L = [dev(p.left) for p, _ in work]
+    R = [dev(p.right) for p, _ in work]
+    gts = [dev(p.disp.astype(np.float32)) for p, _ in work]
+    masks = [dev(synth.loss_mask(p.nonocc, n, D)) for p, _ in work]
+    Ds, Ks = [D] * 8, [K] * 8
+    flags = M.FLAG_BATCHED | M.FLAG_GRAPH
+    print("diff960 x 8 full size, batched graph", flush=True)
+    outs = M.disparity_many(L, R, Ds, Ks, n, r, eps, soft_radius=rs, tau=tau, flags=flags)
+    p1 = [o["prior1"] for o in outs]
+    g = [torch.sign(o["soft"] - t) * m / m.sum().clamp(min=1) for o, t, m in zip(outs, gts, masks)]
+    grads = M.backward_many(L, R, p1, g, Ds, Ks, n, r, eps, rs, tau, flags=flags)
+    for i, (p, _) in enumerate(work):
+        li, ri, qi = host(L[i]), host(R[i]), host(p1[i])
+        ds_o, *_ = oracle.soft_level0(li, ri, n, D, qi, rs, tau, eps)
+        ds = host(outs[i]["soft"]).astype(np.float64)
+        err = float(np.abs(ds - ds_o).max())
+        mask = synth.loss_mask(p.nonocc, n, D)
+        lo, go = oracle.l1_loss(ds_o, p.disp, mask)
+        firm = np.abs(ds_o - p.disp) > 1e-2  # the sign is fixed where d_soft is farther than its tolerance
+        gi = host(g[i]).astype(np.float64)
+        assert np.allclose(gi[firm], go[firm], rtol=1e-6, atol=0), i
+        print(f"diff960 pair {i}: soft max |dd| {err:.2e}, loss {lo:.4f}")
+        assert err <= 1e-2
+        if i in (0, 3, 7):
+            i0, i1 = (40, 100) if i != 7 else (470, 540)
+            oL, oR = oracle.backward(li, ri, n, D, qi, rs, tau, eps, gi, rows=(i0, i1))
+            a, b = _band_rows(i0, i1, n, li.shape[0])
+            eL = rel(host(grads[i][0])[a:b].astype(np.float64), oL[a:b])
+            eR = rel(host(grads[i][1])[a:b].astype(np.float64), oR[a:b])
+            print(f"  gradient rows {a}..{b - 1}: rel error left {eL:.2e} right {eR:.2e}")
+            assert eL <= REL_TOL and eR <= REL_TOL
 
 
 def test_backward_linearity_zero_and_locality(M):

@@ -380,12 +380,14 @@ def test_median_in_the_hierarchy(M, dtype, K, alpha):
         assert torch.equal(got["prior1"], out["prior1"])
 
 
-def test_mid1436_full_size_sampled(M):
-    """The benchmark workload at full size, in the launch configuration the
-    benchmark times; level 0 checked on sampled pixels against the oracle fed
-    the GPU's level-1 map."""
+@pytest.mark.parametrize("K", [4, 5])
+def test_mid1436_full_size_sampled(M, K):
+    """The 1436x992 workload at full size, in the launch configuration the
+    benchmark times, with 4 levels (32 candidates at the coarsest level) and 5
+    (16 at the coarsest); level 0 checked on sampled pixels against the oracle
+    fed the GPU's level-1 map."""
     p, cfg = synth.workload("mid1436")
-    K, n, r, D, eps = cfg.levels, cfg.half_window, cfg.refine_radius, cfg.max_disp, cfg.var_eps
+    n, r, D, eps = cfg.half_window, cfg.refine_radius, cfg.max_disp, cfg.var_eps
     out = M.disparity(dev(p.left), dev(p.right), D, K, n, r, eps, with_prior1=True)
     d, C, p1 = host(out["disp"]), host(out["cost"]), host(out["prior1"])
     rng = np.random.Generator(np.random.PCG64(99))
@@ -402,6 +404,34 @@ def test_mid1436_full_size_sampled(M):
     err = np.abs(d.astype(np.float64) - p.disp)
     print("mid1436 mean |d - gt| on visible pixels", err[vis].mean(), "bad>2px", (err[vis] > 2).mean())
     assert (err[vis] <= 2).mean() > 0.8
+
+
+def test_mid1436_flat_block_matching_full_size_sampled(M):
+    """Flat block matching (the full 256-candidate search at level 0) of the
+    1436x992 uint8 pair at full size, the comparison the benchmark times: the
+    default kernel shape on sampled pixels (borders and the left strip where
+    the candidate range is clipped included) against the oracle, and every
+    full-search shape (statistics in LDS, XCD order, candidate split) identical
+    to it."""
+    p, cfg = synth.workload("mid1436")
+    n, D, eps = cfg.half_window, cfg.max_disp, cfg.var_eps
+    Lg, Rg = dev(p.left), dev(p.right)
+    M.force_variant(-1)
+    d, C = M.match_level(Lg, Rg, n, D, None, 0, eps)
+    d, C = host(d), host(C)
+    H, W = d.shape
+    rng = np.random.Generator(np.random.PCG64(98))
+    ii = np.concatenate([rng.integers(0, H, 4000), np.zeros(40, int), np.full(40, H - 1), rng.integers(0, H, 300)])
+    jj = np.concatenate([rng.integers(0, W, 4000), rng.integers(0, W, 80), np.arange(300) % 260])
+    st = check_pixels(d, C, p.left, p.right, n, D, None, 0, eps, ii, jj)
+    print("mid1436 flat block matching sampled", st)
+    try:
+        for v in range(8):
+            M.force_variant(v)
+            dv, Cv = M.match_level(Lg, Rg, n, D, None, 0, eps)
+            assert np.array_equal(host(dv), d) and np.array_equal(host(Cv), C), v
+    finally:
+        M.force_variant(-1)
 
 
 def test_repeatable(M):

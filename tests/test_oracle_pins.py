@@ -649,3 +649,61 @@ def test_backward_levels_matches_central_differences():
                 Rm[i, j] -= h
             fd = (loss(Lp, Rp) - loss(Lm, Rm)) / (2 * h)
             assert abs(fd - G[i, j]) <= 1e-5 * max(1.0, abs(fd)), (which, i, j, fd, G[i, j])
+
+
+# ----------------------------- sampled-evaluation helpers the full-size tests use
+
+def test_zncc_many_equals_zncc_triple_by_triple():
+    """The list form scores each (i, j, z) exactly as the single-triple form,
+    on a non-square image, at border rows and columns, and for z > j (the right
+    window clamps at the left edge), in a shuffled order."""
+    rng = _rng(50)
+    H, W, n = 9, 17, 2
+    L = rng.random((H, W))
+    R = rng.random((H, W))
+    ii, jj, zz = [], [], []
+    for i in (0, 1, 4, H - 2, H - 1):
+        for j in (0, 1, 2, 8, W - 2, W - 1):
+            for z in (0, 1, 3, j, j + 2):
+                ii.append(i)
+                jj.append(j)
+                zz.append(z)
+    perm = rng.permutation(len(ii))
+    ii, jj, zz = (np.array(x)[perm] for x in (ii, jj, zz))
+    got = oracle.zncc_many(L, R, n, ii, jj, zz, 1e-9)
+    want = np.array([oracle.zncc(L, R, n, int(i), int(j), int(z), 1e-9) for i, j, z in zip(ii, jj, zz)])
+    np.testing.assert_array_equal(got, want)
+    # and the single form against an independent Pearson correlation at one
+    # interior triple, so a transposed pair of indices shows up
+    i, j, z = 4, 8, 3
+    wl = _window(L, i, j, n)
+    wr = _window(R, i, j - z, n)
+    assert abs(want[(ii == i) & (jj == j) & (zz == z)][0] - _pearson(wl, wr)) < 1e-12
+
+
+@pytest.mark.parametrize("restricted", [False, True])
+def test_match_pixels_equals_match_level_at_the_listed_pixels(restricted):
+    """The pixel-list form returns, pixel by pixel, the map's winner, its score
+    and the runner-up score, for a full and a restricted search, with the list
+    holding border columns (clipped candidate intervals) in a shuffled order."""
+    rng = _rng(51 + restricted)
+    H, W, n, Dk, r = 11, 19, 1, 9, 2
+    L = rng.random((H, W))
+    R = rng.random((H, W))
+    coarse = None
+    if restricted:
+        coarse = rng.integers(0, (Dk - 1) // 2 + 1, size=((H + 1) // 2, (W + 1) // 2)).astype(np.int16)
+    d, C, C2 = oracle.match_level(L, R, n, Dk, coarse, r, 1e-9)
+    ii, jj = np.nonzero(np.ones((H, W), dtype=bool))
+    perm = rng.permutation(ii.size)
+    ii, jj = ii[perm], jj[perm]
+    pd, pC, pC2 = oracle.match_pixels(L, R, n, Dk, coarse, r, 1e-9, ii, jj)
+    np.testing.assert_array_equal(pd, d[ii, jj])
+    np.testing.assert_array_equal(pC, C[ii, jj])
+    np.testing.assert_array_equal(pC2, C2[ii, jj])
+    # a short list (the sampled tests' use) gives the same values
+    sel = perm[:7]
+    qi, qj = np.nonzero(np.ones((H, W), dtype=bool))
+    qd, qC, _ = oracle.match_pixels(L, R, n, Dk, coarse, r, 1e-9, qi[sel], qj[sel])
+    np.testing.assert_array_equal(qd, d[qi[sel], qj[sel]])
+    np.testing.assert_array_equal(qC, C[qi[sel], qj[sel]])

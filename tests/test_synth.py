@@ -51,3 +51,19 @@ def test_texture_statistics():
     c1 = np.corrcoef(t[:, :-1].ravel(), t[:, 1:].ravel())[0, 1]
     c9 = np.corrcoef(t[:, :-9].ravel(), t[:, 9:].ravel())[0, 1]
     assert c1 > 0.7 and abs(c9) < 0.1
+
+
+def test_loss_mask_keeps_every_candidate_window_inside():
+    """Every loss pixel's own window and the right window of every candidate
+    z in [0, D-1] lie inside the image; visibility is respected."""
+    rng = np.random.Generator(np.random.PCG64(7))
+    H, W, n, D = 23, 41, 2, 9
+    vis = rng.random((H, W)) > 0.2
+    m = synth.loss_mask(vis, n, D)
+    ii, jj = np.nonzero(m)
+    assert m.any() and not (m & ~vis).any()
+    assert ii.min() >= n and ii.max() <= H - 1 - n
+    assert jj.max() <= W - 1 - n and (jj - (D - 1) - n).min() >= 0
+    # and it is the largest such set: the first admissible column is kept
+    j0 = n + D - 1
+    assert np.array_equal(m[n:H - n, j0], vis[n:H - n, j0])
