@@ -1,25 +1,30 @@
 #!/usr/bin/env python3
 """Throughput of the hierarchical ZNCC block-matching forward pass on one MI355X.
 
-A step is one hierarchical forward of the 1436x992 uint8 pair (4 levels, 9x9
-ZNCC windows, 256 candidates at full resolution, refine radius 2): pyramid of
-both views, window statistics, full search at the coarsest level, restricted
-search at the three finer levels.  Inputs, workspace and outputs are resident in
-device memory before the timed region starts.
+A step is one hierarchical forward of a batch of 32 uint8 stereo pairs of
+uneven sizes (W ~ U{640..2880}, H ~ U{480..1988}, D ~ U{64..400}; 9x9 ZNCC
+windows, refine radius 2, per pair the smallest level count whose coarsest
+level has at most 32 candidates): pyramid of both views, window statistics,
+full search at each pair's coarsest level, restricted search at every finer
+level, for all 32 pairs, replayed from one captured hipGraph of the
+stage-batched launches.  Inputs, workspace and outputs are resident in device
+memory before the timed region starts.
 
 Prints ONE JSON line.  `value` = pixel-disparity ZNCC evaluations per second
-(valid candidates actually scored, summed over levels) of the plain per-pair
-path.  Extra fields:
-  flat_full_search  the same pair by flat full-range block matching;
-  kernels           per-launch HIP-event timings of the timed step;
-  roofline          the dominant kernel (level-0 restricted search) against the
-                    FP32 vector peak, with HBM traffic from hardware counters;
-  batched           32 pairs of uneven sizes: 32 plain per-pair calls vs the
-                    stage-batched call vs its graph replay;
+(valid candidates actually scored, summed over levels and pairs).  Extra fields:
+  batch             the same batch as 32 plain per-pair calls, as stage-batched
+                    launches without the graph, and per-stage HIP-event times;
+  roofline          the dominant kernel (the batched level-0 restricted search)
+                    against the FP32 vector peak, with HBM traffic from
+                    hardware counters;
+  single_pair       the 1436x992 pair alone (plain per-pair path, K = 4 and
+                    K = 5) and by flat full-range block matching;
+  batch_variants    the batch with the selective median, the confidence
+                    gating and the paper's whole method, plain vs graph;
   fwd_bwd           forward + masked-L1 loss gradient + backward of 8 x 960x540
                     and 4 x 2880x1988 float pairs, plain vs batched graph;
-  cpu_baseline      the FP64 oracle timed on the host cores (a reported
-                    baseline, not a target).
+  cpu_baseline      the FP64 oracle timed on the host cores over pairs of the
+                    same batch (a reported baseline, not a target).
 `python bench.py --copy-probe BYTES` only runs a plain device copy (used to
 scale hardware traffic counters) and prints nothing.
 """
@@ -45,8 +50,8 @@ MEDIAN_ALPHA = 0.9  # the threshold of the selective median filter that Section 
 GATE_ALPHA = GATE_BETA = 0.9  # the gating thresholds Section IV reports
 
 METRIC = "pixel-disparity ZNCC evals/s + ms/pair, batched vs plain; fwd+bwd ms"
-DOMINANT = "match_refine_l0"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "match_refine_l0_mid1436_traffic.md")
+DOMINANT = "batch_match_refine_l0"   # timing label of the batched level-0 restricted search
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "match_multi_refine_l0_batch32_traffic.md")
 # sources of the dominant kernel: a recorded traffic figure holds only while
 # these files are unchanged
 KERNEL_SOURCES = ["paper_1901_09593_amd/csrc/match_impl.hpp", "paper_1901_09593_amd/csrc/common.hpp",
@@ -66,6 +71,14 @@ def kernel_flops_per_eval(n: int) -> float:
     block's four windows, plus 6 adds to split them and 5 flops per evaluation to
     normalise and compare."""
     return (2.0 * (2 * n + 2) ** 2 + 6.0) / 4.0 + 5.0
+
+
+def algorithmic_bytes_per_px_u8() -> float:
+    """HBM bytes a restricted search of a uint8 level must move per pixel: both
+    views read once (2), the coarser int16 prior (2 bytes per 4 pixels), the
+    int16 disparity and the float score written (6).  Window statistics are
+    this build's intermediate, not part of the algorithm's bytes."""
+    return 2.0 + 0.5 + 6.0
 
 
 def kernel_sha() -> str:
@@ -123,22 +136,17 @@ def hier_counts(torch, M, L, R, D, K, n, r, eps):
     return level_counts(torch, maps, D, K, r)
 
 
-def tune_summary(table, H, W, K):
-    """Kernel shapes the autotuner chose for the headline pair's levels, and how
-    often each shape won over every measured level shape."""
-    dims = set()
-    h, w = H, W
-    for _ in range(K):
-        dims.add((h, w))
-        h, w = (h + 1) // 2, (w + 1) // 2
+def tune_summary(table):
+    """Kernel shapes the autotuner measured and how often each shape won."""
     mode = ["full", "refine", "soft"]
-    head = [{"mode": mode[t[0]], "dtype": ["u8", "f32"][t[3]], "H": t[4], "W": t[5], "Dk": t[6],
-             "variant": t[7], "us": round(t[8], 2)} for t in table if (t[4], t[5]) in dims and t[1] == 4]
     wins = {}
     for t in table:
         wins[str(t[7])] = wins.get(str(t[7]), 0) + 1
-    return {"variant_bits": "1 = statistics in LDS (full search), 2 = XCD-aware tile order, 4 = candidates split over waves (full search), 8 = fixed candidate window (restricted search)",
-            "headline_levels": head, "wins_over_all_shapes": wins, "shapes_measured": len(table)}
+    return {"variant_bits": "1 = statistics in LDS (full search), 2 = XCD-aware tile order, 4 = candidates split over "
+                            "waves, 8 = fixed candidate window (restricted search)",
+            "wins_over_all_shapes": wins, "shapes_measured": len(table),
+            "level0_shapes": [{"mode": mode[t[0]], "dtype": ["u8", "f32"][t[3]], "H": t[4], "W": t[5], "Dk": t[6],
+                               "variant": t[7], "us": round(t[8], 2)} for t in table if t[1] == 4 and t[0] == 1][:8]}
 
 
 def time_ms(torch, fn, steps, warmup):
@@ -157,8 +165,9 @@ def time_ms(torch, fn, steps, warmup):
 
 # --------------------------------------------------------------------------- sections
 
-def section_batched(torch, M, synth, steps):
-    """32 uneven uint8 pairs: plain per-pair calls vs one stage-batched call."""
+def batch_setup(torch, M, synth):
+    """The 32-pair uneven batch on the device, with the valid candidates scored
+    per pair and level (from every level's winner map)."""
     dev = torch.device("cuda:0")
     work = synth.batch_workload(32, 1000, workers=8)
     L = [torch.from_numpy(p.left).to(dev) for p, _ in work]
@@ -166,35 +175,27 @@ def section_batched(torch, M, synth, steps):
     D = [c.max_disp for _, c in work]
     K = [c.levels for _, c in work]
     n, r, eps = work[0][1].half_window, work[0][1].refine_radius, work[0][1].var_eps
-    evals = sum(sum(hier_counts(torch, M, L[i], R[i], D[i], K[i], n, r, eps)) for i in range(len(L)))
-    level0_px = sum(p.left.size for p, _ in work)
-    res = {"workload": "32 uint8 pairs, W ~ U{640..2880}, H ~ U{480..1988}, D ~ U{64..400} (shape seed "
-                       "1000, pair i seed i), 8 slanted planes, noise 2; 9x9 ZNCC, refine +-2, K per pair "
-                       "(smallest with D_(K-1) <= 32)",
-           "pairs": len(L), "level0_pixels": level0_px, "evals_per_batch": evals,
-           "levels": sorted(set(K))}
-    pairs_arr = M._pairs(L, R, D, K)[0]
-    for name, flags in (("plain", 0), ("batched", M.FLAG_BATCHED),
-                        ("graph", M.FLAG_BATCHED | M.FLAG_GRAPH)):
-        ws = torch.empty(M.workspace_bytes(pairs_arr, len(L), M.make_config(n, r, eps, flags=flags)),
-                         dtype=torch.uint8, device=dev)
-        outs = M.disparity_many(L, R, D, K, n, r, eps, flags=flags, workspace=ws)
+    counts = [hier_counts(torch, M, L[i], R[i], D[i], K[i], n, r, eps) for i in range(len(L))]
+    return {"work": work, "L": L, "R": R, "D": D, "K": K, "n": n, "r": r, "eps": eps, "counts": counts,
+            "evals": sum(sum(c) for c in counts), "evals_l0": sum(c[0] for c in counts),
+            "level0_px": sum(p.left.size for p, _ in work)}
 
-        def step():
-            M.disparity_many(L, R, D, K, n, r, eps, flags=flags, workspace=ws, outputs=outs)
-        ms = time_ms(torch, step, steps, 3)
-        res[name] = {"ms_per_batch": ms, "ms_per_pair": ms / len(L), "evals_per_s": evals / (ms * 1e-3)}
-        if name == "plain":
-            ref = outs
-        else:
-            res[name]["identical_to_plain"] = all(torch.equal(a[k], b[k]) for a, b in zip(ref, outs) for k in a)
-        del ws
-    res["graph_speedup_vs_plain"] = res["plain"]["ms_per_batch"] / res["graph"]["ms_per_batch"]
-    res["batched_speedup_vs_plain"] = res["plain"]["ms_per_batch"] / res["batched"]["ms_per_batch"]
-    # the same batch with the selective median (Eq. 10), with the confidence
-    # gating (Eqs. 5-9), and with the paper's whole method (pre-blur, gating,
-    # median, windows halved from 11 x 11 level by level, refine +-1)
+
+BATCH_WORKLOAD = ("32 uint8 pairs, W ~ U{640..2880}, H ~ U{480..1988}, D ~ U{64..400} (shape seed 1000, "
+                  "pair i seed i), 8 slanted planes d in [0.05 D, 0.9 D], noise 2; 9x9 ZNCC, refine +-2, K per "
+                  "pair (smallest with D_(K-1) <= 32); batched stages replayed from one hipGraph")
+
+
+def section_batch_variants(torch, M, B, steps):
+    """The batch with the selective median (Eq. 10), with the confidence gating
+    (Eqs. 5-9), and with the paper's whole method (pre-blur, gating, median,
+    windows halved from 11 x 11 level by level, refine +-1): plain per-pair
+    calls against the batched graph."""
+    dev = torch.device("cuda:0")
+    L, R, D, K, n, r, eps = B["L"], B["R"], B["D"], B["K"], B["n"], B["r"], B["eps"]
+    pairs_arr = M._pairs(L, R, D, K)[0]
     gate = {"gate": (GATE_ALPHA, GATE_BETA)}
+    res = {}
     for key, opts, vflags, vn, vr in (
             ("with_median", {"median_alpha": MEDIAN_ALPHA}, 0, n, r),
             ("with_gating", gate, 0, n, r),
@@ -218,6 +219,51 @@ def section_batched(torch, M, synth, steps):
         res[key] = var
     return res
 
+
+def section_single(torch, M, synth, steps):
+    """The 1436x992 pair alone on the plain per-pair path (K = 4, and K = 5:
+    16 candidates at the coarsest level), per-launch HIP-event times, and flat
+    full-range block matching of the same pair."""
+    dev = torch.device("cuda:0")
+    p, cfg = synth.workload("mid1436")
+    H, W, D, n, r, eps = cfg.height, cfg.width, cfg.max_disp, cfg.half_window, cfg.refine_radius, cfg.var_eps
+    Lg = torch.from_numpy(p.left).to(dev)
+    Rg = torch.from_numpy(p.right).to(dev)
+    res = {"workload": "1436x992 uint8 stereo pair, 8 slanted planes d 10..250, gain 0.9, offset +8, noise 4; "
+                       "9x9 ZNCC, D=256, refine +-2, plain per-pair forward"}
+    for K in (cfg.levels, cfg.levels + 1):
+        counts = hier_counts(torch, M, Lg, Rg, D, K, n, r, eps)
+        ws = torch.empty(M.workspace_bytes(M._pairs([Lg], [Rg], [D], [K])[0], 1, M.make_config(n, r, eps)),
+                         dtype=torch.uint8, device=dev)
+        outs = M.disparity_many([Lg], [Rg], [D], [K], n, r, eps, with_cost=True, workspace=ws)
+
+        def step():
+            M.disparity_many([Lg], [Rg], [D], [K], n, r, eps, with_cost=True, workspace=ws, outputs=outs)
+        ms = time_ms(torch, step, steps, 5)
+        M.timing_enable(True)
+        for _ in range(steps):
+            step()
+        torch.cuda.synchronize()
+        tim = M.timing_read()
+        M.timing_enable(False)
+        res[f"K{K}"] = {"ms_per_pair": ms, "evals_per_pair": sum(counts), "evals_per_level": counts,
+                        "evals_per_s": sum(counts) / (ms * 1e-3),
+                        "kernels_us": {k: round(1e3 * v[0] / v[1], 2) for k, v in sorted(tim.items())}}
+        del ws
+    # flat full search at full resolution (standard block matching) for comparison
+    flat_evals = int(sum(min(D, j + 1) for j in range(W)) * H)
+    dflat = torch.empty((H, W), dtype=torch.int16, device=dev)
+    wsl = torch.empty(M.lib().msibm_level_workspace_size(H, W), dtype=torch.uint8, device=dev)
+
+    def flat():
+        M._check(M.lib().msibm_match_level(
+            M._ptr(Lg), M._ptr(Rg), 0, H, W, W, n, D, None, 0, 0, 0, 0, float(eps),
+            M._ptr(dflat), None, W, None, M._ptr(wsl), wsl.numel(), M._stream(dev)))
+    flat_ms = time_ms(torch, flat, max(3, steps // 4), 3)
+    res["flat_full_search"] = {"ms_per_pair": flat_ms, "evals_per_pair": flat_evals,
+                               "evals_per_s": flat_evals / (flat_ms * 1e-3),
+                               "hierarchical_speedup": flat_ms / res[f"K{cfg.levels}"]["ms_per_pair"]}
+    return res
 
 def section_accuracy(torch, M, synth, steps):
     """Disparity error against the generator's ground truth (the synthetic
@@ -377,14 +423,8 @@ def section_fwd_bwd(torch, M, synth, name, count, steps):
     L = [torch.from_numpy(p.left).to(dev) for p, _ in work]
     R = [torch.from_numpy(p.right).to(dev) for p, _ in work]
     gt = [torch.from_numpy(p.disp.astype(np.float32)).to(dev) for p, _ in work]
-    # loss pixels: non-occluded, window inside the image, every candidate's right
-    # window inside too (left column >= n + D-1 is a sufficient, fixed test)
-    mask = []
-    for p, _ in work:
-        m = p.nonocc.copy()
-        m[:n, :] = m[H - n:, :] = False
-        m[:, :n + D - 1] = m[:, W - n:] = False
-        mask.append(torch.from_numpy(m).to(dev))
+    # loss pixels: the one mask definition the tests and the oracle use too
+    mask = [torch.from_numpy(synth.loss_mask(p.nonocc, n, D)).to(dev) for p, _ in work]
     cnt = [mm.sum().clamp(min=1).float() for mm in mask]
     Ds, Ks = [D] * count, [K] * count
     pairs_arr = M._pairs(L, R, Ds, Ks)[0]
@@ -442,16 +482,16 @@ def section_fwd_bwd(torch, M, synth, name, count, steps):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="wall time budget of the oracle baseline sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune-cache", default=None,
                     help="kernel-shape table to read and extend (profiling runs reuse a plain run's choices)")
-    ap.add_argument("--sections", default="batched,fwd_bwd,accuracy,gated,levels",
-                    help="extra sections beside the headline step: batched, fwd_bwd, accuracy, gated, levels, "
-                         "or none")
+    ap.add_argument("--sections", default="single,variants,fwd_bwd,accuracy,gated,levels",
+                    help="extra sections beside the headline step: single, variants, fwd_bwd, accuracy, gated, "
+                         "levels, or none")
     ap.add_argument("--no-tune", action="store_true",
                     help="use the default kernel shapes instead of measuring them first")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -482,22 +522,26 @@ def main():
         # first use of each level shape measures its kernel shapes (or takes
         # them from the cache file, which profiling runs share with a plain one)
         msibm.autotune(True, args.tune_cache)
-    p, cfg = synth.workload("mid1436")
-    H, W, D, K, n, r, eps = cfg.height, cfg.width, cfg.max_disp, cfg.levels, cfg.half_window, \
-        cfg.refine_radius, cfg.var_eps
-    Lg = torch.from_numpy(p.left).to(dev)
-    Rg = torch.from_numpy(p.right).to(dev)
-    counts = hier_counts(torch, msibm, Lg, Rg, D, K, n, r, eps)
-    evals = sum(counts)
+    B = batch_setup(torch, msibm, synth)
+    L, R, D, K, n, r, eps = B["L"], B["R"], B["D"], B["K"], B["n"], B["r"], B["eps"]
+    npairs, evals = len(L), B["evals"]
+    pairs_arr = msibm._pairs(L, R, D, K)[0]
 
-    # resident buffers, then the timed loop
-    pairs_ws = msibm.workspace_bytes(msibm._pairs([Lg], [Rg], [D], [K])[0], 1, msibm.make_config(n, r, eps))
-    ws = torch.empty(pairs_ws, dtype=torch.uint8, device=dev)
-    outs = msibm.disparity_many([Lg], [Rg], [D], [K], n, r, eps, with_cost=True, workspace=ws)
+    # resident buffers for the three forms of the same batch
+    runs = {}
+    for name, flags in (("graph", msibm.FLAG_BATCHED | msibm.FLAG_GRAPH), ("batched", msibm.FLAG_BATCHED),
+                        ("plain", 0)):
+        ws = torch.empty(msibm.workspace_bytes(pairs_arr, npairs, msibm.make_config(n, r, eps, flags=flags)),
+                         dtype=torch.uint8, device=dev)
+        outs = msibm.disparity_many(L, R, D, K, n, r, eps, flags=flags, workspace=ws)
+        runs[name] = (flags, ws, outs)
 
-    def step():
-        msibm.disparity_many([Lg], [Rg], [D], [K], n, r, eps, with_cost=True, workspace=ws, outputs=outs)
+    def step_of(name):
+        flags, ws, outs = runs[name]
+        return lambda: msibm.disparity_many(L, R, D, K, n, r, eps, flags=flags, workspace=ws, outputs=outs)
 
+    # the timed region: K steps of the graph-replayed batch
+    step = step_of("graph")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -512,61 +556,77 @@ def main():
     ms_step = e0.elapsed_time(e1) / args.steps
     value = evals / (ms_step * 1e-3)
 
-    # per-kernel HIP-event timings: the same steps again with every launch
-    # bracketed by events on the stream it is launched on
+    nsteps = max(3, min(args.steps, 20))
+    plain_ms = time_ms(torch, step_of("plain"), nsteps, 3)
+    batched_ms = time_ms(torch, step_of("batched"), nsteps, 3)
+    ref = runs["plain"][2]
+    identical = {nm: all(torch.equal(a[k], b[k]) for a, b in zip(ref, runs[nm][2]) for k in a)
+                 for nm in ("graph", "batched")}
+
+    # per-stage HIP-event timings: the stage-batched launches (the kernels the
+    # graph replays), each bracketed by events on the stream it is launched on
     msibm.timing_enable(True)
+    bstep = step_of("batched")
     for _ in range(args.steps):
-        step()
+        bstep()
     torch.cuda.synchronize()
     tim = msibm.timing_read()
     msibm.timing_enable(False)
-    kernels = {k: {"avg_us": 1e3 * v[0] / v[1], "launches": v[1]} for k, v in sorted(tim.items())}
+    stages = {k: {"avg_us": round(1e3 * v[0] / v[1], 2), "launches": v[1]} for k, v in sorted(tim.items())}
 
-    dom_us = kernels[DOMINANT]["avg_us"]
-    ach = direct_flops_per_eval(n) * counts[0] / (dom_us * 1e-6) / 1e12
-    issued = kernel_flops_per_eval(n) * counts[0] / (dom_us * 1e-6) / 1e12
+    dom_us = stages[DOMINANT]["avg_us"]
+    ev0 = B["evals_l0"]
+    ach = direct_flops_per_eval(n) * ev0 / (dom_us * 1e-6) / 1e12
+    issued = kernel_flops_per_eval(n) * ev0 / (dom_us * 1e-6) / 1e12
     traffic = recorded_traffic()
+    alg_bytes = algorithmic_bytes_per_px_u8() * B["level0_px"]
     roof = {
-        "kernel": DOMINANT,
+        "kernel": DOMINANT + " (match_multi_kernel<u8, n=4, 5 slots, refine>)",
         "bound": "alu",
         "achieved": round(ach, 2),
-        "peak": round(PEAK_FP32_UNPACKED, 1),
+        "peak": PEAK_FP32_PUBLISHED,
         "unit": "TFLOP/s",
-        "frac": round(ach / PEAK_FP32_UNPACKED, 4),
+        "frac": round(ach / PEAK_FP32_PUBLISHED, 4),
         "traffic": traffic,
         "flops_per_eval": direct_flops_per_eval(n),
-        "evals_per_launch": counts[0],
-        "avg_launch_us": round(dom_us, 2),
-        "frac_of_published_fp32_157_3": round(ach / PEAK_FP32_PUBLISHED, 4),
+        "evals_per_launch": ev0,
+        "avg_launch_us": dom_us,
+        "frac_of_unpacked_78_6": round(ach / PEAK_FP32_UNPACKED, 4),
         "issued_flops_per_eval": kernel_flops_per_eval(n),
         "issued_tflops": round(issued, 2),
-        "issued_frac": round(issued / PEAK_FP32_UNPACKED, 4),
+        "issued_frac": round(issued / PEAK_FP32_PUBLISHED, 4),
+        "issued_frac_of_unpacked": round(issued / PEAK_FP32_UNPACKED, 4),
+        "algorithmic_bytes_per_launch": alg_bytes,
+        "traffic_over_algorithmic": None if traffic is None else round(traffic / alg_bytes, 3),
         "hbm_gbps_from_traffic": None if traffic is None else round(traffic / (dom_us * 1e-6) / 1e9, 1),
     }
-
-    # flat full search at full resolution (standard block matching) for comparison
-    flat_evals = int(sum(min(D, j + 1) for j in range(W)) * H)
-    dflat = torch.empty((H, W), dtype=torch.int16, device=dev)
-    wsl = torch.empty(msibm.lib().msibm_level_workspace_size(H, W), dtype=torch.uint8, device=dev)
-
-    def flat():
-        msibm._check(msibm.lib().msibm_match_level(
-            msibm._ptr(Lg), msibm._ptr(Rg), 0, H, W, W, n, D, None, 0, 0, 0, 0, float(eps),
-            msibm._ptr(dflat), None, W, None, msibm._ptr(wsl), wsl.numel(), msibm._stream(dev)))
-    flat_ms = time_ms(torch, flat, max(3, args.steps // 20), 3)
-    del wsl, dflat
+    batch = {
+        "pairs": npairs, "level0_pixels": B["level0_px"], "evals_per_batch": evals, "evals_level0": ev0,
+        "levels": sorted(set(K)),
+        "graph": {"ms_per_batch": ms_step, "ms_per_pair": ms_step / npairs, "evals_per_s": value,
+                  "identical_to_plain": identical["graph"]},
+        "batched": {"ms_per_batch": batched_ms, "ms_per_pair": batched_ms / npairs,
+                    "evals_per_s": evals / (batched_ms * 1e-3), "identical_to_plain": identical["batched"]},
+        "plain": {"ms_per_batch": plain_ms, "ms_per_pair": plain_ms / npairs,
+                  "evals_per_s": evals / (plain_ms * 1e-3)},
+        "graph_speedup_vs_plain": plain_ms / ms_step,
+        "stages_us": stages,
+    }
+    for nm in ("batched", "plain"):
+        del runs[nm]
+    torch.cuda.empty_cache()
 
     extra = {}
-    nsteps = max(3, min(args.steps, 20))
-    if "batched" in sections:
-        extra["batched"] = section_batched(torch, msibm, synth, nsteps)
-        torch.cuda.empty_cache()
+    if "single" in sections:
+        extra["single_pair"] = section_single(torch, msibm, synth, nsteps)
+    if "variants" in sections:
+        extra["batch_variants"] = section_batch_variants(torch, msibm, B, nsteps)
+    torch.cuda.empty_cache()
     if "fwd_bwd" in sections:
         extra["fwd_bwd"] = {
             "diff960x8": section_fwd_bwd(torch, msibm, synth, "diff960", 8, nsteps),
             "hires2880x4": section_fwd_bwd(torch, msibm, synth, "hires2880", 4, max(3, nsteps // 2)),
         }
-
     if "accuracy" in sections:
         extra["accuracy"] = section_accuracy(torch, msibm, synth, nsteps)
     if "gated" in sections:
@@ -574,18 +634,20 @@ def main():
     if "levels" in sections:
         extra["levels"] = section_levels(torch, msibm, synth, nsteps)
 
-    # the FP64 oracle on the host cores: whole pairs until the time budget is used
+    # the FP64 oracle on the host cores: the batch's pairs in order until the
+    # time budget is used (the whole batch if it fits)
     cpu = None
     if not args.no_cpu:
         import oracle
-        reps, t0 = 0, time.perf_counter()
-        while True:
-            oracle.disparity(p.left, p.right, D, K, n, r, eps)
-            reps += 1
+        done, done_evals, t0 = 0, 0, time.perf_counter()
+        for (p, c), cnt in zip(B["work"], B["counts"]):
+            oracle.disparity(p.left, p.right, c.max_disp, c.levels, c.half_window, c.refine_radius, c.var_eps)
+            done += 1
+            done_evals += sum(cnt)
             el = time.perf_counter() - t0
             if el >= args.cpu_seconds:
                 break
-        # one core, on the small pair (the paper's CPU setting is one process)
+        # one core, on the 320x240 pair (the paper's CPU setting is one process)
         ps, cs = synth.workload("small320")
         oracle.set_threads(1)
         reps1, t1 = 0, time.perf_counter()
@@ -603,9 +665,10 @@ def main():
                 model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
         except OSError:
             pass
-        cpu = {"value": evals * reps / el, "unit": "evals/s", "cores": oracle.num_threads(),
-               "kind": "oracle", "ms_per_pair": 1e3 * el / reps,
-               "sample": f"{reps} full hierarchical forwards of the 1436x992 pair ({el:.1f} s)",
+        cpu = {"value": done_evals / el, "unit": "evals/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "ms_per_pair": 1e3 * el / done,
+               "sample": f"pairs 0..{done - 1} of the 32-pair batch, one full hierarchical forward each "
+                         f"({done_evals} evaluations, {el:.1f} s)",
                "cpu_model": model,
                "one_core_small320_ms_per_pair": 1e3 * el1 / reps1,
                "one_core_sample": f"{reps1} forwards of the 320x240 pair on one thread ({el1:.1f} s)"}
@@ -623,17 +686,11 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "1436x992 uint8 stereo pair, 8 slanted planes d 10..250, gain 0.9, "
-                               "offset +8, noise 4; K=4 levels, 9x9 ZNCC, D=256, refine +-2, "
-                               "plain per-pair forward",
-                   "evals_per_pair": evals, "evals_per_level": counts},
-        "ms_per_pair": ms_step,
+        "config": {"workload": BATCH_WORKLOAD, "pairs": npairs, "evals_per_batch": evals},
+        "ms_per_pair": ms_step / npairs,
         "host_wall_ms_per_step": 1e3 * wall / args.steps,
-        "flat_full_search": {"ms_per_pair": flat_ms, "evals_per_pair": flat_evals,
-                             "evals_per_s": flat_evals / (flat_ms * 1e-3),
-                             "hierarchical_speedup": flat_ms / ms_step},
-        "kernels": kernels,
-        "autotune": tune_summary(msibm.autotune_table(), H, W, K),
+        "batch": batch,
+        "autotune": tune_summary(msibm.autotune_table()),
         "roofline": roof,
         **extra,
         "cpu_baseline": cpu,
