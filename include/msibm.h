@@ -371,6 +371,38 @@ msibm_status msibm_disparity(const msibm_pair* pairs, int32_t n_pairs, const msi
                              int16_t* const* prior1, void* workspace, size_t ws_bytes,
                              void* stream);
 
+/* Bytes of device scratch msibm_disparity_noalloc holds on each device: enough
+ * for a 1920 x 1080 pair with any of PREBLUR, MEDIAN and GATED. */
+#define MSIBM_NOALLOC_SCRATCH_BYTES (96u << 20)
+
+/*
+ * msibm_disparity_noalloc - msibm_disparity for ONE pair on the plain per-pair
+ * path, with no workspace argument and no allocation of any kind.  For callers
+ * that cannot allocate: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.
+ *   pair, cfg   as for msibm_disparity with n_pairs = 1; cfg->flags may hold
+ *               PREBLUR, MEDIAN and GATED, not BATCHED or GRAPH.
+ *   disp, cost, soft_disp, prior1   as msibm_disparity's entries of the pair
+ *               (cost and prior1 may be NULL; soft_disp is required iff
+ *               soft_radius > 0).  The caller owns them.
+ * Scratch: a device array of MSIBM_NOALLOC_SCRATCH_BYTES inside the library,
+ * one per device, held from the device's first call until the process ends;
+ * the first call on a device looks up its address with that device current.
+ * No call calls hipMalloc, hipFree, an allocating library routine or creates
+ * an event: the autotuner only reads kernel shapes it measured before (it
+ * never measures here) and per-launch timing records nothing.  Every call on a
+ * device uses that device's one array, which keeps the last call's contents
+ * (the forward writes every scratch byte it reads, so nothing is cleared):
+ * calls that overlap in time on one device (several streams or host threads)
+ * race and must be serialised by the caller.
+ * Errors: INVALID_ARG, SHAPE, UNSUPPORTED (as msibm_disparity; BATCHED or
+ *         GRAPH), WORKSPACE (the pair needs more scratch than
+ *         MSIBM_NOALLOC_SCRATCH_BYTES: msibm_workspace_size gives its need),
+ *         HIP.
+ */
+msibm_status msibm_disparity_noalloc(const msibm_pair* pair, const msibm_config* cfg, int16_t* disp, float* cost,
+                                     float* soft_disp, int16_t* prior1, void* stream);
+
 /*
  * msibm_backward - gradient of sum_{ij} g(i,j) d_soft(i,j) with respect to the
  * level-0 left and right images, with the level-1 prior held fixed (it is

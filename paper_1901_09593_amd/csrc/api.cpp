@@ -5,6 +5,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -173,6 +174,43 @@ PairLayout pair_layout(const msibm_pair& p, int K, bool preblur, bool median, bo
 }
 
 }  // namespace msibm
+
+// ------------------------------------------- scratch of the allocation-free entry point
+// One copy of this array exists on every device the library runs on, for the
+// life of the process.  Host code never passes the array's name to a kernel
+// or a copy (on the host it only stands for the symbol): it looks up the
+// device address once per device and uses that.
+static __device__ __align__(256) unsigned char scratch[MSIBM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxScratchDevices];  // device address of `scratch`, per device
+
+// Address of the current device's scratch array, looked up on the first call
+// on that device (with that device current).
+msibm_status scratch_address(void** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxScratchDevices)
+        return fail(MSIBM_ERR_UNSUPPORTED, "device %d: the allocation-free entry point serves devices 0..%d", dev,
+                    kMaxScratchDevices - 1);
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!ptr) return fail(MSIBM_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return MSIBM_OK;
+}
+
+}  // namespace
 
 // ------------------------------------------------------------------ C ABI
 
@@ -477,6 +515,39 @@ msibm_status msibm_disparity(const msibm_pair* pairs, int32_t n_pairs, const msi
                                       &err);
         if (rc != MSIBM_OK) return fail(rc, "pair %d: %s", p, err.c_str());
     }
+    return ok();
+}
+
+msibm_status msibm_disparity_noalloc(const msibm_pair* pair, const msibm_config* cfg, int16_t* disp, float* cost,
+                                     float* soft_disp, int16_t* prior1, void* stream)
+{
+    if (!pair || !disp) return fail(MSIBM_ERR_INVALID_ARG, "pair or disp is NULL");
+    msibm_status st = validate_config(cfg);
+    if (st != MSIBM_OK) return st;
+    if (cfg->flags & (MSIBM_FLAG_BATCHED | MSIBM_FLAG_GRAPH))
+        return fail(MSIBM_ERR_UNSUPPORTED, "the allocation-free entry point runs the plain path (no BATCHED, GRAPH)");
+    int K;
+    st = validate_pair(*pair, 0, cfg, &K);
+    if (st != MSIBM_OK) return st;
+    if (cfg->soft_radius > 0 && !soft_disp)
+        return fail(MSIBM_ERR_INVALID_ARG, "soft_disp is NULL but soft_radius > 0");
+    const PairLayout lay = pair_layout(*pair, K, (cfg->flags & MSIBM_FLAG_PREBLUR) != 0,
+                                       (cfg->flags & MSIBM_FLAG_MEDIAN) != 0, (cfg->flags & MSIBM_FLAG_GATED) != 0);
+    if (lay.bytes > (size_t)MSIBM_NOALLOC_SCRATCH_BYTES)
+        return fail(MSIBM_ERR_WORKSPACE,
+                    "the pair needs %zu bytes of scratch, more than the %zu bytes the allocation-free entry "
+                    "point holds (use msibm_disparity with a workspace)",
+                    lay.bytes, (size_t)MSIBM_NOALLOC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    st = scratch_address(&ws);
+    if (st != MSIBM_OK) return st;
+    // nothing in the plain forward reads scratch it has not written in the
+    // same call, so nothing needs clearing first
+    NoAllocScope no_alloc;
+    std::string err;
+    const int rc = run_pair_plain(*pair, lay, cfg, (char*)ws, disp, cost, soft_disp, prior1, (hipStream_t)stream,
+                                  &err);
+    if (rc != MSIBM_OK) return fail(rc, "%s", err.c_str());
     return ok();
 }
 

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "msibm.h"
+#include "tune.hpp"
 
 namespace msibm {
 
@@ -51,7 +52,7 @@ bool timing_on() { return state().on; }
 int timing_begin(const char* label, hipStream_t s)
 {
     State& st = state();
-    if (!st.on) return -1;
+    if (!st.on || in_no_alloc_scope()) return -1;
     std::lock_guard<std::mutex> g(st.mu);
     Pending p{label, take(st), take(st)};
     if (!p.start || !p.stop) return -1;

@@ -161,6 +161,14 @@ std::string autotune_table()
     return table_text(t);
 }
 
+namespace {
+thread_local int t_no_alloc_depth = 0;
+}
+
+NoAllocScope::NoAllocScope() { ++t_no_alloc_depth; }
+NoAllocScope::~NoAllocScope() { --t_no_alloc_depth; }
+bool in_no_alloc_scope() { return t_no_alloc_depth > 0; }
+
 int select_variant(const MatchArgs& a, int n, int dtype, int mode, int nc, hipStream_t s)
 {
     Tuner& t = tuner();
@@ -176,7 +184,7 @@ int select_variant(const MatchArgs& a, int n, int dtype, int mode, int nc, hipSt
     const Key key(mode, n, nc, dtype, a.H, a.W, a.Dk);
     auto it = t.table.find(key);
     if (it != t.table.end()) return it->second.variant & valid;
-    if (!t.on) return default_variant(a, mode) & valid;
+    if (!t.on || in_no_alloc_scope()) return default_variant(a, mode) & valid;
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone)
         return default_variant(a, mode) & valid;

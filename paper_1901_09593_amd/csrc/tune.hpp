@@ -18,6 +18,17 @@ namespace msibm {
 int select_variant(const MatchArgs& a, int n, int dtype, int mode, int nc, hipStream_t s);
 
 void force_variant(int v);
+
+// While one is alive on a thread, the calls that thread makes allocate
+// nothing: select_variant only reads shapes already in the table (measuring
+// creates events and synchronises) and per-launch timing records nothing.
+struct NoAllocScope {
+    NoAllocScope();
+    ~NoAllocScope();
+    NoAllocScope(const NoAllocScope&) = delete;
+    NoAllocScope& operator=(const NoAllocScope&) = delete;
+};
+bool in_no_alloc_scope();
 // Turns measuring on or off; `path` (may be empty) names a text cache that is
 // read now and rewritten after every new measurement.  Returns false when the
 // file exists but cannot be parsed.

@@ -110,6 +110,9 @@ def lib() -> ctypes.CDLL:
         L.msibm_disparity.argtypes = [ctypes.POINTER(Pair), _I32, ctypes.POINTER(Config), _PP, _PP,
                                       _PP, _PP, _VP, ctypes.c_size_t, _VP]
         L.msibm_disparity.restype = _I32
+        L.msibm_disparity_noalloc.argtypes = [ctypes.POINTER(Pair), ctypes.POINTER(Config), _VP, _VP, _VP, _VP,
+                                              _VP]
+        L.msibm_disparity_noalloc.restype = _I32
         L.msibm_backward.argtypes = [ctypes.POINTER(Pair), _I32, ctypes.POINTER(Config), _PP, _PP,
                                      _PP, _PP, _VP, ctypes.c_size_t, _VP]
         L.msibm_backward.restype = _I32
@@ -443,6 +446,22 @@ def disparity_many(lefts: Sequence[torch.Tensor], rights: Sequence[torch.Tensor]
     pri = _ptr_array([o.get("prior1") for o in outputs])
     _check(lib().msibm_disparity(pairs, npair, ctypes.byref(cfg), disp, cost, soft, pri,
                                  _ptr(workspace), workspace.numel(), _stream(dev)))
+    del keep
+    return outputs
+
+
+def disparity_noalloc(L: torch.Tensor, R: torch.Tensor, D: int, K: int, n, r: int, var_eps: float,
+                      outputs: Dict[str, torch.Tensor], soft_radius: int = 0, tau: float = 0.05,
+                      flags: int = 0, median_alpha: Optional[float] = None,
+                      gate: Optional[Tuple[float, float]] = None) -> Dict[str, torch.Tensor]:
+    """The forward of one pair through msibm_disparity_noalloc: no workspace,
+    the library's own device scratch.  `outputs` holds 'disp' and optionally
+    'cost', 'soft' and 'prior1' tensors, which are filled in place."""
+    pairs, keep = _pairs([L], [R], [D], [K])
+    cfg = make_config(n, r, var_eps, soft_radius, tau, flags, median_alpha, gate)
+    _check(lib().msibm_disparity_noalloc(pairs, ctypes.byref(cfg), _ptr(outputs["disp"]),
+                                         _ptr(outputs.get("cost")), _ptr(outputs.get("soft")),
+                                         _ptr(outputs.get("prior1")), _stream(L.device)))
     del keep
     return outputs
 

@@ -163,6 +163,32 @@ def test_config_and_pair_validation(lib):
     assert msibm.auto_levels(32) == 1 and msibm.auto_levels(33) == 2 and msibm.auto_levels(400) == 5
 
 
+def test_noalloc_validation_from_host(lib):
+    """The allocation-free entry point rejects, before touching a device, what
+    it cannot run: a pair needing more scratch than it holds, the batched
+    path, missing outputs, a soft level on uint8 images."""
+    from paper_1901_09593_amd import msibm
+    e = msibm.lib()
+    good = msibm.make_config(3, 2, 0.065)
+    big = (msibm.Pair * 1)(msibm.Pair(0x1000, 0x2000, 0, 4000, 4000, 4000, 64, 0))
+    need = e.msibm_workspace_size(big, 1, ctypes.byref(good))
+    assert need > (96 << 20)
+    d = ctypes.c_void_p(0x3000)
+    assert e.msibm_disparity_noalloc(big, ctypes.byref(good), d, None, None, None, None) == -3
+    assert b"scratch" in e.msibm_last_error()
+    small = (msibm.Pair * 1)(msibm.Pair(0x1000, 0x2000, 0, 64, 80, 80, 32, 0))
+    for flags in (msibm.FLAG_BATCHED, msibm.FLAG_BATCHED | msibm.FLAG_GRAPH):
+        cfg = msibm.make_config(3, 2, 0.065, flags=flags)
+        assert e.msibm_disparity_noalloc(small, ctypes.byref(cfg), d, None, None, None, None) == -4
+    assert e.msibm_disparity_noalloc(small, ctypes.byref(good), None, None, None, None, None) == -1
+    assert e.msibm_disparity_noalloc(None, ctypes.byref(good), d, None, None, None, None) == -1
+    soft = msibm.make_config(3, 2, 0.065, 3, 0.05)
+    assert e.msibm_disparity_noalloc(small, ctypes.byref(soft), d, None, None, None, None) == -4
+    fsmall = (msibm.Pair * 1)(msibm.Pair(0x1000, 0x2000, 1, 64, 80, 80, 32, 2))
+    assert e.msibm_disparity_noalloc(fsmall, ctypes.byref(soft), d, None, None, None, None) == -1
+    assert b"soft_disp" in e.msibm_last_error()
+
+
 def test_workspace_grows_with_levels(lib):
     from paper_1901_09593_amd import msibm
     e = msibm.lib()
