@@ -432,6 +432,43 @@ msibm_status msibm_backward(const msibm_pair* pairs, int32_t n_pairs, const msib
                             size_t ws_bytes, void* stream);
 
 /*
+ * msibm_fwd_bwd_l1 - the forward, the masked mean-L1 loss and the backward of
+ * n_pairs float pairs in one call (a training step's work on the
+ * differentiable finest level; not in the paper, which has no loss).  Per pair
+ *   L = (1/|M|) sum_{(i,j) in M} |d_soft(i,j) - gt(i,j)|   (L = 0 when M is empty)
+ * and dL/dd_soft = sign(d_soft - gt)/|M| on M (sign(0) = 0), 0 elsewhere,
+ * carried to both images as msibm_backward does.  Levels K-1..1 run as in
+ * msibm_disparity; level 0 is one fused launch that computes the soft level,
+ * forms each pixel's loss gradient from its d_soft and runs the backward with
+ * it (no soft-level launch of its own, no dL/dd_soft buffer, and the level-0
+ * window statistics of the forward are reused).  The d_soft, winner and score
+ * it writes are those msibm_disparity computes, up to the summation order of
+ * the window sums (the backward's pixel-row order), within the forward's
+ * tolerances.
+ *   pairs[p]        MSIBM_F32, K >= 2; cfg: soft_radius >= 1, no PREBLUR,
+ *                   MEDIAN or GATED.
+ *   d_gt[p]         device float H x W (pitch W): target disparity.
+ *   mask[p]         device uint8 H x W (pitch W): nonzero on the loss pixels M.
+ *   disp[p], cost[p] (cost may be NULL), soft_disp[p], prior1[p] (may be NULL)
+ *                   outputs as for msibm_disparity.
+ *   grad_left[p], grad_right[p]  device float H x W (pitch W), OVERWRITTEN.
+ *   loss[p]         device float, receives L.
+ *   workspace       msibm_workspace_size(pairs, n_pairs, cfg) bytes.
+ * Without MSIBM_FLAG_BATCHED the pairs run one after another; with it every
+ * stage is one launch for all pairs; with MSIBM_FLAG_GRAPH too the whole
+ * sequence (forward, loss and backward) is one captured graph, replayed as
+ * described for msibm_disparity (keyed by the pairs, cfg and every buffer
+ * pointer).  Gradients and the loss sum use float atomics (low bits depend on
+ * the summation order).
+ * Errors: INVALID_ARG, SHAPE, UNSUPPORTED, WORKSPACE, HIP.
+ */
+msibm_status msibm_fwd_bwd_l1(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg,
+                              const float* const* d_gt, const uint8_t* const* mask, int16_t* const* disp,
+                              float* const* cost, float* const* soft_disp, int16_t* const* prior1,
+                              float* const* grad_left, float* const* grad_right, float* const* loss,
+                              void* workspace, size_t ws_bytes, void* stream);
+
+/*
  * Launch timing (instrumentation, off by default).  While enabled, every kernel
  * launch that msibm_disparity and msibm_backward enqueue is bracketed by two HIP
  * events on the launch stream, labelled by kernel and level (for example

@@ -163,6 +163,8 @@ PairLayout pair_layout(const msibm_pair& p, int K, bool preblur, bool median, bo
         L.ctmp = off;
         off = align_up(off + (size_t)p.height * p.width * sizeof(float));
     }
+    L.l1acc = off;
+    off = align_up(off + 2 * sizeof(float));
     if (level_grads)
         for (int k = 1; k <= K - 2; ++k)
             for (int v = 0; v < 2; ++v) {
@@ -591,6 +593,53 @@ msibm_status msibm_backward(const msibm_pair* pairs, int32_t n_pairs, const msib
         std::string err;
         const int rc = run_pair_backward(pairs[p], lay, cfg, ws, prior1[p], grad_soft[p], grad_left[p],
                                          grad_right[p], s, &err);
+        if (rc != MSIBM_OK) return fail(rc, "pair %d: %s", p, err.c_str());
+    }
+    return ok();
+}
+
+msibm_status msibm_fwd_bwd_l1(const msibm_pair* pairs, int32_t n_pairs, const msibm_config* cfg,
+                              const float* const* d_gt, const uint8_t* const* mask, int16_t* const* disp,
+                              float* const* cost, float* const* soft_disp, int16_t* const* prior1,
+                              float* const* grad_left, float* const* grad_right, float* const* loss,
+                              void* workspace, size_t ws_bytes, void* stream)
+{
+    if (!pairs || !d_gt || !mask || !disp || !soft_disp || !grad_left || !grad_right || !loss)
+        return fail(MSIBM_ERR_INVALID_ARG, "NULL argument");
+    if (n_pairs < 1 || n_pairs > MSIBM_MAX_PAIRS)
+        return fail(MSIBM_ERR_INVALID_ARG, "n_pairs %d outside 1..%d", n_pairs, MSIBM_MAX_PAIRS);
+    msibm_status st = validate_config(cfg);
+    if (st != MSIBM_OK) return st;
+    if (cfg->soft_radius < 1) return fail(MSIBM_ERR_INVALID_ARG, "the fused step needs soft_radius >= 1");
+    if (cfg->flags & (MSIBM_FLAG_PREBLUR | MSIBM_FLAG_MEDIAN | MSIBM_FLAG_GATED))
+        return fail(MSIBM_ERR_UNSUPPORTED, "PREBLUR, MEDIAN and GATED are forward-only variants");
+    std::vector<FusedL1Pair> io(n_pairs);
+    for (int p = 0; p < n_pairs; ++p) {
+        int K;
+        st = validate_pair(pairs[p], p, cfg, &K);  // float images and K >= 2 (soft level)
+        if (st != MSIBM_OK) return st;
+        if (!d_gt[p] || !mask[p] || !disp[p] || !soft_disp[p] || !grad_left[p] || !grad_right[p] || !loss[p])
+            return fail(MSIBM_ERR_INVALID_ARG, "pair %d: NULL input or output buffer", p);
+        io[p] = FusedL1Pair{d_gt[p], mask[p], disp[p], cost ? cost[p] : nullptr, soft_disp[p],
+                            prior1 ? prior1[p] : nullptr, grad_left[p], grad_right[p], loss[p]};
+    }
+    const size_t need = msibm_workspace_size(pairs, n_pairs, cfg);
+    if (!workspace || ws_bytes < need)
+        return fail(MSIBM_ERR_WORKSPACE, "workspace %zu bytes < %zu needed", workspace ? ws_bytes : (size_t)0, need);
+    hipStream_t s = (hipStream_t)stream;
+    std::string err;
+    if (cfg->flags & MSIBM_FLAG_BATCHED) {
+        const int rc = run_batched_fused_l1(pairs, n_pairs, cfg, io.data(), workspace, ws_bytes, s, &err);
+        if (rc != MSIBM_OK) return fail(rc, "%s", err.c_str());
+        return ok();
+    }
+    size_t base = 0;
+    for (int p = 0; p < n_pairs; ++p) {
+        int K;
+        validate_pair(pairs[p], p, cfg, &K);
+        const PairLayout lay = pair_layout(pairs[p], K);
+        const int rc = run_pair_fused_l1(pairs[p], lay, cfg, (char*)workspace + base, io[p], s, &err);
+        base += lay.bytes;
         if (rc != MSIBM_OK) return fail(rc, "pair %d: %s", p, err.c_str());
     }
     return ok();

@@ -52,6 +52,19 @@ struct BackArgs {
     int gpitch;
     float* gL;                // H x W, pitch gpitch; accumulated (zero first)
     float* gR;
+    // Fused masked-L1 form (the FUSED kernels): the upstream gradient is formed
+    // in the kernel from the soft disparity it computes, g = sign(d_soft - gt) /
+    // |M| on the loss pixels M and 0 elsewhere, instead of being read from g;
+    // the kernel also writes the soft level's outputs and adds the pair's
+    // sum over M of |d_soft - gt| into loss_sum.
+    const float* gt;          // ground-truth disparity, pitch gpitch
+    const uint8_t* mask;      // nonzero on M, pitch gpitch
+    int* count;               // |M| (the mask count kernel's result)
+    float* loss_sum;          // one float per pair, zeroed before the launch
+    float* loss_out;          // the pair's loss, sum / |M| (the finalize kernel)
+    float* soft_out;          // d_soft, pitch gpitch
+    int16_t* d_out;           // hard winner over the soft interval, pitch gpitch
+    float* c_out;             // its score (NULL: not written), pitch gpitch
 };
 
 template <int NW, int CH>
@@ -65,6 +78,7 @@ struct BackSmem {
     unsigned mask;
     int lmin, lmax, rmin, rmax;            // value ranges of the staged tiles (ordered float keys)
     unsigned kmax[5];                      // largest coefficient magnitudes (float bits)
+    float red[16];                         // per-wave partial loss sums (fused form)
 };
 
 // Order-preserving int key of a float (signed comparison), and its inverse.
@@ -155,7 +169,7 @@ __device__ __forceinline__ void row_sums(const float* __restrict__ Ls, const flo
     }
 }
 
-template <int NW, int NC>
+template <int NW, int NC, bool FUSED = false>
 __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by, BackSmem<NW, BACK_CHUNK>& sm)
 {
     constexpr int CH = BACK_CHUNK;
@@ -213,6 +227,10 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
     if (blk) atomicOr(&sm.mask, 1u << ((zs - zlo) / STEP));
     __syncthreads();
     const unsigned mask = sm.mask;
+    // fused form: 1/|M| (as a float reciprocal of the float count) and this
+    // thread's share of the loss sum
+    const float inv_count = FUSED ? 1.f / (float)max(*a.count, 1) : 0.f;
+    float lsum = 0.f;
 
     for (int zc = zlo, ci = 0; zc <= zhi; zc += STEP, ++ci) {
         if (!((mask >> ci) & 1u)) continue;
@@ -266,7 +284,7 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
 #pragma unroll
             for (int pc = 0; pc < 2; ++pc) {
                 stl2[pc] = a.statL[(size_t)ii * a.spitch + jp[pc]];
-                gpx2[pc] = a.g[(size_t)ii * a.gpitch + jp[pc]];
+                gpx2[pc] = FUSED ? a.gt[(size_t)ii * a.gpitch + jp[pc]] : a.g[(size_t)ii * a.gpitch + jp[pc]];
 #pragma unroll
                 for (int s = 0; s < NC; ++s) str2[pc][s] = srow[clampi(jp[pc] - (zs + s), 0, a.W - 1)];
             }
@@ -283,6 +301,7 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
                 float mr[NC], invr[NC], rho[NC];
                 bool ok[NC];
                 float best = -3.f;
+                int bz = 0;
 #pragma unroll
                 for (int s = 0; s < NC; ++s) {
                     const int z = zs + s;
@@ -294,7 +313,10 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
                     rr = fminf(fmaxf(rr, -1.f), 1.f);
                     ok[s] = (z >= lo[pc]) && (z <= hi[pc]);
                     rho[s] = rr;
-                    if (ok[s] && rr > best) best = rr;
+                    if (ok[s] && rr > best) {
+                        best = rr;
+                        bz = z;
+                    }
                 }
                 float e[NC], se = 0.f, sz = 0.f;
 #pragma unroll
@@ -304,7 +326,19 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
                     sz = fmaf(e[s], (float)(zs + s), sz);
                 }
                 const float ds = sz / se;
-                const float gpx = gpx2[pc];
+                float gpx = gpx2[pc];
+                if (FUSED) {
+                    // the soft level's outputs, and the masked-L1 gradient of
+                    // this pixel: sign(d_soft - gt) / |M| on M
+                    const size_t o = (size_t)ii * a.gpitch + jp[pc];
+                    a.soft_out[o] = ds;
+                    a.d_out[o] = (int16_t)bz;
+                    if (a.c_out) a.c_out[o] = best;
+                    const float diff = ds - gpx;
+                    const bool m = a.mask[o] != 0;
+                    gpx = m ? (float)((diff > 0.f) - (diff < 0.f)) * inv_count : 0.f;
+                    if (m) lsum += fabsf(diff);
+                }
                 const float gs = gpx * a.inv_tau / se;
                 float k2r[NC], klp = 0.f, clp = 0.f;
 #pragma unroll
@@ -424,14 +458,34 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
         flush_tile(sm.GLs, G::LSTRIDE, G::LHALF, G::LROWS, G::LCOLS, inv_scale, a.gL, a.gpitch, a.H, a.W, y0 - NW,
                    x0 - NW);
     }
+    if (FUSED) {
+        // the tile's loss sum: waves reduce across lanes, then one add per tile
+        for (int off = MATCH_TX / 2; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off);
+        if ((threadIdx.x & (MATCH_TX - 1)) == 0) sm.red[threadIdx.x / MATCH_TX] = lsum;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float t = 0.f;
+            for (int q = 0; q < BACK_WAVES; ++q) t += sm.red[q];
+            if (t != 0.f) atomicAdd(a.loss_sum, t);
+        }
+    }
     __syncthreads();  // LDS may be reused by the caller's next tile
 }
 
-template <int NW, int NC>
+template <int NW, int NC, bool FUSED>
 __global__ __launch_bounds__(BACK_THREADS) void backward_kernel(BackArgs a)
 {
     __shared__ BackSmem<NW, BACK_CHUNK> sm;
-    backward_tile<NW, NC>(a, blockIdx.x, blockIdx.y, sm);
+    backward_tile<NW, NC, FUSED>(a, blockIdx.x, blockIdx.y, sm);
+}
+
+template <int NW, int NC>
+static void launch_backward_nc(const BackArgs& a, dim3 grid, hipStream_t s)
+{
+    // the fused masked-L1 form is the instance whose upstream gradient comes
+    // from a ground-truth map
+    if (a.gt) hipLaunchKernelGGL((backward_kernel<NW, NC, true>), grid, dim3(BACK_THREADS), 0, s, a);
+    else hipLaunchKernelGGL((backward_kernel<NW, NC, false>), grid, dim3(BACK_THREADS), 0, s, a);
 }
 
 template <int NW>
@@ -439,23 +493,23 @@ static hipError_t dispatch_backward(int nc, const BackArgs& a, hipStream_t s)
 {
     dim3 grid((a.W + TILE_W - 1) / TILE_W, (a.H + TILE_H1 - 1) / TILE_H1, 1);
     switch (nc) {
-        case 3: hipLaunchKernelGGL((backward_kernel<NW, 3>), grid, dim3(BACK_THREADS), 0, s, a); break;
-        case 5: hipLaunchKernelGGL((backward_kernel<NW, 5>), grid, dim3(BACK_THREADS), 0, s, a); break;
-        case 7: hipLaunchKernelGGL((backward_kernel<NW, 7>), grid, dim3(BACK_THREADS), 0, s, a); break;
-        case 9: hipLaunchKernelGGL((backward_kernel<NW, 9>), grid, dim3(BACK_THREADS), 0, s, a); break;
+        case 3: launch_backward_nc<NW, 3>(a, grid, s); break;
+        case 5: launch_backward_nc<NW, 5>(a, grid, s); break;
+        case 7: launch_backward_nc<NW, 7>(a, grid, s); break;
+        case 9: launch_backward_nc<NW, 9>(a, grid, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
 // Backward tiles of several pairs in one launch (level 0 of each pair).
-template <int NW, int NC>
+template <int NW, int NC, bool FUSED>
 __global__ __launch_bounds__(BACK_THREADS) void backward_multi_kernel(MultiArgs a)
 {
     __shared__ BackSmem<NW, BACK_CHUNK> sm;
     const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
     const int t = blockIdx.x - s.task0;
-    backward_tile<NW, NC>(a.back[s.pair], t % s.tiles_x, t / s.tiles_x, sm);
+    backward_tile<NW, NC, FUSED>(a.back[s.pair], t % s.tiles_x, t / s.tiles_x, sm);
 }
 
 // Backward tiles of several soft levels of one pair in one launch.  Their
@@ -476,7 +530,7 @@ __global__ __launch_bounds__(BACK_THREADS) void backward_levels_kernel(BackLevel
     int i = 0;
     while (i + 1 < a.n && a.task0[i + 1] <= (int)blockIdx.x) ++i;
     const int t = (int)blockIdx.x - a.task0[i];
-    backward_tile<NW, NC>(a.lev[i], t % a.tiles_x[i], t / a.tiles_x[i], sm);
+    backward_tile<NW, NC, false>(a.lev[i], t % a.tiles_x[i], t / a.tiles_x[i], sm);
 }
 
 template <int NW>
@@ -500,15 +554,22 @@ hipError_t launch_backward_levels_n4(int nc, const BackLevels& a, int blocks, hi
 hipError_t launch_backward_levels_n5(int nc, const BackLevels& a, int blocks, hipStream_t s);
 hipError_t launch_backward_levels_n6(int nc, const BackLevels& a, int blocks, hipStream_t s);
 
+template <int NW, int NC>
+static void launch_backward_multi_nc(const MultiArgs& a, int blocks, hipStream_t s)
+{
+    if (a.fused) hipLaunchKernelGGL((backward_multi_kernel<NW, NC, true>), dim3(blocks), dim3(BACK_THREADS), 0, s, a);
+    else hipLaunchKernelGGL((backward_multi_kernel<NW, NC, false>), dim3(blocks), dim3(BACK_THREADS), 0, s, a);
+}
+
 template <int NW>
 static hipError_t dispatch_backward_multi(int nc, const MultiArgs& a, int blocks, hipStream_t s)
 {
     if (blocks < 1 || a.nseg < 1) return hipErrorInvalidValue;
     switch (nc) {
-        case 3: hipLaunchKernelGGL((backward_multi_kernel<NW, 3>), dim3(blocks), dim3(BACK_THREADS), 0, s, a); break;
-        case 5: hipLaunchKernelGGL((backward_multi_kernel<NW, 5>), dim3(blocks), dim3(BACK_THREADS), 0, s, a); break;
-        case 7: hipLaunchKernelGGL((backward_multi_kernel<NW, 7>), dim3(blocks), dim3(BACK_THREADS), 0, s, a); break;
-        case 9: hipLaunchKernelGGL((backward_multi_kernel<NW, 9>), dim3(blocks), dim3(BACK_THREADS), 0, s, a); break;
+        case 3: launch_backward_multi_nc<NW, 3>(a, blocks, s); break;
+        case 5: launch_backward_multi_nc<NW, 5>(a, blocks, s); break;
+        case 7: launch_backward_multi_nc<NW, 7>(a, blocks, s); break;
+        case 9: launch_backward_multi_nc<NW, 9>(a, blocks, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

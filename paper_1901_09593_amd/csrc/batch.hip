@@ -35,7 +35,7 @@ static int levels_of(const msibm_pair& p) { return p.num_levels ? p.num_levels :
 
 enum StageKind {
     STAGE_LEVELS = 0, STAGE_STATS = 1, STAGE_MATCH = 2, STAGE_ZERO = 3, STAGE_BACKWARD = 4, STAGE_MEDIAN = 5,
-    STAGE_GATE = 6, STAGE_BLUR = 7
+    STAGE_GATE = 6, STAGE_BLUR = 7, STAGE_COUNT = 8, STAGE_FUSED = 9, STAGE_L1_FINAL = 10
 };
 
 struct StageLaunch {
@@ -61,6 +61,11 @@ __global__ __launch_bounds__(256) void zero_multi_kernel(MultiArgs a)
     const BackArgs& b = a.back[s.pair];
     const size_t count = (size_t)b.H * b.W;
     const size_t base = (size_t)(blockIdx.x - s.task0) * ZERO_TILE + threadIdx.x;
+    // the fused masked-L1 step also clears the pair's count and loss sum
+    if (b.count && (int)blockIdx.x == s.task0 && threadIdx.x == 0) {
+        *b.count = 0;
+        *b.loss_sum = 0.f;
+    }
 #pragma unroll 4
     for (int m = 0; m < ZERO_TILE / 256; ++m) {
         const size_t i = base + (size_t)m * 256;
@@ -122,8 +127,9 @@ static void table_layout(BatchPlan& pl, int nlevels, int np, int nback)
     pl.bytes = align_up(off + sizeof(BackArgs) * (size_t)nback);
 }
 
-// Segments and launches (no device pointers yet).
-static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg, BatchPlan& pl)
+// Segments and launches (no device pointers yet).  Levels below `lowest` are
+// not matched (their pyramid images and statistics are still made).
+static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg, BatchPlan& pl, int lowest = 0)
 {
     std::vector<int> K(np);
     int Kmax = 0;
@@ -170,7 +176,7 @@ static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg
     auto mode_of = [&](int p, int k) {
         return (k == K[p] - 1) ? MODE_FULL : ((k == 0 && cfg->soft_radius > 0) ? MODE_SOFT : MODE_REFINE);
     };
-    for (int k = Kmax - 1; k >= 0; --k) {
+    for (int k = Kmax - 1; k >= lowest; --k) {
         for (int m = 0; m < 3; ++m)
             for (int dt = 0; dt < 2; ++dt) {
                 bool opened = false;
@@ -248,6 +254,40 @@ static void plan_backward_stages(const msibm_pair* pairs, int np, BatchPlan& pl)
         pl.launches.push_back(l);
     }
     table_layout(pl, np, np, np);
+}
+
+// Launch over one segment per pair (tiles of `type`, level 0) appended to the plan.
+static void add_pair_stage(const msibm_pair* pairs, int np, int kind, int type, BatchPlan& pl)
+{
+    StageLaunch l{};
+    l.kind = kind;
+    l.first = (int)pl.segs.size();
+    for (int p = 0; p < np; ++p) {
+        const Segment sg = make_seg(type, p, 0, pairs[p].height, pairs[p].width, pairs[p].dtype, l.blocks);
+        l.blocks += seg_tiles(sg);
+        l.nseg++;
+        pl.segs.push_back(sg);
+    }
+    pl.launches.push_back(l);
+}
+
+// The fused masked-L1 step: gradients and loss accumulators cleared and the
+// loss pixels counted, the forward down to level 1, one fused soft-level and
+// backward launch for level 0 of every pair, the loss values.
+static void plan_fused_stages(const msibm_pair* pairs, int np, const msibm_config* cfg, BatchPlan& pl)
+{
+    add_pair_stage(pairs, np, STAGE_ZERO, SEG_ZERO, pl);
+    add_pair_stage(pairs, np, STAGE_COUNT, SEG_ZERO, pl);
+    plan_stages(pairs, np, cfg, pl, 1);
+    add_pair_stage(pairs, np, STAGE_FUSED, SEG_BACKWARD, pl);
+    StageLaunch fin{};
+    fin.kind = STAGE_L1_FINAL;
+    fin.first = (int)pl.segs.size();
+    fin.blocks = (np + 255) / 256;
+    pl.launches.push_back(fin);
+    int nl = 0;
+    for (int p = 0; p < np; ++p) nl += levels_of(pairs[p]);
+    table_layout(pl, nl, np, np);
 }
 
 // Workspace layout of one pair on the batched path (the same as the size query's).
@@ -331,10 +371,15 @@ static size_t pairs_bytes(const msibm_pair* pairs, int np, const msibm_config* c
 size_t batch_extra_bytes(const msibm_pair* pairs, int n_pairs, const msibm_config* cfg)
 {
     if (!(cfg->flags & MSIBM_FLAG_BATCHED)) return 0;
-    BatchPlan fw, bw;
+    BatchPlan fw, bw, fu;
     plan_stages(pairs, n_pairs, cfg, fw);
     plan_backward_stages(pairs, n_pairs, bw);
-    return fw.bytes > bw.bytes ? fw.bytes : bw.bytes;
+    size_t b = fw.bytes > bw.bytes ? fw.bytes : bw.bytes;
+    if (cfg->soft_radius > 0) {
+        plan_fused_stages(pairs, n_pairs, cfg, fu);
+        b = fu.bytes > b ? fu.bytes : b;
+    }
+    return b;
 }
 
 // Host image of the table: segments, level descriptors, level bases.
@@ -380,6 +425,9 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
             snprintf(lab, sizeof(lab), l.mode == GATE_MODE_FUSED ? "batch_gate_fused_l%d" : "batch_gate_repick_l%d",
                      l.level);
         else if (l.kind == STAGE_BLUR) snprintf(lab, sizeof(lab), "batch_preblur_l0");
+        else if (l.kind == STAGE_COUNT) snprintf(lab, sizeof(lab), "batch_fused_count");
+        else if (l.kind == STAGE_FUSED) snprintf(lab, sizeof(lab), "batch_fused_backward_l0");
+        else if (l.kind == STAGE_L1_FINAL) snprintf(lab, sizeof(lab), "batch_fused_loss");
         else snprintf(lab, sizeof(lab), "batch_match_%s_l%d", mode_name[l.mode], l.level);
         const int slot = timed ? timing_begin(lab, s) : -1;
         hipError_t e = hipSuccess;
@@ -403,8 +451,14 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
         else if (l.kind == STAGE_ZERO) {
             hipLaunchKernelGGL(zero_multi_kernel, dim3(l.blocks), dim3(256), 0, s, a);
             e = hipGetLastError();
-        } else if (l.kind == STAGE_BACKWARD)
+        } else if (l.kind == STAGE_BACKWARD || l.kind == STAGE_FUSED) {
+            a.fused = l.kind == STAGE_FUSED;
             e = launch_backward_multi(level_n(cfg, 0), slots_for_radius(cfg->soft_radius), a, l.blocks, s);
+            a.fused = 0;
+        } else if (l.kind == STAGE_COUNT)
+            e = launch_mask_count_multi(a, l.blocks, s);
+        else if (l.kind == STAGE_L1_FINAL)
+            e = launch_l1_finalize_multi(a, (int)pl.back.size(), s);
         else if (l.kind == STAGE_MEDIAN)
             e = launch_median_multi(a, l.blocks, s);
         else if (l.kind == STAGE_GATE)
@@ -676,6 +730,75 @@ int run_batched_backward(const msibm_pair* pairs, int np, const msibm_config* cf
             b.gpitch = P.width;
             b.gL = g.grad_left[p];
             b.gR = g.grad_right[p];
+            pl.back.push_back(b);
+        }
+    };
+    return run_plan(dev, cfg, graph ? &key : nullptr, build, (char*)workspace + pairs_bytes(pairs, np, cfg), s,
+                    err);
+}
+
+int run_batched_fused_l1(const msibm_pair* pairs, int np, const msibm_config* cfg, const FusedL1Pair* io,
+                         void* workspace, size_t ws_bytes, hipStream_t s, std::string* err)
+{
+    int dev = 0;
+    const hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "device", err);
+    GraphKey key;
+    const bool graph = (cfg->flags & MSIBM_FLAG_GRAPH) != 0;
+    if (graph) {
+        std::vector<const void*> bufs;
+        for (int p = 0; p < np; ++p) {
+            const FusedL1Pair& q = io[p];
+            const void* b[9] = {q.gt, q.mask, q.disp, q.cost, q.soft, q.prior1, q.grad_left, q.grad_right, q.loss};
+            bufs.insert(bufs.end(), b, b + 9);
+        }
+        key = make_key('L', dev, pairs, np, cfg, bufs, workspace, ws_bytes);
+    }
+    std::vector<int16_t*> disp(np), prior(np);
+    std::vector<float*> cost(np), soft(np);
+    for (int p = 0; p < np; ++p) {
+        disp[p] = io[p].disp;
+        prior[p] = io[p].prior1;
+        cost[p] = io[p].cost;
+        soft[p] = io[p].soft;
+    }
+    const BatchOutputs out{disp.data(), cost.data(), soft.data(), prior.data()};
+    auto build = [&](BatchPlan& pl) {
+        plan_fused_stages(pairs, np, cfg, pl);
+        plan_levels(pairs, np, cfg, out, (char*)workspace, pl);
+        size_t base = 0;
+        for (int p = 0; p < np; ++p) {
+            const msibm_pair& P = pairs[p];
+            const PairLayout lay = batch_layout(P, cfg);
+            char* ws = (char*)workspace + base;
+            base += lay.bytes;
+            BackArgs b{};
+            b.L = (const float*)P.left;
+            b.R = (const float*)P.right;
+            b.H = P.height;
+            b.W = P.width;
+            b.pitch = P.pitch;
+            b.statL = (const WinStat*)(ws + lay.stat[0][0]);
+            b.statR = (const WinStat*)(ws + lay.stat[0][1]);
+            b.spitch = P.width;
+            b.D = P.max_disp;
+            b.prior = io[p].prior1 ? io[p].prior1 : (const int16_t*)(ws + lay.map[1]);
+            b.Hc = lay.h[1];
+            b.Wc = lay.w[1];
+            b.ppitch = lay.w[1];
+            b.rs = cfg->soft_radius;
+            b.inv_tau = 1.f / cfg->tau;
+            b.gpitch = P.width;
+            b.gL = io[p].grad_left;
+            b.gR = io[p].grad_right;
+            b.gt = io[p].gt;
+            b.mask = io[p].mask;
+            b.count = (int*)(ws + lay.l1acc);
+            b.loss_sum = (float*)(ws + lay.l1acc) + 1;
+            b.loss_out = io[p].loss;
+            b.soft_out = io[p].soft;
+            b.d_out = io[p].disp;
+            b.c_out = io[p].cost;
             pl.back.push_back(b);
         }
     };

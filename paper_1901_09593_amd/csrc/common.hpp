@@ -216,6 +216,7 @@ struct MultiArgs {
     float inv_tau;
     double median_alpha;      // median launches
     double gate_alpha, gate_beta;  // gating launches
+    int fused;                // backward launches: the fused masked-L1 form
 };
 
 // Tile of the gating kernel.
@@ -296,6 +297,10 @@ hipError_t launch_backward_n5(int nc, const BackArgs& a, hipStream_t s);
 hipError_t launch_backward_n6(int nc, const BackArgs& a, hipStream_t s);
 // Zero `count` floats at each of up to two pointers (graph-capturable fill).
 hipError_t launch_zero(float* a, float* b, size_t count, hipStream_t s);
+hipError_t launch_mask_count(const uint8_t* mask, size_t total, int* count, hipStream_t s);
+hipError_t launch_mask_count_multi(const MultiArgs& a, int blocks, hipStream_t s);
+hipError_t launch_l1_finalize(const float* sum, const int* count, float* loss, hipStream_t s);
+hipError_t launch_l1_finalize_multi(const MultiArgs& a, int np, hipStream_t s);
 hipError_t launch_fill(float* a, float v, size_t count, hipStream_t s);
 
 // Slots evaluated per block: 2r+1, but at least 2 so that a block whose prior

@@ -131,7 +131,7 @@ static int build_stats(const PairLayout& lay, const msibm_config* cfg, char* ws,
 
 int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,
                    int16_t* disp, float* cost, float* soft, int16_t* prior1, hipStream_t s,
-                   std::string* err)
+                   std::string* err, int lowest_level)
 {
     const int K = lay.K;
     hipError_t e;
@@ -171,7 +171,7 @@ int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_confi
         const int st = build_stats(lay, cfg, ws, img, pitch, dts, s, err);
         if (st != MSIBM_OK) return st;
     }
-    for (int k = K - 1; k >= 0; --k) {
+    for (int k = K - 1; k >= lowest_level; --k) {
         MatchArgs a{};
         a.L = img[k][0];
         a.R = img[k][1];
@@ -498,6 +498,67 @@ int run_pair_backward(const msibm_pair& P, const PairLayout& lay, const msibm_co
         e = launch_backward(level_n(cfg, 0), slots_for_radius(cfg->soft_radius), b, s);
     }
     if (e != hipSuccess) return hip_err(e, "backward launch", err);
+    return MSIBM_OK;
+}
+
+// The fused training step of one pair: the forward down to level 1, then one
+// launch for level 0 that computes the soft level, forms the masked-L1
+// gradient sign(d_soft - gt) / |M| per pixel and runs the backward with it,
+// reusing the level-0 statistics the forward stored.
+int run_pair_fused_l1(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,
+                      const FusedL1Pair& io, hipStream_t s, std::string* err)
+{
+    hipError_t e;
+    const int H = P.height, W = P.width;
+    int* count = (int*)(ws + lay.l1acc);
+    float* lsum = (float*)(ws + lay.l1acc) + 1;
+    {
+        TimedLaunch t("fused_zero", s);
+        e = launch_zero(io.grad_left, io.grad_right, (size_t)H * W, s);
+        if (e == hipSuccess) e = launch_fill((float*)count, 0.f, 2, s);  // count and sum: all-zero bits
+    }
+    if (e != hipSuccess) return hip_err(e, "zero launch", err);
+    {
+        TimedLaunch t("fused_count", s);
+        e = launch_mask_count(io.mask, (size_t)H * W, count, s);
+    }
+    if (e != hipSuccess) return hip_err(e, "mask count launch", err);
+    const int st = run_pair_plain(P, lay, cfg, ws, io.disp, io.cost, io.soft, io.prior1, s, err, 1);
+    if (st != MSIBM_OK) return st;
+    BackArgs b{};
+    b.L = (const float*)P.left;
+    b.R = (const float*)P.right;
+    b.H = H;
+    b.W = W;
+    b.pitch = P.pitch;
+    b.statL = (const WinStat*)(ws + lay.stat[0][0]);
+    b.statR = (const WinStat*)(ws + lay.stat[0][1]);
+    b.spitch = W;
+    b.D = P.max_disp;
+    b.prior = io.prior1 ? io.prior1 : (const int16_t*)(ws + lay.map[1]);
+    b.Hc = lay.h[1];
+    b.Wc = lay.w[1];
+    b.ppitch = lay.w[1];
+    b.rs = cfg->soft_radius;
+    b.inv_tau = 1.f / cfg->tau;
+    b.gpitch = W;
+    b.gL = io.grad_left;
+    b.gR = io.grad_right;
+    b.gt = io.gt;
+    b.mask = io.mask;
+    b.count = count;
+    b.loss_sum = lsum;
+    b.loss_out = io.loss;
+    b.soft_out = io.soft;
+    b.d_out = io.disp;
+    b.c_out = io.cost;
+    {
+        TimedLaunch t("fused_backward_l0", s);
+        e = launch_backward(level_n(cfg, 0), slots_for_radius(cfg->soft_radius), b, s);
+    }
+    if (e != hipSuccess) return hip_err(e, "fused backward launch", err);
+    e = launch_l1_finalize(lsum, count, io.loss, s);
+    if (e != hipSuccess) return hip_err(e, "loss launch", err);
     return MSIBM_OK;
 }
 

@@ -36,6 +36,7 @@ struct PairLayout {
     size_t ctmp;              // level 0's cost (float) when the caller takes none
     size_t grad[MSIBM_MAX_LEVELS][2]; // levels 1..K-2: both views' image gradients (float),
                                       // for the backward through every level
+    size_t l1acc;             // the fused masked-L1 step: {int |M|, float sum |d_soft - gt|}
     size_t bytes;
 };
 
@@ -58,10 +59,33 @@ struct BatchOutputs {
     int16_t* const* prior1;
 };
 
-// Plain per-pair forward: 2K launches on `s`.
+// Plain per-pair forward: 2K launches on `s`.  Levels below lowest_level are
+// not matched (their pyramid images and statistics are still built).
 int run_pair_plain(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,
                    int16_t* disp, float* cost, float* soft, int16_t* prior1, hipStream_t s,
-                   std::string* err);
+                   std::string* err, int lowest_level = 0);
+
+// Buffers of the fused forward, masked-L1 loss and backward of one pair.
+struct FusedL1Pair {
+    const float* gt;          // ground-truth disparity, H x W, pitch W
+    const uint8_t* mask;      // loss pixels (nonzero), H x W, pitch W
+    int16_t* disp;            // level-0 hard winner over the soft interval
+    float* cost;              // its score, or NULL
+    float* soft;              // level-0 d_soft
+    int16_t* prior1;          // level-1 map, or NULL (then kept in the workspace)
+    float* grad_left;
+    float* grad_right;
+    float* loss;              // one float
+};
+
+// Levels K-1..1 of the forward, then one fused launch for level 0: its soft
+// level, the masked-L1 gradient and the backward to both images.
+int run_pair_fused_l1(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,
+                      const FusedL1Pair& io, hipStream_t s, std::string* err);
+
+// The same for several pairs, stage by stage (optionally replayed from a graph).
+int run_batched_fused_l1(const msibm_pair* pairs, int n_pairs, const msibm_config* cfg, const FusedL1Pair* io,
+                         void* workspace, size_t ws_bytes, hipStream_t s, std::string* err);
 
 int run_pair_backward(const msibm_pair& P, const PairLayout& lay, const msibm_config* cfg, char* ws,
                       const int16_t* prior1, const float* grad_soft, float* grad_left,

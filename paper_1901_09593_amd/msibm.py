@@ -116,6 +116,9 @@ def lib() -> ctypes.CDLL:
         L.msibm_backward.argtypes = [ctypes.POINTER(Pair), _I32, ctypes.POINTER(Config), _PP, _PP,
                                      _PP, _PP, _VP, ctypes.c_size_t, _VP]
         L.msibm_backward.restype = _I32
+        L.msibm_fwd_bwd_l1.argtypes = [ctypes.POINTER(Pair), _I32, ctypes.POINTER(Config), _PP, _PP, _PP, _PP,
+                                       _PP, _PP, _PP, _PP, _PP, _VP, ctypes.c_size_t, _VP]
+        L.msibm_fwd_bwd_l1.restype = _I32
         L.msibm_force_variant.argtypes = [_I32]
         L.msibm_force_variant.restype = _I32
         L.msibm_autotune.argtypes = [_I32, ctypes.c_char_p]
@@ -500,6 +503,46 @@ def backward_many(lefts: Sequence[torch.Tensor], rights: Sequence[torch.Tensor],
                                 _ptr_array([o[1] for o in outputs]), _ptr(workspace),
                                 workspace.numel(), _stream(dev)))
     del keep, g, p1
+    return outputs
+
+
+def fwd_bwd_l1(lefts: Sequence[torch.Tensor], rights: Sequence[torch.Tensor], gts: Sequence[torch.Tensor],
+               masks: Sequence[torch.Tensor], Ds: Sequence[int], Ks: Sequence[int], n: int, r: int,
+               var_eps: float, soft_radius: int, tau: float, flags: int = 0, with_cost: bool = False,
+               workspace: Optional[torch.Tensor] = None,
+               outputs: Optional[List[Dict[str, torch.Tensor]]] = None) -> List[Dict[str, torch.Tensor]]:
+    """Forward, masked mean-L1 loss (targets `gts`, uint8 `masks`) and backward
+    of several float pairs in one msibm_fwd_bwd_l1 call.  Returns per pair a
+    dict with 'disp', 'soft', 'prior1', 'grad_left', 'grad_right', 'loss' (a
+    one-element float tensor) and optionally 'cost'."""
+    pairs, keep = _pairs(lefts, rights, Ds, Ks)
+    npair = len(lefts)
+    cfg = make_config(n, r, var_eps, soft_radius, tau, flags)
+    ws_bytes = workspace_bytes(pairs, npair, cfg)
+    dev = lefts[0].device
+    if workspace is None or workspace.numel() < ws_bytes:
+        workspace = torch.empty(ws_bytes, dtype=torch.uint8, device=dev)
+    if outputs is None:
+        outputs = []
+        for i in range(npair):
+            H, W = lefts[i].shape
+            o = {"disp": torch.empty((H, W), dtype=torch.int16, device=dev),
+                 "soft": torch.empty((H, W), dtype=torch.float32, device=dev),
+                 "prior1": torch.empty((level_dim(H, 1), level_dim(W, 1)), dtype=torch.int16, device=dev),
+                 "grad_left": torch.empty((H, W), dtype=torch.float32, device=dev),
+                 "grad_right": torch.empty((H, W), dtype=torch.float32, device=dev),
+                 "loss": torch.empty(1, dtype=torch.float32, device=dev)}
+            if with_cost:
+                o["cost"] = torch.empty((H, W), dtype=torch.float32, device=dev)
+            outputs.append(o)
+    gt = [g.contiguous() for g in gts]
+    mk = [m.to(torch.uint8).contiguous() for m in masks]
+    arrs = [_ptr_array(gt), _ptr_array(mk)] + [_ptr_array([o.get(k) for o in outputs]) for k in
+                                                ("disp", "cost", "soft", "prior1", "grad_left", "grad_right",
+                                                 "loss")]
+    _check(lib().msibm_fwd_bwd_l1(pairs, npair, ctypes.byref(cfg), *arrs, _ptr(workspace), workspace.numel(),
+                                  _stream(dev)))
+    del keep
     return outputs
 
 
