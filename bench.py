@@ -22,7 +22,9 @@ Prints ONE JSON line.  `value` = pixel-disparity ZNCC evaluations per second
   batch_variants    the batch with the selective median, the confidence
                     gating and the paper's whole method, plain vs graph;
   fwd_bwd           forward + masked-L1 loss gradient + backward of 8 x 960x540
-                    and 4 x 2880x1988 float pairs, plain vs batched graph;
+                    and 4 x 2880x1988 float pairs: plain per-pair forward plus
+                    separate backward, the same as batched graphs, and the fused
+                    step (one call, one graph for forward, loss and backward);
   cpu_baseline      the FP64 oracle timed on the host cores over pairs of the
                     same batch (a reported baseline, not a target).
 `python bench.py --copy-probe BYTES` only runs a plain device copy (used to
@@ -473,8 +475,32 @@ def section_fwd_bwd(torch, M, synth, name, count, steps):
         res[label] = {"fwd_ms": ms_fwd, "bwd_ms": ms_bwd, "fwd_bwd_ms": ms_step,
                       "fwd_bwd_ms_per_pair": ms_step / count, "workspace_bytes": ws.numel()}
         del ws
+    # the fused step: forward, loss and backward in one call (msibm_fwd_bwd_l1);
+    # with the graph flag one captured graph for all of it
+    mask8 = [m.to(torch.uint8) for m in mask]
+    for label, flags in (("fused_plain", 0), ("fused_batched_graph", M.FLAG_BATCHED | M.FLAG_GRAPH)):
+        ws = torch.empty(M.workspace_bytes(pairs_arr, count, M.make_config(n, r, eps, rs, tau, flags)),
+                         dtype=torch.uint8, device=dev)
+        fo = M.fwd_bwd_l1(L, R, gt, mask8, Ds, Ks, n, r, eps, rs, tau, flags=flags, workspace=ws)
+
+        def fused():
+            M.fwd_bwd_l1(L, R, gt, mask8, Ds, Ks, n, r, eps, rs, tau, flags=flags, workspace=ws, outputs=fo)
+        ms = time_ms(torch, fused, steps, 2)
+        res[label] = {"fwd_bwd_ms": ms, "fwd_bwd_ms_per_pair": ms / count, "workspace_bytes": ws.numel(),
+                      "loss_pair0": float(fo[0]["loss"])}
+        if label == "fused_batched_graph":
+            M.timing_enable(True)
+            for _ in range(steps):
+                M.fwd_bwd_l1(L, R, gt, mask8, Ds, Ks, n, r, eps, rs, tau, flags=M.FLAG_BATCHED, workspace=ws,
+                             outputs=fo)
+            torch.cuda.synchronize()
+            tim = M.timing_read()
+            M.timing_enable(False)
+            res[label]["stages_us"] = {k: round(1e3 * v[0] / v[1], 2) for k, v in sorted(tim.items())}
+        del ws
     res["evals_per_batch_forward"] = evals
     res["fwd_bwd_speedup_batched_vs_plain"] = res["plain"]["fwd_bwd_ms"] / res["batched_graph"]["fwd_bwd_ms"]
+    res["fwd_bwd_speedup_fused_graph_vs_plain"] = res["plain"]["fwd_bwd_ms"] / res["fused_batched_graph"]["fwd_bwd_ms"]
     res["peak_hbm_bytes"] = torch.cuda.max_memory_allocated(dev) - base
     return res
 

@@ -146,13 +146,22 @@ const char* msibm_version(void);
  *      winners; four times the workgroups, a fraction of each thread's work
  *      (for small levels),
  *   8  fixed window (restricted searches whose whole candidate range, about
- *      D_k candidates, fits one staged chunk of 320): both tiles are staged
- *      at once before any prior is read, with no workgroup-wide range step.
- * Results do not depend on the shape.
+ *      D_k candidates, fits one staged chunk): both tiles are staged at once
+ *      before any prior is read, with no workgroup-wide range step,
+ *  16  short right chunk: the right tile is staged 48 (full search) or 128
+ *      (restricted search) candidates at a time instead of 96 or 320 (less
+ *      LDS per workgroup, more chunks where a tile's candidates spread),
+ *  32  tall tiles: 16 pixel rows and 8 waves per workgroup instead of 8 rows
+ *      and 4 waves (fewer halo rows staged per pixel row; not combined with
+ *      the candidate split, which keeps its 2-row tiles).
+ * Per thread the shapes score 4 pixel windows (a 2 x 2 block) at all of its
+ * candidates, or (candidate split) at a quarter of them.  Results do not
+ * depend on the shape.  The batched path uses the fixed window and the
+ * default chunk and tile height for every stage.
  *
  * msibm_force_variant - pin the shape for every later call in this process
  * (bits that do not apply to a launch are ignored); -1 restores the automatic
- * choice.  Errors: INVALID_ARG (outside -1..15).
+ * choice.  Errors: INVALID_ARG (outside -1..63).
  */
 msibm_status msibm_force_variant(int32_t variant);
 

@@ -55,7 +55,9 @@ constexpr int VARIANT_STATS_LDS = 1;  // right statistics staged in LDS (full se
 constexpr int VARIANT_XCD = 2;        // XCD-aware tile order
 constexpr int VARIANT_SPLIT = 4;      // full / restricted search: 2-row tiles, the 4 waves split the candidates
 constexpr int VARIANT_FIXW = 8;       // restricted search: stage the whole candidate range up front
-constexpr int VARIANT_MASK = 15;
+constexpr int VARIANT_SHORT = 16;     // short right chunk: 48 (full) or 128 (restricted) candidates
+constexpr int VARIANT_TALL = 32;      // 16-row tiles of 8 waves (not with the candidate split)
+constexpr int VARIANT_MASK = 63;
 
 // Tile of block b in a grid of gx x gy tiles.  The hardware deals consecutive
 // workgroups round-robin to the 8 XCDs, each with its own L2; the XCD-aware

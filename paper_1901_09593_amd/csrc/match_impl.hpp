@@ -51,9 +51,13 @@ namespace msibm {
 // blocks' windows are data dependent (occluded regions give scattered priors),
 // and with short chunks a wave whose blocks fall into several chunks would run
 // the window code once per chunk with most lanes idle.
-template <int MODE>
+//
+// A short chunk (the VARIANT_SHORT shape: 48 candidates for a full search, 128
+// for a restricted one) halves the right tile's LDS, so more workgroups fit a
+// CU, at the cost of more chunks per tile where the candidates spread.
+template <int MODE, bool SHORT = false>
 struct ChunkOf {
-    static constexpr int value = (MODE == MODE_FULL) ? 96 : 320;
+    static constexpr int value = (MODE == MODE_FULL) ? (SHORT ? 48 : 96) : (SHORT ? 128 : 320);
 };
 // The backward's LDS also holds gradient tiles beside the images; 112 candidates
 // keep a right row (128 + 2n + 111 columns) within two 128-column groups for
@@ -150,13 +154,13 @@ __device__ __forceinline__ void stage_tile(float* dst, int stride, int half, con
 // Both tiles of a fixed-window restricted search in one go: every load of the
 // left and the right tile is issued before the first LDS store, so the two
 // stagings share one memory latency.
-template <typename T, int ROWS, int LMAX, int RMAX>
+template <typename T, int ROWS, int LMAX, int RMAX, int NWAVES = MATCH_TY>
 __device__ __forceinline__ void stage_pair(float* ldst, int lstride, int lhalf, float* rdst, int rstride,
                                            int rhalf, const T* __restrict__ lsrc, const T* __restrict__ rsrc,
                                            int pitch, int H, int W, int gy0, int lx0, int lcols, int rx0,
                                            int rcols, float c)
 {
-    constexpr int RI = (ROWS + MATCH_TY - 1) / MATCH_TY;
+    constexpr int RI = (ROWS + NWAVES - 1) / NWAVES;
     constexpr int LI = (LMAX + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     constexpr int CI = (RMAX + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
@@ -165,7 +169,7 @@ __device__ __forceinline__ void stage_pair(float* ldst, int lstride, int lhalf, 
     T l0[RI][LI], l1[RI][LI], r0[RI][CI], r1[RI][CI];
 #pragma unroll
     for (int ri = 0; ri < RI; ++ri) {
-        const int rr = wave + MATCH_TY * ri;
+        const int rr = wave + NWAVES * ri;
         const size_t ro = (size_t)clampi(gy0 + rr, 0, H - 1) * pitch;
 #pragma unroll
         for (int ci = 0; ci < LI; ++ci) {
@@ -182,7 +186,7 @@ __device__ __forceinline__ void stage_pair(float* ldst, int lstride, int lhalf, 
     }
 #pragma unroll
     for (int ri = 0; ri < RI; ++ri) {
-        const int rr = wave + MATCH_TY * ri;
+        const int rr = wave + NWAVES * ri;
         if (rr >= ROWS) continue;
 #pragma unroll
         for (int ci = 0; ci < LI; ++ci)
@@ -205,19 +209,19 @@ __device__ __forceinline__ void stage_pair(float* ldst, int lstride, int lhalf, 
 // into two split-layout LDS planes: the window mean minus c (its float value and
 // rounding remainder summed after the subtraction) and 1/sd.  Same staging
 // scheme as stage_tile.
-template <int ROWS, int MAXCOLS>
+template <int ROWS, int MAXCOLS, int NWAVES = MATCH_TY>
 __device__ __forceinline__ void stage_stats(float* mc, float* is, int stride, int half,
                                             const WinStat* __restrict__ src, int spitch, int H, int W,
                                             int gy0, int gx0, int cols, float c)
 {
-    constexpr int RI = (ROWS + MATCH_TY - 1) / MATCH_TY;
+    constexpr int RI = (ROWS + NWAVES - 1) / NWAVES;
     constexpr int CI = (MAXCOLS + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
     const int groups = (cols + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     WinStat v0[RI][CI], v1[RI][CI];
 #pragma unroll
     for (int ri = 0; ri < RI; ++ri) {
-        const int rr = wave + MATCH_TY * ri;
+        const int rr = wave + NWAVES * ri;
         const WinStat* srow = src + (size_t)clampi(gy0 + rr, 0, H - 1) * spitch;
 #pragma unroll
         for (int ci = 0; ci < CI; ++ci) {
@@ -228,7 +232,7 @@ __device__ __forceinline__ void stage_stats(float* mc, float* is, int stride, in
     }
 #pragma unroll
     for (int ri = 0; ri < RI; ++ri) {
-        const int rr = wave + MATCH_TY * ri;
+        const int rr = wave + NWAVES * ri;
         if (rr >= ROWS) continue;
 #pragma unroll
         for (int ci = 0; ci < CI; ++ci) {
@@ -341,19 +345,24 @@ struct BlockState {
 // thread of the workgroup must call it (it synchronises the workgroup).
 // SL selects where the right statistics come from: staged in LDS with the right
 // tile (1), or read by each thread from global memory (0).
-template <int SPLIT>
+// Pixel rows of a tile: 2 for the candidate split, else one block row (two
+// pixel rows) per wave: 8 for the usual 4 waves, 16 for the tall shape (8 waves).
+template <int SPLIT, int TY = MATCH_TY>
 struct TileRows {
-    static constexpr int value = SPLIT ? 2 : TILE_H1;
+    static constexpr int value = SPLIT ? 2 : 2 * TY;
 };
 
-template <typename T, int NW, int NC, int MODE, int SPLIT, int SL, bool CV = false>
-__device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
-                                           MatchSmem<NW, ChunkOf<MODE>::value, TileRows<SPLIT>::value, SL>& sm)
+template <typename T, int NW, int NC, int MODE, int SPLIT, int SL, bool CV = false, int TY = MATCH_TY,
+          bool SHORT = false>
+__device__ __forceinline__ void match_tile(
+    const MatchArgs& a, int bx, int by,
+    MatchSmem<NW, ChunkOf<MODE, SHORT>::value, TileRows<SPLIT, TY>::value, SL>& sm)
 {
-    constexpr int CH = ChunkOf<MODE>::value;
+    constexpr int CH = ChunkOf<MODE, SHORT>::value;
     constexpr int BY = 1;
-    using G = Geo<NW, CH, TileRows<SPLIT>::value>;
+    using G = Geo<NW, CH, TileRows<SPLIT, TY>::value>;
     static_assert(!SPLIT || MODE != MODE_SOFT, "the soft level needs every slot of a block in one thread");
+    static_assert(!SPLIT || TY == MATCH_TY, "the candidate split combines the winners of four waves");
     constexpr float Nf = (float)((2 * NW + 1) * (2 * NW + 1));
     // A block of a restricted search scores the candidate slots [zs, zs + NCF).
     // Unsplit, that is one window of NC = NCF slots; split (RSPLIT), the span is
@@ -415,9 +424,10 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
             }
         }
     }
-    // right centring value: one pixel per 8-row band of tiles, whatever the tile
-    // height, so that every kernel shape rounds the scores identically
-    const int cy = min((y0 & ~(TILE_H1 - 1)) + TILE_H1 / 2, a.H - 1), cx = min(x0 + TILE_W / 2, a.W - 1);
+    // right centring value: one pixel per 16-row band of tiles, whatever the
+    // tile height (2, 8 or 16 rows), so that every kernel shape rounds the
+    // scores identically
+    const int cy = min((y0 & ~15) + 8, a.H - 1), cx = min(x0 + TILE_W / 2, a.W - 1);
     const float cR = to_f(Rg[(size_t)cy * a.pitch + cx]);
 
     // Fixed window (restricted searches whose whole candidate range fits one
@@ -428,13 +438,13 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
     const bool fixw = MODE != MODE_FULL && (a.variant & VARIANT_FIXW) && zhi_f - zlo_f + 1 <= STEP;
     if (fixw) {
         const int ztop = zhi_f + NCX - 1;
-        stage_pair<T, G::LROWS, G::LCOLS, G::RCOLS>(sm.Ls, G::LSTRIDE, G::LHALF, sm.Rs, G::RSTRIDE, G::RHALF, Lg,
-                                                    Rg, a.pitch, a.H, a.W, y0 - NW, x0 - NW, G::LCOLS,
-                                                    x0 - NW - ztop, TILE_W + 2 * NW + (ztop - zlo_f), cR);
+        stage_pair<T, G::LROWS, G::LCOLS, G::RCOLS, TY>(sm.Ls, G::LSTRIDE, G::LHALF, sm.Rs, G::RSTRIDE, G::RHALF,
+                                                        Lg, Rg, a.pitch, a.H, a.W, y0 - NW, x0 - NW, G::LCOLS,
+                                                        x0 - NW - ztop, TILE_W + 2 * NW + (ztop - zlo_f), cR);
     } else {
         // left tile (uncentred: each thread centres its own windows)
-        stage_tile<T, G::LROWS, G::LCOLS>(sm.Ls, G::LSTRIDE, G::LHALF, Lg, a.pitch, a.H, a.W, y0 - NW,
-                                          x0 - NW, G::LCOLS, 0.f);
+        stage_tile<T, G::LROWS, G::LCOLS, TY>(sm.Ls, G::LSTRIDE, G::LHALF, Lg, a.pitch, a.H, a.W, y0 - NW,
+                                              x0 - NW, G::LCOLS, 0.f);
     }
 
     // workgroup-wide candidate range; for a restricted search also the set of
@@ -489,11 +499,11 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
         const int ztop = min(zc + CH - 1, zhi + NCX - 1);
         if (zc != zlo) __syncthreads();  // previous chunk fully consumed
         if (!fixw)
-            stage_tile<T, G::LROWS, G::RCOLS>(sm.Rs, G::RSTRIDE, G::RHALF, Rg, a.pitch, a.H, a.W, y0 - NW,
-                                              x0 - NW - ztop, TILE_W + 2 * NW + (ztop - zc), cR);
+            stage_tile<T, G::LROWS, G::RCOLS, TY>(sm.Rs, G::RSTRIDE, G::RHALF, Rg, a.pitch, a.H, a.W, y0 - NW,
+                                                  x0 - NW - ztop, TILE_W + 2 * NW + (ztop - zc), cR);
         if (SL)
-            stage_stats<G::TH, G::SCOLS>(sm.Sm, sm.Si, G::SSTRIDE, G::SHALF, a.statR, a.spitch, a.H, a.W,
-                                         y0, x0 - ztop, TILE_W + (ztop - zc), cR);
+            stage_stats<G::TH, G::SCOLS, TY>(sm.Sm, sm.Si, G::SSTRIDE, G::SHALF, a.statR, a.spitch, a.H, a.W,
+                                             y0, x0 - ztop, TILE_W + (ztop - zc), cR);
         __syncthreads();
 
 #pragma unroll
@@ -643,13 +653,13 @@ __device__ __forceinline__ void match_tile(const MatchArgs& a, int bx, int by,
     __syncthreads();  // LDS may be reused by the caller's next tile
 }
 
-template <typename T, int NW, int NC, int MODE, int SPLIT, int SL>
-__global__ __launch_bounds__(MATCH_THREADS) void match_kernel(MatchArgs a)
+template <typename T, int NW, int NC, int MODE, int SPLIT, int SL, int TY = MATCH_TY, bool SHORT = false>
+__global__ __launch_bounds__(MATCH_TX * TY) void match_kernel(MatchArgs a)
 {
-    __shared__ MatchSmem<NW, ChunkOf<MODE>::value, TileRows<SPLIT>::value, SL> sm;
+    __shared__ MatchSmem<NW, ChunkOf<MODE, SHORT>::value, TileRows<SPLIT, TY>::value, SL> sm;
     int bx = blockIdx.x, by = blockIdx.y;
     tile_of(a.variant, &bx, &by);
-    match_tile<T, NW, NC, MODE, SPLIT, SL>(a, bx, by, sm);
+    match_tile<T, NW, NC, MODE, SPLIT, SL, false, TY, SHORT>(a, bx, by, sm);
 }
 
 // The same search writing every scored candidate's score to a.costvol (a
@@ -662,20 +672,36 @@ __global__ __launch_bounds__(MATCH_THREADS) void match_costvol_kernel(MatchArgs 
     match_tile<T, NW, NC, MODE, 0, 0, true>(a, blockIdx.x, blockIdx.y, sm);
 }
 
-template <typename T, int NW, int NC, int MODE, int SPLIT>
-static hipError_t launch_shape(const MatchArgs& a, hipStream_t s)
+template <typename T, int NW, int NC, int MODE, int SPLIT, int TY, bool SHORT>
+static hipError_t launch_shape_ts(const MatchArgs& a, hipStream_t s)
 {
-    constexpr int TH = TileRows<SPLIT>::value;
+    constexpr int TH = TileRows<SPLIT, TY>::value;
     dim3 grid((a.W + TILE_W - 1) / TILE_W, (a.H + TH - 1) / TH, 1);
     // statistics staged in LDS is a full-search shape only: a restricted search
     // reads a few statistics per pixel, and its wide right tile leaves no LDS for
     // them
     if (MODE == MODE_FULL && (a.variant & VARIANT_STATS_LDS))
-        hipLaunchKernelGGL((match_kernel<T, NW, NC, MODE, SPLIT, MODE == MODE_FULL ? 1 : 0>), grid,
-                           dim3(MATCH_THREADS), 0, s, a);
+        hipLaunchKernelGGL((match_kernel<T, NW, NC, MODE, SPLIT, MODE == MODE_FULL ? 1 : 0, TY, SHORT>), grid,
+                           dim3(MATCH_TX * TY), 0, s, a);
     else
-        hipLaunchKernelGGL((match_kernel<T, NW, NC, MODE, SPLIT, 0>), grid, dim3(MATCH_THREADS), 0, s, a);
+        hipLaunchKernelGGL((match_kernel<T, NW, NC, MODE, SPLIT, 0, TY, SHORT>), grid, dim3(MATCH_TX * TY), 0, s,
+                           a);
     return hipGetLastError();
+}
+
+// Tile height (the tall shape: 16 rows, 8 waves; not with the candidate split)
+// and chunk length from the variant bits.
+template <typename T, int NW, int NC, int MODE, int SPLIT>
+static hipError_t launch_shape(const MatchArgs& a, hipStream_t s)
+{
+    const bool shrt = (a.variant & VARIANT_SHORT) != 0;
+    if constexpr (!SPLIT) {
+        if (a.variant & VARIANT_TALL)
+            return shrt ? launch_shape_ts<T, NW, NC, MODE, SPLIT, 2 * MATCH_TY, true>(a, s)
+                        : launch_shape_ts<T, NW, NC, MODE, SPLIT, 2 * MATCH_TY, false>(a, s);
+    }
+    return shrt ? launch_shape_ts<T, NW, NC, MODE, SPLIT, MATCH_TY, true>(a, s)
+                : launch_shape_ts<T, NW, NC, MODE, SPLIT, MATCH_TY, false>(a, s);
 }
 
 // Slots per wave of a split restricted search: a quarter of the block's span,

@@ -176,10 +176,10 @@ int select_variant(const MatchArgs& a, int n, int dtype, int mode, int nc, hipSt
     // statistics in LDS: full search only; candidate split: full and restricted
     // (not soft) searches; fixed window: restricted searches whose candidate
     // range fits one staged chunk
-    const int valid = mode == MODE_FULL
-                          ? (VARIANT_STATS_LDS | VARIANT_XCD | VARIANT_SPLIT)
-                          : (VARIANT_XCD | (mode == MODE_REFINE ? VARIANT_SPLIT : 0) |
-                             (fixed_window_fits(a, nc) ? VARIANT_FIXW : 0));
+    const int valid = VARIANT_XCD | VARIANT_SHORT | VARIANT_TALL |
+                      (mode == MODE_FULL ? (VARIANT_STATS_LDS | VARIANT_SPLIT)
+                                         : ((mode == MODE_REFINE ? VARIANT_SPLIT : 0) |
+                                            (fixed_window_fits(a, nc) ? VARIANT_FIXW : 0)));
     if (t.forced >= 0) return t.forced & valid;
     const Key key(mode, n, nc, dtype, a.H, a.W, a.Dk);
     auto it = t.table.find(key);
@@ -196,6 +196,7 @@ int select_variant(const MatchArgs& a, int n, int dtype, int mode, int nc, hipSt
     for (int round = 0; round < 3; ++round)
         for (int v = 0; v <= VARIANT_MASK; ++v) {
             if (v & ~valid) continue;
+            if ((v & VARIANT_SPLIT) && (v & VARIANT_TALL)) continue;  // the split keeps 2-row tiles
             const float us = time_variant(a, v, n, dtype, mode, nc, s);
             if (us >= 0.f && (t_min[v] < 0.f || us < t_min[v])) t_min[v] = us;
         }

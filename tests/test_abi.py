@@ -215,7 +215,7 @@ def test_autotune_cache_parsing_from_host(lib, tmp_path):
     rows = msibm.autotune_table()
     assert (1, 4, 5, 0, 992, 1436, 256, 2) in [r[:8] for r in rows]
     assert e.msibm_autotune(0, None) == 0
-    assert e.msibm_force_variant(16) == -1 and e.msibm_force_variant(15) == 0 and e.msibm_force_variant(-1) == 0
+    assert e.msibm_force_variant(64) == -1 and e.msibm_force_variant(63) == 0 and e.msibm_force_variant(-1) == 0
 
 
 def test_header_is_plain_c_and_links(lib, tmp_path):

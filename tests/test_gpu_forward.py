@@ -411,8 +411,8 @@ def test_mid1436_flat_block_matching_full_size_sampled(M):
     1436x992 uint8 pair at full size, the comparison the benchmark times: the
     default kernel shape on sampled pixels (borders and the left strip where
     the candidate range is clipped included) against the oracle, and every
-    full-search shape (statistics in LDS, XCD order, candidate split) identical
-    to it."""
+    full-search shape (statistics in LDS, XCD order, candidate split, short
+    chunk, tall tiles) identical to it."""
     p, cfg = synth.workload("mid1436")
     n, D, eps = cfg.half_window, cfg.max_disp, cfg.var_eps
     Lg, Rg = dev(p.left), dev(p.right)
@@ -426,7 +426,7 @@ def test_mid1436_flat_block_matching_full_size_sampled(M):
     st = check_pixels(d, C, p.left, p.right, n, D, None, 0, eps, ii, jj)
     print("mid1436 flat block matching sampled", st)
     try:
-        for v in range(8):
+        for v in list(range(8)) + [16, 17, 19, 32, 33, 35, 48, 49, 51]:
             M.force_variant(v)
             dv, Cv = M.match_level(Lg, Rg, n, D, None, 0, eps)
             assert np.array_equal(host(dv), d) and np.array_equal(host(Cv), C), v
@@ -495,7 +495,7 @@ def test_soft_level_parity_diff960_crop(M):
                 ref=(dh_o, C_o, C2_o))
 
 
-@pytest.mark.parametrize("variant", list(range(16)))
+@pytest.mark.parametrize("variant", list(range(64)))
 def test_every_kernel_variant_gives_identical_results(M, variant):
     p, cfg = synth.workload("small320")
     K, n, r, D, eps = cfg.levels, cfg.half_window, cfg.refine_radius, cfg.max_disp, cfg.var_eps
@@ -516,7 +516,7 @@ def test_every_kernel_variant_gives_identical_results(M, variant):
 
 def test_restricted_shapes_identical_at_largest_range(M):
     """Every restricted-search shape (candidate split or not, fixed window or
-    chunked, tile order) gives the same maps and scores where the candidate
+    chunked, tile order, short chunk, tall tiles) gives the same maps and scores where the candidate
     range spans several chunks (D_k = 2048, r = 4, priors over the whole
     range)."""
     H, W, n, Dk, r = 20, 2100, 3, 2048, 4
@@ -526,7 +526,7 @@ def test_restricted_shapes_identical_at_largest_range(M):
     Lg, Rg = dev(p.left), dev(p.right)
     outs = []
     try:
-        for v in (0, 2, 4, 6, 8, 12, 14):
+        for v in (0, 2, 4, 6, 8, 12, 14, 16, 20, 24, 32, 40, 48, 56):
             M.force_variant(v)
             outs.append(M.match_level(Lg, Rg, n, Dk, prior, r, 0.065))
     finally:
@@ -557,7 +557,7 @@ def test_autotune_picks_per_shape_and_keeps_results(M, tmp_path):
     shapes = {(row[4], row[5]) for row in table}
     for k in range(K):
         assert (M.level_dim(240, k), M.level_dim(320, k)) in shapes
-    assert all(0 <= row[7] <= 15 and row[8] > 0 for row in table)
+    assert all(0 <= row[7] <= 63 and row[8] > 0 for row in table)
     # modes: one full search (mode 0) at the coarsest level, restricted below
     assert {row[0] for row in table} == {0, 1}
     lines = cache.read_text().splitlines()
