@@ -14,22 +14,30 @@
 // Flat candidates (1/sd = 0) get k1 = kL = kR = 0; clamped window reads send
 // their gradient to the edge pixel they read.
 //
-// Work split.  Same tiles and LDS staging as the forward matching kernel, with
-// 8 waves per workgroup: a thread owns one pixel row of a 2x2 block (two
-// pixels).  It recomputes their scores with window sums shared by the two
-// columns, then walks their window rows, sums both pixels' gradient values in
-// registers over the union of their windows and adds them into LDS gradient
-// tiles (the left tile and the current right chunk).  Finished tiles are added
-// to the global gradients with hardware float atomics (tiles overlap by their
-// window halos), so the global gradients must be zeroed first.  No cost volume
-// is stored: scores are recomputed from the images and window statistics.
+// Work split.  Same tiles (128 x 8 pixels) and LDS staging as the forward
+// matching kernel, 4 waves per workgroup: a thread owns a 2x2 pixel block.  It
+// recomputes the block's scores with the forward's window sums (products
+// shared by the four windows, so the soft disparities are the forward's bit for
+// bit), then walks the 2n+2 rows of the union of the block's windows: per row
+// it sums, in registers, every pixel's gradient value at each union column
+// (over the candidates and over the pixels whose window covers that cell) and
+// adds one value per cell into LDS gradient tiles (the left tile and the
+// current right chunk).  The first and last union rows are covered by one pixel
+// row, the others by both, so their coefficients are the sums of the two
+// rows' (formed once).  Finished tiles are added to the global gradients with
+// hardware float atomics (tiles overlap by their window halos), so the global
+// gradients must be zeroed first.  No cost volume is stored: scores are
+// recomputed from the images and window statistics.
 //
-// LDS accumulation is in 64-bit fixed point: integer LDS atomics are several
-// tens of times faster than float ones on this chip.  Per chunk the workgroup
-// bounds every value it will add (from the ranges of the staged images and the
-// largest gradient coefficients) and picks a power-of-two scale that maps that
-// bound below 2^30, so each added value becomes an int32 (truncated) with a
-// resolution of 2^-30 of the bound, and the 64-bit sums cannot overflow.
+// LDS accumulation is in 32-bit fixed point: integer LDS atomics are tens of
+// times faster than float ones on this chip, and 32-bit cells keep the four
+// tiles within 80 KB (two workgroups per CU for windows up to 11 x 11).  Per
+// chunk the workgroup bounds every value it will add (from the ranges of the
+// staged images and the largest gradient coefficients) and picks a
+// power-of-two scale that maps that bound below 2^23: each added value (at
+// most half the bound) becomes an integer (rounded) with a resolution of 2^-23
+// of the bound, and a cell, which receives at most one value per thread and
+// chunk (256), stays below 2^30.
 #pragma once
 
 #include "match_impl.hpp"
@@ -72,8 +80,8 @@ struct BackSmem {
     using G = Geo<NW, CH, TILE_H1>;
     float Ls[G::LROWS * G::LSTRIDE];
     float Rs[G::LROWS * G::RSTRIDE];
-    long long GLs[G::LROWS * G::LSTRIDE];  // left gradient tile (same layout as Ls), fixed point
-    long long GRs[G::LROWS * G::RSTRIDE];  // right gradient tile of the current chunk, fixed point
+    int GLs[G::LROWS * G::LSTRIDE];        // left gradient tile (same layout as Ls), fixed point
+    int GRs[G::LROWS * G::RSTRIDE];        // right gradient tile of the current chunk, fixed point
     int lo, hi;
     unsigned mask;
     int lmin, lmax, rmin, rmax;            // value ranges of the staged tiles (ordered float keys)
@@ -89,39 +97,44 @@ __device__ __forceinline__ int fkey(float f)
 }
 __device__ __forceinline__ float fval(int k) { return __int_as_float(k >= 0 ? k : k ^ 0x7fffffff); }
 
-constexpr int BACK_WAVES = 8;
+constexpr int BACK_WAVES = MATCH_TY;
 constexpr int BACK_THREADS = BACK_WAVES * MATCH_TX;
+// Fixed-point headroom: the chunk's bound is below 2^BACK_VBITS in cell units
+// and every value is at most half the bound; a cell receives at most one value
+// per thread and chunk.
+constexpr int BACK_VBITS = 23;
+static_assert((BACK_VBITS - 1) + 9 <= 31 && BACK_THREADS <= 512, "a cell's sum must fit an int32");
 
-// Add v (|v * scale| <= 2^30) to a fixed-point LDS cell, truncated toward zero:
-// an error below 2^-30 of the chunk's bound per value, far inside the gradient
-// tolerance, one instruction cheaper than rounding.  Zeros are added too: a
-// test per value costs more than the add.
-__device__ __forceinline__ void lds_add(long long* p, float v, float scale)
+// Add v (|v * scale| <= 2^22) to a fixed-point LDS cell, rounded to the
+// nearest integer: an error of at most 2^-24 of the chunk's bound per value,
+// unbiased, far inside the gradient tolerance.  Zeros are added too: a test
+// per value costs more than the add.
+__device__ __forceinline__ void lds_add(int* p, float v, float scale)
 {
-    atomicAdd((unsigned long long*)p, (unsigned long long)(long long)(int)(v * scale));
+    atomicAdd(p, __float2int_rn(v * scale));
 }
 
 // Add a fixed-point LDS tile in split layout to a global image with float
 // atomics (value = cell / scale); logical column c of LDS row rr maps to global
 // (clamp(gy0 + rr), clamp(gx0 + c)).  The tile is zeroed behind the reads.
-__device__ __forceinline__ void flush_tile(long long* tile, int stride, int half, int rows, int cols, double inv_scale,
+__device__ __forceinline__ void flush_tile(int* tile, int stride, int half, int rows, int cols, float inv_scale,
                                            float* dst, int dpitch, int H, int W, int gy0, int gx0)
 {
     const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
     for (int rr = wave; rr < rows; rr += BACK_WAVES) {
         float* drow = dst + (size_t)clampi(gy0 + rr, 0, H - 1) * dpitch;
         for (int c = lane; c < cols; c += MATCH_TX) {
-            long long* cell = tile + rr * stride + split_pos(c, half);
-            const long long v = *cell;
+            int* cell = tile + rr * stride + split_pos(c, half);
+            const int v = *cell;
             if (v != 0) {
-                unsafeAtomicAdd(drow + clampi(gx0 + c, 0, W - 1), (float)((double)v * inv_scale));
+                unsafeAtomicAdd(drow + clampi(gx0 + c, 0, W - 1), (float)v * inv_scale);
                 *cell = 0;
             }
         }
     }
 }
 
-__device__ __forceinline__ void zero_lds(long long* p, int count)
+__device__ __forceinline__ void zero_lds(int* p, int count)
 {
     for (int i = threadIdx.x; i < count; i += BACK_THREADS) p[i] = 0;
 }
@@ -142,30 +155,56 @@ __device__ __forceinline__ void tile_range(const float* t, int stride, int half,
     atomicMax(kmax, fkey(mx));
 }
 
-// Window cross sums of one pixel row's two pixels (columns j0, j0 + 1) for NC
-// candidate slots: per window row the products of the 2n interior columns are
-// shared by both pixels, plus one edge product each.  Same operands and
-// centring as the forward's block sums.
+// Gradient values of one union row of a 2x2 block's windows, added into the
+// LDS tiles.  The row is covered by the pixel rows whose coefficients were
+// summed into kl (per pixel column), cl, k1 (per pixel column and slot), qb
+// and qc (per union column of the right tile).  Left union column t is
+// covered by pixel column 0 for t <= WS - 1 and by column 1 for t >= 1; right
+// union column v pairs slot s with left union column v - (NC - 1 - s).
 template <int NW, int NC, class G>
-__device__ __forceinline__ void row_sums(const float* __restrict__ Ls, const float* __restrict__ Rs,
-                                         int lrow0, int ltx, int pa, int pb, float ca, float (&S)[2][NC])
+__device__ __forceinline__ void grad_row(const float* __restrict__ Ls, const float* __restrict__ Rs, int* GLs,
+                                         int* GRs, int row, int tx, int pa, int pb, float ca, const float (&kl)[2],
+                                         const float (&cl)[2], const float (&k1)[2][NC],
+                                         const float (&qb)[2 * NW + NC + 1], const float (&qc)[2 * NW + NC + 1],
+                                         float scale)
 {
-    constexpr int WN = G::WN;
+    constexpr int WS = 2 * NW + 1;
+    constexpr int RU = WS + NC - 1;  // right values one pixel column's window row touches
+    const float* lr_ = Ls + row * G::LSTRIDE + tx;
+    const float* rr_ = Rs + row * G::RSTRIDE;
+    int* glr = GLs + row * G::LSTRIDE + tx;
+    int* grr = GRs + row * G::RSTRIDE;
+    float l[WS + 1], r[RU + 1];
 #pragma unroll
-    for (int s = 0; s < NC; ++s) S[0][s] = S[1][s] = 0.f;
-#pragma unroll 1
-    for (int y = 0; y < WN - 1; ++y) {
-        float l[WN], r[WN + NC - 1];
-        load_row<NW, NC, G::LSTRIDE, G::LHALF, G::RSTRIDE>(Ls, Rs, lrow0 + y, ltx, pa, pb, ca, l, r);
+    for (int t = 0; t <= WS; ++t) l[t] = lr_[(t & 1) ? G::LHALF + (t >> 1) : (t >> 1)] - ca;
+#pragma unroll
+    for (int v = 0; v <= RU; ++v) r[v] = (v & 1) ? rr_[pb + (v >> 1)] : rr_[pa + (v >> 1)];
+#pragma unroll
+    for (int t = 0; t <= WS; ++t) {
+        const bool v0 = t <= WS - 1, v1 = t >= 1;
+        const float klt = (v0 && v1) ? kl[0] + kl[1] : (v0 ? kl[0] : kl[1]);
+        const float clt = (v0 && v1) ? cl[0] + cl[1] : (v0 ? cl[0] : cl[1]);
+        float acc = fmaf(-klt, l[t], clt);
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
-            const int o = NC - 1 - s;
-            float c = 0.f;
-#pragma unroll
-            for (int t = 1; t < WN - 1; ++t) c = fmaf(l[t], r[t + o], c);
-            S[0][s] += fmaf(l[0], r[o], c);
-            S[1][s] += fmaf(l[WN - 1], r[WN - 1 + o], c);
+            const float c = (v0 && v1) ? k1[0][s] + k1[1][s] : (v0 ? k1[0][s] : k1[1][s]);
+            acc = fmaf(c, r[t + NC - 1 - s], acc);
         }
+        lds_add(glr + ((t & 1) ? G::LHALF + (t >> 1) : (t >> 1)), acc, scale);
+    }
+#pragma unroll
+    for (int v = 0; v <= RU; ++v) {
+        float acc = fmaf(-qb[v], r[v], qc[v]);
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const int t = v - (NC - 1 - s);
+            const bool v0 = t >= 0 && t <= WS - 1, v1 = t >= 1 && t <= WS;
+            if (v0 || v1) {
+                const float c = (v0 && v1) ? k1[0][s] + k1[1][s] : (v0 ? k1[0][s] : k1[1][s]);
+                acc = fmaf(c, l[t], acc);
+            }
+        }
+        lds_add(grr + ((v & 1) ? pb + (v >> 1) : pa + (v >> 1)), acc, scale);
     }
 }
 
@@ -180,18 +219,19 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
     constexpr int RU = WS + NC - 1;         // right values a pixel's window row touches
     static_assert((MSIBM_MAX_DISP - 1) / STEP < 32, "chunk mask must hold every chunk");
 
-    const int tx = threadIdx.x & (MATCH_TX - 1), w = threadIdx.x / MATCH_TX;
-    const int ty = w >> 1, pr = w & 1;      // block row, pixel row within the block
+    const int tx = threadIdx.x & (MATCH_TX - 1), ty = threadIdx.x / MATCH_TX;  // block column and row
     const int x0 = bx * TILE_W, y0 = by * G::TH;
     const int i0 = y0 + 2 * ty, j0 = x0 + 2 * tx;
     const bool blk = i0 < a.H && j0 < a.W;  // the block has pixels
-    const int ii = min(i0 + pr, a.H - 1);
-    const bool act[2] = {i0 + pr < a.H && j0 < a.W, i0 + pr < a.H && j0 + 1 < a.W};
+    // pixel p = 2 * pr + pc: row i0 + pr, column j0 + pc (clamped for loads)
+    const int ip[2] = {min(i0, a.H - 1), min(i0 + 1, a.H - 1)};
     const int jp[2] = {min(j0, a.W - 1), min(j0 + 1, a.W - 1)};
+    bool act[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) act[p] = i0 + (p >> 1) < a.H && j0 + (p & 1) < a.W;
 
-    // candidate intervals (as in the forward soft level); both pixel rows of a
-    // block share the prior
-    const int dh = clampi(2 * (int)a.prior[(size_t)(min(i0, a.H - 1) >> 1) * a.ppitch + (jp[0] >> 1)], 0, a.D - 1);
+    // candidate intervals (as in the forward soft level); the block shares the prior
+    const int dh = clampi(2 * (int)a.prior[(size_t)(ip[0] >> 1) * a.ppitch + (jp[0] >> 1)], 0, a.D - 1);
     const int zs = (dh <= j0) ? dh - a.rs : j0 + 2 - NC;
     int lo[2], hi[2];
 #pragma unroll
@@ -200,7 +240,9 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
         lo[pc] = max(0, c - a.rs);
         hi[pc] = min(min(a.D - 1, jp[pc]), c + a.rs);
     }
-    const int cy = min(y0 + G::TH / 2, a.H - 1), cx = min(x0 + TILE_W / 2, a.W - 1);
+    // the forward's right centring (one pixel per 16-row band), so that the
+    // recomputed scores are the forward's
+    const int cy = min((y0 & ~15) + 8, a.H - 1), cx = min(x0 + TILE_W / 2, a.W - 1);
     const float cR = a.R[(size_t)cy * a.pitch + cx];
 
     stage_tile<float, G::LROWS, G::LCOLS, BACK_WAVES>(sm.Ls, G::LSTRIDE, G::LHALF, a.L, a.pitch, a.H, a.W,
@@ -247,8 +289,7 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
         }
         __syncthreads();
 
-        const bool part = blk && (act[0] || act[1]) && zs >= zc && zs < zc + STEP;
-        const float ca = a.statL[(size_t)ii * a.spitch + jp[0]].x;
+        const bool part = blk && zs >= zc && zs < zc + STEP;
         const int rcol0 = 2 * tx + (ztop - zs) - (NC - 1);
         // right-value base offsets (split layout) for logical column rcol0 + u
         int pa, pb;
@@ -259,42 +300,50 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
             pa = G::RHALF + (rcol0 >> 1);
             pb = (rcol0 + 1) >> 1;
         }
-        // per pixel: soft-argmax derivative and the gradient coefficients; the
-        // two pixels' right coefficients summed over the union of their windows
-        // (right offset u of pixel pc is union column u + pc)
-        float k1[2][NC], kl[2], cl[2], qb[RU + 1], qc[RU + 1];
+        // per pixel row pr: the gradient coefficients of its two pixels (left:
+        // kl, cl per pixel column, k1 per pixel column and slot) and the sums
+        // of its right coefficients over the union columns of its windows
+        // (right offset u of pixel column pc is union column u + pc)
+        float kl[2][2], cl[2][2], k1[2][2][NC], qb[2][RU + 1], qc[2][RU + 1];
 #pragma unroll
-        for (int u = 0; u <= RU; ++u) {
-            qb[u] = 0.f;
-            qc[u] = 0.f;
-        }
+        for (int pr = 0; pr < 2; ++pr) {
 #pragma unroll
-        for (int pc = 0; pc < 2; ++pc) {
-            kl[pc] = 0.f;
-            cl[pc] = 0.f;
-#pragma unroll
-            for (int s = 0; s < NC; ++s) k1[pc][s] = 0.f;
-        }
-        if (part) {
-            // statistics and upstream gradients of both pixels, loaded before the
-            // window sums so that their latency overlaps them
-            WinStat stl2[2], str2[2][NC];
-            float gpx2[2];
-            const WinStat* srow = a.statR + (size_t)ii * a.spitch;
+            for (int u = 0; u <= RU; ++u) {
+                qb[pr][u] = 0.f;
+                qc[pr][u] = 0.f;
+            }
 #pragma unroll
             for (int pc = 0; pc < 2; ++pc) {
-                stl2[pc] = a.statL[(size_t)ii * a.spitch + jp[pc]];
-                gpx2[pc] = FUSED ? a.gt[(size_t)ii * a.gpitch + jp[pc]] : a.g[(size_t)ii * a.gpitch + jp[pc]];
+                kl[pr][pc] = 0.f;
+                cl[pr][pc] = 0.f;
 #pragma unroll
-                for (int s = 0; s < NC; ++s) str2[pc][s] = srow[clampi(jp[pc] - (zs + s), 0, a.W - 1)];
+                for (int s = 0; s < NC; ++s) k1[pr][pc][s] = 0.f;
+            }
+        }
+        float ca = 0.f;
+        if (part) {
+            // left statistics and upstream gradients of the four pixels, loaded
+            // before the window sums so that their latency overlaps them (the
+            // right statistics are read per pixel below: holding all four
+            // pixels' would cost 12 NC registers)
+            WinStat stl4[4];
+            float gpx4[4];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const size_t o = (size_t)ip[p >> 1] * a.spitch + jp[p & 1];
+                stl4[p] = a.statL[o];
+                gpx4[p] = FUSED ? a.gt[(size_t)ip[p >> 1] * a.gpitch + jp[p & 1]]
+                                : a.g[(size_t)ip[p >> 1] * a.gpitch + jp[p & 1]];
             }
             asm volatile("" ::: "memory");  // keep the loads ahead of the window sums
-            float S[2][NC];
-            row_sums<NW, NC, G>(sm.Ls, sm.Rs, 2 * ty + pr, tx, pa, pb, ca, S);
+            ca = stl4[0].x;                 // the block's windows are centred on its first pixel's mean
+            float S[4][NC];
+            window_sums<NW, NC, G>(sm.Ls, sm.Rs, 2 * ty, tx, rcol0, ca, S);
 #pragma unroll
-            for (int pc = 0; pc < 2; ++pc) {
-                if (!act[pc]) continue;  // contributes nothing
-                const WinStat stl = stl2[pc];
+            for (int p = 0; p < 4; ++p) {
+                if (!act[p]) continue;  // contributes nothing
+                const int pr = p >> 1, pc = p & 1;
+                const WinStat stl = stl4[p];
                 const float dl = (stl.x - ca) + stl.y;  // mu_l - ca
                 const float invl = stl.z;
                 // right statistics of this pixel's candidates: column jp - z
@@ -302,13 +351,17 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
                 bool ok[NC];
                 float best = -3.f;
                 int bz = 0;
+                const WinStat* srow = a.statR + (size_t)ip[pr] * a.spitch;
+#pragma unroll
+                for (int s = 0; s < NC; ++s) {
+                    const WinStat st = srow[clampi(jp[pc] - (zs + s), 0, a.W - 1)];
+                    mr[s] = (st.x - cR) + st.y;  // mu_r - cR
+                    invr[s] = st.z;
+                }
 #pragma unroll
                 for (int s = 0; s < NC; ++s) {
                     const int z = zs + s;
-                    const WinStat st = str2[pc][s];
-                    mr[s] = (st.x - cR) + st.y;  // mu_r - cR
-                    invr[s] = st.z;
-                    const float C = fmaf(-Nf * dl, mr[s], S[pc][s]);
+                    const float C = fmaf(-Nf * dl, mr[s], S[p][s]);
                     float rr = C * invl * invr[s];
                     rr = fminf(fmaxf(rr, -1.f), 1.f);
                     ok[s] = (z >= lo[pc]) && (z <= hi[pc]);
@@ -326,11 +379,11 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
                     sz = fmaf(e[s], (float)(zs + s), sz);
                 }
                 const float ds = sz / se;
-                float gpx = gpx2[pc];
+                float gpx = gpx4[p];
                 if (FUSED) {
                     // the soft level's outputs, and the masked-L1 gradient of
                     // this pixel: sign(d_soft - gt) / |M| on M
-                    const size_t o = (size_t)ii * a.gpitch + jp[pc];
+                    const size_t o = (size_t)ip[pr] * a.gpitch + jp[pc];
                     a.soft_out[o] = ds;
                     a.d_out[o] = (int16_t)bz;
                     if (a.c_out) a.c_out[o] = best;
@@ -340,50 +393,51 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
                     if (m) lsum += fabsf(diff);
                 }
                 const float gs = gpx * a.inv_tau / se;
-                float k2r[NC], klp = 0.f, clp = 0.f;
+                float klp = 0.f, clp = 0.f;
 #pragma unroll
                 for (int s = 0; s < NC; ++s) {
                     const float gz = gs * e[s] * ((float)(zs + s) - ds);
-                    k1[pc][s] = gz * invl * invr[s];
-                    const float kls = gz * rho[s] * invl * invl;
-                    k2r[s] = gz * rho[s] * invr[s] * invr[s];
-                    klp += kls;
-                    clp = fmaf(-k1[pc][s], mr[s], clp);
-                }
-                kl[pc] = klp;
-                cl[pc] = fmaf(klp, dl, clp);
+                    const float k1s = gz * invl * invr[s];
+                    k1[pr][pc][s] = k1s;
+                    klp += gz * rho[s] * invl * invl;
+                    clp = fmaf(-k1s, mr[s], clp);
+                    // slot s pairs right offset u with window column u - (NC - 1 - s):
+                    // its right coefficients reach offsets NC - 1 - s .. NC - 2 - s + WS
+                    const float k2r = gz * rho[s] * invr[s] * invr[s];
+                    const float cq = fmaf(k2r, mr[s], -k1s * dl);
 #pragma unroll
-                for (int u = 0; u < RU; ++u) {
-#pragma unroll
-                    for (int s = 0; s < NC; ++s) {
-                        const int b = u - (NC - 1 - s);
-                        if (b >= 0 && b < WS) {
-                            qb[u + pc] += k2r[s];
-                            qc[u + pc] += fmaf(k2r[s], mr[s], -k1[pc][s] * dl);
-                        }
+                    for (int u = NC - 1 - s; u < NC - 1 - s + WS; ++u) {
+                        qb[pr][u + pc] += k2r;
+                        qc[pr][u + pc] += cq;
                     }
                 }
+                kl[pr][pc] = klp;
+                cl[pr][pc] = fmaf(klp, dl, clp);
             }
         }
-        float k1s[NC], k1a = 0.f;
+        // bounds of every value a cell receives: the coefficient magnitudes of
+        // all four pixels together cover any one union row's combination
+        float ka = 0.f, kla = 0.f, cla = 0.f, qba = 0.f, qca = 0.f;
 #pragma unroll
-        for (int s = 0; s < NC; ++s) {
-            k1s[s] = k1[0][s] + k1[1][s];
-            k1a += fabsf(k1[0][s]) + fabsf(k1[1][s]);
-        }
-        const float kls = kl[0] + kl[1], cls = cl[0] + cl[1];
-        float qba = 0.f, qca = 0.f;
+        for (int pr = 0; pr < 2; ++pr)
+#pragma unroll
+            for (int pc = 0; pc < 2; ++pc) {
+                kla += fabsf(kl[pr][pc]);
+                cla += fabsf(cl[pr][pc]);
+#pragma unroll
+                for (int s = 0; s < NC; ++s) ka += fabsf(k1[pr][pc][s]);
+            }
 #pragma unroll
         for (int u = 0; u <= RU; ++u) {
-            qba = fmaxf(qba, fabsf(qb[u]));
-            qca = fmaxf(qca, fabsf(qc[u]));
+            qba = fmaxf(qba, fabsf(qb[0][u]) + fabsf(qb[1][u]));
+            qca = fmaxf(qca, fabsf(qc[0][u]) + fabsf(qc[1][u]));
         }
         // workgroup maxima of the coefficient magnitudes and the right range
         tile_range(sm.Rs, G::RSTRIDE, G::RHALF, G::LROWS, rcols, &sm.rmin, &sm.rmax);
         if (part) {
-            atomicMax(&sm.kmax[0], __float_as_uint(fabsf(kl[0]) + fabsf(kl[1])));
-            atomicMax(&sm.kmax[1], __float_as_uint(fabsf(cl[0]) + fabsf(cl[1])));
-            atomicMax(&sm.kmax[2], __float_as_uint(k1a));
+            atomicMax(&sm.kmax[0], __float_as_uint(kla));
+            atomicMax(&sm.kmax[1], __float_as_uint(cla));
+            atomicMax(&sm.kmax[2], __float_as_uint(ka));
             atomicMax(&sm.kmax[3], __float_as_uint(qba));
             atomicMax(&sm.kmax[4], __float_as_uint(qca));
         }
@@ -399,57 +453,34 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
         int be = 0;
         frexpf(bound, &be);  // bound < 2^be
         // (at most 2^100, a finite float, for vanishing bounds)
-        const int sh = (bound > 0.f && isfinite(bound)) ? min(30 - be, 100) : 0;
+        const int sh = (bound > 0.f && isfinite(bound)) ? min(BACK_VBITS - be, 100) : 0;
         const float scale = ldexpf(1.f, sh);
-        const double inv_scale = ldexp(1.0, -sh);
+        const float inv_scale = ldexpf(1.f, -sh);
 
         if (part && bound > 0.f && isfinite(bound)) {
-            // window rows of the pixel row
-#pragma unroll 1
-            for (int y = 0; y < WS; ++y) {
-                const int row = 2 * ty + pr + y;
-                const float* lr_ = sm.Ls + row * G::LSTRIDE + tx;
-                const float* rr_ = sm.Rs + row * G::RSTRIDE;
-                long long* glr = sm.GLs + row * G::LSTRIDE + tx;
-                long long* grr = sm.GRs + row * G::RSTRIDE;
-                float l[WS + 1], r[RU + 1];
+            // union row 0: the upper pixel row only; the last one: the lower
+            // pixel row only; the rows between: both (coefficients summed once)
+            const int row0 = 2 * ty;
+            grad_row<NW, NC, G>(sm.Ls, sm.Rs, sm.GLs, sm.GRs, row0, tx, pa, pb, ca, kl[0], cl[0], k1[0], qb[0], qc[0],
+                                scale);
+            grad_row<NW, NC, G>(sm.Ls, sm.Rs, sm.GLs, sm.GRs, row0 + WS, tx, pa, pb, ca, kl[1], cl[1], k1[1], qb[1],
+                                qc[1], scale);
 #pragma unroll
-                for (int t = 0; t <= WS; ++t) l[t] = lr_[(t & 1) ? G::LHALF + (t >> 1) : (t >> 1)] - ca;
+            for (int pc = 0; pc < 2; ++pc) {
+                kl[0][pc] += kl[1][pc];
+                cl[0][pc] += cl[1][pc];
 #pragma unroll
-                for (int v = 0; v <= RU; ++v) r[v] = (v & 1) ? rr_[pb + (v >> 1)] : rr_[pa + (v >> 1)];
-                // left gradient at union column t: pixel 0 covers t <= WS - 1,
-                // pixel 1 covers t >= 1 (compile-time choices once unrolled)
-#pragma unroll
-                for (int t = 0; t <= WS; ++t) {
-                    const bool v0 = t <= WS - 1, v1 = t >= 1;
-                    const float klt = (v0 && v1) ? kls : (v0 ? kl[0] : kl[1]);
-                    const float clt = (v0 && v1) ? cls : (v0 ? cl[0] : cl[1]);
-                    float acc = fmaf(-klt, l[t], clt);
-#pragma unroll
-                    for (int s = 0; s < NC; ++s) {
-                        const float c = (v0 && v1) ? k1s[s] : (v0 ? k1[0][s] : k1[1][s]);
-                        acc = fmaf(c, r[t + NC - 1 - s], acc);
-                    }
-                    lds_add(glr + ((t & 1) ? G::LHALF + (t >> 1) : (t >> 1)), acc, scale);
-                }
-                // right gradient at union column v: slot s pairs it with left union
-                // column v - (NC - 1 - s), which pixel pc covers when that column
-                // lies in [pc, WS - 1 + pc]
-#pragma unroll
-                for (int v = 0; v <= RU; ++v) {
-                    float acc = fmaf(-qb[v], r[v], qc[v]);
-#pragma unroll
-                    for (int s = 0; s < NC; ++s) {
-                        const int t = v - (NC - 1 - s);
-                        const bool v0 = t >= 0 && t <= WS - 1, v1 = t >= 1 && t <= WS;
-                        if (v0 || v1) {
-                            const float c = (v0 && v1) ? k1s[s] : (v0 ? k1[0][s] : k1[1][s]);
-                            acc = fmaf(c, l[t], acc);
-                        }
-                    }
-                    lds_add(grr + ((v & 1) ? pb + (v >> 1) : pa + (v >> 1)), acc, scale);
-                }
+                for (int s = 0; s < NC; ++s) k1[0][pc][s] += k1[1][pc][s];
             }
+#pragma unroll
+            for (int u = 0; u <= RU; ++u) {
+                qb[0][u] += qb[1][u];
+                qc[0][u] += qc[1][u];
+            }
+#pragma unroll 1
+            for (int y = 1; y < WS; ++y)
+                grad_row<NW, NC, G>(sm.Ls, sm.Rs, sm.GLs, sm.GRs, row0 + y, tx, pa, pb, ca, kl[0], cl[0], k1[0],
+                                    qb[0], qc[0], scale);
         }
         __syncthreads();
         // both tiles carry this chunk's scale: flush (and clear) them now
@@ -473,7 +504,7 @@ __device__ __forceinline__ void backward_tile(const BackArgs& a, int bx, int by,
 }
 
 template <int NW, int NC, bool FUSED>
-__global__ __launch_bounds__(BACK_THREADS) void backward_kernel(BackArgs a)
+__global__ __launch_bounds__(BACK_THREADS, 2) void backward_kernel(BackArgs a)
 {
     __shared__ BackSmem<NW, BACK_CHUNK> sm;
     backward_tile<NW, NC, FUSED>(a, blockIdx.x, blockIdx.y, sm);
@@ -504,7 +535,7 @@ static hipError_t dispatch_backward(int nc, const BackArgs& a, hipStream_t s)
 
 // Backward tiles of several pairs in one launch (level 0 of each pair).
 template <int NW, int NC, bool FUSED>
-__global__ __launch_bounds__(BACK_THREADS) void backward_multi_kernel(MultiArgs a)
+__global__ __launch_bounds__(BACK_THREADS, 2) void backward_multi_kernel(MultiArgs a)
 {
     __shared__ BackSmem<NW, BACK_CHUNK> sm;
     const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
@@ -524,7 +555,7 @@ struct BackLevels {
 };
 
 template <int NW, int NC>
-__global__ __launch_bounds__(BACK_THREADS) void backward_levels_kernel(BackLevels a)
+__global__ __launch_bounds__(BACK_THREADS, 2) void backward_levels_kernel(BackLevels a)
 {
     __shared__ BackSmem<NW, BACK_CHUNK> sm;
     int i = 0;

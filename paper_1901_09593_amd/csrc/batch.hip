@@ -104,6 +104,10 @@ static Segment make_seg(int type, int p, int k, int h, int w, int dtype, int tas
         s.tiles_x = (int)(((size_t)h * w + ZERO_TILE - 1) / ZERO_TILE);
         s.tiles_y = 1;
         s.views = 1;
+    } else if (type == SEG_COUNT) {
+        s.tiles_x = (int)(((size_t)h * w + COUNT_TILE - 1) / COUNT_TILE);
+        s.tiles_y = 1;
+        s.views = 1;
     } else {
         s.tiles_x = cdiv(w, TILE_W);
         s.tiles_y = cdiv(h, TILE_H1);
@@ -277,7 +281,7 @@ static void add_pair_stage(const msibm_pair* pairs, int np, int kind, int type, 
 static void plan_fused_stages(const msibm_pair* pairs, int np, const msibm_config* cfg, BatchPlan& pl)
 {
     add_pair_stage(pairs, np, STAGE_ZERO, SEG_ZERO, pl);
-    add_pair_stage(pairs, np, STAGE_COUNT, SEG_ZERO, pl);
+    add_pair_stage(pairs, np, STAGE_COUNT, SEG_COUNT, pl);
     plan_stages(pairs, np, cfg, pl, 1);
     add_pair_stage(pairs, np, STAGE_FUSED, SEG_BACKWARD, pl);
     StageLaunch fin{};

@@ -172,7 +172,7 @@ struct ConvertArgs {
 
 enum SegType {
     SEG_REDUCE = 0, SEG_STATS = 1, SEG_FULL = 2, SEG_REFINE = 3, SEG_SOFT = 4, SEG_ZERO = 5, SEG_BACKWARD = 6,
-    SEG_MEDIAN = 7, SEG_GATE = 8
+    SEG_MEDIAN = 7, SEG_GATE = 8, SEG_COUNT = 9
 };
 
 struct BackArgs;
@@ -229,6 +229,8 @@ constexpr int MD_W = 64, MD_H = 4;
 
 // Floats a zero-fill tile clears in each gradient (256 threads x 16).
 constexpr int ZERO_TILE = 4096;
+// Mask bytes a loss-count workgroup sums (256 threads x 16 bytes x 16 steps).
+constexpr int COUNT_TILE = 65536;
 
 // Segment of launch block b: binary search over the launch's segment table
 // (block-uniform, so it runs on the scalar unit).
