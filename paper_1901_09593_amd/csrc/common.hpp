@@ -30,6 +30,15 @@ struct WinStat {
     float x, y, z;
 };
 
+// Window statistics of a uint8 level, written in place of WinStat (the same
+// buffers, 8 bytes per pixel at the same row pitch in records): the window sum
+// S1 (an integer below 2^24, exact in float) and 1/sqrt(A), 0 for a flat
+// window.  With uint8 values every window sum of products is an exact
+// integer too, so the cross term is formed exactly as C N = N S - S1_l S1_r.
+struct WinStatU8 {
+    float s1, z;
+};
+
 struct MatchArgs {
     const void* L;
     const void* R;

@@ -193,9 +193,16 @@ __device__ __forceinline__ void gate_tile(const GateArgs& a, int bx, int by)
         nmul[q] = 0.0;
         isl[q] = 0.f;
         if (in) {
-            const WinStat st = a.statL[(size_t)yy * a.spitch + xx];
-            nmul[q] = NN * ((double)st.x + (double)st.y);
-            isl[q] = st.z;
+            const size_t o = (size_t)yy * a.spitch + xx;
+            if constexpr (std::is_same<T, uint8_t>::value) {
+                const WinStatU8 st = reinterpret_cast<const WinStatU8*>(a.statL)[o];  // N mu_l = S1_l
+                nmul[q] = (double)st.s1;
+                isl[q] = st.z;
+            } else {
+                const WinStat st = a.statL[o];
+                nmul[q] = NN * ((double)st.x + (double)st.y);
+                isl[q] = st.z;
+            }
         }
     }
     // neighbours of an owned pixel inside the image: rows, and columns at or
@@ -230,13 +237,19 @@ __device__ __forceinline__ void gate_tile(const GateArgs& a, int bx, int by)
     // candidate (read from global memory: one new value per candidate)
     double rmu[RUN];
     float ris[RUN];
-    const WinStat* srow = a.statR + (size_t)clampi(ry0 + sy, 0, H - 1) * a.spitch;
-    WinStat nxt{};
+    // (uint8 levels: records of the exact window sum, mu_r = S1_r / N)
+    using SR = typename std::conditional<std::is_same<T, uint8_t>::value, WinStatU8, WinStat>::type;
+    const SR* srow = reinterpret_cast<const SR*>(a.statR) + (size_t)clampi(ry0 + sy, 0, H - 1) * a.spitch;
+    auto mean_of = [](const SR& st) -> double {
+        if constexpr (std::is_same<SR, WinStatU8>::value) return (double)st.s1 * (1.0 / NN);
+        else return (double)st.x + (double)st.y;
+    };
+    SR nxt{};
     if (scorer) {
 #pragma unroll
         for (int q = 0; q < RUN; ++q) {
-            const WinStat st = srow[clampi(rx0 + su + q, 0, W - 1)];
-            rmu[q] = (double)st.x + (double)st.y;
+            const SR st = srow[clampi(rx0 + su + q, 0, W - 1)];
+            rmu[q] = mean_of(st);
             ris[q] = st.z;
         }
     }
@@ -288,7 +301,7 @@ __device__ __forceinline__ void gate_tile(const GateArgs& a, int bx, int by)
                             rmu[q] = rmu[q - 1];
                             ris[q] = ris[q - 1];
                         }
-                        rmu[0] = (double)nxt.x + (double)nxt.y;
+                        rmu[0] = mean_of(nxt);
                         ris[0] = nxt.z;
                     }
                     nxt = srow[clampi(rx0 + su - (zu + 1), 0, W - 1)];

@@ -380,8 +380,9 @@ __device__ __forceinline__ void stats_tile(const T* __restrict__ srcA, WinStat* 
     }
 }
 
-// Statistics of one 32 x 64 tile of both views of a uint8 level: the same
-// quantities as stats_tile, from exact integer window sums.
+// Statistics of one 32 x 64 tile of both views of a uint8 level, from exact
+// integer window sums: the window sum S1 and 1/sqrt(A) as WinStatU8 records
+// (8 bytes per pixel, written into the statistics buffer at the same pitch).
 template <int NW>
 __device__ __forceinline__ void stats_tile_u8(const uint8_t* __restrict__ srcA, WinStat* __restrict__ dstA,
                                               const uint8_t* __restrict__ srcB, WinStat* __restrict__ dstB, int H,
@@ -482,9 +483,9 @@ __device__ __forceinline__ void stats_tile_u8(const uint8_t* __restrict__ srcA, 
                 const double d1 = (double)s1, d2 = (double)s2;
                 const double A = d2 - d1 * d1 * invN;
                 const float inv = (A <= N * var_eps) ? 0.f : rsqrtf((float)A);
-                const double mu = (double)c + d1 * invN;
-                const float hi = (float)mu;
-                dst[(size_t)gy * dpitch + gx] = WinStat{hi, (float)(mu - (double)hi), inv};
+                // the window sum of the uncentred values, an exact integer
+                reinterpret_cast<WinStatU8*>(dst)[(size_t)gy * dpitch + gx] =
+                    WinStatU8{(float)(s1 + wn * wn * c), inv};
             }
         }
         __syncthreads();  // LDS is reused by the next view and the caller's next tile

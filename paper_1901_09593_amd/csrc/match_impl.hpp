@@ -36,7 +36,11 @@
 //   C = sum (l - a)(r - cR) - N (mu_l - a)(mu_r - cR)
 // cancels little; the window means carry their float rounding remainder so
 // (mu - a) and (mu - cR) keep their low bits.  rho = C * invsd_l * invsd_r,
-// clamped to [-1, 1].
+// clamped to [-1, 1].  uint8 levels need none of this: staged as they are,
+// every product is an integer up to 255^2 and every window sum of products an
+// integer below 2^24, exact in float, so with the exact window sums S1 of the
+// statistics the cross term is formed exactly, N C = N S - S1_l S1_r (in
+// double), and only the final products round.
 #pragma once
 
 #include <type_traits>
@@ -209,11 +213,47 @@ __device__ __forceinline__ void stage_pair(float* ldst, int lstride, int lhalf, 
 // into two split-layout LDS planes: the window mean minus c (its float value and
 // rounding remainder summed after the subtraction) and 1/sd.  Same staging
 // scheme as stage_tile.
-template <int ROWS, int MAXCOLS, int NWAVES = MATCH_TY>
+template <int ROWS, int MAXCOLS, int NWAVES = MATCH_TY, bool U8 = false>
 __device__ __forceinline__ void stage_stats(float* mc, float* is, int stride, int half,
                                             const WinStat* __restrict__ src, int spitch, int H, int W,
                                             int gy0, int gx0, int cols, float c)
 {
+    if constexpr (U8) {
+        // uint8 level: the exact window sum S1 and 1/sd
+        constexpr int RI = (ROWS + NWAVES - 1) / NWAVES;
+        constexpr int CI = (MAXCOLS + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
+        const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
+        const int groups = (cols + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
+        const WinStatU8* s8 = reinterpret_cast<const WinStatU8*>(src);
+        WinStatU8 v0[RI][CI], v1[RI][CI];
+#pragma unroll
+        for (int ri = 0; ri < RI; ++ri) {
+            const int rr = wave + NWAVES * ri;
+            const WinStatU8* srow = s8 + (size_t)clampi(gy0 + rr, 0, H - 1) * spitch;
+#pragma unroll
+            for (int ci = 0; ci < CI; ++ci) {
+                const int cc = 2 * (lane + MATCH_TX * ci);
+                v0[ri][ci] = srow[clampi(gx0 + min(cc, cols - 1), 0, W - 1)];
+                v1[ri][ci] = srow[clampi(gx0 + min(cc + 1, cols - 1), 0, W - 1)];
+            }
+        }
+#pragma unroll
+        for (int ri = 0; ri < RI; ++ri) {
+            const int rr = wave + NWAVES * ri;
+            if (rr >= ROWS) continue;
+#pragma unroll
+            for (int ci = 0; ci < CI; ++ci) {
+                if (ci < groups) {
+                    const int ch = lane + MATCH_TX * ci;
+                    mc[rr * stride + ch] = v0[ri][ci].s1;
+                    is[rr * stride + ch] = v0[ri][ci].z;
+                    mc[rr * stride + half + ch] = v1[ri][ci].s1;
+                    is[rr * stride + half + ch] = v1[ri][ci].z;
+                }
+            }
+        }
+        return;
+    }
     constexpr int RI = (ROWS + NWAVES - 1) / NWAVES;
     constexpr int CI = (MAXCOLS + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
@@ -249,7 +289,7 @@ __device__ __forceinline__ void stage_stats(float* mc, float* is, int stride, in
 
 // One window row: load the block's 2n+2 left values (centred by ca) and
 // 2n+1+NC right values.
-template <int NW, int NC, int LSTRIDE, int LHALF, int RSTRIDE>
+template <int NW, int NC, int LSTRIDE, int LHALF, int RSTRIDE, bool CENTRE = true>
 __device__ __forceinline__ void load_row(const float* __restrict__ Ls, const float* __restrict__ Rs,
                                          int row, int ltx, int pa, int pb, float ca,
                                          float (&l)[2 * NW + 2], float (&r)[2 * NW + 1 + NC])
@@ -257,7 +297,10 @@ __device__ __forceinline__ void load_row(const float* __restrict__ Ls, const flo
     const float* lr_ = Ls + row * LSTRIDE + ltx;
     const float* rr_ = Rs + row * RSTRIDE;
 #pragma unroll
-    for (int t = 0; t < 2 * NW + 2; ++t) l[t] = lr_[(t & 1) ? LHALF + (t >> 1) : (t >> 1)] - ca;
+    for (int t = 0; t < 2 * NW + 2; ++t) {
+        l[t] = lr_[(t & 1) ? LHALF + (t >> 1) : (t >> 1)];
+        if constexpr (CENTRE) l[t] -= ca;
+    }
 #pragma unroll
     for (int u = 0; u < 2 * NW + 1 + NC; ++u) r[u] = (u & 1) ? rr_[pb + (u >> 1)] : rr_[pa + (u >> 1)];
 }
@@ -272,7 +315,9 @@ __device__ __forceinline__ void load_row(const float* __restrict__ Ls, const flo
 // Rows 1..2n feed both pixel rows (accumulated once: MC for the columns both
 // pixel columns share, M0/M1 for each column's extra edge column); row 0 feeds
 // only the upper pixels and row 2n+1 only the lower ones.
-template <int NW, int NC, class G>
+// CENTRE = false (uint8 levels): the values are used as staged, uncentred;
+// every product and sum is then an exact integer below 2^24.
+template <int NW, int NC, class G, bool CENTRE = true>
 __device__ __forceinline__ void window_sums(const float* __restrict__ Ls, const float* __restrict__ Rs,
                                             int lrow0, int ltx, int rcol0, float ca, float (&S)[4][NC])
 {
@@ -289,7 +334,7 @@ __device__ __forceinline__ void window_sums(const float* __restrict__ Ls, const 
     float l[WN], r[WN + NC - 1];
     float MC[NC], M0[NC], M1[NC];
     // first row: upper pixels only
-    load_row<NW, NC, G::LSTRIDE, G::LHALF, G::RSTRIDE>(Ls, Rs, lrow0, ltx, pa, pb, ca, l, r);
+    load_row<NW, NC, G::LSTRIDE, G::LHALF, G::RSTRIDE, CENTRE>(Ls, Rs, lrow0, ltx, pa, pb, ca, l, r);
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
         const int o = NC - 1 - s;  // slot s pairs column t with right value t + o
@@ -303,7 +348,7 @@ __device__ __forceinline__ void window_sums(const float* __restrict__ Ls, const 
     // shared rows
 #pragma unroll 2
     for (int y = 1; y < WN - 1; ++y) {
-        load_row<NW, NC, G::LSTRIDE, G::LHALF, G::RSTRIDE>(Ls, Rs, lrow0 + y, ltx, pa, pb, ca, l, r);
+        load_row<NW, NC, G::LSTRIDE, G::LHALF, G::RSTRIDE, CENTRE>(Ls, Rs, lrow0 + y, ltx, pa, pb, ca, l, r);
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
             const int o = NC - 1 - s;
@@ -316,7 +361,7 @@ __device__ __forceinline__ void window_sums(const float* __restrict__ Ls, const 
         }
     }
     // last row: lower pixels only
-    load_row<NW, NC, G::LSTRIDE, G::LHALF, G::RSTRIDE>(Ls, Rs, lrow0 + WN - 1, ltx, pa, pb, ca, l, r);
+    load_row<NW, NC, G::LSTRIDE, G::LHALF, G::RSTRIDE, CENTRE>(Ls, Rs, lrow0 + WN - 1, ltx, pa, pb, ca, l, r);
 #pragma unroll
     for (int s = 0; s < NC; ++s) {
         const int o = NC - 1 - s;
@@ -428,7 +473,9 @@ __device__ __forceinline__ void match_tile(
     // tile height (2, 8 or 16 rows), so that every kernel shape rounds the
     // scores identically
     const int cy = min((y0 & ~15) + 8, a.H - 1), cx = min(x0 + TILE_W / 2, a.W - 1);
-    const float cR = to_f(Rg[(size_t)cy * a.pitch + cx]);
+    // (uint8 levels are not centred: their sums are exact integers)
+    constexpr bool U8 = std::is_same<T, uint8_t>::value;
+    const float cR = U8 ? 0.f : to_f(Rg[(size_t)cy * a.pitch + cx]);
 
     // Fixed window (restricted searches whose whole candidate range fits one
     // chunk): every block's slots lie in [zlo_f, zhi_f], so both tiles are
@@ -502,8 +549,8 @@ __device__ __forceinline__ void match_tile(
             stage_tile<T, G::LROWS, G::RCOLS, TY>(sm.Rs, G::RSTRIDE, G::RHALF, Rg, a.pitch, a.H, a.W, y0 - NW,
                                                   x0 - NW - ztop, TILE_W + 2 * NW + (ztop - zc), cR);
         if (SL)
-            stage_stats<G::TH, G::SCOLS, TY>(sm.Sm, sm.Si, G::SSTRIDE, G::SHALF, a.statR, a.spitch, a.H, a.W,
-                                             y0, x0 - ztop, TILE_W + (ztop - zc), cR);
+            stage_stats<G::TH, G::SCOLS, TY, U8>(sm.Sm, sm.Si, G::SSTRIDE, G::SHALF, a.statR, a.spitch, a.H,
+                                                 a.W, y0, x0 - ztop, TILE_W + (ztop - zc), cR);
         __syncthreads();
 
 #pragma unroll
@@ -520,25 +567,37 @@ __device__ __forceinline__ void match_tile(
                 w_last = (q.zs >= zc && q.zs < zc + STEP) ? q.zs + NCX - NC : q.zs - 1;
             }
             if (w_first > w_last) continue;
-            // left statistics; the block's left windows are centred on its
-            // first pixel's window mean
-            WinStat stl[4];
-            stl[0] = a.statL[(size_t)q.ia * a.spitch + q.ja];
-            stl[1] = a.statL[(size_t)q.ia * a.spitch + q.jb];
-            stl[2] = a.statL[(size_t)q.ib * a.spitch + q.ja];
-            stl[3] = a.statL[(size_t)q.ib * a.spitch + q.jb];
-            const float ca = stl[0].x;
+            // left statistics.  Float levels: the block's left windows are
+            // centred on its first pixel's window mean, ndl = -N (mu_l - ca).
+            // uint8 levels: ndl = -S1_l (the exact window sum), invl = 1/(sd N)
+            const size_t lo0 = (size_t)q.ia * a.spitch, lo1 = (size_t)q.ib * a.spitch;
+            const size_t so[4] = {lo0 + q.ja, lo0 + q.jb, lo1 + q.ja, lo1 + q.jb};
+            float ca = 0.f;
             float ndl[4], invl[4];
+            if constexpr (U8) {
+                const WinStatU8* s8 = reinterpret_cast<const WinStatU8*>(a.statL);
 #pragma unroll
-            for (int p = 0; p < 4; ++p) {
-                ndl[p] = -Nf * ((stl[p].x - ca) + stl[p].y);
-                invl[p] = stl[p].z;
+                for (int p = 0; p < 4; ++p) {
+                    const WinStatU8 st = s8[so[p]];
+                    ndl[p] = -st.s1;
+                    invl[p] = st.z * (1.f / Nf);
+                }
+            } else {
+                WinStat stl[4];
+#pragma unroll
+                for (int p = 0; p < 4; ++p) stl[p] = a.statL[so[p]];
+                ca = stl[0].x;
+#pragma unroll
+                for (int p = 0; p < 4; ++p) {
+                    ndl[p] = -Nf * ((stl[p].x - ca) + stl[p].y);
+                    invl[p] = stl[p].z;
+                }
             }
             const int lrow0 = 2 * tyb + TILE_H1 * b;
             for (int wz = w_first + (SPLIT ? ty * NC : 0); wz <= w_last; wz += NC * (SPLIT ? MATCH_TY : 1)) {
                 float S[4][NC];
                 const int rcol0 = 2 * tx + (ztop - wz) - (NC - 1);
-                window_sums<NW, NC, G>(sm.Ls, sm.Rs, lrow0, tx, rcol0, ca, S);
+                window_sums<NW, NC, G, !U8>(sm.Ls, sm.Rs, lrow0, tx, rcol0, ca, S);
                 // right statistics of columns c0 - q, q = 0..NC (c0 = the centre
                 // of pixel column j0 + 1 at slot 0): pixel column cp at slot s is
                 // q = s + 1 - cp
@@ -547,12 +606,13 @@ __device__ __forceinline__ void match_tile(
                 const int bo = (c0 & 1) ? (c0 >> 1) : G::SHALF + (c0 >> 1) - 1;  // q odd
                 // right statistics from global memory: every load of the window
                 // issued before the first use, so they share one latency
-                WinStat stg[2][SL ? 1 : NC + 1];
+                using SR = typename std::conditional<U8, WinStatU8, WinStat>::type;
+                SR stg[2][SL ? 1 : NC + 1];
                 if (!SL) {
 #pragma unroll
                     for (int rowp = 0; rowp < 2; ++rowp) {
                         // columns j0 + 1 - wz - q of pixel row ia or ib
-                        const WinStat* srow = a.statR + (size_t)(rowp ? q.ib : q.ia) * a.spitch;
+                        const SR* srow = reinterpret_cast<const SR*>(a.statR) + (size_t)(rowp ? q.ib : q.ia) * a.spitch;
 #pragma unroll
                         for (int qq = 0; qq <= NC; ++qq) stg[rowp][SL ? 0 : qq] = srow[clampi(j0 + 1 - wz - qq, 0, a.W - 1)];
                     }
@@ -572,8 +632,12 @@ __device__ __forceinline__ void match_tile(
                     } else {
 #pragma unroll
                         for (int qq = 0; qq <= NC; ++qq) {
-                            const WinStat st = stg[rowp][SL ? 0 : qq];
-                            smc[qq] = (st.x - cR) + st.y;
+                            const SR st = stg[rowp][SL ? 0 : qq];
+                            if constexpr (U8) {
+                                smc[qq] = st.s1;
+                            } else {
+                                smc[qq] = (st.x - cR) + st.y;
+                            }
                             sis[qq] = st.z;
                         }
                     }
@@ -584,7 +648,13 @@ __device__ __forceinline__ void match_tile(
                         for (int s = 0; s < NC; ++s) {
                             const int z = wz + s;
                             const int qq = s + 1 - cp;
-                            const float C = fmaf(ndl[p], smc[qq], S[p][s]);
+                            float C;
+                            if constexpr (U8) {
+                                // C N = N S - S1_l S1_r, exact in double (integers below 2^53)
+                                C = (float)fma((double)ndl[p], (double)smc[qq], (double)Nf * (double)S[p][s]);
+                            } else {
+                                C = fmaf(ndl[p], smc[qq], S[p][s]);
+                            }
                             float rho = C * invl[p] * sis[qq];
                             rho = fminf(fmaxf(rho, -1.f), 1.f);
                             const bool ok = (z >= q.lo[p]) && (z <= q.hi[p]);
