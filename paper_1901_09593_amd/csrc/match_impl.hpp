@@ -119,10 +119,80 @@ __device__ __forceinline__ int split_pos(int c, int half) { return (c & 1) ? hal
 // columns past `cols` re-read the last staged column, and only the groups that
 // hold staged columns are stored (a wave-uniform test).  A half holds whole
 // groups, and columns past `cols` are never read.
+// uint8 rows read as 32-bit words: lane l of group q takes the 4 columns
+// 4 (l + 64 q) .. + 3 of each row as one byte-aligned window of two aligned
+// words (the row's byte offset within a word is the same for every lane), and
+// writes them, as floats, to the even and odd halves.  The caller guarantees
+// that every row's columns [gx0 - 4, gx0 + cols + 8) are inside the image, so
+// no read is clamped; lanes past `cols` re-read the last word group and store
+// nothing (columns past `cols` are never read, and a stored pair index stays
+// below `half`).  Loads are all issued before the first store.
+template <int ROWS, int MAXCOLS, int NWAVES>
+struct RowWordsU8 {
+    static constexpr int RI = (ROWS + NWAVES - 1) / NWAVES;
+    static constexpr int QI = (MAXCOLS + 4 * MATCH_TX - 1) / (4 * MATCH_TX);
+    uint32_t w0[RI][QI], w1[RI][QI];
+    uint32_t sh[RI];
+
+    __device__ __forceinline__ void load(const uint8_t* __restrict__ src, int pitch, int H, int gy0, int gx0,
+                                         int cols)
+    {
+        const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
+        const int last = (cols - 1) & ~3;
+#pragma unroll
+        for (int ri = 0; ri < RI; ++ri) {
+            const int rr = wave + NWAVES * ri;
+            const uintptr_t a = reinterpret_cast<uintptr_t>(src + (size_t)clampi(gy0 + rr, 0, H - 1) * pitch + gx0);
+            sh[ri] = (uint32_t)(a & 3);
+            const uint32_t* wp = reinterpret_cast<const uint32_t*>(a & ~(uintptr_t)3);
+#pragma unroll
+            for (int qi = 0; qi < QI; ++qi) {
+                const int col = min(4 * (lane + MATCH_TX * qi), last);
+                w0[ri][qi] = wp[col >> 2];
+                w1[ri][qi] = wp[(col >> 2) + 1];
+            }
+        }
+    }
+
+    __device__ __forceinline__ void store(float* dst, int stride, int half, int cols) const
+    {
+        const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
+#pragma unroll
+        for (int ri = 0; ri < RI; ++ri) {
+            const int rr = wave + NWAVES * ri;
+            if (rr >= ROWS) continue;
+            float* drow = dst + rr * stride;
+#pragma unroll
+            for (int qi = 0; qi < QI; ++qi) {
+                const int m = lane + MATCH_TX * qi;
+                if (4 * m < cols) {
+                    const uint32_t w = __builtin_amdgcn_alignbyte(w1[ri][qi], w0[ri][qi], sh[ri]);
+                    drow[2 * m] = (float)(w & 0xffu);
+                    drow[2 * m + 1] = (float)((w >> 16) & 0xffu);
+                    drow[half + 2 * m] = (float)((w >> 8) & 0xffu);
+                    drow[half + 2 * m + 1] = (float)(w >> 24);
+                }
+            }
+        }
+    }
+};
+
+// Whether rows of a uint8 image may be staged with RowWordsU8 (no clamped column).
+__device__ __forceinline__ bool words_inside(int gx0, int cols, int W) { return gx0 >= 4 && gx0 + cols + 8 <= W; }
+
 template <typename T, int ROWS, int MAXCOLS, int NWAVES = MATCH_TY>
 __device__ __forceinline__ void stage_tile(float* dst, int stride, int half, const T* __restrict__ src,
                                            int pitch, int H, int W, int gy0, int gx0, int cols, float c)
 {
+    if constexpr (std::is_same<T, uint8_t>::value) {
+        // uint8 levels are staged uncentred (c = 0)
+        if (words_inside(gx0, cols, W)) {
+            RowWordsU8<ROWS, MAXCOLS, NWAVES> rw;
+            rw.load(src, pitch, H, gy0, gx0, cols);
+            rw.store(dst, stride, half, cols);
+            return;
+        }
+    }
     constexpr int RI = (ROWS + NWAVES - 1) / NWAVES;
     constexpr int CI = (MAXCOLS + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
@@ -164,6 +234,18 @@ __device__ __forceinline__ void stage_pair(float* ldst, int lstride, int lhalf, 
                                            int pitch, int H, int W, int gy0, int lx0, int lcols, int rx0,
                                            int rcols, float c)
 {
+    if constexpr (std::is_same<T, uint8_t>::value) {
+        // uint8 levels are staged uncentred (c = 0)
+        if (words_inside(lx0, lcols, W) && words_inside(rx0, rcols, W)) {
+            RowWordsU8<ROWS, LMAX, NWAVES> lw;
+            RowWordsU8<ROWS, RMAX, NWAVES> rw;
+            lw.load(lsrc, pitch, H, gy0, lx0, lcols);
+            rw.load(rsrc, pitch, H, gy0, rx0, rcols);
+            lw.store(ldst, lstride, lhalf, lcols);
+            rw.store(rdst, rstride, rhalf, rcols);
+            return;
+        }
+    }
     constexpr int RI = (ROWS + NWAVES - 1) / NWAVES;
     constexpr int LI = (LMAX + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     constexpr int CI = (RMAX + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
@@ -724,7 +806,7 @@ __device__ __forceinline__ void match_tile(
 }
 
 template <typename T, int NW, int NC, int MODE, int SPLIT, int SL, int TY = MATCH_TY, bool SHORT = false>
-__global__ __launch_bounds__(MATCH_TX * TY) void match_kernel(MatchArgs a)
+__global__ __launch_bounds__(MATCH_TX * TY, (MODE == MODE_REFINE && NC <= 7) ? 3 : 1) void match_kernel(MatchArgs a)
 {
     __shared__ MatchSmem<NW, ChunkOf<MODE, SHORT>::value, TileRows<SPLIT, TY>::value, SL> sm;
     int bx = blockIdx.x, by = blockIdx.y;
@@ -831,7 +913,7 @@ static hipError_t dispatch_match(int dtype, int mode, int nc, const MatchArgs& a
 // Matching of several (pair, level) segments of one mode and element type in
 // one launch: the level's arguments come from its pair's level descriptors.
 template <typename T, int NW, int NC, int MODE, int SL>
-__global__ __launch_bounds__(MATCH_THREADS) void match_multi_kernel(MultiArgs a)
+__global__ __launch_bounds__(MATCH_THREADS, (MODE == MODE_REFINE && NC <= 7) ? 3 : 1) void match_multi_kernel(MultiArgs a)
 {
     __shared__ MatchSmem<NW, ChunkOf<MODE>::value, TILE_H1, SL> sm;
     const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
