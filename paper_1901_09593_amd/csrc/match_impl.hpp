@@ -198,15 +198,27 @@ __device__ __forceinline__ void stage_tile(float* dst, int stride, int half, con
     const int lane = threadIdx.x & (MATCH_TX - 1), wave = threadIdx.x / MATCH_TX;
     const int groups = (cols + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     T v0[RI][CI], v1[RI][CI];
+    // rows whose columns all lie inside the image need no column clamp
+    const bool inside = gx0 >= 0 && gx0 + cols <= W;
 #pragma unroll
     for (int ri = 0; ri < RI; ++ri) {
         const int rr = wave + NWAVES * ri;
         const T* srow = src + (size_t)clampi(gy0 + rr, 0, H - 1) * pitch;
+        if (inside) {
+            const T* sp = srow + gx0;
 #pragma unroll
-        for (int ci = 0; ci < CI; ++ci) {
-            const int cc = 2 * (lane + MATCH_TX * ci);
-            v0[ri][ci] = srow[clampi(gx0 + min(cc, cols - 1), 0, W - 1)];
-            v1[ri][ci] = srow[clampi(gx0 + min(cc + 1, cols - 1), 0, W - 1)];
+            for (int ci = 0; ci < CI; ++ci) {
+                const int cc = 2 * (lane + MATCH_TX * ci);
+                v0[ri][ci] = sp[min(cc, cols - 1)];
+                v1[ri][ci] = sp[min(cc + 1, cols - 1)];
+            }
+        } else {
+#pragma unroll
+            for (int ci = 0; ci < CI; ++ci) {
+                const int cc = 2 * (lane + MATCH_TX * ci);
+                v0[ri][ci] = srow[clampi(gx0 + min(cc, cols - 1), 0, W - 1)];
+                v1[ri][ci] = srow[clampi(gx0 + min(cc + 1, cols - 1), 0, W - 1)];
+            }
         }
     }
 #pragma unroll
@@ -253,21 +265,40 @@ __device__ __forceinline__ void stage_pair(float* ldst, int lstride, int lhalf, 
     const int lgroups = (lcols + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     const int rgroups = (rcols + 2 * MATCH_TX - 1) / (2 * MATCH_TX);
     T l0[RI][LI], l1[RI][LI], r0[RI][CI], r1[RI][CI];
+    // rows whose columns all lie inside the image need no column clamp
+    const bool inside = lx0 >= 0 && lx0 + lcols <= W && rx0 >= 0 && rx0 + rcols <= W;
 #pragma unroll
     for (int ri = 0; ri < RI; ++ri) {
         const int rr = wave + NWAVES * ri;
         const size_t ro = (size_t)clampi(gy0 + rr, 0, H - 1) * pitch;
+        if (inside) {
+            const T* lp = lsrc + ro + lx0;
+            const T* rp = rsrc + ro + rx0;
 #pragma unroll
-        for (int ci = 0; ci < LI; ++ci) {
-            const int cc = 2 * (lane + MATCH_TX * ci);
-            l0[ri][ci] = lsrc[ro + clampi(lx0 + min(cc, lcols - 1), 0, W - 1)];
-            l1[ri][ci] = lsrc[ro + clampi(lx0 + min(cc + 1, lcols - 1), 0, W - 1)];
-        }
+            for (int ci = 0; ci < LI; ++ci) {
+                const int cc = 2 * (lane + MATCH_TX * ci);
+                l0[ri][ci] = lp[min(cc, lcols - 1)];
+                l1[ri][ci] = lp[min(cc + 1, lcols - 1)];
+            }
 #pragma unroll
-        for (int ci = 0; ci < CI; ++ci) {
-            const int cc = 2 * (lane + MATCH_TX * ci);
-            r0[ri][ci] = rsrc[ro + clampi(rx0 + min(cc, rcols - 1), 0, W - 1)];
-            r1[ri][ci] = rsrc[ro + clampi(rx0 + min(cc + 1, rcols - 1), 0, W - 1)];
+            for (int ci = 0; ci < CI; ++ci) {
+                const int cc = 2 * (lane + MATCH_TX * ci);
+                r0[ri][ci] = rp[min(cc, rcols - 1)];
+                r1[ri][ci] = rp[min(cc + 1, rcols - 1)];
+            }
+        } else {
+#pragma unroll
+            for (int ci = 0; ci < LI; ++ci) {
+                const int cc = 2 * (lane + MATCH_TX * ci);
+                l0[ri][ci] = lsrc[ro + clampi(lx0 + min(cc, lcols - 1), 0, W - 1)];
+                l1[ri][ci] = lsrc[ro + clampi(lx0 + min(cc + 1, lcols - 1), 0, W - 1)];
+            }
+#pragma unroll
+            for (int ci = 0; ci < CI; ++ci) {
+                const int cc = 2 * (lane + MATCH_TX * ci);
+                r0[ri][ci] = rsrc[ro + clampi(rx0 + min(cc, rcols - 1), 0, W - 1)];
+                r1[ri][ci] = rsrc[ro + clampi(rx0 + min(cc + 1, rcols - 1), 0, W - 1)];
+            }
         }
     }
 #pragma unroll
