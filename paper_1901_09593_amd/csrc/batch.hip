@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void zero_multi_kernel(MultiArgs a)
 
 // Tiles of one level: reduce tiles cover one view each, statistics and
 // matching tiles both.
-static Segment make_seg(int type, int p, int k, int h, int w, int dtype, int task0)
+static Segment make_seg(int type, int p, int k, int h, int w, int dtype, int task0, int n = 0, int gmode = 0)
 {
     Segment s{};
     s.type = type;
@@ -93,7 +93,7 @@ static Segment make_seg(int type, int p, int k, int h, int w, int dtype, int tas
         s.tiles_y = cdiv(h, stats_tile_h(dtype));
         s.views = 1;
     } else if (type == SEG_GATE) {
-        s.tiles_x = cdiv(w, GATE_TW);
+        s.tiles_x = cdiv(w, gate_tile_w(dtype, n, gmode));
         s.tiles_y = cdiv(h, GATE_TH);
         s.views = 1;
     } else if (type == SEG_MEDIAN) {
@@ -159,7 +159,8 @@ static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg
     };
     auto add = [&](int type, int p, int k) {
         StageLaunch& l = pl.launches.back();
-        const Segment s = make_seg(type, p, k, h_of(p, k), w_of(p, k), dtype_at(p, k), l.blocks);
+        const Segment s =
+            make_seg(type, p, k, h_of(p, k), w_of(p, k), dtype_at(p, k), l.blocks, level_n(cfg, k), l.mode);
         l.blocks += seg_tiles(s);
         l.nseg++;
         pl.segs.push_back(s);

@@ -182,7 +182,14 @@ __device__ __forceinline__ void gate_tile(const GateArgs& a, int bx, int by)
     }
 
     // left statistics of the scored region pixels (N mu_l, 1/sqrt(A_l))
+    // uint8 levels: N C = N S - S1_l S1_r exactly in 32-bit integers (up to
+    // 15x15 windows every factor is an integer below 2^24, both products fit
+    // 32 unsigned bits and their difference, N^2 times a covariance of bytes,
+    // lies within +-2^31), so the left window sum is kept as an integer and
+    // 1/sd is scaled by 1/N
+    constexpr bool U8 = std::is_same<T, uint8_t>::value;
     double nmul[RUN];
+    unsigned s1l[RUN];
     float isl[RUN];
     int sxa[RUN];     // region pixel column, or -1 outside the image
 #pragma unroll
@@ -191,13 +198,14 @@ __device__ __forceinline__ void gate_tile(const GateArgs& a, int bx, int by)
         const bool in = scorer && su + q < RC && yy >= 0 && yy < H && xx >= 0 && xx < W;
         sxa[q] = in ? xx : -1;
         nmul[q] = 0.0;
+        s1l[q] = 0u;
         isl[q] = 0.f;
         if (in) {
             const size_t o = (size_t)yy * a.spitch + xx;
             if constexpr (std::is_same<T, uint8_t>::value) {
                 const WinStatU8 st = reinterpret_cast<const WinStatU8*>(a.statL)[o];  // N mu_l = S1_l
-                nmul[q] = (double)st.s1;
-                isl[q] = st.z;
+                s1l[q] = (unsigned)st.s1;
+                isl[q] = st.z * (float)(1.0 / NN);
             } else {
                 const WinStat st = a.statL[o];
                 nmul[q] = NN * ((double)st.x + (double)st.y);
@@ -236,6 +244,7 @@ __device__ __forceinline__ void gate_tile(const GateArgs& a, int bx, int by)
     // right window means and 1/sqrt(A) of the scored run at the current
     // candidate (read from global memory: one new value per candidate)
     double rmu[RUN];
+    unsigned s1r[RUN];  // uint8 levels: the right window sums of the run
     float ris[RUN];
     // (uint8 levels: records of the exact window sum, mu_r = S1_r / N)
     using SR = typename std::conditional<std::is_same<T, uint8_t>::value, WinStatU8, WinStat>::type;
@@ -249,7 +258,8 @@ __device__ __forceinline__ void gate_tile(const GateArgs& a, int bx, int by)
 #pragma unroll
         for (int q = 0; q < RUN; ++q) {
             const SR st = srow[clampi(rx0 + su + q, 0, W - 1)];
-            rmu[q] = mean_of(st);
+            if constexpr (U8) s1r[q] = (unsigned)st.s1;
+            else rmu[q] = mean_of(st);
             ris[q] = st.z;
         }
     }
@@ -298,10 +308,12 @@ __device__ __forceinline__ void gate_tile(const GateArgs& a, int bx, int by)
                     if (zu > 0) {
 #pragma unroll
                         for (int q = RUN - 1; q > 0; --q) {
-                            rmu[q] = rmu[q - 1];
+                            if constexpr (U8) s1r[q] = s1r[q - 1];
+                            else rmu[q] = rmu[q - 1];
                             ris[q] = ris[q - 1];
                         }
-                        rmu[0] = mean_of(nxt);
+                        if constexpr (U8) s1r[0] = (unsigned)nxt.s1;
+                        else rmu[0] = mean_of(nxt);
                         ris[0] = nxt.z;
                     }
                     nxt = srow[clampi(rx0 + su - (zu + 1), 0, W - 1)];
@@ -320,7 +332,12 @@ __device__ __forceinline__ void gate_tile(const GateArgs& a, int bx, int by)
                         // rounding (relative 6e-8) is far below the score
                         // tolerance
                         const bool valid = sxa[q] >= zu && zu <= zend;
-                        const float c = (float)fma(-nmul[q], rmu[q], (double)sr);
+                        float c;
+                        if constexpr (U8) {
+                            c = (float)(int)(__umul24((unsigned)NN, (unsigned)sr) - __umul24(s1l[q], s1r[q]));
+                        } else {
+                            c = (float)fma(-nmul[q], rmu[q], (double)sr);
+                        }
                         const float e = valid ? fminf(1.f, fmaxf(-1.f, c * isl[q] * ris[q])) : 0.f;
                         ev[q] = e;
                         if constexpr (FUSED) {
@@ -412,17 +429,418 @@ __device__ __forceinline__ void gate_tile(const GateArgs& a, int bx, int by)
     }
 }
 
-template <typename T, int NW, int MODE>
-__global__ __launch_bounds__(GT_THREADS) void gate_kernel(GateArgs a)
+// ---- uint8 levels ---------------------------------------------------------
+//
+// On a uint8 level every product, window sum and cross term is an integer, so
+// the three sums per candidate are formed in 32-bit integers:
+//  * column pass (lanes 128..255, one column of the extended region each):
+//    the left column is held packed four rows to a word and the right column
+//    is staged in LDS the same way, so one v_dot4_u32_u8 adds four row
+//    products; prefix sums down the column give every (2n+1)-row sum as the
+//    difference of two prefixes.
+//  * row pass (16 lanes per region row, 8 region columns each): a sliding
+//    (2n+1)-column sum of the column sums gives S, and N C = N S - S1_l S1_r
+//    is exact (every factor below 2^24, the difference within +-2^31 up to
+//    13x13 windows); the score is N C * (invsd_l / N) * invsd_r clamped to
+//    [-1, 1].  The re-pick's 5-column sums of the scores take the next lane's
+//    first four scores across the 16-lane row with a DPP shift.
+//  * box pass (re-pick; one output column and four output rows per lane):
+//    five-row sums of the 5-column sums.
+// Two barriers per candidate: [row pass z] then [column pass z + 1, box pass
+// z].  Candidates up to x0 - 2 (x0 for the plain fallback search) lie left of
+// every region pixel and leave every output's neighbour count at its full
+// value, so they run without the per-pixel candidate checks.
+constexpr int GU_EW = GATE_U8_EW;  // extended-region columns
+constexpr int GU_RUN = 8;          // region columns a row-pass lane scores
+constexpr int GU_ZC = 32;          // candidates per staged right chunk
+constexpr int GU_VP = 144;         // LDS row pitch of the column and 5-column sums (16 mod 32 banks)
+
+// LDS index of region column u in a row of sums: one pad word per 8 columns,
+// so the 16 runs of a row start on 16 distinct banks and the next row's on
+// the other 16.
+__host__ __device__ constexpr int gu_idx(int u) { return u + (u >> 3); }
+
+// S1_r (an integer) and invsd_r of a uint8 window as one 64-bit register pair.
+__device__ __forceinline__ uint64_t pack_stat(const WinStatU8& st)
 {
-    gate_tile<T, NW, MODE>(a, blockIdx.x, blockIdx.y);
+    return ((uint64_t)__float_as_uint(st.z) << 32) | (uint32_t)(int)st.s1;
+}
+
+// Lane i of each 16-lane row takes lane i + 1's value (0 past the row's end).
+__device__ __forceinline__ float next_lane_in_row(float x)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x101, 0xf, 0xf, true));
+}
+
+template <int NW, int MODE>
+__device__ __forceinline__ void gate_tile_u8(const GateArgs& a, int bx, int by)
+{
+    constexpr bool REPICK = MODE != GATE_FULL;
+    constexpr bool FUSED = MODE == GATE_FUSED;
+    constexpr int HB = REPICK ? 2 : 0;            // halo of the averaged scores
+    constexpr int TH = GATE_TH;
+    constexpr int RR = TH + 2 * HB;               // region rows
+    constexpr int ER = RR + 2 * NW;               // extended rows
+    constexpr int RW = GU_EW - 2 * NW;            // region columns
+    constexpr int TW = RW - 2 * HB;               // tile columns
+    constexpr int NWORD = (ER + 3) / 4;           // packed 4-row words per column
+    constexpr int CP = NWORD | 1;                 // staged column pitch in words (odd: distinct banks)
+    // (each staged word is held as its first 1, 2, 3 and 4 rows, 16 bytes)
+    constexpr int RSC = GU_EW + GU_ZC - 1;        // staged right columns per chunk
+    constexpr int VREAD = GU_RUN + 2 * NW;        // column sums a run reads
+    constexpr int NN = (2 * NW + 1) * (2 * NW + 1);
+    // all 16 runs of a row are scored (uniform lanes); runs past the region
+    // read past its column sums and their scores are discarded
+    constexpr int VTAIL = gu_idx(GU_RUN * 15 + VREAD - 1) + 1 - GU_VP;
+    static_assert(RW <= 16 * GU_RUN && RR * 16 <= 256 && TW <= 128 && gu_idx(GU_EW - 1) < GU_VP && VTAIL > 0,
+                  "tile shape");
+    static_assert(TW == gate_tile_w(MSIBM_U8, NW, MODE), "host tile width");
+
+    __shared__ uint4 RsT[RSC * CP];
+    __shared__ int Vs[RR * GU_VP + VTAIL];
+    __shared__ float Hs[REPICK ? RR * GU_VP : 1];
+    __shared__ uint8_t fgs[FUSED ? TH * TW : 1];
+    __shared__ float fbe[FUSED ? TH * TW : 1];
+    __shared__ short fbz[FUSED ? TH * TW : 1];
+    __shared__ float rcpT[36];
+    __shared__ int s_xmax;
+
+    const int tid = threadIdx.x;
+    const int x0 = bx * TW, y0 = by * TH;
+    const int ry0 = y0 - HB, rx0 = x0 - HB;       // region origin
+    const int ey0 = ry0 - NW, ex0 = rx0 - NW;     // extended origin
+    const int H = a.H, W = a.W;
+    const uint8_t* Limg = (const uint8_t*)a.L;
+    const uint8_t* Rimg = (const uint8_t*)a.R;
+
+    // row-pass lanes: 16 per region row; with the re-pick halo the first wave
+    // takes the four halo rows, so the fallback tracking skips it as a whole
+    const int g = tid >> 4, kr = tid & 15;
+    int sy = g;
+    if constexpr (REPICK) sy = g < 2 ? g : (g < 4 ? g + RR - 4 : g - 2);
+    const bool scorer = g < RR;
+    const int su = kr * GU_RUN;
+    // column-pass lanes
+    const bool colw = tid >= 256 - GU_EW;
+    const int ce = tid - (256 - GU_EW);
+    // box-pass lanes (re-pick): output column bc (none past the tile), rows
+    // 4 bh .. 4 bh + 3
+    const int bc = tid & 127, bh = tid >> 7;
+    const bool boxer = REPICK && bc < TW;  // owns outputs
+
+    if (tid == 0) s_xmax = -1;
+    if (tid < 36) {
+        const int r = tid / 6, c = tid - 6 * r;
+        rcpT[tid] = (r > 0 && c > 0) ? 1.f / (float)(r * c) : 0.f;
+    }
+    __syncthreads();
+
+    // owned output pixels: the box lanes' four (re-pick), else the row lanes' run
+    constexpr int OWN = REPICK ? 4 : GU_RUN;
+    bool act[OWN], fg[OWN];
+#pragma unroll
+    for (int p = 0; p < OWN; ++p) {
+        const int t = REPICK ? 4 * bh + p : sy;
+        const int tx = REPICK ? bc : su + p;
+        const bool own = REPICK ? boxer : (scorer && su + p < TW);
+        const int i = y0 + t, j = x0 + tx;
+        act[p] = false;
+        fg[p] = false;
+        if (own && i < H && j < W) {
+            if constexpr (MODE == GATE_REPICK) {
+                act[p] = !((double)a.c[(size_t)i * a.opitch + j] > a.thresh);
+            } else if constexpr (MODE == GATE_FULL) {
+                act[p] = !(upsampled_cost(a.ccost, a.Hc, a.Wc, a.cpitch, i, j) > a.thresh);
+            } else {
+                fg[p] = !(upsampled_cost(a.ccost, a.Hc, a.Wc, a.cpitch, i, j) > a.thresh2);
+                act[p] = fg[p] || !((double)a.c[(size_t)i * a.opitch + j] > a.thresh);
+            }
+            if (act[p]) atomicMax(&s_xmax, j);
+        }
+        if constexpr (FUSED)
+            if (own) fgs[t * TW + tx] = fg[p];
+    }
+    __syncthreads();
+    const int xmax = s_xmax;
+    if (xmax < 0) return;  // uniform: no gated pixel in the tile
+    const int zmax = min(a.Dk - 1, xmax);
+    const int zbulk = x0 - HB;  // last candidate valid for the whole region (none if negative)
+
+    // ---- row-pass state: left statistics, right statistics of the run at the
+    // current candidate, and the tracked best of the fallback (or plain) search
+    int ns1l[GU_RUN];   // -S1_l
+    float isn[GU_RUN];  // invsd_l / N (0 outside the image: the score is 0)
+    // S1_r (low half) and invsd_r (high half) at the current candidate, one
+    // 64-bit register pair per column so the shift per candidate moves pairs
+    uint64_t rst[GU_RUN];
+    float tb[GU_RUN];   // tracked best (4: never replaced)
+    int tz[GU_RUN];
+    const int yy = ry0 + sy;
+    const WinStatU8* srow =
+        reinterpret_cast<const WinStatU8*>(a.statR) + (size_t)clampi(yy, 0, H - 1) * a.spitch;
+#pragma unroll
+    for (int q = 0; q < GU_RUN; ++q) {
+        const int xx = rx0 + su + q;
+        const bool in = scorer && su + q < RW && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        ns1l[q] = 0;
+        isn[q] = 0.f;
+        if (in) {
+            const WinStatU8 st = reinterpret_cast<const WinStatU8*>(a.statL)[(size_t)yy * a.spitch + xx];
+            ns1l[q] = -(int)st.s1;
+            isn[q] = st.z * (float)(1.0 / NN);
+        }
+        const int ty = sy - HB, tx = su + q - HB;
+        bool trk = false;
+        if constexpr (FUSED) trk = scorer && ty >= 0 && ty < TH && tx >= 0 && tx < TW && fgs[ty * TW + tx];
+        else if constexpr (!REPICK) trk = act[q];
+        tb[q] = trk ? -3.0f : 4.0f;
+        tz[q] = 0;
+        // the run's right statistics at candidate -1 (each row pass first
+        // shifts them to its own candidate)
+        rst[q] = 0;
+        if (scorer) rst[q] = pack_stat(srow[clampi(xx + 1, 0, W - 1)]);
+    }
+    WinStatU8 nxt{};
+    if (scorer) nxt = srow[clampi(rx0 + su, 0, W - 1)];
+    // the fallback tracking skips the halo-only first wave (re-pick modes)
+    const bool track_wave = !REPICK || (FUSED && __builtin_amdgcn_readfirstlane(tid) >= 64);
+
+    // ---- column-pass state: the left column packed four rows to a word
+    uint32_t Lw[NWORD];
+    {
+        const int xx = clampi(ex0 + ce, 0, W - 1);
+#pragma unroll
+        for (int k = 0; k < NWORD; ++k) {
+            uint32_t w = 0;
+            if (colw) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (4 * k + i < ER)
+                        w |= (uint32_t)Limg[(size_t)clampi(ey0 + 4 * k + i, 0, H - 1) * a.pitch + xx] << (8 * i);
+            }
+            Lw[k] = w;
+        }
+    }
+
+    // ---- box-pass state
+    // (neighbour counts: rows inside the image times columns inside at or
+    // right of the pixel, plus the columns left of it the candidate allows;
+    // reciprocals from the table, the full-row one held)
+    float bb[4];
+    int bzv[4];
+    float r5[4];
+    const int bj = x0 + bc;
+    const int cols_r = max(1, min(bj + 2, W - 1) - bj + 1);
+    auto rows_in = [&](int p) {
+        const int i = y0 + 4 * bh + p;
+        return max(1, min(i + 2, H - 1) - max(i - 2, 0) + 1);
+    };
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+        bb[p] = (REPICK && act[p & (OWN - 1)]) ? -3.0f : 4.0f;
+        bzv[p] = 0;
+        r5[p] = 1.f / (float)(rows_in(p) * (cols_r + 2));
+    }
+
+    // right columns ex0 - zhi .. ex0 - zhi + RSC - 1 of the extended rows for
+    // the chunk of candidates ending at zhi, packed four rows to a word
+    auto stage = [&](int zc) {
+        const int zhi = zc + GU_ZC - 1;
+        for (int idx = tid; idx < RSC * NWORD; idx += 256) {
+            const int w = idx / RSC, col = idx - w * RSC;
+            const int xx = clampi(ex0 - zhi + col, 0, W - 1);
+            uint32_t word = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (4 * w + i < ER)
+                    word |= (uint32_t)Rimg[(size_t)clampi(ey0 + 4 * w + i, 0, H - 1) * a.pitch + xx] << (8 * i);
+            RsT[col * CP + w] = make_uint4(word & 0xffu, word & 0xffffu, word & 0xffffffu, word);
+        }
+    };
+
+    // column sums of the products at candidate z: V(y) = P(y + 2n + 1) - P(y)
+    // with P the prefix sums down the column (a partial word's products take
+    // the right word cut to its first rows)
+    auto colpass = [&](int z) {
+        const int zhi = (z & ~(GU_ZC - 1)) + GU_ZC - 1;
+        const uint4* rc = RsT + (ce + zhi - z) * CP;
+        uint32_t P[4 * NWORD + 1];
+        P[0] = 0;
+#pragma unroll
+        for (int k = 0; k < NWORD; ++k) {
+            const uint4 rw = rc[k];
+            const uint32_t cut[4] = {rw.x, rw.y, rw.z, rw.w};
+#pragma unroll
+            for (int m = 1; m <= 4; ++m)
+                if (4 * k + m <= ER) P[4 * k + m] = __builtin_amdgcn_udot4(Lw[k], cut[m - 1], P[4 * k], false);
+        }
+        int* vc = Vs + gu_idx(ce);
+#pragma unroll
+        for (int y = 0; y < RR; ++y) vc[y * GU_VP] = (int)(P[y + 2 * NW + 1] - P[y]);
+    };
+
+    // scores of the run at candidate z, the tracked best, and (re-pick) the
+    // run's 5-column sums of the scores
+    auto rowpass = [&](int z, auto bulk_tag) {
+        constexpr bool BULK = decltype(bulk_tag)::value;
+        // column q at z is column q - 1 at z - 1: one new right statistic
+#pragma unroll
+        for (int q = GU_RUN - 1; q > 0; --q) rst[q] = rst[q - 1];
+        rst[0] = pack_stat(nxt);
+        nxt = srow[clampi(rx0 + su - (z + 1), 0, W - 1)];
+        const int* vr = Vs + sy * GU_VP + gu_idx(su);
+        int v[VREAD];
+#pragma unroll
+        for (int b = 0; b < VREAD; ++b) v[b] = vr[gu_idx(b)];
+        int S = 0;
+#pragma unroll
+        for (int b = 0; b <= 2 * NW; ++b) S += v[b];
+        float E[GU_RUN];
+#pragma unroll
+        for (int q = 0; q < GU_RUN; ++q) {
+            if (q > 0) S += v[q + 2 * NW] - v[q - 1];
+            const int rs1 = (int)(uint32_t)rst[q];
+            const float ris = __uint_as_float((uint32_t)(rst[q] >> 32));
+            const int nc = (int)__umul24((unsigned)NN, (unsigned)S) + __mul24(ns1l[q], rs1);  // N C
+            float e = fminf(1.f, fmaxf(-1.f, (float)nc * isn[q] * ris));
+            bool valid = true;
+            if constexpr (!BULK) {
+                valid = z <= rx0 + su + q;
+                e = valid ? e : 0.f;
+            }
+            E[q] = e;
+        }
+        if constexpr (!REPICK || FUSED) {
+            if (track_wave) {
+#pragma unroll
+                for (int q = 0; q < GU_RUN; ++q) {
+                    const bool better = (BULK || z <= rx0 + su + q) && E[q] > tb[q];
+                    tb[q] = better ? E[q] : tb[q];
+                    tz[q] = better ? z : tz[q];
+                }
+            }
+        }
+        if constexpr (REPICK) {
+            // H(q) = E(q) + .. + E(q + 4), sliding; E(8..11) are the next
+            // run's first four scores
+            float Ex[GU_RUN + 4];
+#pragma unroll
+            for (int q = 0; q < GU_RUN; ++q) Ex[q] = E[q];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) Ex[GU_RUN + m] = next_lane_in_row(E[m]);
+            float* hr = Hs + sy * GU_VP + gu_idx(su);
+            float h = ((Ex[0] + Ex[1]) + (Ex[2] + Ex[3])) + Ex[4];
+            hr[0] = h;
+#pragma unroll
+            for (int q = 1; q < GU_RUN; ++q) {
+                h += Ex[q + 4] - Ex[q - 1];
+                hr[q] = h;
+            }
+        }
+    };
+
+    // 5x5 sums of the scores at candidate z for the lane's four outputs
+    auto boxpass = [&](int z, auto bulk_tag) {
+        constexpr bool BULK = decltype(bulk_tag)::value;
+        const float* hc = Hs + 4 * bh * GU_VP + gu_idx(bc);
+        float h[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) h[m] = hc[m * GU_VP];
+        const float s01 = h[0] + h[1], s23 = h[2] + h[3], s45 = h[4] + h[5], s67 = h[6] + h[7];
+        const float s2345 = s23 + s45;
+        const float A[4] = {(s01 + s23) + h[4], h[1] + s2345, s2345 + h[6], h[3] + (s45 + s67)};
+        const int left = (z <= bj - 2) ? 2 : (z == bj - 1 ? 1 : 0);
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const float rc = BULK ? r5[p] : rcpT[rows_in(p) * 6 + cols_r + left];
+            const float ebar = A[p] * rc;
+            const bool better = (BULK || z <= bj) && ebar > bb[p];
+            bb[p] = better ? ebar : bb[p];
+            bzv[p] = better ? z : bzv[p];
+        }
+    };
+
+    // one candidate: [row pass z] [column pass z + 1, box pass z]
+    auto step = [&](int z, auto bulk_tag) {
+        if (scorer) rowpass(z, bulk_tag);
+        const int zn = z + 1;
+        if (zn <= zmax && (zn & (GU_ZC - 1)) == 0) stage(zn);  // the row pass reads no staged pixel
+        __syncthreads();
+        if (colw && zn <= zmax) colpass(zn);
+        if constexpr (REPICK) boxpass(z, bulk_tag);  // every lane (those past the tile own nothing)
+        __syncthreads();
+    };
+    stage(0);
+    __syncthreads();
+    if (colw) colpass(0);
+    __syncthreads();
+    // the candidates valid for the whole region, then the rest (separate
+    // loops: no merge of the two forms inside the loop)
+    const int zb = min(zbulk, zmax);
+    int z = 0;
+    for (; z <= zb; ++z) step(z, std::true_type{});
+    for (; z <= zmax; ++z) step(z, std::false_type{});
+
+    if constexpr (FUSED) {
+        // the fallback results to their owners
+        if (scorer) {
+#pragma unroll
+            for (int q = 0; q < GU_RUN; ++q) {
+                const int ty = sy - HB, tx = su + q - HB;
+                if (ty >= 0 && ty < TH && tx >= 0 && tx < TW) {
+                    fbe[ty * TW + tx] = tb[q];
+                    fbz[ty * TW + tx] = (short)tz[q];
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int p = 0; p < OWN; ++p) {
+        if (!act[p]) continue;
+        const int t = REPICK ? 4 * bh + p : sy;
+        const int tx = REPICK ? bc : su + p;
+        const size_t o = (size_t)(y0 + t) * a.opitch + (x0 + tx);
+        if constexpr (FUSED) {
+            // Eqs. 8-9 (the fallback or the restricted search's result), then
+            // Eqs. 5-7 on that cost
+            const int d1 = fg[p] ? (int)fbz[t * TW + tx] : (int)a.d[o];
+            const float c1 = fg[p] ? fbe[t * TW + tx] : a.c[o];
+            const bool pick = !((double)c1 > a.thresh);
+            a.d[o] = (int16_t)(pick ? bzv[p] : d1);
+            a.c[o] = pick ? bb[p] : c1;
+        } else if constexpr (REPICK) {
+            a.d[o] = (int16_t)bzv[p];
+            a.c[o] = bb[p];
+        } else {
+            a.d[o] = (int16_t)tz[p];
+            a.c[o] = tb[p];
+        }
+    }
+}
+
+// uint8 tiles: at most 168 VGPRs, three waves per SIMD
+template <typename T>
+constexpr int GATE_MIN_WAVES = std::is_same<T, uint8_t>::value ? 3 : 1;
+
+template <typename T, int NW, int MODE>
+__device__ __forceinline__ void gate_tile_any(const GateArgs& a, int bx, int by)
+{
+    if constexpr (std::is_same<T, uint8_t>::value) gate_tile_u8<NW, MODE>(a, bx, by);
+    else gate_tile<T, NW, MODE>(a, bx, by);
+}
+
+template <typename T, int NW, int MODE>
+__global__ __launch_bounds__(GT_THREADS, GATE_MIN_WAVES<T>) void gate_kernel(GateArgs a)
+{
+    gate_tile_any<T, NW, MODE>(a, blockIdx.x, blockIdx.y);
 }
 
 // Gating of several (pair, level) segments of one mode and element type in one
 // launch; a level's map and cost are those its search wrote (the scratch map
 // with the median), the coarser level's cost that of its own gating.
 template <typename T, int NW, int MODE>
-__global__ __launch_bounds__(GT_THREADS) void gate_multi_kernel(MultiArgs m)
+__global__ __launch_bounds__(GT_THREADS, GATE_MIN_WAVES<T>) void gate_multi_kernel(MultiArgs m)
 {
     const Segment s = m.segs[segment_of(m.segs, m.nseg, blockIdx.x)];
     const LevelDesc* lv = m.levels + m.level_base[s.pair];
@@ -450,7 +868,7 @@ __global__ __launch_bounds__(GT_THREADS) void gate_multi_kernel(MultiArgs m)
         g.cpitch = C.W;
     }
     const int t = blockIdx.x - s.task0;
-    gate_tile<T, NW, MODE>(g, t % s.tiles_x, t / s.tiles_x);
+    gate_tile_any<T, NW, MODE>(g, t % s.tiles_x, t / s.tiles_x);
 }
 
 template <typename T, int MODE>
@@ -471,7 +889,8 @@ hipError_t launch_gate_multi_t(int n, const MultiArgs& a, int blocks, hipStream_
 template <typename T, int MODE>
 hipError_t launch_gate_t(int n, const GateArgs& a, hipStream_t s)
 {
-    dim3 grid((a.W + GT_W - 1) / GT_W, (a.H + GT_H - 1) / GT_H, 1);
+    const int tw = gate_tile_w(std::is_same<T, uint8_t>::value ? MSIBM_U8 : MSIBM_F32, n, MODE);
+    dim3 grid((a.W + tw - 1) / tw, (a.H + GT_H - 1) / GT_H, 1);
     switch (n) {
         case 1: hipLaunchKernelGGL((gate_kernel<T, 1, MODE>), grid, dim3(GT_THREADS), 0, s, a); break;
         case 2: hipLaunchKernelGGL((gate_kernel<T, 2, MODE>), grid, dim3(GT_THREADS), 0, s, a); break;
