@@ -230,14 +230,14 @@ struct MultiArgs {
     int fused;                // backward launches: the fused masked-L1 form
 };
 
-// Tile of the gating kernel: 8 rows by 64 columns on float levels; on uint8
-// levels 8 rows by as many columns as keep the tile, its re-pick halo and its
-// windows' halo within 128 columns (one column-sum lane per column).
-constexpr int GATE_TH = 8, GATE_TW = 64;
-constexpr int GATE_U8_EW = 128;
+// Tile of the gating kernel: 8 rows by as many columns as keep the tile, its
+// re-pick halo and its windows' halo within 128 columns (one column-sum lane
+// per column).
+constexpr int GATE_TH = 8;
+constexpr int GATE_EW = 128;
 __host__ __device__ constexpr int gate_tile_w(int dtype, int n, int mode)
 {
-    return dtype == MSIBM_U8 ? GATE_U8_EW - 2 * n - (mode == GATE_MODE_FULL ? 0 : 4) : GATE_TW;
+    return (void)dtype, GATE_EW - 2 * n - (mode == GATE_MODE_FULL ? 0 : 4);
 }
 
 // Tile of the selective median filter.

@@ -5,21 +5,19 @@
 // z of the full interval: the fallback full search (pixels whose upsampled
 // coarser cost is at most beta) takes each pixel's best z, and the re-pick
 // (pixels whose cost is at most alpha) takes the best z of the scores averaged
-// over each pixel's 5x5 neighbourhood.  One workgroup handles an 8 x 64 tile
+// over each pixel's 5x5 neighbourhood.  One workgroup handles an 8-row tile
 // and walks z upwards; at each z it scores a region (the tile, plus the 5x5
 // halo for the re-pick) with box sums instead of per-window loops:
 //   V(y, e) = sum over the 2n+1 window rows of L(v, e) R(v, e - z)   (columns)
 //   S(y, u) = sum over the 2n+1 window columns of V                  (rows)
-// so a score costs O(1) instead of O((2n+1)^2) multiply-adds.  The sums run in
-// double for float levels; for a uint8 level every product (<= 255^2), column
-// sum (<= 13 products) and row sum (<= 13 column sums, below 2^24) is an
-// integer that float holds exactly, so those sums run in float at no loss.
-// With the window means of the statistics kernel the cross term is
+// so a score costs O(1) instead of O((2n+1)^2) multiply-adds.  With the window
+// statistics the cross term is
 //   C = S - N mu_l mu_r   (= sum (l - mu_l)(r - mu_r))
-// formed in double (its cancellation is what needs the precision), and
+// exact in 32-bit integers on a uint8 level and formed in double on a float
+// level (its cancellation is what needs the precision), and
 // rho = C * invsd_l * invsd_r clamped to [-1, 1], 0 for a flat window
-// (invsd = 0).  Tiles without a gated pixel leave
-// at once; the z range stops at the rightmost gated pixel's last candidate.
+// (invsd = 0).  Tiles without a gated pixel leave at once; the z range stops
+// at the rightmost gated pixel's last candidate.
 #include <type_traits>
 
 #include "common.hpp"
@@ -29,10 +27,7 @@ namespace msibm {
 namespace {
 
 constexpr int GT_H = GATE_TH;  // tile rows
-constexpr int GT_W = GATE_TW;  // tile columns
-constexpr int GT_ZC = 32;      // candidates per staged right chunk
 constexpr int GT_THREADS = 256;
-constexpr int ZU = 1;          // candidates scored per round of barriers (divides GT_ZC)
 
 // Keys' cubic weights (a = -1/2) of the four coarse taps around fine index i
 // at scale 2 with aligned pixel centres: the fine pixel sits 3/4 (even i) or
@@ -69,390 +64,39 @@ __global__ __launch_bounds__(256) void upsample_kernel(const float* cc, int Hc, 
     out[(size_t)i * opitch + j] = upsampled_cost(cc, Hc, Wc, cpitch, i, j);
 }
 
-template <typename T>
-__device__ __forceinline__ float pix(const void* img, int pitch, int y, int x)
-{
-    return (float)((const T*)img)[(size_t)y * pitch + x];
-}
-
 // MODE: GATE_FULL (the fallback full search), GATE_REPICK (the averaged-score
 // re-pick), GATE_FUSED (both in one walk: the fallback search's scores of the
 // tile pixels are region scores of the re-pick, and the re-pick decision needs
 // the fallback's result only at the end).
 constexpr int GATE_FULL = GATE_MODE_FULL, GATE_REPICK = GATE_MODE_REPICK, GATE_FUSED = GATE_MODE_FUSED;
 
-template <typename T, int NW, int MODE>
-__device__ __forceinline__ void gate_tile(const GateArgs& a, int bx, int by)
-{
-    constexpr bool REPICK = MODE != GATE_FULL;
-    constexpr bool FUSED = MODE == GATE_FUSED;
-    constexpr int HB = REPICK ? 2 : 0;                 // halo of the averaged scores
-    constexpr int RR = GT_H + 2 * HB;                  // region scored at each z
-    constexpr int RC = GT_W + 2 * HB;
-    constexpr int ER = RR + 2 * NW;                    // plus the windows' halo
-    constexpr int EC = RC + 2 * NW;
-    constexpr int RSW = EC + GT_ZC - 1;                // staged right columns per chunk
-    constexpr double NN = (double)((2 * NW + 1) * (2 * NW + 1));
-    constexpr int VG = 4;                              // rows of column sums per thread
-    constexpr int NVG = RR / VG;
-    // region columns scored per thread: an odd run keeps the lanes' row-sum
-    // reads (stride RUN doubles) on distinct LDS banks
-    constexpr int RUN = REPICK ? 5 : 3;
-    constexpr int NRUN = (RC + RUN - 1) / RUN;
-    constexpr int OWN = REPICK ? 2 : RUN;              // output pixels per thread
-    // box-sum type: exact float sums of integer products for uint8 levels
-    using acc_t = typename std::conditional<std::is_same<T, uint8_t>::value, float, double>::type;
-    static_assert(RR % VG == 0, "row groups");
-    static_assert(EC * NVG <= GT_THREADS && RR * NRUN <= GT_THREADS, "one item per thread");
-
-    __shared__ float Rs[ER][RSW];
-    __shared__ acc_t V[ZU][RR][EC];
-    // suffix and prefix sums of the scores along each scoring run (re-pick)
-    __shared__ float SUF[ZU][REPICK ? RR : 1][REPICK ? NRUN * RUN : 1];
-    __shared__ float PRE[ZU][REPICK ? RR : 1][REPICK ? NRUN * RUN : 1];
-    __shared__ int s_xmax;
-    // fused: which tile pixels take the fallback search, and its results
-    __shared__ int fgs[FUSED ? GT_H : 1][FUSED ? GT_W : 1];
-    __shared__ float fbe[FUSED ? GT_H : 1][FUSED ? GT_W : 1];
-    __shared__ int fbz[FUSED ? GT_H : 1][FUSED ? GT_W : 1];
-
-    const int tid = threadIdx.x;
-    const int x0 = bx * GT_W, y0 = by * GT_H;
-    const int ry0 = y0 - HB, rx0 = x0 - HB;            // region origin
-    const int ey0 = ry0 - NW, ex0 = rx0 - NW;          // extended origin
-    const int H = a.H, W = a.W;
-
-    // the region pixels this thread scores: row sy, columns su .. su + RUN - 1
-    const int sy = tid / NRUN, su = (tid - sy * NRUN) * RUN;
-    const bool scorer = tid < RR * NRUN;
-
-    // owned output pixels: the re-pick gives thread t column t % 64 and rows
-    // 2 (t / 64) + {0, 1}; the full search owns the pixels it scores itself
-    int oy[OWN], ox[OWN];
-#pragma unroll
-    for (int p = 0; p < OWN; ++p) {
-        if constexpr (REPICK) {
-            ox[p] = tid & 63;
-            oy[p] = 2 * (tid >> 6) + p;
-        } else {
-            oy[p] = scorer ? sy : GT_H;  // GT_H: owns nothing
-            ox[p] = su + p;
-        }
-    }
-    bool act[OWN];
-    bool fg[OWN];     // fused: the pixel takes the fallback search
-    float best[OWN];
-    int bz[OWN];
-    if (tid == 0) s_xmax = -1;
-    __syncthreads();
-#pragma unroll
-    for (int p = 0; p < OWN; ++p) {
-        const int i = y0 + oy[p], j = x0 + ox[p];
-        act[p] = false;
-        fg[p] = false;
-        best[p] = -3.0f;  // below every score
-        bz[p] = 0;
-        if (oy[p] < GT_H && ox[p] < GT_W && i < H && j < W) {
-            if constexpr (MODE == GATE_REPICK) {
-                act[p] = !((double)a.c[(size_t)i * a.opitch + j] > a.thresh);
-            } else if constexpr (MODE == GATE_FULL) {
-                act[p] = !(upsampled_cost(a.ccost, a.Hc, a.Wc, a.cpitch, i, j) > a.thresh);
-            } else {
-                // a fallback pixel may end up re-picked, so it walks too
-                fg[p] = !(upsampled_cost(a.ccost, a.Hc, a.Wc, a.cpitch, i, j) > a.thresh2);
-                act[p] = fg[p] || !((double)a.c[(size_t)i * a.opitch + j] > a.thresh);
-            }
-            if (act[p]) atomicMax(&s_xmax, j);
-        }
-        if constexpr (FUSED) fgs[oy[p]][ox[p]] = fg[p];
-    }
-    __syncthreads();
-    const int xmax = s_xmax;
-    if (xmax < 0) return;  // uniform: no gated pixel in the tile
-    const int zmax = min(a.Dk - 1, xmax);
-
-    // the left column a column-sum thread multiplies at every candidate, held
-    // in registers (the left tile does not move with z; clamped reads)
-    float lcol[VG + 2 * NW];
-    {
-        const int g = min(tid / EC, NVG - 1), e = tid - (tid / EC) * EC;
-#pragma unroll
-        for (int t = 0; t < VG + 2 * NW; ++t)
-            lcol[t] = pix<T>(a.L, a.pitch, clampi(ey0 + g * VG + t, 0, H - 1), clampi(ex0 + e, 0, W - 1));
-    }
-
-    // left statistics of the scored region pixels (N mu_l, 1/sqrt(A_l))
-    // uint8 levels: N C = N S - S1_l S1_r exactly in 32-bit integers (up to
-    // 15x15 windows every factor is an integer below 2^24, both products fit
-    // 32 unsigned bits and their difference, N^2 times a covariance of bytes,
-    // lies within +-2^31), so the left window sum is kept as an integer and
-    // 1/sd is scaled by 1/N
-    constexpr bool U8 = std::is_same<T, uint8_t>::value;
-    double nmul[RUN];
-    unsigned s1l[RUN];
-    float isl[RUN];
-    int sxa[RUN];     // region pixel column, or -1 outside the image
-#pragma unroll
-    for (int q = 0; q < RUN; ++q) {
-        const int yy = ry0 + sy, xx = rx0 + su + q;
-        const bool in = scorer && su + q < RC && yy >= 0 && yy < H && xx >= 0 && xx < W;
-        sxa[q] = in ? xx : -1;
-        nmul[q] = 0.0;
-        s1l[q] = 0u;
-        isl[q] = 0.f;
-        if (in) {
-            const size_t o = (size_t)yy * a.spitch + xx;
-            if constexpr (std::is_same<T, uint8_t>::value) {
-                const WinStatU8 st = reinterpret_cast<const WinStatU8*>(a.statL)[o];  // N mu_l = S1_l
-                s1l[q] = (unsigned)st.s1;
-                isl[q] = st.z * (float)(1.0 / NN);
-            } else {
-                const WinStat st = a.statL[o];
-                nmul[q] = NN * ((double)st.x + (double)st.y);
-                isl[q] = st.z;
-            }
-        }
-    }
-    // neighbours of an owned pixel inside the image: rows, and columns at or
-    // right of it (every z <= j is a candidate of those)
-    // (reciprocal counts for 2, 1 and 0 contributing columns left of the pixel)
-    float rcp5[OWN], rcp4[OWN], rcp3[OWN];
-#pragma unroll
-    for (int p = 0; p < OWN; ++p) {
-        const int i = y0 + oy[p], j = x0 + ox[p];
-        const int rows_in = min(i + 2, H - 1) - max(i - 2, 0) + 1;
-        const int cols_r = min(j + 2, W - 1) - j + 1;
-        rcp5[p] = 1.f / (float)(rows_in * (cols_r + 2));
-        rcp4[p] = 1.f / (float)(rows_in * (cols_r + 1));
-        rcp3[p] = 1.f / (float)(rows_in * cols_r);
-    }
-
-    // fused: the scorer tracks the fallback search of the tile pixels it scores
-    bool sfg[RUN];
-    float fbest[RUN];
-    int fbzv[RUN];
-#pragma unroll
-    for (int q = 0; q < RUN; ++q) {
-        const int ty = sy - HB, tx = su + q - HB;
-        sfg[q] = false;
-        if constexpr (FUSED)
-            sfg[q] = scorer && ty >= 0 && ty < GT_H && tx >= 0 && tx < GT_W && fgs[ty][tx];
-        fbest[q] = -3.0f;
-        fbzv[q] = 0;
-    }
-
-    // right window means and 1/sqrt(A) of the scored run at the current
-    // candidate (read from global memory: one new value per candidate)
-    double rmu[RUN];
-    unsigned s1r[RUN];  // uint8 levels: the right window sums of the run
-    float ris[RUN];
-    // (uint8 levels: records of the exact window sum, mu_r = S1_r / N)
-    using SR = typename std::conditional<std::is_same<T, uint8_t>::value, WinStatU8, WinStat>::type;
-    const SR* srow = reinterpret_cast<const SR*>(a.statR) + (size_t)clampi(ry0 + sy, 0, H - 1) * a.spitch;
-    auto mean_of = [](const SR& st) -> double {
-        if constexpr (std::is_same<SR, WinStatU8>::value) return (double)st.s1 * (1.0 / NN);
-        else return (double)st.x + (double)st.y;
-    };
-    SR nxt{};
-    if (scorer) {
-#pragma unroll
-        for (int q = 0; q < RUN; ++q) {
-            const SR st = srow[clampi(rx0 + su + q, 0, W - 1)];
-            if constexpr (U8) s1r[q] = (unsigned)st.s1;
-            else rmu[q] = mean_of(st);
-            ris[q] = st.z;
-        }
-    }
-
-    for (int z0 = 0; z0 <= zmax; z0 += GT_ZC) {
-        const int zhi = z0 + GT_ZC - 1;
-        __syncthreads();  // the previous chunk's staged data is consumed
-        for (int idx = tid; idx < ER * RSW; idx += GT_THREADS) {
-            const int v = idx / RSW, w = idx - v * RSW;
-            Rs[v][w] = pix<T>(a.R, a.pitch, clampi(ey0 + v, 0, H - 1), clampi(ex0 - zhi + w, 0, W - 1));
-        }
-        __syncthreads();
-        const int zend = min(zhi, zmax);
-        // ZU candidates per round of barriers (two per round measured no faster)
-        for (int z = z0; z <= zend; z += ZU) {
-            // column sums of the products over each window's rows
-            if (tid < EC * NVG) {
-                const int g = tid / EC, e = tid - g * EC;
-#pragma unroll
-                for (int u = 0; u < ZU; ++u) {
-                    const int zz = max(zhi - (z + u), 0);  // a candidate past zend is scored, not used
-                    acc_t pr[VG + 2 * NW];
-#pragma unroll
-                    for (int t = 0; t < VG + 2 * NW; ++t)
-                        pr[t] = (acc_t)lcol[t] * (acc_t)Rs[g * VG + t][e + zz];
-                    acc_t sv = 0;
-#pragma unroll
-                    for (int t = 0; t <= 2 * NW; ++t) sv += pr[t];
-                    V[u][g * VG][e] = sv;
-#pragma unroll
-                    for (int t = 1; t < VG; ++t) {
-                        sv += pr[t + 2 * NW] - pr[t - 1];
-                        V[u][g * VG + t][e] = sv;
-                    }
-                }
-            }
-            __syncthreads();
-            // row sums, then the scores of the region pixels
-            if (scorer) {
-#pragma unroll
-                for (int u = 0; u < ZU; ++u) {
-                    const int zu = z + u;
-                    // right statistics of the run: column q at candidate z is
-                    // column q - 1 at z - 1, so one new value per candidate,
-                    // loaded one candidate ahead
-                    if (zu > 0) {
-#pragma unroll
-                        for (int q = RUN - 1; q > 0; --q) {
-                            if constexpr (U8) s1r[q] = s1r[q - 1];
-                            else rmu[q] = rmu[q - 1];
-                            ris[q] = ris[q - 1];
-                        }
-                        if constexpr (U8) s1r[0] = (unsigned)nxt.s1;
-                        else rmu[0] = mean_of(nxt);
-                        ris[0] = nxt.z;
-                    }
-                    nxt = srow[clampi(rx0 + su - (zu + 1), 0, W - 1)];
-                    acc_t sr = 0;
-                    float ev[RUN];
-#pragma unroll
-                    for (int b = 0; b <= 2 * NW; ++b) sr += (su + b < EC) ? V[u][sy][su + b] : (acc_t)0;
-#pragma unroll
-                    for (int q = 0; q < RUN; ++q) {
-                        if (q > 0) {
-                            const int hi = su + q + 2 * NW;
-                            sr += (hi < EC ? V[u][sy][hi] : (acc_t)0) - V[u][sy][su + q - 1];
-                        }
-                        // computed for every column of the run, kept where
-                        // valid: no branch per column.  C in double; its float
-                        // rounding (relative 6e-8) is far below the score
-                        // tolerance
-                        const bool valid = sxa[q] >= zu && zu <= zend;
-                        float c;
-                        if constexpr (U8) {
-                            c = (float)(int)(__umul24((unsigned)NN, (unsigned)sr) - __umul24(s1l[q], s1r[q]));
-                        } else {
-                            c = (float)fma(-nmul[q], rmu[q], (double)sr);
-                        }
-                        const float e = valid ? fminf(1.f, fmaxf(-1.f, c * isl[q] * ris[q])) : 0.f;
-                        ev[q] = e;
-                        if constexpr (FUSED) {
-                            const bool better = sfg[q] && valid && e > fbest[q];
-                            fbest[q] = better ? e : fbest[q];
-                            fbzv[q] = better ? zu : fbzv[q];
-                        }
-                        if constexpr (!REPICK) {
-                            // the scorer of (sy, su + q) owns it
-                            const bool better = act[q] && valid && e > best[q];
-                            best[q] = better ? e : best[q];
-                            bz[q] = better ? zu : bz[q];
-                        }
-                    }
-                    if constexpr (REPICK) {
-                        // the run's suffix sums (SUF[c] = e[c] + .. + e[end of
-                        // run]) and prefix sums (PRE[start + k] = the run's
-                        // first k scores): a 5-column sum starting at c is
-                        // SUF[c] + PRE[c + 5]
-                        float acc = 0.f;
-#pragma unroll
-                        for (int q = RUN - 1; q >= 0; --q) {
-                            acc += ev[q];
-                            SUF[u][sy][su + q] = acc;
-                        }
-                        acc = 0.f;
-#pragma unroll
-                        for (int q = 0; q < RUN; ++q) {
-                            PRE[u][sy][su + q] = acc;
-                            acc += ev[q];
-                        }
-                    }
-                }
-            }
-            __syncthreads();
-            if constexpr (REPICK) {
-                // 5x5 sums of the scores (0 where a neighbour does not count):
-                // the 5-column sums of six region rows, then the 5-row sums of
-                // the thread's two output pixels
-                const int c0 = tid & 63, r0 = oy[0];
-#pragma unroll
-                for (int u = 0; u < ZU; ++u) {
-                    const int zu = z + u;
-                    float hs[6];
-#pragma unroll
-                    for (int t = 0; t < 6; ++t) hs[t] = SUF[u][r0 + t][c0] + PRE[u][r0 + t][c0 + 5];
-                    const float mid = hs[1] + hs[2] + hs[3] + hs[4];
-                    const float sum[2] = {hs[0] + mid, mid + hs[5]};
-#pragma unroll
-                    for (int p = 0; p < 2; ++p) {
-                        const int j = x0 + ox[p];
-                        // the count changes only where z passes j - 2 and j - 1
-                        const float rc = (zu <= j - 2) ? rcp5[p] : (zu == j - 1 ? rcp4[p] : rcp3[p]);
-                        const float ebar = sum[p] * rc;
-                        const bool better = act[p] && zu <= j && zu <= zend && ebar > best[p];
-                        best[p] = better ? ebar : best[p];
-                        bz[p] = better ? zu : bz[p];
-                    }
-                }
-            }
-        }
-    }
-    if constexpr (FUSED) {
-        // the fallback results to their owners
-#pragma unroll
-        for (int q = 0; q < RUN; ++q)
-            if (sfg[q]) {
-                fbe[sy - HB][su + q - HB] = fbest[q];
-                fbz[sy - HB][su + q - HB] = fbzv[q];
-            }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int p = 0; p < OWN; ++p) {
-        if (!act[p]) continue;
-        const size_t o = (size_t)(y0 + oy[p]) * a.opitch + (x0 + ox[p]);
-        if constexpr (FUSED) {
-            // Eqs. 8-9 (the fallback or the restricted search's result), then
-            // Eqs. 5-7 on that cost
-            const int d1 = fg[p] ? fbz[oy[p]][ox[p]] : (int)a.d[o];
-            const float c1 = fg[p] ? fbe[oy[p]][ox[p]] : a.c[o];
-            const bool pick = !((double)c1 > a.thresh);
-            a.d[o] = (int16_t)(pick ? bz[p] : d1);
-            a.c[o] = pick ? best[p] : c1;
-        } else {
-            a.d[o] = (int16_t)bz[p];
-            a.c[o] = best[p];
-        }
-    }
-}
-
-// ---- uint8 levels ---------------------------------------------------------
+// ---- the three-pass tile ---------------------------------------------------
 //
-// On a uint8 level every product, window sum and cross term is an integer, so
-// the three sums per candidate are formed in 32-bit integers:
+// The tile the gating runs on: 8 output rows and as many columns as keep the
+// extended region (tile, re-pick halo, windows' halo) within 128 columns.  Per
+// candidate three passes share the work:
 //  * column pass (lanes 128..255, one column of the extended region each):
-//    the left column is held packed four rows to a word and the right column
-//    is staged in LDS the same way, so one v_dot4_u32_u8 adds four row
-//    products; prefix sums down the column give every (2n+1)-row sum as the
-//    difference of two prefixes.
+//    prefix sums of the products down the column give every (2n+1)-row sum
+//    as the difference of two prefixes.  On a uint8 level the left column is
+//    held packed four rows to a word and the right column is staged in LDS
+//    the same way, so one v_dot4_u32_u8 adds four row products (exact 32-bit
+//    integers); on a float level each product is formed exactly in double
+//    (the left column held in double, the staged right pixel converted).
 //  * row pass (16 lanes per region row, 8 region columns each): a sliding
-//    (2n+1)-column sum of the column sums gives S, and N C = N S - S1_l S1_r
-//    is exact (every factor below 2^24, the difference within +-2^31 up to
-//    13x13 windows); the score is N C * (invsd_l / N) * invsd_r clamped to
-//    [-1, 1].  The re-pick's 5-column sums of the scores take the next lane's
-//    first four scores across the 16-lane row with a DPP shift.
+//    (2n+1)-column sum of the column sums gives S.  uint8: N C = N S - S1_l
+//    S1_r is exact (every factor below 2^24, the difference within +-2^31 up
+//    to 13x13 windows) and the score is N C * (invsd_l / N) * invsd_r; float:
+//    C = S - N mu_l mu_r in double, the score C * invsd_l * invsd_r; both
+//    clamped to [-1, 1].  The re-pick's 5-column sums of the scores take the
+//    next lane's first four scores across the 16-lane row with a DPP shift.
 //  * box pass (re-pick; one output column and four output rows per lane):
 //    five-row sums of the 5-column sums.
 // Two barriers per candidate: [row pass z] then [column pass z + 1, box pass
 // z].  Candidates up to x0 - 2 (x0 for the plain fallback search) lie left of
 // every region pixel and leave every output's neighbour count at its full
 // value, so they run without the per-pixel candidate checks.
-constexpr int GU_EW = GATE_U8_EW;  // extended-region columns
+constexpr int GU_EW = GATE_EW;     // extended-region columns
 constexpr int GU_RUN = 8;          // region columns a row-pass lane scores
-constexpr int GU_ZC = 32;          // candidates per staged right chunk
 constexpr int GU_VP = 144;         // LDS row pitch of the column and 5-column sums (16 mod 32 banks)
 
 // LDS index of region column u in a row of sums: one pad word per 8 columns,
@@ -472,9 +116,11 @@ __device__ __forceinline__ float next_lane_in_row(float x)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x101, 0xf, 0xf, true));
 }
 
-template <int NW, int MODE>
-__device__ __forceinline__ void gate_tile_u8(const GateArgs& a, int bx, int by)
+template <typename T, int NW, int MODE>
+__device__ __forceinline__ void gate_tile_box(const GateArgs& a, int bx, int by)
 {
+    constexpr bool U8 = std::is_same<T, uint8_t>::value;
+    using VT = typename std::conditional<U8, int, double>::type;  // column and window sums
     constexpr bool REPICK = MODE != GATE_FULL;
     constexpr bool FUSED = MODE == GATE_FUSED;
     constexpr int HB = REPICK ? 2 : 0;            // halo of the averaged scores
@@ -486,7 +132,11 @@ __device__ __forceinline__ void gate_tile_u8(const GateArgs& a, int bx, int by)
     constexpr int NWORD = (ER + 3) / 4;           // packed 4-row words per column
     constexpr int CP = NWORD | 1;                 // staged column pitch in words (odd: distinct banks)
     // (each staged word is held as its first 1, 2, 3 and 4 rows, 16 bytes)
-    constexpr int RSC = GU_EW + GU_ZC - 1;        // staged right columns per chunk
+    constexpr int ZC = U8 ? 32 : 16;              // candidates per staged right chunk
+    constexpr int RSC = GU_EW + ZC - 1;           // staged right columns per chunk
+    // float levels: a staged column's rows in 16-byte groups, the column pitch
+    // 4 mod 8 words so eight lanes' 16-byte reads fall on distinct banks
+    constexpr int RP = ((ER + 3) & ~3) % 8 == 0 ? ((ER + 3) & ~3) + 4 : ((ER + 3) & ~3);
     constexpr int VREAD = GU_RUN + 2 * NW;        // column sums a run reads
     constexpr int NN = (2 * NW + 1) * (2 * NW + 1);
     // all 16 runs of a row are scored (uniform lanes); runs past the region
@@ -494,14 +144,22 @@ __device__ __forceinline__ void gate_tile_u8(const GateArgs& a, int bx, int by)
     constexpr int VTAIL = gu_idx(GU_RUN * 15 + VREAD - 1) + 1 - GU_VP;
     static_assert(RW <= 16 * GU_RUN && RR * 16 <= 256 && TW <= 128 && gu_idx(GU_EW - 1) < GU_VP && VTAIL > 0,
                   "tile shape");
-    static_assert(TW == gate_tile_w(MSIBM_U8, NW, MODE), "host tile width");
+    static_assert(TW == gate_tile_w(MSIBM_U8, NW, MODE) && TW == gate_tile_w(MSIBM_F32, NW, MODE),
+                  "host tile width");
 
-    __shared__ uint4 RsT[RSC * CP];
-    __shared__ int Vs[RR * GU_VP + VTAIL];
+    // the staged right pixels; before the walk and after it the same memory
+    // holds the fused mode's fallback flags and results
+    constexpr int STAGE_B = U8 ? RSC * CP * 16 : RSC * RP * 4;
+    static_assert(!FUSED || 7 * TH * TW <= STAGE_B, "fused arrays fit the staging memory");
+    __shared__ uint4 stage_mem[STAGE_B / 16];
+    uint4* const RsT = stage_mem;
+    float* const RsF = reinterpret_cast<float*>(stage_mem);
+    float* const fbe = reinterpret_cast<float*>(stage_mem);
+    short* const fbz = reinterpret_cast<short*>(fbe + TH * TW);
+    uint8_t* const fgs = reinterpret_cast<uint8_t*>(fbz + TH * TW);
+    __shared__ __attribute__((aligned(16))) float LsF[U8 ? 1 : GU_EW * RP];  // float: the left columns
+    __shared__ VT Vs[RR * GU_VP + VTAIL];
     __shared__ float Hs[REPICK ? RR * GU_VP : 1];
-    __shared__ uint8_t fgs[FUSED ? TH * TW : 1];
-    __shared__ float fbe[FUSED ? TH * TW : 1];
-    __shared__ short fbz[FUSED ? TH * TW : 1];
     __shared__ float rcpT[36];
     __shared__ int s_xmax;
 
@@ -510,8 +168,8 @@ __device__ __forceinline__ void gate_tile_u8(const GateArgs& a, int bx, int by)
     const int ry0 = y0 - HB, rx0 = x0 - HB;       // region origin
     const int ey0 = ry0 - NW, ex0 = rx0 - NW;     // extended origin
     const int H = a.H, W = a.W;
-    const uint8_t* Limg = (const uint8_t*)a.L;
-    const uint8_t* Rimg = (const uint8_t*)a.R;
+    const T* Limg = (const T*)a.L;
+    const T* Rimg = (const T*)a.R;
 
     // row-pass lanes: 16 per region row; with the re-pick halo the first wave
     // takes the four halo rows, so the fallback tracking skips it as a whole
@@ -568,26 +226,46 @@ __device__ __forceinline__ void gate_tile_u8(const GateArgs& a, int bx, int by)
 
     // ---- row-pass state: left statistics, right statistics of the run at the
     // current candidate, and the tracked best of the fallback (or plain) search
-    int ns1l[GU_RUN];   // -S1_l
-    float isn[GU_RUN];  // invsd_l / N (0 outside the image: the score is 0)
-    // S1_r (low half) and invsd_r (high half) at the current candidate, one
-    // 64-bit register pair per column so the shift per candidate moves pairs
-    uint64_t rst[GU_RUN];
+    // uint8: -S1_l and invsd_l / N; float: N mu_l and invsd_l (invsd 0
+    // outside the image: the score is 0)
+    int ns1l[U8 ? GU_RUN : 1];
+    double nmul[U8 ? 1 : GU_RUN];
+    float isn[GU_RUN];
+    // the right statistics at the current candidate.  uint8: S1_r (low half)
+    // and invsd_r (high half) in one 64-bit register pair per column, so the
+    // shift per candidate moves pairs; float: mu_r and invsd_r
+    uint64_t rst[U8 ? GU_RUN : 1];
+    double rmu[U8 ? 1 : GU_RUN];
+    float ris[U8 ? 1 : GU_RUN];
     float tb[GU_RUN];   // tracked best (4: never replaced)
     int tz[GU_RUN];
     const int yy = ry0 + sy;
-    const WinStatU8* srow =
-        reinterpret_cast<const WinStatU8*>(a.statR) + (size_t)clampi(yy, 0, H - 1) * a.spitch;
+    using SR = typename std::conditional<U8, WinStatU8, WinStat>::type;
+    const SR* srow = reinterpret_cast<const SR*>(a.statR) + (size_t)clampi(yy, 0, H - 1) * a.spitch;
+    auto shift_in = [&](int q, const SR& st) {
+        if constexpr (U8) {
+            rst[q] = pack_stat(st);
+        } else {
+            rmu[q] = (double)st.x + (double)st.y;
+            ris[q] = st.z;
+        }
+    };
 #pragma unroll
     for (int q = 0; q < GU_RUN; ++q) {
         const int xx = rx0 + su + q;
         const bool in = scorer && su + q < RW && yy >= 0 && yy < H && xx >= 0 && xx < W;
-        ns1l[q] = 0;
+        if constexpr (U8) ns1l[q] = 0;
+        else nmul[q] = 0.0;
         isn[q] = 0.f;
         if (in) {
-            const WinStatU8 st = reinterpret_cast<const WinStatU8*>(a.statL)[(size_t)yy * a.spitch + xx];
-            ns1l[q] = -(int)st.s1;
-            isn[q] = st.z * (float)(1.0 / NN);
+            const SR st = reinterpret_cast<const SR*>(a.statL)[(size_t)yy * a.spitch + xx];
+            if constexpr (U8) {
+                ns1l[q] = -(int)st.s1;
+                isn[q] = st.z * (float)(1.0 / NN);
+            } else {
+                nmul[q] = (double)NN * ((double)st.x + (double)st.y);
+                isn[q] = st.z;
+            }
         }
         const int ty = sy - HB, tx = su + q - HB;
         bool trk = false;
@@ -597,28 +275,35 @@ __device__ __forceinline__ void gate_tile_u8(const GateArgs& a, int bx, int by)
         tz[q] = 0;
         // the run's right statistics at candidate -1 (each row pass first
         // shifts them to its own candidate)
-        rst[q] = 0;
-        if (scorer) rst[q] = pack_stat(srow[clampi(xx + 1, 0, W - 1)]);
+        shift_in(q, scorer ? srow[clampi(xx + 1, 0, W - 1)] : SR{});
     }
-    WinStatU8 nxt{};
+    SR nxt{};
     if (scorer) nxt = srow[clampi(rx0 + su, 0, W - 1)];
     // the fallback tracking skips the halo-only first wave (re-pick modes)
     const bool track_wave = !REPICK || (FUSED && __builtin_amdgcn_readfirstlane(tid) >= 64);
 
-    // ---- column-pass state: the left column packed four rows to a word
-    uint32_t Lw[NWORD];
+    // ---- column-pass state: the left column, packed four rows to a word
+    // (uint8), or staged in LDS and widened at each use (float)
+    uint32_t Lw[U8 ? NWORD : 1];
     {
         const int xx = clampi(ex0 + ce, 0, W - 1);
+        if constexpr (U8) {
 #pragma unroll
-        for (int k = 0; k < NWORD; ++k) {
-            uint32_t w = 0;
-            if (colw) {
+            for (int k = 0; k < NWORD; ++k) {
+                uint32_t w = 0;
+                if (colw) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (4 * k + i < ER)
-                        w |= (uint32_t)Limg[(size_t)clampi(ey0 + 4 * k + i, 0, H - 1) * a.pitch + xx] << (8 * i);
+                    for (int i = 0; i < 4; ++i)
+                        if (4 * k + i < ER)
+                            w |= (uint32_t)Limg[(size_t)clampi(ey0 + 4 * k + i, 0, H - 1) * a.pitch + xx]
+                                 << (8 * i);
+                }
+                Lw[k] = w;
             }
-            Lw[k] = w;
+        } else {
+            if (colw)
+                for (int t = 0; t < ER; ++t)
+                    LsF[ce * RP + t] = (float)Limg[(size_t)clampi(ey0 + t, 0, H - 1) * a.pitch + xx];
         }
     }
 
@@ -645,7 +330,16 @@ __device__ __forceinline__ void gate_tile_u8(const GateArgs& a, int bx, int by)
     // right columns ex0 - zhi .. ex0 - zhi + RSC - 1 of the extended rows for
     // the chunk of candidates ending at zhi, packed four rows to a word
     auto stage = [&](int zc) {
-        const int zhi = zc + GU_ZC - 1;
+        const int zhi = zc + ZC - 1;
+        if constexpr (!U8) {
+            // float: one pixel per lane and step, columns fastest
+            for (int idx = tid; idx < RSC * ER; idx += 256) {
+                const int v = idx / RSC, col = idx - v * RSC;
+                RsF[col * RP + v] =
+                    Rimg[(size_t)clampi(ey0 + v, 0, H - 1) * a.pitch + clampi(ex0 - zhi + col, 0, W - 1)];
+            }
+            return;
+        }
         for (int idx = tid; idx < RSC * NWORD; idx += 256) {
             const int w = idx / RSC, col = idx - w * RSC;
             const int xx = clampi(ex0 - zhi + col, 0, W - 1);
@@ -662,7 +356,30 @@ __device__ __forceinline__ void gate_tile_u8(const GateArgs& a, int bx, int by)
     // with P the prefix sums down the column (a partial word's products take
     // the right word cut to its first rows)
     auto colpass = [&](int z) {
-        const int zhi = (z & ~(GU_ZC - 1)) + GU_ZC - 1;
+        const int zhi = (z & ~(ZC - 1)) + ZC - 1;
+        if constexpr (!U8) {
+            // each column sum is written as soon as its upper prefix exists,
+            // so at most 2n + 2 prefixes are live
+            const float4* rc = reinterpret_cast<const float4*>(RsF + (ce + zhi - z) * RP);
+            const float4* lc = reinterpret_cast<const float4*>(LsF + ce * RP);
+            VT* vc = Vs + gu_idx(ce);
+            double P[ER + 1];
+            P[0] = 0.0;
+#pragma unroll
+            for (int k = 0; k < (ER + 3) / 4; ++k) {
+                const float4 r4 = rc[k], l4 = lc[k];
+                const float rv[4] = {r4.x, r4.y, r4.z, r4.w}, lv[4] = {l4.x, l4.y, l4.z, l4.w};
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int t = 4 * k + i + 1;
+                    if (t <= ER) {
+                        P[t] = fma((double)lv[i], (double)rv[i], P[t - 1]);
+                        if (t >= 2 * NW + 1) vc[(t - 2 * NW - 1) * GU_VP] = P[t] - P[t - 2 * NW - 1];
+                    }
+                }
+            }
+            return;
+        }
         const uint4* rc = RsT + (ce + zhi - z) * CP;
         uint32_t P[4 * NWORD + 1];
         P[0] = 0;
@@ -674,7 +391,7 @@ __device__ __forceinline__ void gate_tile_u8(const GateArgs& a, int bx, int by)
             for (int m = 1; m <= 4; ++m)
                 if (4 * k + m <= ER) P[4 * k + m] = __builtin_amdgcn_udot4(Lw[k], cut[m - 1], P[4 * k], false);
         }
-        int* vc = Vs + gu_idx(ce);
+        VT* vc = Vs + gu_idx(ce);
 #pragma unroll
         for (int y = 0; y < RR; ++y) vc[y * GU_VP] = (int)(P[y + 2 * NW + 1] - P[y]);
     };
@@ -685,24 +402,37 @@ __device__ __forceinline__ void gate_tile_u8(const GateArgs& a, int bx, int by)
         constexpr bool BULK = decltype(bulk_tag)::value;
         // column q at z is column q - 1 at z - 1: one new right statistic
 #pragma unroll
-        for (int q = GU_RUN - 1; q > 0; --q) rst[q] = rst[q - 1];
-        rst[0] = pack_stat(nxt);
+        for (int q = GU_RUN - 1; q > 0; --q) {
+            if constexpr (U8) {
+                rst[q] = rst[q - 1];
+            } else {
+                rmu[q] = rmu[q - 1];
+                ris[q] = ris[q - 1];
+            }
+        }
+        shift_in(0, nxt);
         nxt = srow[clampi(rx0 + su - (z + 1), 0, W - 1)];
-        const int* vr = Vs + sy * GU_VP + gu_idx(su);
-        int v[VREAD];
+        const VT* vr = Vs + sy * GU_VP + gu_idx(su);
+        VT v[VREAD];
 #pragma unroll
         for (int b = 0; b < VREAD; ++b) v[b] = vr[gu_idx(b)];
-        int S = 0;
+        VT S = 0;
 #pragma unroll
         for (int b = 0; b <= 2 * NW; ++b) S += v[b];
         float E[GU_RUN];
 #pragma unroll
         for (int q = 0; q < GU_RUN; ++q) {
             if (q > 0) S += v[q + 2 * NW] - v[q - 1];
-            const int rs1 = (int)(uint32_t)rst[q];
-            const float ris = __uint_as_float((uint32_t)(rst[q] >> 32));
-            const int nc = (int)__umul24((unsigned)NN, (unsigned)S) + __mul24(ns1l[q], rs1);  // N C
-            float e = fminf(1.f, fmaxf(-1.f, (float)nc * isn[q] * ris));
+            float e;
+            if constexpr (U8) {
+                const int rs1 = (int)(uint32_t)rst[q];
+                const float rz = __uint_as_float((uint32_t)(rst[q] >> 32));
+                const int nc = (int)__umul24((unsigned)NN, (unsigned)S) + __mul24(ns1l[q], rs1);  // N C
+                e = fminf(1.f, fmaxf(-1.f, (float)nc * isn[q] * rz));
+            } else {
+                const float c = (float)fma(-nmul[q], rmu[q], S);  // C
+                e = fminf(1.f, fmaxf(-1.f, c * isn[q] * ris[q]));
+            }
             bool valid = true;
             if constexpr (!BULK) {
                 valid = z <= rx0 + su + q;
@@ -764,12 +494,13 @@ __device__ __forceinline__ void gate_tile_u8(const GateArgs& a, int bx, int by)
     auto step = [&](int z, auto bulk_tag) {
         if (scorer) rowpass(z, bulk_tag);
         const int zn = z + 1;
-        if (zn <= zmax && (zn & (GU_ZC - 1)) == 0) stage(zn);  // the row pass reads no staged pixel
+        if (zn <= zmax && (zn & (ZC - 1)) == 0) stage(zn);  // the row pass reads no staged pixel
         __syncthreads();
         if (colw && zn <= zmax) colpass(zn);
         if constexpr (REPICK) boxpass(z, bulk_tag);  // every lane (those past the tile own nothing)
         __syncthreads();
     };
+    if constexpr (FUSED) __syncthreads();  // the fallback flags are read: the staging memory is free
     stage(0);
     __syncthreads();
     if (colw) colpass(0);
@@ -819,15 +550,14 @@ __device__ __forceinline__ void gate_tile_u8(const GateArgs& a, int bx, int by)
     }
 }
 
-// uint8 tiles: at most 168 VGPRs, three waves per SIMD
+// at most 168 VGPRs: three waves per SIMD
 template <typename T>
-constexpr int GATE_MIN_WAVES = std::is_same<T, uint8_t>::value ? 3 : 1;
+constexpr int GATE_MIN_WAVES = 3;
 
 template <typename T, int NW, int MODE>
 __device__ __forceinline__ void gate_tile_any(const GateArgs& a, int bx, int by)
 {
-    if constexpr (std::is_same<T, uint8_t>::value) gate_tile_u8<NW, MODE>(a, bx, by);
-    else gate_tile<T, NW, MODE>(a, bx, by);
+    gate_tile_box<T, NW, MODE>(a, bx, by);
 }
 
 template <typename T, int NW, int MODE>
