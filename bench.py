@@ -330,11 +330,11 @@ def section_gated(torch, M, synth, steps):
     """The paper's confidence gating (Eqs. 5-9) on the 1436x992 pair: time per
     pair, per-kernel times, and the work of the level-0 gate launch (the
     fallback full search and the re-pick fused in one walk).  It scores, for
-    every tile (8 x 64 pixels) holding a pixel that takes the fallback search
-    or whose restricted-search cost is at most alpha, every region pixel (the
-    tile plus a 2-pixel ring) at every candidate up to the tile's last such
-    column's range; the scores per launch are counted here from the same inputs
-    the launch sees."""
+    every tile (8 rows x (128 - 2n - 4) columns) holding a pixel that takes
+    the fallback search or whose restricted-search cost is at most alpha, every
+    region pixel (the tile plus a 2-pixel ring) at every candidate up to the
+    tile's last such column's range; the scores per launch are counted here
+    from the same inputs the launch sees."""
     dev = torch.device("cuda:0")
     p, cfg = synth.workload("mid1436")
     H, W, D, K, n, r, eps = cfg.height, cfg.width, cfg.max_disp, cfg.levels, cfg.half_window, \
@@ -365,7 +365,7 @@ def section_gated(torch, M, synth, steps):
     walk_mask = full_mask | (~(Cr.double() > gate[0])).cpu().numpy()
 
     def scores(mask, halo):
-        th, tw = 8, 64
+        th, tw = 8, 128 - 2 * n - 2 * halo
         total = 0
         for y0 in range(0, H, th):
             for x0 in range(0, W, tw):

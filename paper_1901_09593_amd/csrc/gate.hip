@@ -550,9 +550,9 @@ __device__ __forceinline__ void gate_tile_box(const GateArgs& a, int bx, int by)
     }
 }
 
-// at most 168 VGPRs: three waves per SIMD
+// uint8 tiles at most 128 VGPRs (four waves per SIMD), float ones 168 (three)
 template <typename T>
-constexpr int GATE_MIN_WAVES = 3;
+constexpr int GATE_MIN_WAVES = std::is_same<T, uint8_t>::value ? 4 : 3;
 
 template <typename T, int NW, int MODE>
 __device__ __forceinline__ void gate_tile_any(const GateArgs& a, int bx, int by)
