@@ -538,10 +538,13 @@ struct GraphKey {
 };
 struct GraphEntry {
     hipGraphExec_t exec = nullptr;
-    char* table = nullptr;  // device copy of the plan's table, owned by the entry
+    char* table = nullptr;      // device copy of the plan's table, owned by the entry
+    hipEvent_t done = nullptr;  // recorded after each replay: the last replay's end
+    uint64_t last_use = 0;
 };
 static std::mutex g_graph_mu;
 static std::map<GraphKey, GraphEntry> g_graphs;
+static uint64_t g_graph_clock = 0;
 static const size_t GRAPH_CACHE_MAX = 64;
 
 // Key bytes: direction tag, device, pairs, cfg, then the call's buffer pointers.
@@ -567,6 +570,7 @@ static void destroy_entry(GraphEntry& e)
 {
     if (e.exec) hipGraphExecDestroy(e.exec);
     if (e.table) hipFree(e.table);
+    if (e.done) hipEventDestroy(e.done);
     e = GraphEntry{};
 }
 
@@ -604,6 +608,7 @@ static int capture_graph(int dev, const BatchPlan& pl, const msibm_config* cfg, 
     }
     if (e == hipSuccess) e = hipGraphInstantiate(&ent->exec, graph, nullptr, nullptr, 0);
     if (graph) hipGraphDestroy(graph);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&ent->done, hipEventDisableTiming);
     if (e != hipSuccess) {
         destroy_entry(*ent);
         return hip_fail(e, "graph capture", err);
@@ -619,24 +624,38 @@ static int run_plan(int dev, const msibm_config* cfg, const GraphKey* key, Build
 {
     hipError_t e;
     if (key) {
-        std::lock_guard<std::mutex> g(g_graph_mu);
-        auto it = g_graphs.find(*key);
-        if (it == g_graphs.end()) {
-            BatchPlan pl;
-            build(pl);
-            GraphEntry ent;
-            const int rc = capture_graph(dev, pl, cfg, &ent, err);
-            if (rc != MSIBM_OK) return rc;
-            if (g_graphs.size() >= GRAPH_CACHE_MAX) {  // drop everything rather than track use
-                hipDeviceSynchronize();
-                for (auto& kv : g_graphs) destroy_entry(kv.second);
-                g_graphs.clear();
+        // a full cache gives up its least recently replayed entry; the entry
+        // leaves the map under the lock and is freed after the lock, once its
+        // last replay has ended (a wait on that replay only)
+        GraphEntry victim;
+        {
+            std::lock_guard<std::mutex> g(g_graph_mu);
+            auto it = g_graphs.find(*key);
+            if (it == g_graphs.end()) {
+                BatchPlan pl;
+                build(pl);
+                GraphEntry ent;
+                const int rc = capture_graph(dev, pl, cfg, &ent, err);
+                if (rc != MSIBM_OK) return rc;
+                if (g_graphs.size() >= GRAPH_CACHE_MAX) {
+                    auto lru = g_graphs.begin();
+                    for (auto jt = g_graphs.begin(); jt != g_graphs.end(); ++jt)
+                        if (jt->second.last_use < lru->second.last_use) lru = jt;
+                    victim = lru->second;
+                    g_graphs.erase(lru);
+                }
+                it = g_graphs.emplace(*key, ent).first;
             }
-            it = g_graphs.emplace(*key, ent).first;
+            it->second.last_use = ++g_graph_clock;
+            const int slot = timing_begin("batch_graph", s);
+            e = hipGraphLaunch(it->second.exec, s);
+            timing_end(slot, s);
+            if (e == hipSuccess) e = hipEventRecord(it->second.done, s);
         }
-        const int slot = timing_begin("batch_graph", s);
-        e = hipGraphLaunch(it->second.exec, s);
-        timing_end(slot, s);
+        if (victim.exec) {
+            hipEventSynchronize(victim.done);
+            destroy_entry(victim);
+        }
         if (e != hipSuccess) return hip_fail(e, "graph launch", err);
         return MSIBM_OK;
     }

@@ -115,6 +115,29 @@ def test_graph_cache_keys_on_outputs(M):
     _equal(ref, b, "b")
 
 
+def test_graph_cache_evicts_least_recently_used(M):
+    """More distinct calls than the graph cache holds (64 entries): each new
+    call past the limit gives up the least recently replayed graph after its
+    last replay ended; every call's output equals the direct path's, and a
+    call whose graph was evicted is captured again and still equal."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    L = torch.from_numpy(rng.integers(0, 256, (40, 72)).astype(np.uint8)).cuda()
+    R = torch.from_numpy(rng.integers(0, 256, (40, 72)).astype(np.uint8)).cuda()
+    n, r, eps, D, K = 2, 1, 0.065, 16, 2
+    ref = M.disparity_many([L], [R], [D], [K], n, r, eps)
+    flags = M.FLAG_BATCHED | M.FLAG_GRAPH
+    keep = [M.disparity_many([L], [R], [D], [K], n, r, eps, flags=flags) for _ in range(70)]
+    torch.cuda.synchronize()
+    for i, got in enumerate(keep):
+        _equal(ref, got, i)
+    first = keep[0]
+    for t in first[0].values():
+        t.fill_(-5 if t.dtype == torch.int16 else 5.0)
+    M.disparity_many([L], [R], [D], [K], n, r, eps, flags=flags, outputs=first)
+    torch.cuda.synchronize()
+    _equal(ref, first, "recaptured")
+
+
 @pytest.mark.skip(reason=PERSISTENT_OFF)
 @pytest.mark.parametrize("dtype,n,r,rs", [("u8", 4, 2, 0), ("u8", 3, 3, 0), ("f32", 5, 2, 0),
                                           ("f32", 3, 2, 3)])
