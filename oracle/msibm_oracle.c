@@ -124,9 +124,9 @@ double orc_zncc(const double* L, const double* R, int H, int W, int n,
  * Restricted search (Eqs. 8-9, first branch): the prior is the coarser map
  * upsampled by nearest neighbour with its values doubled,
  * dhat = 2 d^{k+1}(i/2, j/2); with c = min(dhat, j) the interval is
- * [max(0, c - r), min(D_k - 1, j, c + r)].  Readings: the paper's open interval
- * around dhat with "3 comparisons" is taken as the closed radius-r interval,
- * and the prior is doubled because d_max halves per level. */
+ * [max(0, c - r), min(D_k - 1, j, c + r)].  Readings: the paper's interval
+ * around dhat, stated as open and as three candidates, is taken as the closed
+ * radius-r interval, and the prior is doubled because d_max halves per level. */
 static void cand_range(int i, int j, int Dk, const int16_t* coarse, int Wc,
                        int r, int* lo, int* hi)
 {
