@@ -395,11 +395,11 @@ __device__ __forceinline__ void stats_tile_u8(const uint8_t* __restrict__ srcA, 
     constexpr int TASKS = rows * 8, NT = (TASKS + 255) / 256;  // (row, 8-column segment) tasks
     const size_t corner = (size_t)min(y0, H - 1) * spitch + min(x0, W - 1);
     const int cv[2] = {srcA[corner], srcB[corner]};
-    // interior tiles of images with 4-byte aligned rows load whole words: a
-    // thread's bytes start at the same offset SH within a word in every row
-    constexpr int SH = (4 - n % 4) % 4, NDW = (SH + NF + 3) / 4;
-    const bool words = x0 - n - SH >= 0 && x0 + ST_W + n + 3 < W && (spitch & 3) == 0 &&
-                       ((reinterpret_cast<uintptr_t>(srcA) | reinterpret_cast<uintptr_t>(srcB)) & 3) == 0;
+    // interior tiles load whole aligned words: a thread's NF bytes start at
+    // byte offset sh (of its row's address) within the first of NG + 1 words,
+    // and v_alignbyte lines them up four at a time (any row pitch)
+    constexpr int NG = (NF + 3) / 4;
+    const bool words = x0 - n >= 0 && x0 + ST_W + n + 8 <= W;
     int f[NT][2][NF];
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
@@ -408,18 +408,28 @@ __device__ __forceinline__ void stats_tile_u8(const uint8_t* __restrict__ srcA, 
         const size_t ro = (size_t)clampi(y0 - n + tr, 0, H - 1) * spitch;
         const int cx = x0 + ST_SEG * seg - n;
         if (words) {
-            const uint32_t* pa = reinterpret_cast<const uint32_t*>(srcA + ro + cx - SH);
-            const uint32_t* pb = reinterpret_cast<const uint32_t*>(srcB + ro + cx - SH);
-            uint32_t wa[NDW], wb[NDW];
+            const uintptr_t aa = reinterpret_cast<uintptr_t>(srcA + ro + cx);
+            const uintptr_t ab = reinterpret_cast<uintptr_t>(srcB + ro + cx);
+            const uint32_t* pa = reinterpret_cast<const uint32_t*>(aa & ~(uintptr_t)3);
+            const uint32_t* pb = reinterpret_cast<const uint32_t*>(ab & ~(uintptr_t)3);
+            const uint32_t sha = (uint32_t)(aa & 3), shb = (uint32_t)(ab & 3);
+            uint32_t wa[NG + 1], wb[NG + 1];
 #pragma unroll
-            for (int d = 0; d < NDW; ++d) {
+            for (int d = 0; d <= NG; ++d) {
                 wa[d] = pa[d];
                 wb[d] = pb[d];
             }
 #pragma unroll
-            for (int t = 0; t < NF; ++t) {
-                f[q][0][t] = (wa[(t + SH) >> 2] >> (8 * ((t + SH) & 3))) & 0xff;
-                f[q][1][t] = (wb[(t + SH) >> 2] >> (8 * ((t + SH) & 3))) & 0xff;
+            for (int g = 0; g < NG; ++g) {
+                const uint32_t ga = __builtin_amdgcn_alignbyte(wa[g + 1], wa[g], sha);
+                const uint32_t gb = __builtin_amdgcn_alignbyte(wb[g + 1], wb[g], shb);
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    if (4 * g + b < NF) {
+                        f[q][0][4 * g + b] = (ga >> (8 * b)) & 0xff;
+                        f[q][1][4 * g + b] = (gb >> (8 * b)) & 0xff;
+                    }
+                }
             }
         } else {
 #pragma unroll
