@@ -2,12 +2,13 @@
 // stage whose grid holds the tiles of every pair at that stage.
 //
 // Stages, in stream order: the pyramid reduce of level k for k = 1..K_max-1,
-// the window statistics of every level, then the matching of level k from
-// k = K_max-1 down to 0 (a pair whose coarsest level is k does its full search
-// in that step; finer levels refine the map the previous step wrote).  Within
-// a launch no tile waits on another; the stream order between launches carries
-// every dependency.  A matching step holds one launch per (mode, element type)
-// present, since those are separate kernel instances.
+// the window statistics of every level, the full search of every pair's
+// coarsest level (one launch for all levels), then the restricted search of
+// level k from k = K_max-2 down to 0, each refining the map the previous step
+// wrote.  Within a launch no tile waits on another; the stream order between
+// launches carries every dependency.  A matching step holds one launch per
+// (mode, element type, window size) present, since those are separate kernel
+// instances.
 //
 // Launches find their tiles through a table of segments (one per pair and
 // level) and per-level descriptors.  Without MSIBM_FLAG_GRAPH the table is
@@ -181,8 +182,35 @@ static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg
     auto mode_of = [&](int p, int k) {
         return (k == K[p] - 1) ? MODE_FULL : ((k == 0 && cfg->soft_radius > 0) ? MODE_SOFT : MODE_REFINE);
     };
+    // A pair's coarsest level is searched in full from that level's statistics
+    // alone, so the full searches of all levels share one launch per window
+    // size and element type ahead of the refinement chain.
+    {
+        std::vector<int> ns;
+        for (int k = Kmax - 1; k >= lowest; --k) {
+            const int n = level_n(cfg, k);
+            bool seen = false;
+            for (int v : ns) seen = seen || v == n;
+            if (!seen) ns.push_back(n);
+        }
+        for (int n : ns)
+            for (int dt = 0; dt < 2; ++dt) {
+                bool opened = false;
+                for (int k = Kmax - 1; k >= lowest; --k) {
+                    if (level_n(cfg, k) != n) continue;
+                    for (int p = 0; p < np; ++p) {
+                        if (k != K[p] - 1 || dtype_at(p, k) != dt) continue;
+                        if (!opened) {
+                            begin(STAGE_MATCH, k, MODE_FULL, dt, FULL_NC);
+                            opened = true;
+                        }
+                        add(SEG_FULL, p, k);
+                    }
+                }
+            }
+    }
     for (int k = Kmax - 1; k >= lowest; --k) {
-        for (int m = 0; m < 3; ++m)
+        for (int m = 1; m < 3; ++m)
             for (int dt = 0; dt < 2; ++dt) {
                 bool opened = false;
                 for (int p = 0; p < np; ++p) {
@@ -433,6 +461,7 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
         else if (l.kind == STAGE_COUNT) snprintf(lab, sizeof(lab), "batch_fused_count");
         else if (l.kind == STAGE_FUSED) snprintf(lab, sizeof(lab), "batch_fused_backward_l0");
         else if (l.kind == STAGE_L1_FINAL) snprintf(lab, sizeof(lab), "batch_fused_loss");
+        else if (l.mode == MODE_FULL) snprintf(lab, sizeof(lab), "batch_match_full");
         else snprintf(lab, sizeof(lab), "batch_match_%s_l%d", mode_name[l.mode], l.level);
         const int slot = timed ? timing_begin(lab, s) : -1;
         hipError_t e = hipSuccess;

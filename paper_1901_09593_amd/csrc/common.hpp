@@ -263,6 +263,22 @@ __device__ __forceinline__ int segment_of(const Segment* segs, int nseg, int b)
 
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return min(max(v, lo), hi); }
 
+// Task index of workgroup b of a multi-segment launch.  The hardware deals
+// workgroups round-robin to the 8 XCDs, each with its own L2; here the k-th
+// workgroup of XCD x takes task (k / XCD_RUN * 8 + x) * XCD_RUN + k % XCD_RUN,
+// so every XCD works through runs of XCD_RUN consecutive tiles (neighbours,
+// which share window halos, meet in one L2) while the runs of every segment
+// are spread over all XCDs.  Workgroups past the last whole group of 8 runs
+// keep their index.  A bijection on [0, gridDim.x).
+constexpr int XCD_RUN = 64;
+__device__ __forceinline__ int xcd_task(int b)
+{
+    const int full = (int)(gridDim.x / (8 * XCD_RUN)) * (8 * XCD_RUN);
+    if (b >= full) return b;
+    const int x = b & 7, k = b >> 3;
+    return ((k / XCD_RUN) * 8 + x) * XCD_RUN + (k % XCD_RUN);
+}
+
 template <typename T>
 __device__ __forceinline__ float to_f(T v) { return static_cast<float>(v); }
 

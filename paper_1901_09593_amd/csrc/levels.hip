@@ -109,8 +109,9 @@ template <int NW>
 __global__ __launch_bounds__(256) void stats_multi_kernel(MultiArgs a)
 {
     __shared__ StatsSmem<NW> sm;
-    const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
-    stats_seg_tile<NW>(a, s, blockIdx.x - s.task0, sm);
+    const int b = xcd_task(blockIdx.x);
+    const Segment s = a.segs[segment_of(a.segs, a.nseg, b)];
+    stats_seg_tile<NW>(a, s, b - s.task0, sm);
 }
 
 // Statistics and reduce segments side by side in one launch (one pyramid step
@@ -122,9 +123,10 @@ __global__ __launch_bounds__(256) void levels_multi_kernel(MultiArgs a)
         StatsSmem<NW> st;
         ReduceSmem rd;
     } sm;
-    const Segment s = a.segs[segment_of(a.segs, a.nseg, blockIdx.x)];
-    if (s.type == SEG_STATS) stats_seg_tile<NW>(a, s, blockIdx.x - s.task0, sm.st);
-    else reduce_seg_tile(a, s, blockIdx.x - s.task0, sm.rd);
+    const int b = xcd_task(blockIdx.x);
+    const Segment s = a.segs[segment_of(a.segs, a.nseg, b)];
+    if (s.type == SEG_STATS) stats_seg_tile<NW>(a, s, b - s.task0, sm.st);
+    else reduce_seg_tile(a, s, b - s.task0, sm.rd);
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(float* a, float* b, size_t count)
