@@ -171,7 +171,12 @@ static void plan_stages(const msibm_pair* pairs, int np, const msibm_config* cfg
     // pyramid step k: level k's statistics (heavier tiles first) side by side
     // with the reduce that makes level k + 1
     for (int k = 0; k < Kmax; ++k) {
-        begin(STAGE_LEVELS, k, 0, 0, 0);
+        // a step whose statistics all read uint8 levels (their reduces then read
+        // the same uint8 images) takes the leaner uint8 kernel
+        bool all_u8 = true;
+        for (int p = 0; p < np; ++p)
+            if (k < K[p]) all_u8 = all_u8 && dtype_at(p, k) == MSIBM_U8;
+        begin(STAGE_LEVELS, k, 0, all_u8 ? MSIBM_U8 : MSIBM_F32, 0);
         for (int p = 0; p < np; ++p)
             if (k < K[p]) add(SEG_STATS, p, k);
         for (int p = 0; p < np; ++p)
@@ -480,7 +485,7 @@ static hipError_t enqueue_stages(const BatchPlan& pl, const char* table, const m
                 b.dpitch = d.pitch;
                 e = launch_blur(d.sdtype, b, s);
             }
-        } else if (l.kind == STAGE_LEVELS) e = launch_levels_multi(level_n(cfg, l.level), a, l.blocks, s);
+        } else if (l.kind == STAGE_LEVELS) e = launch_levels_multi(level_n(cfg, l.level), l.dtype, a, l.blocks, s);
         else if (l.kind == STAGE_STATS) e = launch_stats_multi(level_n(cfg, 0), a, l.blocks, s);
         else if (l.kind == STAGE_ZERO) {
             hipLaunchKernelGGL(zero_multi_kernel, dim3(l.blocks), dim3(256), 0, s, a);

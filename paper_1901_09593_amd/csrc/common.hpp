@@ -300,7 +300,9 @@ hipError_t launch_match(int n, int dtype, int mode, int nc, const MatchArgs& a, 
 
 // Multi-segment launches (batched path); `blocks` = total tiles of the segments.
 hipError_t launch_match_multi(int n, int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);
-hipError_t launch_levels_multi(int n, const MultiArgs& a, int blocks, hipStream_t s);
+// dtype MSIBM_U8: every statistics and reduce tile of the launch reads a
+// uint8 level (a leaner kernel); anything else: the general kernel.
+hipError_t launch_levels_multi(int n, int dtype, const MultiArgs& a, int blocks, hipStream_t s);
 hipError_t launch_stats_multi(int n, const MultiArgs& a, int blocks, hipStream_t s);
 hipError_t launch_match_multi_n1(int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);
 hipError_t launch_match_multi_n2(int dtype, int mode, int nc, const MultiArgs& a, int blocks, hipStream_t s);

@@ -14,6 +14,8 @@
 //   accumulated in double precision, so the flat test and A match the
 //   double-precision definition; every level and view of a pair in one launch.
 //   HBM-bound: 1 or 4 bytes read and 12 bytes written per pixel.
+#include <type_traits>
+
 #include "levels_impl.hpp"
 
 namespace msibm {
@@ -41,7 +43,7 @@ __device__ __forceinline__ void stats_block(const StatsArgs& a, int b, StatsSmem
     const int x0 = (t % tw) * ST_W, y0 = (t / tw) * stats_tile_h(g.dtype);
     if (g.dtype == 0)
         stats_tile_u8<NW>((const uint8_t*)g.src, g.dst, (const uint8_t*)h.src, h.dst, g.H, g.W, g.spitch, g.dpitch,
-                          a.var_eps, x0, y0, sm);
+                          a.var_eps, x0, y0, sm.i);
     else
         stats_tile<float, NW>((const float*)g.src, g.dst, (const float*)h.src, h.dst, g.H, g.W, g.spitch,
                               g.dpitch, a.var_eps, x0, y0, sm);
@@ -68,7 +70,8 @@ __global__ __launch_bounds__(TW_THREADS) void tower_kernel(TowerArgs a)
 // Tile t of a reduce segment: reads level k-1 of its pair (the caller's input
 // at k = 1, also where level 0 is matched on its blurred copy) and writes
 // level k of one view.
-__device__ __forceinline__ void reduce_seg_tile(const MultiArgs& a, const Segment& s, int t, ReduceSmem& sm)
+template <typename S>
+__device__ __forceinline__ void reduce_seg_tile(const MultiArgs& a, const Segment& s, int t, ReduceSmemT<S>& sm)
 {
     const LevelDesc* lv = a.levels + a.level_base[s.pair];
     const LevelDesc& P = lv[s.level - 1];
@@ -86,8 +89,12 @@ __device__ __forceinline__ void reduce_seg_tile(const MultiArgs& a, const Segmen
     ra.Ho = L.H;
     ra.Wo = L.W;
     ra.dpitch = L.pitch;
-    if ((own ? P.sdtype : P.dtype) == 0) reduce_tile<uint8_t>(ra, 0, tx, ty, sm);
-    else reduce_tile<float>(ra, 0, tx, ty, sm);
+    if constexpr (std::is_same<S, uint8_t>::value) {
+        reduce_tile<uint8_t, uint8_t>(ra, 0, tx, ty, sm);  // the launch holds uint8 sources only
+    } else {
+        if ((own ? P.sdtype : P.dtype) == 0) reduce_tile<uint8_t, float>(ra, 0, tx, ty, sm);
+        else reduce_tile<float, float>(ra, 0, tx, ty, sm);
+    }
 }
 
 // Tile t of a statistics segment: both views of one level of its pair.
@@ -98,7 +105,7 @@ __device__ __forceinline__ void stats_seg_tile(const MultiArgs& a, const Segment
     const int x0 = (t % s.tiles_x) * ST_W, y0 = (t / s.tiles_x) * stats_tile_h(L.dtype);
     if (L.dtype == 0)
         stats_tile_u8<NW>((const uint8_t*)L.img[0], L.stat[0], (const uint8_t*)L.img[1], L.stat[1], L.H, L.W,
-                          L.pitch, L.W, a.var_eps, x0, y0, sm);
+                          L.pitch, L.W, a.var_eps, x0, y0, sm.i);
     else
         stats_tile<float, NW>((const float*)L.img[0], L.stat[0], (const float*)L.img[1], L.stat[1], L.H, L.W,
                               L.pitch, L.W, a.var_eps, x0, y0, sm);
@@ -127,6 +134,31 @@ __global__ __launch_bounds__(256) void levels_multi_kernel(MultiArgs a)
     const Segment s = a.segs[segment_of(a.segs, a.nseg, b)];
     if (s.type == SEG_STATS) stats_seg_tile<NW>(a, s, b - s.task0, sm.st);
     else reduce_seg_tile(a, s, b - s.task0, sm.rd);
+}
+
+// The same for a pyramid step whose statistics and reduce tiles all read
+// uint8 levels (level 0 of uint8 pairs): integer statistics only and the
+// reduce's input staged as bytes, so the LDS (and the registers of the float
+// paths) no longer limit how many workgroups share a CU.
+constexpr int LEVELS_U8_MIN_BLOCKS = 7;
+template <int NW>
+__global__ __launch_bounds__(256, LEVELS_U8_MIN_BLOCKS) void levels_u8_multi_kernel(MultiArgs a)
+{
+    __shared__ union {
+        StatsSmemI<NW> st;
+        ReduceSmemU8 rd;
+    } sm;
+    const int b = xcd_task(blockIdx.x);
+    const Segment s = a.segs[segment_of(a.segs, a.nseg, b)];
+    const int t = b - s.task0;
+    if (s.type == SEG_STATS) {
+        const LevelDesc& L = a.levels[a.level_base[s.pair] + s.level];
+        const int x0 = (t % s.tiles_x) * ST_W, y0 = (t / s.tiles_x) * SU_H;
+        stats_tile_u8<NW>((const uint8_t*)L.img[0], L.stat[0], (const uint8_t*)L.img[1], L.stat[1], L.H, L.W,
+                          L.pitch, L.W, a.var_eps, x0, y0, sm.st);
+    } else {
+        reduce_seg_tile(a, s, t, sm.rd);
+    }
 }
 
 __global__ __launch_bounds__(256) void zero_kernel(float* a, float* b, size_t count)
@@ -412,9 +444,21 @@ hipError_t launch_stats(StatsArgs a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_levels_multi(int n, const MultiArgs& a, int blocks, hipStream_t s)
+hipError_t launch_levels_multi(int n, int dtype, const MultiArgs& a, int blocks, hipStream_t s)
 {
     if (blocks < 1 || a.nseg < 1) return hipErrorInvalidValue;
+    if (dtype == MSIBM_U8) {
+        switch (n) {
+            case 1: hipLaunchKernelGGL(levels_u8_multi_kernel<1>, dim3(blocks), dim3(256), 0, s, a); break;
+            case 2: hipLaunchKernelGGL(levels_u8_multi_kernel<2>, dim3(blocks), dim3(256), 0, s, a); break;
+            case 3: hipLaunchKernelGGL(levels_u8_multi_kernel<3>, dim3(blocks), dim3(256), 0, s, a); break;
+            case 4: hipLaunchKernelGGL(levels_u8_multi_kernel<4>, dim3(blocks), dim3(256), 0, s, a); break;
+            case 5: hipLaunchKernelGGL(levels_u8_multi_kernel<5>, dim3(blocks), dim3(256), 0, s, a); break;
+            case 6: hipLaunchKernelGGL(levels_u8_multi_kernel<6>, dim3(blocks), dim3(256), 0, s, a); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (n) {
         case 1: hipLaunchKernelGGL(levels_multi_kernel<1>, dim3(blocks), dim3(256), 0, s, a); break;
         case 2: hipLaunchKernelGGL(levels_multi_kernel<2>, dim3(blocks), dim3(256), 0, s, a); break;

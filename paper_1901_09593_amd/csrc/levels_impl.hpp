@@ -8,20 +8,25 @@ namespace msibm {
 constexpr int RD_W = 64, RD_H = 16;                 // output tile
 constexpr int RD_IW = 2 * RD_W + 3, RD_IH = 2 * RD_H + 3;  // input region (5-tap halo)
 
-struct ReduceSmem {
-    float in[RD_IH][RD_IW + 1];
+// The staged input region (floats, or the bytes themselves for a uint8
+// source, a quarter of the LDS) and the horizontal sums.
+template <typename S>
+struct ReduceSmemT {
+    S in[RD_IH][RD_IW + 1];
     float hs[RD_IH][RD_W + 1];
 };
+using ReduceSmem = ReduceSmemT<float>;
+using ReduceSmemU8 = ReduceSmemT<uint8_t>;
 
 // One 16 x 64 output tile of one view: the input region is staged in LDS once,
 // the horizontal 5-tap sums are taken at even columns, then the vertical ones at
 // even rows.  Same arithmetic order as a direct evaluation: h = sum_b w_b x,
 // out = 2^-8 sum_t w_t h_t with integer weights, all partial sums exact for
 // uint8 input up to level 2.  Every thread of the workgroup must call it.
-template <typename T>
-__device__ __forceinline__ void reduce_tile(const ReduceArgs& a, int view, int bx, int by, ReduceSmem& sm)
+template <typename T, typename S>
+__device__ __forceinline__ void reduce_tile(const ReduceArgs& a, int view, int bx, int by, ReduceSmemT<S>& sm)
 {
-    float (*in)[RD_IW + 1] = sm.in;
+    S (*in)[RD_IW + 1] = sm.in;
     float (*hs)[RD_W + 1] = sm.hs;
     const T* __restrict__ src = static_cast<const T*>(a.src[view]);
     float* __restrict__ dst = a.dst[view];
@@ -49,7 +54,7 @@ __device__ __forceinline__ void reduce_tile(const ReduceArgs& a, int view, int b
 #pragma unroll
         for (int ci = 0; ci < CI; ++ci) {
             const int cc = lane + 64 * ci;
-            if (rr < RD_IH && cc < RD_IW) in[rr][cc] = to_f(v[ri][ci]);
+            if (rr < RD_IH && cc < RD_IW) in[rr][cc] = (S)v[ri][ci];
         }
     }
     __syncthreads();
@@ -57,7 +62,7 @@ __device__ __forceinline__ void reduce_tile(const ReduceArgs& a, int view, int b
     for (int rr = wave; rr < RD_IH; rr += 4) {
         float h = 0.f;
 #pragma unroll
-        for (int b = 0; b < 5; ++b) h = fmaf(w[b], in[rr][2 * lane + b], h);
+        for (int b = 0; b < 5; ++b) h = fmaf(w[b], to_f(in[rr][2 * lane + b]), h);
         hs[rr][lane] = h;
     }
     __syncthreads();
@@ -77,7 +82,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void reduce_kernel(ReduceArgs a)
 {
     __shared__ ReduceSmem sm;
-    reduce_tile<T>(a, blockIdx.z, blockIdx.x, blockIdx.y, sm);
+    reduce_tile<T, float>(a, blockIdx.z, blockIdx.x, blockIdx.y, sm);
 }
 
 // One 16 x 64 tile of the same binomial blur at every pixel (stride 1) of one
@@ -387,20 +392,22 @@ template <int NW>
 __device__ __forceinline__ void stats_tile_u8(const uint8_t* __restrict__ srcA, WinStat* __restrict__ dstA,
                                               const uint8_t* __restrict__ srcB, WinStat* __restrict__ dstB, int H,
                                               int W, int spitch, int dpitch, double var_eps, int x0, int y0,
-                                              StatsSmem<NW>& sm)
+                                              StatsSmemI<NW>& sm)
 {
-    int* h1 = sm.i.h1;
-    int* h2 = sm.i.h2;
+    int* h1 = sm.h1;
+    int* h2 = sm.h2;
     constexpr int n = NW, wn = 2 * NW + 1, rows = SU_H + 2 * NW, NF = ST_SEG + 2 * NW;
     constexpr int TASKS = rows * 8, NT = (TASKS + 255) / 256;  // (row, 8-column segment) tasks
     const size_t corner = (size_t)min(y0, H - 1) * spitch + min(x0, W - 1);
     const int cv[2] = {srcA[corner], srcB[corner]};
     // interior tiles load whole aligned words: a thread's NF bytes start at
     // byte offset sh (of its row's address) within the first of NG + 1 words,
-    // and v_alignbyte lines them up four at a time (any row pitch)
+    // and v_alignbyte lines them up four at a time (any row pitch); edge tiles
+    // load byte by byte (clamped) and pack the bytes into words (offset 0).
+    // The words are kept packed until each view is summed.
     constexpr int NG = (NF + 3) / 4;
     const bool words = x0 - n >= 0 && x0 + ST_W + n + 8 <= W;
-    int f[NT][2][NF];
+    uint32_t wd[NT][2][NG + 1], sh[NT][2];
 #pragma unroll
     for (int q = 0; q < NT; ++q) {
         const int task = min((int)threadIdx.x + 256 * q, TASKS - 1);
@@ -408,35 +415,27 @@ __device__ __forceinline__ void stats_tile_u8(const uint8_t* __restrict__ srcA, 
         const size_t ro = (size_t)clampi(y0 - n + tr, 0, H - 1) * spitch;
         const int cx = x0 + ST_SEG * seg - n;
         if (words) {
-            const uintptr_t aa = reinterpret_cast<uintptr_t>(srcA + ro + cx);
-            const uintptr_t ab = reinterpret_cast<uintptr_t>(srcB + ro + cx);
-            const uint32_t* pa = reinterpret_cast<const uint32_t*>(aa & ~(uintptr_t)3);
-            const uint32_t* pb = reinterpret_cast<const uint32_t*>(ab & ~(uintptr_t)3);
-            const uint32_t sha = (uint32_t)(aa & 3), shb = (uint32_t)(ab & 3);
-            uint32_t wa[NG + 1], wb[NG + 1];
 #pragma unroll
-            for (int d = 0; d <= NG; ++d) {
-                wa[d] = pa[d];
-                wb[d] = pb[d];
-            }
+            for (int vw = 0; vw < 2; ++vw) {
+                const uintptr_t ad = reinterpret_cast<uintptr_t>((vw ? srcB : srcA) + ro + cx);
+                const uint32_t* pw = reinterpret_cast<const uint32_t*>(ad & ~(uintptr_t)3);
+                sh[q][vw] = (uint32_t)(ad & 3);
 #pragma unroll
-            for (int g = 0; g < NG; ++g) {
-                const uint32_t ga = __builtin_amdgcn_alignbyte(wa[g + 1], wa[g], sha);
-                const uint32_t gb = __builtin_amdgcn_alignbyte(wb[g + 1], wb[g], shb);
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    if (4 * g + b < NF) {
-                        f[q][0][4 * g + b] = (ga >> (8 * b)) & 0xff;
-                        f[q][1][4 * g + b] = (gb >> (8 * b)) & 0xff;
-                    }
-                }
+                for (int d = 0; d <= NG; ++d) wd[q][vw][d] = pw[d];
             }
         } else {
 #pragma unroll
-            for (int t = 0; t < NF; ++t) {
-                const int cc = clampi(cx + t, 0, W - 1);
-                f[q][0][t] = srcA[ro + cc];
-                f[q][1][t] = srcB[ro + cc];
+            for (int vw = 0; vw < 2; ++vw) {
+                const uint8_t* src = vw ? srcB : srcA;
+                sh[q][vw] = 0;
+#pragma unroll
+                for (int g = 0; g <= NG; ++g) {
+                    uint32_t w = 0;
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        if (4 * g + b < NF) w |= (uint32_t)src[ro + clampi(cx + 4 * g + b, 0, W - 1)] << (8 * b);
+                    wd[q][vw][g] = w;
+                }
             }
         }
     }
@@ -452,10 +451,14 @@ __device__ __forceinline__ void stats_tile_u8(const uint8_t* __restrict__ srcA, 
             if (task < TASKS) {
                 int v[NF], sq[NF];
 #pragma unroll
-                for (int t = 0; t < NF; ++t) {
-                    v[t] = f[q][vw][t] - c;
-                    sq[t] = v[t] * v[t];
+                for (int g = 0; g < NG; ++g) {
+                    const uint32_t w = __builtin_amdgcn_alignbyte(wd[q][vw][g + 1], wd[q][vw][g], sh[q][vw]);
+#pragma unroll
+                    for (int b = 0; b < 4; ++b)
+                        if (4 * g + b < NF) v[4 * g + b] = (int)((w >> (8 * b)) & 0xffu) - c;
                 }
+#pragma unroll
+                for (int t = 0; t < NF; ++t) sq[t] = v[t] * v[t];
                 int s1 = 0, s2 = 0;
 #pragma unroll
                 for (int t = 0; t < wn; ++t) {
