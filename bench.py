@@ -27,8 +27,9 @@ Prints ONE JSON line.  `value` = pixel-disparity ZNCC evaluations per second
                     step (one call, one graph for forward, loss and backward);
   cpu_baseline      the FP64 oracle timed on the host cores over pairs of the
                     same batch (a reported baseline, not a target).
-`python bench.py --copy-probe BYTES` only runs a plain device copy (used to
-scale hardware traffic counters) and prints nothing.
+`python bench.py --copy-probe BYTES` only runs a plain device copy of known
+size (used to check how the hardware traffic counters count bytes) and prints
+nothing.
 """
 import argparse
 import hashlib
