@@ -39,8 +39,9 @@
 // clamped to [-1, 1].  uint8 levels need none of this: staged as they are,
 // every product is an integer up to 255^2 and every window sum of products an
 // integer below 2^24, exact in float, so with the exact window sums S1 of the
-// statistics the cross term is formed exactly, N C = N S - S1_l S1_r (in
-// double), and only the final products round.
+// statistics the cross term is formed exactly, N C = N S - S1_l S1_r (in 32-bit
+// integers: 24-bit multiplies, the difference within +-2^31), and only the
+// final products round.
 #pragma once
 
 #include <type_traits>
@@ -521,7 +522,8 @@ __device__ __forceinline__ void match_tile(
     using G = Geo<NW, CH, TileRows<SPLIT, TY>::value>;
     static_assert(!SPLIT || MODE != MODE_SOFT, "the soft level needs every slot of a block in one thread");
     static_assert(!SPLIT || TY == MATCH_TY, "the candidate split combines the winners of four waves");
-    constexpr float Nf = (float)((2 * NW + 1) * (2 * NW + 1));
+    constexpr int NN = (2 * NW + 1) * (2 * NW + 1);
+    constexpr float Nf = (float)NN;
     // A block of a restricted search scores the candidate slots [zs, zs + NCF).
     // Unsplit, that is one window of NC = NCF slots; split (RSPLIT), the span is
     // covered by windows of NC slots, one per wave (NCX: the span rounded up to
@@ -734,6 +736,7 @@ __device__ __forceinline__ void match_tile(
 #pragma unroll
                 for (int rowp = 0; rowp < 2; ++rowp) {
                     float smc[NC + 1], sis[NC + 1];
+                    int smi[NC + 1];  // uint8: the exact right window sums as integers
                     if (SL) {
                         const int so = (lrow0 + rowp) * G::SSTRIDE;
 #pragma unroll
@@ -741,6 +744,7 @@ __device__ __forceinline__ void match_tile(
                             const int o = so + ((qq & 1) ? bo - (qq >> 1) : be - (qq >> 1));
                             smc[qq] = sm.Sm[o];
                             sis[qq] = sm.Si[o];
+                            if constexpr (U8) smi[qq] = (int)smc[qq];
                         }
                     } else {
 #pragma unroll
@@ -748,6 +752,7 @@ __device__ __forceinline__ void match_tile(
                             const SR st = stg[rowp][SL ? 0 : qq];
                             if constexpr (U8) {
                                 smc[qq] = st.s1;
+                                smi[qq] = (int)st.s1;
                             } else {
                                 smc[qq] = (st.x - cR) + st.y;
                             }
@@ -763,8 +768,13 @@ __device__ __forceinline__ void match_tile(
                             const int qq = s + 1 - cp;
                             float C;
                             if constexpr (U8) {
-                                // C N = N S - S1_l S1_r, exact in double (integers below 2^53)
-                                C = (float)fma((double)ndl[p], (double)smc[qq], (double)Nf * (double)S[p][s]);
+                                // C N = N S - S1_l S1_r in 32-bit integers: every factor
+                                // is an integer below 2^24 and the difference lies within
+                                // +-2^31 up to 13x13 windows, so C N is exact and rounds
+                                // to float once
+                                const int ncn = __mul24((int)ndl[p], smi[qq]) +
+                                                (int)__umul24((unsigned)NN, (unsigned)(int)S[p][s]);
+                                C = (float)ncn;
                             } else {
                                 C = fmaf(ndl[p], smc[qq], S[p][s]);
                             }
