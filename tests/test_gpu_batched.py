@@ -56,7 +56,8 @@ def _equal(ref, got, tag=""):
 
 @pytest.mark.parametrize("dtypes,n,r,rs", [(("u8",), 4, 2, 0), (("u8",), 3, 3, 0), (("f32",), 5, 2, 0),
                                            (("f32",), 3, 2, 3), (("u8", "f32"), 2, 1, 0),
-                                           (("f32",), 6, 4, 4), (("u8",), 1, 0, 0)])
+                                           (("f32",), 6, 4, 4), (("u8",), 1, 0, 0), (("u8",), 5, 1, 0),
+                                           (("u8",), 6, 2, 0)])
 def test_batched_equals_plain(M, dtypes, n, r, rs):
     pairs = _batch(dtypes, seed=n * 10 + r, dmin=33 if rs else 24)  # soft needs K >= 2
     eps = 0.065 if dtypes == ("u8",) else 1e-6
