@@ -6,52 +6,11 @@ exact arithmetic beside them; see tests/golden/README.md for the format.  The
 values are exact rationals, so the oracle's FP64 results must agree to a few
 units in the last place.
 """
-import os
-from fractions import Fraction
-
 import numpy as np
 import pytest
 
 import oracle
-
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
-MATRICES = ("left", "right", "image", "expect", "disp", "cost")
-
-
-def _num(tok):
-    return float(Fraction(tok))
-
-
-def load_cases(name):
-    """Cases of one fixture file: dicts of scalar fields (lists of numbers)
-    and matrices (2-D float arrays)."""
-    cases, cur, mat = [], None, None
-    with open(os.path.join(GOLDEN, name)) as fh:
-        for raw in fh:
-            line = raw.strip()
-            if not line or line.startswith("#"):
-                continue
-            tok = line.split()
-            if tok[0] == "case":
-                cur, mat = {"name": tok[1]}, None
-            elif tok[0] == "end":
-                cases.append({k: (np.array(v) if k in MATRICES else v) for k, v in cur.items()})
-                cur, mat = None, None
-            elif tok[0] in MATRICES and len(tok) == 1:
-                mat = tok[0]
-                cur[mat] = []
-            elif mat is not None and not tok[0].isalpha():
-                cur[mat].append([_num(t) for t in tok])
-            else:
-                mat = None
-                cur[tok[0]] = tok[1] if tok[0] == "op" else [_num(t) for t in tok[1:]]
-    assert cur is None, f"{name}: unterminated case"
-    return cases
-
-
-def _ids(cases):
-    return [c["name"] for c in cases]
-
+from golden_cases import ids, load_cases
 
 ZNCC = load_cases("zncc_worked.txt")
 PYR = load_cases("pyramid_worked.txt")
@@ -63,7 +22,7 @@ def test_fixtures_are_there():
     assert len(ZNCC) == 4 and len(PYR) == 5 and len(MED) == 4 and len(BIC) == 3
 
 
-@pytest.mark.parametrize("case", ZNCC, ids=_ids(ZNCC))
+@pytest.mark.parametrize("case", ZNCC, ids=ids(ZNCC))
 def test_zncc_worked(case):
     n = int(case["n"][0])
     i, j = (int(v) for v in case["pixel"])
@@ -72,7 +31,7 @@ def test_zncc_worked(case):
     assert got == pytest.approx(case["expect"][0, 0], rel=1e-14, abs=1e-15)
 
 
-@pytest.mark.parametrize("case", PYR, ids=_ids(PYR))
+@pytest.mark.parametrize("case", PYR, ids=ids(PYR))
 def test_pyramid_worked(case):
     f = {"reduce": oracle.reduce, "blur": oracle.blur}[case["op"]]
     got = f(case["image"])
@@ -80,13 +39,13 @@ def test_pyramid_worked(case):
     np.testing.assert_allclose(got, case["expect"], rtol=1e-14, atol=1e-12)
 
 
-@pytest.mark.parametrize("case", MED, ids=_ids(MED))
+@pytest.mark.parametrize("case", MED, ids=ids(MED))
 def test_median_worked(case):
     got = oracle.median_filter(case["disp"].astype(np.int16), case["cost"], case["alpha"][0])
     np.testing.assert_array_equal(got, case["expect"].astype(np.int16))
 
 
-@pytest.mark.parametrize("case", BIC, ids=_ids(BIC))
+@pytest.mark.parametrize("case", BIC, ids=ids(BIC))
 def test_bicubic_worked(case):
     H, W = (int(v) for v in case["size"])
     got = oracle.bicubic_up(case["image"], H, W, case["a"][0])
