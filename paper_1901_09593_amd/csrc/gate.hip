@@ -158,8 +158,17 @@ __device__ __forceinline__ void gate_tile_box(const GateArgs& a, int bx, int by)
     short* const fbz = reinterpret_cast<short*>(fbe + TH * TW);
     uint8_t* const fgs = reinterpret_cast<uint8_t*>(fbz + TH * TW);
     __shared__ __attribute__((aligned(16))) float LsF[U8 ? 1 : GU_EW * RP];  // float: the left columns
-    __shared__ VT Vs[RR * GU_VP + VTAIL];
-    __shared__ float Hs[REPICK ? RR * GU_VP : 1];
+    // uint8 tiles up to 9 x 9 windows walk the candidates in a pipeline (the
+    // row pass of z beside the column pass of z + 1 and the box pass of z - 1,
+    // one barrier per candidate), with the column and 5-column sums in two
+    // buffers by candidate parity, within the 40 KB that keep four workgroups
+    // on a CU; float tiles (double column sums) and larger windows would lose a
+    // workgroup per CU, and take two barriers per candidate and one buffer
+    constexpr bool PIPE = U8 && NW <= 4;
+    constexpr int NB = PIPE ? 2 : 1;
+    constexpr int VSZ = RR * GU_VP + VTAIL, HSZ = REPICK ? RR * GU_VP : 1;
+    __shared__ VT Vs[NB * VSZ];
+    __shared__ float Hs[NB * HSZ];
     __shared__ float rcpT[36];
     __shared__ int s_xmax;
 
@@ -362,7 +371,7 @@ __device__ __forceinline__ void gate_tile_box(const GateArgs& a, int bx, int by)
             // so at most 2n + 2 prefixes are live
             const float4* rc = reinterpret_cast<const float4*>(RsF + (ce + zhi - z) * RP);
             const float4* lc = reinterpret_cast<const float4*>(LsF + ce * RP);
-            VT* vc = Vs + gu_idx(ce);
+            VT* vc = Vs + (z & (NB - 1)) * VSZ + gu_idx(ce);
             double P[ER + 1];
             P[0] = 0.0;
 #pragma unroll
@@ -391,7 +400,7 @@ __device__ __forceinline__ void gate_tile_box(const GateArgs& a, int bx, int by)
             for (int m = 1; m <= 4; ++m)
                 if (4 * k + m <= ER) P[4 * k + m] = __builtin_amdgcn_udot4(Lw[k], cut[m - 1], P[4 * k], false);
         }
-        VT* vc = Vs + gu_idx(ce);
+        VT* vc = Vs + (z & (NB - 1)) * VSZ + gu_idx(ce);
 #pragma unroll
         for (int y = 0; y < RR; ++y) vc[y * GU_VP] = (int)(P[y + 2 * NW + 1] - P[y]);
     };
@@ -412,7 +421,7 @@ __device__ __forceinline__ void gate_tile_box(const GateArgs& a, int bx, int by)
         }
         shift_in(0, nxt);
         nxt = srow[clampi(rx0 + su - (z + 1), 0, W - 1)];
-        const VT* vr = Vs + sy * GU_VP + gu_idx(su);
+        const VT* vr = Vs + (z & (NB - 1)) * VSZ + sy * GU_VP + gu_idx(su);
         VT v[VREAD];
 #pragma unroll
         for (int b = 0; b < VREAD; ++b) v[b] = vr[gu_idx(b)];
@@ -458,7 +467,7 @@ __device__ __forceinline__ void gate_tile_box(const GateArgs& a, int bx, int by)
             for (int q = 0; q < GU_RUN; ++q) Ex[q] = E[q];
 #pragma unroll
             for (int m = 0; m < 4; ++m) Ex[GU_RUN + m] = next_lane_in_row(E[m]);
-            float* hr = Hs + sy * GU_VP + gu_idx(su);
+            float* hr = Hs + (z & (NB - 1)) * HSZ + sy * GU_VP + gu_idx(su);
             float h = ((Ex[0] + Ex[1]) + (Ex[2] + Ex[3])) + Ex[4];
             hr[0] = h;
 #pragma unroll
@@ -472,7 +481,7 @@ __device__ __forceinline__ void gate_tile_box(const GateArgs& a, int bx, int by)
     // 5x5 sums of the scores at candidate z for the lane's four outputs
     auto boxpass = [&](int z, auto bulk_tag) {
         constexpr bool BULK = decltype(bulk_tag)::value;
-        const float* hc = Hs + 4 * bh * GU_VP + gu_idx(bc);
+        const float* hc = Hs + (z & (NB - 1)) * HSZ + 4 * bh * GU_VP + gu_idx(bc);
         float h[8];
 #pragma unroll
         for (int m = 0; m < 8; ++m) h[m] = hc[m * GU_VP];
@@ -508,9 +517,41 @@ __device__ __forceinline__ void gate_tile_box(const GateArgs& a, int bx, int by)
     // the candidates valid for the whole region, then the rest (separate
     // loops: no merge of the two forms inside the loop)
     const int zb = min(zbulk, zmax);
-    int z = 0;
-    for (; z <= zb; ++z) step(z, std::true_type{});
-    for (; z <= zmax; ++z) step(z, std::false_type{});
+    if constexpr (PIPE) {
+        using Tt = std::true_type;
+        using Ft = std::false_type;
+        // phase t: [staging of the chunk starting at t + 1 and a barrier]
+        // [row pass t, column pass t + 1, box pass t - 1]
+        auto phase = [&](int t, auto row_tag, auto box_tag, bool row, bool box) {
+            const int zn = t + 1;
+            if (zn <= zmax && (zn & (ZC - 1)) == 0) {  // the column pass of t read the last chunk
+                stage(zn);
+                __syncthreads();
+            }
+            if (row && scorer) rowpass(t, row_tag);
+            if (colw && zn <= zmax) colpass(zn);
+            if constexpr (REPICK)
+                if (box) boxpass(t - 1, box_tag);
+            __syncthreads();
+        };
+        if (zb >= 0) phase(0, Tt{}, Tt{}, true, false);
+        else phase(0, Ft{}, Ft{}, true, false);
+        int t = 1;
+        for (; t <= zb; ++t) phase(t, Tt{}, Tt{}, true, true);
+        if (zb >= 0 && t == zb + 1 && t <= zmax) {
+            phase(t, Ft{}, Tt{}, true, true);
+            ++t;
+        }
+        for (; t <= zmax; ++t) phase(t, Ft{}, Ft{}, true, true);
+        if constexpr (REPICK) {
+            if (zb == zmax) phase(zmax + 1, Ft{}, Tt{}, false, true);
+            else phase(zmax + 1, Ft{}, Ft{}, false, true);
+        }
+    } else {
+        int z = 0;
+        for (; z <= zb; ++z) step(z, std::true_type{});
+        for (; z <= zmax; ++z) step(z, std::false_type{});
+    }
 
     if constexpr (FUSED) {
         // the fallback results to their owners
