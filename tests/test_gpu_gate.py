@@ -256,14 +256,19 @@ def test_gating_degenerate_shapes(M, H, W, D, n):
                       alpha, 0.065)
 
 
-def test_gating_pitched_images_and_largest_range(M):
+@pytest.mark.parametrize("dtype", ["f32", "u8"])
+def test_gating_pitched_images_and_largest_range(M, dtype):
     """Row-pitched inputs, and a range of 2048 candidates (every tile walks up
-    to 2048 candidates; the right-most pixels checked against the oracle)."""
+    to 2048 candidates through 64 staged chunks; the right-most pixels checked
+    against the oracle)."""
     rng = np.random.Generator(np.random.PCG64(77))
     H, W, D, n = 12, 2100, 2048, 2
     base = synth.texture(rng, H, W + 40) * 255
-    wide_L = np.zeros((H, W + 11), np.float32)
-    wide_R = np.zeros((H, W + 11), np.float32)
+    npt = np.float32 if dtype == "f32" else np.uint8
+    if dtype == "u8":
+        base = np.clip(np.rint(base), 0, 255)
+    wide_L = np.zeros((H, W + 11), npt)
+    wide_R = np.zeros((H, W + 11), npt)
     wide_L[:, :W] = base[:, :W]          # a shift of 40: R(x - 40) = L(x)
     wide_R[:, :W] = base[:, 40:40 + W]
     Lg, Rg = dev(wide_L)[:, :W], dev(wide_R)[:, :W]
