@@ -536,13 +536,26 @@ __device__ __forceinline__ void gate_tile_box(const GateArgs& a, int bx, int by)
         };
         if (zb >= 0) phase(0, Tt{}, Tt{}, true, false);
         else phase(0, Ft{}, Ft{}, true, false);
+        // the loops take phases two at a time from an odd candidate (written
+        // 2k + 1 and 2k + 2, so each phase's buffer parity is a constant)
         int t = 1;
-        for (; t <= zb; ++t) phase(t, Tt{}, Tt{}, true, true);
+        for (int k = 0; 2 * k + 2 <= zb; ++k) {
+            phase(2 * k + 1, Tt{}, Tt{}, true, true);
+            phase(2 * k + 2, Tt{}, Tt{}, true, true);
+            t = 2 * k + 3;
+        }
+        if (t <= zb) phase(t++, Tt{}, Tt{}, true, true);
         if (zb >= 0 && t == zb + 1 && t <= zmax) {
             phase(t, Ft{}, Tt{}, true, true);
             ++t;
         }
-        for (; t <= zmax; ++t) phase(t, Ft{}, Ft{}, true, true);
+        if (t <= zmax && !(t & 1)) phase(t++, Ft{}, Ft{}, true, true);
+        for (int k = t >> 1; 2 * k + 2 <= zmax; ++k) {
+            phase(2 * k + 1, Ft{}, Ft{}, true, true);
+            phase(2 * k + 2, Ft{}, Ft{}, true, true);
+            t = 2 * k + 3;
+        }
+        if (t <= zmax) phase(t++, Ft{}, Ft{}, true, true);
         if constexpr (REPICK) {
             if (zb == zmax) phase(zmax + 1, Ft{}, Tt{}, false, true);
             else phase(zmax + 1, Ft{}, Ft{}, false, true);
