@@ -116,7 +116,7 @@ __device__ __forceinline__ float next_lane_in_row(float x)
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x101, 0xf, 0xf, true));
 }
 
-template <typename T, int NW, int MODE>
+template <typename T, int NW, int MODE, bool PF = false>
 __device__ __forceinline__ void gate_tile_box(const GateArgs& a, int bx, int by)
 {
     constexpr bool U8 = std::is_same<T, uint8_t>::value;
@@ -163,8 +163,10 @@ __device__ __forceinline__ void gate_tile_box(const GateArgs& a, int bx, int by)
     // one barrier per candidate), with the column and 5-column sums in two
     // buffers by candidate parity, within the 40 KB that keep four workgroups
     // on a CU; float tiles (double column sums) and larger windows would lose a
-    // workgroup per CU, and take two barriers per candidate and one buffer
-    constexpr bool PIPE = U8 && NW <= 4;
+    // workgroup per CU, and take two barriers per candidate and one buffer,
+    // except in the float launches too small to fill two workgroups per CU
+    // (PF), where the residency does not matter
+    constexpr bool PIPE = U8 ? NW <= 4 : PF;
     constexpr int NB = PIPE ? 2 : 1;
     constexpr int VSZ = RR * GU_VP + VTAIL, HSZ = REPICK ? RR * GU_VP : 1;
     __shared__ VT Vs[NB * VSZ];
@@ -604,27 +606,30 @@ __device__ __forceinline__ void gate_tile_box(const GateArgs& a, int bx, int by)
     }
 }
 
-// uint8 tiles at most 128 VGPRs (four waves per SIMD), float ones 168 (three)
-template <typename T>
-constexpr int GATE_MIN_WAVES = std::is_same<T, uint8_t>::value ? 4 : 3;
+// uint8 tiles at most 128 VGPRs (four waves per SIMD), float ones 168
+// (three), the float pipelined ones 256 (two: their LDS holds two per CU)
+template <typename T, bool PF>
+constexpr int GATE_MIN_WAVES = std::is_same<T, uint8_t>::value ? 4 : (PF ? 2 : 3);
+// float launches of at most this many workgroups take the pipelined walk
+constexpr int GATE_PF_MAX_BLOCKS = 512;
 
-template <typename T, int NW, int MODE>
+template <typename T, int NW, int MODE, bool PF>
 __device__ __forceinline__ void gate_tile_any(const GateArgs& a, int bx, int by)
 {
-    gate_tile_box<T, NW, MODE>(a, bx, by);
+    gate_tile_box<T, NW, MODE, PF>(a, bx, by);
 }
 
-template <typename T, int NW, int MODE>
-__global__ __launch_bounds__(GT_THREADS, GATE_MIN_WAVES<T>) void gate_kernel(GateArgs a)
+template <typename T, int NW, int MODE, bool PF>
+__global__ __launch_bounds__(GT_THREADS, (GATE_MIN_WAVES<T, PF>)) void gate_kernel(GateArgs a)
 {
-    gate_tile_any<T, NW, MODE>(a, blockIdx.x, blockIdx.y);
+    gate_tile_any<T, NW, MODE, PF>(a, blockIdx.x, blockIdx.y);
 }
 
 // Gating of several (pair, level) segments of one mode and element type in one
 // launch; a level's map and cost are those its search wrote (the scratch map
 // with the median), the coarser level's cost that of its own gating.
-template <typename T, int NW, int MODE>
-__global__ __launch_bounds__(GT_THREADS, GATE_MIN_WAVES<T>) void gate_multi_kernel(MultiArgs m)
+template <typename T, int NW, int MODE, bool PF>
+__global__ __launch_bounds__(GT_THREADS, (GATE_MIN_WAVES<T, PF>)) void gate_multi_kernel(MultiArgs m)
 {
     const Segment s = m.segs[segment_of(m.segs, m.nseg, blockIdx.x)];
     const LevelDesc* lv = m.levels + m.level_base[s.pair];
@@ -652,19 +657,42 @@ __global__ __launch_bounds__(GT_THREADS, GATE_MIN_WAVES<T>) void gate_multi_kern
         g.cpitch = C.W;
     }
     const int t = blockIdx.x - s.task0;
-    gate_tile_any<T, NW, MODE>(g, t % s.tiles_x, t / s.tiles_x);
+    gate_tile_any<T, NW, MODE, PF>(g, t % s.tiles_x, t / s.tiles_x);
+}
+
+template <typename T, int MODE, bool PF>
+hipError_t launch_gate_multi_p(int n, const MultiArgs& a, int blocks, hipStream_t s)
+{
+    switch (n) {
+        case 1: hipLaunchKernelGGL((gate_multi_kernel<T, 1, MODE, PF>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((gate_multi_kernel<T, 2, MODE, PF>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((gate_multi_kernel<T, 3, MODE, PF>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((gate_multi_kernel<T, 4, MODE, PF>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((gate_multi_kernel<T, 5, MODE, PF>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((gate_multi_kernel<T, 6, MODE, PF>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 template <typename T, int MODE>
 hipError_t launch_gate_multi_t(int n, const MultiArgs& a, int blocks, hipStream_t s)
 {
+    if constexpr (!std::is_same<T, uint8_t>::value)
+        if (blocks <= GATE_PF_MAX_BLOCKS) return launch_gate_multi_p<T, MODE, true>(n, a, blocks, s);
+    return launch_gate_multi_p<T, MODE, false>(n, a, blocks, s);
+}
+
+template <typename T, int MODE, bool PF>
+hipError_t launch_gate_p(int n, const GateArgs& a, dim3 grid, hipStream_t s)
+{
     switch (n) {
-        case 1: hipLaunchKernelGGL((gate_multi_kernel<T, 1, MODE>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((gate_multi_kernel<T, 2, MODE>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
-        case 3: hipLaunchKernelGGL((gate_multi_kernel<T, 3, MODE>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
-        case 4: hipLaunchKernelGGL((gate_multi_kernel<T, 4, MODE>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
-        case 5: hipLaunchKernelGGL((gate_multi_kernel<T, 5, MODE>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
-        case 6: hipLaunchKernelGGL((gate_multi_kernel<T, 6, MODE>), dim3(blocks), dim3(GT_THREADS), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((gate_kernel<T, 1, MODE, PF>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((gate_kernel<T, 2, MODE, PF>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 3: hipLaunchKernelGGL((gate_kernel<T, 3, MODE, PF>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((gate_kernel<T, 4, MODE, PF>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 5: hipLaunchKernelGGL((gate_kernel<T, 5, MODE, PF>), grid, dim3(GT_THREADS), 0, s, a); break;
+        case 6: hipLaunchKernelGGL((gate_kernel<T, 6, MODE, PF>), grid, dim3(GT_THREADS), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -675,16 +703,10 @@ hipError_t launch_gate_t(int n, const GateArgs& a, hipStream_t s)
 {
     const int tw = gate_tile_w(std::is_same<T, uint8_t>::value ? MSIBM_U8 : MSIBM_F32, n, MODE);
     dim3 grid((a.W + tw - 1) / tw, (a.H + GT_H - 1) / GT_H, 1);
-    switch (n) {
-        case 1: hipLaunchKernelGGL((gate_kernel<T, 1, MODE>), grid, dim3(GT_THREADS), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((gate_kernel<T, 2, MODE>), grid, dim3(GT_THREADS), 0, s, a); break;
-        case 3: hipLaunchKernelGGL((gate_kernel<T, 3, MODE>), grid, dim3(GT_THREADS), 0, s, a); break;
-        case 4: hipLaunchKernelGGL((gate_kernel<T, 4, MODE>), grid, dim3(GT_THREADS), 0, s, a); break;
-        case 5: hipLaunchKernelGGL((gate_kernel<T, 5, MODE>), grid, dim3(GT_THREADS), 0, s, a); break;
-        case 6: hipLaunchKernelGGL((gate_kernel<T, 6, MODE>), grid, dim3(GT_THREADS), 0, s, a); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    // (the separate gated search, mode GATE_FULL, keeps one form)
+    if constexpr (!std::is_same<T, uint8_t>::value && MODE != GATE_FULL)
+        if ((long)grid.x * grid.y <= GATE_PF_MAX_BLOCKS) return launch_gate_p<T, MODE, true>(n, a, grid, s);
+    return launch_gate_p<T, MODE, false>(n, a, grid, s);
 }
 
 }  // namespace

@@ -187,13 +187,19 @@ def test_gated_hierarchy_equals_level_chain_and_oracle(M, dtype, K, median):
             assert torch.equal(got[key], out[key]), key
 
 
-def test_gated_mid1436_level0_sampled(M):
+@pytest.mark.parametrize("dtype", ["u8", "f32"])
+def test_gated_mid1436_level0_sampled(M, dtype):
     """The mid-size workload at full size with the paper's thresholds: level 0's
     gated search and re-pick checked on sampled pixels against the oracle fed the
-    GPU's level-1 map and cost."""
+    GPU's level-1 map and cost.  As float images (the same values), level 0's
+    launches hold more workgroups than the two-per-CU pipelined float walk
+    takes, so they run the two-barrier walk, and the coarser levels the
+    pipelined one."""
     p, cfg = synth.workload("mid1436")
     K, n, r, D, eps = cfg.levels, cfg.half_window, cfg.refine_radius, cfg.max_disp, cfg.var_eps
     ab = (0.9, 0.9)
+    if dtype == "f32":
+        p.left, p.right = p.left.astype(np.float32), p.right.astype(np.float32)
     Lg, Rg = dev(p.left), dev(p.right)
     PL, PR = M.pyramid(Lg, 2), M.pyramid(Rg, 2)
     out = M.disparity(Lg, Rg, D, K, n, r, eps, with_prior1=True, gate=ab)
